@@ -1,0 +1,306 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU parity tests and
+the benchmark.
+
+This module holds problem set-ups only (particle placement, initial fields,
+masses in integer quanta); none of the SPH method's arithmetic lives here, so
+the oracle and the HIP library can both be fed from it without sharing any of
+the computation they are compared on.  Every generator takes an explicit seed
+and uses numpy's PCG64 generator.
+
+Workloads follow the set-ups of Muta & Ramachandran (arXiv 2107.01276):
+the periodic Taylor-Green vortex (section 4.1), and the channel with a
+circular cylinder (section 4.4), built here from a stated grading recipe
+because the paper's layout figure is not available.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def mass_quantum(m_cap: float) -> float:
+    """Power-of-two mass quantum so that every mass up to m_cap is an integer
+    number of quanta below 2**53, hence exactly representable as mq * q."""
+    e = math.floor(math.log2(m_cap))
+    return math.ldexp(1.0, e - 51)
+
+
+def quantize_mass(m: np.ndarray, q: float) -> np.ndarray:
+    return np.rint(np.asarray(m, dtype=np.float64) / q).astype(np.int64)
+
+
+@dataclass
+class Domain:
+    lo: tuple
+    hi: tuple
+    periodic: tuple
+
+    @property
+    def area(self):
+        return (self.hi[0] - self.lo[0]) * (self.hi[1] - self.lo[1])
+
+
+# ---------------------------------------------------------------------------
+# Taylor-Green vortex on the periodic unit square (section 4.1)
+# ---------------------------------------------------------------------------
+
+def tgv_fields(x, y, t=0.0, re=100.0):
+    """Exact Taylor-Green solution (U = L = rho0 = 1), decay rate b = -8 pi^2/Re."""
+    b = -8.0 * math.pi ** 2 / re
+    e = math.exp(b * t)
+    u = -e * np.cos(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    v = e * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    p = -(e * e) * (np.cos(4 * np.pi * x) + np.cos(4 * np.pi * y)) / 4.0
+    return u, v, p
+
+
+def tgv(nx: int = 50, seed: int = 1, jitter: float = 0.05, hdx: float = 1.0,
+        re: float = 100.0, rho0: float = 1.0, cs: float = 10.0, perturb: bool = True):
+    """nx*nx particles on a lattice jittered by U(-jitter, jitter)*dx per axis."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / nx
+    i, j = np.meshgrid(np.arange(nx), np.arange(nx), indexing="ij")
+    x = ((i.ravel() + 0.5) * dx).astype(np.float64)
+    y = ((j.ravel() + 0.5) * dx).astype(np.float64)
+    if perturb and jitter > 0:
+        x = x + rng.uniform(-jitter, jitter, x.size) * dx
+        y = y + rng.uniform(-jitter, jitter, y.size) * dx
+    x = np.mod(x, 1.0)
+    y = np.mod(y, 1.0)
+    u, v, p = tgv_fields(x, y, 0.0, re)
+    m = np.full(x.size, rho0 * dx * dx)
+    q = mass_quantum(1.05 * m.max())
+    mq = quantize_mass(m, q)
+    h = np.full(x.size, hdx * dx)
+    nu = 1.0 / re
+    hmin = hdx * dx
+    dt = min(0.25 * hmin / (1.0 + cs), 0.125 * hmin * hmin / nu)
+    return {
+        "x": x, "y": y, "u": u, "v": v, "p": p, "h": h,
+        "mq": mq, "mass_q": q, "m": mq.astype(np.float64) * q,
+        "rho": np.full(x.size, rho0), "mref": np.full(x.size, rho0 * dx * dx),
+        "kind": np.zeros(x.size, np.int32),
+        "domain": Domain((0.0, 0.0), (1.0, 1.0), (True, True)),
+        "params": {"rho0": rho0, "cs": cs, "nu": nu, "hdx": hdx, "re": re},
+        "dt": dt, "dx": dx,
+    }
+
+
+# ---------------------------------------------------------------------------
+# Random variable-h sets for neighbour-search parity
+# ---------------------------------------------------------------------------
+
+def random_varh(n: int, seed: int, h_lo: float = 0.01, ratio: float = 8.0,
+                periodic=(True, True), lo=(0.0, 0.0), hi=(1.0, 1.0)):
+    """Uniform positions, smoothing lengths log-uniform in [h_lo, ratio*h_lo]."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(lo[0], hi[0], n)
+    y = rng.uniform(lo[1], hi[1], n)
+    h = h_lo * np.exp(rng.uniform(0.0, math.log(ratio), n))
+    return {"x": x, "y": y, "h": h, "domain": Domain(tuple(lo), tuple(hi), tuple(periodic))}
+
+
+def clustered_varh(n: int, seed: int, h_lo: float = 0.004, ratio: float = 16.0,
+                   periodic=(False, True), lo=(0.0, -1.0), hi=(3.0, 1.0)):
+    """Positions concentrated around a point, h growing with distance from it
+    (the structure of a graded refinement around a body)."""
+    rng = np.random.default_rng(seed)
+    cx, cy = lo[0] + 0.35 * (hi[0] - lo[0]), 0.5 * (lo[1] + hi[1])
+    r = np.abs(rng.normal(0.0, 0.35, n)) + 0.02
+    th = rng.uniform(0, 2 * np.pi, n)
+    x = np.clip(cx + r * np.cos(th), lo[0], np.nextafter(hi[0], lo[0]))
+    y = cy + r * np.sin(th)
+    span = hi[1] - lo[1]
+    y = lo[1] + np.mod(y - lo[1], span)
+    y = np.where(y >= hi[1], lo[1], y)
+    t = np.clip(r / r.max(), 0, 1)
+    h = h_lo * ratio ** t * np.exp(rng.uniform(-0.1, 0.1, n))
+    return {"x": x, "y": y, "h": h, "domain": Domain(tuple(lo), tuple(hi), tuple(periodic))}
+
+
+# ---------------------------------------------------------------------------
+# Channel with a circular cylinder (section 4.4 set-up, graded by distance)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class ChannelSpec:
+    length: float = 30.0          # in D
+    height: float = 20.0          # in D
+    cyl_x: float = 10.0
+    cyl_y: float = 0.0
+    diameter: float = 1.0
+    ds_min: float = 0.01          # D/100
+    ratio: int = 64               # ds_max / ds_min
+    cr: float = 1.05              # size growth per layer
+    rows_per_layer: float = 6.0   # particle rows per C_r layer
+    hdx: float = 1.2
+    rho0: float = 1.0
+    u_inf: float = 1.0
+    re: float = 100.0
+    cs: float = 10.0
+    wall_layers: int = 5
+    jitter: float = 0.05
+
+
+def _ring_points(rng, r, ds, cx, cy):
+    n = max(int(round(2 * math.pi * r / ds)), 3)
+    th = rng.uniform(0, 2 * math.pi) + 2 * math.pi * np.arange(n) / n
+    return cx + r * np.cos(th), cy + r * np.sin(th)
+
+
+def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
+    """Fluid graded by distance d from the cylinder surface, plus solid
+    dummy-particle layers inside the cylinder.
+
+    Recipe: the target size grows by the factor C_r every `rows_per_layer`
+    rows, i.e. s(d) = ds_min + d ln(C_r)/rows_per_layer, capped at ds_max.
+    Fluid spacings are restricted to ds_min * 2**(k/2) (each refinement level
+    halves the mass), so a particle at distance d takes the largest such
+    spacing not above s(d).  Rings of constant spacing are laid around the
+    cylinder until the spacing reaches ds_max; outside, a lattice of spacing
+    ~ds_max fills the channel (periodic in y).  Every particle is jittered by
+    U(-jitter, jitter) of its spacing.  Velocity is the potential flow past
+    the cylinder, pressure from Bernoulli.
+    """
+    s = spec or ChannelSpec()
+    rng = np.random.default_rng(seed)
+    R = 0.5 * s.diameter
+    ds_max = s.ds_min * s.ratio
+    nlev = int(round(2 * math.log2(s.ratio)))
+    lev_ds = s.ds_min * np.sqrt(2.0) ** np.arange(nlev + 1)
+    lo = (0.0, s.cyl_y - 0.5 * s.height)
+    hi = (s.length, s.cyl_y + 0.5 * s.height)
+    slope = math.log(s.cr) / s.rows_per_layer
+
+    xs, ys, dss = [], [], []
+    r = R + 0.5 * s.ds_min
+    while True:
+        d = r - R
+        target = min(s.ds_min + d * slope, ds_max)
+        k = int(np.searchsorted(lev_ds, target * (1 + 1e-12), side="right") - 1)
+        k = max(0, min(k, nlev))
+        ds = lev_ds[k]
+        if k == nlev:
+            break
+        px, py = _ring_points(rng, r, ds, s.cyl_x, s.cyl_y)
+        xs.append(px); ys.append(py); dss.append(np.full(px.size, ds))
+        r += ds
+    r_outer = r
+    # outer lattice at ~ds_max, aligned to the periodic height
+    ny = max(int(round(s.height / ds_max)), 1)
+    dyl = s.height / ny
+    nx = max(int(round(s.length / dyl)), 1)
+    dxl = s.length / nx
+    gi, gj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    gx = lo[0] + (gi.ravel() + 0.5) * dxl
+    gy = lo[1] + (gj.ravel() + 0.5) * dyl
+    keep = np.hypot(gx - s.cyl_x, gy - s.cyl_y) >= r_outer + 0.25 * dyl
+    xs.append(gx[keep]); ys.append(gy[keep]); dss.append(np.full(int(keep.sum()), math.sqrt(dxl * dyl)))
+    x = np.concatenate(xs); y = np.concatenate(ys); ds = np.concatenate(dss)
+    x = x + rng.uniform(-s.jitter, s.jitter, x.size) * ds
+    y = y + rng.uniform(-s.jitter, s.jitter, y.size) * ds
+    inside = (x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1])
+    x, y, ds = x[inside], y[inside], ds[inside]
+
+    # potential flow past the cylinder
+    X, Y = x - s.cyl_x, y - s.cyl_y
+    r2 = X * X + Y * Y
+    R2 = R * R
+    u = s.u_inf * (1.0 - R2 * (X * X - Y * Y) / (r2 * r2))
+    v = -s.u_inf * 2.0 * R2 * X * Y / (r2 * r2)
+    p = 0.5 * s.rho0 * (s.u_inf ** 2 - (u * u + v * v))
+
+    # solid dummy layers inside the cylinder at ds_min
+    sx, sy = [], []
+    for L in range(s.wall_layers):
+        rr = R - (L + 0.5) * s.ds_min
+        if rr <= 0:
+            break
+        px, py = _ring_points(rng, rr, s.ds_min, s.cyl_x, s.cyl_y)
+        sx.append(px); sy.append(py)
+    sx = np.concatenate(sx); sy = np.concatenate(sy)
+    nf, ns = x.size, sx.size
+
+    m_f = s.rho0 * ds * ds
+    m_s = np.full(ns, s.rho0 * s.ds_min ** 2)
+    q = mass_quantum(1.05 * s.rho0 * ds_max ** 2 * 1.5)
+    allm = np.concatenate([m_f, m_s])
+    mq = quantize_mass(allm, q)
+    X = np.concatenate([x, sx]); Yv = np.concatenate([y, sy])
+    H = np.concatenate([s.hdx * ds, np.full(ns, s.hdx * s.ds_min)])
+    U = np.concatenate([u, np.zeros(ns)]); V = np.concatenate([v, np.zeros(ns)])
+    P = np.concatenate([p, np.zeros(ns)])
+    kind = np.concatenate([np.zeros(nf, np.int32), np.ones(ns, np.int32)])
+    nu = s.u_inf * s.diameter / s.re
+    hmin = s.hdx * s.ds_min
+    dt = min(0.25 * hmin / (s.u_inf + s.cs), 0.125 * hmin * hmin / nu)
+    return {
+        "x": X, "y": Yv, "u": U, "v": V, "p": P, "h": H, "mq": mq, "mass_q": q,
+        "m": mq.astype(np.float64) * q, "rho": np.full(X.size, s.rho0),
+        "mref": np.concatenate([m_f, m_s]), "kind": kind, "n_fluid": nf, "n_solid": ns,
+        "domain": Domain(lo, hi, (False, True)),
+        "params": {"rho0": s.rho0, "cs": s.cs, "nu": nu, "hdx": s.hdx, "re": s.re,
+                   "u_inf": s.u_inf},
+        "dt": dt, "spec": s,
+    }
+
+
+def background_lattice(domain: Domain, ds_max: float, hdx: float, rho0: float,
+                       seed: int = 0, jitter: float = 0.0):
+    """Background particles at the coarsest size ds_max (section 3.3)."""
+    rng = np.random.default_rng(seed)
+    Lx = domain.hi[0] - domain.lo[0]
+    Ly = domain.hi[1] - domain.lo[1]
+    nx = max(int(round(Lx / ds_max)), 1)
+    ny = max(int(round(Ly / ds_max)), 1)
+    gi, gj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x = domain.lo[0] + (gi.ravel() + 0.5) * (Lx / nx)
+    y = domain.lo[1] + (gj.ravel() + 0.5) * (Ly / ny)
+    if jitter > 0:
+        x = x + rng.uniform(-jitter, jitter, x.size) * ds_max
+        y = y + rng.uniform(-jitter, jitter, y.size) * ds_max
+    n = x.size
+    m = rho0 * ds_max * ds_max
+    q = mass_quantum(1.05 * m * 1.5)
+    return {"x": x, "y": y, "h": np.full(n, hdx * ds_max), "ds": np.full(n, ds_max),
+            "mask": np.zeros(n, np.int32), "mq": np.full(n, int(round(m / q)), np.int64),
+            "mass_q": q, "mref": np.full(n, m)}
+
+
+def square_solid(cx: float, cy: float, side: float, ds: float, hdx: float, layers: int = 3):
+    """A square solid body discretised at spacing ds (section 3.3 example)."""
+    xs, ys = [], []
+    n = max(int(round(side / ds)), 1)
+    for L in range(layers):
+        a = side / 2 - (L + 0.5) * ds
+        if a <= 0:
+            break
+        m = max(int(round(2 * a / ds)), 1)
+        t = np.linspace(-a, a, m + 1)
+        xs += [cx + t, cx + t, np.full(m + 1, cx - a), np.full(m + 1, cx + a)]
+        ys += [np.full(m + 1, cy - a), np.full(m + 1, cy + a), cy + t, cy + t]
+    x = np.concatenate(xs); y = np.concatenate(ys)
+    pts = np.unique(np.round(np.stack([x, y], 1), 12), axis=0)
+    del n
+    return {"x": pts[:, 0].copy(), "y": pts[:, 1].copy(), "h": np.full(len(pts), hdx * ds)}
+
+
+# ---------------------------------------------------------------------------
+# Serving mix: independent periodic vortex instances
+# ---------------------------------------------------------------------------
+
+def serving_requests(n_req: int = 256, seed: int = 4, n_lo: int = 2000, n_hi: int = 200000,
+                     re_lo: float = 100.0, re_hi: float = 1000.0, rate: float = 1.0):
+    """Request specs: particle count log-uniform in [n_lo, n_hi] (lattice side
+    ceil(sqrt N)), Re uniform in [re_lo, re_hi], Poisson arrival times at
+    `rate` requests per unit time."""
+    rng = np.random.default_rng(seed)
+    N = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), n_req))).astype(np.int64)
+    side = np.ceil(np.sqrt(N)).astype(np.int64)
+    re = rng.uniform(re_lo, re_hi, n_req)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
+    seeds = rng.integers(1, 2 ** 31 - 1, n_req)
+    return [{"side": int(side[k]), "re": float(re[k]), "arrival": float(arrivals[k]),
+             "seed": int(seeds[k])} for k in range(n_req)]
