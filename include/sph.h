@@ -1,0 +1,206 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of adaptive-resolution weakly-compressible SPH (Muta & Ramachandran,
+ * "Efficient and accurate adaptive resolution for weakly-compressible SPH",
+ * arXiv 2107.01276): variable-h neighbour search, the pairwise rate loop,
+ * the predict-evaluate-correct step and the split/merge adaptation driven by
+ * background particles.
+ *
+ * Conventions for every call:
+ *   - Particle data are structure-of-arrays in device memory owned by the
+ *     caller; each array holds at least `capacity` entries and entries
+ *     [0, n) are live.  Rows of a neighbour list and particle indices are
+ *     "slots": positions in these arrays.
+ *   - Positions, velocities, pressure, density, smoothing length and
+ *     reference mass are double.  Mass is an int64 number of quanta `mq`;
+ *     the mass of a particle is mq * mass_q exactly (mass_q is a power of
+ *     two chosen so every mq < 2^53), which keeps total mass exactly
+ *     conserved through splits and merges.
+ *   - All work is issued on the context's stream in order.  Calls that
+ *     return counts to the host (nnz, new particle count) synchronise that
+ *     stream before returning; the others only enqueue work.
+ *   - Scratch memory comes from the caller's workspace (sph_create); the
+ *     library allocates no device memory.
+ *   - Return value: SPH_OK (0) or a negative SPH_E_* code; sph_last_error()
+ *     gives a message.  On error no caller-visible array has been modified
+ *     unless the call's comment says otherwise.
+ *   - 2D only; periodic axes use the minimum image.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SPH_OK = 0,
+    SPH_E_INVAL = -1,     /* bad argument or configuration */
+    SPH_E_CAPACITY = -2,  /* result does not fit the caller's arrays */
+    SPH_E_NOMEM = -3,     /* workspace too small */
+    SPH_E_DEVICE = -4,    /* HIP runtime error */
+    SPH_E_NONFINITE = -5, /* NaN or Inf found in the state */
+    SPH_E_AGAIN = -6      /* serving pool full: retry later */
+};
+
+enum { SPH_FP64 = 0, SPH_FP32 = 1 };             /* pair arithmetic precision */
+enum { SPH_FLUID = 0, SPH_SOLID = 1 };           /* particle kinds */
+
+/* Run configuration.  Physical constants follow section 2 of the paper:
+ * rho0, c_s, nu, alpha_e (eq. edac-alpha), the kernel support 3h (eq.
+ * kernel).  Adaptation constants follow section 3: split_alpha and
+ * split_eps (section 3.1), m_max = mmax_f m_ref and m_min = mmin_f m_ref
+ * (section 3.3), merge_iters and shift_iters (section 3.2), hdx = C of
+ * h = C (m/rho)^(1/2) (section 3.1).  Background constants follow section
+ * 3.3: C_r, ds_min, ds_max, N_r and the number of h-smoothing + shifting
+ * repetitions. */
+typedef struct sph_config {
+    int32_t precision;      /* SPH_FP64 or SPH_FP32 */
+    int32_t periodic[2];    /* per axis: 1 = periodic */
+    double lo[2], hi[2];    /* domain box; periodic axes wrap into [lo, hi) */
+    double h_lo, h_hi;      /* expected smoothing-length range; sizes the grid.
+                               Results never depend on it: any h is handled,
+                               h far outside only costs time. */
+    double rho0, cs, nu, alpha_e, hdx, u_ref;
+    double body_force[2];
+    double split_alpha, split_eps, mmax_f, mmin_f;
+    double mass_q;          /* fluid mass quantum */
+    int32_t merge_iters, shift_iters;
+    double cr, ds_min, ds_max, n_r;
+    int32_t bg_smooth_iters;
+    double bg_mass_q;       /* background mass quantum */
+} sph_config;
+
+/* Caller-owned particle set (device pointers, see conventions). kind may be
+ * NULL (all fluid). */
+typedef struct sph_particles {
+    int64_t n, capacity;
+    double *x, *y, *u, *v, *p, *rho, *h, *mref;
+    int64_t *mq;
+    int32_t *kind;
+} sph_particles;
+
+/* Neighbour lists in CSR form (device arrays): row_ptr[n+1], col[nnz_cap].
+ * Row i holds every j with |r_i - r_j| < 3 max(h_i, h_j), i itself
+ * included, in ascending order. nnz is written (host) by the call. */
+typedef struct sph_csr {
+    int64_t *row_ptr;
+    int32_t *col;
+    int64_t nnz_cap;
+    int64_t nnz;
+} sph_csr;
+
+/* Outputs of one rate evaluation (device arrays of length >= n, slot
+ * order). Any pointer may be NULL to skip that field. */
+typedef struct sph_rates_out {
+    double *rho, *beta, *pavg, *nnb, *dxs, *dys, *dpdt, *dudt, *dvdt;
+} sph_rates_out;
+
+/* Index map of one adaptation (sph_adapt).  origin and sat are device
+ * arrays of length >= capacity; the counters are written on the host. */
+typedef struct sph_adapt_map {
+    int64_t *origin;    /* new slot -> pre-adaptation slot it descends from */
+    int32_t *sat;       /* 1 for the six off-centre children of a split */
+    int64_t n_split;    /* particles split */
+    int64_t n_required; /* size needed by the split (capacity check) */
+    int64_t n_merged[8];/* merged pairs per merge iteration */
+} sph_adapt_map;
+
+/* Background particles of section 3.3 (device arrays, caller-owned). */
+typedef struct sph_background {
+    int64_t n, capacity;
+    double *x, *y, *h, *ds, *mref;
+    int32_t *mask;
+    int64_t *mq;
+} sph_background;
+
+/* Scalar diagnostics (host), section 4.1: kinetic energy, volume error
+ * sum(m/rho), linear momentum, total mass in quanta, extreme speed. */
+typedef struct sph_diag {
+    double ke, vol, mom_x, mom_y, umax;
+    int64_t mq_total, n;
+} sph_diag;
+
+typedef struct sph_ctx sph_ctx;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int sph_version(void);
+
+/* Bytes of device workspace sph_create needs for `capacity` particles. */
+size_t sph_workspace_bytes(const sph_config *cfg, int64_t capacity);
+
+/* Creates a context on the current HIP device.  `workspace` (device,
+ * >= sph_workspace_bytes, 256-byte aligned) is owned by the caller and must
+ * outlive the context.  `stream` is a hipStream_t (NULL = default stream).
+ * Errors: SPH_E_INVAL (bad config), SPH_E_NOMEM (workspace too small). */
+int sph_create(const sph_config *cfg, int64_t capacity, void *workspace,
+               size_t workspace_bytes, void *stream, sph_ctx **out);
+void sph_destroy(sph_ctx *ctx);
+const char *sph_last_error(const sph_ctx *ctx);
+int sph_set_stream(sph_ctx *ctx, void *stream);
+
+/* Neighbour search (paper section 2: kernel support 3h; symmetric because
+ * the rates of eqs. edac:sph and mom-sph use W(h_i) and W(h_j)).  Builds
+ * the search structure for `ps`; if `out` is non-NULL also writes the CSR.
+ * Distances use the minimum image on periodic axes and are compared as
+ * dx*dx + dy*dy < (3 max(h_i,h_j))^2 in double precision.
+ * SPH_E_CAPACITY if nnz > out->nnz_cap (out->nnz = required, col untouched).
+ * Synchronises when `out` is non-NULL. */
+int sph_build_neighbors(sph_ctx *ctx, const sph_particles *ps, sph_csr *out);
+
+/* One rate evaluation on the given state (section 2): pass A = summation
+ * density (eq. sd-gather), beta (eq. beta), neighbour count and average
+ * pressure (eq. pavg), limited shifting (eqs. shift-deltar, shift-limit);
+ * pass B = EDAC pressure rate (eq. edac:sph) and momentum (eq. mom-sph).
+ * Pair arithmetic in the configured precision.  dt enters through the
+ * transport-velocity term (eq. shift-tvf). */
+int sph_rates(sph_ctx *ctx, const sph_particles *ps, double dt, sph_rates_out *out);
+
+/* nsteps predict-evaluate-correct steps (eqs. int-pre, int-cor) of size dt,
+ * neighbours rebuilt before each of the two evaluations per step.  Fluid
+ * particles are integrated; solid particles stay in place.  Updates x, y,
+ * u, v, p and rho (last summation density) in place. */
+int sph_step(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps);
+
+/* Fluid reference mass from the background (section 3.3 and the algorithm of
+ * section 3.4, item 4): m_ref,i = min of the background m_ref within
+ * 3 max(h_i, h_b); if none is in range, that of the nearest background
+ * particle (lowest slot on ties).  Writes ps->mref. */
+int sph_mref_lookup(sph_ctx *ctx, const sph_particles *ps, const sph_background *bg);
+
+/* Adaptation (section 3; algorithm of section 3.4 items 5-7): split every
+ * fluid particle with m > mmax_f m_ref into 7 (section 3.1), merge mutually
+ * closest pairs merge_iters times (section 3.2), shift shift_iters times
+ * with the Taylor correction (eq. shift-correct), then set h from the mean
+ * neighbour mass.  If bg is non-NULL, m_ref is looked up first.
+ * Two-phase: when the split needs more than ps->capacity slots, returns
+ * SPH_E_CAPACITY with map->n_required set and the state untouched.
+ * Updates ps->n on the host.  Synchronises. */
+int sph_adapt(sph_ctx *ctx, sph_particles *ps, const sph_background *bg, sph_adapt_map *map);
+
+/* Background update (section 3.3 steps 1-4), `passes` times: mark background
+ * particles near solids (or with phi > phi_thresh when phi, a device array
+ * over the background, is non-NULL; solution adaptivity), grade sizes by
+ * C_r, split, then smooth h (eq. h-smoothing) and shift.  Updates bg->n.
+ * *nsplit receives the number of splits.  Synchronises. */
+int sph_bg_update(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
+                  const double *phi, double phi_thresh, int32_t passes, int64_t *nsplit);
+
+/* Scalar diagnostics over [0, n).  Synchronises. */
+int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
+
+/* Profiling: when enabled, the library brackets every launch of the named
+ * kernel ("pass_a", "pass_b", "build") with HIP events on its stream and
+ * accumulates the elapsed time.  sph_profile_read synchronises and returns
+ * total milliseconds and launch count since the last reset. */
+int sph_profile_enable(sph_ctx *ctx, int32_t on);
+int sph_profile_read(sph_ctx *ctx, const char *kernel, double *ms, int64_t *launches);
+int sph_profile_reset(sph_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

@@ -562,6 +562,9 @@ void or_pass_a(const or_domain* d, const or_params* P, int64_t n, const double* 
 /* (r_ij^2 + eta_i) as the viscous term is; A_i, A_j and the third line of   */
 /* eq. (mom-sph) are not used (remark after eq. mom-corr); eta_i =           */
 /* 0.001 h_i^2; P_i from eq. (mom:pre) with p_avg from eq. (pavg).           */
+/* READING (degenerate case the paper leaves open): beta_i <= 0 happens only */
+/* when no neighbour lies inside particle i's own support; then P_i = 0 and  */
+/* the sums scaled by 1/beta_i are dropped, so its rates stay finite.        */
 /* ------------------------------------------------------------------------ */
 
 void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* x,
@@ -574,7 +577,7 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
     const double rho0 = P->rho0, cs = P->cs, nu = P->nu, ae = P->alpha_e;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
-        double Pi = (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]);
+        double Pi = beta[i] > 0.0 ? (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]) : 0.0;
         double nui = ae * cs * h[i] / 8.0;
         double eta = 0.001 * h[i] * h[i];
         double s_div = 0.0, s_dif = 0.0, gx = 0.0, gy = 0.0, vx = 0.0, vy = 0.0;
@@ -594,7 +597,8 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
             double gbx = 0.5 * (gix + gjx), gby = 0.5 * (giy + gjy);
             double uij = u[i] - u[j], vij = v[i] - v[j];
             double Vj = m[j] / rho[j];
-            double Pj = P->pref_mode ? (p[j] - pavg[i]) / (rho[j] * rho[j] * beta[j])
+            double Pj = beta[j] <= 0.0 ? 0.0
+                      : P->pref_mode ? (p[j] - pavg[i]) / (rho[j] * rho[j] * beta[j])
                                      : (p[j] - pavg[j]) / (rho[j] * rho[j] * beta[j]);
             double nuj = ae * cs * h[j] / 8.0;
             double nuij = 4.0 * nui * nuj / (nui + nuj);
@@ -612,10 +616,10 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
             vy += cvis * vij;
         }
         double b = beta[i];
-        dpdt[i] = (rho0 * cs * cs / b) * s_div + s_dif / b
-                + (dxs[i] / dt) * gx + (dys[i] / dt) * gy;
-        dudt[i] = -gx + vx / b + P->fx;
-        dvdt[i] = -gy + vy / b + P->fy;
+        double edac = b > 0.0 ? (rho0 * cs * cs / b) * s_div + s_dif / b : 0.0;
+        dpdt[i] = edac + (dxs[i] / dt) * gx + (dys[i] / dt) * gy;
+        dudt[i] = -gx + (b > 0.0 ? vx / b : 0.0) + P->fx;
+        dvdt[i] = -gy + (b > 0.0 ? vy / b : 0.0) + P->fy;
     }
 }
 

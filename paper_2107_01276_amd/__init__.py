@@ -1,0 +1,385 @@
+"""Python binding of the gfx950 adaptive-resolution WCSPH library.
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library ``libsph.so`` (C ABI in ``include/sph.h``).  PyTorch provides device
+memory (the particle arrays and the workspace) and the stream.  Importing
+this package fails loudly if the library has not been built; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+SPH_OK, SPH_E_INVAL, SPH_E_CAPACITY, SPH_E_NOMEM = 0, -1, -2, -3
+SPH_E_DEVICE, SPH_E_NONFINITE, SPH_E_AGAIN = -4, -5, -6
+SPH_FP64, SPH_FP32 = 0, 1
+SPH_FLUID, SPH_SOLID = 0, 1
+_ERRNAME = {0: "SPH_OK", -1: "SPH_E_INVAL", -2: "SPH_E_CAPACITY", -3: "SPH_E_NOMEM",
+            -4: "SPH_E_DEVICE", -5: "SPH_E_NONFINITE", -6: "SPH_E_AGAIN"}
+
+
+class SphError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAME.get(code, code)}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------------------
+# C structs (mirror include/sph.h)
+# ---------------------------------------------------------------------------
+
+class sph_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("periodic", C.c_int32 * 2),
+                ("lo", C.c_double * 2), ("hi", C.c_double * 2),
+                ("h_lo", C.c_double), ("h_hi", C.c_double),
+                ("rho0", C.c_double), ("cs", C.c_double), ("nu", C.c_double),
+                ("alpha_e", C.c_double), ("hdx", C.c_double), ("u_ref", C.c_double),
+                ("body_force", C.c_double * 2),
+                ("split_alpha", C.c_double), ("split_eps", C.c_double),
+                ("mmax_f", C.c_double), ("mmin_f", C.c_double), ("mass_q", C.c_double),
+                ("merge_iters", C.c_int32), ("shift_iters", C.c_int32),
+                ("cr", C.c_double), ("ds_min", C.c_double), ("ds_max", C.c_double),
+                ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double)]
+
+
+class sph_particles(C.Structure):
+    _fields_ = [("n", C.c_int64), ("capacity", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("u", C.c_void_p), ("v", C.c_void_p),
+                ("p", C.c_void_p), ("rho", C.c_void_p), ("h", C.c_void_p), ("mref", C.c_void_p),
+                ("mq", C.c_void_p), ("kind", C.c_void_p)]
+
+
+class sph_csr(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("col", C.c_void_p), ("nnz_cap", C.c_int64),
+                ("nnz", C.c_int64)]
+
+
+class sph_rates_out(C.Structure):
+    _fields_ = [(k, C.c_void_p) for k in
+                ("rho", "beta", "pavg", "nnb", "dxs", "dys", "dpdt", "dudt", "dvdt")]
+
+
+class sph_adapt_map(C.Structure):
+    _fields_ = [("origin", C.c_void_p), ("sat", C.c_void_p), ("n_split", C.c_int64),
+                ("n_required", C.c_int64), ("n_merged", C.c_int64 * 8)]
+
+
+class sph_background(C.Structure):
+    _fields_ = [("n", C.c_int64), ("capacity", C.c_int64),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("h", C.c_void_p), ("ds", C.c_void_p),
+                ("mref", C.c_void_p), ("mask", C.c_void_p), ("mq", C.c_void_p)]
+
+
+class sph_diag(C.Structure):
+    _fields_ = [("ke", C.c_double), ("vol", C.c_double), ("mom_x", C.c_double),
+                ("mom_y", C.c_double), ("umax", C.c_double), ("mq_total", C.c_int64),
+                ("n", C.c_int64)]
+
+
+EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
+           "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
+           "sph_adapt", "sph_bg_update", "sph_diagnostics", "sph_profile_enable",
+           "sph_profile_read", "sph_profile_reset")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libsph.so and declares the C signatures.  Raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    L = C.CDLL(path)
+    P, I32, I64, D = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    sig = {
+        "sph_version": (C.c_int, []),
+        "sph_workspace_bytes": (C.c_size_t, [P, I64]),
+        "sph_create": (C.c_int, [P, I64, P, C.c_size_t, P, P]),
+        "sph_destroy": (None, [P]),
+        "sph_last_error": (C.c_char_p, [P]),
+        "sph_set_stream": (C.c_int, [P, P]),
+        "sph_build_neighbors": (C.c_int, [P, P, P]),
+        "sph_rates": (C.c_int, [P, P, D, P]),
+        "sph_step": (C.c_int, [P, P, D, I32]),
+        "sph_mref_lookup": (C.c_int, [P, P, P]),
+        "sph_adapt": (C.c_int, [P, P, P, P]),
+        "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
+        "sph_diagnostics": (C.c_int, [P, P, P]),
+        "sph_profile_enable": (C.c_int, [P, I32]),
+        "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
+        "sph_profile_reset": (C.c_int, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------------------
+# Python-side helpers
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Config:
+    lo: tuple = (0.0, 0.0)
+    hi: tuple = (1.0, 1.0)
+    periodic: tuple = (True, True)
+    h_lo: float = 0.02
+    h_hi: float = 0.02
+    precision: int = SPH_FP64
+    rho0: float = 1.0
+    cs: float = 10.0
+    nu: float = 0.01
+    alpha_e: float = 1.5
+    hdx: float = 1.0
+    u_ref: float = 1.0
+    body_force: tuple = (0.0, 0.0)
+    split_alpha: float = 0.9
+    split_eps: float = 0.4
+    mmax_f: float = 1.05
+    mmin_f: float = 0.5
+    mass_q: float = 2.0 ** -60
+    merge_iters: int = 3
+    shift_iters: int = 3
+    cr: float = 1.05
+    ds_min: float = 0.01
+    ds_max: float = 0.64
+    n_r: float = 48.0
+    bg_smooth_iters: int = 3
+    bg_mass_q: float = 2.0 ** -60
+
+    def c(self) -> sph_config:
+        s = sph_config()
+        s.precision = int(self.precision)
+        s.periodic[0], s.periodic[1] = int(self.periodic[0]), int(self.periodic[1])
+        s.lo[0], s.lo[1] = self.lo
+        s.hi[0], s.hi[1] = self.hi
+        s.body_force[0], s.body_force[1] = self.body_force
+        for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
+                  "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
+                  "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q"):
+            setattr(s, k, getattr(self, k))
+        return s
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+_F64 = ("x", "y", "u", "v", "p", "rho", "h", "mref")
+
+
+class Particles:
+    """Structure-of-arrays particle set in device memory (torch tensors)."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.capacity = int(capacity)
+        self.n = 0
+        self.device = torch.device(device)
+        for k in _F64:
+            setattr(self, k, torch.zeros(self.capacity, dtype=torch.float64, device=self.device))
+        self.mq = torch.zeros(self.capacity, dtype=torch.int64, device=self.device)
+        self.kind = torch.zeros(self.capacity, dtype=torch.int32, device=self.device)
+
+    @classmethod
+    def from_arrays(cls, d: dict, capacity: int | None = None, device="cuda"):
+        n = len(d["x"])
+        P = cls(capacity or n, device)
+        P.n = n
+        for k in _F64:
+            if k in d:
+                getattr(P, k)[:n] = torch.as_tensor(d[k], dtype=torch.float64)
+        if "rho" not in d:
+            P.rho[:n] = 1.0
+        P.mq[:n] = torch.as_tensor(d["mq"], dtype=torch.int64)
+        if "kind" in d:
+            P.kind[:n] = torch.as_tensor(d["kind"], dtype=torch.int32)
+        return P
+
+    def c(self) -> sph_particles:
+        s = sph_particles()
+        s.n, s.capacity = self.n, self.capacity
+        for k in _F64:
+            setattr(s, k, _ptr(getattr(self, k)))
+        s.mq, s.kind = _ptr(self.mq), _ptr(self.kind)
+        return s
+
+    def numpy(self) -> dict:
+        n = self.n
+        out = {k: getattr(self, k)[:n].cpu().numpy() for k in _F64}
+        out["mq"] = self.mq[:n].cpu().numpy()
+        out["kind"] = self.kind[:n].cpu().numpy()
+        return out
+
+
+class Background:
+    """Background particles of section 3.3 (device tensors)."""
+
+    def __init__(self, capacity: int, device="cuda"):
+        self.capacity = int(capacity)
+        self.n = 0
+        dev = torch.device(device)
+        for k in ("x", "y", "h", "ds", "mref"):
+            setattr(self, k, torch.zeros(self.capacity, dtype=torch.float64, device=dev))
+        self.mask = torch.zeros(self.capacity, dtype=torch.int32, device=dev)
+        self.mq = torch.zeros(self.capacity, dtype=torch.int64, device=dev)
+
+    @classmethod
+    def from_arrays(cls, d: dict, capacity: int | None = None, device="cuda"):
+        n = len(d["x"])
+        B = cls(capacity or n, device)
+        B.n = n
+        for k in ("x", "y", "h", "ds", "mref"):
+            getattr(B, k)[:n] = torch.as_tensor(d[k], dtype=torch.float64)
+        B.mask[:n] = torch.as_tensor(d["mask"], dtype=torch.int32)
+        B.mq[:n] = torch.as_tensor(d["mq"], dtype=torch.int64)
+        return B
+
+    def c(self) -> sph_background:
+        s = sph_background()
+        s.n, s.capacity = self.n, self.capacity
+        for k in ("x", "y", "h", "ds", "mref", "mask", "mq"):
+            setattr(s, k, _ptr(getattr(self, k)))
+        return s
+
+    def numpy(self) -> dict:
+        n = self.n
+        out = {k: getattr(self, k)[:n].cpu().numpy() for k in ("x", "y", "h", "ds", "mref")}
+        out["mask"] = self.mask[:n].cpu().numpy()
+        out["mq"] = self.mq[:n].cpu().numpy()
+        return out
+
+
+class Context:
+    """A library context bound to one device, stream and workspace."""
+
+    def __init__(self, cfg: Config, capacity: int, device="cuda", stream=None):
+        self.lib = load_library()
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.capacity = int(capacity)
+        self._c = cfg.c()
+        nbytes = self.lib.sph_workspace_bytes(C.byref(self._c), self.capacity)
+        if nbytes == 0:
+            raise SphError(SPH_E_INVAL, "invalid configuration")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self.lib.sph_create(C.byref(self._c), self.capacity, _ptr(self.workspace), nbytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != SPH_OK:
+            raise SphError(rc, "sph_create failed")
+        self._h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None):
+                self.lib.sph_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != SPH_OK:
+            msg = self.lib.sph_last_error(self._h)
+            raise SphError(rc, msg.decode() if msg else "")
+
+    # -- hot path ----------------------------------------------------------
+
+    def build_neighbors(self, P: Particles, csr: bool = True, nnz_cap: int | None = None):
+        ps = P.c()
+        if not csr:
+            self._check(self.lib.sph_build_neighbors(self._h, C.byref(ps), None))
+            return None
+        cap = nnz_cap if nnz_cap is not None else max(96 * P.n, 1)
+        rp = torch.empty(P.n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        out = sph_csr(row_ptr=_ptr(rp).value, col=_ptr(col).value, nnz_cap=cap, nnz=0)
+        rc = self.lib.sph_build_neighbors(self._h, C.byref(ps), C.byref(out))
+        if rc == SPH_E_CAPACITY and nnz_cap is None:
+            return self.build_neighbors(P, True, int(out.nnz))
+        self._check(rc)
+        return rp, col[:out.nnz]
+
+    def rates(self, P: Particles, dt: float):
+        n = P.n
+        out = {k: torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+               for k in ("rho", "beta", "pavg", "nnb", "dxs", "dys", "dpdt", "dudt", "dvdt")}
+        ro = sph_rates_out(**{k: _ptr(v).value for k, v in out.items()})
+        ps = P.c()
+        self._check(self.lib.sph_rates(self._h, C.byref(ps), float(dt), C.byref(ro)))
+        return {k: v[:n] for k, v in out.items()}
+
+    def step(self, P: Particles, dt: float, nsteps: int = 1):
+        ps = P.c()
+        self._check(self.lib.sph_step(self._h, C.byref(ps), float(dt), int(nsteps)))
+
+    def mref_lookup(self, P: Particles, bg: Background):
+        ps, bs = P.c(), bg.c()
+        self._check(self.lib.sph_mref_lookup(self._h, C.byref(ps), C.byref(bs)))
+
+    def adapt(self, P: Particles, bg: Background | None = None):
+        origin = torch.empty(P.capacity, dtype=torch.int64, device=self.device)
+        sat = torch.empty(P.capacity, dtype=torch.int32, device=self.device)
+        m = sph_adapt_map(origin=_ptr(origin).value, sat=_ptr(sat).value)
+        ps = P.c()
+        bs = bg.c() if bg is not None else None
+        rc = self.lib.sph_adapt(self._h, C.byref(ps), C.byref(bs) if bs is not None else None,
+                                C.byref(m))
+        info = {"n_split": int(m.n_split), "n_required": int(m.n_required),
+                "merged": [int(m.n_merged[k]) for k in range(self.cfg.merge_iters)]}
+        if rc == SPH_E_CAPACITY:
+            info["error"] = rc
+            return info
+        self._check(rc)
+        P.n = int(ps.n)
+        info["origin"] = origin[:P.n]
+        info["sat"] = sat[:P.n]
+        return info
+
+    def bg_update(self, bg: Background, solids: Particles, passes: int, phi=None,
+                  phi_thresh: float = 0.0):
+        bs, ss = bg.c(), solids.c()
+        ns = C.c_int64(0)
+        self._check(self.lib.sph_bg_update(self._h, C.byref(bs), C.byref(ss), _ptr(phi),
+                                           float(phi_thresh), int(passes), C.byref(ns)))
+        bg.n = int(bs.n)
+        return int(ns.value)
+
+    def diagnostics(self, P: Particles) -> dict:
+        d = sph_diag()
+        ps = P.c()
+        self._check(self.lib.sph_diagnostics(self._h, C.byref(ps), C.byref(d)))
+        return {k: getattr(d, k) for k, _ in sph_diag._fields_}
+
+    # -- profiling ---------------------------------------------------------
+
+    def profile(self, on: bool = True):
+        self._check(self.lib.sph_profile_enable(self._h, int(on)))
+
+    def profile_reset(self):
+        self._check(self.lib.sph_profile_reset(self._h))
+
+    def profile_read(self, kernel: str):
+        ms, cnt = C.c_double(0), C.c_int64(0)
+        self._check(self.lib.sph_profile_read(self._h, kernel.encode(), C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+
+def config_for(domain, params: dict, h_lo: float, h_hi: float, precision=SPH_FP64,
+               mass_q: float = 2.0 ** -60, **kw) -> Config:
+    """Config from a workload's domain/params (see the workloads module)."""
+    return Config(lo=tuple(domain.lo), hi=tuple(domain.hi), periodic=tuple(domain.periodic),
+                  h_lo=h_lo, h_hi=h_hi, precision=precision, rho0=params["rho0"],
+                  cs=params["cs"], nu=params["nu"], hdx=params["hdx"], mass_q=mass_q, **kw)

@@ -1,0 +1,319 @@
+// C ABI entry points (declared in include/sph.h): context creation,
+// workspace carving, argument checks, error reporting and profiling.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "sph_internal.h"
+
+#define SPH_VERSION 10000
+#define COL_PER_PARTICLE 96
+
+void set_err(sph_ctx* c, const char* fmt, ...)
+{
+    if (!c) return;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(c->err, sizeof(c->err), fmt, ap);
+    va_end(ap);
+}
+
+int check_hip(sph_ctx* c, hipError_t e, const char* what)
+{
+    set_err(c, "HIP error in %s: %s", what, hipGetErrorString(e));
+    return SPH_E_DEVICE;
+}
+
+// Carves the workspace.  With base == NULL only the size is computed.
+static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        off = (off + 255) & ~(size_t)255;
+        void* p = base ? (void*)(base + off) : nullptr;
+        off += bytes;
+        return p;
+    };
+    int64_t C = cap > 0 ? cap : 1;
+    int64_t nblk = cdiv(C, 2048);
+    int64_t scan_n = (C + 1) > 256 * nblk ? (C + 1) : 256 * nblk;
+    w->capacity = C;
+    w->keys_a = (uint64_t*)take(8 * C);
+    w->keys_b = (uint64_t*)take(8 * C);
+    w->vals_a = (int32_t*)take(4 * C);
+    w->vals_b = (int32_t*)take(4 * C);
+    w->hist = (uint32_t*)take(4 * 256 * nblk);
+    w->scan_tmp = (int64_t*)take(8 * (2 * cdiv(scan_n, 2048) + 256));
+    w->tab = (int2*)take(sizeof(int2) * (g.tab_total > 0 ? g.tab_total : 1));
+    w->hmax_bits = (unsigned long long*)take(8 * SPH_MAXL);
+    w->lcount = (int32_t*)take(4 * SPH_MAXL);
+    w->status = (int32_t*)take(4 * 64);
+    w->long_rows = (int32_t*)take(4 * C);
+    w->xs = (double*)take(8 * C);
+    w->ys = (double*)take(8 * C);
+    w->hs = (double*)take(8 * C);
+    w->us = (double*)take(8 * C);
+    w->vs = (double*)take(8 * C);
+    double** sc[12] = {&w->sc0, &w->sc1, &w->sc2, &w->sc3, &w->sc4, &w->sc5,
+                       &w->sc6, &w->sc7, &w->sc8, &w->sc9, &w->sc10, &w->sc11};
+    for (int k = 0; k < 12; ++k) *sc[k] = (double*)take(8 * (C > 1280 ? C : 1280));
+    w->r_dpdt = (double*)take(8 * C);
+    w->r_dudt = (double*)take(8 * C);
+    w->r_dvdt = (double*)take(8 * C);
+    w->r_dxs = (double*)take(8 * C);
+    w->r_dys = (double*)take(8 * C);
+    w->xh = (double*)take(8 * C);
+    w->yh = (double*)take(8 * C);
+    w->uh = (double*)take(8 * C);
+    w->vh = (double*)take(8 * C);
+    w->ph = (double*)take(8 * C);
+    w->cnt64 = (int64_t*)take(8 * (C + 1));
+    w->rp_tmp = (int64_t*)take(8 * (C + 1));
+    w->col_cap = COL_PER_PARTICLE * C;
+    w->col_tmp = (int32_t*)take(4 * w->col_cap);
+    w->flag = (int32_t*)take(4 * (C + 1));
+    w->closest = (int32_t*)take(4 * C);
+    w->idx_a = (int32_t*)take(4 * (C + 1));
+    w->idx_b = (int32_t*)take(4 * (C + 1));
+    w->i64_a = (int64_t*)take(8 * (C + 1));
+    w->i64_b = (int64_t*)take(8 * (C + 1));
+    for (int k = 0; k < 10; ++k) w->tmp_d[k] = (double*)take(8 * C);
+    for (int k = 0; k < 2; ++k) w->tmp_i32[k] = (int32_t*)take(4 * C);
+    for (int k = 0; k < 3; ++k) w->tmp_i64[k] = (int64_t*)take(8 * C);
+    w->red = (int64_t*)take(8 * 8192);
+    return off + 256;
+}
+
+static int check_cfg(const sph_config* cfg)
+{
+    if (!cfg) return 0;
+    for (int a = 0; a < 2; ++a)
+        if (!(cfg->hi[a] > cfg->lo[a]) || !isfinite(cfg->hi[a]) || !isfinite(cfg->lo[a])) return 0;
+    if (!(cfg->h_lo > 0) || !(cfg->h_hi >= cfg->h_lo)) return 0;
+    if (cfg->precision != SPH_FP64 && cfg->precision != SPH_FP32) return 0;
+    if (!(cfg->rho0 > 0) || !(cfg->mass_q > 0)) return 0;
+    if (cfg->merge_iters < 0 || cfg->merge_iters > 8 || cfg->shift_iters < 0) return 0;
+    return 1;
+}
+
+extern "C" int sph_version(void) { return SPH_VERSION; }
+
+extern "C" size_t sph_workspace_bytes(const sph_config* cfg, int64_t capacity)
+{
+    if (!check_cfg(cfg) || capacity < 0) return 0;
+    Grid g;
+    grid_setup(cfg, &g);
+    Work w;
+    return carve(&w, nullptr, g, capacity);
+}
+
+extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspace,
+                          size_t workspace_bytes, void* stream, sph_ctx** out)
+{
+    if (!out) return SPH_E_INVAL;
+    *out = nullptr;
+    if (!check_cfg(cfg) || capacity < 0 || capacity > (int64_t)INT32_MAX - 1) return SPH_E_INVAL;
+    sph_ctx* c = (sph_ctx*)calloc(1, sizeof(sph_ctx));
+    if (!c) return SPH_E_NOMEM;
+    c->cfg = *cfg;
+    grid_setup(cfg, &c->grid);
+    c->capacity = capacity;
+    c->stream = (hipStream_t)stream;
+    size_t need = carve(&c->w, nullptr, c->grid, capacity);
+    if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) {
+        free(c);
+        return SPH_E_NOMEM;
+    }
+    carve(&c->w, (char*)workspace, c->grid, capacity);
+    c->prof[SPH_PROF_PASS_A].name = "pass_a";
+    c->prof[SPH_PROF_PASS_B].name = "pass_b";
+    c->prof[SPH_PROF_BUILD].name = "build";
+    c->prof[3].name = "unused";
+    *out = c;
+    return SPH_OK;
+}
+
+static void prof_free(sph_ctx* c)
+{
+    if (!c->prof_on) return;
+    for (int s = 0; s < 4; ++s)
+        for (int k = 0; k < 512; ++k) {
+            hipEventDestroy(c->prof[s].ev[0][k]);
+            hipEventDestroy(c->prof[s].ev[1][k]);
+        }
+    c->prof_on = 0;
+}
+
+extern "C" void sph_destroy(sph_ctx* c)
+{
+    if (!c) return;
+    prof_free(c);
+    free(c);
+}
+
+extern "C" const char* sph_last_error(const sph_ctx* c) { return c ? c->err : "no context"; }
+
+extern "C" int sph_set_stream(sph_ctx* c, void* stream)
+{
+    if (!c) return SPH_E_INVAL;
+    c->stream = (hipStream_t)stream;
+    return SPH_OK;
+}
+
+static int check_ps(sph_ctx* c, const sph_particles* ps, int need_state)
+{
+    if (!ps) { set_err(c, "particles is NULL"); return 0; }
+    if (ps->n < 0 || ps->n > ps->capacity || ps->capacity > c->capacity) {
+        set_err(c, "n=%lld capacity=%lld context capacity=%lld", (long long)ps->n,
+                (long long)ps->capacity, (long long)c->capacity);
+        return 0;
+    }
+    if (!ps->x || !ps->y || !ps->h) { set_err(c, "x, y, h must be set"); return 0; }
+    if (need_state && (!ps->u || !ps->v || !ps->p || !ps->mq)) {
+        set_err(c, "u, v, p, mq must be set");
+        return 0;
+    }
+    return 1;
+}
+
+extern "C" int sph_build_neighbors(sph_ctx* c, const sph_particles* ps, sph_csr* out)
+{
+    if (!c) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 0)) return SPH_E_INVAL;
+    int rc = nbr_build(c, (int)ps->n, ps->x, ps->y, ps->h);
+    if (rc || !out) return rc;
+    if (!out->row_ptr || (!out->col && out->nnz_cap > 0)) {
+        set_err(c, "csr arrays not set");
+        return SPH_E_INVAL;
+    }
+    return nbr_export_csr(c, (int)ps->n, out->row_ptr, out->col, out->nnz_cap, &out->nnz);
+}
+
+extern "C" int sph_rates(sph_ctx* c, const sph_particles* ps, double dt, sph_rates_out* out)
+{
+    if (!c || !out) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1)) return SPH_E_INVAL;
+    if (!(dt > 0)) { set_err(c, "dt must be > 0"); return SPH_E_INVAL; }
+    return rates_eval(c, (int)ps->n, ps, dt, out);
+}
+
+extern "C" int sph_step(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps)
+{
+    if (!c) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    if (!(dt > 0) || nsteps < 0) { set_err(c, "dt must be > 0, nsteps >= 0"); return SPH_E_INVAL; }
+    return step_run(c, ps, dt, nsteps);
+}
+
+extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* out)
+{
+    if (!c || !out) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    return diag_run(c, ps, out);
+}
+
+extern "C" int sph_mref_lookup(sph_ctx* c, const sph_particles* ps, const sph_background* bg)
+{
+    if (!c || !bg) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 0) || !ps->mref) return SPH_E_INVAL;
+    return mref_lookup_run(c, ps, bg);
+}
+
+extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map)
+{
+    if (!c || !map) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref) return SPH_E_INVAL;
+    return adapt_run(c, ps, bg, map);
+}
+
+extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles* solids,
+                             const double* phi, double phi_thresh, int32_t passes, int64_t* nsplit)
+{
+    if (!c || !bg || !solids || !nsplit || passes < 0) return SPH_E_INVAL;
+    if (bg->n < 0 || bg->n > bg->capacity || bg->capacity > c->capacity) {
+        set_err(c, "background n/capacity out of range");
+        return SPH_E_INVAL;
+    }
+    return bg_update_run(c, bg, solids, phi, phi_thresh, passes, nsplit);
+}
+
+// ---- profiling -------------------------------------------------------------
+
+static void prof_flush(sph_ctx* c, int slot)
+{
+    ProfSlot& s = c->prof[slot];
+    if (s.count == 0) return;
+    hipEventSynchronize(s.ev[1][s.count - 1]);
+    for (int k = 0; k < s.count; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, s.ev[0][k], s.ev[1][k]) == hipSuccess) s.ms += ms;
+    }
+    s.launches += s.count;
+    s.count = 0;
+}
+
+void prof_begin(sph_ctx* c, int slot)
+{
+    if (!c->prof_on) return;
+    ProfSlot& s = c->prof[slot];
+    if (s.count == 512) prof_flush(c, slot);
+    hipEventRecord(s.ev[0][s.count], c->stream);
+}
+
+void prof_end(sph_ctx* c, int slot)
+{
+    if (!c->prof_on) return;
+    ProfSlot& s = c->prof[slot];
+    hipEventRecord(s.ev[1][s.count], c->stream);
+    s.count++;
+}
+
+extern "C" int sph_profile_enable(sph_ctx* c, int32_t on)
+{
+    if (!c) return SPH_E_INVAL;
+    if (on && !c->prof_on) {
+        for (int s = 0; s < 4; ++s) {
+            for (int k = 0; k < 512; ++k) {
+                HIPCHK(c, hipEventCreate(&c->prof[s].ev[0][k]));
+                HIPCHK(c, hipEventCreate(&c->prof[s].ev[1][k]));
+            }
+            c->prof[s].count = 0;
+            c->prof[s].ms = 0;
+            c->prof[s].launches = 0;
+        }
+        c->prof_on = 1;
+    } else if (!on) {
+        for (int s = 0; s < 4; ++s) prof_flush(c, s);
+        prof_free(c);
+    }
+    return SPH_OK;
+}
+
+extern "C" int sph_profile_reset(sph_ctx* c)
+{
+    if (!c) return SPH_E_INVAL;
+    if (!c->prof_on) return SPH_OK;
+    for (int s = 0; s < 4; ++s) {
+        prof_flush(c, s);
+        c->prof[s].ms = 0;
+        c->prof[s].launches = 0;
+    }
+    return SPH_OK;
+}
+
+extern "C" int sph_profile_read(sph_ctx* c, const char* kernel, double* ms, int64_t* launches)
+{
+    if (!c || !kernel || !ms || !launches) return SPH_E_INVAL;
+    for (int s = 0; s < 4; ++s) {
+        if (strcmp(c->prof[s].name, kernel) == 0) {
+            if (c->prof_on) prof_flush(c, s);
+            *ms = c->prof[s].ms;
+            *launches = c->prof[s].launches;
+            return SPH_OK;
+        }
+    }
+    set_err(c, "unknown kernel name %s", kernel);
+    return SPH_E_INVAL;
+}

@@ -1,0 +1,551 @@
+// Neighbour search for variable smoothing length on gfx950: level/Morton
+// keys, stable LSD radix sort, per-(level, resolution) cell-run tables and
+// CSR export.  The neighbour relation is |r_i - r_j| < 3 max(h_i, h_j) with
+// the quintic support of eq. (kernel); it is symmetric because the rates of
+// eqs. (edac:sph) and (mom-sph) use both W(h_i) and W(h_j).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "sph_device.h"
+
+// ---------------------------------------------------------------------------
+// Grid geometry (host)
+// ---------------------------------------------------------------------------
+
+void grid_setup(const sph_config* cfg, Grid* g)
+{
+    memset(g, 0, sizeof(*g));
+    double hlo = cfg->h_lo > 0 ? cfg->h_lo : 1e-3;
+    double hhi = cfg->h_hi > hlo ? cfg->h_hi : hlo;
+    double cmin = 3.0 * hlo * (1.0 + 1e-9);
+    for (int a = 0; a < 2; ++a) {
+        double L = cfg->hi[a] - cfg->lo[a];
+        g->lo[a] = cfg->lo[a];
+        g->hi[a] = cfg->hi[a];
+        g->periodic[a] = cfg->periodic[a] ? 1 : 0;
+        g->L[a] = L;
+        g->half[a] = 0.5 * L;
+        g->org[a] = cfg->lo[a];
+    }
+    // keep the finest table modest: at most 2^25 level-0 cells
+    for (;;) {
+        double n0 = 1, n1 = 1;
+        for (int a = 0; a < 2; ++a) {
+            double L = g->L[a];
+            double nx = g->periodic[a] ? floor(L / cmin) : floor(L / cmin) + 1;
+            if (nx < 1) nx = 1;
+            (a ? n1 : n0) = nx;
+        }
+        if (n0 * n1 <= (double)(1 << 25)) break;
+        cmin *= 2.0;
+    }
+    for (int a = 0; a < 2; ++a) {
+        double L = g->L[a];
+        if (g->periodic[a]) {
+            int nx = (int)floor(L / cmin);
+            if (nx < 1) nx = 1;
+            g->nx0[a] = nx;
+            g->cw0[a] = L / nx;
+        } else {
+            g->nx0[a] = (int)floor(L / cmin) + 1;
+            g->cw0[a] = cmin;
+        }
+    }
+    g->cmin0 = g->cw0[0] < g->cw0[1] ? g->cw0[0] : g->cw0[1];
+    int nlev = 1;
+    double c = g->cmin0;
+    while (c < 3.0 * hhi * (1.0 + 1e-9) && nlev < SPH_MAXL) {
+        c *= 2.0;
+        ++nlev;
+    }
+    g->nlev = nlev;
+    int mx = g->nx0[0] > g->nx0[1] ? g->nx0[0] : g->nx0[1];
+    int bits = 1;
+    while ((1 << bits) < mx) ++bits;
+    g->bits = bits;
+    g->cumq[0] = 0;
+    for (int q = 0; q < SPH_MAXL; ++q) {
+        for (int a = 0; a < 2; ++a) g->nxq[q][a] = ((g->nx0[a] - 1) >> q) + 1;
+        g->cumq[q + 1] = g->cumq[q] + (int64_t)g->nxq[q][0] * g->nxq[q][1];
+    }
+    int64_t acc = 0;
+    for (int l = 0; l < nlev; ++l) {
+        g->lbase[l] = acc - g->cumq[l];
+        acc += g->cumq[nlev] - g->cumq[l];
+    }
+    g->tab_total = acc;
+}
+
+static int key_bits(const Grid* g)
+{
+    int lb = 0;
+    while ((1 << lb) < g->nlev) ++lb;
+    return 2 * g->bits + lb;
+}
+
+#define RS_THREADS 256
+#define RS_ITEMS 8
+#define RS_TILE (RS_THREADS * RS_ITEMS)
+#define SCAN_T 256
+#define SCAN_E 8
+#define SCAN_TILE (SCAN_T * SCAN_E)
+
+size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g)
+{
+    (void)cfg;
+    int64_t nb = cdiv(capacity > 0 ? capacity : 1, RS_TILE);
+    size_t b = 0;
+    b += (size_t)g->tab_total * sizeof(int2) + 256;
+    b += (size_t)256 * nb * sizeof(uint32_t) + 256;
+    return b;
+}
+
+// ---------------------------------------------------------------------------
+// Scans (exclusive; output has n + 1 entries, out[n] = total)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_T) void k_scan_block(const T* in, T* out, int64_t n_in,
+                                                       int64_t n_out, T* bsum)
+{
+    __shared__ T wsum[SCAN_T / 64];
+    const int t = threadIdx.x, lane = __lane_id(), wid = t >> 6;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)t * SCAN_E;
+    T v[SCAN_E];
+    T tot = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_E; ++k) {
+        int64_t i = base + k;
+        v[k] = (i < n_in) ? in[i] : T(0);
+        tot += v[k];
+    }
+    T incl = wave_incl_scan<T>(tot);
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    if (wid == 0) {
+        T w = lane < SCAN_T / 64 ? wsum[lane] : T(0);
+        w = wave_incl_scan<T>(w);
+        if (lane < SCAN_T / 64) wsum[lane] = w;
+    }
+    __syncthreads();
+    T run = incl - tot + (wid > 0 ? wsum[wid - 1] : T(0));
+#pragma unroll
+    for (int k = 0; k < SCAN_E; ++k) {
+        int64_t i = base + k;
+        if (i < n_out) out[i] = run;
+        run += v[k];
+    }
+    if (t == SCAN_T - 1) bsum[blockIdx.x] = wsum[SCAN_T / 64 - 1];
+}
+
+template <typename T>
+__global__ void k_scan_add(T* out, int64_t n_out, const T* boff)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_out) out[i] += boff[i / SCAN_TILE];
+}
+
+// Exclusive scan of in[0, n_in) into out[0, n_out) (n_out >= n_in; entries
+// past n_in scan zeros).  tmp needs about 2 * n_out / SCAN_TILE + 64 entries.
+template <typename T>
+static int scan_rec(sph_ctx* c, const T* in, T* out, int64_t n_in, int64_t n_out, T* tmp)
+{
+    int64_t nb = cdiv(n_out, SCAN_TILE);
+    hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, c->stream, in, out,
+                       n_in, n_out, tmp);
+    LAUNCHCHK(c, "scan_block");
+    if (nb > 1) {
+        int rc = scan_rec<T>(c, tmp, tmp, nb, nb, tmp + nb);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)cdiv(n_out, 256)), dim3(256), 0, c->stream,
+                           out, n_out, tmp);
+        LAUNCHCHK(c, "scan_add");
+    }
+    return SPH_OK;
+}
+
+int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n)
+{
+    return scan_rec<int64_t>(c, in, out, n, n + 1, c->w.scan_tmp);
+}
+
+int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n)
+{
+    return scan_rec<int32_t>(c, in, out, n, n + 1, (int32_t*)c->w.scan_tmp);
+}
+
+// ---------------------------------------------------------------------------
+// Keys
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ h, uint64_t* keys,
+                                              int32_t* vals, unsigned long long* hmax_bits,
+                                              int32_t* lcount)
+{
+    __shared__ unsigned long long s_h[SPH_MAXL];
+    __shared__ int32_t s_c[SPH_MAXL];
+    if (threadIdx.x < SPH_MAXL) {
+        s_h[threadIdx.x] = 0ull;
+        s_c[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        double hi = h[i];
+        int l = level_of(g, hi);
+        uint32_t kx = (uint32_t)cell0(g, 0, x[i]);
+        uint32_t ky = (uint32_t)cell0(g, 1, y[i]);
+        uint64_t m = spread2(kx) | (spread2(ky) << 1);
+        keys[i] = ((uint64_t)l << (2 * g.bits)) | m;
+        vals[i] = i;
+        atomicMax(&s_h[l], (unsigned long long)__double_as_longlong(hi));
+        atomicAdd(&s_c[l], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)g.nlev && s_c[threadIdx.x] > 0) {
+        atomicMax(&hmax_bits[threadIdx.x], s_h[threadIdx.x]);
+        atomicAdd(&lcount[threadIdx.x], s_c[threadIdx.x]);
+    }
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_zero_int2(int2* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = make_int2(0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits.  Each block owns RS_TILE consecutive
+// keys; each wave owns a contiguous quarter of the tile and ranks its keys
+// with 8 ballots per 64-key chunk (lanes with equal digits), so the order of
+// equal digits is the input order.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int n,
+                                                        int shift, uint32_t* hist, int nblk)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int base = blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        int i = base + k * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                           const int32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout,
+                                                           int32_t* __restrict__ vout, int n,
+                                                           int shift,
+                                                           const uint32_t* __restrict__ offs,
+                                                           int nblk)
+{
+    constexpr int NW = RS_THREADS / 64;
+    __shared__ uint32_t wcnt[NW][256];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < NW * 256; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int wbase = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS);
+    uint64_t kk[RS_ITEMS];
+    int32_t vv[RS_ITEMS];
+    uint32_t dd[RS_ITEMS], rk[RS_ITEMS];
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        int i = wbase + it * 64 + lane;
+        bool valid = i < n;
+        uint64_t k = valid ? kin[i] : 0ull;
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            mask &= bit ? bal : ~bal;
+        }
+        uint32_t before = (uint32_t)__popcll(mask & lt_mask);
+        uint32_t cnt = (uint32_t)__popcll(mask);
+        uint32_t old = valid ? wcnt[w][d] : 0u;
+        // all lanes have read the running count before the group leader
+        // (lowest lane of its digit group) advances it
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) wcnt[w][d] = old + cnt;
+        __builtin_amdgcn_wave_barrier();
+        kk[it] = k;
+        vv[it] = valid ? vin[i] : 0;
+        dd[it] = valid ? d : 256u;
+        rk[it] = old + before;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            uint32_t t = wcnt[q][threadIdx.x];
+            wcnt[q][threadIdx.x] = s;
+            s += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        uint32_t d = dd[it];
+        if (d < 256u) {
+            uint32_t pos = offs[(int64_t)d * nblk + blockIdx.x] + wcnt[w][d] + rk[it];
+            kout[pos] = kk[it];
+            vout[pos] = vv[it];
+        }
+    }
+}
+
+// Sorts (keys, vals) of length n; the result ends in (keys_a, vals_a).
+static int radix_sort(sph_ctx* c, int n, int keybits)
+{
+    Work& w = c->w;
+    int nblk = (int)cdiv(n, RS_TILE);
+    int npass = (keybits + 7) / 8;
+    uint64_t *ka = w.keys_a, *kb = w.keys_b;
+    int32_t *va = w.vals_a, *vb = w.vals_b;
+    for (int p = 0; p < npass; ++p) {
+        int shift = 8 * p;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, n, shift,
+                           w.hist, nblk);
+        LAUNCHCHK(c, "rs_hist");
+        int rc = scan_rec<uint32_t>(c, w.hist, w.hist, (int64_t)256 * nblk, (int64_t)256 * nblk,
+                                    (uint32_t*)w.scan_tmp);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, va, kb,
+                           vb, n, shift, w.hist, nblk);
+        LAUNCHCHK(c, "rs_scatter");
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    if (ka != w.keys_a) {
+        HIPCHK(c, hipMemcpyAsync(w.keys_a, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(w.vals_a, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Cell-run tables and sorted shadows
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* __restrict__ keys,
+                                                int2* tab)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int sh = 2 * g.bits;
+    const uint64_t mmask = (sh >= 64) ? ~0ull : ((1ull << sh) - 1ull);
+    uint64_t key = keys[s];
+    int l = (int)(key >> sh);
+    uint64_t m = key & mmask;
+    uint64_t kp = s > 0 ? keys[s - 1] : ~0ull;
+    uint64_t kn = s < n - 1 ? keys[s + 1] : ~0ull;
+    bool lp = s > 0 && (int)(kp >> sh) == l;
+    bool ln = s < n - 1 && (int)(kn >> sh) == l;
+    for (int Q = l; Q < g.nlev; ++Q) {
+        uint64_t cell = m >> (2 * Q);
+        bool sp = lp && ((kp & mmask) >> (2 * Q)) == cell;
+        bool sn = ln && ((kn & mmask) >> (2 * Q)) == cell;
+        if (sp && sn) continue;
+        int cx = (int)compact2(cell), cy = (int)compact2(cell >> 1);
+        int64_t idx = g.lbase[l] + g.cumq[Q] + (int64_t)cy * g.nxq[Q][0] + cx;
+        if (!sp) tab[idx].x = s;
+        if (!sn) tab[idx].y = s + 1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather_pos(int n, const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ h, double* xs,
+                                                    double* ys, double* hs)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    xs[s] = x[i];
+    ys[s] = y[i];
+    hs[s] = h[i];
+}
+
+int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+{
+    Work& w = c->w;
+    const Grid& g = c->grid;
+    prof_begin(c, SPH_PROF_BUILD);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, w.hmax_bits, (int64_t)SPH_MAXL);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.lcount, (int64_t)SPH_MAXL);
+    hipLaunchKernelGGL(k_zero_int2, dim3((unsigned)cdiv(g.tab_total, 256)), dim3(256), 0, c->stream,
+                       w.tab, g.tab_total);
+    LAUNCHCHK(c, "zero");
+    if (n > 0) {
+        hipLaunchKernelGGL(k_keys, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n, x, y,
+                           h, w.keys_a, w.vals_a, w.hmax_bits, w.lcount);
+        LAUNCHCHK(c, "keys");
+        int rc = radix_sort(c, n, key_bits(&g));
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
+                           w.keys_a, w.tab);
+        hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
+                           w.vals_a, x, y, h, w.xs, w.ys, w.hs);
+        LAUNCHCHK(c, "tables");
+    }
+    prof_end(c, SPH_PROF_BUILD);
+    c->built_n = n;
+    return SPH_OK;
+}
+
+NbrView nbr_view(sph_ctx* c)
+{
+    NbrView v;
+    v.xs = c->w.xs;
+    v.ys = c->w.ys;
+    v.hs = c->w.hs;
+    v.perm = c->w.vals_a;
+    v.keys = c->w.keys_a;
+    v.tab = c->w.tab;
+    v.hmax_bits = c->w.hmax_bits;
+    v.lcount = c->w.lcount;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// CSR export: count, scan, fill, sort rows ascending
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_csr_count(Grid g, NbrView nv, int n, int64_t* cnt)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
+    int li = key_level(g, nv.keys[s]);
+    int64_t k = 0;
+    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int, double, double, double, double) { ++k; });
+    cnt[nv.perm[s]] = k;
+}
+
+__global__ __launch_bounds__(256) void k_csr_fill(Grid g, NbrView nv, int n,
+                                                  const int64_t* __restrict__ rp, int32_t* col)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
+    int li = key_level(g, nv.keys[s]);
+    int64_t k = rp[nv.perm[s]];
+    for_each_neighbor(g, nv, xi, yi, hi, li,
+                      [&](int js, double, double, double, double) { col[k++] = nv.perm[js]; });
+}
+
+// One wave per row: bitonic sort across the 64 lanes for rows of <= 64
+// entries; longer rows are listed for the per-thread path.
+__global__ __launch_bounds__(256) void k_sort_rows(int n, const int64_t* __restrict__ rp,
+                                                   int32_t* col, int32_t* long_rows,
+                                                   int32_t* n_long)
+{
+    const int lane = __lane_id();
+    int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    int64_t beg = rp[row];
+    int len = (int)(rp[row + 1] - beg);
+    if (len > 64) {
+        if (lane == 0) long_rows[atomicAdd(n_long, 1)] = row;
+        return;
+    }
+    int v = lane < len ? col[beg + lane] : 0x7fffffff;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            int o = __shfl_xor(v, j, 64);
+            bool up = (lane & k) == 0;
+            bool low = (lane & j) == 0;
+            v = (low == up) ? min(v, o) : max(v, o);
+        }
+    }
+    if (lane < len) col[beg + lane] = v;
+}
+
+__global__ void k_sort_long_rows(const int64_t* __restrict__ rp, int32_t* col,
+                                 const int32_t* long_rows, const int32_t* n_long)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *n_long) return;
+    int row = long_rows[t];
+    int64_t b = rp[row], e = rp[row + 1];
+    for (int64_t i = b + 1; i < e; ++i) {
+        int v = col[i];
+        int64_t j = i - 1;
+        while (j >= b && col[j] > v) {
+            col[j + 1] = col[j];
+            --j;
+        }
+        col[j + 1] = v;
+    }
+}
+
+int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz)
+{
+    Work& w = c->w;
+    const Grid& g = c->grid;
+    NbrView nv = nbr_view(c);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_csr_count, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv,
+                           n, w.cnt64);
+        LAUNCHCHK(c, "csr_count");
+    }
+    int rc = scan_exclusive_i64(c, w.cnt64, row_ptr, n);
+    if (rc) return rc;
+    int64_t tot = 0;
+    HIPCHK(c, hipMemcpyAsync(&tot, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *nnz = tot;
+    if (tot > cap) {
+        set_err(c, "neighbour list needs %lld entries, capacity %lld", (long long)tot, (long long)cap);
+        return SPH_E_CAPACITY;
+    }
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv, n,
+                       row_ptr, col);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.status, (int64_t)1);
+    hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, c->stream, n, row_ptr,
+                       col, w.long_rows, w.status);
+    hipLaunchKernelGGL(k_sort_long_rows, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream,
+                       row_ptr, col, w.long_rows, w.status);
+    LAUNCHCHK(c, "csr_fill");
+    return SPH_OK;
+}

@@ -1,0 +1,421 @@
+// Rate evaluation and time stepping on gfx950.
+//
+// Pass A (per particle, gather over its neighbours): summation density
+// (eq. sd-gather), the variable-h correction beta (eq. beta, d = 2), the
+// neighbour count and average pressure (eq. pavg) and the limited Lind
+// shifting displacement (eqs. shift-deltar, shift-limit).
+// Pass B: EDAC pressure rate (eq. edac:sph) and momentum (eq. mom-sph) with
+// the averaged kernel gradient (eq. dw-avg), the harmonic EDAC viscosity
+// (eqs. edac-alpha, nu-cleary), the pressure reduction of eq. (mom:pre) and
+// the transport-velocity term u~ - u = dr/dt (eq. shift-tvf).
+// Readings: the EDAC diffusion term is divided by (r^2 + eta_i) like the
+// viscous term; A_i, A_j and the third line of eq. (mom-sph) are not used
+// (the remark after eq. mom-corr); both P_i and P_j subtract p_avg,i.
+//
+// Pair arithmetic is templated on T (float or double).  Position, velocity
+// and pressure differences are always formed in double and then converted,
+// and the density, pressure, beta, shifting and divergence sums use
+// Neumaier compensation in float.  The neighbour predicate is always the
+// double-precision one.
+#include <math.h>
+
+#include "sph_device.h"
+
+template <typename T>
+struct RatesBufs {
+    T *m, *rho, *beta, *dpav, *dxs, *dys, *V, *B, *ih, *nnb;
+    double *ps;     // sorted pressure (double)
+};
+
+template <typename T>
+static RatesBufs<T> rbufs(sph_ctx* c)
+{
+    Work& w = c->w;
+    RatesBufs<T> b;
+    b.m = (T*)w.sc0;
+    b.rho = (T*)w.sc2;
+    b.beta = (T*)w.sc3;
+    b.dpav = (T*)w.sc4;
+    b.dxs = (T*)w.sc5;
+    b.dys = (T*)w.sc6;
+    b.V = (T*)w.sc7;
+    b.B = (T*)w.sc8;
+    b.ih = (T*)w.sc10;
+    b.nnb = (T*)w.sc11;
+    b.ps = w.sc1;
+    return b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ u,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ p,
+                                                      const int64_t* __restrict__ mq, double mass_q,
+                                                      const double* __restrict__ hs, double* us,
+                                                      double* vs, double* ps, T* ms, T* ih)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int i = perm[s];
+    us[s] = u[i];
+    vs[s] = v[i];
+    ps[s] = p[i];
+    ms[s] = (T)((double)mq[i] * mass_q);
+    ih[s] = (T)(1.0 / hs[s]);
+}
+
+struct PassAOut {
+    double *rho, *beta, *pavg, *nnb, *dxs, *dys; // slot order, optional
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
+                                                const double* __restrict__ us, double rho0,
+                                                PassAOut out, double* r_dxs, double* r_dys)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s], pi = b.ps[s];
+    const int li = key_level(g, nv.keys[s]);
+    const T ih = b.ih[s];
+    const T sig = T(SPH_SIGMA2) * ih * ih;
+    const T irho0 = T(1.0 / rho0);
+    const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
+    CSum<T> sr, sb, sp, sx, sy;
+    int cnt = 0;
+    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+        const T mj = b.m[js];
+        const T r = fsqrt<T>((T)r2);
+        const T q = r * ih;
+        sr.add(mj * (sig * kern_f<T>(q)));
+        sb.add(mj * r * (sig * ih * kern_fp<T>(q)));
+        sp.add((T)(b.ps[js] - pi));
+        ++cnt;
+        if (r > T(0)) {
+            const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
+            const T qij = r * ihij;
+            const T wr = kern_f<T>(qij) * ifxi;
+            const T wr2 = wr * wr;
+            const T coef = (mj * irho0) * (T(1) + T(0.24) * (wr2 * wr2));
+            const T dwij = T(SPH_SIGMA2) * ihij * ihij * ihij * kern_fp<T>(qij);
+            const T t = coef * dwij * rcp<T>(r);
+            sx.add(t * (T)dx);
+            sy.add(t * (T)dy);
+        }
+    });
+    const T rho = sr.get();
+    const T beta = -sb.get() / (T(2) * rho);
+    const T N = (T)cnt;
+    const T dpav = sp.get() / N;
+    const T pref = T(-0.5) * (T)(hi * hi);
+    T ddx = pref * sx.get(), ddy = pref * sy.get();
+    const T mag = fsqrt<T>(ddx * ddx + ddy * ddy);
+    const T lim = T(0.25) * (T)hi;
+    if (mag > lim) {
+        const T th = lim / mag;
+        ddx *= th;
+        ddy *= th;
+    }
+    b.rho[s] = rho;
+    b.beta[s] = beta;
+    b.dpav[s] = dpav;
+    b.dxs[s] = ddx;
+    b.dys[s] = ddy;
+    b.nnb[s] = N;
+    // per-particle factors for pass B
+    b.V[s] = b.m[s] / rho;
+    // beta <= 0 only when no neighbour lies inside the particle's own
+    // support: its pressure term is taken as zero (and so are its 1/beta sums)
+    b.B[s] = beta > T(0) ? T(1) / (rho * rho * beta) : T(0);
+    const int slot = nv.perm[s];
+    r_dxs[slot] = (double)ddx;
+    r_dys[slot] = (double)ddy;
+    if (out.rho) out.rho[slot] = (double)rho;
+    if (out.beta) out.beta[slot] = (double)beta;
+    if (out.pavg) out.pavg[slot] = pi + (double)dpav;
+    if (out.nnb) out.nnb[slot] = (double)cnt;
+    if (out.dxs) out.dxs[slot] = (double)ddx;
+    if (out.dys) out.dys[slot] = (double)ddy;
+    (void)us;
+}
+
+struct PassBParams {
+    double rho0, cs, nu, alpha_e, fx, fy, dt;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
+                                                const double* __restrict__ us,
+                                                const double* __restrict__ vs, PassBParams P,
+                                                double* dpdt, double* dudt, double* dvdt)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
+    const double ui = us[s], vi = vs[s], pi = b.ps[s];
+    const int li = key_level(g, nv.keys[s]);
+    const T ih = b.ih[s];
+    const T sigi = T(SPH_SIGMA2) * ih * ih * ih;
+    const T rhoi = b.rho[s];
+    const T dpav = b.dpav[s];
+    const T Bi = b.B[s];
+    const T Pi = -dpav * Bi;
+    const T aecs8 = (T)(P.alpha_e * P.cs / 8.0);
+    const T nui = aecs8 * (T)hi;
+    const T eta = (T)(0.001 * hi * hi);
+    const T nu4 = (T)(4.0 * P.nu);
+    CSum<T> sdiv, sdif;
+    T gx = 0, gy = 0, vx = 0, vy = 0;
+    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+        const T r = fsqrt<T>((T)r2);
+        if (!(r > T(0))) return;  // the self pair contributes nothing
+        const T ir = rcp<T>(r);
+        const T ihj = b.ih[js];
+        const T dwi = sigi * kern_fp<T>(r * ih);
+        const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * kern_fp<T>(r * ihj);
+        const T fi = dwi * ir, fj = dwj * ir;
+        const T dxT = (T)dx, dyT = (T)dy;
+        const T uij = (T)(ui - us[js]), vij = (T)(vi - vs[js]);
+        const T dpij = (T)(pi - b.ps[js]);
+        const T Vj = b.V[js], mj = b.m[js];
+        const T Pj = (-dpij - dpav) * b.B[js];
+        const T nuj = aecs8 * (T)hj;
+        const T nuij = T(4) * nui * nuj * rcp<T>(nui + nuj);
+        const T rdotg = T(0.5) * (dwi + dwj) * r;
+        const T iden = rcp<T>((T)r2 + eta);
+        sdiv.add(Vj * (fi * (uij * dxT + vij * dyT)));
+        sdif.add(Vj * nuij * dpij * rdotg * iden);
+        const T gf = mj * (Pi * fi + Pj * fj);
+        gx += gf * dxT;
+        gy += gf * dyT;
+        const T cv = mj * nu4 * rcp<T>(rhoi + b.rho[js]) * rdotg * iden;
+        vx += cv * uij;
+        vy += cv * vij;
+    });
+    const T beta = b.beta[s];
+    const T ib = beta > T(0) ? T(1) / beta : T(0);
+    const double dxs = (double)b.dxs[s], dys = (double)b.dys[s];
+    const int slot = nv.perm[s];
+    dpdt[slot] = (double)((T)(P.rho0 * P.cs * P.cs) * ib * sdiv.get() + sdif.get() * ib) +
+                 (dxs / P.dt) * (double)gx + (dys / P.dt) * (double)gy;
+    dudt[slot] = (double)(-gx + vx * ib) + P.fx;
+    dvdt[slot] = (double)(-gy + vy * ib) + P.fy;
+}
+
+// One evaluation on (x, y, u, v, p, h, mq): build + pass A + pass B.
+template <typename T>
+static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const double* u,
+                  const double* v, const double* p, const double* h, const int64_t* mq, double dt,
+                  PassAOut aout, double* dpdt, double* dudt, double* dvdt)
+{
+    Work& w = c->w;
+    int rc = nbr_build(c, n, x, y, h);
+    if (rc) return rc;
+    if (n == 0) return SPH_OK;
+    NbrView nv = nbr_view(c);
+    RatesBufs<T> b = rbufs<T>(c);
+    const sph_config& cf = c->cfg;
+    unsigned nb = (unsigned)cdiv(n, 256);
+    hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
+                       cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih);
+    LAUNCHCHK(c, "gather_state");
+    prof_begin(c, SPH_PROF_PASS_A);
+    hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b,
+                       (const double*)w.us, cf.rho0, aout, w.r_dxs, w.r_dys);
+    prof_end(c, SPH_PROF_PASS_A);
+    LAUNCHCHK(c, "pass_a");
+    PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
+    prof_begin(c, SPH_PROF_PASS_B);
+    hipLaunchKernelGGL(k_pass_b<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b,
+                       (const double*)w.us, (const double*)w.vs, P, dpdt, dudt, dvdt);
+    prof_end(c, SPH_PROF_PASS_B);
+    LAUNCHCHK(c, "pass_b");
+    return SPH_OK;
+}
+
+static int eval(sph_ctx* c, int n, const double* x, const double* y, const double* u,
+                const double* v, const double* p, const double* h, const int64_t* mq, double dt,
+                PassAOut aout, double* dpdt, double* dudt, double* dvdt)
+{
+    if (c->cfg.precision == SPH_FP32)
+        return eval_T<float>(c, n, x, y, u, v, p, h, mq, dt, aout, dpdt, dudt, dvdt);
+    return eval_T<double>(c, n, x, y, u, v, p, h, mq, dt, aout, dpdt, dudt, dvdt);
+}
+
+int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out)
+{
+    Work& w = c->w;
+    PassAOut a{out->rho, out->beta, out->pavg, out->nnb, out->dxs, out->dys};
+    int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, dt, a, w.r_dpdt, w.r_dudt,
+                  w.r_dvdt);
+    if (rc) return rc;
+    if (n > 0) {
+        if (out->dpdt)
+            HIPCHK(c, hipMemcpyAsync(out->dpdt, w.r_dpdt, 8 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+        if (out->dudt)
+            HIPCHK(c, hipMemcpyAsync(out->dudt, w.r_dudt, 8 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+        if (out->dvdt)
+            HIPCHK(c, hipMemcpyAsync(out->dvdt, w.r_dvdt, 8 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Predict-evaluate-correct, eqs. (int-pre) and (int-cor), in double.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* __restrict__ kind,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ u,
+                                                 const double* __restrict__ v,
+                                                 const double* __restrict__ p,
+                                                 const double* __restrict__ ap,
+                                                 const double* __restrict__ au,
+                                                 const double* __restrict__ av,
+                                                 const double* __restrict__ dxs,
+                                                 const double* __restrict__ dys, double dt,
+                                                 double* xh, double* yh, double* uh, double* vh,
+                                                 double* ph)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (kind && kind[i] != SPH_FLUID) {
+        xh[i] = x[i]; yh[i] = y[i]; uh[i] = u[i]; vh[i] = v[i]; ph[i] = p[i];
+        return;
+    }
+    double un = u[i] + 0.5 * dt * au[i];
+    double vn = v[i] + 0.5 * dt * av[i];
+    double tu = un + dxs[i] / dt;
+    double tv = vn + dys[i] / dt;
+    xh[i] = wrap_axis(g, 0, x[i] + 0.5 * dt * tu);
+    yh[i] = wrap_axis(g, 1, y[i] + 0.5 * dt * tv);
+    uh[i] = un;
+    vh[i] = vn;
+    ph[i] = p[i] + 0.5 * dt * ap[i];
+}
+
+__global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* __restrict__ kind,
+                                                 double* x, double* y, double* u, double* v,
+                                                 double* p, const double* __restrict__ ap,
+                                                 const double* __restrict__ au,
+                                                 const double* __restrict__ av,
+                                                 const double* __restrict__ dxs,
+                                                 const double* __restrict__ dys, double dt)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (kind && kind[i] != SPH_FLUID) return;
+    double un = u[i] + dt * au[i];
+    double vn = v[i] + dt * av[i];
+    double tu = un + dxs[i] / dt;
+    double tv = vn + dys[i] / dt;
+    x[i] = wrap_axis(g, 0, x[i] + dt * tu);
+    y[i] = wrap_axis(g, 1, y[i] + dt * tv);
+    u[i] = un;
+    v[i] = vn;
+    p[i] = p[i] + dt * ap[i];
+}
+
+int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    if (n == 0) return SPH_OK;
+    unsigned nb = (unsigned)cdiv(n, 256);
+    PassAOut none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    for (int s = 0; s < nsteps; ++s) {
+        int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, dt, none, w.r_dpdt,
+                      w.r_dudt, w.r_dvdt);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_predict, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
+                           ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
+                           w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph);
+        LAUNCHCHK(c, "predict");
+        rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, dt,
+                  s == nsteps - 1 ? withrho : none, w.r_dpdt, w.r_dudt, w.r_dvdt);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_correct, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
+                           ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
+                           w.r_dys, dt);
+        LAUNCHCHK(c, "correct");
+    }
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: deterministic two-stage reductions.
+// ---------------------------------------------------------------------------
+
+#define DIAG_BLOCKS 256
+
+__global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __restrict__ u,
+                                                      const double* __restrict__ v,
+                                                      const double* __restrict__ rho,
+                                                      const int64_t* __restrict__ mq,
+                                                      double mass_q, double* part,
+                                                      int64_t* partq)
+{
+    __shared__ double sh[5][256];
+    __shared__ int64_t sq[256];
+    double ke = 0, vol = 0, mx = 0, my = 0, um = 0;
+    int64_t q = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double m = (double)mq[i] * mass_q;
+        double s2 = u[i] * u[i] + v[i] * v[i];
+        ke += 0.5 * m * s2;
+        vol += m / rho[i];
+        mx += m * u[i];
+        my += m * v[i];
+        um = fmax(um, sqrt(s2));
+        q += mq[i];
+    }
+    int t = threadIdx.x;
+    sh[0][t] = ke; sh[1][t] = vol; sh[2][t] = mx; sh[3][t] = my; sh[4][t] = um; sq[t] = q;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) {
+            for (int k = 0; k < 4; ++k) sh[k][t] += sh[k][t + o];
+            sh[4][t] = fmax(sh[4][t], sh[4][t + o]);
+            sq[t] += sq[t + o];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        for (int k = 0; k < 5; ++k) part[k * DIAG_BLOCKS + blockIdx.x] = sh[k][0];
+        partq[blockIdx.x] = sq[0];
+    }
+}
+
+int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    double* part = w.sc9;  // 5 * DIAG_BLOCKS doubles
+    int64_t* partq = w.red;
+    hipLaunchKernelGGL(k_diag_partial, dim3(DIAG_BLOCKS), dim3(256), 0, c->stream, n, ps->u, ps->v,
+                       ps->rho, ps->mq, c->cfg.mass_q, part, partq);
+    LAUNCHCHK(c, "diag");
+    double hp[5 * DIAG_BLOCKS];
+    int64_t hq[DIAG_BLOCKS];
+    HIPCHK(c, hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hq, partq, sizeof(hq), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double r[5] = {0, 0, 0, 0, 0};
+    int64_t q = 0;
+    for (int b = 0; b < DIAG_BLOCKS; ++b) {
+        for (int k = 0; k < 4; ++k) r[k] += hp[k * DIAG_BLOCKS + b];
+        r[4] = r[4] > hp[4 * DIAG_BLOCKS + b] ? r[4] : hp[4 * DIAG_BLOCKS + b];
+        q += hq[b];
+    }
+    out->ke = r[0];
+    out->vol = r[1];
+    out->mom_x = r[2];
+    out->mom_y = r[3];
+    out->umax = r[4];
+    out->mq_total = q;
+    out->n = n;
+    return SPH_OK;
+}

@@ -1,0 +1,146 @@
+// Internal declarations of the gfx950 SPH library (not part of the C ABI).
+//
+// Neighbour search layout.  Particles are binned by smoothing-length level:
+// level l holds particles with 3 h <= c0 * 2^l (c0 = finest cell width), so
+// a pair of particles at levels <= l is closer than one level-l cell when it
+// interacts.  All levels share one nested grid: a level-Q cell is a 2^Q x 2^Q
+// block of level-0 cells.  Particles are radix-sorted by the key
+// (level, Morton code of the level-0 cell), so the particles of any level
+// inside any cell of any resolution Q form one contiguous run of the sorted
+// order.  For every level l and every resolution Q >= l a dense table gives
+// that run (start, end) per cell.  Particle i visits level l with search
+// radius 3 max(h_i, hmax_l) at resolution max(l, l_i): a 3x3 (or smaller)
+// block of cells per level, from whichever side of the pair is coarser.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sph.h"
+
+#define SPH_MAXL 16
+
+struct Grid {
+    double org[2];      // origin of the level-0 grid per axis
+    double cw0[2];      // level-0 cell width per axis
+    double L[2];        // period per axis (periodic axes)
+    double half[2];     // L/2
+    double lo[2], hi[2];
+    double cmin0;       // min(cw0[0], cw0[1])
+    int32_t nx0[2];     // level-0 cells per axis
+    int32_t periodic[2];
+    int32_t nlev;       // number of levels
+    int32_t bits;       // Morton bits per axis
+    int32_t nxq[SPH_MAXL][2];   // cells per axis at resolution Q
+    int64_t cumq[SPH_MAXL + 1]; // prefix of cells(Q)
+    int64_t lbase[SPH_MAXL];    // table offset(l, Q) = lbase[l] + cumq[Q]
+    int64_t tab_total;          // int2 entries over all (l, Q >= l)
+};
+
+// Device view of a built neighbour structure (all in sorted order).
+struct NbrView {
+    const double* xs;     // positions and smoothing lengths, sorted order
+    const double* ys;
+    const double* hs;
+    const int32_t* perm;  // sorted position -> slot
+    const uint64_t* keys; // sorted keys (level in the high bits)
+    const int2* tab;      // cell run tables
+    const unsigned long long* hmax_bits; // per-level max h (bit pattern)
+    const int32_t* lcount;               // per-level particle count
+};
+
+// Workspace carve-out (device pointers).
+struct Work {
+    uint64_t *keys_a, *keys_b;
+    int32_t *vals_a, *vals_b;
+    uint32_t* hist;        // radix digit counts
+    int64_t* scan_tmp;     // block sums for scans
+    int2* tab;
+    unsigned long long* hmax_bits;
+    int32_t* lcount;
+    int32_t* status;       // [0] overflow rows count, [1] nonfinite flag, ...
+    int32_t* long_rows;    // rows needing the long-row sort path
+    double *xs, *ys, *hs;  // sorted shadows
+    double *us, *vs;       // sorted velocity (double: differences taken in FP64)
+    double *sc0, *sc1, *sc2, *sc3, *sc4, *sc5, *sc6, *sc7, *sc8, *sc9, *sc10, *sc11; // typed scratch
+    double *r_dpdt, *r_dudt, *r_dvdt, *r_dxs, *r_dys; // rates in slot order
+    double *xh, *yh, *uh, *vh, *ph;                   // half-step state
+    int64_t* cnt64;        // per-slot counters (scan input)
+    int64_t* rp_tmp;       // internal CSR row pointers
+    int32_t* col_tmp;      // internal CSR columns
+    int64_t col_cap;
+    // adaptation scratch
+    int32_t *flag, *closest, *idx_a, *idx_b;
+    int64_t *i64_a, *i64_b;
+    double *tmp_d[10];
+    int32_t *tmp_i32[2];
+    int64_t *tmp_i64[3];
+    int64_t* red;          // reduction scratch
+    int64_t capacity;
+};
+
+struct ProfSlot {
+    const char* name;
+    hipEvent_t ev[2][512];
+    int32_t count;
+    double ms;
+    int64_t launches;
+};
+
+struct sph_ctx {
+    sph_config cfg;
+    Grid grid;
+    Work w;
+    hipStream_t stream;
+    int64_t capacity;
+    int32_t nsort_blocks_max;
+    char err[512];
+    int32_t prof_on;
+    ProfSlot prof[4];
+    int built_n;       // particle count of the last build
+};
+
+// ---- host-side launch wrappers (implemented in the .hip files) ----------
+
+// nbr.hip
+int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h);
+NbrView nbr_view(sph_ctx* c);
+int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
+int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
+void grid_setup(const sph_config* cfg, Grid* g);
+size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g);
+
+// rates.hip
+int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out);
+int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps);
+int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
+
+// adapt.hip
+int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map);
+int mref_lookup_run(sph_ctx* c, const sph_particles* ps, const sph_background* bg);
+int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, const double* phi,
+                  double phi_thresh, int passes, int64_t* nsplit);
+
+// api.hip
+void set_err(sph_ctx* c, const char* fmt, ...);
+int check_hip(sph_ctx* c, hipError_t e, const char* what);
+void prof_begin(sph_ctx* c, int slot);
+void prof_end(sph_ctx* c, int slot);
+
+#define SPH_PROF_PASS_A 0
+#define SPH_PROF_PASS_B 1
+#define SPH_PROF_BUILD 2
+
+#define HIPCHK(c, expr)                                         \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return check_hip((c), e_, #expr); \
+    } while (0)
+
+#define LAUNCHCHK(c, what)                                             \
+    do {                                                               \
+        hipError_t e_ = hipGetLastError();                             \
+        if (e_ != hipSuccess) return check_hip((c), e_, (what));       \
+    } while (0)
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

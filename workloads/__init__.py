@@ -134,7 +134,7 @@ class ChannelSpec:
     ds_min: float = 0.01          # D/100
     ratio: int = 64               # ds_max / ds_min
     cr: float = 1.05              # size growth per layer
-    rows_per_layer: float = 6.0   # particle rows per C_r layer
+    rows_per_layer: float = 5.0   # particle rows per C_r layer
     hdx: float = 1.2
     rho0: float = 1.0
     u_inf: float = 1.0
