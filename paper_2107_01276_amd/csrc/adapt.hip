@@ -1,23 +1,755 @@
-// Adaptive refinement on gfx950 (section 3): background m_ref lookup,
-// split, mutual-closest merge, shifting with Taylor correction, h update,
-// and the background-particle update.
+// Adaptive refinement on gfx950 (section 3 of the paper).
+//
+//  - fluid m_ref from the background (section 3.3; algorithm of section 3.4,
+//    item 4): minimum background m_ref within 3 max(h_i, h_b), else the
+//    nearest background particle;
+//  - split (section 3.1): m > mmax_f m_ref -> 7 children, the centre child in
+//    the parent slot, six on a hexagon of radius eps h appended in
+//    (parent slot, k) order; integer mass ledger (six get floor(mq/7));
+//  - mutual-closest merge (section 3.2, eqs. merged-pos, merged-prop,
+//    merged-h) with stable compaction of the deleted slots;
+//  - shifting with Taylor correction (eqs. shift-deltar, shift-limit,
+//    shift-correct) and h = C sqrt(mbar/rho) (section 3.1);
+//  - background update (section 3.3 steps 1-4, eq. h-smoothing).
+//
+// Everything is double precision.  Sums run over CSR rows in ascending slot
+// order with the operation order of the definition, so results are
+// bit-exact with a sequential evaluation; argmin / min / any are
+// order-free.  Compaction uses wave ballots: a lane's rank among the set
+// flags of its wave is popcount(ballot & lanes-below), plus the wave and
+// block offsets.
+#include <math.h>
+
 #include "sph_device.h"
 
-int mref_lookup_run(sph_ctx* c, const sph_particles*, const sph_background*)
+int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
+
+// ---------------------------------------------------------------------------
+// Ballot compaction: rank[i] = number of set flags before i; returns total.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_flag_count(int n, const int32_t* __restrict__ flag,
+                                                    int32_t* bcount)
 {
-    set_err(c, "mref lookup not available in this build");
-    return SPH_E_INVAL;
+    __shared__ int32_t wc[4];
+    int i = blockIdx.x * 256 + threadIdx.x;
+    bool f = i < n && flag[i] != 0;
+    uint64_t b = __ballot(f);
+    if (__lane_id() == 0) wc[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
 }
 
-int adapt_run(sph_ctx* c, sph_particles*, const sph_background*, sph_adapt_map*)
+__global__ __launch_bounds__(256) void k_flag_rank(int n, const int32_t* __restrict__ flag,
+                                                   const int32_t* __restrict__ boff, int32_t* rank)
 {
-    set_err(c, "adaptation not available in this build");
-    return SPH_E_INVAL;
+    __shared__ int32_t wc[4];
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    int i = blockIdx.x * 256 + threadIdx.x;
+    bool f = i < n && flag[i] != 0;
+    uint64_t b = __ballot(f);
+    if (lane == 0) wc[w] = __popcll(b);
+    __syncthreads();
+    int off = boff[blockIdx.x];
+    for (int q = 0; q < w; ++q) off += wc[q];
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (i < n) rank[i] = off + __popcll(b & lt);
 }
 
-int bg_update_run(sph_ctx* c, sph_background*, const sph_particles*, const double*, double, int,
-                  int64_t*)
+static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, int32_t* total)
 {
-    set_err(c, "background update not available in this build");
-    return SPH_E_INVAL;
+    Work& w = c->w;
+    *total = 0;
+    if (n <= 0) return SPH_OK;
+    int nb = (int)cdiv(n, 256);
+    hipLaunchKernelGGL(k_flag_count, dim3(nb), dim3(256), 0, c->stream, n, flag, w.idx_b);
+    LAUNCHCHK(c, "flag_count");
+    int rc = scan_exclusive_i32(c, w.idx_b, w.idx_b, nb);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_flag_rank, dim3(nb), dim3(256), 0, c->stream, n, flag, w.idx_b, rank);
+    LAUNCHCHK(c, "flag_rank");
+    HIPCHK(c, hipMemcpyAsync(total, w.idx_b + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// m_ref lookup
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ y,
+                                                     const double* __restrict__ h,
+                                                     const double* __restrict__ bmref,
+                                                     double* mref_out, int32_t* none)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = x[i], yi = y[i], hi = h[i];
+    const int li = level_of(g, hi);
+    double mn = 0.0;
+    int found = 0;
+    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double, double, double, double) {
+        double v = bmref[nv.perm[js]];
+        if (!found || v < mn) mn = v;
+        found = 1;
+    });
+    none[i] = !found;
+    if (found) mref_out[i] = mn;
+}
+
+// Nearest background particle for the (rare) fluid particles with none in
+// range: brute force, ties to the lower background slot.
+__global__ __launch_bounds__(256) void k_mref_nearest(Grid g, int n, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const int32_t* __restrict__ none, int nb,
+                                                      const double* __restrict__ bx,
+                                                      const double* __restrict__ by,
+                                                      const double* __restrict__ bmref,
+                                                      double* mref_out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !none[i]) return;
+    int best = -1;
+    double br = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        double dx = mi_axis(g, 0, x[i] - bx[b]);
+        double dy = mi_axis(g, 1, y[i] - by[b]);
+        double r2 = dx * dx + dy * dy;
+        if (best < 0 || r2 < br) { best = b; br = r2; }
+    }
+    if (best >= 0) mref_out[i] = bmref[best];
+}
+
+static int mref_lookup_into(sph_ctx* c, const sph_particles* ps, const sph_background* bg,
+                            double* mref_out)
+{
+    Work& w = c->w;
+    int n = (int)ps->n, nb = (int)bg->n;
+    if (n == 0 || nb == 0) return SPH_OK;
+    int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
+    if (rc) return rc;
+    NbrView nv = nbr_view(c);
+    hipLaunchKernelGGL(k_mref_lookup, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
+                       nv, n, ps->x, ps->y, ps->h, bg->mref, mref_out, w.flag);
+    hipLaunchKernelGGL(k_mref_nearest, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
+                       n, ps->x, ps->y, w.flag, nb, bg->x, bg->y, bg->mref, mref_out);
+    LAUNCHCHK(c, "mref_lookup");
+    return SPH_OK;
+}
+
+int mref_lookup_run(sph_ctx* c, const sph_particles* ps, const sph_background* bg)
+{
+    return mref_lookup_into(c, ps, bg, ps->mref);
+}
+
+// ---------------------------------------------------------------------------
+// Split
+// ---------------------------------------------------------------------------
+
+struct FluidState {
+    double *x, *y, *u, *v, *p, *rho, *h, *mref;
+    int64_t *mq, *origin;
+    int32_t *kind, *sat;
+};
+
+__global__ __launch_bounds__(256) void k_split_flags(int n, const int64_t* __restrict__ mq,
+                                                     const double* __restrict__ mref,
+                                                     const int32_t* __restrict__ kind, double q,
+                                                     double mmax_f, int32_t* flag)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m = (double)mq[i] * q;
+    int k = kind ? kind[i] : SPH_FLUID;
+    flag[i] = (k == SPH_FLUID && m > mmax_f * mref[i]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_init_map(int n, int64_t* origin, int32_t* sat)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    origin[i] = i;
+    sat[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_split_apply(Grid g, int n, FluidState s,
+                                                     const int32_t* __restrict__ flag,
+                                                     const int32_t* __restrict__ rank,
+                                                     double alpha, double eps)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flag[i]) return;
+    const double ck[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    const double sk[6] = {0.0, SPH_SIN60, SPH_SIN60, 0.0, -SPH_SIN60, -SPH_SIN60};
+    const int64_t c = s.mq[i] / 7;
+    const double r = eps * s.h[i];
+    const double hc = alpha * s.h[i];
+    const double xi = s.x[i], yi = s.y[i];
+    const int64_t base = (int64_t)n + 6 * (int64_t)rank[i];
+    for (int k = 0; k < 6; ++k) {
+        int64_t t = base + k;
+        s.x[t] = wrap_axis(g, 0, xi + r * ck[k]);
+        s.y[t] = wrap_axis(g, 1, yi + r * sk[k]);
+        s.u[t] = s.u[i];
+        s.v[t] = s.v[i];
+        s.p[t] = s.p[i];
+        s.rho[t] = s.rho[i];
+        s.h[t] = hc;
+        s.mref[t] = s.mref[i];
+        s.mq[t] = c;
+        if (s.kind) s.kind[t] = s.kind[i];
+        s.origin[t] = s.origin[i];
+        s.sat[t] = 1;
+    }
+    s.mq[i] = s.mq[i] - 6 * c;
+    s.h[i] = hc;
+}
+
+// ---------------------------------------------------------------------------
+// Merge
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n, FluidState s,
+                                                       double q, double mmax_f, int32_t* closest)
+{
+    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= n) return;
+    const int i = nv.perm[sp];
+    const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
+    const int li = key_level(g, nv.keys[sp]);
+    const double mi = (double)s.mq[i] * q;
+    const double mmi = mmax_f * s.mref[i];
+    const int ki = s.kind ? s.kind[i] : SPH_FLUID;
+    int best = -1;
+    double br = 0.0;
+    if (ki == SPH_FLUID && !(mi > mmi)) {
+        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+            const int j = nv.perm[js];
+            if (j == i) return;
+            if (s.kind && s.kind[j] != SPH_FLUID) return;
+            const double mj = (double)s.mq[j] * q;
+            const double mmj = mmax_f * s.mref[j];
+            if (mj > mmj) return;
+            const double hh = 0.5 * (hi + hj);
+            if (!(r2 < hh * hh)) return;
+            const double msum = (double)(s.mq[i] + s.mq[j]) * q;
+            const double mm = mmi > mmj ? mmi : mmj;
+            if (!(msum < mm)) return;
+            if (best < 0 || r2 < br || (r2 == br && j < best)) {
+                best = j;
+                br = r2;
+            }
+        });
+    }
+    closest[i] = best;
+}
+
+__global__ __launch_bounds__(256) void k_merge_keep(int n, const int32_t* __restrict__ closest,
+                                                    int32_t* keep)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int j = closest[i];
+    bool mutual = j >= 0 && closest[j] == i;
+    keep[i] = (mutual && j < i) ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_merge_apply(Grid g, int n, FluidState s, FluidState d,
+                                                     const int32_t* __restrict__ closest,
+                                                     const int32_t* __restrict__ keep,
+                                                     const int32_t* __restrict__ rank, double q)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !keep[i]) return;
+    const int t = rank[i];
+    const int j = closest[i];
+    const bool mutual = j >= 0 && closest[j] == i;
+    d.x[t] = s.x[i]; d.y[t] = s.y[i]; d.u[t] = s.u[i]; d.v[t] = s.v[i];
+    d.p[t] = s.p[i]; d.rho[t] = s.rho[i]; d.h[t] = s.h[i]; d.mref[t] = s.mref[i];
+    d.mq[t] = s.mq[i]; d.origin[t] = s.origin[i]; d.sat[t] = s.sat[i];
+    if (s.kind) d.kind[t] = s.kind[i];
+    if (!mutual) return;
+    // i < j: i is kept and absorbs j
+    const double ma = (double)s.mq[i] * q;
+    const double mb = (double)s.mq[j] * q;
+    const int64_t mqm = s.mq[i] + s.mq[j];
+    const double mm = (double)mqm * q;
+    const double xa = s.x[i], ya = s.y[i];
+    const double xb = xa - mi_axis(g, 0, xa - s.x[j]);
+    const double yb = ya - mi_axis(g, 1, ya - s.y[j]);
+    const double xm = (ma * xa + mb * xb) / mm;
+    const double ym = (ma * ya + mb * yb) / mm;
+    const double dax = xm - xa, day = ym - ya;
+    const double dbx = xm - xb, dby = ym - yb;
+    const double ra = sqrt(dax * dax + day * day);
+    const double rb = sqrt(dbx * dbx + dby * dby);
+    const double den = ma * kern_w64(ra, s.h[i]) + mb * kern_w64(rb, s.h[j]);
+    const double w01 = kern_w64(0.0, 1.0);
+    d.h[t] = sqrt(mm * w01 / den);
+    d.x[t] = wrap_axis(g, 0, xm);
+    d.y[t] = wrap_axis(g, 1, ym);
+    d.u[t] = (ma * s.u[i] + mb * s.u[j]) / mm;
+    d.v[t] = (ma * s.v[i] + mb * s.v[j]) / mm;
+    d.p[t] = (ma * s.p[i] + mb * s.p[j]) / mm;
+    d.rho[t] = (ma * s.rho[i] + mb * s.rho[j]) / mm;
+    d.mref[t] = s.mref[i] < s.mref[j] ? s.mref[i] : s.mref[j];
+    d.mq[t] = mqm;
+}
+
+// ---------------------------------------------------------------------------
+// Shift + Taylor correction, h update (CSR rows in ascending slot order)
+// ---------------------------------------------------------------------------
+
+// Limited Lind shift of particle i over its row, eqs. (shift-deltar) and
+// (shift-limit), with volume m_j / rho0 and the gradient at h_ij.
+__device__ __forceinline__ void shift_row(const Grid& g, int i, const int64_t* __restrict__ rp,
+                                          const int32_t* __restrict__ col,
+                                          const double* __restrict__ x,
+                                          const double* __restrict__ y,
+                                          const double* __restrict__ h,
+                                          const int64_t* __restrict__ mq, double q, double rho0,
+                                          double* ox, double* oy)
+{
+    const double fxi = kern_f<double>(SPH_XI);
+    double sx = 0.0, sy = 0.0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const double dx = mi_axis(g, 0, x[i] - x[j]);
+        const double dy = mi_axis(g, 1, y[i] - y[j]);
+        const double r = sqrt(dx * dx + dy * dy);
+        if (r <= 0.0) continue;
+        const double hij = 0.5 * (h[i] + h[j]);
+        const double wr = kern_f<double>(r / hij) / fxi;
+        const double mj = (double)mq[j] * q;
+        const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+        const double t = coef * (kern_dw64(r, hij) / r);
+        sx = sx + t * dx;
+        sy = sy + t * dy;
+    }
+    const double pref = -0.5 * (h[i] * h[i]);
+    double ddx = pref * sx, ddy = pref * sy;
+    const double mag = sqrt(ddx * ddx + ddy * ddy);
+    const double lim = 0.25 * h[i];
+    if (mag > lim) {
+        const double th = lim / mag;
+        ddx = ddx * th;
+        ddy = ddy * th;
+    }
+    *ox = ddx;
+    *oy = ddy;
+}
+
+__global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState s,
+                                                      const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col, double q,
+                                                      double rho0, double* ddx_o, double* ddy_o,
+                                                      double* nu_o, double* nv_o, double* np_o)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (s.kind && s.kind[i] != SPH_FLUID) {
+        ddx_o[i] = 0.0; ddy_o[i] = 0.0;
+        nu_o[i] = s.u[i]; nv_o[i] = s.v[i]; np_o[i] = s.p[i];
+        return;
+    }
+    double ddx, ddy;
+    shift_row(g, i, rp, col, s.x, s.y, s.h, s.mq, q, rho0, &ddx, &ddy);
+    double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
+    const double xi = s.x[i], yi = s.y[i], hi = s.h[i];
+    const double ui = s.u[i], vi = s.v[i], pi = s.p[i];
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const double dx = mi_axis(g, 0, xi - s.x[j]);
+        const double dy = mi_axis(g, 1, yi - s.y[j]);
+        const double r = sqrt(dx * dx + dy * dy);
+        if (r <= 0.0) continue;
+        const double f = kern_dw64(r, hi) / r;
+        const double wx = f * dx, wy = f * dy;
+        const double Vj = ((double)s.mq[j] * q) / s.rho[j];
+        const double du = s.u[j] - ui, dv = s.v[j] - vi, dp = s.p[j] - pi;
+        gux += Vj * du * wx; guy += Vj * du * wy;
+        gvx += Vj * dv * wx; gvy += Vj * dv * wy;
+        gpx += Vj * dp * wx; gpy += Vj * dp * wy;
+    }
+    ddx_o[i] = ddx;
+    ddy_o[i] = ddy;
+    nu_o[i] = ui + (gux * ddx + guy * ddy);
+    nv_o[i] = vi + (gvx * ddx + gvy * ddy);
+    np_o[i] = pi + (gpx * ddx + gpy * ddy);
+}
+
+__global__ __launch_bounds__(256) void k_shift_apply(Grid g, int n, FluidState s,
+                                                     const double* __restrict__ ddx,
+                                                     const double* __restrict__ ddy,
+                                                     const double* __restrict__ nu,
+                                                     const double* __restrict__ nv,
+                                                     const double* __restrict__ np)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    s.x[i] = wrap_axis(g, 0, s.x[i] + ddx[i]);
+    s.y[i] = wrap_axis(g, 1, s.y[i] + ddy[i]);
+    s.u[i] = nu[i];
+    s.v[i] = nv[i];
+    s.p[i] = np[i];
+}
+
+__global__ __launch_bounds__(256) void k_hupdate(int n, const int64_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col,
+                                                 const int64_t* __restrict__ mq,
+                                                 const double* __restrict__ rho,
+                                                 const int32_t* __restrict__ kind, double q,
+                                                 double hdx, const double* __restrict__ h,
+                                                 double* nh)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (kind && kind[i] != SPH_FLUID) {
+        nh[i] = h[i];
+        return;
+    }
+    double sm = 0.0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) sm += (double)mq[col[k]] * q;
+    const double mbar = sm / (double)(rp[i + 1] - rp[i]);
+    nh[i] = hdx * sqrt(mbar / rho[i]);
+}
+
+__global__ void k_copy_f64(int n, const double* __restrict__ a, double* b)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// Builds the neighbour structure of (x, y, h) and exports CSR to the
+// internal buffers (rows ascending).
+static int internal_csr(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+{
+    Work& w = c->w;
+    int rc = nbr_build(c, n, x, y, h);
+    if (rc) return rc;
+    int64_t nnz = 0;
+    rc = nbr_export_csr(c, n, w.rp_tmp, w.col_tmp, w.col_cap, &nnz);
+    if (rc == SPH_E_CAPACITY)
+        set_err(c, "internal neighbour list needs %lld entries (limit %lld)", (long long)nnz,
+                (long long)w.col_cap);
+    return rc;
+}
+
+static FluidState fluid_of(sph_particles* ps, sph_adapt_map* map)
+{
+    FluidState s{ps->x, ps->y, ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mref,
+                 ps->mq, map->origin, ps->kind, map->sat};
+    return s;
+}
+
+static FluidState tmp_state(sph_ctx* c, bool with_kind)
+{
+    Work& w = c->w;
+    FluidState d{w.tmp_d[0], w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], w.tmp_d[5],
+                 w.tmp_d[6], w.tmp_d[7], w.tmp_i64[0], w.tmp_i64[1],
+                 with_kind ? w.tmp_i32[0] : nullptr, w.tmp_i32[1]};
+    return d;
+}
+
+static int copy_state(sph_ctx* c, const FluidState& a, FluidState& b, int n)
+{
+    hipStream_t st = c->stream;
+    size_t d8 = 8 * (size_t)n, d4 = 4 * (size_t)n;
+    const double* sa[8] = {a.x, a.y, a.u, a.v, a.p, a.rho, a.h, a.mref};
+    double* sb[8] = {b.x, b.y, b.u, b.v, b.p, b.rho, b.h, b.mref};
+    for (int k = 0; k < 8; ++k) HIPCHK(c, hipMemcpyAsync(sb[k], sa[k], d8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b.mq, a.mq, d8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b.origin, a.origin, d8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(b.sat, a.sat, d4, hipMemcpyDeviceToDevice, st));
+    if (a.kind && b.kind) HIPCHK(c, hipMemcpyAsync(b.kind, a.kind, d4, hipMemcpyDeviceToDevice, st));
+    return SPH_OK;
+}
+
+int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map)
+{
+    Work& w = c->w;
+    const sph_config& cf = c->cfg;
+    int n = (int)ps->n;
+    map->n_split = 0;
+    map->n_required = n;
+    for (int k = 0; k < 8; ++k) map->n_merged[k] = 0;
+    if (!map->origin || !map->sat) {
+        set_err(c, "adapt map arrays not set");
+        return SPH_E_INVAL;
+    }
+    // m_ref from the background goes to scratch first: nothing visible
+    // changes before the capacity check
+    double* mref_new = w.tmp_d[9];
+    if (n > 0) {
+        HIPCHK(c, hipMemcpyAsync(mref_new, ps->mref, 8 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+        if (bg) {
+            int rc = mref_lookup_into(c, ps, bg, mref_new);
+            if (rc) return rc;
+        }
+    }
+    const unsigned nbk = (unsigned)cdiv(n > 0 ? n : 1, 256);
+    hipLaunchKernelGGL(k_split_flags, dim3(nbk), dim3(256), 0, c->stream, n, ps->mq, mref_new,
+                       ps->kind, cf.mass_q, cf.mmax_f, w.flag);
+    LAUNCHCHK(c, "split_flags");
+    int32_t ns = 0;
+    int rc = compact_ranks(c, n, w.flag, w.idx_a, &ns);
+    if (rc) return rc;
+    map->n_split = ns;
+    map->n_required = (int64_t)n + 6 * (int64_t)ns;
+    if (map->n_required > ps->capacity) {
+        set_err(c, "split needs %lld slots, capacity %lld", (long long)map->n_required,
+                (long long)ps->capacity);
+        return SPH_E_CAPACITY;
+    }
+    if (n > 0)
+        HIPCHK(c, hipMemcpyAsync(ps->mref, mref_new, 8 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+    FluidState s = fluid_of(ps, map);
+    hipLaunchKernelGGL(k_init_map, dim3(nbk), dim3(256), 0, c->stream, n, map->origin, map->sat);
+    hipLaunchKernelGGL(k_split_apply, dim3(nbk), dim3(256), 0, c->stream, c->grid, n, s, w.flag,
+                       w.idx_a, cf.split_alpha, cf.split_eps);
+    LAUNCHCHK(c, "split_apply");
+    n = n + 6 * ns;
+
+    FluidState d = tmp_state(c, ps->kind != nullptr);
+    for (int it = 0; it < cf.merge_iters; ++it) {
+        if (n == 0) break;
+        rc = nbr_build(c, n, ps->x, ps->y, ps->h);
+        if (rc) return rc;
+        NbrView nv = nbr_view(c);
+        unsigned nb = (unsigned)cdiv(n, 256);
+        hipLaunchKernelGGL(k_merge_closest, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, s,
+                           cf.mass_q, cf.mmax_f, w.closest);
+        hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, w.closest, w.flag);
+        LAUNCHCHK(c, "merge_closest");
+        // number of pairs = number of deleted slots
+        int32_t nkeep = 0;
+        rc = compact_ranks(c, n, w.flag, w.idx_a, &nkeep);
+        if (rc) return rc;
+        map->n_merged[it] = n - nkeep;
+        hipLaunchKernelGGL(k_merge_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, d,
+                           w.closest, w.flag, w.idx_a, cf.mass_q);
+        LAUNCHCHK(c, "merge_apply");
+        rc = copy_state(c, d, s, nkeep);
+        if (rc) return rc;
+        n = nkeep;
+    }
+
+    for (int it = 0; it < cf.shift_iters; ++it) {
+        if (n == 0) break;
+        rc = internal_csr(c, n, ps->x, ps->y, ps->h);
+        if (rc) return rc;
+        unsigned nb = (unsigned)cdiv(n, 256);
+        hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.rp_tmp,
+                           w.col_tmp, cf.mass_q, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2],
+                           w.tmp_d[3], w.tmp_d[4]);
+        hipLaunchKernelGGL(k_shift_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.tmp_d[0],
+                           w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4]);
+        LAUNCHCHK(c, "shift");
+    }
+    if (n > 0) {
+        rc = internal_csr(c, n, ps->x, ps->y, ps->h);
+        if (rc) return rc;
+        unsigned nb = (unsigned)cdiv(n, 256);
+        hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, n, w.rp_tmp, w.col_tmp, ps->mq,
+                           ps->rho, ps->kind, cf.mass_q, cf.hdx, ps->h, w.tmp_d[0]);
+        hipLaunchKernelGGL(k_copy_f64, dim3(nb), dim3(256), 0, c->stream, n, w.tmp_d[0], ps->h);
+        LAUNCHCHK(c, "hupdate");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    ps->n = n;
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Background update (section 3.3)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bg_mask(Grid g, NbrView nv, int nb,
+                                                 const double* __restrict__ bx,
+                                                 const double* __restrict__ by,
+                                                 const double* __restrict__ bh,
+                                                 const double* __restrict__ phi, double phi_thresh,
+                                                 double ds_min, int32_t* mask, double* ds,
+                                                 int have_solids)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    int m = 0;
+    if (have_solids) {
+        const double xi = bx[b], yi = by[b], hi = bh[b];
+        for_each_neighbor(g, nv, xi, yi, hi, level_of(g, hi),
+                          [&](int, double, double, double, double) { m = 1; });
+    }
+    if (phi && phi[b] > phi_thresh) m = 1;
+    mask[b] = m;
+    if (m) ds[b] = ds_min;
+}
+
+__global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
+                                                  const int32_t* __restrict__ mask,
+                                                  const double* __restrict__ ds, double cr,
+                                                  double ds_min, double ds_max, double* nds)
+{
+    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nb) return;
+    const int b = nv.perm[sp];
+    if (mask[b]) {
+        nds[b] = ds[b];
+        return;
+    }
+    double mn = 0.0, mx = 0.0, sl = 0.0;
+    int cnt = 0;
+    for_each_neighbor(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]),
+                      [&](int js, double, double, double, double) {
+                          const double v = ds[nv.perm[js]];
+                          if (cnt == 0 || v < mn) mn = v;
+                          if (cnt == 0 || v > mx) mx = v;
+                          sl += log(v);
+                          ++cnt;
+                      });
+    const double cr3 = cr * cr * cr;
+    const double geo = exp(sl / (double)cnt);
+    double v = (mx / mn < cr3) ? cr * mn : geo;
+    if (v < ds_min) v = ds_min;
+    if (v > ds_max) v = ds_max;
+    nds[b] = v;
+}
+
+__global__ __launch_bounds__(256) void k_bg_setds(int nb, const double* __restrict__ nds,
+                                                  double rho0, double* ds, double* mref)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    ds[b] = nds[b];
+    mref[b] = rho0 * (nds[b] * nds[b]);
+}
+
+__global__ __launch_bounds__(256) void k_bg_split_flags(int nb, const int64_t* __restrict__ mq,
+                                                        const double* __restrict__ mref, double q,
+                                                        double mmax_f, int32_t* flag)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    flag[b] = ((double)mq[b] * q > mmax_f * mref[b]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_bg_split_apply(Grid g, int nb, sph_background B,
+                                                        const int32_t* __restrict__ flag,
+                                                        const int32_t* __restrict__ rank,
+                                                        double alpha, double eps)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb || !flag[b]) return;
+    const double ck[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    const double sk[6] = {0.0, SPH_SIN60, SPH_SIN60, 0.0, -SPH_SIN60, -SPH_SIN60};
+    const int64_t c = B.mq[b] / 7;
+    const double r = eps * B.h[b];
+    const double hc = alpha * B.h[b];
+    const int64_t base = (int64_t)nb + 6 * (int64_t)rank[b];
+    for (int k = 0; k < 6; ++k) {
+        int64_t t = base + k;
+        B.x[t] = wrap_axis(g, 0, B.x[b] + r * ck[k]);
+        B.y[t] = wrap_axis(g, 1, B.y[b] + r * sk[k]);
+        B.h[t] = hc;
+        B.ds[t] = B.ds[b];
+        B.mask[t] = B.mask[b];
+        B.mref[t] = B.mref[b];
+        B.mq[t] = c;
+    }
+    B.mq[b] = B.mq[b] - 6 * c;
+    B.h[b] = hc;
+}
+
+__global__ __launch_bounds__(256) void k_bg_smooth(Grid g, int nb, sph_background B,
+                                                   const int64_t* __restrict__ rp,
+                                                   const int32_t* __restrict__ col, double q,
+                                                   double rho0, double n_r, double* nh,
+                                                   double* ddx, double* ddy)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double N = (double)(rp[b + 1] - rp[b]);
+    double sh = 0.0;
+    for (int64_t k = rp[b]; k < rp[b + 1]; ++k) sh += B.h[col[k]];
+    nh[b] = 0.5 * ((B.h[b] / 2.0) * (1.0 + sqrt(n_r / N)) + sh / N);
+    shift_row(g, b, rp, col, B.x, B.y, B.h, B.mq, q, rho0, &ddx[b], &ddy[b]);
+}
+
+__global__ __launch_bounds__(256) void k_bg_smooth_apply(Grid g, int nb, sph_background B,
+                                                         const double* __restrict__ nh,
+                                                         const double* __restrict__ ddx,
+                                                         const double* __restrict__ ddy)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    B.h[b] = nh[b];
+    B.x[b] = wrap_axis(g, 0, B.x[b] + ddx[b]);
+    B.y[b] = wrap_axis(g, 1, B.y[b] + ddy[b]);
+}
+
+int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, const double* phi,
+                  double phi_thresh, int passes, int64_t* nsplit)
+{
+    Work& w = c->w;
+    const sph_config& cf = c->cfg;
+    *nsplit = 0;
+    int nb = (int)bg->n;
+    const int ns = (int)solids->n;
+    for (int pass = 0; pass < passes; ++pass) {
+        if (nb == 0) break;
+        unsigned nbk = (unsigned)cdiv(nb, 256);
+        // step 1: boundary mask
+        if (ns > 0) {
+            int rc = nbr_build(c, ns, solids->x, solids->y, solids->h);
+            if (rc) return rc;
+        }
+        NbrView sv = nbr_view(c);
+        hipLaunchKernelGGL(k_bg_mask, dim3(nbk), dim3(256), 0, c->stream, c->grid, sv, nb, bg->x,
+                           bg->y, bg->h, pass == 0 ? phi : nullptr, phi_thresh, cf.ds_min, bg->mask,
+                           bg->ds, ns > 0 ? 1 : 0);
+        LAUNCHCHK(c, "bg_mask");
+        // step 2: size grading (Jacobi)
+        int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
+        if (rc) return rc;
+        NbrView nv = nbr_view(c);
+        hipLaunchKernelGGL(k_bg_grade, dim3(nbk), dim3(256), 0, c->stream, c->grid, nv, nb, bg->mask,
+                           bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0]);
+        hipLaunchKernelGGL(k_bg_setds, dim3(nbk), dim3(256), 0, c->stream, nb, w.tmp_d[0], cf.rho0,
+                           bg->ds, bg->mref);
+        LAUNCHCHK(c, "bg_grade");
+        // step 3: split
+        hipLaunchKernelGGL(k_bg_split_flags, dim3(nbk), dim3(256), 0, c->stream, nb, bg->mq, bg->mref,
+                           cf.bg_mass_q, cf.mmax_f, w.flag);
+        int32_t cnt = 0;
+        rc = compact_ranks(c, nb, w.flag, w.idx_a, &cnt);
+        if (rc) return rc;
+        if ((int64_t)nb + 6 * (int64_t)cnt > bg->capacity) {
+            set_err(c, "background split needs %lld slots, capacity %lld",
+                    (long long)nb + 6 * (long long)cnt, (long long)bg->capacity);
+            bg->n = nb;
+            return SPH_E_CAPACITY;
+        }
+        hipLaunchKernelGGL(k_bg_split_apply, dim3(nbk), dim3(256), 0, c->stream, c->grid, nb, *bg,
+                           w.flag, w.idx_a, cf.split_alpha, cf.split_eps);
+        LAUNCHCHK(c, "bg_split");
+        *nsplit += cnt;
+        nb += 6 * cnt;
+        // step 4: h smoothing + shifting
+        for (int it = 0; it < cf.bg_smooth_iters; ++it) {
+            rc = internal_csr(c, nb, bg->x, bg->y, bg->h);
+            if (rc) return rc;
+            unsigned nbk2 = (unsigned)cdiv(nb, 256);
+            hipLaunchKernelGGL(k_bg_smooth, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
+                               w.rp_tmp, w.col_tmp, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
+                               w.tmp_d[1], w.tmp_d[2]);
+            hipLaunchKernelGGL(k_bg_smooth_apply, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
+                               w.tmp_d[0], w.tmp_d[1], w.tmp_d[2]);
+            LAUNCHCHK(c, "bg_smooth");
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    bg->n = nb;
+    return SPH_OK;
 }

@@ -9,7 +9,7 @@
 #include "sph_internal.h"
 
 #define SPH_VERSION 10000
-#define COL_PER_PARTICLE 96
+#define COL_PER_PARTICLE 160
 
 void set_err(sph_ctx* c, const char* fmt, ...)
 {
