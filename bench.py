@@ -68,7 +68,7 @@ def timed_steps(ctx, P, dt, steps, warmup, torch):
     e1.record(s)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    prof = {k: ctx.profile_read(k) for k in ("pass_a", "pass_b", "build")}
+    prof = {k: ctx.profile_read(k) for k in ("pass_a", "pass_b", "build", "list")}
     ctx.profile(False)
     return ms, prof
 

@@ -10,6 +10,7 @@
 
 #define SPH_VERSION 10000
 #define COL_PER_PARTICLE 160
+#define NL_K 128
 
 void set_err(sph_ctx* c, const char* fmt, ...)
 {
@@ -83,6 +84,9 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
     for (int k = 0; k < 2; ++k) w->tmp_i32[k] = (int32_t*)take(4 * C);
     for (int k = 0; k < 3; ++k) w->tmp_i64[k] = (int64_t*)take(8 * C);
     w->red = (int64_t*)take(8 * 8192);
+    w->nl_k = NL_K;
+    w->nl_idx = (int32_t*)take(4 * (size_t)NL_K * C);
+    w->nl_cnt = (int32_t*)take(4 * C);
     return off + 256;
 }
 
@@ -130,7 +134,7 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->prof[SPH_PROF_PASS_A].name = "pass_a";
     c->prof[SPH_PROF_PASS_B].name = "pass_b";
     c->prof[SPH_PROF_BUILD].name = "build";
-    c->prof[3].name = "unused";
+    c->prof[SPH_PROF_LIST].name = "list";
     *out = c;
     return SPH_OK;
 }

@@ -53,6 +53,12 @@ void grid_setup(const sph_config* cfg, Grid* g)
         }
     }
     g->cmin0 = g->cw0[0] < g->cw0[1] ? g->cw0[0] : g->cw0[1];
+    g->icw0[0] = 1.0 / g->cw0[0];
+    g->icw0[1] = 1.0 / g->cw0[1];
+    for (int a = 0; a < 2; ++a) {
+        g->mi_l[a] = g->periodic[a] ? g->L[a] : 0.0;
+        g->mi_h[a] = g->periodic[a] ? g->half[a] : HUGE_VAL;
+    }
     int nlev = 1;
     double c = g->cmin0;
     while (c < 3.0 * hhi * (1.0 + 1e-9) && nlev < SPH_MAXL) {
@@ -210,8 +216,7 @@ __global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __res
         int l = level_of(g, hi);
         uint32_t kx = (uint32_t)cell0(g, 0, x[i]);
         uint32_t ky = (uint32_t)cell0(g, 1, y[i]);
-        uint64_t m = spread2(kx) | (spread2(ky) << 1);
-        keys[i] = ((uint64_t)l << (2 * g.bits)) | m;
+        keys[i] = ((uint64_t)l << (2 * g.bits)) | hilbert_d(kx, ky, g.bits);
         vals[i] = i;
         atomicMax(&s_h[l], (unsigned long long)__double_as_longlong(hi));
         atomicAdd(&s_c[l], 1);
@@ -363,8 +368,12 @@ static int radix_sort(sph_ctx* c, int n, int keybits)
 // Cell-run tables and sorted shadows
 // ---------------------------------------------------------------------------
 
+// Run boundaries per (level, resolution Q): consecutive sorted particles of
+// one level share a Q-cell iff their curve indices agree above bit 2Q.  The
+// cell's coordinates come from the particle's position.
 __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* __restrict__ keys,
-                                                int2* tab)
+                                                const double* __restrict__ xs,
+                                                const double* __restrict__ ys, int2* tab)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -377,12 +386,13 @@ __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* _
     uint64_t kn = s < n - 1 ? keys[s + 1] : ~0ull;
     bool lp = s > 0 && (int)(kp >> sh) == l;
     bool ln = s < n - 1 && (int)(kn >> sh) == l;
+    const int kx0 = cell0(g, 0, xs[s]), ky0 = cell0(g, 1, ys[s]);
     for (int Q = l; Q < g.nlev; ++Q) {
         uint64_t cell = m >> (2 * Q);
         bool sp = lp && ((kp & mmask) >> (2 * Q)) == cell;
         bool sn = ln && ((kn & mmask) >> (2 * Q)) == cell;
         if (sp && sn) continue;
-        int cx = (int)compact2(cell), cy = (int)compact2(cell >> 1);
+        int cx = kx0 >> Q, cy = ky0 >> Q;
         int64_t idx = g.lbase[l] + g.cumq[Q] + (int64_t)cy * g.nxq[Q][0] + cx;
         if (!sp) tab[idx].x = s;
         if (!sn) tab[idx].y = s + 1;
@@ -419,10 +429,10 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
         LAUNCHCHK(c, "keys");
         int rc = radix_sort(c, n, key_bits(&g));
         if (rc) return rc;
-        hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
-                           w.keys_a, w.tab);
         hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
                            w.vals_a, x, y, h, w.xs, w.ys, w.hs);
+        hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
+                           w.keys_a, w.xs, w.ys, w.tab);
         LAUNCHCHK(c, "tables");
     }
     prof_end(c, SPH_PROF_BUILD);
@@ -442,6 +452,201 @@ NbrView nbr_view(sph_ctx* c)
     v.hmax_bits = c->w.hmax_bits;
     v.lcount = c->w.lcount;
     return v;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour list for the rate passes, built per wave.  A wave owns 64
+// consecutive sorted particles and splits them into segments wherever the
+// level changes or two consecutive particles are more than two supports apart
+// (the Hilbert order keeps segments few and compact).  For each segment and
+// level the wave walks the cells of the segment's union box that meet some
+// member's search disk (a wave vote), loads each cell's particles 64 at a
+// time (one per lane, coalesced) and broadcasts them lane by lane, so every
+// lane runs the same loop and only members test.  Boxes that straddle half a
+// period, and waves with more than LIST_MAX_SEG segments, use the per-lane
+// search.  Entry k of sorted particle s goes to idx[k * stride + s]; counts
+// above K are recorded (the rate passes then search again for it).
+// ---------------------------------------------------------------------------
+
+#define LIST_MAX_SEG 8
+
+// Minimum image, resolved at compile time for open axes.
+template <bool P>
+__device__ __forceinline__ double mi_t(const Grid& g, int a, double d)
+{
+    return P ? mi_axis(g, a, d) : d;
+}
+
+template <bool PX, bool PY>
+__global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, NbrList nl)
+{
+    __shared__ int s_pre[4][64], s_beg[4][64];
+    const int lane = __lane_id();
+    const int w = threadIdx.x >> 6;
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s0 = s - lane;
+    if (s0 >= n) return;  // whole wave past the end
+    const bool valid = s < n;
+    const int sv = valid ? s : s0;
+    const double xi = nv.xs[sv], yi = nv.ys[sv], hi = nv.hs[sv];
+    const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+    const int li = key_level(g, nv.keys[sv]);
+    int cnt = 0;
+    auto emit = [&](int js) {
+        // an overflowing row (cnt > K) is searched again by the rate passes,
+        // so its last slot may be overwritten
+        const int k = cnt < nl.K ? cnt : nl.K - 1;
+        nl.idx[(int64_t)k * nl.stride + s] = js;
+        ++cnt;
+    };
+    // segments of the wave
+    const double xp = __shfl_up(xi, 1, 64), yp = __shfl_up(yi, 1, 64);
+    const int lp = __shfl_up(li, 1, 64);
+    const double ex = mi_axis(g, 0, xi - xp), ey = mi_axis(g, 1, yi - yp);
+    const double thr = 6.0 * hi;
+    const bool start = lane == 0 || (valid && (li != lp || ex * ex + ey * ey > thr * thr));
+    const uint64_t sb = __ballot(start);
+    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    const int seg = __popcll(sb & le) - 1;
+    const int nseg = __popcll(sb);
+    if (nseg > LIST_MAX_SEG) {
+        if (valid) {
+            for_each_neighbor(g, nv, xi, yi, hi, li,
+                              [&](int js, double, double, double, double) { emit(js); });
+            nl.cnt[s] = cnt;
+        }
+        return;
+    }
+    const double INF = 1e300;
+    for (int sg = 0; sg < nseg; ++sg) {
+        const bool mem = valid && seg == sg;
+        const int lseg = wave_min_i(mem ? li : 0x7fffffff);
+        for (int l = 0; l < g.nlev; ++l) {
+            if (nv.lcount[l] == 0) continue;
+            const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
+            const double R = 3.0 * (hi > hl ? hi : hl);
+            const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
+            const double bx0 = wave_min_d(mem ? xi - R : INF), bx1 = wave_max_d(mem ? xi + R : -INF);
+            const double by0 = wave_min_d(mem ? yi - R : INF), by1 = wave_max_d(mem ? yi + R : -INF);
+            const bool wrap = (g.periodic[0] && bx1 - bx0 > g.half[0]) ||
+                              (g.periodic[1] && by1 - by0 > g.half[1]);
+            if (wrap) {
+                if (mem)
+                    for_each_neighbor_level(g, nv, xi, yi, hi, li, l,
+                                            [&](int js, double, double, double, double) { emit(js); });
+                continue;
+            }
+            const int Q = l > lseg ? l : lseg;
+            const Span xr = axis_span(g, 0, 0.5 * (bx0 + bx1), 0.5 * (bx1 - bx0), Q);
+            const Span yr = axis_span(g, 1, 0.5 * (by0 + by1), 0.5 * (by1 - by0), Q);
+            const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
+            const int nq = g.nxq[Q][0];
+            const int nx_a = xr.b0 - xr.a0 + 1, nx_t = nx_a + (xr.n == 2 ? xr.b1 - xr.a1 + 1 : 0);
+            const int ny_a = yr.b0 - yr.a0 + 1, ny_t = ny_a + (yr.n == 2 ? yr.b1 - yr.a1 + 1 : 0);
+            const int ncell = nx_t * ny_t;
+            // cells of the box, 64 per round: lane t fetches cell t's run,
+            // a wave scan turns run lengths into offsets of one candidate
+            // stream, and the stream is tested 64 candidates at a time while
+            // the next 64 are being loaded
+            for (int c0 = 0; c0 < ncell; c0 += 64) {
+                const int t = c0 + lane;
+                int len = 0, beg = 0;
+                if (t < ncell) {
+                    const int ix = t % nx_t, iy = t / nx_t;
+                    const int cx = ix < nx_a ? xr.a0 + ix : xr.a1 + (ix - nx_a);
+                    const int cy = iy < ny_a ? yr.a0 + iy : yr.a1 + (iy - ny_a);
+                    const int2 se = tab[(int64_t)cy * nq + cx];
+                    beg = se.x;
+                    len = se.y - se.x;
+                }
+                const int incl = wave_incl_scan<int>(len);
+                const int total = __builtin_amdgcn_readlane(incl, 63);
+                if (total == 0) continue;
+                s_pre[w][lane] = incl - len;
+                s_beg[w][lane] = beg;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int nc = ncell - c0 < 64 ? ncell - c0 : 64;
+                auto fetch = [&](int p, int& js, double& fx, double& fy, double& fh) {
+                    js = 0;
+                    fx = 0.0; fy = 0.0; fh = 0.0;
+                    if (p < total) {
+                        int lo = 0, hi2 = nc - 1;  // last cell whose offset <= p
+                        while (lo < hi2) {
+                            const int mid = (lo + hi2 + 1) >> 1;
+                            if (s_pre[w][mid] <= p) lo = mid;
+                            else hi2 = mid - 1;
+                        }
+                        js = s_beg[w][lo] + (p - s_pre[w][lo]);
+                        fx = nv.xs[js];
+                        fy = nv.ys[js];
+                        const double r3 = 3.0 * nv.hs[js];
+                        fh = r3 * r3;
+                    }
+                };
+                int jA;
+                double xA, yA, hA;
+                fetch(lane, jA, xA, yA, hA);
+                for (int base = 0; base < total; base += 64) {
+                    int jB;
+                    double xB, yB, hB;
+                    fetch(base + 64 + lane, jB, xB, yB, hB);
+                    const int m = total - base < 64 ? total - base : 64;
+                    // r2 < (3 max(h_i, h_j))^2  <=>  r2 < max((3 h_i)^2, (3 h_j)^2),
+                    // exactly, since scaling and squaring round monotonically
+                    int k = 0;
+                    for (; k + 4 <= m; k += 4) {
+                        bool hit[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const double xj = lane_bcast(xA, k + u);
+                            const double yj = lane_bcast(yA, k + u);
+                            const double rj2 = lane_bcast(hA, k + u);
+                            const double dx = mi_t<PX>(g, 0, xi - xj);
+                            const double dy = mi_t<PY>(g, 1, yi - yj);
+                            const double r2 = dx * dx + dy * dy;
+                            hit[u] = mem && r2 < fmax(ri2, rj2);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (hit[u]) emit(__builtin_amdgcn_readlane(jA, k + u));
+                    }
+                    for (; k < m; ++k) {
+                        const double xj = lane_bcast(xA, k);
+                        const double yj = lane_bcast(yA, k);
+                        const double rj2 = lane_bcast(hA, k);
+                        const double dx = mi_t<PX>(g, 0, xi - xj);
+                        const double dy = mi_t<PY>(g, 1, yi - yj);
+                        const double r2 = dx * dx + dy * dy;
+                        if (mem && r2 < fmax(ri2, rj2)) emit(__builtin_amdgcn_readlane(jA, k));
+                    }
+                    jA = jB;
+                    xA = xB;
+                    yA = yB;
+                    hA = hB;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+    }
+    if (valid) nl.cnt[s] = cnt;
+}
+
+int nbr_build_list(sph_ctx* c, int n)
+{
+    Work& w = c->w;
+    if (n == 0) return SPH_OK;
+    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n};
+    prof_begin(c, SPH_PROF_LIST);
+    const Grid& g = c->grid;
+    auto kern = g.periodic[0] ? (g.periodic[1] ? k_build_list<true, true> : k_build_list<true, false>)
+                              : (g.periodic[1] ? k_build_list<false, true> : k_build_list<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nbr_view(c), n,
+                       nl);
+    prof_end(c, SPH_PROF_LIST);
+    LAUNCHCHK(c, "build_list");
+    return SPH_OK;
 }
 
 // ---------------------------------------------------------------------------

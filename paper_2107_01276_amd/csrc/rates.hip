@@ -71,8 +71,8 @@ struct PassAOut {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                const double* __restrict__ us, double rho0,
-                                                PassAOut out, double* r_dxs, double* r_dys)
+                                                NbrList nl, double rho0, PassAOut out,
+                                                double* r_dxs, double* r_dys)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -83,15 +83,13 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     const T irho0 = T(1.0 / rho0);
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
     CSum<T> sr, sb, sp, sx, sy;
-    int cnt = 0;
-    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+    auto body = [&](int js, double dx, double dy, double r2, double hj) __attribute__((always_inline)) {
         const T mj = b.m[js];
         const T r = fsqrt<T>((T)r2);
         const T q = r * ih;
         sr.add(mj * (sig * kern_f<T>(q)));
         sb.add(mj * r * (sig * ih * kern_fp<T>(q)));
         sp.add((T)(b.ps[js] - pi));
-        ++cnt;
         if (r > T(0)) {
             const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
             const T qij = r * ihij;
@@ -103,7 +101,17 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
             sx.add(t * (T)dx);
             sy.add(t * (T)dy);
         }
-    });
+    };
+    int cnt = nl.cnt[s];
+    if (cnt <= nl.K) {
+        for_each_listed(g, nv, nl, s, cnt, xi, yi, body);
+    } else {
+        cnt = 0;
+        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+            body(js, dx, dy, r2, hj);
+            ++cnt;
+        });
+    }
     const T rho = sr.get();
     const T beta = -sb.get() / (T(2) * rho);
     const T N = (T)cnt;
@@ -137,7 +145,6 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     if (out.nnb) out.nnb[slot] = (double)cnt;
     if (out.dxs) out.dxs[slot] = (double)ddx;
     if (out.dys) out.dys[slot] = (double)ddy;
-    (void)us;
 }
 
 struct PassBParams {
@@ -146,7 +153,7 @@ struct PassBParams {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                const double* __restrict__ us,
+                                                NbrList nl, const double* __restrict__ us,
                                                 const double* __restrict__ vs, PassBParams P,
                                                 double* dpdt, double* dudt, double* dvdt)
 {
@@ -154,7 +161,6 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     if (s >= n) return;
     const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
     const double ui = us[s], vi = vs[s], pi = b.ps[s];
-    const int li = key_level(g, nv.keys[s]);
     const T ih = b.ih[s];
     const T sigi = T(SPH_SIGMA2) * ih * ih * ih;
     const T rhoi = b.rho[s];
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     const T nu4 = (T)(4.0 * P.nu);
     CSum<T> sdiv, sdif;
     T gx = 0, gy = 0, vx = 0, vy = 0;
-    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+    auto body = [&](int js, double dx, double dy, double r2, double hj) __attribute__((always_inline)) {
         const T r = fsqrt<T>((T)r2);
         if (!(r > T(0))) return;  // the self pair contributes nothing
         const T ir = rcp<T>(r);
@@ -192,7 +198,13 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
         const T cv = mj * nu4 * rcp<T>(rhoi + b.rho[js]) * rdotg * iden;
         vx += cv * uij;
         vy += cv * vij;
-    });
+    };
+    const int cnt = nl.cnt[s];
+    if (cnt <= nl.K) {
+        for_each_listed(g, nv, nl, s, cnt, xi, yi, body);
+    } else {
+        for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), body);
+    }
     const T beta = b.beta[s];
     const T ib = beta > T(0) ? T(1) / beta : T(0);
     const double dxs = (double)b.dxs[s], dys = (double)b.dys[s];
@@ -220,14 +232,17 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const dou
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
                        cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih);
     LAUNCHCHK(c, "gather_state");
+    rc = nbr_build_list(c, n);
+    if (rc) return rc;
+    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n};
     prof_begin(c, SPH_PROF_PASS_A);
-    hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b,
-                       (const double*)w.us, cf.rho0, aout, w.r_dxs, w.r_dys);
+    hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+                       cf.rho0, aout, w.r_dxs, w.r_dys);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B);
-    hipLaunchKernelGGL(k_pass_b<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b,
+    hipLaunchKernelGGL(k_pass_b<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                        (const double*)w.us, (const double*)w.vs, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");

@@ -80,12 +80,15 @@ struct CSum<double> {
 
 // ---- geometry -------------------------------------------------------------
 
+// Minimum image r_i - r_j on axis a: beyond +L/2 subtract L, below -L/2 add
+// L (a displacement of exactly L/2 is kept).  Written as two selects so the
+// pair loops do not branch; open axes have L = 0 and L/2 = +inf, leaving d
+// unchanged.
 __device__ __forceinline__ double mi_axis(const Grid& g, int a, double d)
 {
-    if (g.periodic[a]) {
-        if (d > g.half[a]) d = d - g.L[a];
-        else if (d < -g.half[a]) d = d + g.L[a];
-    }
+    const double lo = d - g.mi_l[a], hi = d + g.mi_l[a];
+    d = d > g.mi_h[a] ? lo : d;
+    d = d < -g.mi_h[a] ? hi : d;
     return d;
 }
 
@@ -120,6 +123,30 @@ __device__ __forceinline__ int cell0(const Grid& g, int a, double x)
     return (int)k;
 }
 
+// Hilbert index of cell (x, y) on the 2^bits x 2^bits square.  Every aligned
+// 2^Q x 2^Q block is one contiguous index range, identified by d >> 2Q, and
+// consecutive indices are adjacent cells (no jumps, unlike Morton order).
+__device__ __forceinline__ uint64_t hilbert_d(uint32_t x, uint32_t y, int bits)
+{
+    uint64_t d = 0;
+    const uint32_t n1 = (bits >= 32) ? 0xffffffffu : ((1u << bits) - 1u);
+    for (int b = bits - 1; b >= 0; --b) {
+        const uint32_t s = 1u << b;
+        const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+        d += (uint64_t)s * s * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) {
+                x = n1 - x;
+                y = n1 - y;
+            }
+            const uint32_t t = x;
+            x = y;
+            y = t;
+        }
+    }
+    return d;
+}
+
 __device__ __forceinline__ uint64_t spread2(uint32_t v)
 {
     uint64_t x = v;
@@ -141,26 +168,25 @@ __device__ __forceinline__ uint32_t compact2(uint64_t x)
     return (uint32_t)x;
 }
 
-// Cell intervals (resolution Q) covering [x - R, x + R] on axis a.  Returns
-// the number of disjoint intervals (1 or 2) written to iv[0..3].  Every
-// interval lies in [0, nq - 1] for any input, NaN and far-out positions
-// included (those only cost time).
-__device__ __forceinline__ int axis_ranges(const Grid& g, int a, double x, double R, int Q, int* iv)
+// Cell intervals (resolution Q) covering [x - R, x + R] on axis a: n (1 or
+// 2) disjoint intervals [a0, b0], [a1, b1].  Every interval lies in
+// [0, nq - 1] for any input, NaN and far-out positions included (those only
+// cost time).
+struct Span {
+    int n, a0, b0, a1, b1;
+};
+
+__device__ __forceinline__ Span axis_span(const Grid& g, int a, double x, double R, int Q)
 {
     const int nx0 = g.nx0[a];
     const int nq = g.nxq[Q][a];
-    double slack = 1e-9 * R + 1e-12 * (fabs(x) + fabs(g.org[a]) + g.cw0[a] * nx0);
-    double fa = floor((x - R - slack - g.org[a]) / g.cw0[a]);
-    double fb = floor((x + R + slack - g.org[a]) / g.cw0[a]);
-    if (!(fa > -1e15 && fa < 1e15 && fb > -1e15 && fb < 1e15 && fb >= fa)) {
-        iv[0] = 0; iv[1] = nq - 1;
-        return 1;
-    }
+    Span sp{1, 0, nq - 1, 0, -1};
+    const double slack = 1e-9 * R + 1e-12 * (fabs(x) + fabs(g.org[a]) + g.cw0[a] * nx0);
+    double fa = floor((x - R - slack - g.org[a]) * g.icw0[a]);
+    double fb = floor((x + R + slack - g.org[a]) * g.icw0[a]);
+    if (!(fa > -1e15 && fa < 1e15 && fb > -1e15 && fb < 1e15 && fb >= fa)) return sp;
     if (g.periodic[a]) {
-        if (fb - fa + 1.0 >= (double)nx0) {
-            iv[0] = 0; iv[1] = nq - 1;
-            return 1;
-        }
+        if (fb - fa + 1.0 >= (double)nx0) return sp;
         // shift by whole periods so that fa lies in [0, nx0)
         double sh = floor(fa / (double)nx0) * (double)nx0;
         int ka = (int)(fa - sh), kb = (int)(fb - sh);
@@ -168,58 +194,166 @@ __device__ __forceinline__ int axis_ranges(const Grid& g, int a, double x, doubl
         if (ka > nx0 - 1) { ka -= nx0; kb -= nx0; }
         if (kb >= nx0) {
             int A = ka >> Q, B = (kb - nx0) >> Q;
-            if (A <= B + 1) { iv[0] = 0; iv[1] = nq - 1; return 1; }
-            iv[0] = 0; iv[1] = B; iv[2] = A; iv[3] = nq - 1;
-            return 2;
+            if (A <= B + 1) return sp;
+            sp.n = 2; sp.a0 = 0; sp.b0 = B; sp.a1 = A; sp.b1 = nq - 1;
+            return sp;
         }
-        iv[0] = ka >> Q; iv[1] = kb >> Q;
-        return 1;
+        sp.a0 = ka >> Q; sp.b0 = kb >> Q;
+        return sp;
     }
     if (fa < 0.0) fa = 0.0;
     if (fb > (double)(nx0 - 1)) fb = (double)(nx0 - 1);
     if (fa > (double)(nx0 - 1)) fa = (double)(nx0 - 1);
     if (fb < 0.0) fb = 0.0;
-    iv[0] = ((int)fa) >> Q; iv[1] = ((int)fb) >> Q;
-    return 1;
+    sp.a0 = ((int)fa) >> Q; sp.b0 = ((int)fb) >> Q;
+    return sp;
+}
+
+// Distance along axis a from x to cell k of resolution Q (0 inside).  On
+// open axes the first and last cells extend to infinity, because positions
+// outside the box are clamped into them.
+__device__ __forceinline__ double cell_gap(const Grid& g, int a, double x, int k, int Q)
+{
+    const int nx0 = g.nx0[a];
+    const int k0 = k << Q;
+    int k1 = (k + 1) << Q;
+    if (k1 > nx0) k1 = nx0;
+    const double lo = g.org[a] + (double)k0 * g.cw0[a];
+    const double hi = g.org[a] + (double)k1 * g.cw0[a];
+    if (g.periodic[a]) {
+        const double d = fabs(mi_axis(g, a, x - 0.5 * (lo + hi))) - 0.5 * (hi - lo);
+        return d > 0.0 ? d : 0.0;
+    }
+    if (x < lo && k0 > 0) return lo - x;
+    if (x > hi && k1 < nx0) return x - hi;
+    return 0.0;
 }
 
 __device__ __forceinline__ int key_level(const Grid& g, uint64_t key) { return (int)(key >> (2 * g.bits)); }
 
-// Visits every j with |r_i - r_j|^2 < (3 max(h_i, h_j))^2, calling
-// f(js, dx, dy, r2, hj) with js the sorted position of j and (dx, dy) the
-// minimum-image displacement r_i - r_j.  The predicate is evaluated in
-// double with the operation order of the definition.
+// Visits every j of level l with |r_i - r_j|^2 < (3 max(h_i, h_j))^2,
+// calling f(js, dx, dy, r2, hj) with js the sorted position of j and
+// (dx, dy) the minimum-image displacement r_i - r_j.  Level l is searched
+// with radius 3 max(h_i, hmax_l) at resolution max(l, l_i); cells whose box
+// misses that disk are skipped.  The predicate is evaluated in double with
+// the operation order of the definition.
+template <class F>
+__device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const NbrView& nv,
+                                                        double xi, double yi, double hi, int li,
+                                                        int l, F&& f)
+{
+    const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
+    const double R = 3.0 * (hi > hl ? hi : hl);
+    const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
+    const double Rs2 = Rs * Rs;
+    const int Q = l > li ? l : li;
+    const Span xr = axis_span(g, 0, xi, R, Q);
+    const Span yr = axis_span(g, 1, yi, R, Q);
+    const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
+    const int nq = g.nxq[Q][0];
+    for (int ty = 0; ty < yr.n; ++ty) {
+        const int cy0 = ty ? yr.a1 : yr.a0, cy1 = ty ? yr.b1 : yr.b0;
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const double gy = cell_gap(g, 1, yi, cy, Q);
+            if (gy > Rs) continue;
+            for (int tx = 0; tx < xr.n; ++tx) {
+                const int cx0 = tx ? xr.a1 : xr.a0, cx1 = tx ? xr.b1 : xr.b0;
+                for (int cx = cx0; cx <= cx1; ++cx) {
+                    const double gx = cell_gap(g, 0, xi, cx, Q);
+                    if (gx * gx + gy * gy > Rs2) continue;
+                    const int2 se = tab[(int64_t)cy * nq + cx];
+                    for (int js = se.x; js < se.y; ++js) {
+                        const double xj = nv.xs[js], yj = nv.ys[js], hj = nv.hs[js];
+                        const double dx = mi_axis(g, 0, xi - xj);
+                        const double dy = mi_axis(g, 1, yi - yj);
+                        const double r2 = dx * dx + dy * dy;
+                        const double hm = hi > hj ? hi : hj;
+                        const double RR = 3.0 * hm;
+                        if (r2 < RR * RR) f(js, dx, dy, r2, hj);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// All levels: every j with |r_i - r_j| < 3 max(h_i, h_j).
 template <class F>
 __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& nv, double xi,
                                                   double yi, double hi, int li, F&& f)
 {
     for (int l = 0; l < g.nlev; ++l) {
         if (nv.lcount[l] == 0) continue;
-        double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
-        double R = 3.0 * (hi > hl ? hi : hl);
-        int Q = l > li ? l : li;
-        int xv[4], yv[4];
-        int nxv = axis_ranges(g, 0, xi, R, Q, xv);
-        int nyv = axis_ranges(g, 1, yi, R, Q, yv);
-        const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
-        const int nq = g.nxq[Q][0];
-        for (int a = 0; a < nyv; ++a) {
-            for (int cy = yv[2 * a]; cy <= yv[2 * a + 1]; ++cy) {
-                for (int b = 0; b < nxv; ++b) {
-                    for (int cx = xv[2 * b]; cx <= xv[2 * b + 1]; ++cx) {
-                        int2 se = tab[(int64_t)cy * nq + cx];
-                        for (int js = se.x; js < se.y; ++js) {
-                            double xj = nv.xs[js], yj = nv.ys[js], hj = nv.hs[js];
-                            double dx = mi_axis(g, 0, xi - xj);
-                            double dy = mi_axis(g, 1, yi - yj);
-                            double r2 = dx * dx + dy * dy;
-                            double hm = hi > hj ? hi : hj;
-                            double RR = 3.0 * hm;
-                            if (r2 < RR * RR) f(js, dx, dy, r2, hj);
-                        }
-                    }
-                }
-            }
+        for_each_neighbor_level(g, nv, xi, yi, hi, li, l, f);
+    }
+}
+
+// ---- wave64 helpers ----------------------------------------------------------
+
+__device__ __forceinline__ double wave_min_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// Value of lane k (k wave-uniform) for every lane.
+__device__ __forceinline__ double lane_bcast(double v, int k)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Column-major neighbour list written by pass A and read by pass B:
+// entry k of sorted particle s is idx[k * stride + s] (coalesced across a
+// wave); rows longer than K fall back to the traversal.
+struct NbrList {
+    int32_t* idx;
+    int32_t* cnt;
+    int K;
+    int stride;
+};
+
+// Row s of the list, four neighbours per iteration: the index and position
+// loads of four neighbours are issued before any of their pair terms, so a
+// wave keeps several gathers in flight.
+template <class F>
+__device__ __forceinline__ void for_each_listed(const Grid& g, const NbrView& nv,
+                                                const NbrList& nl, int s, int cnt, double xi,
+                                                double yi, F&& body)
+{
+    int k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        int j[4];
+        double dx[4], dy[4], hj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = nl.idx[(int64_t)(k + u) * nl.stride + s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            dx[u] = mi_axis(g, 0, xi - nv.xs[j[u]]);
+            dy[u] = mi_axis(g, 1, yi - nv.ys[j[u]]);
+            hj[u] = nv.hs[j[u]];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) body(j[u], dx[u], dy[u], dx[u] * dx[u] + dy[u] * dy[u], hj[u]);
+    }
+    for (; k < cnt; ++k) {
+        const int js = nl.idx[(int64_t)k * nl.stride + s];
+        const double ddx = mi_axis(g, 0, xi - nv.xs[js]);
+        const double ddy = mi_axis(g, 1, yi - nv.ys[js]);
+        body(js, ddx, ddy, ddx * ddx + ddy * ddy, nv.hs[js]);
     }
 }

@@ -27,6 +27,10 @@ struct Grid {
     double half[2];     // L/2
     double lo[2], hi[2];
     double cmin0;       // min(cw0[0], cw0[1])
+    double icw0[2];     // 1 / cw0 (cell ranges are conservative, so a
+                        // product instead of a quotient is safe)
+    double mi_l[2];     // minimum image: period (0 on open axes)
+    double mi_h[2];     // minimum image: half period (+inf on open axes)
     int32_t nx0[2];     // level-0 cells per axis
     int32_t periodic[2];
     int32_t nlev;       // number of levels
@@ -76,6 +80,8 @@ struct Work {
     int32_t *tmp_i32[2];
     int64_t *tmp_i64[3];
     int64_t* red;          // reduction scratch
+    int32_t *nl_idx, *nl_cnt; // pass A -> pass B neighbour list
+    int32_t nl_k;
     int64_t capacity;
 };
 
@@ -105,6 +111,7 @@ struct sph_ctx {
 // nbr.hip
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 NbrView nbr_view(sph_ctx* c);
+int nbr_build_list(sph_ctx* c, int n);
 int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
 int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void grid_setup(const sph_config* cfg, Grid* g);
@@ -130,6 +137,7 @@ void prof_end(sph_ctx* c, int slot);
 #define SPH_PROF_PASS_A 0
 #define SPH_PROF_PASS_B 1
 #define SPH_PROF_BUILD 2
+#define SPH_PROF_LIST 3
 
 #define HIPCHK(c, expr)                                         \
     do {                                                        \
