@@ -158,6 +158,7 @@ def main():
                  "ms_per_step": results["fp64"]["ms_per_step"], "steps": args.fp64_steps},
         "fp32_over_fp64": r32["pair_evals_per_s"] / results["fp64"]["pair_evals_per_s"],
         "kernel_ms": {k: (v[0] / max(v[1], 1)) for k, v in r32["prof"].items()},
+        "kernel_launches": {k: v[1] for k, v in r32["prof"].items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }

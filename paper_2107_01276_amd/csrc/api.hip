@@ -10,7 +10,7 @@
 
 #define SPH_VERSION 10000
 #define COL_PER_PARTICLE 160
-#define NL_K 128
+#define NL_K 160
 
 void set_err(sph_ctx* c, const char* fmt, ...)
 {
@@ -87,6 +87,11 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
     w->nl_k = NL_K;
     w->nl_idx = (int32_t*)take(4 * (size_t)NL_K * C);
     w->nl_cnt = (int32_t*)take(4 * C);
+    w->xref = (double*)take(8 * C);
+    w->yref = (double*)take(8 * C);
+    w->href = (double*)take(8 * C);
+    w->list_flag = (int32_t*)take(4 * 64);
+    w->pk = (float4*)take(16 * C);
     return off + 256;
 }
 
@@ -135,6 +140,8 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->prof[SPH_PROF_PASS_B].name = "pass_b";
     c->prof[SPH_PROF_BUILD].name = "build";
     c->prof[SPH_PROF_LIST].name = "list";
+    c->skin = 0.1;
+    c->list_valid = 0;
     *out = c;
     return SPH_OK;
 }

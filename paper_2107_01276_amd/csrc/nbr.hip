@@ -59,6 +59,16 @@ void grid_setup(const sph_config* cfg, Grid* g)
         g->mi_l[a] = g->periodic[a] ? g->L[a] : 0.0;
         g->mi_h[a] = g->periodic[a] ? g->half[a] : HUGE_VAL;
     }
+    // coordinates relative to the origin stay below ext in magnitude (with
+    // generous room for particles outside an open box); a difference of two
+    // of them rounded to FP32, with one period folded in, is off by at most
+    // a few ulp of ext
+    double ext = 0.0;
+    for (int a = 0; a < 2; ++a) {
+        double e = 4.0 * (fabs(g->lo[a]) + fabs(g->hi[a]) + g->L[a]) + 1.0;
+        if (e > ext) ext = e;
+    }
+    g->f32_pad = 16.0 * ldexp(ext, -24);
     int nlev = 1;
     double c = g->cmin0;
     while (c < 3.0 * hhi * (1.0 + 1e-9) && nlev < SPH_MAXL) {
@@ -417,6 +427,7 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
 {
     Work& w = c->w;
     const Grid& g = c->grid;
+    c->list_valid = 0;  // a new sorted order invalidates any reusable list
     prof_begin(c, SPH_PROF_BUILD);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, w.hmax_bits, (int64_t)SPH_MAXL);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.lcount, (int64_t)SPH_MAXL);
@@ -437,6 +448,19 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
     }
     prof_end(c, SPH_PROF_BUILD);
     c->built_n = n;
+    return SPH_OK;
+}
+
+// Refreshes the sorted positions for the current state without sorting
+// again (the order of the last build is kept).
+int nbr_regather(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+{
+    Work& w = c->w;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
+                           w.vals_a, x, y, h, w.xs, w.ys, w.hs);
+        LAUNCHCHK(c, "regather");
+    }
     return SPH_OK;
 }
 
@@ -477,8 +501,23 @@ __device__ __forceinline__ double mi_t(const Grid& g, int a, double d)
     return P ? mi_axis(g, a, d) : d;
 }
 
+// Sorted particles packed for the list pre-test: FP32 coordinates relative
+// to the grid origin and the squared search radius sf 3 h padded by the
+// FP32 rounding bound of a displacement.
+__global__ __launch_bounds__(256) void k_pack32(Grid g, int n, const double* __restrict__ xs,
+                                                const double* __restrict__ ys,
+                                                const double* __restrict__ hs, double sf,
+                                                float4* pk)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double r = (3.0 * hs[s]) * sf * (1.0 + 1e-6) + g.f32_pad;
+    pk[s] = make_float4((float)(xs[s] - g.org[0]), (float)(ys[s] - g.org[1]), (float)(r * r), 0.f);
+}
+
 template <bool PX, bool PY>
-__global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, NbrList nl)
+__global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, NbrList nl,
+                                                    double sf, const float4* __restrict__ pk)
 {
     __shared__ int s_pre[4][64], s_beg[4][64];
     const int lane = __lane_id();
@@ -489,14 +528,19 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
     const bool valid = s < n;
     const int sv = valid ? s : s0;
     const double xi = nv.xs[sv], yi = nv.ys[sv], hi = nv.hs[sv];
-    const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+    const float4 pi = pk[sv];
+    const float xi32 = pi.x, yi32 = pi.y, ri2f = pi.z;
+    const float Lx = (float)g.mi_l[0], Ly = (float)g.mi_l[1];
+    const float hLx = 0.5f * Lx, hLy = 0.5f * Ly;
     const int li = key_level(g, nv.keys[sv]);
     int cnt = 0;
+    int32_t* out = nl.idx + s;                            // row cnt of this particle
+    int32_t* const last = nl.idx + (int64_t)(nl.K - 1) * nl.stride + s;
     auto emit = [&](int js) {
         // an overflowing row (cnt > K) is searched again by the rate passes,
         // so its last slot may be overwritten
-        const int k = cnt < nl.K ? cnt : nl.K - 1;
-        nl.idx[(int64_t)k * nl.stride + s] = js;
+        *out = js;
+        out = out == last ? out : out + nl.stride;
         ++cnt;
     };
     // segments of the wave
@@ -512,8 +556,9 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
     if (nseg > LIST_MAX_SEG) {
         if (valid) {
             for_each_neighbor(g, nv, xi, yi, hi, li,
-                              [&](int js, double, double, double, double) { emit(js); });
+                              [&](int js, double, double, double, double) { emit(js); }, sf);
             nl.cnt[s] = cnt;
+            if (cnt > nl.K) nl.flag[0] = 1;
         }
         return;
     }
@@ -524,8 +569,7 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
         for (int l = 0; l < g.nlev; ++l) {
             if (nv.lcount[l] == 0) continue;
             const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
-            const double R = 3.0 * (hi > hl ? hi : hl);
-            const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
+            const double R = 3.0 * (hi > hl ? hi : hl) * sf;
             const double bx0 = wave_min_d(mem ? xi - R : INF), bx1 = wave_max_d(mem ? xi + R : -INF);
             const double by0 = wave_min_d(mem ? yi - R : INF), by1 = wave_max_d(mem ? yi + R : -INF);
             const bool wrap = (g.periodic[0] && bx1 - bx0 > g.half[0]) ||
@@ -533,7 +577,8 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
             if (wrap) {
                 if (mem)
                     for_each_neighbor_level(g, nv, xi, yi, hi, li, l,
-                                            [&](int js, double, double, double, double) { emit(js); });
+                                            [&](int js, double, double, double, double) { emit(js); },
+                                            sf);
                 continue;
             }
             const int Q = l > lseg ? l : lseg;
@@ -568,9 +613,9 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const int nc = ncell - c0 < 64 ? ncell - c0 : 64;
-                auto fetch = [&](int p, int& js, double& fx, double& fy, double& fh) {
+                auto fetch = [&](int p, int& js, float4& f) {
                     js = 0;
-                    fx = 0.0; fy = 0.0; fh = 0.0;
+                    f = make_float4(0.f, 0.f, 0.f, 0.f);
                     if (p < total) {
                         int lo = 0, hi2 = nc - 1;  // last cell whose offset <= p
                         while (lo < hi2) {
@@ -579,71 +624,67 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
                             else hi2 = mid - 1;
                         }
                         js = s_beg[w][lo] + (p - s_pre[w][lo]);
-                        fx = nv.xs[js];
-                        fy = nv.ys[js];
-                        const double r3 = 3.0 * nv.hs[js];
-                        fh = r3 * r3;
+                        f = pk[js];
                     }
                 };
+                auto bc = [](float v, int k) {
+                    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+                };
+                // conservative FP32 pre-test: a superset of the pairs closer
+                // than sf 3 max(h_i, h_j); the rate passes test exactly
+                auto test = [&](const float4& A, int k) -> bool {
+                    float dx = xi32 - bc(A.x, k), dy = yi32 - bc(A.y, k);
+                    if (PX) dx = dx > hLx ? dx - Lx : (dx < -hLx ? dx + Lx : dx);
+                    if (PY) dy = dy > hLy ? dy - Ly : (dy < -hLy ? dy + Ly : dy);
+                    return mem && dx * dx + dy * dy < fmaxf(ri2f, bc(A.z, k));
+                };
                 int jA;
-                double xA, yA, hA;
-                fetch(lane, jA, xA, yA, hA);
+                float4 A;
+                fetch(lane, jA, A);
                 for (int base = 0; base < total; base += 64) {
                     int jB;
-                    double xB, yB, hB;
-                    fetch(base + 64 + lane, jB, xB, yB, hB);
+                    float4 B;
+                    fetch(base + 64 + lane, jB, B);
                     const int m = total - base < 64 ? total - base : 64;
-                    // r2 < (3 max(h_i, h_j))^2  <=>  r2 < max((3 h_i)^2, (3 h_j)^2),
-                    // exactly, since scaling and squaring round monotonically
                     int k = 0;
                     for (; k + 4 <= m; k += 4) {
                         bool hit[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const double xj = lane_bcast(xA, k + u);
-                            const double yj = lane_bcast(yA, k + u);
-                            const double rj2 = lane_bcast(hA, k + u);
-                            const double dx = mi_t<PX>(g, 0, xi - xj);
-                            const double dy = mi_t<PY>(g, 1, yi - yj);
-                            const double r2 = dx * dx + dy * dy;
-                            hit[u] = mem && r2 < fmax(ri2, rj2);
-                        }
+                        for (int u = 0; u < 4; ++u) hit[u] = test(A, k + u);
+                        if (__ballot(hit[0] || hit[1] || hit[2] || hit[3]) == 0ull) continue;
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
                             if (hit[u]) emit(__builtin_amdgcn_readlane(jA, k + u));
                     }
-                    for (; k < m; ++k) {
-                        const double xj = lane_bcast(xA, k);
-                        const double yj = lane_bcast(yA, k);
-                        const double rj2 = lane_bcast(hA, k);
-                        const double dx = mi_t<PX>(g, 0, xi - xj);
-                        const double dy = mi_t<PY>(g, 1, yi - yj);
-                        const double r2 = dx * dx + dy * dy;
-                        if (mem && r2 < fmax(ri2, rj2)) emit(__builtin_amdgcn_readlane(jA, k));
-                    }
+                    for (; k < m; ++k)
+                        if (test(A, k)) emit(__builtin_amdgcn_readlane(jA, k));
                     jA = jB;
-                    xA = xB;
-                    yA = yB;
-                    hA = hB;
+                    A = B;
                 }
                 __builtin_amdgcn_wave_barrier();
             }
         }
     }
-    if (valid) nl.cnt[s] = cnt;
+    if (valid) {
+        nl.cnt[s] = cnt;
+        if (cnt > nl.K) nl.flag[0] = 1;
+    }
 }
 
-int nbr_build_list(sph_ctx* c, int n)
+int nbr_build_list(sph_ctx* c, int n, double skin)
 {
     Work& w = c->w;
     if (n == 0) return SPH_OK;
-    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n};
+    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
     prof_begin(c, SPH_PROF_LIST);
     const Grid& g = c->grid;
+    const double sf = 1.0 + skin;
+    hipLaunchKernelGGL(k_pack32, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n, w.xs, w.ys,
+                       w.hs, sf, w.pk);
     auto kern = g.periodic[0] ? (g.periodic[1] ? k_build_list<true, true> : k_build_list<true, false>)
                               : (g.periodic[1] ? k_build_list<false, true> : k_build_list<false, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nbr_view(c), n,
-                       nl);
+                       nl, sf, (const float4*)w.pk);
     prof_end(c, SPH_PROF_LIST);
     LAUNCHCHK(c, "build_list");
     return SPH_OK;

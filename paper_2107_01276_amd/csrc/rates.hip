@@ -83,7 +83,9 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     const T irho0 = T(1.0 / rho0);
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
     CSum<T> sr, sb, sp, sx, sy;
+    int nn = 0;  // |N(i)|
     auto body = [&](int js, double dx, double dy, double r2, double hj) __attribute__((always_inline)) {
+        ++nn;
         const T mj = b.m[js];
         const T r = fsqrt<T>((T)r2);
         const T q = r * ih;
@@ -102,19 +104,12 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
             sy.add(t * (T)dy);
         }
     };
-    int cnt = nl.cnt[s];
-    if (cnt <= nl.K) {
-        for_each_listed(g, nv, nl, s, cnt, xi, yi, body);
-    } else {
-        cnt = 0;
-        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
-            body(js, dx, dy, r2, hj);
-            ++cnt;
-        });
-    }
+    const int cnt = nl.cnt[s];
+    if (cnt <= nl.K) for_each_listed(g, nv, nl, s, cnt, xi, yi, hi, body);
+    else for_each_neighbor(g, nv, xi, yi, hi, li, body);
     const T rho = sr.get();
     const T beta = -sb.get() / (T(2) * rho);
-    const T N = (T)cnt;
+    const T N = (T)nn;
     const T dpav = sp.get() / N;
     const T pref = T(-0.5) * (T)(hi * hi);
     T ddx = pref * sx.get(), ddy = pref * sy.get();
@@ -142,7 +137,7 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     if (out.rho) out.rho[slot] = (double)rho;
     if (out.beta) out.beta[slot] = (double)beta;
     if (out.pavg) out.pavg[slot] = pi + (double)dpav;
-    if (out.nnb) out.nnb[slot] = (double)cnt;
+    if (out.nnb) out.nnb[slot] = (double)nn;
     if (out.dxs) out.dxs[slot] = (double)ddx;
     if (out.dys) out.dys[slot] = (double)ddy;
 }
@@ -201,7 +196,7 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     };
     const int cnt = nl.cnt[s];
     if (cnt <= nl.K) {
-        for_each_listed(g, nv, nl, s, cnt, xi, yi, body);
+        for_each_listed(g, nv, nl, s, cnt, xi, yi, hi, body);
     } else {
         for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), body);
     }
@@ -215,14 +210,84 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     dvdt[slot] = (double)(-gy + vy * ib) + P.fy;
 }
 
-// One evaluation on (x, y, u, v, p, h, mq): build + pass A + pass B.
+// Does the list built on (xref, yref, href) still hold N(i) for (x, y, h)?
+// Not if some particle moved by 1.5 skin h_i or more (then a pair may have
+// closed by 3 skin max(h_i, h_j)) or changed h; flag[0] is set then.
+__global__ __launch_bounds__(256) void k_list_check(Grid g, int n, const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ h,
+                                                    const double* __restrict__ xref,
+                                                    const double* __restrict__ yref,
+                                                    const double* __restrict__ href, double lim,
+                                                    int32_t* flag)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double dx = mi_axis(g, 0, x[i] - xref[i]);
+    const double dy = mi_axis(g, 1, y[i] - yref[i]);
+    const double r = lim * href[i];
+    if (!(dx * dx + dy * dy < r * r) || h[i] != href[i]) flag[0] = 1;
+}
+
+__global__ void k_clear_flag(int32_t* flag)
+{
+    if (threadIdx.x == 0) flag[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_copy3(int n, const double* __restrict__ a,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ c, double* a2,
+                                               double* b2, double* c2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    a2[i] = a[i];
+    b2[i] = b[i];
+    c2[i] = c[i];
+}
+
+// Neighbour structure and list for (x, y, h): reuses the last list (only
+// the sorted positions are refreshed) when it still covers every pair, else
+// sorts and builds a list with a skin.
+static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+{
+    Work& w = c->w;
+    bool reuse = c->list_valid && c->list_n == n && c->skin > 0 && n > 0;
+    unsigned nb = (unsigned)cdiv(n > 0 ? n : 1, 256);
+    if (reuse) {
+        hipLaunchKernelGGL(k_list_check, dim3(nb), dim3(256), 0, c->stream, c->grid, n, x, y, h, w.xref,
+                           w.yref, w.href, 1.5 * c->skin, w.list_flag);
+        LAUNCHCHK(c, "list_check");
+        int32_t f = 1;
+        HIPCHK(c, hipMemcpyAsync(&f, w.list_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        reuse = (f == 0);
+    }
+    if (reuse) {
+        c->list_reuses++;
+        return nbr_regather(c, n, x, y, h);
+    }
+    int rc = nbr_build(c, n, x, y, h);
+    if (rc || n == 0) return rc;
+    hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, c->stream, w.list_flag);
+    rc = nbr_build_list(c, n, c->skin);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_copy3, dim3(nb), dim3(256), 0, c->stream, n, x, y, h, w.xref, w.yref, w.href);
+    LAUNCHCHK(c, "list_ref");
+    c->list_valid = 1;
+    c->list_n = n;
+    c->list_builds++;
+    return SPH_OK;
+}
+
+// One evaluation on (x, y, u, v, p, h, mq): neighbours + pass A + pass B.
 template <typename T>
 static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const double* u,
                   const double* v, const double* p, const double* h, const int64_t* mq, double dt,
                   PassAOut aout, double* dpdt, double* dudt, double* dvdt)
 {
     Work& w = c->w;
-    int rc = nbr_build(c, n, x, y, h);
+    int rc = ensure_list(c, n, x, y, h);
     if (rc) return rc;
     if (n == 0) return SPH_OK;
     NbrView nv = nbr_view(c);
@@ -232,9 +297,7 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const dou
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
                        cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih);
     LAUNCHCHK(c, "gather_state");
-    rc = nbr_build_list(c, n);
-    if (rc) return rc;
-    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n};
+    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
     prof_begin(c, SPH_PROF_PASS_A);
     hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                        cf.rho0, aout, w.r_dxs, w.r_dys);

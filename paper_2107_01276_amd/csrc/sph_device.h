@@ -237,13 +237,15 @@ __device__ __forceinline__ int key_level(const Grid& g, uint64_t key) { return (
 // with radius 3 max(h_i, hmax_l) at resolution max(l, l_i); cells whose box
 // misses that disk are skipped.  The predicate is evaluated in double with
 // the operation order of the definition.
+// With sf > 1 the radius 3 max(h_i, h_j) is scaled by sf (a superset of
+// N(i), used for reusable lists); sf = 1 is the exact predicate.
 template <class F>
 __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const NbrView& nv,
                                                         double xi, double yi, double hi, int li,
-                                                        int l, F&& f)
+                                                        int l, F&& f, double sf = 1.0)
 {
     const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
-    const double R = 3.0 * (hi > hl ? hi : hl);
+    const double R = 3.0 * (hi > hl ? hi : hl) * sf;
     const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
     const double Rs2 = Rs * Rs;
     const int Q = l > li ? l : li;
@@ -268,7 +270,7 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
                         const double dy = mi_axis(g, 1, yi - yj);
                         const double r2 = dx * dx + dy * dy;
                         const double hm = hi > hj ? hi : hj;
-                        const double RR = 3.0 * hm;
+                        const double RR = (3.0 * hm) * sf;
                         if (r2 < RR * RR) f(js, dx, dy, r2, hj);
                     }
                 }
@@ -277,14 +279,15 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
     }
 }
 
-// All levels: every j with |r_i - r_j| < 3 max(h_i, h_j).
+// All levels: every j with |r_i - r_j| < sf 3 max(h_i, h_j).
 template <class F>
 __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& nv, double xi,
-                                                  double yi, double hi, int li, F&& f)
+                                                  double yi, double hi, int li, F&& f,
+                                                  double sf = 1.0)
 {
     for (int l = 0; l < g.nlev; ++l) {
         if (nv.lcount[l] == 0) continue;
-        for_each_neighbor_level(g, nv, xi, yi, hi, li, l, f);
+        for_each_neighbor_level(g, nv, xi, yi, hi, li, l, f, sf);
     }
 }
 
@@ -325,16 +328,28 @@ struct NbrList {
     int32_t* cnt;
     int K;
     int stride;
+    int32_t* flag;  // set to 1 when a row overflows K
 };
 
 // Row s of the list, four neighbours per iteration: the index and position
 // loads of four neighbours are issued before any of their pair terms, so a
 // wave keeps several gathers in flight.
+// Rows may hold a superset of N(i) (a list built with a skin and reused
+// after the particles moved); every entry is re-tested with the exact
+// predicate r2 < (3 max(h_i, h_j))^2, written as r2 < max((3 h_i)^2,
+// (3 h_j)^2), which is the same test because scaling and squaring round
+// monotonically.
 template <class F>
 __device__ __forceinline__ void for_each_listed(const Grid& g, const NbrView& nv,
                                                 const NbrList& nl, int s, int cnt, double xi,
-                                                double yi, F&& body)
+                                                double yi, double hi, F&& body)
 {
+    const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+    auto test = [&](int js, double dx, double dy, double hj) __attribute__((always_inline)) {
+        const double r2 = dx * dx + dy * dy;
+        const double rj3 = 3.0 * hj;
+        if (r2 < fmax(ri2, rj3 * rj3)) body(js, dx, dy, r2, hj);
+    };
     int k = 0;
     for (; k + 4 <= cnt; k += 4) {
         int j[4];
@@ -348,12 +363,10 @@ __device__ __forceinline__ void for_each_listed(const Grid& g, const NbrView& nv
             hj[u] = nv.hs[j[u]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) body(j[u], dx[u], dy[u], dx[u] * dx[u] + dy[u] * dy[u], hj[u]);
+        for (int u = 0; u < 4; ++u) test(j[u], dx[u], dy[u], hj[u]);
     }
     for (; k < cnt; ++k) {
         const int js = nl.idx[(int64_t)k * nl.stride + s];
-        const double ddx = mi_axis(g, 0, xi - nv.xs[js]);
-        const double ddy = mi_axis(g, 1, yi - nv.ys[js]);
-        body(js, ddx, ddy, ddx * ddx + ddy * ddy, nv.hs[js]);
+        test(js, mi_axis(g, 0, xi - nv.xs[js]), mi_axis(g, 1, yi - nv.ys[js]), nv.hs[js]);
     }
 }

@@ -31,6 +31,8 @@ struct Grid {
                         // product instead of a quotient is safe)
     double mi_l[2];     // minimum image: period (0 on open axes)
     double mi_h[2];     // minimum image: half period (+inf on open axes)
+    double f32_pad;     // bound on the FP32 rounding of a displacement
+                        // relative to the grid origin (list pre-test)
     int32_t nx0[2];     // level-0 cells per axis
     int32_t periodic[2];
     int32_t nlev;       // number of levels
@@ -82,6 +84,9 @@ struct Work {
     int64_t* red;          // reduction scratch
     int32_t *nl_idx, *nl_cnt; // pass A -> pass B neighbour list
     int32_t nl_k;
+    double *xref, *yref, *href; // state the list was built on (slot order)
+    float4* pk;                 // sorted (x - org, y - org, padded radius^2) in FP32
+    int32_t* list_flag;         // [0]: rebuild needed (moved / h changed / overflow)
     int64_t capacity;
 };
 
@@ -104,6 +109,14 @@ struct sph_ctx {
     int32_t prof_on;
     ProfSlot prof[4];
     int built_n;       // particle count of the last build
+    // Neighbour-list reuse: the list holds every pair closer than
+    // (1 + skin) 3 max(h_i, h_j) at build time, so it stays a superset of
+    // N(i) while every particle has moved less than 1.5 skin h_i; the rate
+    // passes re-apply the exact predicate.
+    double skin;
+    int list_valid;
+    int list_n;
+    int64_t list_builds, list_reuses;
 };
 
 // ---- host-side launch wrappers (implemented in the .hip files) ----------
@@ -111,7 +124,8 @@ struct sph_ctx {
 // nbr.hip
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 NbrView nbr_view(sph_ctx* c);
-int nbr_build_list(sph_ctx* c, int n);
+int nbr_build_list(sph_ctx* c, int n, double skin);
+int nbr_regather(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
 int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void grid_setup(const sph_config* cfg, Grid* g);

@@ -101,6 +101,36 @@ def test_rates_vs_oracle(case, prec):
         assert errs[k] < tol, (k, errs[k])
 
 
+def test_list_reuse_after_moves():
+    """The rate passes reuse a neighbour list built with a skin while every
+    particle moved less than the allowance, and rebuild otherwise.  Rates
+    must match the oracle after a small move (list reused), after a move
+    larger than the allowance (list rebuilt) and after changing h."""
+    P = lib()
+    s = _rates_case("clustered")
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    rng = np.random.default_rng(3)
+    dt = 1e-4
+    for label, scale in (("initial", 0.0), ("small", 0.02), ("large", 0.6), ("small2", 0.02)):
+        s = dict(s)
+        jit = scale * s["h"]
+        s["x"] = s["x"] + rng.uniform(-jit, jit)
+        s["y"] = s["y"] + rng.uniform(-jit, jit)
+        lo, hi = s["domain"].lo, s["domain"].hi
+        s["y"] = lo[1] + np.mod(s["y"] - lo[1], hi[1] - lo[1])
+        s["x"] = np.clip(s["x"], lo[0], np.nextafter(hi[0], lo[0]))
+        r = ctx.rates(particles(P, s), dt)
+        o = _oracle_rates(s, dt)
+        assert np.array_equal(r["nnb"].cpu().numpy(), o["nnb"]), label
+        for k in FIELDS:
+            assert rel_norm(r[k].cpu().numpy(), o[k]) < 1e-12, (label, k)
+    s = dict(s)
+    s["h"] = s["h"] * 1.05
+    r = ctx.rates(particles(P, s), dt)
+    o = _oracle_rates(s, dt)
+    assert np.array_equal(r["nnb"].cpu().numpy(), o["nnb"])
+
+
 def test_pec_steps_vs_oracle():
     """Periodic Taylor-Green, 50x50, Re = 100, 20 PEC steps in FP64."""
     P = lib()
