@@ -247,6 +247,39 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
     }
 
 
+def channel_background(spec: ChannelSpec | None = None, seed: int = 3, sparsity: float = 2.0):
+    """Background particles for the channel, prescribed from the grading
+    recipe of `channel_cylinder` (section 3.3 allows the reference mass to be
+    assigned directly; for a stationary body the background is never
+    updated).  Rings around the cylinder at spacing `sparsity` * s(d), with
+    size ds = s(d) (the continuous target size), m_ref = rho0 ds^2 and
+    h = 1.3 * sparsity * s(d) (about N_r = 48 neighbours)."""
+    s = spec or ChannelSpec()
+    rng = np.random.default_rng(seed)
+    R = 0.5 * s.diameter
+    ds_max = s.ds_min * s.ratio
+    slope = math.log(s.cr) / s.rows_per_layer
+    lo = (0.0, s.cyl_y - 0.5 * s.height)
+    hi = (s.length, s.cyl_y + 0.5 * s.height)
+    rmax = math.hypot(max(s.cyl_x - lo[0], hi[0] - s.cyl_x), 0.5 * s.height) + ds_max
+    xs, ys, dss = [], [], []
+    r = R
+    while r < rmax:
+        size = min(s.ds_min + (r - R) * slope, ds_max)
+        step = sparsity * size
+        px, py = _ring_points(rng, r, step, s.cyl_x, s.cyl_y)
+        xs.append(px); ys.append(py); dss.append(np.full(px.size, size))
+        r += step
+    x = np.concatenate(xs); y = np.concatenate(ys); ds = np.concatenate(dss)
+    keep = (x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1])
+    x, y, ds = x[keep], y[keep], ds[keep]
+    m = s.rho0 * ds * ds
+    q = mass_quantum(1.05 * s.rho0 * ds_max ** 2 * 1.5)
+    return {"x": x, "y": y, "h": 1.3 * sparsity * ds, "ds": ds,
+            "mask": (ds <= s.ds_min * (1 + 1e-12)).astype(np.int32),
+            "mq": quantize_mass(m, q), "mass_q": q, "mref": m}
+
+
 def background_lattice(domain: Domain, ds_max: float, hdx: float, rho0: float,
                        seed: int = 0, jitter: float = 0.0):
     """Background particles at the coarsest size ds_max (section 3.3)."""
