@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
                                                      const double* __restrict__ bmref,
                                                      double* mref_out, int32_t* none)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double xi = x[i], yi = y[i], hi = h[i];
     const int li = level_of(g, hi);
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_split_apply(Grid g, int n, FluidState s
 __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n, FluidState s,
                                                        double q, double mmax_f, int32_t* closest)
 {
-    int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (sp >= n) return;
     const int i = nv.perm[sp];
     const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
@@ -225,6 +225,8 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     int best = -1;
     double br = 0.0;
     if (ki == SPH_FLUID && !(mi > mmi)) {
+        // a merge partner lies within (h_i + h_j)/2 <= max(h_i, h_j): a third
+        // of the support radius (0.34 leaves margin for rounding) bounds it
         for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
             const int j = nv.perm[js];
             if (j == i) return;
@@ -241,7 +243,7 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
                 best = j;
                 br = r2;
             }
-        });
+        }, 0.34);
     }
     closest[i] = best;
 }
@@ -347,15 +349,17 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
                                                       double rho0, double* ddx_o, double* ddy_o,
                                                       double* nu_o, double* nv_o, double* np_o)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (s.kind && s.kind[i] != SPH_FLUID) {
         ddx_o[i] = 0.0; ddy_o[i] = 0.0;
         nu_o[i] = s.u[i]; nv_o[i] = s.v[i]; np_o[i] = s.p[i];
         return;
     }
-    double ddx, ddy;
-    shift_row(g, i, rp, col, s.x, s.y, s.h, s.mq, q, rho0, &ddx, &ddy);
+    // shift sums and the Taylor gradients share one sweep over the row; every
+    // accumulator still adds its terms in ascending column order
+    const double fxi = kern_f<double>(SPH_XI);
+    double sx = 0.0, sy = 0.0;
     double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
     const double xi = s.x[i], yi = s.y[i], hi = s.h[i];
     const double ui = s.u[i], vi = s.v[i], pi = s.p[i];
@@ -365,13 +369,31 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
         const double dy = mi_axis(g, 1, yi - s.y[j]);
         const double r = sqrt(dx * dx + dy * dy);
         if (r <= 0.0) continue;
+        const double mj = (double)s.mq[j] * q;
+        // shifting term at h_ij
+        const double hij = 0.5 * (hi + s.h[j]);
+        const double wr = kern_f<double>(r / hij) / fxi;
+        const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+        const double t = coef * (kern_dw64(r, hij) / r);
+        sx = sx + t * dx;
+        sy = sy + t * dy;
+        // gradients at h_i
         const double f = kern_dw64(r, hi) / r;
         const double wx = f * dx, wy = f * dy;
-        const double Vj = ((double)s.mq[j] * q) / s.rho[j];
+        const double Vj = mj / s.rho[j];
         const double du = s.u[j] - ui, dv = s.v[j] - vi, dp = s.p[j] - pi;
         gux += Vj * du * wx; guy += Vj * du * wy;
         gvx += Vj * dv * wx; gvy += Vj * dv * wy;
         gpx += Vj * dp * wx; gpy += Vj * dp * wy;
+    }
+    const double pref = -0.5 * (hi * hi);
+    double ddx = pref * sx, ddy = pref * sy;
+    const double mag = sqrt(ddx * ddx + ddy * ddy);
+    const double lim = 0.25 * hi;
+    if (mag > lim) {
+        const double th = lim / mag;
+        ddx = ddx * th;
+        ddy = ddy * th;
     }
     ddx_o[i] = ddx;
     ddy_o[i] = ddy;
@@ -404,7 +426,7 @@ __global__ __launch_bounds__(256) void k_hupdate(int n, const int64_t* __restric
                                                  double hdx, const double* __restrict__ h,
                                                  double* nh)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (kind && kind[i] != SPH_FLUID) {
         nh[i] = h[i];
@@ -453,17 +475,29 @@ static FluidState tmp_state(sph_ctx* c, bool with_kind)
     return d;
 }
 
+__global__ __launch_bounds__(256) void k_copy_state(FluidState a, FluidState b, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    b.x[i] = a.x[i];
+    b.y[i] = a.y[i];
+    b.u[i] = a.u[i];
+    b.v[i] = a.v[i];
+    b.p[i] = a.p[i];
+    b.rho[i] = a.rho[i];
+    b.h[i] = a.h[i];
+    b.mref[i] = a.mref[i];
+    b.mq[i] = a.mq[i];
+    b.origin[i] = a.origin[i];
+    b.sat[i] = a.sat[i];
+    if (a.kind && b.kind) b.kind[i] = a.kind[i];
+}
+
 static int copy_state(sph_ctx* c, const FluidState& a, FluidState& b, int n)
 {
-    hipStream_t st = c->stream;
-    size_t d8 = 8 * (size_t)n, d4 = 4 * (size_t)n;
-    const double* sa[8] = {a.x, a.y, a.u, a.v, a.p, a.rho, a.h, a.mref};
-    double* sb[8] = {b.x, b.y, b.u, b.v, b.p, b.rho, b.h, b.mref};
-    for (int k = 0; k < 8; ++k) HIPCHK(c, hipMemcpyAsync(sb[k], sa[k], d8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(b.mq, a.mq, d8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(b.origin, a.origin, d8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, hipMemcpyAsync(b.sat, a.sat, d4, hipMemcpyDeviceToDevice, st));
-    if (a.kind && b.kind) HIPCHK(c, hipMemcpyAsync(b.kind, a.kind, d4, hipMemcpyDeviceToDevice, st));
+    if (n <= 0) return SPH_OK;
+    hipLaunchKernelGGL(k_copy_state, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, a, b, n);
+    LAUNCHCHK(c, "copy_state");
     return SPH_OK;
 }
 

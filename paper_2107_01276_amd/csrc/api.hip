@@ -225,10 +225,25 @@ extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* ou
     return diag_run(c, ps, out);
 }
 
+// The background shares the context's search workspace: it must fit it.
+static bool check_bg(sph_ctx* c, const sph_background* bg)
+{
+    if (bg->n < 0 || bg->n > bg->capacity || bg->capacity > c->capacity) {
+        set_err(c, "background n=%lld capacity=%lld context capacity=%lld", (long long)bg->n,
+                (long long)bg->capacity, (long long)c->capacity);
+        return false;
+    }
+    if (bg->n > 0 && (!bg->x || !bg->y || !bg->h || !bg->mref)) {
+        set_err(c, "background arrays not set");
+        return false;
+    }
+    return true;
+}
+
 extern "C" int sph_mref_lookup(sph_ctx* c, const sph_particles* ps, const sph_background* bg)
 {
     if (!c || !bg) return SPH_E_INVAL;
-    if (!check_ps(c, ps, 0) || !ps->mref) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 0) || !ps->mref || !check_bg(c, bg)) return SPH_E_INVAL;
     return mref_lookup_run(c, ps, bg);
 }
 
@@ -236,6 +251,7 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
 {
     if (!c || !map) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref) return SPH_E_INVAL;
+    if (bg && !check_bg(c, bg)) return SPH_E_INVAL;
     return adapt_run(c, ps, bg, map);
 }
 
@@ -243,10 +259,7 @@ extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles
                              const double* phi, double phi_thresh, int32_t passes, int64_t* nsplit)
 {
     if (!c || !bg || !solids || !nsplit || passes < 0) return SPH_E_INVAL;
-    if (bg->n < 0 || bg->n > bg->capacity || bg->capacity > c->capacity) {
-        set_err(c, "background n/capacity out of range");
-        return SPH_E_INVAL;
-    }
+    if (!check_bg(c, bg)) return SPH_E_INVAL;
     return bg_update_run(c, bg, solids, phi, phi_thresh, passes, nsplit);
 }
 

@@ -522,7 +522,7 @@ __global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, N
     __shared__ int s_pre[4][64], s_beg[4][64];
     const int lane = __lane_id();
     const int w = threadIdx.x >> 6;
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int s0 = s - lane;
     if (s0 >= n) return;  // whole wave past the end
     const bool valid = s < n;
@@ -694,21 +694,10 @@ int nbr_build_list(sph_ctx* c, int n, double skin)
 // CSR export: count, scan, fill, sort rows ascending
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_csr_count(Grid g, NbrView nv, int n, int64_t* cnt)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
-    int li = key_level(g, nv.keys[s]);
-    int64_t k = 0;
-    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int, double, double, double, double) { ++k; });
-    cnt[nv.perm[s]] = k;
-}
-
 __global__ __launch_bounds__(256) void k_csr_fill(Grid g, NbrView nv, int n,
                                                   const int64_t* __restrict__ rp, int32_t* col)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
     int li = key_level(g, nv.keys[s]);
@@ -764,20 +753,112 @@ __global__ void k_sort_long_rows(const int64_t* __restrict__ rp, int32_t* col,
     }
 }
 
+// One traversal: each row's columns (slots, traversal order) go to a
+// row-major staging area of K entries per row; cnt gets the full count and
+// flag[0] is set when a row has more than K entries.
+__global__ __launch_bounds__(256) void k_csr_stage(Grid g, NbrView nv, int n, int K,
+                                                   int32_t* __restrict__ stage,
+                                                   int64_t* __restrict__ cnt, int32_t* flag)
+{
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
+    int li = key_level(g, nv.keys[s]);
+    const int slot = nv.perm[s];
+    int32_t* row = stage + (int64_t)slot * K;
+    int k = 0;
+    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double, double, double, double) {
+        if (k < K) row[k] = nv.perm[js];
+        ++k;
+    });
+    cnt[slot] = k;
+    if (k > K) flag[0] = 1;
+}
+
+// One wave per row: bitonic sort of up to 64 R entries held R per lane
+// (element e = r 64 + lane), written ascending to the row's CSR range.
+template <int R>
+__device__ __forceinline__ void wave_sort_row(const int32_t* __restrict__ src, int len,
+                                              int32_t* __restrict__ dst, int lane)
+{
+    int v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        v[r] = e < len ? src[e] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+                const int rj = j >> 6;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if (r & rj) continue;
+                    const int r2 = r | rj;
+                    const bool up = ((r * 64 + lane) & k) == 0;
+                    const int a = v[r], b = v[r2];
+                    const int lo = a < b ? a : b, hi = a < b ? b : a;
+                    v[r] = up ? lo : hi;
+                    v[r2] = up ? hi : lo;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int o = __shfl_xor(v[r], j, 64);
+                    const bool up = ((r * 64 + lane) & k) == 0;
+                    const bool low = (lane & j) == 0;
+                    v[r] = (low == up) ? min(v[r], o) : max(v[r], o);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = r * 64 + lane;
+        if (e < len) dst[e] = v[r];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_csr_sort_staged(int n, int K, const int32_t* __restrict__ stage,
+                                                         const int64_t* __restrict__ rp,
+                                                         int32_t* __restrict__ col)
+{
+    const int lane = __lane_id();
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int64_t beg = rp[row];
+    const int len = (int)(rp[row + 1] - beg);
+    const int32_t* src = stage + (int64_t)row * K;
+    if (len <= 64)
+        wave_sort_row<1>(src, len, col + beg, lane);
+    else if (len <= 128)
+        wave_sort_row<2>(src, len, col + beg, lane);
+    else
+        wave_sort_row<4>(src, len, col + beg, lane);
+}
+
 int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz)
 {
     Work& w = c->w;
     const Grid& g = c->grid;
     NbrView nv = nbr_view(c);
+    // the staging area is the rate passes' neighbour-list buffer
+    const int K = w.nl_k < 256 ? w.nl_k : 256;
+    c->list_valid = 0;
     if (n > 0) {
-        hipLaunchKernelGGL(k_csr_count, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv,
-                           n, w.cnt64);
-        LAUNCHCHK(c, "csr_count");
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.status, (int64_t)4);
+        hipLaunchKernelGGL(k_csr_stage, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv,
+                           n, K, w.nl_idx, w.cnt64, w.status + 2);
+        LAUNCHCHK(c, "csr_stage");
     }
     int rc = scan_exclusive_i64(c, w.cnt64, row_ptr, n);
     if (rc) return rc;
     int64_t tot = 0;
+    int32_t st[4] = {0, 0, 0, 0};
     HIPCHK(c, hipMemcpyAsync(&tot, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(st, w.status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *nnz = tot;
     if (tot > cap) {
@@ -785,9 +866,15 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
         return SPH_E_CAPACITY;
     }
     if (n == 0) return SPH_OK;
+    if (st[2] == 0) {
+        hipLaunchKernelGGL(k_csr_sort_staged, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, c->stream, n, K,
+                           w.nl_idx, row_ptr, col);
+        LAUNCHCHK(c, "csr_sort");
+        return SPH_OK;
+    }
+    // some row is longer than the staging width: traverse again into the CSR
     hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv, n,
                        row_ptr, col);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.status, (int64_t)1);
     hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, c->stream, n, row_ptr,
                        col, w.long_rows, w.status);
     hipLaunchKernelGGL(k_sort_long_rows, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream,

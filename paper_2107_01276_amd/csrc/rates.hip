@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
                                                 NbrList nl, double rho0, PassAOut out,
                                                 double* r_dxs, double* r_dys)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s], pi = b.ps[s];
     const int li = key_level(g, nv.keys[s]);
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
                                                 const double* __restrict__ vs, PassBParams P,
                                                 double* dpdt, double* dudt, double* dvdt)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
     const double ui = us[s], vi = vs[s], pi = b.ps[s];

@@ -291,6 +291,18 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& 
     }
 }
 
+// ---- XCD-aware block order -----------------------------------------------------
+// Workgroups are dispatched to the 8 XCDs round-robin (XCD = blockIdx % 8),
+// and each XCD has its own L2.  Renumbering so that XCD x runs a contiguous
+// 1/8 of the blocks keeps each XCD on one spatial region of the sorted
+// particles.  A bijection on [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int x = b & 7, loc = b >> 3;
+    return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+}
+
 // ---- wave64 helpers ----------------------------------------------------------
 
 __device__ __forceinline__ double wave_min_d(double v)
