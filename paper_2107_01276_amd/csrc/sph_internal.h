@@ -5,9 +5,10 @@
 // a pair of particles at levels <= l is closer than one level-l cell when it
 // interacts.  All levels share one nested grid: a level-Q cell is a 2^Q x 2^Q
 // block of level-0 cells.  Particles are radix-sorted by the key
-// (level, Morton code of the level-0 cell), so the particles of any level
-// inside any cell of any resolution Q form one contiguous run of the sorted
-// order.  For every level l and every resolution Q >= l a dense table gives
+// (level, Hilbert index of the level-0 cell), so the particles of any
+// level inside any cell of any resolution Q form one contiguous run of the
+// sorted order (a Hilbert index, like a Morton code, keeps every aligned
+// 2^Q x 2^Q block contiguous).  For every level l and every resolution Q >= l a dense table gives
 // that run (start, end) per cell.  Particle i visits level l with search
 // radius 3 max(h_i, hmax_l) at resolution max(l, l_i): a 3x3 (or smaller)
 // block of cells per level, from whichever side of the pair is coarser.
@@ -36,7 +37,7 @@ struct Grid {
     int32_t nx0[2];     // level-0 cells per axis
     int32_t periodic[2];
     int32_t nlev;       // number of levels
-    int32_t bits;       // Morton bits per axis
+    int32_t bits;       // key bits per axis
     int32_t nxq[SPH_MAXL][2];   // cells per axis at resolution Q
     int64_t cumq[SPH_MAXL + 1]; // prefix of cells(Q)
     int64_t lbase[SPH_MAXL];    // table offset(l, Q) = lbase[l] + cumq[Q]
