@@ -47,6 +47,15 @@ class Params(C.Structure):
                 ("merge_iters", C.c_int32), ("shift_iters", C.c_int32), ("pref_mode", C.c_int32)]
 
 
+class Bc(C.Structure):
+    _fields_ = [("awx", C.c_double), ("awy", C.c_double)]
+
+
+class Io(C.Structure):
+    _fields_ = [("x_in", C.c_double), ("len_in", C.c_double), ("x_out", C.c_double),
+                ("len_out", C.c_double)]
+
+
 class BgParams(C.Structure):
     _fields_ = [("rho0", C.c_double), ("cr", C.c_double), ("ds_min", C.c_double),
                 ("ds_max", C.c_double), ("n_r", C.c_double), ("split_alpha", C.c_double),
@@ -72,7 +81,11 @@ def lib():
             "or_xnbr_cells_alloc": (I64, [P, I64, P, P, P, I64, P, P, P, P, P]),
             "or_free": (None, [P]),
             "or_pass_a": (None, [P, P, I64] + [P] * 13),
-            "or_pass_b": (None, [P, P, I64] + [P] * 12 + [D, P, P, P, P, P]),
+            "or_pass_b": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 7),
+            "or_boundary": (None, [P, P, P, I64] + [P] * 12),
+            "or_rates_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 9),
+            "or_step_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D, I64]),
+            "or_inout": (I64, [P, I64, I64] + [P] * 12),
             "or_rates": (C.c_int, [P, P, I64] + [P] * 7 + [D] + [P] * 9),
             "or_step": (C.c_int, [P, P, I64] + [P] * 7 + [D, I64, P]),
             "or_adapt": (I64, [P, P, I64, I64] + [P] * 13),
@@ -250,16 +263,98 @@ def pass_a(dom: Dom, prm: Prm, x, y, h, m, p, rp, col):
     return out
 
 
-def pass_b(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col):
+def pass_b(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col, ug=None, vg=None):
     x, y, u, v, p, h, m = map(_f64, (x, y, u, v, p, h, m))
+    ug = None if ug is None else _f64(ug)
+    vg = None if vg is None else _f64(vg)
     rp, col = _i64(rp), _i32(col)
     n = x.size
     out = {k: np.zeros(n) for k in ("dpdt", "dudt", "dvdt")}
     lib().or_pass_b(C.byref(dom.c()), C.byref(prm.c()), n, _p(x), _p(y), _p(u), _p(v), _p(p),
                     _p(h), _p(m), _p(_f64(a["rho"])), _p(_f64(a["beta"])), _p(_f64(a["pavg"])),
                     _p(_f64(a["dxs"])), _p(_f64(a["dys"])), float(dt), _p(rp), _p(col),
-                    _p(out["dpdt"]), _p(out["dudt"]), _p(out["dvdt"]))
+                    _p(ug), _p(vg), _p(out["dpdt"]), _p(out["dudt"]), _p(out["dvdt"]))
     return out
+
+
+FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
+
+
+def boundary(dom: Dom, prm: Prm, x, y, h, rho, kind, u, v, p, rp, col, aw=(0.0, 0.0)):
+    """Boundary pass of section 2.2 on copies of u, v, p.
+    Returns (u, v, p, ug, vg)."""
+    x, y, h, rho = map(_f64, (x, y, h, rho))
+    u, v, p = (_f64(a).copy() for a in (u, v, p))
+    kind, rp, col = _i32(kind), _i64(rp), _i32(col)
+    n = x.size
+    ug, vg = np.zeros(n), np.zeros(n)
+    bc = Bc(float(aw[0]), float(aw[1]))
+    lib().or_boundary(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n, _p(x), _p(y), _p(h),
+                      _p(rho), _p(kind), _p(rp), _p(col), _p(u), _p(v), _p(p), _p(ug), _p(vg))
+    return u, v, p, ug, vg
+
+
+def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0)):
+    """One evaluation with boundary particles (state needs 'kind' and 'rho',
+    the stored density).  Returns the fields plus the state's u, v, p after
+    the boundary pass."""
+    st = {k: _f64(state[k]).copy() for k in ("x", "y", "u", "v", "p", "h", "m", "rho")}
+    kind = _i32(state["kind"])
+    n = st["x"].size
+    out = {k: np.zeros(n) for k in ("rho", "beta", "nnb", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")}
+    bc = Bc(float(aw[0]), float(aw[1]))
+    rc = lib().or_rates_k(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
+                          *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
+                          _p(st["rho"]), float(dt),
+                          *[_p(out[k]) for k in ("rho", "beta", "nnb", "pavg", "dxs", "dys",
+                                                 "dpdt", "dudt", "dvdt")])
+    if rc != 0:
+        raise RuntimeError(f"oracle rates failed: {rc}")
+    out["u_bc"], out["v_bc"], out["p_bc"] = st["u"], st["v"], st["p"]
+    return out
+
+
+def step_k(dom: Dom, prm: Prm, state: dict, dt: float, nsteps: int, aw=(0.0, 0.0)):
+    """PEC steps with boundary particles on copies; state needs 'kind' and
+    'rho' (stored density, updated to the latest summation)."""
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "u", "v", "p", "h", "m", "rho")}
+    kind = _i32(state["kind"])
+    n = s["x"].size
+    bc = Bc(float(aw[0]), float(aw[1]))
+    rc = lib().or_step_k(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
+                         *[_p(s[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
+                         _p(s["rho"]), float(dt), int(nsteps))
+    if rc != 0:
+        raise RuntimeError(f"oracle step failed: {rc}")
+    s["kind"] = kind
+    return s
+
+
+_IO_F = ("x", "y", "u", "v", "p", "rho", "h", "mref")
+
+
+def inout(io: dict, state: dict, cap: int):
+    """Inlet/outlet update of section 2.2 on copies.  Returns (state, origin,
+    counts) or raises on capacity."""
+    n = state["x"].size
+    st = {}
+    for k in _IO_F:
+        a = np.zeros(max(cap, 1))
+        a[:n] = state[k]
+        st[k] = a
+    mq = np.zeros(max(cap, 1), np.int64); mq[:n] = state["mq"]
+    kind = np.zeros(max(cap, 1), np.int32); kind[:n] = state["kind"]
+    origin = np.zeros(max(cap, 1), np.int64)
+    counts = np.zeros(4, np.int64)
+    cio = Io(float(io["x_in"]), float(io["len_in"]), float(io["x_out"]), float(io["len_out"]))
+    nn = lib().or_inout(C.byref(cio), n, cap, *[_p(st[k]) for k in _IO_F], _p(mq), _p(kind),
+                        _p(origin), _p(counts))
+    if nn < 0:
+        raise RuntimeError(f"oracle inout failed: {nn}")
+    out = {k: st[k][:nn].copy() for k in _IO_F}
+    out["mq"], out["kind"] = mq[:nn].copy(), kind[:nn].copy()
+    return out, origin[:nn].copy(), {"appended": int(counts[0]), "deleted": int(counts[1]),
+                                     "to_fluid": int(counts[2]), "to_outlet": int(counts[3])}
 
 
 def rates(dom: Dom, prm: Prm, x, y, u, v, p, h, m, dt, method: str = "cells"):

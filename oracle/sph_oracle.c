@@ -567,14 +567,20 @@ void or_pass_a(const or_domain* d, const or_params* P, int64_t n, const double* 
 /* the sums scaled by 1/beta_i are dropped, so its rates stay finite.        */
 /* ------------------------------------------------------------------------ */
 
+/* ug, vg: the velocity used in the viscous term.  For fluid particles it is
+ * u, v; for wall particles it is the no-slip ghost velocity of eq. (bc-wall)
+ * (section 2.2).  NULL means ug = u, vg = v. */
 void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* x,
                const double* y, const double* u, const double* v, const double* p,
                const double* h, const double* m, const double* rho,
                const double* beta, const double* pavg, const double* dxs,
                const double* dys, double dt, const int64_t* rp, const int32_t* col,
+               const double* ug, const double* vg,
                double* dpdt, double* dudt, double* dvdt)
 {
     const double rho0 = P->rho0, cs = P->cs, nu = P->nu, ae = P->alpha_e;
+    if (!ug) ug = u;
+    if (!vg) vg = v;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         double Pi = beta[i] > 0.0 ? (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]) : 0.0;
@@ -612,8 +618,8 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
             gy += m[j] * (Pi * giy + Pj * gjy);
             /* viscous */
             double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
-            vx += cvis * uij;
-            vy += cvis * vij;
+            vx += cvis * (ug[i] - ug[j]);
+            vy += cvis * (vg[i] - vg[j]);
         }
         double b = beta[i];
         double edac = b > 0.0 ? (rho0 * cs * cs / b) * s_div + s_dif / b : 0.0;
@@ -623,23 +629,117 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
     }
 }
 
-/* One full rate evaluation: neighbours (cell list), pass A, pass B. */
+/* ------------------------------------------------------------------------ */
+/* Boundary particles, section 2.2.  Kinds: 0 fluid, 1 solid (dummy wall     */
+/* particles of Adami et al.), 2 inlet, 3 outlet.  For every non-fluid       */
+/* particle b the Shepard sums of eq. (shepard) run over its fluid           */
+/* neighbours f with W(r_bf, h_bf), h_bf = (h_b + h_f)/2:                    */
+/*   solid:  p_b by eq. (bc-pre) with g the body force and a_w the wall      */
+/*           acceleration; ghost velocity 2 u_b - u^_b (eq. bc-wall), used    */
+/*           in the viscous term; u_b (the prescribed wall velocity) stays   */
+/*           and is the one the pressure equation sees (no penetration);     */
+/*   inlet:  u_b prescribed; p_b = Shepard average of the fluid pressure;    */
+/*   outlet: u_b, v_b, p_b = Shepard averages of the fluid values.           */
+/* READING (the paper uses the characteristic variables of Lastiwka et al.   */
+/* at inlet and outlet): a zero-gradient Shepard extrapolation of p (and of  */
+/* u at the outlet) with the inlet velocity held at its prescribed value.    */
+/* READING: rho_f in eq. (bc-pre) is the stored density (the one from the    */
+/* latest summation).  A particle with no fluid neighbour keeps u, v, p and  */
+/* its ghost velocity is u; by the symmetry of N no fluid particle sees it.  */
+/* ------------------------------------------------------------------------ */
+
+enum { OR_FLUID = 0, OR_SOLID = 1, OR_INLET = 2, OR_OUTLET = 3 };
+
+typedef struct {
+    double awx, awy;  /* wall acceleration a_w of eq. (bc-pre) */
+} or_bc;
+
+void or_boundary(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+                 const double* x, const double* y, const double* h, const double* rho,
+                 const int32_t* kind, const int64_t* rp, const int32_t* col, double* u,
+                 double* v, double* p, double* ug, double* vg)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        ug[i] = u[i];
+        vg[i] = v[i];
+    }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < n; ++b) {
+        if (kind[b] == OR_FLUID) continue;
+        double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
+        for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+            int64_t f = col[k];
+            if (kind[f] != OR_FLUID) continue;
+            double dx = mi_axis(d, 0, x[b] - x[f]);
+            double dy = mi_axis(d, 1, y[b] - y[f]);
+            double r = sqrt(dx * dx + dy * dy);
+            double w = or_w(r, 0.5 * (h[b] + h[f]));
+            S += w;
+            su += u[f] * w;
+            sv += v[f] * w;
+            sp += p[f] * w;
+            srx += rho[f] * dx * w;
+            sry += rho[f] * dy * w;
+        }
+        if (!(S > 0.0)) continue;
+        if (kind[b] == OR_SOLID) {
+            p[b] = (sp + ((P->fx - B->awx) * srx + (P->fy - B->awy) * sry)) / S;
+            ug[b] = 2.0 * u[b] - su / S;
+            vg[b] = 2.0 * v[b] - sv / S;
+        } else if (kind[b] == OR_INLET) {
+            p[b] = sp / S;
+        } else {
+            u[b] = su / S;
+            v[b] = sv / S;
+            p[b] = sp / S;
+            ug[b] = u[b];
+            vg[b] = v[b];
+        }
+    }
+}
+
+/* One full rate evaluation: neighbours (cell list), the boundary pass when
+ * kind is given (it overwrites p, and u, v of outlet particles, in place;
+ * rho_in is the stored density it uses), pass A, pass B. */
+int or_rates_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+               const double* x, const double* y, double* u, double* v, double* p,
+               const double* h, const double* m, const int32_t* kind, const double* rho_in,
+               double dt, double* rho, double* beta, double* nnb, double* pavg, double* dxs,
+               double* dys, double* dpdt, double* dudt, double* dvdt)
+{
+    int64_t* rp = NULL;
+    int32_t* col = NULL;
+    int64_t nnz = or_nbr_cells_alloc(d, n, x, y, h, &rp, &col);
+    if (nnz < 0) return (int)nnz;
+    double *ug = NULL, *vg = NULL;
+    if (kind) {
+        size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+        ug = malloc(sz);
+        vg = malloc(sz);
+        if (!ug || !vg) {
+            free(ug); free(vg); free(rp); free(col);
+            return OR_E_NOMEM;
+        }
+        or_boundary(d, P, B, n, x, y, h, rho_in, kind, rp, col, u, v, p, ug, vg);
+    }
+    or_pass_a(d, P, n, x, y, h, m, p, rp, col, rho, beta, nnb, pavg, dxs, dys);
+    or_pass_b(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug, vg,
+              dpdt, dudt, dvdt);
+    free(ug);
+    free(vg);
+    free(rp);
+    free(col);
+    return OR_OK;
+}
+
 int or_rates(const or_domain* d, const or_params* P, int64_t n, const double* x,
              const double* y, const double* u, const double* v, const double* p,
              const double* h, const double* m, double dt, double* rho, double* beta,
              double* nnb, double* pavg, double* dxs, double* dys, double* dpdt,
              double* dudt, double* dvdt)
 {
-    int64_t* rp = NULL;
-    int32_t* col = NULL;
-    int64_t nnz = or_nbr_cells_alloc(d, n, x, y, h, &rp, &col);
-    if (nnz < 0) return (int)nnz;
-    or_pass_a(d, P, n, x, y, h, m, p, rp, col, rho, beta, nnb, pavg, dxs, dys);
-    or_pass_b(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col,
-              dpdt, dudt, dvdt);
-    free(rp);
-    free(col);
-    return OR_OK;
+    return or_rates_k(d, P, NULL, n, x, y, (double*)u, (double*)v, (double*)p, h, m, NULL, NULL,
+                      dt, rho, beta, nnb, pavg, dxs, dys, dpdt, dudt, dvdt);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -647,21 +747,42 @@ int or_rates(const or_domain* d, const or_params* P, int64_t n, const double* x,
 /* the transport velocity u~ = u + dr/dt of eq. (shift-tvf).  Neighbours are */
 /* rebuilt before each of the two evaluations per step.  Positions on        */
 /* periodic axes are wrapped into [lo, hi).                                  */
+/* With kinds: fluid particles are integrated as above; solid particles stay */
+/* in place; inlet and outlet particles move with their own velocity (no     */
+/* shifting), the half step with u^n, the full step with the velocity of the */
+/* half-step boundary pass.  Every non-fluid particle keeps the half-step    */
+/* boundary values of u, v, p at the end of the step.  rho carries the       */
+/* stored density in and the latest summation density out.                 */
 /* ------------------------------------------------------------------------ */
 
-int or_step(const or_domain* d, const or_params* P, int64_t n, double* x, double* y,
-            double* u, double* v, double* p, double* h, const double* m, double dt,
-            int64_t nsteps, double* rho_out)
+int or_step_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n, double* x,
+              double* y, double* u, double* v, double* p, double* h, const double* m,
+              const int32_t* kind, double* rho, double dt, int64_t nsteps)
 {
     size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
-    double *rho = malloc(sz), *beta = malloc(sz), *nnb = malloc(sz), *pavg = malloc(sz);
+    double *rn = malloc(sz), *beta = malloc(sz), *nnb = malloc(sz), *pavg = malloc(sz);
     double *dxs = malloc(sz), *dys = malloc(sz), *ap = malloc(sz), *au = malloc(sz), *av = malloc(sz);
     double *xh = malloc(sz), *yh = malloc(sz), *uh = malloc(sz), *vh = malloc(sz), *ph = malloc(sz);
     int rc = OR_OK;
+    if (!rn || !beta || !nnb || !pavg || !dxs || !dys || !ap || !au || !av || !xh || !yh || !uh ||
+        !vh || !ph)
+        rc = OR_E_NOMEM;
     for (int64_t s = 0; s < nsteps && rc == OR_OK; ++s) {
-        rc = or_rates(d, P, n, x, y, u, v, p, h, m, dt, rho, beta, nnb, pavg, dxs, dys, ap, au, av);
+        rc = or_rates_k(d, P, B, n, x, y, u, v, p, h, m, kind, rho, dt, rn, beta, nnb, pavg, dxs,
+                        dys, ap, au, av);
         if (rc) break;
+        memcpy(rho, rn, sz);
         for (int64_t i = 0; i < n; ++i) {
+            int k = kind ? kind[i] : OR_FLUID;
+            if (k != OR_FLUID) {
+                double adv = (k == OR_INLET || k == OR_OUTLET) ? 1.0 : 0.0;
+                xh[i] = adv > 0.0 ? wrap_axis(d, 0, x[i] + 0.5 * dt * u[i]) : x[i];
+                yh[i] = adv > 0.0 ? wrap_axis(d, 1, y[i] + 0.5 * dt * v[i]) : y[i];
+                uh[i] = u[i];
+                vh[i] = v[i];
+                ph[i] = p[i];
+                continue;
+            }
             uh[i] = u[i] + 0.5 * dt * au[i];
             vh[i] = v[i] + 0.5 * dt * av[i];
             double tu = uh[i] + dxs[i] / dt;
@@ -670,9 +791,22 @@ int or_step(const or_domain* d, const or_params* P, int64_t n, double* x, double
             yh[i] = wrap_axis(d, 1, y[i] + 0.5 * dt * tv);
             ph[i] = p[i] + 0.5 * dt * ap[i];
         }
-        rc = or_rates(d, P, n, xh, yh, uh, vh, ph, h, m, dt, rho, beta, nnb, pavg, dxs, dys, ap, au, av);
+        rc = or_rates_k(d, P, B, n, xh, yh, uh, vh, ph, h, m, kind, rho, dt, rn, beta, nnb, pavg,
+                        dxs, dys, ap, au, av);
         if (rc) break;
+        memcpy(rho, rn, sz);
         for (int64_t i = 0; i < n; ++i) {
+            int k = kind ? kind[i] : OR_FLUID;
+            if (k != OR_FLUID) {
+                if (k == OR_INLET || k == OR_OUTLET) {
+                    x[i] = wrap_axis(d, 0, x[i] + dt * uh[i]);
+                    y[i] = wrap_axis(d, 1, y[i] + dt * vh[i]);
+                }
+                u[i] = uh[i];
+                v[i] = vh[i];
+                p[i] = ph[i];
+                continue;
+            }
             double un = u[i] + dt * au[i];
             double vn = v[i] + dt * av[i];
             double tu = un + dxs[i] / dt;
@@ -684,10 +818,91 @@ int or_step(const or_domain* d, const or_params* P, int64_t n, double* x, double
             p[i] = p[i] + dt * ap[i];
         }
     }
-    if (rho_out) memcpy(rho_out, rho, sz);
-    free(rho); free(beta); free(nnb); free(pavg); free(dxs); free(dys); free(ap); free(au); free(av);
+    free(rn); free(beta); free(nnb); free(pavg); free(dxs); free(dys); free(ap); free(au); free(av);
     free(xh); free(yh); free(uh); free(vh); free(ph);
     return rc;
+}
+
+int or_step(const or_domain* d, const or_params* P, int64_t n, double* x, double* y,
+            double* u, double* v, double* p, double* h, const double* m, double dt,
+            int64_t nsteps, double* rho_out)
+{
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double* rho = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!rho) return OR_E_NOMEM;
+    int rc = or_step_k(d, P, NULL, n, x, y, u, v, p, h, m, NULL, rho, dt, nsteps);
+    if (rho_out && rc == OR_OK) memcpy(rho_out, rho, sz);
+    free(rho);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inlet and outlet (section 2.2): after a step, on the pre-update kinds,    */
+/*   an inlet particle at x >= x_in becomes fluid and a copy of it (same y,  */
+/*   h, mass, m_ref, u, v, p, rho) re-enters the inlet at x - len_in;        */
+/*   a fluid particle at x >= x_out becomes an outlet particle;              */
+/*   an outlet particle at x >= x_out + len_out is deleted.                  */
+/* Deleted slots are removed by stable compaction and the inlet copies are   */
+/* appended in ascending order of their source slot.  origin[new] is the     */
+/* old slot (of the source, for a copy).  Returns the new count, or          */
+/* OR_E_CAPACITY (state unchanged) when the result exceeds cap; counts[0..3] */
+/* = appended, deleted, inlet->fluid, fluid->outlet.                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double x_in, len_in, x_out, len_out;
+} or_io;
+
+int64_t or_inout(const or_io* io, int64_t n, int64_t cap, double* x, double* y, double* u,
+                 double* v, double* p, double* rho, double* h, double* mref, int64_t* mq,
+                 int32_t* kind, int64_t* origin, int64_t* counts)
+{
+    int64_t na = 0, nd = 0, nf = 0, no = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] == OR_INLET && x[i] >= io->x_in) ++na;
+        if (kind[i] == OR_OUTLET && x[i] >= io->x_out + io->len_out) ++nd;
+    }
+    for (int k = 0; k < 4; ++k) counts[k] = 0;
+    if (n - nd + na > cap) return OR_E_CAPACITY;
+    size_t m = (size_t)(n > 0 ? n : 1);
+    int32_t* nk = malloc(m * sizeof(int32_t));
+    int64_t* src = malloc((size_t)(n + na > 0 ? n + na : 1) * sizeof(int64_t));
+    if (!nk || !src) { free(nk); free(src); return OR_E_NOMEM; }
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        nk[i] = kind[i];
+        if (kind[i] == OR_INLET && x[i] >= io->x_in) { nk[i] = OR_FLUID; ++nf; }
+        else if (kind[i] == OR_FLUID && x[i] >= io->x_out) { nk[i] = OR_OUTLET; ++no; }
+        if (kind[i] == OR_OUTLET && x[i] >= io->x_out + io->len_out) continue;
+        src[t++] = i;
+    }
+    int64_t nkeep = t;
+    for (int64_t i = 0; i < n; ++i)
+        if (kind[i] == OR_INLET && x[i] >= io->x_in) src[t++] = i;
+    /* gather every array into the new order through a temporary */
+    double* arrs[] = {x, y, u, v, p, rho, h, mref};
+    double* tmpd = malloc((size_t)(t > 0 ? t : 1) * sizeof(double));
+    int64_t* tmpq = malloc((size_t)(t > 0 ? t : 1) * sizeof(int64_t));
+    int32_t* tmpk = malloc((size_t)(t > 0 ? t : 1) * sizeof(int32_t));
+    if (!tmpd || !tmpq || !tmpk) {
+        free(nk); free(src); free(tmpd); free(tmpq); free(tmpk);
+        return OR_E_NOMEM;
+    }
+    for (int a = 0; a < 8; ++a) {
+        double* A = arrs[a];
+        for (int64_t k = 0; k < t; ++k) tmpd[k] = A[src[k]];
+        if (a == 0)
+            for (int64_t k = nkeep; k < t; ++k) tmpd[k] = A[src[k]] - io->len_in;
+        memcpy(A, tmpd, (size_t)t * sizeof(double));
+    }
+    for (int64_t k = 0; k < t; ++k) tmpq[k] = mq[src[k]];
+    memcpy(mq, tmpq, (size_t)t * sizeof(int64_t));
+    for (int64_t k = 0; k < t; ++k) tmpk[k] = k < nkeep ? nk[src[k]] : OR_INLET;
+    memcpy(kind, tmpk, (size_t)t * sizeof(int32_t));
+    for (int64_t k = 0; k < t; ++k) origin[k] = src[k];
+    counts[0] = na; counts[1] = nd; counts[2] = nf; counts[3] = no;
+    free(nk); free(src); free(tmpd); free(tmpq); free(tmpk);
+    return t;
 }
 
 /* Time step of eq. (timestep): min(0.25 h_min/(U + c_s), 0.125 h_min^2/nu). */

@@ -1,0 +1,277 @@
+"""Pins of the oracle's boundary particles (section 2.2): the Adami wall
+pressure of eq. (bc-pre), the ghost velocity of eq. (bc-wall) with the
+Shepard average of eq. (shepard), the inlet/outlet extrapolation, the
+kind-aware PEC step and the inlet/outlet update.
+
+The wall pressure is pinned by an identity: for a hydrostatic field
+p = p0 + rho0 g . r and uniform fluid density, eq. (bc-pre) returns the
+field's value at the wall particle exactly, whatever the particle
+arrangement, because the Shepard averages of p_f and of rho_f (r_w - r_f)
+carry the same weights.  A wrong sign of r_wf, a missing rho_f or a
+dropped (g - a_w) term breaks it.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def _dom(orc, d):
+    return orc.Dom(d.lo, d.hi, d.periodic)
+
+
+def _prm(orc, **kw):
+    return orc.Prm(**kw)
+
+
+def _rows(orc, dom, s):
+    return orc.neighbors(dom, s["x"], s["y"], s["h"])
+
+
+def test_wall_pressure_hydrostatic_identity(orc):
+    s = W.wall_box(nx=20, ny=20, layers=3, jitter=0.1)
+    dom = _dom(orc, s["domain"])
+    G = 2.5
+    prm = _prm(orc, fy=-G)
+    p0 = 3.0
+    p = p0 - 1.0 * G * s["y"]             # grad p = rho0 g, g = (0, -G)
+    p_f = np.where(s["kind"] == W.FLUID, p, 0.0)
+    rp, col = _rows(orc, dom, s)
+    u, v, pw, ug, vg = orc.boundary(dom, prm, s["x"], s["y"], s["h"], s["rho"], s["kind"],
+                                    s["u"], s["v"], p_f, rp, col)
+    wall = s["kind"] == W.SOLID
+    # which walls see fluid: the first layers
+    sees = np.array([any(s["kind"][c] == W.FLUID for c in col[rp[i]:rp[i + 1]]) for i in range(s["x"].size)])
+    sel = wall & sees
+    assert sel.sum() >= 40
+    np.testing.assert_allclose(pw[sel], p[sel], rtol=0, atol=1e-12 * p0)
+    # fluid untouched; walls without fluid neighbours keep their value
+    fl = s["kind"] == W.FLUID
+    assert np.array_equal(pw[fl], p_f[fl])
+    assert np.array_equal(pw[wall & ~sees], p_f[wall & ~sees])
+    # a wall accelerating with g removes the hydrostatic correction: p_w is
+    # then the plain Shepard average, which differs from the field value
+    _, _, pw2, _, _ = orc.boundary(dom, prm, s["x"], s["y"], s["h"], s["rho"], s["kind"],
+                                   s["u"], s["v"], p_f, rp, col, aw=(0.0, -G))
+    assert np.max(np.abs(pw2[sel] - p[sel])) > 1e-3
+    # ... and at the level of the first wall layer it is above the wall value
+    # for the bottom wall (fluid above is at lower pressure)
+    bottom = sel & (s["y"] < 0)
+    assert np.all(pw2[bottom] < p[bottom])
+
+
+def test_wall_ghost_velocity(orc):
+    s = W.wall_box(nx=16, ny=12, layers=3, jitter=0.1, seed=7)
+    dom = _dom(orc, s["domain"])
+    prm = _prm(orc)
+    n = s["x"].size
+    U, V = 0.7, -0.2
+    fl = s["kind"] == W.FLUID
+    u = np.where(fl, U, 0.0)
+    v = np.where(fl, V, 0.0)
+    # top wall slides at (1, 0), bottom wall at rest
+    top = (~fl) & (s["y"] > 0.5)
+    u[top] = 1.0
+    rp, col = _rows(orc, dom, s)
+    u2, v2, p2, ug, vg = orc.boundary(dom, prm, s["x"], s["y"], s["h"], s["rho"], s["kind"],
+                                      u, v, s["p"], rp, col)
+    sees = np.array([any(fl[c] for c in col[rp[i]:rp[i + 1]]) for i in range(n)])
+    w = (~fl) & sees
+    # uniform fluid velocity: Shepard average is exact, ghost = 2 u_w - U
+    np.testing.assert_allclose(ug[w], 2 * u[w] - U, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(vg[w], 2 * v[w] - V, rtol=0, atol=1e-14)
+    assert np.array_equal(ug[fl], u[fl]) and np.array_equal(vg[fl], v[fl])
+    # the wall's own velocity (seen by the pressure equation) is unchanged
+    assert np.array_equal(u2, u) and np.array_equal(v2, v)
+    assert np.array_equal(ug[(~fl) & ~sees], u[(~fl) & ~sees])
+
+
+def test_inlet_outlet_extrapolation(orc):
+    s = W.inout_strip(nx=12, ny=8, n_in=6, n_out=6, jitter=0.1)
+    dom = _dom(orc, s["domain"])
+    prm = _prm(orc)
+    n = s["x"].size
+    k = s["kind"]
+    u = np.where(k == W.FLUID, 0.8, s["u"])
+    v = np.where(k == W.FLUID, 0.1, 0.0)
+    p = np.where(k == W.FLUID, 2.0, -1.0)
+    rp, col = _rows(orc, dom, s)
+    u2, v2, p2, ug, vg = orc.boundary(dom, prm, s["x"], s["y"], s["h"], s["rho"], k, u, v, p,
+                                      rp, col)
+    sees = np.array([any(k[c] == W.FLUID for c in col[rp[i]:rp[i + 1]]) for i in range(n)])
+    inl = (k == W.INLET) & sees
+    out = (k == W.OUTLET) & sees
+    assert inl.sum() > 0 and out.sum() > 0
+    # uniform fluid values are reproduced exactly by the Shepard average
+    np.testing.assert_allclose(p2[inl], 2.0, atol=1e-14)
+    assert np.array_equal(u2[inl], u[inl])              # prescribed inlet velocity kept
+    np.testing.assert_allclose(u2[out], 0.8, atol=1e-14)
+    np.testing.assert_allclose(v2[out], 0.1, atol=1e-14)
+    np.testing.assert_allclose(p2[out], 2.0, atol=1e-14)
+    np.testing.assert_allclose(ug[out], 0.8, atol=1e-14)
+    far = (k != W.FLUID) & ~sees
+    assert far.sum() > 0
+    assert np.array_equal(p2[far], p[far]) and np.array_equal(u2[far], u[far])
+
+
+def test_rates_k_moving_wall_with_fluid_equals_plain(orc):
+    # walls moving with a uniform fluid and zero pressure: the boundary pass
+    # changes nothing and the ghost velocity equals u, so the evaluation with
+    # kinds is the plain evaluation, bit for bit
+    s = W.wall_box(nx=16, ny=12, layers=3, jitter=0.1, seed=8)
+    dom = _dom(orc, s["domain"])
+    prm = _prm(orc)
+    st = dict(s)
+    st["u"] = np.full(s["x"].size, 0.5)
+    a = orc.rates_k(dom, prm, st, 1e-3)
+    b = orc.rates(dom, prm, st["x"], st["y"], st["u"], st["v"], st["p"], st["h"], st["m"], 1e-3)
+    for key in ("rho", "dpdt", "dudt", "dvdt", "dxs", "dys"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_rates_k_stationary_wall_drag(orc):
+    s = W.wall_box(nx=16, ny=12, layers=3, jitter=0.0, seed=9)
+    dom = _dom(orc, s["domain"])
+    prm = _prm(orc, nu=0.01)
+    st = dict(s)
+    fl = s["kind"] == W.FLUID
+    st["u"] = np.where(fl, 1.0, 0.0)
+    a = orc.rates_k(dom, prm, st, 1e-3)
+    dx = s["dx"]
+    near_bot = fl & (s["y"] < 1.5 * dx)
+    near_top = fl & (s["y"] > s["H"] - 1.5 * dx)
+    mid = fl & (np.abs(s["y"] - 0.5 * s["H"]) < 2 * dx)
+    # no-slip walls decelerate the adjacent layers, symmetrically; the bulk
+    # of a uniform flow is not decelerated
+    assert np.all(a["dudt"][near_bot] < -0.1)
+    np.testing.assert_allclose(np.sort(a["dudt"][near_bot]), np.sort(a["dudt"][near_top]),
+                               rtol=1e-9)
+    assert np.max(np.abs(a["dudt"][mid])) < 1e-9
+    # the ghost velocity doubles the wall-side velocity jump: the drag on the
+    # first layer is larger than with the wall's own (zero) velocity
+    b = orc.rates(dom, prm, st["x"], st["y"], st["u"], st["v"], st["p"], st["h"], st["m"], 1e-3)
+    assert np.all(a["dudt"][near_bot] < b["dudt"][near_bot] - 0.05)
+
+
+def test_step_k_all_fluid_equals_plain_step(orc):
+    s = W.tgv(nx=12, seed=3)
+    dom = orc.Dom()
+    prm = orc.Prm(nu=0.01)
+    st = dict(s)
+    st["kind"] = np.zeros(s["x"].size, np.int32)
+    st["rho"] = np.ones(s["x"].size)
+    a = orc.step_k(dom, prm, st, 1e-3, 3)
+    b = orc.step(dom, prm, s, 1e-3, 3)
+    for key in ("x", "y", "u", "v", "p", "rho"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_step_k_solids_fixed_inlet_advected(orc):
+    s = W.inout_strip(nx=10, ny=6, n_in=3, n_out=3, jitter=0.0)
+    dom = _dom(orc, s["domain"])
+    prm = orc.Prm(nu=0.01)
+    st = dict(s)
+    st["kind"] = s["kind"].copy()
+    # one column of the fluid made solid (a fixed obstacle row)
+    obst = (s["kind"] == W.FLUID) & (np.abs(s["x"] - 0.55) < 0.05)
+    st["kind"][obst] = W.SOLID
+    st["u"] = np.where(obst, 0.0, s["u"])
+    dt, ns = 1e-3, 4
+    out = orc.step_k(dom, prm, st, dt, ns)
+    assert np.array_equal(out["x"][obst], s["x"][obst])
+    assert np.array_equal(out["y"][obst], s["y"][obst])
+    inl = st["kind"] == W.INLET
+    xe = s["x"][inl].copy()
+    for _ in range(ns):
+        xe = xe + dt * 1.0
+    assert np.array_equal(out["x"][inl], xe)
+    assert np.array_equal(out["u"][inl], s["u"][inl])
+
+
+def _inout_python(io, st):
+    """The inlet/outlet rules written out with Python lists."""
+    n = st["x"].size
+    keep, copies, kinds = [], [], []
+    for i in range(n):
+        k = int(st["kind"][i])
+        x = st["x"][i]
+        nk = k
+        if k == W.INLET and x >= io["x_in"]:
+            nk = W.FLUID
+            copies.append(i)
+        elif k == W.FLUID and x >= io["x_out"]:
+            nk = W.OUTLET
+        if k == W.OUTLET and x >= io["x_out"] + io["len_out"]:
+            continue
+        keep.append(i)
+        kinds.append(nk)
+    origin = keep + copies
+    kinds += [W.INLET] * len(copies)
+    x = [st["x"][i] for i in keep] + [st["x"][i] - io["len_in"] for i in copies]
+    return np.array(origin), np.array(kinds, np.int32), np.array(x)
+
+
+def test_inout_rules_and_mass(orc):
+    s = W.inout_strip(nx=10, ny=6, n_in=3, n_out=3, jitter=0.3, seed=11)
+    rng = np.random.default_rng(12)
+    st = {k: s[k].copy() for k in ("x", "y", "u", "v", "p", "rho", "h", "mref", "mq", "kind")}
+    # push particles across every threshold
+    st["x"] = st["x"] + rng.uniform(0.0, 0.6 * s["dx"] * 3, st["x"].size)
+    io = s["io"]
+    out, origin, cnt = orc.inout(io, st, cap=2 * st["x"].size)
+    eo, ek, ex = _inout_python(io, st)
+    assert np.array_equal(origin, eo)
+    assert np.array_equal(out["kind"], ek)
+    assert np.array_equal(out["x"], ex)
+    for key in ("y", "u", "v", "p", "rho", "h", "mref", "mq"):
+        assert np.array_equal(out[key], st[key][eo]), key
+    assert cnt["appended"] > 0 and cnt["deleted"] > 0 and cnt["to_outlet"] > 0
+    assert cnt["to_fluid"] == cnt["appended"]
+    # mass ledger: exactly the copies' mass added and the deleted mass removed
+    deleted = (st["kind"] == W.OUTLET) & (st["x"] >= io["x_out"] + io["len_out"])
+    added = (st["kind"] == W.INLET) & (st["x"] >= io["x_in"])
+    assert out["mq"].sum() == st["mq"].sum() + st["mq"][added].sum() - st["mq"][deleted].sum()
+
+
+def test_inout_capacity(orc):
+    s = W.inout_strip(nx=10, ny=6, n_in=3, n_out=3)
+    st = {k: s[k].copy() for k in ("x", "y", "u", "v", "p", "rho", "h", "mref", "mq", "kind")}
+    inl = st["kind"] == W.INLET
+    st["x"][inl] = st["x"][inl] + 1.5 * s["dx"]
+    n = st["x"].size
+    with pytest.raises(RuntimeError):
+        orc.inout(s["io"], st, cap=n)
+    out, origin, cnt = orc.inout(s["io"], st, cap=n + 100)
+    assert out["x"].size == n + cnt["appended"] - cnt["deleted"]
+
+
+def _couette_series(y, t, H, U, nu, N=400):
+    """Start-up of plane Couette flow (bottom wall at rest, top wall at U
+    from t = 0): u = U y/H + sum_n 2U(-1)^n/(n pi) sin(n pi y/H) e^(-n^2 pi^2 nu t/H^2)."""
+    u = U * y / H
+    for n in range(1, N):
+        u = u + 2 * U / (n * np.pi) * (-1) ** n * np.sin(n * np.pi * y / H) * np.exp(
+            -n * n * np.pi ** 2 * nu * t / H ** 2)
+    return u
+
+
+def test_couette_startup_series(orc):
+    # no-slip walls (ghost velocity) + the viscous term of eq. (mom-sph):
+    # the start-up flow follows the series solution and settles on the
+    # linear profile; the walls sit half a spacing outside the fluid rows
+    s = W.wall_box(nx=10, ny=10, layers=4, jitter=0.0, hdx=1.2)
+    dom = _dom(orc, s["domain"])
+    U, nu = 1.0, 0.5
+    prm = orc.Prm(nu=nu, cs=10.0)
+    st = dict(s)
+    st["u"] = np.where((s["kind"] == W.SOLID) & (s["y"] > 0.5), U, 0.0)
+    dt = orc.lib().or_timestep(1.2 * s["dx"], U, 10.0, nu)
+    st = orc.step_k(dom, prm, st, dt, 100)
+    fl = st["kind"] == W.FLUID
+    T = 100 * dt
+    err = np.abs(st["u"][fl] - _couette_series(st["y"][fl], T, s["H"], U, nu))
+    assert err.max() < 0.01
+    st = orc.step_k(dom, prm, st, dt, 500)
+    err = np.abs(st["u"][fl] - U * st["y"][fl] / s["H"])
+    assert err.max() < 0.003
+    assert np.abs(st["v"][fl]).max() < 1e-3

@@ -280,6 +280,65 @@ def channel_background(spec: ChannelSpec | None = None, seed: int = 3, sparsity:
             "mq": quantize_mass(m, q), "mass_q": q, "mref": m}
 
 
+FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
+
+
+def wall_box(nx: int = 20, ny: int = 20, layers: int = 3, jitter: float = 0.0, seed: int = 5,
+             hdx: float = 1.2, rho0: float = 1.0, top: bool = True):
+    """Fluid on [0, 1) x [0, ny/nx) (periodic in x, open in y) between
+    `layers` rows of wall particles below (and above when `top`), all on one
+    lattice of spacing 1/nx; fluid positions jittered by U(-j, j) dx."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / nx
+    H = ny * dx
+    j_lo = -layers
+    j_hi = ny + (layers if top else 0)
+    i, j = np.meshgrid(np.arange(nx), np.arange(j_lo, j_hi), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    x = (i + 0.5) * dx
+    y = (j + 0.5) * dx
+    kind = np.where((j < 0) | (j >= ny), SOLID, FLUID).astype(np.int32)
+    fl = kind == FLUID
+    if jitter > 0:
+        x[fl] = np.mod(x[fl] + rng.uniform(-jitter, jitter, fl.sum()) * dx, 1.0)
+        y[fl] = y[fl] + rng.uniform(-jitter, jitter, fl.sum()) * dx
+    n = x.size
+    m = np.full(n, rho0 * dx * dx)
+    q = mass_quantum(1.05 * m.max() * 1.5)
+    dom = Domain((0.0, -(layers + 1) * dx), (1.0, H + (layers + 1) * dx), (True, False))
+    return {"x": x, "y": y, "u": np.zeros(n), "v": np.zeros(n), "p": np.zeros(n),
+            "rho": np.full(n, rho0), "h": np.full(n, hdx * dx), "m": m,
+            "mq": quantize_mass(m, q), "mass_q": q, "mref": m.copy(), "kind": kind,
+            "domain": dom, "dx": dx, "H": H}
+
+
+def inout_strip(nx: int = 30, ny: int = 10, n_in: int = 4, n_out: int = 4, U: float = 1.0,
+                seed: int = 6, jitter: float = 0.0, hdx: float = 1.2, rho0: float = 1.0):
+    """A channel strip periodic in y: inlet particles on x in [-n_in dx, 0),
+    fluid on [0, L), outlet particles on [L, L + n_out dx), L = nx dx,
+    dx = 1/ny; uniform velocity (U, 0)."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / ny
+    i, j = np.meshgrid(np.arange(-n_in, nx + n_out), np.arange(ny), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    x = (i + 0.5) * dx
+    y = (j + 0.5) * dx
+    if jitter > 0:
+        x = x + rng.uniform(-jitter, jitter, x.size) * dx
+        y = np.mod(y + rng.uniform(-jitter, jitter, y.size) * dx, 1.0)
+    L = nx * dx
+    kind = np.where(x < 0.0, INLET, np.where(x >= L, OUTLET, FLUID)).astype(np.int32)
+    n = x.size
+    m = np.full(n, rho0 * dx * dx)
+    q = mass_quantum(1.05 * m.max() * 1.5)
+    dom = Domain((-(n_in + 2) * dx, 0.0), (L + (n_out + 2) * dx, 1.0), (False, True))
+    io = {"x_in": 0.0, "len_in": n_in * dx, "x_out": L, "len_out": n_out * dx}
+    return {"x": x, "y": y, "u": np.full(n, U), "v": np.zeros(n), "p": np.zeros(n),
+            "rho": np.full(n, rho0), "h": np.full(n, hdx * dx), "m": m,
+            "mq": quantize_mass(m, q), "mass_q": q, "mref": m.copy(), "kind": kind,
+            "domain": dom, "dx": dx, "io": io}
+
+
 def background_lattice(domain: Domain, ds_max: float, hdx: float, rho0: float,
                        seed: int = 0, jitter: float = 0.0):
     """Background particles at the coarsest size ds_max (section 3.3)."""
