@@ -47,7 +47,10 @@ enum {
 };
 
 enum { SPH_FP64 = 0, SPH_FP32 = 1 };             /* pair arithmetic precision */
-enum { SPH_FLUID = 0, SPH_SOLID = 1 };           /* particle kinds */
+/* Particle kinds (section 2.2): fluid; solid = dummy wall particles of the
+ * Adami et al. wall treatment; inlet and outlet particles of an open
+ * channel. */
+enum { SPH_FLUID = 0, SPH_SOLID = 1, SPH_INLET = 2, SPH_OUTLET = 3 };
 
 /* Run configuration.  Physical constants follow section 2 of the paper:
  * rho0, c_s, nu, alpha_e (eq. edac-alpha), the kernel support 3h (eq.
@@ -72,6 +75,8 @@ typedef struct sph_config {
     double cr, ds_min, ds_max, n_r;
     int32_t bg_smooth_iters;
     double bg_mass_q;       /* background mass quantum */
+    double wall_accel[2];   /* a_w of eq. (bc-pre): acceleration of the solid
+                               particles (0 for a stationary body) */
 } sph_config;
 
 /* Caller-owned particle set (device pointers, see conventions). kind may be
@@ -108,6 +113,22 @@ typedef struct sph_adapt_map {
     int64_t n_required; /* size needed by the split (capacity check) */
     int64_t n_merged[8];/* merged pairs per merge iteration */
 } sph_adapt_map;
+
+/* Open-boundary zones of section 2.2 along x: inlet particles occupy
+ * [x_in - len_in, x_in), outlet particles [x_out, x_out + len_out). */
+typedef struct sph_inout_params {
+    double x_in, len_in, x_out, len_out;
+} sph_inout_params;
+
+/* Result of sph_inout.  origin is a device array of length >= capacity;
+ * the counters are written on the host. */
+typedef struct sph_inout_map {
+    int64_t *origin;      /* new slot -> old slot (the source, for an inlet copy) */
+    int64_t n_appended;   /* inlet copies appended (= inlet -> fluid) */
+    int64_t n_deleted;    /* outlet particles removed */
+    int64_t n_to_outlet;  /* fluid -> outlet */
+    int64_t n_required;   /* size the update needs (capacity check) */
+} sph_inout_map;
 
 /* Background particles of section 3.3 (device arrays, caller-owned). */
 typedef struct sph_background {
@@ -156,13 +177,27 @@ int sph_build_neighbors(sph_ctx *ctx, const sph_particles *ps, sph_csr *out);
  * pressure (eq. pavg), limited shifting (eqs. shift-deltar, shift-limit);
  * pass B = EDAC pressure rate (eq. edac:sph) and momentum (eq. mom-sph).
  * Pair arithmetic in the configured precision.  dt enters through the
- * transport-velocity term (eq. shift-tvf). */
+ * transport-velocity term (eq. shift-tvf).
+ * When ps->kind is non-NULL, a boundary pass (section 2.2) runs first: over
+ * its fluid neighbours, with the Shepard weights W(r, (h_b + h_f)/2) of eq.
+ * (shepard), every solid particle gets p by eq. (bc-pre) (g = body_force,
+ * a_w = wall_accel, rho_f = ps->rho, the stored density) and the no-slip
+ * ghost velocity 2 u_b - u^ of eq. (bc-wall), which the viscous term uses
+ * (the solid's own u, its prescribed velocity, is what the pressure
+ * equation sees); inlet particles get the Shepard average of p; outlet
+ * particles get the Shepard averages of u, v and p.  These values are
+ * written into ps->p (and ps->u, ps->v of outlet particles).  A boundary
+ * particle with no fluid neighbour keeps its values. */
 int sph_rates(sph_ctx *ctx, const sph_particles *ps, double dt, sph_rates_out *out);
 
 /* nsteps predict-evaluate-correct steps (eqs. int-pre, int-cor) of size dt,
  * neighbours rebuilt before each of the two evaluations per step.  Fluid
- * particles are integrated; solid particles stay in place.  Updates x, y,
- * u, v, p and rho (last summation density) in place. */
+ * particles are integrated; solid particles stay in place; inlet and outlet
+ * particles move with their own velocity (u^n for the half step, the
+ * half-step boundary value for the full step).  Every evaluation runs the
+ * boundary pass of sph_rates and stores its summation density in ps->rho,
+ * which the next boundary pass reads.  Updates x, y, u, v, p and rho in
+ * place; non-fluid particles end with their half-step boundary values. */
 int sph_step(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps);
 
 /* Fluid reference mass from the background (section 3.3 and the algorithm of
@@ -188,6 +223,17 @@ int sph_adapt(sph_ctx *ctx, sph_particles *ps, const sph_background *bg, sph_ada
  * *nsplit receives the number of splits.  Synchronises. */
 int sph_bg_update(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
                   const double *phi, double phi_thresh, int32_t passes, int64_t *nsplit);
+
+/* Inlet/outlet update (section 2.2), to be called after a step.  On the
+ * kinds before the call: an inlet particle with x >= x_in becomes fluid and
+ * a copy of it (every field, kind inlet) is appended at x - len_in; a fluid
+ * particle with x >= x_out becomes an outlet particle; an outlet particle
+ * with x >= x_out + len_out is deleted.  Deleted slots are removed by stable
+ * compaction; copies follow in ascending order of their source slot.
+ * Requires ps->kind.  Two-phase: SPH_E_CAPACITY with map->n_required set
+ * and the state untouched when the result exceeds ps->capacity.  Updates
+ * ps->n.  Synchronises. */
+int sph_inout(sph_ctx *ctx, sph_particles *ps, const sph_inout_params *io, sph_inout_map *map);
 
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);

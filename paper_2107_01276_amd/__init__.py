@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libsph.so")
 SPH_OK, SPH_E_INVAL, SPH_E_CAPACITY, SPH_E_NOMEM = 0, -1, -2, -3
 SPH_E_DEVICE, SPH_E_NONFINITE, SPH_E_AGAIN = -4, -5, -6
 SPH_FP64, SPH_FP32 = 0, 1
-SPH_FLUID, SPH_SOLID = 0, 1
+SPH_FLUID, SPH_SOLID, SPH_INLET, SPH_OUTLET = 0, 1, 2, 3
 _ERRNAME = {0: "SPH_OK", -1: "SPH_E_INVAL", -2: "SPH_E_CAPACITY", -3: "SPH_E_NOMEM",
             -4: "SPH_E_DEVICE", -5: "SPH_E_NONFINITE", -6: "SPH_E_AGAIN"}
 
@@ -46,7 +46,8 @@ class sph_config(C.Structure):
                 ("mmax_f", C.c_double), ("mmin_f", C.c_double), ("mass_q", C.c_double),
                 ("merge_iters", C.c_int32), ("shift_iters", C.c_int32),
                 ("cr", C.c_double), ("ds_min", C.c_double), ("ds_max", C.c_double),
-                ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double)]
+                ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double),
+                ("wall_accel", C.c_double * 2)]
 
 
 class sph_particles(C.Structure):
@@ -71,6 +72,16 @@ class sph_adapt_map(C.Structure):
                 ("n_required", C.c_int64), ("n_merged", C.c_int64 * 8)]
 
 
+class sph_inout_params(C.Structure):
+    _fields_ = [("x_in", C.c_double), ("len_in", C.c_double), ("x_out", C.c_double),
+                ("len_out", C.c_double)]
+
+
+class sph_inout_map(C.Structure):
+    _fields_ = [("origin", C.c_void_p), ("n_appended", C.c_int64), ("n_deleted", C.c_int64),
+                ("n_to_outlet", C.c_int64), ("n_required", C.c_int64)]
+
+
 class sph_background(C.Structure):
     _fields_ = [("n", C.c_int64), ("capacity", C.c_int64),
                 ("x", C.c_void_p), ("y", C.c_void_p), ("h", C.c_void_p), ("ds", C.c_void_p),
@@ -85,7 +96,7 @@ class sph_diag(C.Structure):
 
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
-           "sph_adapt", "sph_bg_update", "sph_diagnostics", "sph_profile_enable",
+           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_profile_enable",
            "sph_profile_read", "sph_profile_reset")
 
 _lib = None
@@ -113,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         "sph_mref_lookup": (C.c_int, [P, P, P]),
         "sph_adapt": (C.c_int, [P, P, P, P]),
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
+        "sph_inout": (C.c_int, [P, P, P, P]),
         "sph_diagnostics": (C.c_int, [P, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
@@ -158,6 +170,7 @@ class Config:
     n_r: float = 48.0
     bg_smooth_iters: int = 3
     bg_mass_q: float = 2.0 ** -60
+    wall_accel: tuple = (0.0, 0.0)
 
     def c(self) -> sph_config:
         s = sph_config()
@@ -166,6 +179,7 @@ class Config:
         s.lo[0], s.lo[1] = self.lo
         s.hi[0], s.hi[1] = self.hi
         s.body_force[0], s.body_force[1] = self.body_force
+        s.wall_accel[0], s.wall_accel[1] = self.wall_accel
         for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
                   "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
                   "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q"):
@@ -346,6 +360,24 @@ class Context:
         P.n = int(ps.n)
         info["origin"] = origin[:P.n]
         info["sat"] = sat[:P.n]
+        return info
+
+    def inout(self, P: Particles, io: dict):
+        """Inlet/outlet update (sph_inout); io has x_in, len_in, x_out, len_out."""
+        origin = torch.empty(P.capacity, dtype=torch.int64, device=self.device)
+        m = sph_inout_map(origin=_ptr(origin).value)
+        prm = sph_inout_params(float(io["x_in"]), float(io["len_in"]), float(io["x_out"]),
+                               float(io["len_out"]))
+        ps = P.c()
+        rc = self.lib.sph_inout(self._h, C.byref(ps), C.byref(prm), C.byref(m))
+        info = {"appended": int(m.n_appended), "deleted": int(m.n_deleted),
+                "to_outlet": int(m.n_to_outlet), "n_required": int(m.n_required)}
+        if rc == SPH_E_CAPACITY:
+            info["error"] = rc
+            return info
+        self._check(rc)
+        P.n = int(ps.n)
+        info["origin"] = origin[:P.n]
         return info
 
     def bg_update(self, bg: Background, solids: Particles, passes: int, phi=None,

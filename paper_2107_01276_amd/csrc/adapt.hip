@@ -787,3 +787,134 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
     bg->n = nb;
     return SPH_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Inlet / outlet update (section 2.2)
+// ---------------------------------------------------------------------------
+
+__global__ void k_io_zero(int32_t* cnt) { cnt[0] = 0; }
+
+__global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restrict__ x,
+                                                  const int32_t* __restrict__ kind,
+                                                  sph_inout_params io, int32_t* keep, int32_t* app,
+                                                  int32_t* n_out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = i < n ? kind[i] : -1;
+    const double xi = i < n ? x[i] : 0.0;
+    const uint64_t b = __ballot(k == SPH_FLUID && xi >= io.x_out);
+    if (__lane_id() == 0 && b) atomicAdd(n_out, (int32_t)__popcll(b));
+    if (i >= n) return;
+    keep[i] = !(k == SPH_OUTLET && xi >= io.x_out + io.len_out);
+    app[i] = k == SPH_INLET && xi >= io.x_in;
+}
+
+// Kept slot i goes to rank_keep[i] with its new kind; an inlet particle
+// that entered the fluid also leaves a copy at nkeep + rank_app[i], moved
+// back by the inlet length.
+__global__ __launch_bounds__(256) void k_io_apply(int n, FluidState s, FluidState d,
+                                                  const int32_t* __restrict__ keep,
+                                                  const int32_t* __restrict__ rk,
+                                                  const int32_t* __restrict__ app,
+                                                  const int32_t* __restrict__ ra, int nkeep,
+                                                  sph_inout_params io)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int k = s.kind[i];
+    const double xi = s.x[i];
+    auto put = [&](int t) {
+        d.x[t] = xi; d.y[t] = s.y[i]; d.u[t] = s.u[i]; d.v[t] = s.v[i]; d.p[t] = s.p[i];
+        d.rho[t] = s.rho[i]; d.h[t] = s.h[i]; d.mref[t] = s.mref[i]; d.mq[t] = s.mq[i];
+        d.origin[t] = i;
+    };
+    if (keep[i]) {
+        const int t = rk[i];
+        put(t);
+        int nk = k;
+        if (k == SPH_INLET && xi >= io.x_in) nk = SPH_FLUID;
+        else if (k == SPH_FLUID && xi >= io.x_out) nk = SPH_OUTLET;
+        d.kind[t] = nk;
+    }
+    if (app[i]) {
+        const int t = nkeep + ra[i];
+        put(t);
+        d.x[t] = xi - io.len_in;
+        d.kind[t] = SPH_INLET;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_io_copy(int n, FluidState d, FluidState s, int64_t* origin)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    s.x[t] = d.x[t]; s.y[t] = d.y[t]; s.u[t] = d.u[t]; s.v[t] = d.v[t]; s.p[t] = d.p[t];
+    s.rho[t] = d.rho[t]; s.h[t] = d.h[t]; s.mref[t] = d.mref[t]; s.mq[t] = d.mq[t];
+    s.kind[t] = d.kind[t];
+    origin[t] = d.origin[t];
+}
+
+__global__ __launch_bounds__(256) void k_io_iota(int n, int64_t* origin)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) origin[i] = i;
+}
+
+int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    map->n_appended = map->n_deleted = map->n_to_outlet = 0;
+    map->n_required = n;
+    if (n == 0) return SPH_OK;
+    const unsigned nb = (unsigned)cdiv(n, 256);
+    // scratch that the neighbour structure does not use, so that an update
+    // which keeps every slot leaves the rate passes' list valid
+    int32_t *keep = w.flag, *rk = w.idx_a, *app = w.tmp_i32[1], *ra = w.closest;
+    int32_t* n_out = w.status + 8;
+    hipLaunchKernelGGL(k_io_zero, dim3(1), dim3(1), 0, c->stream, n_out);
+    hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
+                       (const int32_t*)ps->kind, *io, keep, app, n_out);
+    LAUNCHCHK(c, "io_flags");
+    int32_t nkeep = 0, na = 0, nto = 0;
+    int rc = compact_ranks(c, n, keep, rk, &nkeep);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(&nto, n_out, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    rc = compact_ranks(c, n, app, ra, &na);  // synchronises: nto is on the host after it
+    if (rc) return rc;
+    map->n_required = (int64_t)nkeep + na;
+    if (map->n_required > ps->capacity) {
+        set_err(c, "inlet/outlet update needs %lld slots, capacity %lld", (long long)map->n_required,
+                (long long)ps->capacity);
+        return SPH_E_CAPACITY;
+    }
+    map->n_to_outlet = nto;
+    map->n_appended = na;
+    map->n_deleted = n - nkeep;
+    if (na == 0 && nkeep == n && nto == 0) {
+        // nothing changes: identity map
+        hipLaunchKernelGGL(k_io_iota, dim3(nb), dim3(256), 0, c->stream, n, map->origin);
+        LAUNCHCHK(c, "io_iota");
+        return SPH_OK;
+    }
+    FluidState s{ps->x, ps->y, ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mref,
+                 ps->mq, map->origin, ps->kind, nullptr};
+    FluidState d = tmp_state(c, true);
+    d.sat = nullptr;
+    hipLaunchKernelGGL(k_io_apply, dim3(nb), dim3(256), 0, c->stream, n, s, d, (const int32_t*)keep,
+                       (const int32_t*)rk, (const int32_t*)app, (const int32_t*)ra, nkeep, *io);
+    LAUNCHCHK(c, "io_apply");
+    const int nn = nkeep + na;
+    if (nn > 0) {
+        hipLaunchKernelGGL(k_io_copy, dim3((unsigned)cdiv(nn, 256)), dim3(256), 0, c->stream, nn, d, s,
+                           map->origin);
+        LAUNCHCHK(c, "io_copy");
+    }
+    if (na > 0 || nkeep != n) {
+        // slots moved: the neighbour structure no longer matches them
+        c->list_valid = 0;
+        c->built_n = -1;
+    }
+    ps->n = nn;
+    return SPH_OK;
+}

@@ -92,6 +92,10 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
     w->href = (double*)take(8 * C);
     w->list_flag = (int32_t*)take(4 * 64);
     w->pk = (float4*)take(16 * C);
+    w->ug = (double*)take(8 * C);
+    w->vg = (double*)take(8 * C);
+    w->ugs = (double*)take(8 * C);
+    w->vgs = (double*)take(8 * C);
     return off + 256;
 }
 
@@ -104,6 +108,7 @@ static int check_cfg(const sph_config* cfg)
     if (cfg->precision != SPH_FP64 && cfg->precision != SPH_FP32) return 0;
     if (!(cfg->rho0 > 0) || !(cfg->mass_q > 0)) return 0;
     if (cfg->merge_iters < 0 || cfg->merge_iters > 8 || cfg->shift_iters < 0) return 0;
+    if (!isfinite(cfg->wall_accel[0]) || !isfinite(cfg->wall_accel[1])) return 0;
     return 1;
 }
 
@@ -207,6 +212,7 @@ extern "C" int sph_rates(sph_ctx* c, const sph_particles* ps, double dt, sph_rat
     if (!c || !out) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1)) return SPH_E_INVAL;
     if (!(dt > 0)) { set_err(c, "dt must be > 0"); return SPH_E_INVAL; }
+    if (ps->kind && !ps->rho) { set_err(c, "boundary particles need rho"); return SPH_E_INVAL; }
     return rates_eval(c, (int)ps->n, ps, dt, out);
 }
 
@@ -253,6 +259,22 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
     if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref) return SPH_E_INVAL;
     if (bg && !check_bg(c, bg)) return SPH_E_INVAL;
     return adapt_run(c, ps, bg, map);
+}
+
+extern "C" int sph_inout(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
+{
+    if (!c || !io || !map) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref || !ps->kind) {
+        set_err(c, "inout needs the full state including rho, mref and kind");
+        return SPH_E_INVAL;
+    }
+    if (!map->origin) { set_err(c, "inout map origin not set"); return SPH_E_INVAL; }
+    if (!isfinite(io->x_in) || !isfinite(io->x_out) || !(io->len_in >= 0) || !(io->len_out >= 0) ||
+        !isfinite(io->len_in) || !isfinite(io->len_out)) {
+        set_err(c, "inout zones must be finite with non-negative lengths");
+        return SPH_E_INVAL;
+    }
+    return inout_run(c, ps, io, map);
 }
 
 extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles* solids,

@@ -53,13 +53,20 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       const double* __restrict__ p,
                                                       const int64_t* __restrict__ mq, double mass_q,
                                                       const double* __restrict__ hs, double* us,
-                                                      double* vs, double* ps, T* ms, T* ih)
+                                                      double* vs, double* ps, T* ms, T* ih,
+                                                      const double* __restrict__ ug,
+                                                      const double* __restrict__ vg, double* ugs,
+                                                      double* vgs)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
     us[s] = u[i];
     vs[s] = v[i];
+    if (ug) {
+        ugs[s] = ug[i];
+        vgs[s] = vg[i];
+    }
     ps[s] = p[i];
     ms[s] = (T)((double)mq[i] * mass_q);
     ih[s] = (T)(1.0 / hs[s]);
@@ -69,10 +76,76 @@ struct PassAOut {
     double *rho, *beta, *pavg, *nnb, *dxs, *dys; // slot order, optional
 };
 
+// Boundary pass (section 2.2), one lane per sorted particle; fluid lanes
+// only copy their velocity into the viscous-term arrays.  A boundary
+// particle b sums over its fluid neighbours f, with the weights
+// W(r_bf, (h_b + h_f)/2) of eq. (shepard): the Shepard averages of u, v, p
+// and of rho_f (r_b - r_f), which gives the wall pressure of eq. (bc-pre)
+// (g the body force, a_w the wall acceleration).  Solids keep their own
+// (prescribed) velocity and get the no-slip ghost velocity 2 u_b - u^ of
+// eq. (bc-wall) for the viscous term; inlet particles get p; outlet
+// particles get u, v and p.  Only boundary slots are written and only
+// fluid slots are read, so lanes do not race.
+__global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl, int n,
+                                                  const int32_t* __restrict__ kind,
+                                                  const double* __restrict__ rho, double* u,
+                                                  double* v, double* p, double* ug, double* vg,
+                                                  double gx, double gy)
+{
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int b = nv.perm[s];
+    const int kb = kind[b];
+    if (kb == SPH_FLUID) {
+        ug[b] = u[b];
+        vg[b] = v[b];
+        return;
+    }
+    const double xb = nv.xs[s], yb = nv.ys[s], hb = nv.hs[s];
+    double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
+    auto body = [&](int js, double dx, double dy, double r2, double hj) {
+        const int f = nv.perm[js];
+        if (kind[f] != SPH_FLUID) return;
+        const double w = kern_w64(sqrt(r2), 0.5 * (hb + hj));
+        S += w;
+        su += u[f] * w;
+        sv += v[f] * w;
+        sp += p[f] * w;
+        srx += rho[f] * dx * w;
+        sry += rho[f] * dy * w;
+    };
+    const int cnt = nl.cnt[s];
+    if (cnt <= nl.K) for_each_listed(g, nv, nl, s, cnt, xb, yb, hb, body);
+    else for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[s]), body);
+    double ub = u[b], vb = v[b];
+    if (S > 0.0) {
+        if (kb == SPH_SOLID) {
+            p[b] = (sp + (gx * srx + gy * sry)) / S;
+            ug[b] = 2.0 * ub - su / S;
+            vg[b] = 2.0 * vb - sv / S;
+            return;
+        }
+        if (kb == SPH_INLET) {
+            p[b] = sp / S;
+        } else {
+            ub = su / S;
+            vb = sv / S;
+            u[b] = ub;
+            v[b] = vb;
+            p[b] = sp / S;
+        }
+    }
+    ug[b] = ub;
+    vg[b] = vb;
+}
+
+
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
                                                 NbrList nl, double rho0, PassAOut out,
-                                                double* r_dxs, double* r_dys)
+                                                double* r_dxs, double* r_dys,
+                                                const int32_t* __restrict__ kind)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -126,12 +199,15 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     b.dxs[s] = ddx;
     b.dys[s] = ddy;
     b.nnb[s] = N;
-    // per-particle factors for pass B
-    b.V[s] = b.m[s] / rho;
+    // per-particle factors for pass B; the volume of a solid (wall)
+    // particle is stored negated, which tells pass B to use its ghost
+    // velocity in the viscous term
+    const int slot = nv.perm[s];
+    const T Vs = b.m[s] / rho;
+    b.V[s] = (kind && kind[slot] == SPH_SOLID) ? -Vs : Vs;
     // beta <= 0 only when no neighbour lies inside the particle's own
     // support: its pressure term is taken as zero (and so are its 1/beta sums)
     b.B[s] = beta > T(0) ? T(1) / (rho * rho * beta) : T(0);
-    const int slot = nv.perm[s];
     r_dxs[slot] = (double)ddx;
     r_dys[slot] = (double)ddy;
     if (out.rho) out.rho[slot] = (double)rho;
@@ -146,16 +222,31 @@ struct PassBParams {
     double rho0, cs, nu, alpha_e, fx, fy, dt;
 };
 
-template <typename T>
+// GH: boundary particles present; the viscous term then takes the velocity
+// difference of (ugs, vgs), which holds the ghost velocity of solids and u
+// of everything else.
+template <typename T, bool GH>
 __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
                                                 NbrList nl, const double* __restrict__ us,
-                                                const double* __restrict__ vs, PassBParams P,
+                                                const double* __restrict__ vs,
+                                                const double* __restrict__ ugs,
+                                                const double* __restrict__ vgs, PassBParams P,
                                                 double* dpdt, double* dudt, double* dvdt)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
     const double ui = us[s], vi = vs[s], pi = b.ps[s];
+    // a negative volume marks a solid particle (ghost velocity in ugs, vgs)
+    double ugi = ui, vgi = vi;
+    bool solid_i = false;
+    if constexpr (GH) {
+        solid_i = b.V[s] < T(0);
+        if (solid_i) {
+            ugi = ugs[s];
+            vgi = vgs[s];
+        }
+    }
     const T ih = b.ih[s];
     const T sigi = T(SPH_SIGMA2) * ih * ih * ih;
     const T rhoi = b.rho[s];
@@ -177,9 +268,11 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
         const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * kern_fp<T>(r * ihj);
         const T fi = dwi * ir, fj = dwj * ir;
         const T dxT = (T)dx, dyT = (T)dy;
-        const T uij = (T)(ui - us[js]), vij = (T)(vi - vs[js]);
+        const double uj = us[js], vj = vs[js];
+        const T uij = (T)(ui - uj), vij = (T)(vi - vj);
         const T dpij = (T)(pi - b.ps[js]);
-        const T Vj = b.V[js], mj = b.m[js];
+        const T Vraw = b.V[js], mj = b.m[js];
+        const T Vj = GH ? fabs(Vraw) : Vraw;
         const T Pj = (-dpij - dpav) * b.B[js];
         const T nuj = aecs8 * (T)hj;
         const T nuij = T(4) * nui * nuj * rcp<T>(nui + nuj);
@@ -191,8 +284,20 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
         gx += gf * dxT;
         gy += gf * dyT;
         const T cv = mj * nu4 * rcp<T>(rhoi + b.rho[js]) * rdotg * iden;
-        vx += cv * uij;
-        vy += cv * vij;
+        if constexpr (GH) {
+            if (solid_i || Vraw < T(0)) {
+                const double ugj = Vraw < T(0) ? ugs[js] : uj;
+                const double vgj = Vraw < T(0) ? vgs[js] : vj;
+                vx += cv * (T)(ugi - ugj);
+                vy += cv * (T)(vgi - vgj);
+            } else {
+                vx += cv * uij;
+                vy += cv * vij;
+            }
+        } else {
+            vx += cv * uij;
+            vy += cv * vij;
+        }
     };
     const int cnt = nl.cnt[s];
     if (cnt <= nl.K) {
@@ -280,11 +385,14 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
     return SPH_OK;
 }
 
-// One evaluation on (x, y, u, v, p, h, mq): neighbours + pass A + pass B.
+// One evaluation on (x, y, u, v, p, h, mq): neighbours, the boundary pass
+// when kinds are given (it writes p, and u, v of outlet particles, of the
+// boundary slots; rho_in is the stored density it reads), pass A, pass B.
 template <typename T>
-static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const double* u,
-                  const double* v, const double* p, const double* h, const int64_t* mq, double dt,
-                  PassAOut aout, double* dpdt, double* dudt, double* dvdt)
+static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u, double* v,
+                  double* p, const double* h, const int64_t* mq, const int32_t* kind,
+                  const double* rho_in, double dt, PassAOut aout, double* dpdt, double* dudt,
+                  double* dvdt)
 {
     Work& w = c->w;
     int rc = ensure_list(c, n, x, y, h);
@@ -294,39 +402,54 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, const dou
     RatesBufs<T> b = rbufs<T>(c);
     const sph_config& cf = c->cfg;
     unsigned nb = (unsigned)cdiv(n, 256);
-    hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
-                       cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih);
-    LAUNCHCHK(c, "gather_state");
+    const bool gh = kind != nullptr;
     NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
+    if (gh) {
+        hipLaunchKernelGGL(k_boundary, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, nl, n, kind,
+                           rho_in, u, v, p, w.ug, w.vg, cf.body_force[0] - cf.wall_accel[0],
+                           cf.body_force[1] - cf.wall_accel[1]);
+        LAUNCHCHK(c, "boundary");
+    }
+    hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
+                       cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih,
+                       gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
+                       w.ugs, w.vgs);
+    LAUNCHCHK(c, "gather_state");
     prof_begin(c, SPH_PROF_PASS_A);
     hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       cf.rho0, aout, w.r_dxs, w.r_dys);
+                       cf.rho0, aout, w.r_dxs, w.r_dys, kind);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B);
-    hipLaunchKernelGGL(k_pass_b<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       (const double*)w.us, (const double*)w.vs, P, dpdt, dudt, dvdt);
+    if (gh)
+        hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+                           (const double*)w.us, (const double*)w.vs, (const double*)w.ugs,
+                           (const double*)w.vgs, P, dpdt, dudt, dvdt);
+    else
+        hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+                           (const double*)w.us, (const double*)w.vs, (const double*)nullptr,
+                           (const double*)nullptr, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");
     return SPH_OK;
 }
 
-static int eval(sph_ctx* c, int n, const double* x, const double* y, const double* u,
-                const double* v, const double* p, const double* h, const int64_t* mq, double dt,
-                PassAOut aout, double* dpdt, double* dudt, double* dvdt)
+static int eval(sph_ctx* c, int n, const double* x, const double* y, double* u, double* v, double* p,
+                const double* h, const int64_t* mq, const int32_t* kind, const double* rho_in,
+                double dt, PassAOut aout, double* dpdt, double* dudt, double* dvdt)
 {
     if (c->cfg.precision == SPH_FP32)
-        return eval_T<float>(c, n, x, y, u, v, p, h, mq, dt, aout, dpdt, dudt, dvdt);
-    return eval_T<double>(c, n, x, y, u, v, p, h, mq, dt, aout, dpdt, dudt, dvdt);
+        return eval_T<float>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt);
+    return eval_T<double>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt);
 }
 
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out)
 {
     Work& w = c->w;
     PassAOut a{out->rho, out->beta, out->pavg, out->nnb, out->dxs, out->dys};
-    int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, dt, a, w.r_dpdt, w.r_dudt,
-                  w.r_dvdt);
+    int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, dt, a,
+                  w.r_dpdt, w.r_dudt, w.r_dvdt);
     if (rc) return rc;
     if (n > 0) {
         if (out->dpdt)
@@ -360,7 +483,11 @@ __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* _
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     if (kind && kind[i] != SPH_FLUID) {
-        xh[i] = x[i]; yh[i] = y[i]; uh[i] = u[i]; vh[i] = v[i]; ph[i] = p[i];
+        // inlet and outlet particles move with their own velocity; solids stay
+        const bool adv = kind[i] == SPH_INLET || kind[i] == SPH_OUTLET;
+        xh[i] = adv ? wrap_axis(g, 0, x[i] + 0.5 * dt * u[i]) : x[i];
+        yh[i] = adv ? wrap_axis(g, 1, y[i] + 0.5 * dt * v[i]) : y[i];
+        uh[i] = u[i]; vh[i] = v[i]; ph[i] = p[i];
         return;
     }
     double un = u[i] + 0.5 * dt * au[i];
@@ -380,11 +507,25 @@ __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* _
                                                  const double* __restrict__ au,
                                                  const double* __restrict__ av,
                                                  const double* __restrict__ dxs,
-                                                 const double* __restrict__ dys, double dt)
+                                                 const double* __restrict__ dys, double dt,
+                                                 const double* __restrict__ uh,
+                                                 const double* __restrict__ vh,
+                                                 const double* __restrict__ ph)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (kind && kind[i] != SPH_FLUID) return;
+    if (kind && kind[i] != SPH_FLUID) {
+        // boundary particles keep the half-step boundary values; inlet and
+        // outlet particles advance with the half-step velocity
+        if (kind[i] == SPH_INLET || kind[i] == SPH_OUTLET) {
+            x[i] = wrap_axis(g, 0, x[i] + dt * uh[i]);
+            y[i] = wrap_axis(g, 1, y[i] + dt * vh[i]);
+        }
+        u[i] = uh[i];
+        v[i] = vh[i];
+        p[i] = ph[i];
+        return;
+    }
     double un = u[i] + dt * au[i];
     double vn = v[i] + dt * av[i];
     double tu = un + dxs[i] / dt;
@@ -402,22 +543,24 @@ int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
     const int n = (int)ps->n;
     if (n == 0) return SPH_OK;
     unsigned nb = (unsigned)cdiv(n, 256);
-    PassAOut none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // every evaluation stores its summation density: the next boundary pass
+    // reads it, and the caller gets the last one
     PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
     for (int s = 0; s < nsteps; ++s) {
-        int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, dt, none, w.r_dpdt,
-                      w.r_dudt, w.r_dvdt);
+        int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, dt,
+                      withrho, w.r_dpdt, w.r_dudt, w.r_dvdt);
         if (rc) return rc;
         hipLaunchKernelGGL(k_predict, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
                            ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
                            w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph);
         LAUNCHCHK(c, "predict");
-        rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, dt,
-                  s == nsteps - 1 ? withrho : none, w.r_dpdt, w.r_dudt, w.r_dvdt);
+        rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, ps->kind, ps->rho, dt, withrho,
+                  w.r_dpdt, w.r_dudt, w.r_dvdt);
         if (rc) return rc;
         hipLaunchKernelGGL(k_correct, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
                            ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
-                           w.r_dys, dt);
+                           w.r_dys, dt, (const double*)w.uh, (const double*)w.vh,
+                           (const double*)w.ph);
         LAUNCHCHK(c, "correct");
     }
     return SPH_OK;

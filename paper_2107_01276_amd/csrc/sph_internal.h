@@ -87,6 +87,8 @@ struct Work {
     int32_t nl_k;
     double *xref, *yref, *href; // state the list was built on (slot order)
     float4* pk;                 // sorted (x - org, y - org, padded radius^2) in FP32
+    double *ug, *vg;            // viscous-term velocity (ghost velocity of walls), slot order
+    double *ugs, *vgs;          // the same, sorted order
     int32_t* list_flag;         // [0]: rebuild needed (moved / h changed / overflow)
     int64_t capacity;
 };
@@ -139,6 +141,7 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
 
 // adapt.hip
 int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map);
+int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map);
 int mref_lookup_run(sph_ctx* c, const sph_particles* ps, const sph_background* bg);
 int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, const double* phi,
                   double phi_thresh, int passes, int64_t* nsplit);

@@ -141,6 +141,7 @@ class ChannelSpec:
     re: float = 100.0
     cs: float = 10.0
     wall_layers: int = 5
+    io_layers: int = 4            # inlet/outlet buffer columns (0: closed ends)
     jitter: float = 0.05
 
 
@@ -212,6 +213,45 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
     v = -s.u_inf * 2.0 * R2 * X * Y / (r2 * r2)
     p = 0.5 * s.rho0 * (s.u_inf ** 2 - (u * u + v * v))
 
+    # inlet buffer columns left of x = 0 (prescribed u_inf) and outlet
+    # columns right of x = length, each a lattice at the graded spacing the
+    # fluid has where the zone meets it (the spacing level of s(d) at the
+    # point of the boundary closest to the cylinder)
+    def zone_ds(d):
+        target = min(s.ds_min + d * slope, ds_max)
+        k = int(np.searchsorted(lev_ds, target * (1 + 1e-12), side="right") - 1)
+        return float(lev_ds[max(0, min(k, nlev))])
+    zx, zy, zk, zd = [], [], [], []
+    for side, kd in ((-1, INLET), (1, OUTLET)):
+        if s.io_layers <= 0:
+            continue
+        edge = lo[0] if side < 0 else hi[0]
+        dsz = zone_ds(abs(edge - s.cyl_x) - R)
+        nyz = max(int(round(s.height / dsz)), 1)
+        dyz = s.height / nyz
+        cols = np.arange(s.io_layers)
+        ci, cj = np.meshgrid(cols, np.arange(nyz), indexing="ij")
+        cx = edge + side * (ci.ravel() + 0.5) * dyz
+        cy = lo[1] + (cj.ravel() + 0.5) * dyz
+        cx = cx + rng.uniform(-s.jitter, s.jitter, cx.size) * dyz
+        cy = cy + rng.uniform(-s.jitter, s.jitter, cy.size) * dyz
+        zx.append(cx); zy.append(cy); zk.append(np.full(cx.size, kd, np.int32))
+        zd.append(np.full(cx.size, dyz))
+        if side < 0:
+            len_in = s.io_layers * dyz
+        else:
+            len_out = s.io_layers * dyz
+    if zx:
+        zx = np.concatenate(zx); zy = np.concatenate(zy); zk = np.concatenate(zk); zd = np.concatenate(zd)
+    else:
+        zx = zy = zd = np.zeros(0); zk = np.zeros(0, np.int32)
+        len_in = len_out = 0.0
+    nz = zx.size
+    x = np.concatenate([x, zx]); y = np.concatenate([y, zy]); ds = np.concatenate([ds, zd])
+    u = np.concatenate([u, np.full(nz, s.u_inf)]); v = np.concatenate([v, np.zeros(nz)])
+    p = np.concatenate([p, np.zeros(nz)])
+    kind_f = np.concatenate([np.zeros(x.size - nz, np.int32), zk])
+
     # solid dummy layers inside the cylinder at ds_min
     sx, sy = [], []
     for L in range(s.wall_layers):
@@ -232,15 +272,17 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
     H = np.concatenate([s.hdx * ds, np.full(ns, s.hdx * s.ds_min)])
     U = np.concatenate([u, np.zeros(ns)]); V = np.concatenate([v, np.zeros(ns)])
     P = np.concatenate([p, np.zeros(ns)])
-    kind = np.concatenate([np.zeros(nf, np.int32), np.ones(ns, np.int32)])
+    kind = np.concatenate([kind_f, np.full(ns, SOLID, np.int32)])
     nu = s.u_inf * s.diameter / s.re
     hmin = s.hdx * s.ds_min
     dt = min(0.25 * hmin / (s.u_inf + s.cs), 0.125 * hmin * hmin / nu)
     return {
         "x": X, "y": Yv, "u": U, "v": V, "p": P, "h": H, "mq": mq, "mass_q": q,
         "m": mq.astype(np.float64) * q, "rho": np.full(X.size, s.rho0),
-        "mref": np.concatenate([m_f, m_s]), "kind": kind, "n_fluid": nf, "n_solid": ns,
-        "domain": Domain(lo, hi, (False, True)),
+        "mref": np.concatenate([m_f, m_s]), "kind": kind, "n_fluid": int((kind == FLUID).sum()), "n_solid": ns,
+        "domain": Domain((lo[0] - len_in - 2 * s.ds_min * s.ratio, lo[1]),
+                         (hi[0] + len_out + 2 * s.ds_min * s.ratio, hi[1]), (False, True)),
+        "io": {"x_in": lo[0], "len_in": len_in, "x_out": hi[0], "len_out": len_out},
         "params": {"rho0": s.rho0, "cs": s.cs, "nu": nu, "hdx": s.hdx, "re": s.re,
                    "u_inf": s.u_inf},
         "dt": dt, "spec": s,
