@@ -37,6 +37,7 @@ METRIC = "pair evals/s per step, FP32 vs FP64 plain; batched-serve p50/p99 step 
 PASS_B_FLOPS_PER_PAIR = 79
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
 ADAPT_WARM = 4
 
 
@@ -49,7 +50,54 @@ def parse():
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=40)
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="for hardware-counter runs: a calibration copy of known size, then a "
+                         "few FP32 rate evaluations of the channel; prints nothing else")
     return ap.parse_args()
+
+
+CALIB_BYTES = 1 << 29  # bytes read (and written) by the calibration copy
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_b_channel_traffic.md")
+KERNEL_SOURCES = ("paper_2107_01276_amd/csrc/rates.hip", "paper_2107_01276_amd/csrc/sph_device.h")
+
+
+def measured_traffic():
+    """HBM bytes per pass-B launch from the committed counter summary, or
+    None when the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def pmc_sample(SPH, W, torch):
+    """One plain device copy of CALIB_BYTES (its FETCH_SIZE / WRITE_SIZE give
+    the counter-to-bytes factor), then 4 FP32 rate evaluations of the
+    channel (the pass-B dispatches whose traffic is measured)."""
+    src = torch.ones(CALIB_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = W.channel_cylinder(seed=2)
+    cfg = SPH.config_for(s["domain"], s["params"], float(s["h"].min()), float(s["h"].max()),
+                         precision=SPH.SPH_FP32, mass_q=s["mass_q"])
+    ctx = SPH.Context(cfg, s["x"].size)
+    P = SPH.Particles.from_arrays(s)
+    for _ in range(4):
+        ctx.rates(P, s["dt"])
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_sample": True, "calib_bytes": CALIB_BYTES, "n": P.n}))
 
 
 def count_pairs(ctx, P):
@@ -110,6 +158,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.pmc_sample:
+        pmc_sample(SPH, W, torch)
+        return
     s = W.channel_cylinder(seed=2)
     bg = W.channel_background(s["spec"], seed=3)
     n0 = s["x"].size
@@ -132,10 +183,15 @@ def main():
     avg_b = ms_b / max(nb, 1)
     flops = PASS_B_FLOPS_PER_PAIR * r32["pairs"]
     achieved = flops / (avg_b * 1e-3) / 1e12
+    traffic = measured_traffic()
     roof = {"bound": "alu", "kernel": "k_pass_b<float>", "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None, "avg_launch_ms": avg_b, "flops_per_launch": flops,
+            "traffic": traffic, "avg_launch_ms": avg_b, "flops_per_launch": flops,
             "flops_per_pair": PASS_B_FLOPS_PER_PAIR}
+    if traffic is not None:
+        gbs = traffic / (avg_b * 1e-3) / 1e9
+        roof["hbm_GBps"] = gbs
+        roof["hbm_frac"] = gbs / PEAK_HBM_GBPS
 
     cpu = None
     if not args.no_cpu_baseline:
