@@ -50,6 +50,11 @@ def parse():
     ap.add_argument("--adapt-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-steps", type=int, default=100)
+    ap.add_argument("--serve-arena-gib", type=float, default=4.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="for hardware-counter runs: a calibration copy of known size, then a "
                          "few FP32 rate evaluations of the channel; prints nothing else")
@@ -59,6 +64,41 @@ def parse():
 CALIB_BYTES = 1 << 29  # bytes read (and written) by the calibration copy
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_b_channel_traffic.md")
 KERNEL_SOURCES = ("paper_2107_01276_amd/csrc/rates.hip", "paper_2107_01276_amd/csrc/sph_device.h")
+
+
+def serving_bench(SPH, W, args):
+    """Continuous batching of periodic Taylor-Green requests (particle counts
+    log-uniform in [2e3, 2e5], Re uniform in [100, 1000], each with its own
+    dt, FP32) over a fixed arena.  A calibration run (the first 32 requests,
+    all present at t = 0, 10 steps) measures the saturated completion rate;
+    the requests then arrive as a Poisson process at 0.8 of it."""
+    from paper_2107_01276_amd import serving
+    reqs = W.serving_requests(n_req=args.serve_requests, seed=4, rate=1.0)
+    built = {}
+
+    def make(req):
+        key = (req["side"], req["seed"])
+        if key not in built:
+            st = W.tgv(req["side"], seed=req["seed"], re=req["re"])
+            cfg = SPH.config_for(st["domain"], st["params"], float(st["h"].min()),
+                                 float(st["h"].max()), precision=SPH.SPH_FP32,
+                                 mass_q=st["mass_q"], list_skin=0.0, lean=1)
+            built[key] = (cfg, st, st["dt"])
+        return built[key]
+
+    for r in reqs:
+        make(r)
+    arena = int(args.serve_arena_gib * (1 << 30))
+    ncal = min(32, len(reqs))
+    cal = [dict(r, arrival=0.0) for r in reqs[:ncal]]
+    c = serving.serve(cal, make, arena, args.serve_streams, steps=10)
+    rate = 0.8 * ncal / c["wall_s"] * 10.0 / args.serve_steps
+    for r in reqs:
+        r["arrival"] = r["arrival"] / rate
+    res = serving.serve(reqs, make, arena, args.serve_streams, steps=args.serve_steps)
+    res["arrival_rate_per_s"] = rate
+    res["particles_total"] = int(sum(make(r)[1]["x"].size for r in reqs))
+    return res
 
 
 def measured_traffic():
@@ -193,6 +233,11 @@ def main():
         roof["hbm_GBps"] = gbs
         roof["hbm_frac"] = gbs / PEAK_HBM_GBPS
 
+    serve = None
+    if not args.no_serve:
+        serve = serving_bench(SPH, W, args)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -236,6 +281,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in r32["prof"].items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(out))
 

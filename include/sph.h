@@ -77,6 +77,17 @@ typedef struct sph_config {
     double bg_mass_q;       /* background mass quantum */
     double wall_accel[2];   /* a_w of eq. (bc-pre): acceleration of the solid
                                particles (0 for a stationary body) */
+    int32_t list_k;         /* columns of the rate passes' neighbour list
+                               (0 = 160); longer rows fall back to a cell walk */
+    int32_t lean;           /* 1: workspace without the adaptation buffers;
+                               sph_adapt, sph_bg_update, sph_mref_lookup and
+                               sph_inout then return SPH_E_INVAL */
+    double list_skin;       /* in [0, 1]: the rate passes' list holds pairs
+                               closer than (1 + skin) 3 max(h_i, h_j) and is
+                               reused while every particle moved less than
+                               1.5 skin h_i (results are unchanged: the exact
+                               predicate is re-applied); 0 rebuilds it at
+                               every evaluation without a host round trip */
 } sph_config;
 
 /* Caller-owned particle set (device pointers, see conventions). kind may be
@@ -234,6 +245,62 @@ int sph_bg_update(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
  * and the state untouched when the result exceeds ps->capacity.  Updates
  * ps->n.  Synchronises. */
 int sph_inout(sph_ctx *ctx, sph_particles *ps, const sph_inout_params *io, sph_inout_map *map);
+
+/* ---- Serving pool: continuous batching of independent simulations ------
+ * A pool owns nothing but host bookkeeping and a few streams; its device
+ * memory is the caller's arena.  Each admitted simulation takes one block
+ * of it (its state, a pair counter and a lean context workspace: the
+ * simulation is stepped, never adapted).  sph_pool_step advances every
+ * resident simulation by nsteps of its own dt with the step of sph_step
+ * (neighbour list rebuilt at every evaluation), captured once per
+ * simulation into a HIP graph and replayed; simulations are spread over the
+ * pool's streams by resident particle count so that their graphs overlap
+ * on the device.  Admission and retirement may happen between any two
+ * steps.  Single-threaded use. */
+typedef struct sph_pool sph_pool;
+
+typedef struct sph_pool_stats {
+    int64_t bytes_total, bytes_used, largest_free;
+    int64_t resident;   /* simulations */
+    int64_t particles;  /* resident particles */
+} sph_pool_stats;
+
+/* Arena bytes one simulation of n particles with this configuration needs. */
+size_t sph_pool_footprint(const sph_config *cfg, int64_t n);
+
+/* arena: device memory (256-byte aligned) owned by the caller, outliving the
+ * pool; nstreams in [1, 8].  Errors: SPH_E_INVAL, SPH_E_DEVICE. */
+int sph_pool_create(void *arena, size_t arena_bytes, int32_t nstreams, sph_pool **out);
+void sph_pool_destroy(sph_pool *pool);
+const char *sph_pool_last_error(const sph_pool *pool);
+
+/* Admits a simulation whose initial state is `init` (device arrays, copied
+ * before the call returns; x, y, u, v, p, rho, h, mq required, mref and
+ * kind optional) with time step dt.  SPH_E_AGAIN (nothing changed) when no
+ * free block of the arena holds sph_pool_footprint(cfg, init->n).  Writes
+ * the simulation's id.  Waits for all work on the device before copying. */
+int sph_pool_admit(sph_pool *pool, const sph_config *cfg, const sph_particles *init, double dt,
+                   int32_t *sim_id);
+
+/* Advances every resident simulation by nsteps steps (eqs. int-pre and
+ * int-cor, with the rates of section 2).  Returns when all are done. */
+int sph_pool_step(sph_pool *pool, int32_t nsteps);
+
+/* Per simulation: the time from the start of the last sph_pool_step to the
+ * end of its work (ms, device clock), steps taken, and interacting ordered
+ * pairs evaluated so far (sum over evaluations of |N(i)| - 1).
+ * Any pointer may be NULL. */
+int sph_pool_sim_stats(sph_pool *pool, int32_t sim_id, double *last_ms, int64_t *steps,
+                       int64_t *pair_evals);
+
+/* Copies a simulation's state into dst (device arrays, capacity >= n).
+ * Waits for all work on the device first, and for the copy. */
+int sph_pool_read(sph_pool *pool, int32_t sim_id, sph_particles *dst);
+
+/* Removes a simulation and returns its block to the arena. */
+int sph_pool_retire(sph_pool *pool, int32_t sim_id);
+
+int sph_pool_info(sph_pool *pool, sph_pool_stats *out);
 
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);

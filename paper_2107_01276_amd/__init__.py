@@ -47,7 +47,8 @@ class sph_config(C.Structure):
                 ("merge_iters", C.c_int32), ("shift_iters", C.c_int32),
                 ("cr", C.c_double), ("ds_min", C.c_double), ("ds_max", C.c_double),
                 ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double),
-                ("wall_accel", C.c_double * 2)]
+                ("wall_accel", C.c_double * 2), ("list_k", C.c_int32), ("lean", C.c_int32),
+                ("list_skin", C.c_double)]
 
 
 class sph_particles(C.Structure):
@@ -82,6 +83,11 @@ class sph_inout_map(C.Structure):
                 ("n_to_outlet", C.c_int64), ("n_required", C.c_int64)]
 
 
+class sph_pool_stats(C.Structure):
+    _fields_ = [("bytes_total", C.c_int64), ("bytes_used", C.c_int64), ("largest_free", C.c_int64),
+                ("resident", C.c_int64), ("particles", C.c_int64)]
+
+
 class sph_background(C.Structure):
     _fields_ = [("n", C.c_int64), ("capacity", C.c_int64),
                 ("x", C.c_void_p), ("y", C.c_void_p), ("h", C.c_void_p), ("ds", C.c_void_p),
@@ -97,7 +103,9 @@ class sph_diag(C.Structure):
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
            "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_profile_enable",
-           "sph_profile_read", "sph_profile_reset")
+           "sph_profile_read", "sph_profile_reset", "sph_pool_footprint", "sph_pool_create",
+           "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
+           "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info")
 
 _lib = None
 
@@ -129,6 +137,16 @@ def load_library(path: str = LIB_PATH):
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
         "sph_profile_reset": (C.c_int, [P]),
+        "sph_pool_footprint": (C.c_size_t, [P, I64]),
+        "sph_pool_create": (C.c_int, [P, C.c_size_t, I32, P]),
+        "sph_pool_destroy": (None, [P]),
+        "sph_pool_last_error": (C.c_char_p, [P]),
+        "sph_pool_admit": (C.c_int, [P, P, P, D, P]),
+        "sph_pool_step": (C.c_int, [P, I32]),
+        "sph_pool_sim_stats": (C.c_int, [P, I32, P, P, P]),
+        "sph_pool_read": (C.c_int, [P, I32, P]),
+        "sph_pool_retire": (C.c_int, [P, I32]),
+        "sph_pool_info": (C.c_int, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -171,6 +189,9 @@ class Config:
     bg_smooth_iters: int = 3
     bg_mass_q: float = 2.0 ** -60
     wall_accel: tuple = (0.0, 0.0)
+    list_k: int = 0
+    lean: int = 0
+    list_skin: float = 0.1
 
     def c(self) -> sph_config:
         s = sph_config()
@@ -182,7 +203,7 @@ class Config:
         s.wall_accel[0], s.wall_accel[1] = self.wall_accel
         for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
                   "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
-                  "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q"):
+                  "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q", "list_k", "lean", "list_skin"):
             setattr(s, k, getattr(self, k))
         return s
 
@@ -407,6 +428,79 @@ class Context:
         ms, cnt = C.c_double(0), C.c_int64(0)
         self._check(self.lib.sph_profile_read(self._h, kernel.encode(), C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+
+class Pool:
+    """Serving pool (sph_pool_*): independent simulations resident in one
+    device arena, stepped together; admission by footprint."""
+
+    def __init__(self, arena_bytes: int, nstreams: int = 4, device="cuda"):
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        rc = self.lib.sph_pool_create(_ptr(self.arena), int(arena_bytes), int(nstreams), C.byref(h))
+        if rc != SPH_OK:
+            raise SphError(rc, "pool creation failed")
+        self._h = h
+
+    def _check(self, rc):
+        if rc != SPH_OK:
+            raise SphError(rc, self.lib.sph_pool_last_error(self._h).decode())
+
+    def footprint(self, cfg: Config, n: int) -> int:
+        c = cfg.c()
+        return int(self.lib.sph_pool_footprint(C.byref(c), int(n)))
+
+    def admit(self, cfg: Config, P: Particles, dt: float, with_kind: bool = False):
+        """Returns the simulation id, or None when the arena has no room."""
+        c = cfg.c()
+        ps = P.c()
+        if not with_kind:
+            ps.kind = None
+        sid = C.c_int32(-1)
+        rc = self.lib.sph_pool_admit(self._h, C.byref(c), C.byref(ps), float(dt), C.byref(sid))
+        if rc == SPH_E_AGAIN:
+            return None
+        self._check(rc)
+        return int(sid.value)
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.sph_pool_step(self._h, int(nsteps)))
+
+    def stats(self, sim_id: int, pairs: bool = False) -> dict:
+        ms, st, pe = C.c_double(0), C.c_int64(0), C.c_int64(0)
+        self._check(self.lib.sph_pool_sim_stats(self._h, int(sim_id), C.byref(ms), C.byref(st),
+                                                C.byref(pe) if pairs else None))
+        out = {"last_ms": ms.value, "steps": st.value}
+        if pairs:
+            out["pair_evals"] = pe.value
+        return out
+
+    def read(self, sim_id: int, P: Particles):
+        ps = P.c()
+        self._check(self.lib.sph_pool_read(self._h, int(sim_id), C.byref(ps)))
+        P.n = int(ps.n)
+        return P
+
+    def retire(self, sim_id: int):
+        self._check(self.lib.sph_pool_retire(self._h, int(sim_id)))
+
+    def info(self) -> dict:
+        st = sph_pool_stats()
+        self._check(self.lib.sph_pool_info(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in sph_pool_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.sph_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def config_for(domain, params: dict, h_lo: float, h_hi: float, precision=SPH_FP64,

@@ -28,7 +28,7 @@ int check_hip(sph_ctx* c, hipError_t e, const char* what)
 }
 
 // Carves the workspace.  With base == NULL only the size is computed.
-static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
+static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, int list_k)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
@@ -71,21 +71,24 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap)
     w->vh = (double*)take(8 * C);
     w->ph = (double*)take(8 * C);
     w->cnt64 = (int64_t*)take(8 * (C + 1));
-    w->rp_tmp = (int64_t*)take(8 * (C + 1));
-    w->col_cap = COL_PER_PARTICLE * C;
-    w->col_tmp = (int32_t*)take(4 * w->col_cap);
-    w->flag = (int32_t*)take(4 * (C + 1));
-    w->closest = (int32_t*)take(4 * C);
-    w->idx_a = (int32_t*)take(4 * (C + 1));
-    w->idx_b = (int32_t*)take(4 * (C + 1));
-    w->i64_a = (int64_t*)take(8 * (C + 1));
-    w->i64_b = (int64_t*)take(8 * (C + 1));
-    for (int k = 0; k < 10; ++k) w->tmp_d[k] = (double*)take(8 * C);
-    for (int k = 0; k < 2; ++k) w->tmp_i32[k] = (int32_t*)take(4 * C);
-    for (int k = 0; k < 3; ++k) w->tmp_i64[k] = (int64_t*)take(8 * C);
+    w->lean = lean;
+    // adaptation, background and inlet/outlet buffers (not in a lean workspace)
+    const int64_t CA = lean ? 0 : C;
+    w->rp_tmp = lean ? nullptr : (int64_t*)take(8 * (C + 1));
+    w->col_cap = COL_PER_PARTICLE * CA;
+    w->col_tmp = lean ? nullptr : (int32_t*)take(4 * w->col_cap);
+    w->flag = lean ? nullptr : (int32_t*)take(4 * (C + 1));
+    w->closest = lean ? nullptr : (int32_t*)take(4 * C);
+    w->idx_a = lean ? nullptr : (int32_t*)take(4 * (C + 1));
+    w->idx_b = lean ? nullptr : (int32_t*)take(4 * (C + 1));
+    w->i64_a = lean ? nullptr : (int64_t*)take(8 * (C + 1));
+    w->i64_b = lean ? nullptr : (int64_t*)take(8 * (C + 1));
+    for (int k = 0; k < 10; ++k) w->tmp_d[k] = lean ? nullptr : (double*)take(8 * C);
+    for (int k = 0; k < 2; ++k) w->tmp_i32[k] = lean ? nullptr : (int32_t*)take(4 * C);
+    for (int k = 0; k < 3; ++k) w->tmp_i64[k] = lean ? nullptr : (int64_t*)take(8 * C);
     w->red = (int64_t*)take(8 * 8192);
-    w->nl_k = NL_K;
-    w->nl_idx = (int32_t*)take(4 * (size_t)NL_K * C);
+    w->nl_k = list_k;
+    w->nl_idx = (int32_t*)take(4 * (size_t)list_k * C);
     w->nl_cnt = (int32_t*)take(4 * C);
     w->xref = (double*)take(8 * C);
     w->yref = (double*)take(8 * C);
@@ -109,6 +112,8 @@ static int check_cfg(const sph_config* cfg)
     if (!(cfg->rho0 > 0) || !(cfg->mass_q > 0)) return 0;
     if (cfg->merge_iters < 0 || cfg->merge_iters > 8 || cfg->shift_iters < 0) return 0;
     if (!isfinite(cfg->wall_accel[0]) || !isfinite(cfg->wall_accel[1])) return 0;
+    if (cfg->list_k < 0 || cfg->list_k > 1024 || (cfg->lean != 0 && cfg->lean != 1)) return 0;
+    if (!(cfg->list_skin >= 0.0 && cfg->list_skin <= 1.0)) return 0;
     return 1;
 }
 
@@ -120,7 +125,7 @@ extern "C" size_t sph_workspace_bytes(const sph_config* cfg, int64_t capacity)
     Grid g;
     grid_setup(cfg, &g);
     Work w;
-    return carve(&w, nullptr, g, capacity);
+    return carve(&w, nullptr, g, capacity, cfg->lean, cfg->list_k > 0 ? cfg->list_k : NL_K);
 }
 
 extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspace,
@@ -135,17 +140,18 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     grid_setup(cfg, &c->grid);
     c->capacity = capacity;
     c->stream = (hipStream_t)stream;
-    size_t need = carve(&c->w, nullptr, c->grid, capacity);
+    const int lk = cfg->list_k > 0 ? cfg->list_k : NL_K;
+    size_t need = carve(&c->w, nullptr, c->grid, capacity, cfg->lean, lk);
     if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) {
         free(c);
         return SPH_E_NOMEM;
     }
-    carve(&c->w, (char*)workspace, c->grid, capacity);
+    carve(&c->w, (char*)workspace, c->grid, capacity, cfg->lean, lk);
     c->prof[SPH_PROF_PASS_A].name = "pass_a";
     c->prof[SPH_PROF_PASS_B].name = "pass_b";
     c->prof[SPH_PROF_BUILD].name = "build";
     c->prof[SPH_PROF_LIST].name = "list";
-    c->skin = 0.1;
+    c->skin = cfg->list_skin;
     c->list_valid = 0;
     *out = c;
     return SPH_OK;
@@ -248,6 +254,10 @@ static bool check_bg(sph_ctx* c, const sph_background* bg)
 
 extern "C" int sph_mref_lookup(sph_ctx* c, const sph_particles* ps, const sph_background* bg)
 {
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
     if (!c || !bg) return SPH_E_INVAL;
     if (!check_ps(c, ps, 0) || !ps->mref || !check_bg(c, bg)) return SPH_E_INVAL;
     return mref_lookup_run(c, ps, bg);
@@ -255,6 +265,10 @@ extern "C" int sph_mref_lookup(sph_ctx* c, const sph_particles* ps, const sph_ba
 
 extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map)
 {
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
     if (!c || !map) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref) return SPH_E_INVAL;
     if (bg && !check_bg(c, bg)) return SPH_E_INVAL;
@@ -263,6 +277,10 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
 
 extern "C" int sph_inout(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
 {
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
     if (!c || !io || !map) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref || !ps->kind) {
         set_err(c, "inout needs the full state including rho, mref and kind");
@@ -280,6 +298,10 @@ extern "C" int sph_inout(sph_ctx* c, sph_particles* ps, const sph_inout_params* 
 extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles* solids,
                              const double* phi, double phi_thresh, int32_t passes, int64_t* nsplit)
 {
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
     if (!c || !bg || !solids || !nsplit || passes < 0) return SPH_E_INVAL;
     if (!check_bg(c, bg)) return SPH_E_INVAL;
     return bg_update_run(c, bg, solids, phi, phi_thresh, passes, nsplit);

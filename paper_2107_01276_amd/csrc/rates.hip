@@ -315,6 +315,23 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     dvdt[slot] = (double)(-gy + vy * ib) + P.fy;
 }
 
+// Adds the evaluation's interacting ordered pairs, sum over i of
+// (|N(i)| - 1), to *acc (one atomic per block).
+template <typename T>
+__global__ __launch_bounds__(256) void k_count_pairs(int n, const T* __restrict__ nnb,
+                                                     unsigned long long* acc)
+{
+    __shared__ int part[4];
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    int v = s < n ? (int)nnb[s] - 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(acc, (unsigned long long)((long long)part[0] + part[1] + part[2] + part[3]));
+}
+
 // Does the list built on (xref, yref, href) still hold N(i) for (x, y, h)?
 // Not if some particle moved by 1.5 skin h_i or more (then a pair may have
 // closed by 3 skin max(h_i, h_j)) or changed h; flag[0] is set then.
@@ -432,6 +449,11 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
                            (const double*)nullptr, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");
+    if (c->pair_acc) {
+        hipLaunchKernelGGL(k_count_pairs<T>, dim3(nb), dim3(256), 0, c->stream, n, (const T*)b.nnb,
+                           c->pair_acc);
+        LAUNCHCHK(c, "count_pairs");
+    }
     return SPH_OK;
 }
 

@@ -90,6 +90,7 @@ struct Work {
     double *ug, *vg;            // viscous-term velocity (ghost velocity of walls), slot order
     double *ugs, *vgs;          // the same, sorted order
     int32_t* list_flag;         // [0]: rebuild needed (moved / h changed / overflow)
+    int32_t lean;               // 1: the adaptation buffers below are not carved
     int64_t capacity;
 };
 
@@ -120,6 +121,8 @@ struct sph_ctx {
     int list_valid;
     int list_n;
     int64_t list_builds, list_reuses;
+    // when set, every rate evaluation adds its interacting ordered pairs here
+    unsigned long long* pair_acc;
 };
 
 // ---- host-side launch wrappers (implemented in the .hip files) ----------

@@ -1,0 +1,94 @@
+"""Continuous-batching request loop over the serving pool (sph_pool_*).
+
+Requests arrive over wall-clock time.  Between pool steps the loop admits,
+in arrival order, every request that has arrived and whose footprint fits
+the arena (admission stops at the first that does not, so that a large
+request is not starved), steps every resident simulation once, and retires
+the simulations that finished their steps, whose blocks then take the next
+arrivals.  Each pool step gives every resident simulation a step latency:
+the time from the start of the pool step to the end of that simulation's
+work on the device.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+
+from . import Particles, Pool
+
+
+def serve(requests, make_state, arena_bytes: int, nstreams: int = 4, steps: int = 100,
+          on_done=None):
+    """requests: dicts with at least "arrival" (seconds from the start).
+    make_state(req) -> (Config, state dict for Particles.from_arrays, dt).
+    on_done(req, pool, sim_id) is called before a finished simulation is
+    retired (e.g. to read its state).  Returns latency and throughput
+    statistics."""
+    pool = Pool(arena_bytes, nstreams)
+    order = sorted(range(len(requests)), key=lambda k: requests[k]["arrival"])
+    waiting = collections.deque()
+    resident = {}
+    lat = []
+    pair_evals = 0
+    done = 0
+    peak_resident = 0
+    head = None  # (req, Particles, cfg, dt) of the first waiting request
+    t0 = time.perf_counter()
+    nxt = 0
+    busy = 0.0
+    while nxt < len(order) or waiting or head is not None or resident:
+        now = time.perf_counter() - t0
+        while nxt < len(order) and requests[order[nxt]]["arrival"] <= now:
+            waiting.append(requests[order[nxt]])
+            nxt += 1
+        while head is not None or waiting:
+            if head is None:
+                req = waiting.popleft()
+                cfg, st, dt = make_state(req)
+                head = (req, Particles.from_arrays(st), cfg, dt)
+            req, P, cfg, dt = head
+            sid = pool.admit(cfg, P, dt)
+            if sid is None:
+                break
+            req["admitted"] = time.perf_counter() - t0
+            resident[sid] = [req, steps]
+            head = None
+        if not resident:
+            if head is not None:
+                raise RuntimeError("a request does not fit the empty arena")
+            if nxt < len(order):
+                time.sleep(max(0.0, requests[order[nxt]]["arrival"] - (time.perf_counter() - t0)))
+            continue
+        peak_resident = max(peak_resident, len(resident))
+        tb = time.perf_counter()
+        pool.step(1)
+        busy += time.perf_counter() - tb
+        for sid in list(resident):
+            lat.append(pool.stats(sid)["last_ms"])
+            resident[sid][1] -= 1
+            if resident[sid][1] == 0:
+                pair_evals += pool.stats(sid, pairs=True)["pair_evals"]
+                if on_done is not None:
+                    on_done(resident[sid][0], pool, sid)
+                resident[sid][0]["finished"] = time.perf_counter() - t0
+                pool.retire(sid)
+                del resident[sid]
+                done += 1
+    wall = time.perf_counter() - t0
+    pool.close()
+    lat = np.asarray(lat)
+    return {
+        "requests": done,
+        "steps_per_request": steps,
+        "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+        "pair_evals": int(pair_evals),
+        "wall_s": wall,
+        "busy_s": busy,
+        "pair_evals_per_s": pair_evals / wall if wall > 0 else None,
+        "peak_resident": peak_resident,
+        "arena_bytes": int(arena_bytes),
+        "streams": nstreams,
+    }
