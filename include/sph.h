@@ -228,12 +228,33 @@ int sph_mref_lookup(sph_ctx *ctx, const sph_particles *ps, const sph_background 
 int sph_adapt(sph_ctx *ctx, sph_particles *ps, const sph_background *bg, sph_adapt_map *map);
 
 /* Background update (section 3.3 steps 1-4), `passes` times: mark background
- * particles near solids (or with phi > phi_thresh when phi, a device array
- * over the background, is non-NULL; solution adaptivity), grade sizes by
- * C_r, split, then smooth h (eq. h-smoothing) and shift.  Updates bg->n.
- * *nsplit receives the number of splits.  Synchronises. */
+ * particles near solids, grade sizes by C_r, split, then smooth h (eq.
+ * h-smoothing) and shift.  Solution adaptivity: when phi (a device array
+ * over the background as it is at the call) is non-NULL, particles with
+ * phi > phi_thresh get a mark that lasts the whole call (their split
+ * children keep it) and are refined like particles near a body; without
+ * phi no particle is marked.  mask becomes 0, 1 (near a solid) or 3
+ * (marked).  Updates bg->n.  *nsplit receives the number of splits.
+ * Synchronises. */
 int sph_bg_update(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
                   const double *phi, double phi_thresh, int32_t passes, int64_t *nsplit);
+
+/* Vorticity of every particle (solution adaptivity, section 3.3):
+ * omega_i = sum_j (m_j/rho_j) [(v_j - v_i) dW/dx - (u_j - u_i) dW/dy] at
+ * h_i over N(i), with the stored density.  omega: device array >= n. */
+int sph_vorticity(sph_ctx *ctx, const sph_particles *ps, double *omega);
+
+/* Background update with solution adaptivity (section 3.3): |omega| of the
+ * fluid particles (kind 0) is carried to every background particle b by the
+ * Shepard average of eq. (shepard) over the fluid particles within
+ * 3 max(h_b, h_i), with W(r, (h_b + h_i)/2) (0 when none); background
+ * particles with phi_b > k_frac max|omega| are then treated as boundary
+ * background particles, as those near `solids` are, and the update of
+ * sph_bg_update runs (`passes` times).  *omega_max (may be NULL) receives
+ * max|omega|.  Synchronises. */
+int sph_bg_update_solution(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
+                           const sph_particles *fluid, double k_frac, int32_t passes,
+                           int64_t *nsplit, double *omega_max);
 
 /* Inlet/outlet update (section 2.2), to be called after a step.  On the
  * kinds before the call: an inlet particle with x >= x_in becomes fluid and

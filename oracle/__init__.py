@@ -96,6 +96,7 @@ def lib():
             "or_mref_lookup": (C.c_int, [P, I64, P, P, P, I64, P, P, P, P, P]),
             "or_bg_update": (I64, [P, P, I64, I64] + [P] * 7 + [I64, P, P, P, P, D, I32, P]),
             "or_vorticity": (None, [P, I64] + [P] * 10),
+            "or_shepard_to_bg": (C.c_int, [P, I64, P, P, P, I64, P, P, P, P, P, P]),
             "or_timestep": (D, [D, D, D, D]),
         }
         for name, (res, args) in sig.items():
@@ -513,6 +514,17 @@ def vorticity(dom: Dom, x, y, u, v, h, m, rho, rp, col):
     out = np.zeros(x.size)
     lib().or_vorticity(C.byref(dom.c()), x.size, _p(x), _p(y), _p(u), _p(v), _p(h), _p(m), _p(rho),
                        _p(_i64(rp)), _p(_i32(col)), _p(out))
+    return out
+
+
+def shepard_to_bg(dom: Dom, bx, by, bh, x, y, h, f, kind=None):
+    """Shepard average of the fluid field f at the background particles."""
+    bx, by, bh, x, y, h, f = map(_f64, (bx, by, bh, x, y, h, f))
+    kind = None if kind is None else _i32(kind)
+    out = np.zeros(bx.size)
+    rc = lib().or_shepard_to_bg(C.byref(dom.c()), bx.size, _p(bx), _p(by), _p(bh), x.size, _p(x),
+                                _p(y), _p(h), _p(kind), _p(f), _p(out))
+    assert rc == 0
     return out
 
 

@@ -1289,8 +1289,13 @@ int or_mref_lookup(const or_domain* d, int64_t n, const double* x, const double*
 
 /* One background pass, steps 1-4 of section 3.3.
  * Step 1: mask_b = 1 and ds_b = ds_min where a solid particle is within
- *   3 max(h_b, h_s); also where phi_b > phi_thresh when phi is given (the
- *   solution-adaptivity rule of section 3.3).
+ *   3 max(h_b, h_s); also where the background particle carries the
+ *   solution mark (the solution-adaptivity rule of section 3.3): in the
+ *   first pass of an update the mark (mask bit 2) is set where phi_b >
+ *   phi_thresh (cleared everywhere when phi is not given); later passes and
+ *   split children keep it.  READING: the paper marks these particles once
+ *   per update and lets the rest of the algorithm proceed, so the mark
+ *   lasts the whole update.  mask is 0, 1 (near a body) or 3 (marked).
  * Step 2 (Jacobi, self included): for unmasked b, with min, max and
  *   geometric mean of ds over N(b): ds' = C_r min if max/min < C_r^3, else
  *   the geometric mean; READING: clamped to [ds_min, ds_max].
@@ -1304,7 +1309,7 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
                            double* bx, double* by, double* bh, double* bds, int32_t* bmask,
                            int64_t* bmq, double* bmref, int64_t ns, const double* sx,
                            const double* sy, const double* sh, const double* phi,
-                           double phi_thresh, int64_t* nsplit)
+                           double phi_thresh, int first, int64_t* nsplit)
 {
     int64_t *rp = NULL;
     int32_t *col = NULL;
@@ -1313,8 +1318,9 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
     int64_t nnz = or_xnbr_cells_alloc(d, nb, bx, by, bh, ns, sx, sy, sh, &rp, &col);
     if (nnz < 0) return nnz;
     for (int64_t b = 0; b < nb; ++b) {
-        int m = rp[b + 1] > rp[b];
-        if (phi && phi[b] > phi_thresh) m = 1;
+        int sol = first ? ((phi && phi[b] > phi_thresh) ? 2 : 0) : (bmask[b] & 2);
+        int m = rp[b + 1] > rp[b] ? 1 : 0;
+        if (sol) m |= 3;
         bmask[b] = m;
         if (m) bds[b] = B->ds_min;
     }
@@ -1409,7 +1415,7 @@ int64_t or_bg_update(const or_domain* d, const or_bgparams* B, int64_t nb, int64
     *nsplit = 0;
     for (int it = 0; it < passes; ++it) {
         int64_t r = bg_one_pass(d, B, nb, cap, bx, by, bh, bds, bmask, bmq, bmref, ns, sx,
-                                sy, sh, it == 0 ? phi : NULL, phi_thresh, nsplit);
+                                sy, sh, it == 0 ? phi : NULL, phi_thresh, it == 0, nsplit);
         if (r < 0) return r;
         nb = r;
     }
@@ -1437,4 +1443,39 @@ void or_vorticity(const or_domain* d, int64_t n, const double* x, const double* 
         }
         omega[i] = s;
     }
+}
+
+/* Solution adaptivity (section 3.3): a fluid field f (|vorticity|) carried
+ * to the background particles by the Shepard average of eq. (shepard),
+ * phi_b = sum_i f_i W(r_bi, h_bi) / sum_i W(r_bi, h_bi) with
+ * h_bi = (h_b + h_i)/2 over the fluid particles i with
+ * r_bi < 3 max(h_b, h_i) (kind 0 only when kind is given); 0 when none.
+ * READING: the paper says the field is interpolated onto the background
+ * without naming the operator; the Shepard form is the one section 2.2
+ * uses for the same purpose. */
+int or_shepard_to_bg(const or_domain* d, int64_t nb, const double* bx, const double* by,
+                     const double* bh, int64_t n, const double* x, const double* y,
+                     const double* h, const int32_t* kind, const double* f, double* phi)
+{
+    int64_t* rp = NULL;
+    int32_t* col = NULL;
+    int64_t nnz = or_xnbr_cells_alloc(d, nb, bx, by, bh, n, x, y, h, &rp, &col);
+    if (nnz < 0) return (int)nnz;
+    for (int64_t b = 0; b < nb; ++b) {
+        double S = 0.0, sf = 0.0;
+        for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+            int64_t i = col[k];
+            if (kind && kind[i] != 0) continue;
+            double dx = mi_axis(d, 0, bx[b] - x[i]);
+            double dy = mi_axis(d, 1, by[b] - y[i]);
+            double r = sqrt(dx * dx + dy * dy);
+            double w = or_w(r, 0.5 * (bh[b] + h[i]));
+            S += w;
+            sf += f[i] * w;
+        }
+        phi[b] = S > 0.0 ? sf / S : 0.0;
+    }
+    free(rp);
+    free(col);
+    return OR_OK;
 }

@@ -103,7 +103,8 @@ class sph_diag(C.Structure):
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
            "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_profile_enable",
-           "sph_profile_read", "sph_profile_reset", "sph_pool_footprint", "sph_pool_create",
+           "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution",
+           "sph_pool_footprint", "sph_pool_create",
            "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
            "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info")
 
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
         "sph_adapt": (C.c_int, [P, P, P, P]),
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
         "sph_inout": (C.c_int, [P, P, P, P]),
+        "sph_vorticity": (C.c_int, [P, P, P]),
+        "sph_bg_update_solution": (C.c_int, [P, P, P, P, D, I32, P, P]),
         "sph_diagnostics": (C.c_int, [P, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
@@ -382,6 +385,22 @@ class Context:
         info["origin"] = origin[:P.n]
         info["sat"] = sat[:P.n]
         return info
+
+    def vorticity(self, P: Particles):
+        out = torch.empty(max(P.n, 1), dtype=torch.float64, device=self.device)
+        ps = P.c()
+        self._check(self.lib.sph_vorticity(self._h, C.byref(ps), _ptr(out)))
+        return out[:P.n]
+
+    def bg_update_solution(self, bg: "Background", solids: Particles, fluid: Particles,
+                           k_frac: float, passes: int):
+        bs, ss, fs = bg.c(), solids.c(), fluid.c()
+        ns, om = C.c_int64(0), C.c_double(0)
+        self._check(self.lib.sph_bg_update_solution(self._h, C.byref(bs), C.byref(ss), C.byref(fs),
+                                                    float(k_frac), int(passes), C.byref(ns),
+                                                    C.byref(om)))
+        bg.n = int(bs.n)
+        return {"nsplit": int(ns.value), "omega_max": om.value}
 
     def inout(self, P: Particles, io: dict):
         """Inlet/outlet update (sph_inout); io has x_in, len_in, x_out, len_out."""

@@ -19,6 +19,7 @@
 // flags of its wave is popcount(ballot & lanes-below), plus the wave and
 // block offsets.
 #include <math.h>
+#include <string.h>
 
 #include "sph_device.h"
 
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(256) void k_bg_mask(Grid g, NbrView nv, int nb,
                                                  const double* __restrict__ bh,
                                                  const double* __restrict__ phi, double phi_thresh,
                                                  double ds_min, int32_t* mask, double* ds,
-                                                 int have_solids)
+                                                 int have_solids, int first)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= nb) return;
@@ -616,7 +617,11 @@ __global__ __launch_bounds__(256) void k_bg_mask(Grid g, NbrView nv, int nb,
         for_each_neighbor(g, nv, xi, yi, hi, level_of(g, hi),
                           [&](int, double, double, double, double) { m = 1; });
     }
-    if (phi && phi[b] > phi_thresh) m = 1;
+    // solution mark (bit 2): set from phi in the first pass of an update
+    // (cleared when phi is not given), kept by later passes and by split
+    // children; a marked particle is refined like one near a body
+    const int sol = first ? ((phi && phi[b] > phi_thresh) ? 2 : 0) : (mask[b] & 2);
+    if (sol) m |= 3;
     mask[b] = m;
     if (m) ds[b] = ds_min;
 }
@@ -742,7 +747,7 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
         NbrView sv = nbr_view(c);
         hipLaunchKernelGGL(k_bg_mask, dim3(nbk), dim3(256), 0, c->stream, c->grid, sv, nb, bg->x,
                            bg->y, bg->h, pass == 0 ? phi : nullptr, phi_thresh, cf.ds_min, bg->mask,
-                           bg->ds, ns > 0 ? 1 : 0);
+                           bg->ds, ns > 0 ? 1 : 0, pass == 0 ? 1 : 0);
         LAUNCHCHK(c, "bg_mask");
         // step 2: size grading (Jacobi)
         int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
@@ -917,4 +922,130 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     }
     ps->n = nn;
     return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Solution adaptivity (section 3.3): vorticity of the fluid, its magnitude
+// carried to the background by the Shepard average of eq. (shepard), and
+// background particles with phi > k max|omega| refined like those near a
+// body.
+// ---------------------------------------------------------------------------
+
+// omega_i = sum_j V_j [(v_j - v_i) dW/dx - (u_j - u_i) dW/dy] at h_i, the
+// first-order difference SPH curl; V_j = m_j / rho_j with the stored density.
+__global__ __launch_bounds__(256) void k_vorticity(Grid g, NbrView nv, int n,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ rho,
+                                                   const int64_t* __restrict__ mq, double q,
+                                                   double* omega)
+{
+    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int i = nv.perm[s];
+    const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
+    const double ui = u[i], vi = v[i];
+    double acc = 0.0;
+    for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]),
+                      [&](int js, double dx, double dy, double r2, double) {
+                          const double r = sqrt(r2);
+                          if (r <= 0.0) return;
+                          const int j = nv.perm[js];
+                          const double f = kern_dw64(r, hi) / r;
+                          const double Vj = ((double)mq[j] * q) / rho[j];
+                          acc += Vj * ((v[j] - vi) * (f * dx) - (u[j] - ui) * (f * dy));
+                      });
+    omega[i] = acc;
+}
+
+int vorticity_run(sph_ctx* c, const sph_particles* ps, double* omega)
+{
+    const int n = (int)ps->n;
+    int rc = nbr_build(c, n, ps->x, ps->y, ps->h);
+    if (rc || n == 0) return rc;
+    hipLaunchKernelGGL(k_vorticity, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
+                       nbr_view(c), n, (const double*)ps->u, (const double*)ps->v,
+                       (const double*)ps->rho, (const int64_t*)ps->mq, c->cfg.mass_q, omega);
+    LAUNCHCHK(c, "vorticity");
+    return SPH_OK;
+}
+
+// phi_b = sum_i |f_i| W(r_bi, (h_b + h_i)/2) / sum_i W over the fluid
+// particles i with r_bi < 3 max(h_b, h_i) (0 when none), against the fluid
+// neighbour structure.
+__global__ __launch_bounds__(256) void k_bg_phi(Grid g, NbrView nv, int nb,
+                                                const double* __restrict__ bx,
+                                                const double* __restrict__ by,
+                                                const double* __restrict__ bh,
+                                                const int32_t* __restrict__ kind,
+                                                const double* __restrict__ f, double* phi)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const double xb = bx[b], yb = by[b], hb = bh[b];
+    double S = 0.0, sf = 0.0;
+    for_each_neighbor(g, nv, xb, yb, hb, level_of(g, hb),
+                      [&](int js, double, double, double r2, double hj) {
+                          const int i = nv.perm[js];
+                          if (kind && kind[i] != SPH_FLUID) return;
+                          const double w = kern_w64(sqrt(r2), 0.5 * (hb + hj));
+                          S += w;
+                          sf += fabs(f[i]) * w;
+                      });
+    phi[b] = S > 0.0 ? sf / S : 0.0;
+}
+
+// max over fluid slots of |f| as the bit pattern of a non-negative double
+// (monotone in the value), one atomic per block
+__global__ __launch_bounds__(256) void k_absmax(int n, const double* __restrict__ f,
+                                                const int32_t* __restrict__ kind,
+                                                unsigned long long* out)
+{
+    __shared__ double part[4];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = (i < n && (!kind || kind[i] == SPH_FLUID)) ? fabs(f[i]) : 0.0;
+    if (!(v == v)) v = 0.0;
+    v = wave_max_d(v);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+        atomicMax(out, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+__global__ void k_zero_u64_1(unsigned long long* p) { p[0] = 0ull; }
+
+int bg_solution_run(sph_ctx* c, sph_background* bg, const sph_particles* solids,
+                    const sph_particles* fluid, double k_frac, int passes, int64_t* nsplit,
+                    double* omega_max)
+{
+    Work& w = c->w;
+    const int n = (int)fluid->n, nb = (int)bg->n;
+    double* om = w.sc9;
+    double* phi = w.sc10;
+    double mx = 0.0;
+    if (n > 0) {
+        int rc = vorticity_run(c, fluid, om);
+        if (rc) return rc;
+        unsigned long long* red = (unsigned long long*)w.red;
+        hipLaunchKernelGGL(k_zero_u64_1, dim3(1), dim3(1), 0, c->stream, red);
+        hipLaunchKernelGGL(k_absmax, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
+                           (const double*)om, (const int32_t*)fluid->kind, red);
+        if (nb > 0)
+            hipLaunchKernelGGL(k_bg_phi, dim3((unsigned)cdiv(nb, 256)), dim3(256), 0, c->stream,
+                               c->grid, nbr_view(c), nb, (const double*)bg->x, (const double*)bg->y,
+                               (const double*)bg->h, (const int32_t*)fluid->kind,
+                               (const double*)om, phi);
+        LAUNCHCHK(c, "bg_phi");
+        unsigned long long bits = 0;
+        HIPCHK(c, hipMemcpyAsync(&bits, red, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        memcpy(&mx, &bits, sizeof(mx));
+    }
+    if (omega_max) *omega_max = mx;
+    // with no vorticity anywhere nothing is refined by the solution
+    const double thresh = k_frac * mx;
+    return bg_update_run(c, bg, solids, (n > 0 && nb > 0 && mx > 0.0) ? phi : nullptr, thresh,
+                         passes, nsplit);
 }

@@ -275,6 +275,27 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
     return adapt_run(c, ps, bg, map);
 }
 
+extern "C" int sph_vorticity(sph_ctx* c, const sph_particles* ps, double* omega)
+{
+    if (!c || !omega) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    return vorticity_run(c, ps, omega);
+}
+
+extern "C" int sph_bg_update_solution(sph_ctx* c, sph_background* bg, const sph_particles* solids,
+                                      const sph_particles* fluid, double k_frac, int32_t passes,
+                                      int64_t* nsplit, double* omega_max)
+{
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
+    if (!c || !bg || !solids || !fluid || !nsplit || passes < 0) return SPH_E_INVAL;
+    if (!(k_frac >= 0.0) || !isfinite(k_frac)) { set_err(c, "k_frac must be finite and >= 0"); return SPH_E_INVAL; }
+    if (!check_bg(c, bg) || !check_ps(c, fluid, 1) || !fluid->rho) return SPH_E_INVAL;
+    return bg_solution_run(c, bg, solids, fluid, k_frac, passes, nsplit, omega_max);
+}
+
 extern "C" int sph_inout(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
 {
     if (c && c->cfg.lean) {

@@ -145,6 +145,10 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
 // adapt.hip
 int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map);
 int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map);
+int vorticity_run(sph_ctx* c, const sph_particles* ps, double* omega);
+int bg_solution_run(sph_ctx* c, sph_background* bg, const sph_particles* solids,
+                    const sph_particles* fluid, double k_frac, int passes, int64_t* nsplit,
+                    double* omega_max);
 int mref_lookup_run(sph_ctx* c, const sph_particles* ps, const sph_background* bg);
 int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, const double* phi,
                   double phi_thresh, int passes, int64_t* nsplit);

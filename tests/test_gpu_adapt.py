@@ -143,3 +143,59 @@ def test_background_square():
         d = float(np.max(np.abs(gb[k] - ob[k])))
         print(f"[bg] {k} maxdiff={d}", flush=True)
         assert d < 1e-12, k
+
+
+def test_vorticity_vs_oracle():
+    P = lib()
+    s = W.tgv(40, seed=9)
+    rng = np.random.default_rng(9)
+    s["rho"] = 1.0 + 0.01 * rng.standard_normal(s["x"].size)
+    ctx = P.Context(P.config_for(s["domain"], s["params"], float(s["h"].min()), float(s["h"].max()),
+                                 mass_q=s["mass_q"]), s["x"].size)
+    w = ctx.vorticity(P.Particles.from_arrays(s)).cpu().numpy()
+    rp, col = oracle.neighbors(odom(s["domain"]), s["x"], s["y"], s["h"])
+    o = oracle.vorticity(odom(s["domain"]), s["x"], s["y"], s["u"], s["v"], s["h"],
+                         s["mq"] * s["mass_q"], s["rho"], rp, col)
+    err = float(np.linalg.norm(w - o) / np.linalg.norm(o))
+    print(f"[vorticity] rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_background_solution_adaptivity():
+    """Section 3.3, solution adaptivity: |vorticity| of a Taylor-Green field
+    carried to a coarse background; background particles above half the
+    maximum are refined to ds_min and the rest graded by C_r."""
+    P = lib()
+    s = W.tgv(40, seed=10)
+    dom = s["domain"]
+    bg = W.background_lattice(dom, 0.2, 1.2, 1.0)
+    k_frac, passes = 0.5, 10
+    rho = np.ones(s["x"].size)
+    m = s["mq"] * s["mass_q"]
+    rp, col = oracle.neighbors(odom(dom), s["x"], s["y"], s["h"])
+    om = np.abs(oracle.vorticity(odom(dom), s["x"], s["y"], s["u"], s["v"], s["h"], m, rho, rp, col))
+    phi = oracle.shepard_to_bg(odom(dom), bg["x"], bg["y"], bg["h"], s["x"], s["y"], s["h"], om)
+    thresh = k_frac * om.max()
+    empty = {"x": np.zeros(0), "y": np.zeros(0), "h": np.zeros(0)}
+    bp = oracle.BgPrm(cr=1.2, ds_min=0.025, ds_max=0.2, mass_q=bg["mass_q"])
+    ob, onsplit = oracle.bg_update(odom(dom), bp, bg, empty, passes, cap=40000, phi=phi,
+                                   phi_thresh=thresh)
+    cfg = P.Config(lo=dom.lo, hi=dom.hi, periodic=dom.periodic, h_lo=float(s["h"].min()), h_hi=0.5,
+                   cr=1.2, ds_min=0.025, ds_max=0.2, bg_mass_q=bg["mass_q"], mass_q=s["mass_q"])
+    ctx = P.Context(cfg, 40000)
+    B = P.Background.from_arrays(bg, 40000)
+    S = P.Particles.from_arrays({"x": np.zeros(0), "y": np.zeros(0), "h": np.zeros(0),
+                                 "mq": np.zeros(0, np.int64)}, capacity=1)
+    F = P.Particles.from_arrays(s)
+    info = ctx.bg_update_solution(B, S, F, k_frac, passes)
+    gb = B.numpy()
+    print(f"[bg-sol] gpu n={B.n} splits={info['nsplit']} oracle n={ob['x'].size} "
+          f"splits={onsplit} max|w| gpu={info['omega_max']:.12g} oracle={om.max():.12g}", flush=True)
+    assert info["omega_max"] == pytest.approx(om.max(), rel=1e-12)
+    assert onsplit > 0 and (ob["mask"] == 3).sum() > 0
+    assert info["nsplit"] == onsplit and B.n == ob["x"].size
+    assert np.array_equal(gb["mask"], ob["mask"]) and np.array_equal(gb["mq"], ob["mq"])
+    for k in ("ds", "mref"):
+        assert np.allclose(gb[k], ob[k], rtol=1e-12, atol=0), k
+    for k in ("x", "y", "h"):
+        assert float(np.max(np.abs(gb[k] - ob[k]))) < 1e-12, k
