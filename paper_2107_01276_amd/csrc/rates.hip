@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       double* vs, double* ps, T* ms, T* ih,
                                                       const double* __restrict__ ug,
                                                       const double* __restrict__ vg, double* ugs,
-                                                      double* vgs)
+                                                      double* vgs, const int32_t* __restrict__ kind)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -64,8 +64,10 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     us[s] = u[i];
     vs[s] = v[i];
     if (ug) {
-        ugs[s] = ug[i];
-        vgs[s] = vg[i];
+        // the ghost velocity of a solid (fluid, inlet and outlet: their u)
+        const bool sol = kind[i] == SPH_SOLID;
+        ugs[s] = sol ? ug[i] : u[i];
+        vgs[s] = sol ? vg[i] : v[i];
     }
     ps[s] = p[i];
     ms[s] = (T)((double)mq[i] * mass_q);
@@ -76,8 +78,9 @@ struct PassAOut {
     double *rho, *beta, *pavg, *nnb, *dxs, *dys; // slot order, optional
 };
 
-// Boundary pass (section 2.2), one lane per sorted particle; fluid lanes
-// only copy their velocity into the viscous-term arrays.  A boundary
+// Boundary pass (section 2.2).  The boundary particles (non-fluid kinds)
+// are first listed by their sorted positions (order of listing is
+// immaterial: each is then reduced by one wave on its own).  A boundary
 // particle b sums over its fluid neighbours f, with the weights
 // W(r_bf, (h_b + h_f)/2) of eq. (shepard): the Shepard averages of u, v, p
 // and of rho_f (r_b - r_f), which gives the wall pressure of eq. (bc-pre)
@@ -85,61 +88,106 @@ struct PassAOut {
 // (prescribed) velocity and get the no-slip ghost velocity 2 u_b - u^ of
 // eq. (bc-wall) for the viscous term; inlet particles get p; outlet
 // particles get u, v and p.  Only boundary slots are written and only
-// fluid slots are read, so lanes do not race.
+// fluid slots are read, so waves do not race.
+__global__ __launch_bounds__(256) void k_bmark(int n, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ kind, int32_t* list,
+                                               int32_t* count)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bnd = s < n && kind[perm[s]] != SPH_FLUID;
+    const uint64_t m = __ballot(bnd);
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, (int)__popcll(m));
+    base = __shfl(base, 0, 64);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (bnd) list[base + __popcll(m & lt)] = s;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One wave per listed boundary particle; a fixed grid strides over the list
+// (every wave leaves once the list is exhausted).
 __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl, int n,
+                                                  const int32_t* __restrict__ list,
+                                                  const int32_t* __restrict__ count,
                                                   const int32_t* __restrict__ kind,
                                                   const double* __restrict__ rho, double* u,
                                                   double* v, double* p, double* ug, double* vg,
                                                   double gx, double gy)
 {
-    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const int b = nv.perm[s];
-    const int kb = kind[b];
-    if (kb == SPH_FLUID) {
-        ug[b] = u[b];
-        vg[b] = v[b];
-        return;
-    }
-    const double xb = nv.xs[s], yb = nv.ys[s], hb = nv.hs[s];
-    double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
-    auto body = [&](int js, double dx, double dy, double r2, double hj) {
-        const int f = nv.perm[js];
-        if (kind[f] != SPH_FLUID) return;
-        const double w = kern_w64(sqrt(r2), 0.5 * (hb + hj));
-        S += w;
-        su += u[f] * w;
-        sv += v[f] * w;
-        sp += p[f] * w;
-        srx += rho[f] * dx * w;
-        sry += rho[f] * dy * w;
-    };
-    const int cnt = nl.cnt[s];
-    if (cnt <= nl.K) for_each_listed(g, nv, nl, s, cnt, xb, yb, hb, body);
-    else for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[s]), body);
-    double ub = u[b], vb = v[b];
-    if (S > 0.0) {
-        if (kb == SPH_SOLID) {
-            p[b] = (sp + (gx * srx + gy * sry)) / S;
-            ug[b] = 2.0 * ub - su / S;
-            vg[b] = 2.0 * vb - sv / S;
-            return;
+    const int lane = __lane_id();
+    const int nw = (gridDim.x * blockDim.x) >> 6;
+    const int total = *count;
+    for (int e = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < total; e += nw) {
+        const int s = list[e];
+        const int b = nv.perm[s];
+        const int kb = kind[b];
+        const double xb = nv.xs[s], yb = nv.ys[s], hb = nv.hs[s];
+        double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
+        auto body = [&](int js, double dx, double dy, double r2, double hj) {
+            const int f = nv.perm[js];
+            if (kind[f] != SPH_FLUID) return;
+            const double w = kern_w64(sqrt(r2), 0.5 * (hb + hj));
+            S += w;
+            su += u[f] * w;
+            sv += v[f] * w;
+            sp += p[f] * w;
+            srx += rho[f] * dx * w;
+            sry += rho[f] * dy * w;
+        };
+        const int cnt = nl.cnt[s];
+        if (cnt <= nl.K) {
+            const double rb3 = 3.0 * hb, rb2 = rb3 * rb3;
+            for (int k = lane; k < cnt; k += 64) {
+                const int js = nl.idx[(int64_t)k * nl.stride + s];
+                const double dx = mi_axis(g, 0, xb - nv.xs[js]);
+                const double dy = mi_axis(g, 1, yb - nv.ys[js]);
+                const double hj = nv.hs[js];
+                const double r2 = dx * dx + dy * dy;
+                const double rj3 = 3.0 * hj;
+                if (r2 < fmax(rb2, rj3 * rj3)) body(js, dx, dy, r2, hj);
+            }
+        } else if (lane == 0) {
+            for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[s]), body);
         }
-        if (kb == SPH_INLET) {
-            p[b] = sp / S;
-        } else {
-            ub = su / S;
-            vb = sv / S;
-            u[b] = ub;
-            v[b] = vb;
-            p[b] = sp / S;
+        S = wave_sum_d(S);
+        su = wave_sum_d(su);
+        sv = wave_sum_d(sv);
+        sp = wave_sum_d(sp);
+        srx = wave_sum_d(srx);
+        sry = wave_sum_d(sry);
+        if (lane != 0) continue;
+        double ub = u[b], vb = v[b];
+        if (S > 0.0) {
+            if (kb == SPH_SOLID) {
+                p[b] = (sp + (gx * srx + gy * sry)) / S;
+                ug[b] = 2.0 * ub - su / S;
+                vg[b] = 2.0 * vb - sv / S;
+                continue;
+            }
+            if (kb == SPH_INLET) {
+                p[b] = sp / S;
+            } else {
+                ub = su / S;
+                vb = sv / S;
+                u[b] = ub;
+                v[b] = vb;
+                p[b] = sp / S;
+            }
         }
+        ug[b] = ub;
+        vg[b] = vb;
     }
-    ug[b] = ub;
-    vg[b] = vb;
 }
 
-
+__global__ void k_zero_count(int32_t* c) { c[0] = 0; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
@@ -422,15 +470,22 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     const bool gh = kind != nullptr;
     NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
     if (gh) {
-        hipLaunchKernelGGL(k_boundary, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, nl, n, kind,
-                           rho_in, u, v, p, w.ug, w.vg, cf.body_force[0] - cf.wall_accel[0],
+        int32_t* blist = (int32_t*)w.ugs;  // free until the gather below fills it
+        int32_t* bcount = w.status + 16;
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, c->stream, bcount);
+        hipLaunchKernelGGL(k_bmark, dim3(nb), dim3(256), 0, c->stream, n, (const int32_t*)nv.perm, kind,
+                           blist, bcount);
+        const unsigned nbw = (unsigned)(nb < 512 ? nb : 512);
+        hipLaunchKernelGGL(k_boundary, dim3(nbw), dim3(256), 0, c->stream, c->grid, nv, nl, n,
+                           (const int32_t*)blist, (const int32_t*)bcount, kind, rho_in, u, v, p, w.ug,
+                           w.vg, cf.body_force[0] - cf.wall_accel[0],
                            cf.body_force[1] - cf.wall_accel[1]);
         LAUNCHCHK(c, "boundary");
     }
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
                        cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih,
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
-                       w.ugs, w.vgs);
+                       w.ugs, w.vgs, kind);
     LAUNCHCHK(c, "gather_state");
     prof_begin(c, SPH_PROF_PASS_A);
     hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,

@@ -253,6 +253,45 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
     const Span yr = axis_span(g, 1, yi, R, Q);
     const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
     const int nq = g.nxq[Q][0];
+    const int x0n = xr.b0 - xr.a0 + 1, y0n = yr.b0 - yr.a0 + 1;
+    const int nxc = x0n + (xr.n == 2 ? xr.b1 - xr.a1 + 1 : 0);
+    const int nyc = y0n + (yr.n == 2 ? yr.b1 - yr.a1 + 1 : 0);
+    if (nxc <= 3 && nyc <= 3) {
+        // at most 3 x 3 cells (the usual case): issue every table load of the
+        // level before walking any run, in the same cell order as below
+        int cxs[3], cys[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            cxs[k] = k < x0n ? xr.a0 + k : xr.a1 + (k - x0n);
+            cys[k] = k < y0n ? yr.a0 + k : yr.a1 + (k - y0n);
+        }
+        int2 se[9];
+#pragma unroll
+        for (int ty = 0; ty < 3; ++ty) {
+            const double gy = ty < nyc ? cell_gap(g, 1, yi, cys[ty], Q) : HUGE_VAL;
+#pragma unroll
+            for (int tx = 0; tx < 3; ++tx) {
+                se[ty * 3 + tx] = make_int2(0, 0);
+                if (ty < nyc && tx < nxc && gy <= Rs) {
+                    const double gx = cell_gap(g, 0, xi, cxs[tx], Q);
+                    if (gx * gx + gy * gy <= Rs2) se[ty * 3 + tx] = tab[(int64_t)cys[ty] * nq + cxs[tx]];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            for (int js = se[k].x; js < se[k].y; ++js) {
+                const double xj = nv.xs[js], yj = nv.ys[js], hj = nv.hs[js];
+                const double dx = mi_axis(g, 0, xi - xj);
+                const double dy = mi_axis(g, 1, yi - yj);
+                const double r2 = dx * dx + dy * dy;
+                const double hm = hi > hj ? hi : hj;
+                const double RR = (3.0 * hm) * sf;
+                if (r2 < RR * RR) f(js, dx, dy, r2, hj);
+            }
+        }
+        return;
+    }
     for (int ty = 0; ty < yr.n; ++ty) {
         const int cy0 = ty ? yr.a1 : yr.a0, cy1 = ty ? yr.b1 : yr.b0;
         for (int cy = cy0; cy <= cy1; ++cy) {
