@@ -99,6 +99,9 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->vg = (double*)take(8 * C);
     w->ugs = (double*)take(8 * C);
     w->vgs = (double*)take(8 * C);
+    w->pa = (double4*)take(32 * C);
+    w->puv = (double2*)take(16 * C);
+    w->pf = take(32 * C);
     return off + 256;
 }
 

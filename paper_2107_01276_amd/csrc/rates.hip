@@ -52,8 +52,10 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ p,
                                                       const int64_t* __restrict__ mq, double mass_q,
-                                                      const double* __restrict__ hs, double* us,
-                                                      double* vs, double* ps, T* ms, T* ih,
+                                                      const double* __restrict__ xs,
+                                                      const double* __restrict__ ys,
+                                                      const double* __restrict__ hs, double4* pa,
+                                                      double2* puv, T* ms,
                                                       const double* __restrict__ ug,
                                                       const double* __restrict__ vg, double* ugs,
                                                       double* vgs, const int32_t* __restrict__ kind)
@@ -61,17 +63,15 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
-    us[s] = u[i];
-    vs[s] = v[i];
+    pa[s] = make_double4(xs[s], ys[s], hs[s], p[i]);
+    puv[s] = make_double2(u[i], v[i]);
+    ms[s] = (T)((double)mq[i] * mass_q);
     if (ug) {
         // the ghost velocity of a solid (fluid, inlet and outlet: their u)
         const bool sol = kind[i] == SPH_SOLID;
         ugs[s] = sol ? ug[i] : u[i];
         vgs[s] = sol ? vg[i] : v[i];
     }
-    ps[s] = p[i];
-    ms[s] = (T)((double)mq[i] * mass_q);
-    ih[s] = (T)(1.0 / hs[s]);
 }
 
 struct PassAOut {
@@ -191,28 +191,31 @@ __global__ void k_zero_count(int32_t* c) { c[0] = 0; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                NbrList nl, double rho0, PassAOut out,
-                                                double* r_dxs, double* r_dys,
+                                                NbrList nl, const double4* __restrict__ pa,
+                                                typename Vec4<T>::type* pf, double rho0,
+                                                PassAOut out, double* r_dxs, double* r_dys,
                                                 const int32_t* __restrict__ kind)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s], pi = b.ps[s];
+    const double4 ai = pa[s];
+    const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
     const int li = key_level(g, nv.keys[s]);
-    const T ih = b.ih[s];
+    const T ih = (T)(1.0 / hi);
     const T sig = T(SPH_SIGMA2) * ih * ih;
     const T irho0 = T(1.0 / rho0);
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
     CSum<T> sr, sb, sp, sx, sy;
     int nn = 0;  // |N(i)|
-    auto body = [&](int js, double dx, double dy, double r2, double hj) __attribute__((always_inline)) {
+    auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
+        __attribute__((always_inline)) {
         ++nn;
         const T mj = b.m[js];
         const T r = fsqrt<T>((T)r2);
         const T q = r * ih;
         sr.add(mj * (sig * kern_f<T>(q)));
         sb.add(mj * r * (sig * ih * kern_fp<T>(q)));
-        sp.add((T)(b.ps[js] - pi));
+        sp.add((T)(pj - pi));
         if (r > T(0)) {
             const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
             const T qij = r * ihij;
@@ -226,8 +229,13 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
         }
     };
     const int cnt = nl.cnt[s];
-    if (cnt <= nl.K) for_each_listed(g, nv, nl, s, cnt, xi, yi, hi, body);
-    else for_each_neighbor(g, nv, xi, yi, hi, li, body);
+    if (cnt <= nl.K) {
+        for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
+    } else {
+        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+            body(js, dx, dy, r2, hj, pa[js].w);
+        });
+    }
     const T rho = sr.get();
     const T beta = -sb.get() / (T(2) * rho);
     const T N = (T)nn;
@@ -247,15 +255,21 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     b.dxs[s] = ddx;
     b.dys[s] = ddy;
     b.nnb[s] = N;
-    // per-particle factors for pass B; the volume of a solid (wall)
-    // particle is stored negated, which tells pass B to use its ghost
-    // velocity in the viscous term
+    // per-particle factors for pass B, packed with rho and m; the volume of
+    // a solid (wall) particle is stored negated, which tells pass B to use
+    // its ghost velocity in the viscous term
     const int slot = nv.perm[s];
-    const T Vs = b.m[s] / rho;
-    b.V[s] = (kind && kind[slot] == SPH_SOLID) ? -Vs : Vs;
+    const T ms = b.m[s];
+    const T Vs = ms / rho;
     // beta <= 0 only when no neighbour lies inside the particle's own
     // support: its pressure term is taken as zero (and so are its 1/beta sums)
-    b.B[s] = beta > T(0) ? T(1) / (rho * rho * beta) : T(0);
+    const T Bs = beta > T(0) ? T(1) / (rho * rho * beta) : T(0);
+    typename Vec4<T>::type f;
+    f.x = (kind && kind[slot] == SPH_SOLID) ? -Vs : Vs;
+    f.y = Bs;
+    f.z = rho;
+    f.w = ms;
+    pf[s] = f;
     r_dxs[slot] = (double)ddx;
     r_dys[slot] = (double)ddy;
     if (out.rho) out.rho[slot] = (double)rho;
@@ -275,31 +289,35 @@ struct PassBParams {
 // of everything else.
 template <typename T, bool GH>
 __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                NbrList nl, const double* __restrict__ us,
-                                                const double* __restrict__ vs,
+                                                NbrList nl, const double4* __restrict__ pa,
+                                                const double2* __restrict__ puv,
+                                                const typename Vec4<T>::type* __restrict__ pf,
                                                 const double* __restrict__ ugs,
                                                 const double* __restrict__ vgs, PassBParams P,
                                                 double* dpdt, double* dudt, double* dvdt)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
-    const double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
-    const double ui = us[s], vi = vs[s], pi = b.ps[s];
+    const double4 ai = pa[s];
+    const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
+    const double2 uvi = puv[s];
+    const double ui = uvi.x, vi = uvi.y;
+    const typename Vec4<T>::type fi4 = pf[s];
     // a negative volume marks a solid particle (ghost velocity in ugs, vgs)
     double ugi = ui, vgi = vi;
     bool solid_i = false;
     if constexpr (GH) {
-        solid_i = b.V[s] < T(0);
+        solid_i = fi4.x < T(0);
         if (solid_i) {
             ugi = ugs[s];
             vgi = vgs[s];
         }
     }
-    const T ih = b.ih[s];
+    const T ih = (T)(1.0 / hi);
     const T sigi = T(SPH_SIGMA2) * ih * ih * ih;
-    const T rhoi = b.rho[s];
+    const T rhoi = fi4.z;
     const T dpav = b.dpav[s];
-    const T Bi = b.B[s];
+    const T Bi = fi4.y;
     const T Pi = -dpav * Bi;
     const T aecs8 = (T)(P.alpha_e * P.cs / 8.0);
     const T nui = aecs8 * (T)hi;
@@ -307,21 +325,23 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     const T nu4 = (T)(4.0 * P.nu);
     CSum<T> sdiv, sdif;
     T gx = 0, gy = 0, vx = 0, vy = 0;
-    auto body = [&](int js, double dx, double dy, double r2, double hj) __attribute__((always_inline)) {
+    auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
+        __attribute__((always_inline)) {
         const T r = fsqrt<T>((T)r2);
         if (!(r > T(0))) return;  // the self pair contributes nothing
+        const double2 uvj = puv[js];
+        const typename Vec4<T>::type fj4 = pf[js];
         const T ir = rcp<T>(r);
-        const T ihj = b.ih[js];
+        const T ihj = rcp<T>((T)hj);
         const T dwi = sigi * kern_fp<T>(r * ih);
         const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * kern_fp<T>(r * ihj);
         const T fi = dwi * ir, fj = dwj * ir;
         const T dxT = (T)dx, dyT = (T)dy;
-        const double uj = us[js], vj = vs[js];
-        const T uij = (T)(ui - uj), vij = (T)(vi - vj);
-        const T dpij = (T)(pi - b.ps[js]);
-        const T Vraw = b.V[js], mj = b.m[js];
+        const T uij = (T)(ui - uvj.x), vij = (T)(vi - uvj.y);
+        const T dpij = (T)(pi - pj);
+        const T Vraw = fj4.x, mj = fj4.w;
         const T Vj = GH ? fabs(Vraw) : Vraw;
-        const T Pj = (-dpij - dpav) * b.B[js];
+        const T Pj = (-dpij - dpav) * fj4.y;
         const T nuj = aecs8 * (T)hj;
         const T nuij = T(4) * nui * nuj * rcp<T>(nui + nuj);
         const T rdotg = T(0.5) * (dwi + dwj) * r;
@@ -331,11 +351,11 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
         const T gf = mj * (Pi * fi + Pj * fj);
         gx += gf * dxT;
         gy += gf * dyT;
-        const T cv = mj * nu4 * rcp<T>(rhoi + b.rho[js]) * rdotg * iden;
+        const T cv = mj * nu4 * rcp<T>(rhoi + fj4.z) * rdotg * iden;
         if constexpr (GH) {
             if (solid_i || Vraw < T(0)) {
-                const double ugj = Vraw < T(0) ? ugs[js] : uj;
-                const double vgj = Vraw < T(0) ? vgs[js] : vj;
+                const double ugj = Vraw < T(0) ? ugs[js] : uvj.x;
+                const double vgj = Vraw < T(0) ? vgs[js] : uvj.y;
                 vx += cv * (T)(ugi - ugj);
                 vy += cv * (T)(vgi - vgj);
             } else {
@@ -349,9 +369,12 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     };
     const int cnt = nl.cnt[s];
     if (cnt <= nl.K) {
-        for_each_listed(g, nv, nl, s, cnt, xi, yi, hi, body);
+        for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
     } else {
-        for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), body);
+        for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]),
+                          [&](int js, double dx, double dy, double r2, double hj) {
+                              body(js, dx, dy, r2, hj, pa[js].w);
+                          });
     }
     const T beta = b.beta[s];
     const T ib = beta > T(0) ? T(1) / beta : T(0);
@@ -482,26 +505,28 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
                            cf.body_force[1] - cf.wall_accel[1]);
         LAUNCHCHK(c, "boundary");
     }
+    using T4 = typename Vec4<T>::type;
+    T4* pf = (T4*)w.pf;
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
-                       cf.mass_q, nv.hs, w.us, w.vs, b.ps, b.m, b.ih,
+                       cf.mass_q, nv.xs, nv.ys, nv.hs, w.pa, w.puv, b.m,
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
                        w.ugs, w.vgs, kind);
     LAUNCHCHK(c, "gather_state");
     prof_begin(c, SPH_PROF_PASS_A);
     hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       cf.rho0, aout, w.r_dxs, w.r_dys, kind);
+                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B);
     if (gh)
         hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           (const double*)w.us, (const double*)w.vs, (const double*)w.ugs,
-                           (const double*)w.vgs, P, dpdt, dudt, dvdt);
+                           (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                           (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt);
     else
         hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           (const double*)w.us, (const double*)w.vs, (const double*)nullptr,
-                           (const double*)nullptr, P, dpdt, dudt, dvdt);
+                           (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                           (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");
     if (c->pair_acc) {

@@ -371,6 +371,10 @@ __device__ __forceinline__ double lane_bcast(double v, int k)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
 // Column-major neighbour list written by pass A and read by pass B:
 // entry k of sorted particle s is idx[k * stride + s] (coalesced across a
 // wave); rows longer than K fall back to the traversal.
@@ -421,3 +425,37 @@ __device__ __forceinline__ void for_each_listed(const Grid& g, const NbrView& nv
         test(js, mi_axis(g, 0, xi - nv.xs[js]), mi_axis(g, 1, yi - nv.ys[js]), nv.hs[js]);
     }
 }
+
+// Row s of the list against the packed {x, y, h, p} records, four
+// neighbours per iteration; body(js, dx, dy, r2, hj, pj).  Same exact
+// predicate as for_each_listed.
+template <class F>
+__device__ __forceinline__ void for_each_listed_packed(const Grid& g, const double4* __restrict__ pa,
+                                                       const NbrList& nl, int s, int cnt,
+                                                       double xi, double yi, double hi, F&& body)
+{
+    const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+    auto test = [&](int js, const double4& a) __attribute__((always_inline)) {
+        const double dx = mi_axis(g, 0, xi - a.x);
+        const double dy = mi_axis(g, 1, yi - a.y);
+        const double r2 = dx * dx + dy * dy;
+        const double rj3 = 3.0 * a.z;
+        if (r2 < fmax(ri2, rj3 * rj3)) body(js, dx, dy, r2, a.z, a.w);
+    };
+    int k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+        int j[4];
+        double4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = nl.idx[(int64_t)(k + u) * nl.stride + s];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) test(j[u], a[u]);
+    }
+    for (; k < cnt; ++k) {
+        const int js = nl.idx[(int64_t)k * nl.stride + s];
+        test(js, pa[js]);
+    }
+}
+

@@ -89,6 +89,12 @@ struct Work {
     float4* pk;                 // sorted (x - org, y - org, padded radius^2) in FP32
     double *ug, *vg;            // viscous-term velocity (ghost velocity of walls), slot order
     double *ugs, *vgs;          // the same, sorted order
+    // what the rate passes gather per neighbour, packed into 16-byte loads
+    // (sorted order): {x, y, h, p}, {u, v}, and {V, B, rho, m} in the pair
+    // precision (float4 or double4) written by pass A for pass B
+    double4* pa;
+    double2* puv;
+    void* pf;
     int32_t* list_flag;         // [0]: rebuild needed (moved / h changed / overflow)
     int32_t lean;               // 1: the adaptation buffers below are not carved
     int64_t capacity;
