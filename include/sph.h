@@ -78,7 +78,7 @@ typedef struct sph_config {
     double wall_accel[2];   /* a_w of eq. (bc-pre): acceleration of the solid
                                particles (0 for a stationary body) */
     int32_t list_k;         /* columns of the rate passes' neighbour list
-                               (0 = 160); longer rows fall back to a cell walk */
+                               (0 = 256); longer rows fall back to a cell walk */
     int32_t lean;           /* 1: workspace without the adaptation buffers;
                                sph_adapt, sph_bg_update, sph_mref_lookup and
                                sph_inout then return SPH_E_INVAL */

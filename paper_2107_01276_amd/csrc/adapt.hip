@@ -368,11 +368,15 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
         const int j = col[k];
         const double dx = mi_axis(g, 0, xi - s.x[j]);
         const double dy = mi_axis(g, 1, yi - s.y[j]);
-        const double r = sqrt(dx * dx + dy * dy);
+        const double r2 = dx * dx + dy * dy;
+        const double hj = s.h[j];
+        const double RR = 3.0 * (hi > hj ? hi : hj);
+        if (!(r2 < RR * RR)) continue;  // the row may be a superset of N(i)
+        const double r = sqrt(r2);
         if (r <= 0.0) continue;
         const double mj = (double)s.mq[j] * q;
         // shifting term at h_ij
-        const double hij = 0.5 * (hi + s.h[j]);
+        const double hij = 0.5 * (hi + hj);
         const double wr = kern_f<double>(r / hij) / fxi;
         const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
         const double t = coef * (kern_dw64(r, hij) / r);
@@ -419,8 +423,12 @@ __global__ __launch_bounds__(256) void k_shift_apply(Grid g, int n, FluidState s
     s.p[i] = np[i];
 }
 
-__global__ __launch_bounds__(256) void k_hupdate(int n, const int64_t* __restrict__ rp,
+// h = C sqrt(m_bar / rho) with m_bar the mean mass over N(i), self
+// included; the row may be a superset of N(i), filtered by the predicate.
+__global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ y,
                                                  const int64_t* __restrict__ mq,
                                                  const double* __restrict__ rho,
                                                  const int32_t* __restrict__ kind, double q,
@@ -433,9 +441,20 @@ __global__ __launch_bounds__(256) void k_hupdate(int n, const int64_t* __restric
         nh[i] = h[i];
         return;
     }
+    const double xi = x[i], yi = y[i], hi = h[i];
     double sm = 0.0;
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) sm += (double)mq[col[k]] * q;
-    const double mbar = sm / (double)(rp[i + 1] - rp[i]);
+    int64_t cnt = 0;
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+        const int j = col[k];
+        const double dx = mi_axis(g, 0, xi - x[j]);
+        const double dy = mi_axis(g, 1, yi - y[j]);
+        const double hj = h[j];
+        const double RR = 3.0 * (hi > hj ? hi : hj);
+        if (!(dx * dx + dy * dy < RR * RR)) continue;
+        sm += (double)mq[j] * q;
+        ++cnt;
+    }
+    const double mbar = sm / (double)cnt;
     nh[i] = hdx * sqrt(mbar / rho[i]);
 }
 
@@ -447,13 +466,14 @@ __global__ void k_copy_f64(int n, const double* __restrict__ a, double* b)
 
 // Builds the neighbour structure of (x, y, h) and exports CSR to the
 // internal buffers (rows ascending).
-static int internal_csr(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+static int internal_csr(sph_ctx* c, int n, const double* x, const double* y, const double* h,
+                        double sf = 1.0)
 {
     Work& w = c->w;
     int rc = nbr_build(c, n, x, y, h);
     if (rc) return rc;
     int64_t nnz = 0;
-    rc = nbr_export_csr(c, n, w.rp_tmp, w.col_tmp, w.col_cap, &nnz);
+    rc = nbr_export_csr(c, n, w.rp_tmp, w.col_tmp, w.col_cap, &nnz, sf);
     if (rc == SPH_E_CAPACITY)
         set_err(c, "internal neighbour list needs %lld entries (limit %lld)", (long long)nnz,
                 (long long)w.col_cap);
@@ -571,10 +591,26 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         n = nkeep;
     }
 
+    // One CSR serves every shift and the h update: each shift moves a
+    // particle by at most 0.25 h (the limiter), so after k shifts a pair's
+    // distance changed by at most 0.5 k max(h_i, h_j) and every later
+    // neighbour pair lies within (1 + k/6) of the support radius now.  The
+    // kernels re-apply the exact predicate to the ascending rows, so the
+    // sums are those of a fresh neighbour list.  If that superset does not
+    // fit the internal buffer, each pass builds its own exact list.
+    bool super = false;
+    if (n > 0) {
+        const double sf = 1.0 + cf.shift_iters / 6.0 + 1e-9;
+        rc = internal_csr(c, n, ps->x, ps->y, ps->h, sf);
+        if (rc == SPH_OK) super = true;
+        else if (rc != SPH_E_CAPACITY) return rc;
+    }
     for (int it = 0; it < cf.shift_iters; ++it) {
         if (n == 0) break;
-        rc = internal_csr(c, n, ps->x, ps->y, ps->h);
-        if (rc) return rc;
+        if (!super) {
+            rc = internal_csr(c, n, ps->x, ps->y, ps->h);
+            if (rc) return rc;
+        }
         unsigned nb = (unsigned)cdiv(n, 256);
         hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.rp_tmp,
                            w.col_tmp, cf.mass_q, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2],
@@ -584,11 +620,14 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         LAUNCHCHK(c, "shift");
     }
     if (n > 0) {
-        rc = internal_csr(c, n, ps->x, ps->y, ps->h);
-        if (rc) return rc;
+        if (!super) {
+            rc = internal_csr(c, n, ps->x, ps->y, ps->h);
+            if (rc) return rc;
+        }
         unsigned nb = (unsigned)cdiv(n, 256);
-        hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, n, w.rp_tmp, w.col_tmp, ps->mq,
-                           ps->rho, ps->kind, cf.mass_q, cf.hdx, ps->h, w.tmp_d[0]);
+        hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, c->grid, n, w.rp_tmp, w.col_tmp,
+                           ps->x, ps->y, ps->mq, ps->rho, ps->kind, cf.mass_q, cf.hdx, ps->h,
+                           w.tmp_d[0]);
         hipLaunchKernelGGL(k_copy_f64, dim3(nb), dim3(256), 0, c->stream, n, w.tmp_d[0], ps->h);
         LAUNCHCHK(c, "hupdate");
     }

@@ -10,7 +10,7 @@
 
 #define SPH_VERSION 10000
 #define COL_PER_PARTICLE 160
-#define NL_K 160
+#define NL_K 256
 
 void set_err(sph_ctx* c, const char* fmt, ...)
 {

@@ -695,7 +695,8 @@ int nbr_build_list(sph_ctx* c, int n, double skin)
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_csr_fill(Grid g, NbrView nv, int n,
-                                                  const int64_t* __restrict__ rp, int32_t* col)
+                                                  const int64_t* __restrict__ rp, int32_t* col,
+                                                  double sf)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -703,7 +704,7 @@ __global__ __launch_bounds__(256) void k_csr_fill(Grid g, NbrView nv, int n,
     int li = key_level(g, nv.keys[s]);
     int64_t k = rp[nv.perm[s]];
     for_each_neighbor(g, nv, xi, yi, hi, li,
-                      [&](int js, double, double, double, double) { col[k++] = nv.perm[js]; });
+                      [&](int js, double, double, double, double) { col[k++] = nv.perm[js]; }, sf);
 }
 
 // One wave per row: bitonic sort across the 64 lanes for rows of <= 64
@@ -758,7 +759,8 @@ __global__ void k_sort_long_rows(const int64_t* __restrict__ rp, int32_t* col,
 // flag[0] is set when a row has more than K entries.
 __global__ __launch_bounds__(256) void k_csr_stage(Grid g, NbrView nv, int n, int K,
                                                    int32_t* __restrict__ stage,
-                                                   int64_t* __restrict__ cnt, int32_t* flag)
+                                                   int64_t* __restrict__ cnt, int32_t* flag,
+                                                   double sf)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -770,7 +772,7 @@ __global__ __launch_bounds__(256) void k_csr_stage(Grid g, NbrView nv, int n, in
     for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double, double, double, double) {
         if (k < K) row[k] = nv.perm[js];
         ++k;
-    });
+    }, sf);
     cnt[slot] = k;
     if (k > K) flag[0] = 1;
 }
@@ -839,7 +841,8 @@ __global__ __launch_bounds__(256) void k_csr_sort_staged(int n, int K, const int
         wave_sort_row<4>(src, len, col + beg, lane);
 }
 
-int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz)
+int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz,
+                   double sf)
 {
     Work& w = c->w;
     const Grid& g = c->grid;
@@ -850,7 +853,7 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     if (n > 0) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.status, (int64_t)4);
         hipLaunchKernelGGL(k_csr_stage, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv,
-                           n, K, w.nl_idx, w.cnt64, w.status + 2);
+                           n, K, w.nl_idx, w.cnt64, w.status + 2, sf);
         LAUNCHCHK(c, "csr_stage");
     }
     int rc = scan_exclusive_i64(c, w.cnt64, row_ptr, n);
@@ -874,7 +877,7 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     }
     // some row is longer than the staging width: traverse again into the CSR
     hipLaunchKernelGGL(k_csr_fill, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv, n,
-                       row_ptr, col);
+                       row_ptr, col, sf);
     hipLaunchKernelGGL(k_sort_rows, dim3((unsigned)cdiv(n, 4)), dim3(256), 0, c->stream, n, row_ptr,
                        col, w.long_rows, w.status);
     hipLaunchKernelGGL(k_sort_long_rows, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream,

@@ -138,7 +138,10 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
 NbrView nbr_view(sph_ctx* c);
 int nbr_build_list(sph_ctx* c, int n, double skin);
 int nbr_regather(sph_ctx* c, int n, const double* x, const double* y, const double* h);
-int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz);
+// Rows hold every j with |r_i - r_j| < sf 3 max(h_i, h_j) (sf = 1: the
+// neighbour set), ascending.
+int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz,
+                   double sf = 1.0);
 int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void grid_setup(const sph_config* cfg, Grid* g);
 size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g);
