@@ -78,15 +78,18 @@ static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, 
 // m_ref lookup
 // ---------------------------------------------------------------------------
 
+// Queries run in `order` (a spatial order of the fluid slots) when given.
 __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ y,
                                                      const double* __restrict__ h,
                                                      const double* __restrict__ bmref,
-                                                     double* mref_out, int32_t* none)
+                                                     double* mref_out, int32_t* none,
+                                                     const int32_t* __restrict__ order)
 {
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = order ? order[t] : t;
     const double xi = x[i], yi = y[i], hi = h[i];
     const int li = level_of(g, hi);
     double mn = 0.0;
@@ -129,11 +132,19 @@ static int mref_lookup_into(sph_ctx* c, const sph_particles* ps, const sph_backg
     Work& w = c->w;
     int n = (int)ps->n, nb = (int)bg->n;
     if (n == 0 || nb == 0) return SPH_OK;
+    // the fluid's last sorted order (if it still covers these slots) keeps
+    // neighbouring queries together; the background build overwrites it
+    const int32_t* order = nullptr;
+    if (c->built_n == n) {
+        HIPCHK(c, hipMemcpyAsync(w.idx_b, w.vals_a, sizeof(int32_t) * (size_t)n,
+                                 hipMemcpyDeviceToDevice, c->stream));
+        order = w.idx_b;
+    }
     int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
     if (rc) return rc;
     NbrView nv = nbr_view(c);
     hipLaunchKernelGGL(k_mref_lookup, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
-                       nv, n, ps->x, ps->y, ps->h, bg->mref, mref_out, w.flag);
+                       nv, n, ps->x, ps->y, ps->h, bg->mref, mref_out, w.flag, order);
     hipLaunchKernelGGL(k_mref_nearest, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
                        n, ps->x, ps->y, w.flag, nb, bg->x, bg->y, bg->mref, mref_out);
     LAUNCHCHK(c, "mref_lookup");
@@ -836,21 +847,38 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
 // Inlet / outlet update (section 2.2)
 // ---------------------------------------------------------------------------
 
-__global__ void k_io_zero(int32_t* cnt) { cnt[0] = 0; }
+__global__ void k_io_zero(int32_t* cnt) { cnt[0] = 0; cnt[1] = 0; cnt[2] = 0; }
 
+// Flags of the update and their counts: cnt[0] fluid -> outlet, cnt[1]
+// inlet copies, cnt[2] deletions (one atomic per wave and counter).
 __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restrict__ x,
                                                   const int32_t* __restrict__ kind,
                                                   sph_inout_params io, int32_t* keep, int32_t* app,
-                                                  int32_t* n_out)
+                                                  int32_t* cnt)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = i < n ? kind[i] : -1;
     const double xi = i < n ? x[i] : 0.0;
-    const uint64_t b = __ballot(k == SPH_FLUID && xi >= io.x_out);
-    if (__lane_id() == 0 && b) atomicAdd(n_out, (int32_t)__popcll(b));
+    const bool to_out = k == SPH_FLUID && xi >= io.x_out;
+    const bool ap = k == SPH_INLET && xi >= io.x_in;
+    const bool del = k == SPH_OUTLET && xi >= io.x_out + io.len_out;
+    const uint64_t b0 = __ballot(to_out), b1 = __ballot(ap), b2 = __ballot(del);
+    if (__lane_id() == 0) {
+        if (b0) atomicAdd(cnt + 0, (int32_t)__popcll(b0));
+        if (b1) atomicAdd(cnt + 1, (int32_t)__popcll(b1));
+        if (b2) atomicAdd(cnt + 2, (int32_t)__popcll(b2));
+    }
     if (i >= n) return;
-    keep[i] = !(k == SPH_OUTLET && xi >= io.x_out + io.len_out);
-    app[i] = k == SPH_INLET && xi >= io.x_in;
+    keep[i] = !del;
+    app[i] = ap;
+}
+
+// Kind changes only (no copy, no deletion): fluid past x_out becomes outlet.
+__global__ __launch_bounds__(256) void k_io_kinds(int n, const double* __restrict__ x, int32_t* kind,
+                                                  sph_inout_params io)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && kind[i] == SPH_FLUID && x[i] >= io.x_out) kind[i] = SPH_OUTLET;
 }
 
 // Kept slot i goes to rank_keep[i] with its new kind; an inlet particle
@@ -915,16 +943,31 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     // scratch that the neighbour structure does not use, so that an update
     // which keeps every slot leaves the rate passes' list valid
     int32_t *keep = w.flag, *rk = w.idx_a, *app = w.tmp_i32[1], *ra = w.closest;
-    int32_t* n_out = w.status + 8;
-    hipLaunchKernelGGL(k_io_zero, dim3(1), dim3(1), 0, c->stream, n_out);
+    int32_t* cnt = w.status + 8;
+    hipLaunchKernelGGL(k_io_zero, dim3(1), dim3(1), 0, c->stream, cnt);
     hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
-                       (const int32_t*)ps->kind, *io, keep, app, n_out);
+                       (const int32_t*)ps->kind, *io, keep, app, cnt);
     LAUNCHCHK(c, "io_flags");
-    int32_t nkeep = 0, na = 0, nto = 0;
+    int32_t h3[3] = {0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int32_t nto = h3[0];
+    if (h3[1] == 0 && h3[2] == 0) {
+        // no slot changes: at most kinds change, the neighbour list stays valid
+        map->n_to_outlet = nto;
+        if (nto > 0) {
+            hipLaunchKernelGGL(k_io_kinds, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
+                               ps->kind, *io);
+            LAUNCHCHK(c, "io_kinds");
+        }
+        hipLaunchKernelGGL(k_io_iota, dim3(nb), dim3(256), 0, c->stream, n, map->origin);
+        LAUNCHCHK(c, "io_iota");
+        return SPH_OK;
+    }
+    int32_t nkeep = 0, na = 0;
     int rc = compact_ranks(c, n, keep, rk, &nkeep);
     if (rc) return rc;
-    HIPCHK(c, hipMemcpyAsync(&nto, n_out, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    rc = compact_ranks(c, n, app, ra, &na);  // synchronises: nto is on the host after it
+    rc = compact_ranks(c, n, app, ra, &na);
     if (rc) return rc;
     map->n_required = (int64_t)nkeep + na;
     if (map->n_required > ps->capacity) {
@@ -935,12 +978,6 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     map->n_to_outlet = nto;
     map->n_appended = na;
     map->n_deleted = n - nkeep;
-    if (na == 0 && nkeep == n && nto == 0) {
-        // nothing changes: identity map
-        hipLaunchKernelGGL(k_io_iota, dim3(nb), dim3(256), 0, c->stream, n, map->origin);
-        LAUNCHCHK(c, "io_iota");
-        return SPH_OK;
-    }
     FluidState s{ps->x, ps->y, ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mref,
                  ps->mq, map->origin, ps->kind, nullptr};
     FluidState d = tmp_state(c, true);
