@@ -145,10 +145,10 @@ def count_pairs(ctx, P):
     return int(col.numel()) - P.n
 
 
-def prepare(SPH, W, s, bg, prec, capacity):
+def prepare(SPH, W, s, bg, prec, capacity, skin=0.1):
     h_hi = max(float(s["h"].max()), float(bg["h"].max()))
     cfg = SPH.config_for(s["domain"], s["params"], float(s["h"].min()), h_hi, precision=prec,
-                         mass_q=s["mass_q"])
+                         mass_q=s["mass_q"], list_skin=skin)
     ctx = SPH.Context(cfg, capacity)
     P = SPH.Particles.from_arrays(s, capacity)
     B = SPH.Background.from_arrays(bg, bg["x"].size)
@@ -207,10 +207,30 @@ def main():
     dt = s["dt"]
     cap = int(1.6 * n0)
 
+    # list schedule picked by timing the step loop itself (untimed here)
+    from paper_2107_01276_amd import tune
+
+    def maker(prec):
+        def make(skin):
+            ctx, P, B = prepare(SPH, W, s, bg, prec, cap, skin)
+            return {"ctx": ctx, "P": P, "B": B, "k": 0}
+        return make
+
+    def run_steps(st, k):
+        for _ in range(k):
+            st["ctx"].step(st["P"], dt, 1)
+            st["ctx"].inout(st["P"], s["io"])
+            st["k"] += 1
+            if args.adapt_every and st["k"] % args.adapt_every == 0:
+                st["ctx"].adapt(st["P"], st["B"])
+
+    tuning = {}
     results = {}
     for name, prec, steps in (("fp32", SPH.SPH_FP32, args.steps),
                               ("fp64", SPH.SPH_FP64, args.fp64_steps)):
-        ctx, P, B = prepare(SPH, W, s, bg, prec, cap)
+        tuning[name] = tune.tune_list_skin(maker(prec), run_steps,
+                                           steps=2 * max(args.adapt_every, 10))
+        ctx, P, B = prepare(SPH, W, s, bg, prec, cap, tuning[name]["best"])
         ms, prof, pairs = run(ctx, P, B, dt, steps, args.warmup, args.adapt_every, torch, s["io"])
         ms_step = ms / steps
         results[name] = {"ms_per_step": ms_step, "pairs": pairs, "n": P.n, "prof": prof,
@@ -282,6 +302,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "serving": serve,
+        "list_skin_tuning": tuning,
     }
     print(json.dumps(out))
 

@@ -359,10 +359,14 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
                                                       const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col, double q,
                                                       double rho0, double* ddx_o, double* ddy_o,
-                                                      double* nu_o, double* nv_o, double* np_o)
+                                                      double* nu_o, double* nv_o, double* np_o,
+                                                      const int32_t* __restrict__ order)
 {
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    // rows are taken in `order` (a spatial order of the slots) when given,
+    // so that a wave's neighbours share cache lines
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = order ? order[t] : t;
     if (s.kind && s.kind[i] != SPH_FLUID) {
         ddx_o[i] = 0.0; ddy_o[i] = 0.0;
         nu_o[i] = s.u[i]; nv_o[i] = s.v[i]; np_o[i] = s.p[i];
@@ -444,10 +448,11 @@ __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* _
                                                  const double* __restrict__ rho,
                                                  const int32_t* __restrict__ kind, double q,
                                                  double hdx, const double* __restrict__ h,
-                                                 double* nh)
+                                                 double* nh, const int32_t* __restrict__ order)
 {
-    int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int i = order ? order[t] : t;
     if (kind && kind[i] != SPH_FLUID) {
         nh[i] = h[i];
         return;
@@ -623,9 +628,10 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             if (rc) return rc;
         }
         unsigned nb = (unsigned)cdiv(n, 256);
+        // the sorted order of the last build (slots unchanged since)
         hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.rp_tmp,
                            w.col_tmp, cf.mass_q, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2],
-                           w.tmp_d[3], w.tmp_d[4]);
+                           w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
         hipLaunchKernelGGL(k_shift_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.tmp_d[0],
                            w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4]);
         LAUNCHCHK(c, "shift");
@@ -638,7 +644,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         unsigned nb = (unsigned)cdiv(n, 256);
         hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, c->grid, n, w.rp_tmp, w.col_tmp,
                            ps->x, ps->y, ps->mq, ps->rho, ps->kind, cf.mass_q, cf.hdx, ps->h,
-                           w.tmp_d[0]);
+                           w.tmp_d[0], (const int32_t*)w.vals_a);
         hipLaunchKernelGGL(k_copy_f64, dim3(nb), dim3(256), 0, c->stream, n, w.tmp_d[0], ps->h);
         LAUNCHCHK(c, "hupdate");
     }
