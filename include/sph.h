@@ -262,9 +262,10 @@ int sph_bg_update_solution(sph_ctx *ctx, sph_background *bg, const sph_particles
  * particle with x >= x_out becomes an outlet particle; an outlet particle
  * with x >= x_out + len_out is deleted.  Deleted slots are removed by stable
  * compaction; copies follow in ascending order of their source slot.
- * Requires ps->kind.  Two-phase: SPH_E_CAPACITY with map->n_required set
- * and the state untouched when the result exceeds ps->capacity.  Updates
- * ps->n.  Synchronises. */
+ * Requires ps->kind.  map->origin is written only when slots change
+ * (n_appended or n_deleted > 0).  Two-phase: SPH_E_CAPACITY with
+ * map->n_required set and the state untouched when the result exceeds
+ * ps->capacity.  Updates ps->n.  Synchronises. */
 int sph_inout(sph_ctx *ctx, sph_particles *ps, const sph_inout_params *io, sph_inout_map *map);
 
 /* ---- Serving pool: continuous batching of independent simulations ------

@@ -417,7 +417,10 @@ class Context:
             return info
         self._check(rc)
         P.n = int(ps.n)
-        info["origin"] = origin[:P.n]
+        if info["appended"] or info["deleted"]:
+            info["origin"] = origin[:P.n]
+        else:  # no slot moved: the map is the identity (the library leaves it unwritten)
+            info["origin"] = torch.arange(P.n, dtype=torch.int64, device=self.device)
         return info
 
     def bg_update(self, bg: Background, solids: Particles, passes: int, phi=None,

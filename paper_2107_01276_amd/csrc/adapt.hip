@@ -853,14 +853,13 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
 // Inlet / outlet update (section 2.2)
 // ---------------------------------------------------------------------------
 
-__global__ void k_io_zero(int32_t* cnt) { cnt[0] = 0; cnt[1] = 0; cnt[2] = 0; }
-
-// Flags of the update and their counts: cnt[0] fluid -> outlet, cnt[1]
-// inlet copies, cnt[2] deletions (one atomic per wave and counter).
+// Flags of the update and their counts, added to cumulative counters (the
+// host takes differences): cnt[0] fluid -> outlet, cnt[1] inlet copies,
+// cnt[2] deletions (one atomic per wave and counter).
 __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restrict__ x,
                                                   const int32_t* __restrict__ kind,
                                                   sph_inout_params io, int32_t* keep, int32_t* app,
-                                                  int32_t* cnt)
+                                                  unsigned long long* cnt)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = i < n ? kind[i] : -1;
@@ -870,9 +869,9 @@ __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restric
     const bool del = k == SPH_OUTLET && xi >= io.x_out + io.len_out;
     const uint64_t b0 = __ballot(to_out), b1 = __ballot(ap), b2 = __ballot(del);
     if (__lane_id() == 0) {
-        if (b0) atomicAdd(cnt + 0, (int32_t)__popcll(b0));
-        if (b1) atomicAdd(cnt + 1, (int32_t)__popcll(b1));
-        if (b2) atomicAdd(cnt + 2, (int32_t)__popcll(b2));
+        if (b0) atomicAdd(cnt + 0, (unsigned long long)__popcll(b0));
+        if (b1) atomicAdd(cnt + 1, (unsigned long long)__popcll(b1));
+        if (b2) atomicAdd(cnt + 2, (unsigned long long)__popcll(b2));
     }
     if (i >= n) return;
     keep[i] = !del;
@@ -932,12 +931,6 @@ __global__ __launch_bounds__(256) void k_io_copy(int n, FluidState d, FluidState
     origin[t] = d.origin[t];
 }
 
-__global__ __launch_bounds__(256) void k_io_iota(int n, int64_t* origin)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) origin[i] = i;
-}
-
 int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
 {
     Work& w = c->w;
@@ -949,25 +942,26 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     // scratch that the neighbour structure does not use, so that an update
     // which keeps every slot leaves the rate passes' list valid
     int32_t *keep = w.flag, *rk = w.idx_a, *app = w.tmp_i32[1], *ra = w.closest;
-    int32_t* cnt = w.status + 8;
-    hipLaunchKernelGGL(k_io_zero, dim3(1), dim3(1), 0, c->stream, cnt);
+    unsigned long long* cnt = w.ctr;
     hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
                        (const int32_t*)ps->kind, *io, keep, app, cnt);
     LAUNCHCHK(c, "io_flags");
-    int32_t h3[3] = {0, 0, 0};
+    unsigned long long h3[3] = {0, 0, 0};
     HIPCHK(c, hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const int32_t nto = h3[0];
-    if (h3[1] == 0 && h3[2] == 0) {
-        // no slot changes: at most kinds change, the neighbour list stays valid
+    const int32_t nto = (int32_t)(h3[0] - c->io_last[0]);
+    const int32_t nap = (int32_t)(h3[1] - c->io_last[1]);
+    const int32_t ndel = (int32_t)(h3[2] - c->io_last[2]);
+    for (int k = 0; k < 3; ++k) c->io_last[k] = h3[k];
+    if (nap == 0 && ndel == 0) {
+        // no slot changes (origin is left as it is): at most kinds change,
+        // and the neighbour list stays valid
         map->n_to_outlet = nto;
         if (nto > 0) {
             hipLaunchKernelGGL(k_io_kinds, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
                                ps->kind, *io);
             LAUNCHCHK(c, "io_kinds");
         }
-        hipLaunchKernelGGL(k_io_iota, dim3(nb), dim3(256), 0, c->stream, n, map->origin);
-        LAUNCHCHK(c, "io_iota");
         return SPH_OK;
     }
     int32_t nkeep = 0, na = 0;

@@ -51,6 +51,7 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->hmax_bits = (unsigned long long*)take(8 * SPH_MAXL);
     w->lcount = (int32_t*)take(4 * SPH_MAXL);
     w->status = (int32_t*)take(4 * 64);
+    w->ctr = (unsigned long long*)take(8 * 8);
     w->long_rows = (int32_t*)take(4 * C);
     w->xs = (double*)take(8 * C);
     w->ys = (double*)take(8 * C);
@@ -131,6 +132,13 @@ extern "C" size_t sph_workspace_bytes(const sph_config* cfg, int64_t capacity)
     return carve(&w, nullptr, g, capacity, cfg->lean, cfg->list_k > 0 ? cfg->list_k : NL_K);
 }
 
+__global__ void k_init_counters(int32_t* status, unsigned long long* ctr)
+{
+    const int t = threadIdx.x;
+    if (t < 64) status[t] = 0;
+    if (t < 8) ctr[t] = 0ull;
+}
+
 extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspace,
                           size_t workspace_bytes, void* stream, sph_ctx** out)
 {
@@ -156,6 +164,11 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->prof[SPH_PROF_LIST].name = "list";
     c->skin = cfg->list_skin;
     c->list_valid = 0;
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c->stream, c->w.status, c->w.ctr);
+    if (hipGetLastError() != hipSuccess) {
+        free(c);
+        return SPH_E_DEVICE;
+    }
     *out = c;
     return SPH_OK;
 }

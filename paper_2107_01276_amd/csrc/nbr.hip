@@ -451,19 +451,6 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
     return SPH_OK;
 }
 
-// Refreshes the sorted positions for the current state without sorting
-// again (the order of the last build is kept).
-int nbr_regather(sph_ctx* c, int n, const double* x, const double* y, const double* h)
-{
-    Work& w = c->w;
-    if (n > 0) {
-        hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
-                           w.vals_a, x, y, h, w.xs, w.ys, w.hs);
-        LAUNCHCHK(c, "regather");
-    }
-    return SPH_OK;
-}
-
 NbrView nbr_view(sph_ctx* c)
 {
     NbrView v;

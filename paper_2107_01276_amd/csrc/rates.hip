@@ -52,9 +52,10 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ p,
                                                       const int64_t* __restrict__ mq, double mass_q,
-                                                      const double* __restrict__ xs,
-                                                      const double* __restrict__ ys,
-                                                      const double* __restrict__ hs, double4* pa,
+                                                      const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ h, double* xs,
+                                                      double* ys, double* hs, double4* pa,
                                                       double2* puv, T* ms,
                                                       const double* __restrict__ ug,
                                                       const double* __restrict__ vg, double* ugs,
@@ -63,7 +64,12 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
-    pa[s] = make_double4(xs[s], ys[s], hs[s], p[i]);
+    // the sorted positions too: a reused list skips the neighbour build
+    const double xi = x[i], yi = y[i], hi = h[i];
+    xs[s] = xi;
+    ys[s] = yi;
+    hs[s] = hi;
+    pa[s] = make_double4(xi, yi, hi, p[i]);
     puv[s] = make_double2(u[i], v[i]);
     ms[s] = (T)((double)mq[i] * mass_q);
     if (ug) {
@@ -114,22 +120,30 @@ __device__ __forceinline__ double wave_sum_d(double v)
 
 // One wave per listed boundary particle; a fixed grid strides over the list
 // (every wave leaves once the list is exhausted).
+// Positions are read from the slot arrays (the sorted copies are refreshed
+// later in the evaluation).  `count` was filled by k_bmark; `next_count`,
+// the counter of the following evaluation, is cleared here.
 __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl, int n,
                                                   const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ count,
+                                                  int32_t* next_count,
                                                   const int32_t* __restrict__ kind,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ h,
                                                   const double* __restrict__ rho, double* u,
                                                   double* v, double* p, double* ug, double* vg,
                                                   double gx, double gy)
 {
     const int lane = __lane_id();
     const int nw = (gridDim.x * blockDim.x) >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0) next_count[0] = 0;
     const int total = *count;
     for (int e = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < total; e += nw) {
         const int s = list[e];
         const int b = nv.perm[s];
         const int kb = kind[b];
-        const double xb = nv.xs[s], yb = nv.ys[s], hb = nv.hs[s];
+        const double xb = x[b], yb = y[b], hb = h[b];
         double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
         auto body = [&](int js, double dx, double dy, double r2, double hj) {
             const int f = nv.perm[js];
@@ -147,15 +161,27 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
             const double rb3 = 3.0 * hb, rb2 = rb3 * rb3;
             for (int k = lane; k < cnt; k += 64) {
                 const int js = nl.idx[(int64_t)k * nl.stride + s];
-                const double dx = mi_axis(g, 0, xb - nv.xs[js]);
-                const double dy = mi_axis(g, 1, yb - nv.ys[js]);
-                const double hj = nv.hs[js];
+                const int j = nv.perm[js];
+                const double dx = mi_axis(g, 0, xb - x[j]);
+                const double dy = mi_axis(g, 1, yb - y[j]);
+                const double hj = h[j];
                 const double r2 = dx * dx + dy * dy;
                 const double rj3 = 3.0 * hj;
                 if (r2 < fmax(rb2, rj3 * rj3)) body(js, dx, dy, r2, hj);
             }
         } else if (lane == 0) {
-            for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[s]), body);
+            // a row longer than the list: walk the cells (the sorted
+            // positions are those of the last build, refreshed here)
+            for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[s]),
+                              [&](int js, double, double, double, double) {
+                                  const int j = nv.perm[js];
+                                  const double dx = mi_axis(g, 0, xb - x[j]);
+                                  const double dy = mi_axis(g, 1, yb - y[j]);
+                                  const double hj = h[j];
+                                  const double r2 = dx * dx + dy * dy;
+                                  const double rr = 3.0 * (hb > hj ? hb : hj);
+                                  if (r2 < rr * rr) body(js, dx, dy, r2, hj);
+                              });
         }
         S = wave_sum_d(S);
         su = wave_sum_d(su);
@@ -186,8 +212,6 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
         vg[b] = vb;
     }
 }
-
-__global__ void k_zero_count(int32_t* c) { c[0] = 0; }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
@@ -457,8 +481,9 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
         reuse = (f == 0);
     }
     if (reuse) {
+        // the sorted positions are refreshed by the evaluation's gather
         c->list_reuses++;
-        return nbr_regather(c, n, x, y, h);
+        return SPH_OK;
     }
     int rc = nbr_build(c, n, x, y, h);
     if (rc || n == 0) return rc;
@@ -494,21 +519,24 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
     if (gh) {
         int32_t* blist = (int32_t*)w.ugs;  // free until the gather below fills it
-        int32_t* bcount = w.status + 16;
-        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, c->stream, bcount);
+        // two counters used alternately: each evaluation's boundary kernel
+        // clears the other one, so no separate clearing launch is needed
+        int32_t* bcount = w.status + 16 + c->bparity;
+        int32_t* bnext = w.status + 16 + (c->bparity ^ 1);
+        c->bparity ^= 1;
         hipLaunchKernelGGL(k_bmark, dim3(nb), dim3(256), 0, c->stream, n, (const int32_t*)nv.perm, kind,
                            blist, bcount);
         const unsigned nbw = (unsigned)(nb < 512 ? nb : 512);
         hipLaunchKernelGGL(k_boundary, dim3(nbw), dim3(256), 0, c->stream, c->grid, nv, nl, n,
-                           (const int32_t*)blist, (const int32_t*)bcount, kind, rho_in, u, v, p, w.ug,
-                           w.vg, cf.body_force[0] - cf.wall_accel[0],
+                           (const int32_t*)blist, (const int32_t*)bcount, bnext, kind, x, y, h,
+                           rho_in, u, v, p, w.ug, w.vg, cf.body_force[0] - cf.wall_accel[0],
                            cf.body_force[1] - cf.wall_accel[1]);
         LAUNCHCHK(c, "boundary");
     }
     using T4 = typename Vec4<T>::type;
     T4* pf = (T4*)w.pf;
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
-                       cf.mass_q, nv.xs, nv.ys, nv.hs, w.pa, w.puv, b.m,
+                       cf.mass_q, x, y, h, w.xs, w.ys, w.hs, w.pa, w.puv, b.m,
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
                        w.ugs, w.vgs, kind);
     LAUNCHCHK(c, "gather_state");

@@ -66,6 +66,7 @@ struct Work {
     unsigned long long* hmax_bits;
     int32_t* lcount;
     int32_t* status;       // [0] overflow rows count, [1] nonfinite flag, ...
+    unsigned long long* ctr; // cumulative event counters (never cleared)
     int32_t* long_rows;    // rows needing the long-row sort path
     double *xs, *ys, *hs;  // sorted shadows
     double *us, *vs;       // sorted velocity (double: differences taken in FP64)
@@ -129,6 +130,8 @@ struct sph_ctx {
     int64_t list_builds, list_reuses;
     // when set, every rate evaluation adds its interacting ordered pairs here
     unsigned long long* pair_acc;
+    int bparity;                    // which boundary-list counter the next evaluation uses
+    unsigned long long io_last[3];  // inlet/outlet event counters at the last update
 };
 
 // ---- host-side launch wrappers (implemented in the .hip files) ----------
@@ -137,7 +140,6 @@ struct sph_ctx {
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 NbrView nbr_view(sph_ctx* c);
 int nbr_build_list(sph_ctx* c, int n, double skin);
-int nbr_regather(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 // Rows hold every j with |r_i - r_j| < sf 3 max(h_i, h_j) (sf = 1: the
 // neighbour set), ascending.
 int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz,
