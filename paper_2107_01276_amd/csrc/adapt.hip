@@ -355,9 +355,23 @@ __device__ __forceinline__ void shift_row(const Grid& g, int i, const int64_t* _
     *oy = ddy;
 }
 
-__global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState s,
+// Per-slot records for the shift and h-update sweeps, so that a neighbour
+// costs two 32-byte loads: A = {x, y, h, m}, B = {u, v, p, rho} (m = mq q,
+// the same double the oracle uses).
+__global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double q, double4* A,
+                                                    double4* B)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    A[i] = make_double4(s.x[i], s.y[i], s.h[i], (double)s.mq[i] * q);
+    B[i] = make_double4(s.u[i], s.v[i], s.p[i], s.rho[i]);
+}
+
+__global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32_t* __restrict__ kind,
+                                                      const double4* __restrict__ A,
+                                                      const double4* __restrict__ B,
                                                       const int64_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col, double q,
+                                                      const int32_t* __restrict__ col,
                                                       double rho0, double* ddx_o, double* ddy_o,
                                                       double* nu_o, double* nv_o, double* np_o,
                                                       const int32_t* __restrict__ order)
@@ -367,9 +381,11 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int i = order ? order[t] : t;
-    if (s.kind && s.kind[i] != SPH_FLUID) {
+    const double4 ai = A[i], bi = B[i];
+    const double ui = bi.x, vi = bi.y, pi = bi.z;
+    if (kind && kind[i] != SPH_FLUID) {
         ddx_o[i] = 0.0; ddy_o[i] = 0.0;
-        nu_o[i] = s.u[i]; nv_o[i] = s.v[i]; np_o[i] = s.p[i];
+        nu_o[i] = ui; nv_o[i] = vi; np_o[i] = pi;
         return;
     }
     // shift sums and the Taylor gradients share one sweep over the row; every
@@ -377,31 +393,32 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, FluidState 
     const double fxi = kern_f<double>(SPH_XI);
     double sx = 0.0, sy = 0.0;
     double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
-    const double xi = s.x[i], yi = s.y[i], hi = s.h[i];
-    const double ui = s.u[i], vi = s.v[i], pi = s.p[i];
+    const double xi = ai.x, yi = ai.y, hi = ai.z;
     for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
         const int j = col[k];
-        const double dx = mi_axis(g, 0, xi - s.x[j]);
-        const double dy = mi_axis(g, 1, yi - s.y[j]);
+        const double4 aj = A[j];
+        const double dx = mi_axis(g, 0, xi - aj.x);
+        const double dy = mi_axis(g, 1, yi - aj.y);
         const double r2 = dx * dx + dy * dy;
-        const double hj = s.h[j];
+        const double hj = aj.z;
         const double RR = 3.0 * (hi > hj ? hi : hj);
         if (!(r2 < RR * RR)) continue;  // the row may be a superset of N(i)
         const double r = sqrt(r2);
         if (r <= 0.0) continue;
-        const double mj = (double)s.mq[j] * q;
+        const double4 bj = B[j];
+        const double mj = aj.w;
         // shifting term at h_ij
         const double hij = 0.5 * (hi + hj);
         const double wr = kern_f<double>(r / hij) / fxi;
         const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
-        const double t = coef * (kern_dw64(r, hij) / r);
-        sx = sx + t * dx;
-        sy = sy + t * dy;
+        const double tt = coef * (kern_dw64(r, hij) / r);
+        sx = sx + tt * dx;
+        sy = sy + tt * dy;
         // gradients at h_i
         const double f = kern_dw64(r, hi) / r;
         const double wx = f * dx, wy = f * dy;
-        const double Vj = mj / s.rho[j];
-        const double du = s.u[j] - ui, dv = s.v[j] - vi, dp = s.p[j] - pi;
+        const double Vj = mj / bj.w;
+        const double du = bj.x - ui, dv = bj.y - vi, dp = bj.z - pi;
         gux += Vj * du * wx; guy += Vj * du * wy;
         gvx += Vj * dv * wx; gvy += Vj * dv * wy;
         gpx += Vj * dp * wx; gpy += Vj * dp * wy;
@@ -442,32 +459,29 @@ __global__ __launch_bounds__(256) void k_shift_apply(Grid g, int n, FluidState s
 // included; the row may be a superset of N(i), filtered by the predicate.
 __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
-                                                 const double* __restrict__ x,
-                                                 const double* __restrict__ y,
-                                                 const int64_t* __restrict__ mq,
+                                                 const double4* __restrict__ A,
                                                  const double* __restrict__ rho,
-                                                 const int32_t* __restrict__ kind, double q,
-                                                 double hdx, const double* __restrict__ h,
+                                                 const int32_t* __restrict__ kind, double hdx,
                                                  double* nh, const int32_t* __restrict__ order)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int i = order ? order[t] : t;
+    const double4 ai = A[i];
     if (kind && kind[i] != SPH_FLUID) {
-        nh[i] = h[i];
+        nh[i] = ai.z;
         return;
     }
-    const double xi = x[i], yi = y[i], hi = h[i];
+    const double xi = ai.x, yi = ai.y, hi = ai.z;
     double sm = 0.0;
     int64_t cnt = 0;
     for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        const double dx = mi_axis(g, 0, xi - x[j]);
-        const double dy = mi_axis(g, 1, yi - y[j]);
-        const double hj = h[j];
-        const double RR = 3.0 * (hi > hj ? hi : hj);
+        const double4 aj = A[col[k]];
+        const double dx = mi_axis(g, 0, xi - aj.x);
+        const double dy = mi_axis(g, 1, yi - aj.y);
+        const double RR = 3.0 * (hi > aj.z ? hi : aj.z);
         if (!(dx * dx + dy * dy < RR * RR)) continue;
-        sm += (double)mq[j] * q;
+        sm += aj.w;
         ++cnt;
     }
     const double mbar = sm / (double)cnt;
@@ -628,10 +642,14 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             if (rc) return rc;
         }
         unsigned nb = (unsigned)cdiv(n, 256);
-        // the sorted order of the last build (slots unchanged since)
-        hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.rp_tmp,
-                           w.col_tmp, cf.mass_q, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2],
-                           w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
+        // packed records in the rate passes' buffers (free during adaptation);
+        // rows in the sorted order of the last build (slots unchanged since)
+        double4 *pA = w.pa, *pB = (double4*)w.pf;
+        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, pA, pB);
+        hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
+                           (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
+                           w.col_tmp, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2], w.tmp_d[3],
+                           w.tmp_d[4], (const int32_t*)w.vals_a);
         hipLaunchKernelGGL(k_shift_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.tmp_d[0],
                            w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4]);
         LAUNCHCHK(c, "shift");
@@ -642,9 +660,11 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             if (rc) return rc;
         }
         unsigned nb = (unsigned)cdiv(n, 256);
+        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, w.pa,
+                           (double4*)w.pf);
         hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, c->grid, n, w.rp_tmp, w.col_tmp,
-                           ps->x, ps->y, ps->mq, ps->rho, ps->kind, cf.mass_q, cf.hdx, ps->h,
-                           w.tmp_d[0], (const int32_t*)w.vals_a);
+                           (const double4*)w.pa, (const double*)ps->rho, (const int32_t*)ps->kind,
+                           cf.hdx, w.tmp_d[0], (const int32_t*)w.vals_a);
         hipLaunchKernelGGL(k_copy_f64, dim3(nb), dim3(256), 0, c->stream, n, w.tmp_d[0], ps->h);
         LAUNCHCHK(c, "hupdate");
     }
