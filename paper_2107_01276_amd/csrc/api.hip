@@ -56,6 +56,7 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->xs = (double*)take(8 * C);
     w->ys = (double*)take(8 * C);
     w->hs = (double*)take(8 * C);
+    w->xyh = (double4*)take(32 * C);
     w->us = (double*)take(8 * C);
     w->vs = (double*)take(8 * C);
     double** sc[12] = {&w->sc0, &w->sc1, &w->sc2, &w->sc3, &w->sc4, &w->sc5,

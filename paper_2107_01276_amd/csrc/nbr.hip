@@ -413,14 +413,16 @@ __global__ __launch_bounds__(256) void k_gather_pos(int n, const int32_t* __rest
                                                     const double* __restrict__ x,
                                                     const double* __restrict__ y,
                                                     const double* __restrict__ h, double* xs,
-                                                    double* ys, double* hs)
+                                                    double* ys, double* hs, double4* xyh)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
-    xs[s] = x[i];
-    ys[s] = y[i];
-    hs[s] = h[i];
+    const double xi = x[i], yi = y[i], hi = h[i];
+    xs[s] = xi;
+    ys[s] = yi;
+    hs[s] = hi;
+    xyh[s] = make_double4(xi, yi, hi, 0.0);
 }
 
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h)
@@ -441,7 +443,7 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
         int rc = radix_sort(c, n, key_bits(&g));
         if (rc) return rc;
         hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
-                           w.vals_a, x, y, h, w.xs, w.ys, w.hs);
+                           w.vals_a, x, y, h, w.xs, w.ys, w.hs, w.xyh);
         hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
                            w.keys_a, w.xs, w.ys, w.tab);
         LAUNCHCHK(c, "tables");
@@ -457,6 +459,7 @@ NbrView nbr_view(sph_ctx* c)
     v.xs = c->w.xs;
     v.ys = c->w.ys;
     v.hs = c->w.hs;
+    v.xyh = c->w.xyh;
     v.perm = c->w.vals_a;
     v.keys = c->w.keys_a;
     v.tab = c->w.tab;

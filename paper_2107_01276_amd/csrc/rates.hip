@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ y,
                                                       const double* __restrict__ h, double* xs,
-                                                      double* ys, double* hs, double4* pa,
+                                                      double* ys, double* hs, double4* xyh,
+                                                      double4* pa,
                                                       double2* puv, T* ms,
                                                       const double* __restrict__ ug,
                                                       const double* __restrict__ vg, double* ugs,
@@ -69,6 +70,7 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     xs[s] = xi;
     ys[s] = yi;
     hs[s] = hi;
+    xyh[s] = make_double4(xi, yi, hi, 0.0);
     pa[s] = make_double4(xi, yi, hi, p[i]);
     puv[s] = make_double2(u[i], v[i]);
     ms[s] = (T)((double)mq[i] * mass_q);
@@ -536,7 +538,7 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     using T4 = typename Vec4<T>::type;
     T4* pf = (T4*)w.pf;
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
-                       cf.mass_q, x, y, h, w.xs, w.ys, w.hs, w.pa, w.puv, b.m,
+                       cf.mass_q, x, y, h, w.xs, w.ys, w.hs, w.xyh, w.pa, w.puv, b.m,
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
                        w.ugs, w.vgs, kind);
     LAUNCHCHK(c, "gather_state");

@@ -281,7 +281,8 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             for (int js = se[k].x; js < se[k].y; ++js) {
-                const double xj = nv.xs[js], yj = nv.ys[js], hj = nv.hs[js];
+                const double4 aj = nv.xyh[js];
+                const double xj = aj.x, yj = aj.y, hj = aj.z;
                 const double dx = mi_axis(g, 0, xi - xj);
                 const double dy = mi_axis(g, 1, yi - yj);
                 const double r2 = dx * dx + dy * dy;
@@ -304,7 +305,8 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
                     if (gx * gx + gy * gy > Rs2) continue;
                     const int2 se = tab[(int64_t)cy * nq + cx];
                     for (int js = se.x; js < se.y; ++js) {
-                        const double xj = nv.xs[js], yj = nv.ys[js], hj = nv.hs[js];
+                        const double4 aj = nv.xyh[js];
+                const double xj = aj.x, yj = aj.y, hj = aj.z;
                         const double dx = mi_axis(g, 0, xi - xj);
                         const double dy = mi_axis(g, 1, yi - yj);
                         const double r2 = dx * dx + dy * dy;

@@ -49,6 +49,7 @@ struct NbrView {
     const double* xs;     // positions and smoothing lengths, sorted order
     const double* ys;
     const double* hs;
+    const double4* xyh;   // {x, y, h, -} packed, sorted order (one record per candidate)
     const int32_t* perm;  // sorted position -> slot
     const uint64_t* keys; // sorted keys (level in the high bits)
     const int2* tab;      // cell run tables
@@ -69,6 +70,7 @@ struct Work {
     unsigned long long* ctr; // cumulative event counters (never cleared)
     int32_t* long_rows;    // rows needing the long-row sort path
     double *xs, *ys, *hs;  // sorted shadows
+    double4* xyh;          // the same, packed
     double *us, *vs;       // sorted velocity (double: differences taken in FP64)
     double *sc0, *sc1, *sc2, *sc3, *sc4, *sc5, *sc6, *sc7, *sc8, *sc9, *sc10, *sc11; // typed scratch
     double *r_dpdt, *r_dudt, *r_dvdt, *r_dxs, *r_dys; // rates in slot order
