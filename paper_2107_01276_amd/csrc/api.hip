@@ -96,7 +96,6 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->yref = (double*)take(8 * C);
     w->href = (double*)take(8 * C);
     w->list_flag = (int32_t*)take(4 * 64);
-    w->pk = (float4*)take(16 * C);
     w->ug = (double*)take(8 * C);
     w->vg = (double*)take(8 * C);
     w->ugs = (double*)take(8 * C);

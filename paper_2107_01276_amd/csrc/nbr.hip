@@ -59,16 +59,6 @@ void grid_setup(const sph_config* cfg, Grid* g)
         g->mi_l[a] = g->periodic[a] ? g->L[a] : 0.0;
         g->mi_h[a] = g->periodic[a] ? g->half[a] : HUGE_VAL;
     }
-    // coordinates relative to the origin stay below ext in magnitude (with
-    // generous room for particles outside an open box); a difference of two
-    // of them rounded to FP32, with one period folded in, is off by at most
-    // a few ulp of ext
-    double ext = 0.0;
-    for (int a = 0; a < 2; ++a) {
-        double e = 4.0 * (fabs(g->lo[a]) + fabs(g->hi[a]) + g->L[a]) + 1.0;
-        if (e > ext) ext = e;
-    }
-    g->f32_pad = 16.0 * ldexp(ext, -24);
     int nlev = 1;
     double c = g->cmin0;
     while (c < 3.0 * hhi * (1.0 + 1e-9) && nlev < SPH_MAXL) {
@@ -469,196 +459,33 @@ NbrView nbr_view(sph_ctx* c)
 }
 
 // ---------------------------------------------------------------------------
-// Neighbour list for the rate passes, built per wave.  A wave owns 64
-// consecutive sorted particles and splits them into segments wherever the
-// level changes or two consecutive particles are more than two supports apart
-// (the Hilbert order keeps segments few and compact).  For each segment and
-// level the wave walks the cells of the segment's union box that meet some
-// member's search disk (a wave vote), loads each cell's particles 64 at a
-// time (one per lane, coalesced) and broadcasts them lane by lane, so every
-// lane runs the same loop and only members test.  Boxes that straddle half a
-// period, and waves with more than LIST_MAX_SEG segments, use the per-lane
-// search.  Entry k of sorted particle s goes to idx[k * stride + s]; counts
-// above K are recorded (the rate passes then search again for it).
+// Neighbour list for the rate passes: every pair closer than (1 + skin)
+// times the support radius, from a per-lane cell walk.  Entry k of sorted
+// particle s goes to idx[k * stride + s], so a wave's rows are read one
+// coalesced line per k; counts above K are recorded (the rate passes then
+// walk the cells again for that row).
 // ---------------------------------------------------------------------------
 
-#define LIST_MAX_SEG 8
-
-// Minimum image, resolved at compile time for open axes.
-template <bool P>
-__device__ __forceinline__ double mi_t(const Grid& g, int a, double d)
+// Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate).
+__global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int n, NbrList nl,
+                                                         double sf)
 {
-    return P ? mi_axis(g, a, d) : d;
-}
-
-// Sorted particles packed for the list pre-test: FP32 coordinates relative
-// to the grid origin and the squared search radius sf 3 h padded by the
-// FP32 rounding bound of a displacement.
-__global__ __launch_bounds__(256) void k_pack32(Grid g, int n, const double* __restrict__ xs,
-                                                const double* __restrict__ ys,
-                                                const double* __restrict__ hs, double sf,
-                                                float4* pk)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const double r = (3.0 * hs[s]) * sf * (1.0 + 1e-6) + g.f32_pad;
-    pk[s] = make_float4((float)(xs[s] - g.org[0]), (float)(ys[s] - g.org[1]), (float)(r * r), 0.f);
-}
-
-template <bool PX, bool PY>
-__global__ __launch_bounds__(256) void k_build_list(Grid g, NbrView nv, int n, NbrList nl,
-                                                    double sf, const float4* __restrict__ pk)
-{
-    __shared__ int s_pre[4][64], s_beg[4][64];
-    const int lane = __lane_id();
-    const int w = threadIdx.x >> 6;
     const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int s0 = s - lane;
-    if (s0 >= n) return;  // whole wave past the end
-    const bool valid = s < n;
-    const int sv = valid ? s : s0;
-    const double xi = nv.xs[sv], yi = nv.ys[sv], hi = nv.hs[sv];
-    const float4 pi = pk[sv];
-    const float xi32 = pi.x, yi32 = pi.y, ri2f = pi.z;
-    const float Lx = (float)g.mi_l[0], Ly = (float)g.mi_l[1];
-    const float hLx = 0.5f * Lx, hLy = 0.5f * Ly;
-    const int li = key_level(g, nv.keys[sv]);
+    if (s >= n) return;
+    const double4 a = nv.xyh[s];
+    const int li = key_level(g, nv.keys[s]);
     int cnt = 0;
-    int32_t* out = nl.idx + s;                            // row cnt of this particle
+    int32_t* out = nl.idx + s;
     int32_t* const last = nl.idx + (int64_t)(nl.K - 1) * nl.stride + s;
-    auto emit = [&](int js) {
-        // an overflowing row (cnt > K) is searched again by the rate passes,
-        // so its last slot may be overwritten
-        *out = js;
-        out = out == last ? out : out + nl.stride;
-        ++cnt;
-    };
-    // segments of the wave
-    const double xp = __shfl_up(xi, 1, 64), yp = __shfl_up(yi, 1, 64);
-    const int lp = __shfl_up(li, 1, 64);
-    const double ex = mi_axis(g, 0, xi - xp), ey = mi_axis(g, 1, yi - yp);
-    const double thr = 6.0 * hi;
-    const bool start = lane == 0 || (valid && (li != lp || ex * ex + ey * ey > thr * thr));
-    const uint64_t sb = __ballot(start);
-    const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-    const int seg = __popcll(sb & le) - 1;
-    const int nseg = __popcll(sb);
-    if (nseg > LIST_MAX_SEG) {
-        if (valid) {
-            for_each_neighbor(g, nv, xi, yi, hi, li,
-                              [&](int js, double, double, double, double) { emit(js); }, sf);
-            nl.cnt[s] = cnt;
-            if (cnt > nl.K) nl.flag[0] = 1;
-        }
-        return;
-    }
-    const double INF = 1e300;
-    for (int sg = 0; sg < nseg; ++sg) {
-        const bool mem = valid && seg == sg;
-        const int lseg = wave_min_i(mem ? li : 0x7fffffff);
-        for (int l = 0; l < g.nlev; ++l) {
-            if (nv.lcount[l] == 0) continue;
-            const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
-            const double R = 3.0 * (hi > hl ? hi : hl) * sf;
-            const double bx0 = wave_min_d(mem ? xi - R : INF), bx1 = wave_max_d(mem ? xi + R : -INF);
-            const double by0 = wave_min_d(mem ? yi - R : INF), by1 = wave_max_d(mem ? yi + R : -INF);
-            const bool wrap = (g.periodic[0] && bx1 - bx0 > g.half[0]) ||
-                              (g.periodic[1] && by1 - by0 > g.half[1]);
-            if (wrap) {
-                if (mem)
-                    for_each_neighbor_level(g, nv, xi, yi, hi, li, l,
-                                            [&](int js, double, double, double, double) { emit(js); },
-                                            sf);
-                continue;
-            }
-            const int Q = l > lseg ? l : lseg;
-            const Span xr = axis_span(g, 0, 0.5 * (bx0 + bx1), 0.5 * (bx1 - bx0), Q);
-            const Span yr = axis_span(g, 1, 0.5 * (by0 + by1), 0.5 * (by1 - by0), Q);
-            const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
-            const int nq = g.nxq[Q][0];
-            const int nx_a = xr.b0 - xr.a0 + 1, nx_t = nx_a + (xr.n == 2 ? xr.b1 - xr.a1 + 1 : 0);
-            const int ny_a = yr.b0 - yr.a0 + 1, ny_t = ny_a + (yr.n == 2 ? yr.b1 - yr.a1 + 1 : 0);
-            const int ncell = nx_t * ny_t;
-            // cells of the box, 64 per round: lane t fetches cell t's run,
-            // a wave scan turns run lengths into offsets of one candidate
-            // stream, and the stream is tested 64 candidates at a time while
-            // the next 64 are being loaded
-            for (int c0 = 0; c0 < ncell; c0 += 64) {
-                const int t = c0 + lane;
-                int len = 0, beg = 0;
-                if (t < ncell) {
-                    const int ix = t % nx_t, iy = t / nx_t;
-                    const int cx = ix < nx_a ? xr.a0 + ix : xr.a1 + (ix - nx_a);
-                    const int cy = iy < ny_a ? yr.a0 + iy : yr.a1 + (iy - ny_a);
-                    const int2 se = tab[(int64_t)cy * nq + cx];
-                    beg = se.x;
-                    len = se.y - se.x;
-                }
-                const int incl = wave_incl_scan<int>(len);
-                const int total = __builtin_amdgcn_readlane(incl, 63);
-                if (total == 0) continue;
-                s_pre[w][lane] = incl - len;
-                s_beg[w][lane] = beg;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int nc = ncell - c0 < 64 ? ncell - c0 : 64;
-                auto fetch = [&](int p, int& js, float4& f) {
-                    js = 0;
-                    f = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (p < total) {
-                        int lo = 0, hi2 = nc - 1;  // last cell whose offset <= p
-                        while (lo < hi2) {
-                            const int mid = (lo + hi2 + 1) >> 1;
-                            if (s_pre[w][mid] <= p) lo = mid;
-                            else hi2 = mid - 1;
-                        }
-                        js = s_beg[w][lo] + (p - s_pre[w][lo]);
-                        f = pk[js];
-                    }
-                };
-                auto bc = [](float v, int k) {
-                    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-                };
-                // conservative FP32 pre-test: a superset of the pairs closer
-                // than sf 3 max(h_i, h_j); the rate passes test exactly
-                auto test = [&](const float4& A, int k) -> bool {
-                    float dx = xi32 - bc(A.x, k), dy = yi32 - bc(A.y, k);
-                    if (PX) dx = dx > hLx ? dx - Lx : (dx < -hLx ? dx + Lx : dx);
-                    if (PY) dy = dy > hLy ? dy - Ly : (dy < -hLy ? dy + Ly : dy);
-                    return mem && dx * dx + dy * dy < fmaxf(ri2f, bc(A.z, k));
-                };
-                int jA;
-                float4 A;
-                fetch(lane, jA, A);
-                for (int base = 0; base < total; base += 64) {
-                    int jB;
-                    float4 B;
-                    fetch(base + 64 + lane, jB, B);
-                    const int m = total - base < 64 ? total - base : 64;
-                    int k = 0;
-                    for (; k + 4 <= m; k += 4) {
-                        bool hit[4];
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) hit[u] = test(A, k + u);
-                        if (__ballot(hit[0] || hit[1] || hit[2] || hit[3]) == 0ull) continue;
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (hit[u]) emit(__builtin_amdgcn_readlane(jA, k + u));
-                    }
-                    for (; k < m; ++k)
-                        if (test(A, k)) emit(__builtin_amdgcn_readlane(jA, k));
-                    jA = jB;
-                    A = B;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-        }
-    }
-    if (valid) {
-        nl.cnt[s] = cnt;
-        if (cnt > nl.K) nl.flag[0] = 1;
-    }
+    for_each_neighbor(g, nv, a.x, a.y, a.z, li,
+                      [&](int js, double, double, double, double) {
+                          *out = js;
+                          out = out == last ? out : out + nl.stride;
+                          ++cnt;
+                      },
+                      sf);
+    nl.cnt[s] = cnt;
+    if (cnt > nl.K) nl.flag[0] = 1;
 }
 
 int nbr_build_list(sph_ctx* c, int n, double skin)
@@ -669,12 +496,8 @@ int nbr_build_list(sph_ctx* c, int n, double skin)
     prof_begin(c, SPH_PROF_LIST);
     const Grid& g = c->grid;
     const double sf = 1.0 + skin;
-    hipLaunchKernelGGL(k_pack32, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n, w.xs, w.ys,
-                       w.hs, sf, w.pk);
-    auto kern = g.periodic[0] ? (g.periodic[1] ? k_build_list<true, true> : k_build_list<true, false>)
-                              : (g.periodic[1] ? k_build_list<false, true> : k_build_list<false, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nbr_view(c), n,
-                       nl, sf, (const float4*)w.pk);
+    hipLaunchKernelGGL(k_build_list_lane, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g,
+                       nbr_view(c), n, nl, sf);
     prof_end(c, SPH_PROF_LIST);
     LAUNCHCHK(c, "build_list");
     return SPH_OK;

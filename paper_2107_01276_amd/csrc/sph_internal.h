@@ -32,8 +32,6 @@ struct Grid {
                         // product instead of a quotient is safe)
     double mi_l[2];     // minimum image: period (0 on open axes)
     double mi_h[2];     // minimum image: half period (+inf on open axes)
-    double f32_pad;     // bound on the FP32 rounding of a displacement
-                        // relative to the grid origin (list pre-test)
     int32_t nx0[2];     // level-0 cells per axis
     int32_t periodic[2];
     int32_t nlev;       // number of levels
@@ -89,7 +87,6 @@ struct Work {
     int32_t *nl_idx, *nl_cnt; // pass A -> pass B neighbour list
     int32_t nl_k;
     double *xref, *yref, *href; // state the list was built on (slot order)
-    float4* pk;                 // sorted (x - org, y - org, padded radius^2) in FP32
     double *ug, *vg;            // viscous-term velocity (ghost velocity of walls), slot order
     double *ugs, *vgs;          // the same, sorted order
     // what the rate passes gather per neighbour, packed into 16-byte loads
