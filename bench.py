@@ -157,16 +157,26 @@ def prepare(SPH, W, s, bg, prec, capacity, skin=0.1):
     return ctx, P, B
 
 
-def run(ctx, P, B, dt, steps, warmup, adapt_every, torch, io=None):
-    def one(k):
-        ctx.step(P, dt, 1)
+def advance(st, nsteps, dt, io, adapt_every):
+    """nsteps of the timed loop: steps with the inlet/outlet update after each
+    (one library call per run of steps), and an adaptation every
+    `adapt_every` steps.  st holds ctx, P, B and the step counter k."""
+    left = nsteps
+    while left > 0:
+        k = left if not adapt_every else min(left, adapt_every - st["k"] % adapt_every)
         if io is not None:
-            ctx.inout(P, io)
-        if adapt_every and (k + 1) % adapt_every == 0:
-            ctx.adapt(P, B)
+            st["ctx"].step_inout(st["P"], dt, k, io)
+        else:
+            st["ctx"].step(st["P"], dt, k)
+        st["k"] += k
+        left -= k
+        if adapt_every and st["k"] % adapt_every == 0:
+            st["ctx"].adapt(st["P"], st["B"])
 
-    for k in range(warmup):
-        one(k)
+
+def run(ctx, P, B, dt, steps, warmup, adapt_every, torch, io=None):
+    st = {"ctx": ctx, "P": P, "B": B, "k": 0}
+    advance(st, warmup, dt, io, adapt_every)
     torch.cuda.synchronize()
     pairs0 = count_pairs(ctx, P)
     ctx.profile(True)
@@ -175,8 +185,7 @@ def run(ctx, P, B, dt, steps, warmup, adapt_every, torch, io=None):
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(ctx.stream)
-    for k in range(steps):
-        one(k)
+    advance(st, steps, dt, io, adapt_every)
     e1.record(ctx.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
@@ -217,12 +226,7 @@ def main():
         return make
 
     def run_steps(st, k):
-        for _ in range(k):
-            st["ctx"].step(st["P"], dt, 1)
-            st["ctx"].inout(st["P"], s["io"])
-            st["k"] += 1
-            if args.adapt_every and st["k"] % args.adapt_every == 0:
-                st["ctx"].adapt(st["P"], st["B"])
+        advance(st, k, dt, s["io"], args.adapt_every)
 
     tuning = {}
     results = {}

@@ -324,6 +324,16 @@ int sph_pool_retire(sph_pool *pool, int32_t sim_id);
 
 int sph_pool_info(sph_pool *pool, sph_pool_stats *out);
 
+/* nsteps of { sph_step with nsteps = 1, then sph_inout }, with the same
+ * results as those calls in sequence; the inlet/outlet round trip also
+ * carries the list check of the next step.  The map's counters are summed
+ * over the steps and map->origin is the composition of the steps' maps
+ * (new slot -> slot before the call), written only when some step moved a
+ * slot.  A capacity error stops at the step that needed it (earlier steps
+ * stay applied; ps->n is current).  Synchronises. */
+int sph_step_inout(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps,
+                   const sph_inout_params *io, sph_inout_map *map);
+
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 

@@ -103,7 +103,7 @@ class sph_diag(C.Structure):
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
            "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_profile_enable",
-           "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution",
+           "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
            "sph_pool_footprint", "sph_pool_create",
            "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
            "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info")
@@ -135,6 +135,7 @@ def load_library(path: str = LIB_PATH):
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
         "sph_inout": (C.c_int, [P, P, P, P]),
         "sph_vorticity": (C.c_int, [P, P, P]),
+        "sph_step_inout": (C.c_int, [P, P, D, I32, P, P]),
         "sph_bg_update_solution": (C.c_int, [P, P, P, P, D, I32, P, P]),
         "sph_diagnostics": (C.c_int, [P, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
@@ -384,6 +385,25 @@ class Context:
         P.n = int(ps.n)
         info["origin"] = origin[:P.n]
         info["sat"] = sat[:P.n]
+        return info
+
+    def step_inout(self, P: Particles, dt: float, nsteps: int, io: dict):
+        """nsteps of (step, inlet/outlet update) in one call (sph_step_inout)."""
+        origin = torch.empty(P.capacity, dtype=torch.int64, device=self.device)
+        m = sph_inout_map(origin=_ptr(origin).value)
+        prm = sph_inout_params(float(io["x_in"]), float(io["len_in"]), float(io["x_out"]),
+                               float(io["len_out"]))
+        ps = P.c()
+        rc = self.lib.sph_step_inout(self._h, C.byref(ps), float(dt), int(nsteps), C.byref(prm),
+                                     C.byref(m))
+        P.n = int(ps.n)
+        self._check(rc)
+        info = {"appended": int(m.n_appended), "deleted": int(m.n_deleted),
+                "to_outlet": int(m.n_to_outlet)}
+        if info["appended"] or info["deleted"]:
+            info["origin"] = origin[:P.n]
+        else:
+            info["origin"] = torch.arange(P.n, dtype=torch.int64, device=self.device)
         return info
 
     def vorticity(self, P: Particles):

@@ -951,7 +951,8 @@ __global__ __launch_bounds__(256) void k_io_copy(int n, FluidState d, FluidState
     origin[t] = d.origin[t];
 }
 
-int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map)
+int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map,
+              bool precheck)
 {
     Work& w = c->w;
     const int n = (int)ps->n;
@@ -966,8 +967,13 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
                        (const int32_t*)ps->kind, *io, keep, app, cnt);
     LAUNCHCHK(c, "io_flags");
+    // the list check of the next evaluation rides on the same round trip
+    const bool checked = precheck && launch_list_check(c, n, ps->x, ps->y, ps->h);
     unsigned long long h3[3] = {0, 0, 0};
+    int32_t lflag = 1;
     HIPCHK(c, hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, c->stream));
+    if (checked)
+        HIPCHK(c, hipMemcpyAsync(&lflag, w.list_flag, sizeof(lflag), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     const int32_t nto = (int32_t)(h3[0] - c->io_last[0]);
     const int32_t nap = (int32_t)(h3[1] - c->io_last[1]);
@@ -981,6 +987,10 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
             hipLaunchKernelGGL(k_io_kinds, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
                                ps->kind, *io);
             LAUNCHCHK(c, "io_kinds");
+        }
+        if (checked) {
+            c->precheck_valid = 1;
+            c->precheck_ok = lflag == 0;
         }
         return SPH_OK;
     }
@@ -1144,4 +1154,69 @@ int bg_solution_run(sph_ctx* c, sph_background* bg, const sph_particles* solids,
     const double thresh = k_frac * mx;
     return bg_update_run(c, bg, solids, (n > 0 && nb > 0 && mx > 0.0) ? phi : nullptr, thresh,
                          passes, nsplit);
+}
+
+// Origin maps of successive updates compose: total[t] = before[step[t]].
+__global__ __launch_bounds__(256) void k_compose(int n, const int64_t* __restrict__ before,
+                                                 const int64_t* __restrict__ step, int64_t* total)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) total[t] = before[step[t]];
+}
+
+__global__ __launch_bounds__(256) void k_copy_i64(int n, const int64_t* __restrict__ a, int64_t* b)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// nsteps of (PEC step, inlet/outlet update).  Counters add up over the
+// steps; map->origin is the composition of the steps' maps (left unwritten
+// when no step moved a slot).
+int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const sph_inout_params* io,
+                   sph_inout_map* map)
+{
+    Work& w = c->w;
+    int64_t tot_app = 0, tot_del = 0, tot_out = 0;
+    bool moved = false;
+    int64_t* comp = w.tmp_i64[2];  // composed map so far
+    int rc = SPH_OK;
+    for (int s = 0; s < nsteps && rc == SPH_OK; ++s) {
+        rc = step_run(c, ps, dt, 1);
+        if (rc) break;
+        const int n_before = (int)ps->n;
+        sph_inout_map m{w.i64_b, 0, 0, 0, 0};
+        rc = inout_run(c, ps, io, &m, s + 1 < nsteps);
+        if (rc) break;
+        tot_app += m.n_appended;
+        tot_del += m.n_deleted;
+        tot_out += m.n_to_outlet;
+        if (m.n_appended || m.n_deleted) {
+            const int nn = (int)ps->n;
+            const unsigned nb = (unsigned)cdiv(nn > 0 ? nn : 1, 256);
+            if (!moved) {
+                hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
+                                   (const int64_t*)w.i64_b, comp);
+            } else {
+                hipLaunchKernelGGL(k_compose, dim3(nb), dim3(256), 0, c->stream, nn,
+                                   (const int64_t*)comp, (const int64_t*)w.i64_b, w.i64_a);
+                hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
+                                   (const int64_t*)w.i64_a, comp);
+            }
+            LAUNCHCHK(c, "compose");
+            moved = true;
+        }
+        (void)n_before;
+    }
+    c->precheck_valid = 0;
+    map->n_appended = tot_app;
+    map->n_deleted = tot_del;
+    map->n_to_outlet = tot_out;
+    map->n_required = ps->n;
+    if (rc == SPH_OK && moved && ps->n > 0) {
+        hipLaunchKernelGGL(k_copy_i64, dim3((unsigned)cdiv(ps->n, 256)), dim3(256), 0, c->stream,
+                           (int)ps->n, (const int64_t*)comp, map->origin);
+        LAUNCHCHK(c, "origin");
+    }
+    return rc;
 }

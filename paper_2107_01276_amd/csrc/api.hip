@@ -291,6 +291,28 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
     return adapt_run(c, ps, bg, map);
 }
 
+extern "C" int sph_step_inout(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps,
+                              const sph_inout_params* io, sph_inout_map* map)
+{
+    if (c && c->cfg.lean) {
+        set_err(c, "this context was created lean (no adaptation buffers)");
+        return SPH_E_INVAL;
+    }
+    if (!c || !io || !map) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref || !ps->kind) {
+        set_err(c, "step_inout needs the full state including rho, mref and kind");
+        return SPH_E_INVAL;
+    }
+    if (!(dt > 0) || nsteps < 0) { set_err(c, "dt must be > 0, nsteps >= 0"); return SPH_E_INVAL; }
+    if (!map->origin) { set_err(c, "inout map origin not set"); return SPH_E_INVAL; }
+    if (!isfinite(io->x_in) || !isfinite(io->x_out) || !(io->len_in >= 0) || !(io->len_out >= 0) ||
+        !isfinite(io->len_in) || !isfinite(io->len_out)) {
+        set_err(c, "inout zones must be finite with non-negative lengths");
+        return SPH_E_INVAL;
+    }
+    return step_inout_run(c, ps, dt, nsteps, io, map);
+}
+
 extern "C" int sph_vorticity(sph_ctx* c, const sph_particles* ps, double* omega)
 {
     if (!c || !omega) return SPH_E_INVAL;

@@ -448,6 +448,17 @@ __global__ __launch_bounds__(256) void k_list_check(Grid g, int n, const double*
     if (!(dx * dx + dy * dy < r * r) || h[i] != href[i]) flag[0] = 1;
 }
 
+// Launches the list check of the next evaluation on (x, y, h) when a list
+// is held (flag left in the list flag); returns whether it was launched.
+bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h)
+{
+    if (!(c->list_valid && c->list_n == n && c->skin > 0 && n > 0)) return false;
+    Work& w = c->w;
+    hipLaunchKernelGGL(k_list_check, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid, n,
+                       x, y, h, w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag);
+    return hipGetLastError() == hipSuccess;
+}
+
 __global__ void k_clear_flag(int32_t* flag)
 {
     if (threadIdx.x == 0) flag[0] = 0;
@@ -473,7 +484,10 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
     Work& w = c->w;
     bool reuse = c->list_valid && c->list_n == n && c->skin > 0 && n > 0;
     unsigned nb = (unsigned)cdiv(n > 0 ? n : 1, 256);
-    if (reuse) {
+    if (reuse && c->precheck_valid) {
+        // checked on these very positions already (combined step call)
+        reuse = c->precheck_ok != 0;
+    } else if (reuse) {
         hipLaunchKernelGGL(k_list_check, dim3(nb), dim3(256), 0, c->stream, c->grid, n, x, y, h, w.xref,
                            w.yref, w.href, 1.5 * c->skin, w.list_flag);
         LAUNCHCHK(c, "list_check");
@@ -482,6 +496,7 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
         HIPCHK(c, hipStreamSynchronize(c->stream));
         reuse = (f == 0);
     }
+    c->precheck_valid = 0;
     if (reuse) {
         // the sorted positions are refreshed by the evaluation's gather
         c->list_reuses++;

@@ -130,6 +130,9 @@ struct sph_ctx {
     // when set, every rate evaluation adds its interacting ordered pairs here
     unsigned long long* pair_acc;
     int bparity;                    // which boundary-list counter the next evaluation uses
+    // a list check already done (with the inlet/outlet update of a combined
+    // step call) for the next evaluation: valid flag and outcome
+    int precheck_valid, precheck_ok;
     unsigned long long io_last[3];  // inlet/outlet event counters at the last update
 };
 
@@ -150,11 +153,15 @@ size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* 
 // rates.hip
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out);
 int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps);
+bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
 
 // adapt.hip
 int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map);
-int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map);
+int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map,
+              bool precheck = false);
+int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const sph_inout_params* io,
+                   sph_inout_map* map);
 int vorticity_run(sph_ctx* c, const sph_particles* ps, double* omega);
 int bg_solution_run(sph_ctx* c, sph_background* bg, const sph_particles* solids,
                     const sph_particles* fluid, double k_frac, int passes, int64_t* nsplit,
