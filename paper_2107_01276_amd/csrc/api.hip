@@ -92,6 +92,7 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->nl_k = list_k;
     w->nl_idx = (int32_t*)take(4 * (size_t)list_k * C);
     w->nl_cnt = (int32_t*)take(4 * C);
+    w->cnt_ex = lean ? nullptr : (int32_t*)take(4 * C);
     w->xref = (double*)take(8 * C);
     w->yref = (double*)take(8 * C);
     w->href = (double*)take(8 * C);

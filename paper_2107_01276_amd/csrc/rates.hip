@@ -21,6 +21,9 @@
 
 #include "sph_device.h"
 
+// columns of the exact neighbour rows pass A hands to pass B
+#define EX_K 160
+
 template <typename T>
 struct RatesBufs {
     T *m, *rho, *beta, *dpav, *dxs, *dys, *V, *B, *ih, *nnb;
@@ -215,12 +218,15 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
     }
 }
 
+// When ex.idx is set, pass A also writes the exact neighbours of each row
+// (self excluded), column-major with K columns, for pass B; a row with more
+// gets count K + 1 and pass B uses the skin list for it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
                                                 NbrList nl, const double4* __restrict__ pa,
                                                 typename Vec4<T>::type* pf, double rho0,
                                                 PassAOut out, double* r_dxs, double* r_dys,
-                                                const int32_t* __restrict__ kind)
+                                                const int32_t* __restrict__ kind, NbrList ex)
 {
     int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= n) return;
@@ -233,9 +239,15 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
     CSum<T> sr, sb, sp, sx, sy;
     int nn = 0;  // |N(i)|
+    int ne = 0;  // exact entries written
+    int32_t* exo = ex.idx ? ex.idx + s : nullptr;
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
         ++nn;
+        if (exo && js != s) {
+            if (ne < ex.K) exo[(int64_t)ne * ex.stride] = js;
+            ++ne;
+        }
         const T mj = b.m[js];
         const T r = fsqrt<T>((T)r2);
         const T q = r * ih;
@@ -281,6 +293,7 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     b.dxs[s] = ddx;
     b.dys[s] = ddy;
     b.nnb[s] = N;
+    if (exo) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     // per-particle factors for pass B, packed with rho and m; the volume of
     // a solid (wall) particle is stored negated, which tells pass B to use
     // its ghost velocity in the viscous term
@@ -315,7 +328,7 @@ struct PassBParams {
 // of everything else.
 template <typename T, bool GH>
 __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                NbrList nl, const double4* __restrict__ pa,
+                                                NbrList nl, NbrList ex, const double4* __restrict__ pa,
                                                 const double2* __restrict__ puv,
                                                 const typename Vec4<T>::type* __restrict__ pf,
                                                 const double* __restrict__ ugs,
@@ -393,8 +406,33 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
             vy += cv * vij;
         }
     };
+    const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
     const int cnt = nl.cnt[s];
-    if (cnt <= nl.K) {
+    if (ecnt <= ex.K) {
+        // the exact neighbours pass A found (self excluded), four at a time
+        int k = 0;
+        for (; k + 4 <= ecnt; k += 4) {
+            int j[4];
+            double4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) j[u] = ex.idx[(int64_t)(k + u) * ex.stride + s];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double dx = mi_axis(g, 0, xi - a[u].x);
+                const double dy = mi_axis(g, 1, yi - a[u].y);
+                body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w);
+            }
+        }
+        for (; k < ecnt; ++k) {
+            const int js = ex.idx[(int64_t)k * ex.stride + s];
+            const double4 a = pa[js];
+            const double dx = mi_axis(g, 0, xi - a.x);
+            const double dy = mi_axis(g, 1, yi - a.y);
+            body(js, dx, dy, dx * dx + dy * dy, a.z, a.w);
+        }
+    } else if (cnt <= nl.K) {
         for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
     } else {
         for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]),
@@ -558,19 +596,23 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
                        w.ugs, w.vgs, kind);
     LAUNCHCHK(c, "gather_state");
     prof_begin(c, SPH_PROF_PASS_A);
+    // exact rows for pass B in the adaptation CSR buffer (free during the
+    // rate passes; absent from a lean workspace)
+    NbrList ex{w.col_tmp, w.cnt_ex, EX_K, n, nullptr};
+    if (!w.col_tmp || !w.cnt_ex || w.col_cap < (int64_t)EX_K * n) ex.idx = nullptr;
     hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind);
+                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B);
     if (gh)
         hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                           ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
                            (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt);
     else
         hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                           ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
                            (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");

@@ -84,7 +84,8 @@ struct Work {
     int32_t *tmp_i32[2];
     int64_t *tmp_i64[3];
     int64_t* red;          // reduction scratch
-    int32_t *nl_idx, *nl_cnt; // pass A -> pass B neighbour list
+    int32_t *nl_idx, *nl_cnt; // rate passes' neighbour list (with skin)
+    int32_t* cnt_ex;          // row counts of the exact rows pass A writes for pass B
     int32_t nl_k;
     double *xref, *yref, *href; // state the list was built on (slot order)
     double *ug, *vg;            // viscous-term velocity (ghost velocity of walls), slot order
