@@ -394,18 +394,15 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
     double sx = 0.0, sy = 0.0;
     double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
     const double xi = ai.x, yi = ai.y, hi = ai.z;
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        const double4 aj = A[j];
+    auto term = [&](const double4& aj, const double4& bj) __attribute__((always_inline)) {
         const double dx = mi_axis(g, 0, xi - aj.x);
         const double dy = mi_axis(g, 1, yi - aj.y);
         const double r2 = dx * dx + dy * dy;
         const double hj = aj.z;
         const double RR = 3.0 * (hi > hj ? hi : hj);
-        if (!(r2 < RR * RR)) continue;  // the row may be a superset of N(i)
+        if (!(r2 < RR * RR)) return;  // the row may be a superset of N(i)
         const double r = sqrt(r2);
-        if (r <= 0.0) continue;
-        const double4 bj = B[j];
+        if (r <= 0.0) return;
         const double mj = aj.w;
         // shifting term at h_ij
         const double hij = 0.5 * (hi + hj);
@@ -422,6 +419,27 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
         gux += Vj * du * wx; guy += Vj * du * wy;
         gvx += Vj * dv * wx; gvy += Vj * dv * wy;
         gpx += Vj * dp * wx; gpy += Vj * dp * wy;
+    };
+    // four entries' loads are issued before their terms, which are then
+    // added one by one in column order
+    int64_t k = rp[i];
+    const int64_t e = rp[i + 1];
+    for (; k + 4 <= e; k += 4) {
+        int j[4];
+        double4 aj[4], bj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) j[u] = col[k + u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            aj[u] = A[j[u]];
+            bj[u] = B[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(aj[u], bj[u]);
+    }
+    for (; k < e; ++k) {
+        const int j = col[k];
+        term(A[j], B[j]);
     }
     const double pref = -0.5 * (hi * hi);
     double ddx = pref * sx, ddy = pref * sy;
@@ -475,15 +493,24 @@ __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* _
     const double xi = ai.x, yi = ai.y, hi = ai.z;
     double sm = 0.0;
     int64_t cnt = 0;
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const double4 aj = A[col[k]];
+    auto term = [&](const double4& aj) __attribute__((always_inline)) {
         const double dx = mi_axis(g, 0, xi - aj.x);
         const double dy = mi_axis(g, 1, yi - aj.y);
         const double RR = 3.0 * (hi > aj.z ? hi : aj.z);
-        if (!(dx * dx + dy * dy < RR * RR)) continue;
+        if (!(dx * dx + dy * dy < RR * RR)) return;
         sm += aj.w;
         ++cnt;
+    };
+    int64_t k = rp[i];
+    const int64_t e = rp[i + 1];
+    for (; k + 4 <= e; k += 4) {
+        double4 aj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) aj[u] = A[col[k + u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) term(aj[u]);
     }
+    for (; k < e; ++k) term(A[col[k]]);
     const double mbar = sm / (double)cnt;
     nh[i] = hdx * sqrt(mbar / rho[i]);
 }
