@@ -278,18 +278,26 @@ __device__ __forceinline__ void for_each_neighbor_level(const Grid& g, const Nbr
                 }
             }
         }
+        auto test = [&](int js, const double4& aj) __attribute__((always_inline)) {
+            const double dx = mi_axis(g, 0, xi - aj.x);
+            const double dy = mi_axis(g, 1, yi - aj.y);
+            const double r2 = dx * dx + dy * dy;
+            const double hm = hi > aj.z ? hi : aj.z;
+            const double RR = (3.0 * hm) * sf;
+            if (r2 < RR * RR) f(js, dx, dy, r2, aj.z);
+        };
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            for (int js = se[k].x; js < se[k].y; ++js) {
-                const double4 aj = nv.xyh[js];
-                const double xj = aj.x, yj = aj.y, hj = aj.z;
-                const double dx = mi_axis(g, 0, xi - xj);
-                const double dy = mi_axis(g, 1, yi - yj);
-                const double r2 = dx * dx + dy * dy;
-                const double hm = hi > hj ? hi : hj;
-                const double RR = (3.0 * hm) * sf;
-                if (r2 < RR * RR) f(js, dx, dy, r2, hj);
+            // runs are contiguous: four records are loaded before they are tested
+            int js = se[k].x;
+            for (; js + 4 <= se[k].y; js += 4) {
+                double4 a[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = nv.xyh[js + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) test(js + u, a[u]);
             }
+            for (; js < se[k].y; ++js) test(js, nv.xyh[js]);
         }
         return;
     }

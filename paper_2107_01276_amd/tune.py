@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import torch
 
-CANDIDATES = (0.05, 0.1, 0.15, 0.2, 0.3)
+CANDIDATES = (0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5)
 
 
 def tune_list_skin(make, run_steps, steps: int = 20, warmup: int = 2, candidates=CANDIDATES):
