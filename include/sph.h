@@ -337,10 +337,11 @@ int sph_step_inout(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps,
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 
-/* Profiling: when enabled, the library brackets every launch of the named
- * kernel ("pass_a", "pass_b", "build") with HIP events on its stream and
- * accumulates the elapsed time.  sph_profile_read synchronises and returns
- * total milliseconds and launch count since the last reset. */
+/* Profiling: `on` is a bit mask of the kernels to bracket with HIP events
+ * on the context's stream (1 "pass_a", 2 "pass_b", 4 "build" (neighbour
+ * sort and tables), 8 "list" (rate-pass list)); 0 turns profiling off.
+ * sph_profile_read synchronises and returns total milliseconds and launch
+ * count of the named kernel since the last reset. */
 int sph_profile_enable(sph_ctx *ctx, int32_t on);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, double *ms, int64_t *launches);
 int sph_profile_reset(sph_ctx *ctx);

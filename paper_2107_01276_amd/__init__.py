@@ -460,8 +460,11 @@ class Context:
 
     # -- profiling ---------------------------------------------------------
 
-    def profile(self, on: bool = True):
-        self._check(self.lib.sph_profile_enable(self._h, int(on)))
+    PROFILE_BITS = {"pass_a": 1, "pass_b": 2, "build": 4, "list": 8}
+
+    def profile(self, on: bool = True, kernels=("pass_a", "pass_b", "build", "list")):
+        mask = sum(self.PROFILE_BITS[k] for k in kernels) if on else 0
+        self._check(self.lib.sph_profile_enable(self._h, int(mask)))
 
     def profile_reset(self):
         self._check(self.lib.sph_profile_reset(self._h))

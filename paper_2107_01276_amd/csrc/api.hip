@@ -384,7 +384,7 @@ static void prof_flush(sph_ctx* c, int slot)
 
 void prof_begin(sph_ctx* c, int slot)
 {
-    if (!c->prof_on) return;
+    if (!c->prof_on || !(c->prof_mask & (1 << slot))) return;
     ProfSlot& s = c->prof[slot];
     if (s.count == 512) prof_flush(c, slot);
     hipEventRecord(s.ev[0][s.count], c->stream);
@@ -392,7 +392,7 @@ void prof_begin(sph_ctx* c, int slot)
 
 void prof_end(sph_ctx* c, int slot)
 {
-    if (!c->prof_on) return;
+    if (!c->prof_on || !(c->prof_mask & (1 << slot))) return;
     ProfSlot& s = c->prof[slot];
     hipEventRecord(s.ev[1][s.count], c->stream);
     s.count++;
@@ -401,6 +401,7 @@ void prof_end(sph_ctx* c, int slot)
 extern "C" int sph_profile_enable(sph_ctx* c, int32_t on)
 {
     if (!c) return SPH_E_INVAL;
+    c->prof_mask = on & 15;
     if (on && !c->prof_on) {
         for (int s = 0; s < 4; ++s) {
             for (int k = 0; k < 512; ++k) {

@@ -118,6 +118,7 @@ struct sph_ctx {
     int32_t nsort_blocks_max;
     char err[512];
     int32_t prof_on;
+    int32_t prof_mask;  // which slots are bracketed (bit = slot)
     ProfSlot prof[4];
     int built_n;       // particle count of the last build
     // Neighbour-list reuse: the list holds every pair closer than
