@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--serve-arena-gib", type=float, default=4.0)
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--list-skin", type=float, default=None,
+                    help="use this list skin for both precisions instead of timing the "
+                         "candidates first (for profiled runs)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="for hardware-counter runs: a calibration copy of known size, then a "
                          "few FP32 rate evaluations of the channel; prints nothing else")
@@ -233,8 +236,11 @@ def main():
     results = {}
     for name, prec, steps in (("fp32", SPH.SPH_FP32, args.steps),
                               ("fp64", SPH.SPH_FP64, args.fp64_steps)):
-        tuning[name] = tune.tune_list_skin(maker(prec), run_steps,
-                                           steps=2 * max(args.adapt_every, 10))
+        if args.list_skin is None:
+            tuning[name] = tune.tune_list_skin(maker(prec), run_steps,
+                                               steps=2 * max(args.adapt_every, 10))
+        else:
+            tuning[name] = {"best": args.list_skin, "ms_per_step": None}
         ctx, P, B = prepare(SPH, W, s, bg, prec, cap, tuning[name]["best"])
         ms, prof, pairs = run(ctx, P, B, dt, steps, args.warmup, args.adapt_every, torch, s["io"])
         ms_step = ms / steps
