@@ -23,6 +23,40 @@
 
 // columns of the exact neighbour rows pass A hands to pass B
 #define EX_K 160
+// Pair arithmetic of the rate passes: FMA contraction is allowed inside it
+// (the neighbour predicate, outside it, stays uncontracted).
+#define RATES_FP_CONTRACT _Pragma("clang fp contract(fast)")
+
+// The spline and its derivative for the rate passes.  In double the
+// branch-free form (every bracket clamped at zero) is faster; in float the
+// branches that skip vanished brackets are.
+template <typename T>
+__device__ __forceinline__ void rate_kern(T q, T& f, T& fp)
+{
+    if constexpr (sizeof(T) == 8) {
+        RATES_FP_CONTRACT
+        const T a = fmax(T(3) - q, T(0)), b = fmax(T(2) - q, T(0)), c = fmax(T(1) - q, T(0));
+        const T a2 = a * a, b2 = b * b, c2 = c * c;
+        const T a4 = a2 * a2, b4 = b2 * b2, c4 = c2 * c2;
+        f = a4 * a - T(6) * (b4 * b) + T(15) * (c4 * c);
+        fp = T(-5) * a4 + T(30) * b4 - T(75) * c4;
+    } else {
+        f = kern_f<T>(q);
+        fp = kern_fp<T>(q);
+    }
+}
+template <typename T>
+__device__ __forceinline__ T rate_kern_fp(T q)
+{
+    if constexpr (sizeof(T) == 8) {
+        RATES_FP_CONTRACT
+        const T a = fmax(T(3) - q, T(0)), b = fmax(T(2) - q, T(0)), c = fmax(T(1) - q, T(0));
+        const T a2 = a * a, b2 = b * b, c2 = c * c;
+        return T(-5) * (a2 * a2) + T(30) * (b2 * b2) - T(75) * (c2 * c2);
+    } else {
+        return kern_fp<T>(q);
+    }
+}
 
 template <typename T>
 struct RatesBufs {
@@ -239,37 +273,45 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
     CSum<T> sr, sb, sp, sx, sy;
     int nn = 0;  // |N(i)|
+    // one pair's terms; r = 0 (the self pair, or coincident particles)
+    // adds nothing to the shift sums
+    auto terms = [&](double dx, double dy, double r2, double hj, double pj, T mj)
+        __attribute__((always_inline)) {
+        RATES_FP_CONTRACT
+        const T r = fsqrt<T>((T)r2);
+        T f, fp;
+        rate_kern<T>(r * ih, f, fp);
+        sr.add(mj * (sig * f));
+        sb.add(mj * r * (sig * ih * fp));
+        sp.add((T)(pj - pi));
+        const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
+        T fij, fpij;
+        rate_kern<T>(r * ihij, fij, fpij);
+        const T wr = fij * ifxi;
+        const T wr2 = wr * wr;
+        const T coef = (mj * irho0) * (T(1) + T(0.24) * (wr2 * wr2));
+        const T dwij = T(SPH_SIGMA2) * ihij * ihij * ihij * fpij;
+        const T t = r > T(0) ? coef * dwij * rcp<T>(r) : T(0);
+        sx.add(t * (T)dx);
+        sy.add(t * (T)dy);
+    };
+    const int cnt = nl.cnt[s];
+    int32_t* exo = (ex.idx && cnt <= nl.K) ? ex.idx : nullptr;
     int ne = 0;  // exact entries written
-    int32_t* exo = ex.idx ? ex.idx + s : nullptr;
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
         ++nn;
         if (exo && js != s) {
-            if (ne < ex.K) exo[(int64_t)ne * ex.stride] = js;
+            if (ne < ex.K) exo[(int64_t)ne * ex.stride + s] = js;
             ++ne;
         }
-        const T mj = b.m[js];
-        const T r = fsqrt<T>((T)r2);
-        const T q = r * ih;
-        sr.add(mj * (sig * kern_f<T>(q)));
-        sb.add(mj * r * (sig * ih * kern_fp<T>(q)));
-        sp.add((T)(pj - pi));
-        if (r > T(0)) {
-            const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
-            const T qij = r * ihij;
-            const T wr = kern_f<T>(qij) * ifxi;
-            const T wr2 = wr * wr;
-            const T coef = (mj * irho0) * (T(1) + T(0.24) * (wr2 * wr2));
-            const T dwij = T(SPH_SIGMA2) * ihij * ihij * ihij * kern_fp<T>(qij);
-            const T t = coef * dwij * rcp<T>(r);
-            sx.add(t * (T)dx);
-            sy.add(t * (T)dy);
-        }
+        terms(dx, dy, r2, hj, pj, b.m[js]);
     };
-    const int cnt = nl.cnt[s];
     if (cnt <= nl.K) {
         for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
+        if (exo) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     } else {
+        if (ex.idx) ex.cnt[s] = ex.K + 1;
         for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
             body(js, dx, dy, r2, hj, pa[js].w);
         });
@@ -293,7 +335,6 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     b.dxs[s] = ddx;
     b.dys[s] = ddy;
     b.nnb[s] = N;
-    if (exo) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     // per-particle factors for pass B, packed with rho and m; the volume of
     // a solid (wall) particle is stored negated, which tells pass B to use
     // its ghost velocity in the viscous term
@@ -366,14 +407,16 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     T gx = 0, gy = 0, vx = 0, vy = 0;
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
+        RATES_FP_CONTRACT
         const T r = fsqrt<T>((T)r2);
-        if (!(r > T(0))) return;  // the self pair contributes nothing
         const double2 uvj = puv[js];
         const typename Vec4<T>::type fj4 = pf[js];
-        const T ir = rcp<T>(r);
+        // r = 0 (the self pair, or coincident particles): every term below
+        // carries a factor 1/r * r-free gradient or r itself, and is zero
+        const T ir = r > T(0) ? rcp<T>(r) : T(0);
         const T ihj = rcp<T>((T)hj);
-        const T dwi = sigi * kern_fp<T>(r * ih);
-        const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * kern_fp<T>(r * ihj);
+        const T dwi = sigi * rate_kern_fp<T>(r * ih);
+        const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * rate_kern_fp<T>(r * ihj);
         const T fi = dwi * ir, fj = dwj * ir;
         const T dxT = (T)dx, dyT = (T)dy;
         const T uij = (T)(ui - uvj.x), vij = (T)(vi - uvj.y);
