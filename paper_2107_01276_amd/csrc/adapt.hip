@@ -29,6 +29,9 @@ int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
 // Ballot compaction: rank[i] = number of set flags before i; returns total.
 // ---------------------------------------------------------------------------
 
+// lanes per particle in the cell walks of the m_ref lookup and the merge search
+#define WG 4
+
 __global__ __launch_bounds__(256) void k_flag_count(int n, const int32_t* __restrict__ flag,
                                                     int32_t* bcount)
 {
@@ -87,18 +90,29 @@ __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
                                                      double* mref_out, int32_t* none,
                                                      const int32_t* __restrict__ order)
 {
-    int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = tt / WG, gl = tt % WG;
     if (t >= n) return;
     const int i = order ? order[t] : t;
     const double xi = x[i], yi = y[i], hi = h[i];
     const int li = level_of(g, hi);
     double mn = 0.0;
     int found = 0;
-    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double, double, double, double) {
+    group_walk<WG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double, double, double, double) {
+        if (!pass) return;
         double v = bmref[nv.perm[js]];
         if (!found || v < mn) mn = v;
         found = 1;
     });
+    // the minimum over the group's lanes (exact, independent of order)
+#pragma unroll
+    for (int o = 1; o < WG; o <<= 1) {
+        const double mo = __shfl_xor(mn, o, 64);
+        const int fo = __shfl_xor(found, o, 64);
+        if (fo && (!found || mo < mn)) mn = mo;
+        found |= fo;
+    }
+    if (gl) return;
     none[i] = !found;
     if (found) mref_out[i] = mn;
 }
@@ -143,7 +157,7 @@ static int mref_lookup_into(sph_ctx* c, const sph_particles* ps, const sph_backg
     int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
     if (rc) return rc;
     NbrView nv = nbr_view(c);
-    hipLaunchKernelGGL(k_mref_lookup, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
+    hipLaunchKernelGGL(k_mref_lookup, dim3((unsigned)cdiv((int64_t)n * WG, 256)), dim3(256), 0, c->stream, c->grid,
                        nv, n, ps->x, ps->y, ps->h, bg->mref, mref_out, w.flag, order);
     hipLaunchKernelGGL(k_mref_nearest, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
                        n, ps->x, ps->y, w.flag, nb, bg->x, bg->y, bg->mref, mref_out);
@@ -226,7 +240,8 @@ __global__ __launch_bounds__(256) void k_split_apply(Grid g, int n, FluidState s
 __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n, FluidState s,
                                                        double q, double mmax_f, int32_t* closest)
 {
-    int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int sp = tt / WG, gl = tt % WG;
     if (sp >= n) return;
     const int i = nv.perm[sp];
     const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
@@ -239,7 +254,8 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     if (ki == SPH_FLUID && !(mi > mmi)) {
         // a merge partner lies within (h_i + h_j)/2 <= max(h_i, h_j): a third
         // of the support radius (0.34 leaves margin for rounding) bounds it
-        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
+        group_walk<WG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+            if (!pass) return;
             const int j = nv.perm[js];
             if (j == i) return;
             if (s.kind && s.kind[j] != SPH_FLUID) return;
@@ -257,7 +273,17 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
             }
         }, 0.34);
     }
-    closest[i] = best;
+    // the group's closest (ties to the lower slot), independent of order
+#pragma unroll
+    for (int o = 1; o < WG; o <<= 1) {
+        const int bo = __shfl_xor(best, o, 64);
+        const double ro = __shfl_xor(br, o, 64);
+        if (bo >= 0 && (best < 0 || ro < br || (ro == br && bo < best))) {
+            best = bo;
+            br = ro;
+        }
+    }
+    if (gl == 0) closest[i] = best;
 }
 
 __global__ __launch_bounds__(256) void k_merge_keep(int n, const int32_t* __restrict__ closest,
@@ -631,7 +657,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (rc) return rc;
         NbrView nv = nbr_view(c);
         unsigned nb = (unsigned)cdiv(n, 256);
-        hipLaunchKernelGGL(k_merge_closest, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, s,
+        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * WG, 256)), dim3(256), 0, c->stream, c->grid, nv, n, s,
                            cf.mass_q, cf.mmax_f, w.closest);
         hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, w.closest, w.flag);
         LAUNCHCHK(c, "merge_closest");

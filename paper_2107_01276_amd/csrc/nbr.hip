@@ -466,26 +466,31 @@ NbrView nbr_view(sph_ctx* c)
 // walk the cells again for that row).
 // ---------------------------------------------------------------------------
 
-// Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate).
+// Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate); LG lanes
+// per row walk the cells together.
+#define LG 4
 __global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int n, NbrList nl,
                                                          double sf)
 {
-    const int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int s = t / LG, gl = t % LG;
     if (s >= n) return;
     const double4 a = nv.xyh[s];
     const int li = key_level(g, nv.keys[s]);
     int cnt = 0;
-    int32_t* out = nl.idx + s;
-    int32_t* const last = nl.idx + (int64_t)(nl.K - 1) * nl.stride + s;
-    for_each_neighbor(g, nv, a.x, a.y, a.z, li,
-                      [&](int js, double, double, double, double) {
-                          *out = js;
-                          out = out == last ? out : out + nl.stride;
-                          ++cnt;
-                      },
-                      sf);
-    nl.cnt[s] = cnt;
-    if (cnt > nl.K) nl.flag[0] = 1;
+    int32_t* const row = nl.idx + s;
+    group_walk<LG>(g, nv, a.x, a.y, a.z, li, gl,
+                   [&](int js, bool pass, double, double, double, double) {
+                       int tot;
+                       const int k = cnt + group_rank<LG>(pass, gl, &tot);
+                       if (pass && k < nl.K) row[(int64_t)k * nl.stride] = js;
+                       cnt += tot;
+                   },
+                   sf);
+    if (gl == 0) {
+        nl.cnt[s] = cnt;
+        if (cnt > nl.K) nl.flag[0] = 1;
+    }
 }
 
 int nbr_build_list(sph_ctx* c, int n, double skin)
@@ -496,7 +501,7 @@ int nbr_build_list(sph_ctx* c, int n, double skin)
     prof_begin(c, SPH_PROF_LIST);
     const Grid& g = c->grid;
     const double sf = 1.0 + skin;
-    hipLaunchKernelGGL(k_build_list_lane, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g,
+    hipLaunchKernelGGL(k_build_list_lane, dim3((unsigned)cdiv((int64_t)n * LG, 256)), dim3(256), 0, c->stream, g,
                        nbr_view(c), n, nl, sf);
     prof_end(c, SPH_PROF_LIST);
     LAUNCHCHK(c, "build_list");
@@ -575,19 +580,26 @@ __global__ __launch_bounds__(256) void k_csr_stage(Grid g, NbrView nv, int n, in
                                                    int64_t* __restrict__ cnt, int32_t* flag,
                                                    double sf)
 {
-    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int s = t / LG, gl = t % LG;
     if (s >= n) return;
     double xi = nv.xs[s], yi = nv.ys[s], hi = nv.hs[s];
     int li = key_level(g, nv.keys[s]);
     const int slot = nv.perm[s];
     int32_t* row = stage + (int64_t)slot * K;
     int k = 0;
-    for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double, double, double, double) {
-        if (k < K) row[k] = nv.perm[js];
-        ++k;
-    }, sf);
-    cnt[slot] = k;
-    if (k > K) flag[0] = 1;
+    group_walk<LG>(g, nv, xi, yi, hi, li, gl,
+                   [&](int js, bool pass, double, double, double, double) {
+                       int tot;
+                       const int e = k + group_rank<LG>(pass, gl, &tot);
+                       if (pass && e < K) row[e] = nv.perm[js];
+                       k += tot;
+                   },
+                   sf);
+    if (gl == 0) {
+        cnt[slot] = k;
+        if (k > K) flag[0] = 1;
+    }
 }
 
 // One wave per row: bitonic sort of up to 64 R entries held R per lane
@@ -665,7 +677,7 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     c->list_valid = 0;
     if (n > 0) {
         hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.status, (int64_t)4);
-        hipLaunchKernelGGL(k_csr_stage, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, nv,
+        hipLaunchKernelGGL(k_csr_stage, dim3((unsigned)cdiv((int64_t)n * LG, 256)), dim3(256), 0, c->stream, g, nv,
                            n, K, w.nl_idx, w.cnt64, w.status + 2, sf);
         LAUNCHCHK(c, "csr_stage");
     }

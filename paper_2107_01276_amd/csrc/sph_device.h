@@ -340,6 +340,87 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& 
     }
 }
 
+// ---- the same walk shared by a group of G adjacent lanes ------------------
+// The G lanes of a group (lane gl of the group, 0 <= gl < G) hold the same
+// particle i and visit the same cells; within every cell run the records are
+// dealt round-robin to the lanes, so a group reads consecutive records
+// together and each lane tests about 1/G of the candidates.  f(js, pass, dx,
+// dy, r2, hj) is called by all G lanes together (the loop bounds depend only
+// on i), once per record slot: `pass` is false for a slot past the run's end
+// (whose js is not a record to use) and for a record outside the support.
+template <int G, class F>
+__device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& nv, double xi,
+                                                 double yi, double hi, int li, int l, int gl,
+                                                 F&& f, double sf)
+{
+    const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
+    const double R = 3.0 * (hi > hl ? hi : hl) * sf;
+    const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
+    const double Rs2 = Rs * Rs;
+    const int Q = l > li ? l : li;
+    const Span xr = axis_span(g, 0, xi, R, Q);
+    const Span yr = axis_span(g, 1, yi, R, Q);
+    const int2* tab = nv.tab + g.lbase[l] + g.cumq[Q];
+    const int nq = g.nxq[Q][0];
+    auto run = [&](int2 se) __attribute__((always_inline)) {
+        for (int base = se.x; base < se.y; base += 4 * G) {
+            int js[4];
+            double4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                js[u] = base + gl + G * u;
+                // a slot past the end reads the run's first record (in bounds)
+                a[u] = nv.xyh[js[u] < se.y ? js[u] : se.x];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double dx = mi_axis(g, 0, xi - a[u].x);
+                const double dy = mi_axis(g, 1, yi - a[u].y);
+                const double r2 = dx * dx + dy * dy;
+                const double hm = hi > a[u].z ? hi : a[u].z;
+                const double RR = (3.0 * hm) * sf;
+                f(js[u], js[u] < se.y && r2 < RR * RR, dx, dy, r2, a[u].z);
+            }
+        }
+    };
+    for (int ty = 0; ty < yr.n; ++ty) {
+        const int cy0 = ty ? yr.a1 : yr.a0, cy1 = ty ? yr.b1 : yr.b0;
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const double gy = cell_gap(g, 1, yi, cy, Q);
+            if (gy > Rs) continue;
+            for (int tx = 0; tx < xr.n; ++tx) {
+                const int cx0 = tx ? xr.a1 : xr.a0, cx1 = tx ? xr.b1 : xr.b0;
+                for (int cx = cx0; cx <= cx1; ++cx) {
+                    const double gx = cell_gap(g, 0, xi, cx, Q);
+                    if (gx * gx + gy * gy > Rs2) continue;
+                    run(tab[(int64_t)cy * nq + cx]);
+                }
+            }
+        }
+    }
+}
+
+template <int G, class F>
+__device__ __forceinline__ void group_walk(const Grid& g, const NbrView& nv, double xi, double yi,
+                                           double hi, int li, int gl, F&& f, double sf = 1.0)
+{
+    for (int l = 0; l < g.nlev; ++l) {
+        if (nv.lcount[l] == 0) continue;
+        group_walk_level<G>(g, nv, xi, yi, hi, li, l, gl, f, sf);
+    }
+}
+
+// Rank of this lane's `pass` among the passing lanes of its group of G
+// (lanes G k .. G k + G - 1 of the wave), and the group's pass count.
+template <int G>
+__device__ __forceinline__ int group_rank(bool pass, int gl, int* total)
+{
+    const unsigned long long bal = __ballot(pass);
+    const unsigned gm = (unsigned)(bal >> (__lane_id() & ~(G - 1))) & ((1u << G) - 1u);
+    *total = __popc(gm);
+    return __popc(gm & ((1u << gl) - 1u));
+}
+
 // ---- XCD-aware block order -----------------------------------------------------
 // Workgroups are dispatched to the 8 XCDs round-robin (XCD = blockIdx % 8),
 // and each XCD has its own L2.  Renumbering so that XCD x runs a contiguous
