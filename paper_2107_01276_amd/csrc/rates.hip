@@ -23,6 +23,9 @@
 
 // columns of the exact neighbour rows pass A hands to pass B
 #define EX_K 160
+// lanes per particle in pass A and in pass B
+#define RGA 4
+#define RGB 2
 // Pair arithmetic of the rate passes: FMA contraction is allowed inside it
 // (the neighbour predicate, outside it, stays uncontracted).
 #define RATES_FP_CONTRACT _Pragma("clang fp contract(fast)")
@@ -262,7 +265,8 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
                                                 PassAOut out, double* r_dxs, double* r_dys,
                                                 const int32_t* __restrict__ kind, NbrList ex)
 {
-    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int s = t / RGA, gl = t % RGA;
     if (s >= n) return;
     const double4 ai = pa[s];
     const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
@@ -297,25 +301,64 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     };
     const int cnt = nl.cnt[s];
     int32_t* exo = (ex.idx && cnt <= nl.K) ? ex.idx : nullptr;
-    int ne = 0;  // exact entries written
-    auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
+    int ne = 0;  // exact entries of the row (the same in every lane of the group)
+    // called by all lanes of the group together; `pass` marks a neighbour
+    auto body = [&](int js, bool pass, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
-        ++nn;
-        if (exo && js != s) {
-            if (ne < ex.K) exo[(int64_t)ne * ex.stride + s] = js;
-            ++ne;
+        const bool ext = pass && js != s;
+        int tot;
+        const int k = ne + group_rank<RGA>(ext, gl, &tot);
+        if (exo && ext && k < ex.K) exo[(int64_t)k * ex.stride + s] = js;
+        ne += tot;
+        if (pass) {
+            ++nn;
+            terms(dx, dy, r2, hj, pj, b.m[js]);
         }
-        terms(dx, dy, r2, hj, pj, b.m[js]);
     };
     if (cnt <= nl.K) {
-        for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
-        if (exo) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
+        // the lanes of the group take every RGA-th entry of the row; four
+        // entries' loads are issued before their tests
+        const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+        for (int base = 0; base < cnt; base += 4 * RGA) {
+            int j[4];
+            double4 a[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = base + gl + RGA * u;
+                j[u] = k < cnt ? nl.idx[(int64_t)k * nl.stride + s] : s;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double dx = mi_axis(g, 0, xi - a[u].x);
+                const double dy = mi_axis(g, 1, yi - a[u].y);
+                const double r2 = dx * dx + dy * dy;
+                const double rj3 = 3.0 * a[u].z;
+                const bool pass = base + gl + RGA * u < cnt && r2 < fmax(ri2, rj3 * rj3);
+                body(j[u], pass, dx, dy, r2, a[u].z, a[u].w);
+            }
+        }
+        if (exo && gl == 0) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     } else {
-        if (ex.idx) ex.cnt[s] = ex.K + 1;
-        for_each_neighbor(g, nv, xi, yi, hi, li, [&](int js, double dx, double dy, double r2, double hj) {
-            body(js, dx, dy, r2, hj, pa[js].w);
-        });
+        if (ex.idx && gl == 0) ex.cnt[s] = ex.K + 1;
+        exo = nullptr;
+        group_walk<RGA>(g, nv, xi, yi, hi, li, gl,
+                       [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+                           body(js, pass, dx, dy, r2, hj, pass ? pa[js].w : 0.0);
+                       });
     }
+    // the group's partial sums, combined in every lane
+#pragma unroll
+    for (int o = 1; o < RGA; o <<= 1) {
+        sr.merge_xor(o);
+        sb.merge_xor(o);
+        sp.merge_xor(o);
+        sx.merge_xor(o);
+        sy.merge_xor(o);
+        nn += __shfl_xor(nn, o, 64);
+    }
+    if (gl) return;
     const T rho = sr.get();
     const T beta = -sb.get() / (T(2) * rho);
     const T N = (T)nn;
@@ -376,7 +419,8 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
                                                 const double* __restrict__ vgs, PassBParams P,
                                                 double* dpdt, double* dudt, double* dvdt)
 {
-    int s = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int s = t / RGB, gl = t % RGB;
     if (s >= n) return;
     const double4 ai = pa[s];
     const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
@@ -451,14 +495,16 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     };
     const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
     const int cnt = nl.cnt[s];
+    // the lanes of the group take every RGB-th entry of the row
     if (ecnt <= ex.K) {
-        // the exact neighbours pass A found (self excluded), four at a time
-        int k = 0;
-        for (; k + 4 <= ecnt; k += 4) {
+        // the exact neighbours pass A found (self excluded), four per lane
+        // loaded at a time
+        int k = gl;
+        for (; k + 3 * RGB < ecnt; k += 4 * RGB) {
             int j[4];
             double4 a[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) j[u] = ex.idx[(int64_t)(k + u) * ex.stride + s];
+            for (int u = 0; u < 4; ++u) j[u] = ex.idx[(int64_t)(k + RGB * u) * ex.stride + s];
 #pragma unroll
             for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
 #pragma unroll
@@ -468,7 +514,7 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
                 body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w);
             }
         }
-        for (; k < ecnt; ++k) {
+        for (; k < ecnt; k += RGB) {
             const int js = ex.idx[(int64_t)k * ex.stride + s];
             const double4 a = pa[js];
             const double dx = mi_axis(g, 0, xi - a.x);
@@ -476,13 +522,33 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
             body(js, dx, dy, dx * dx + dy * dy, a.z, a.w);
         }
     } else if (cnt <= nl.K) {
-        for_each_listed_packed(g, pa, nl, s, cnt, xi, yi, hi, body);
+        const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+        for (int k = gl; k < cnt; k += RGB) {
+            const int js = nl.idx[(int64_t)k * nl.stride + s];
+            const double4 a = pa[js];
+            const double dx = mi_axis(g, 0, xi - a.x);
+            const double dy = mi_axis(g, 1, yi - a.y);
+            const double r2 = dx * dx + dy * dy;
+            const double rj3 = 3.0 * a.z;
+            if (r2 < fmax(ri2, rj3 * rj3)) body(js, dx, dy, r2, a.z, a.w);
+        }
     } else {
-        for_each_neighbor(g, nv, xi, yi, hi, key_level(g, nv.keys[s]),
-                          [&](int js, double dx, double dy, double r2, double hj) {
-                              body(js, dx, dy, r2, hj, pa[js].w);
-                          });
+        group_walk<RGB>(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), gl,
+                       [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+                           if (pass) body(js, dx, dy, r2, hj, pa[js].w);
+                       });
     }
+    // the group's partial sums, combined in every lane
+#pragma unroll
+    for (int o = 1; o < RGB; o <<= 1) {
+        sdiv.merge_xor(o);
+        sdif.merge_xor(o);
+        gx += __shfl_xor(gx, o, 64);
+        gy += __shfl_xor(gy, o, 64);
+        vx += __shfl_xor(vx, o, 64);
+        vy += __shfl_xor(vy, o, 64);
+    }
+    if (gl) return;
     const T beta = b.beta[s];
     const T ib = beta > T(0) ? T(1) / beta : T(0);
     const double dxs = (double)b.dxs[s], dys = (double)b.dys[s];
@@ -643,18 +709,19 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     // rate passes; absent from a lean workspace)
     NbrList ex{w.col_tmp, w.cnt_ex, EX_K, n, nullptr};
     if (!w.col_tmp || !w.cnt_ex || w.col_cap < (int64_t)EX_K * n) ex.idx = nullptr;
-    hipLaunchKernelGGL(k_pass_a<T>, dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+    hipLaunchKernelGGL(k_pass_a<T>, dim3((unsigned)cdiv((int64_t)n * RGA, 256)), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                        (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
+    const unsigned nbb = (unsigned)cdiv((int64_t)n * RGB, 256);
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B);
     if (gh)
-        hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+        hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                            ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
                            (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt);
     else
-        hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+        hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                            ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
                            (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt);
     prof_end(c, SPH_PROF_PASS_B);

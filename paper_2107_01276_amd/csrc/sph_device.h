@@ -69,6 +69,13 @@ struct CSum {
         s = t;
     }
     __device__ __forceinline__ T get() const { return s + c; }
+    // adds the sum held by lane (this lane ^ o) of the wave
+    __device__ __forceinline__ void merge_xor(int o)
+    {
+        const T so = __shfl_xor(s, o, 64), co = __shfl_xor(c, o, 64);
+        add(so);
+        c += co;
+    }
 };
 template <>
 struct CSum<double> {
@@ -76,6 +83,7 @@ struct CSum<double> {
     __device__ __forceinline__ CSum() : s(0.0) {}
     __device__ __forceinline__ void add(double x) { s += x; }
     __device__ __forceinline__ double get() const { return s; }
+    __device__ __forceinline__ void merge_xor(int o) { s += __shfl_xor(s, o, 64); }
 };
 
 // ---- geometry -------------------------------------------------------------
