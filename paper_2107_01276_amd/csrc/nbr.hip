@@ -90,12 +90,6 @@ static int key_bits(const Grid* g)
     return 2 * g->bits + lb;
 }
 
-#define RS_THREADS 256
-#define RS_ITEMS 8
-#define RS_TILE (RS_THREADS * RS_ITEMS)
-#define SCAN_T 256
-#define SCAN_E 8
-#define SCAN_TILE (SCAN_T * SCAN_E)
 
 size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g)
 {

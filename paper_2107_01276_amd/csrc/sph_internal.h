@@ -195,4 +195,13 @@ void prof_end(sph_ctx* c, int slot);
         if (e_ != hipSuccess) return check_hip((c), e_, (what));       \
     } while (0)
 
+// Radix-sort tiles (keys per workgroup) and scan tiles; the workspace carve
+// sizes the digit histograms and the scan block sums from them.
+#define RS_THREADS 256
+#define RS_ITEMS 8
+#define RS_TILE (RS_THREADS * RS_ITEMS)
+#define SCAN_T 256
+#define SCAN_E 8
+#define SCAN_TILE (SCAN_T * SCAN_E)
+
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
