@@ -72,9 +72,8 @@ static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, 
     if (rc) return rc;
     hipLaunchKernelGGL(k_flag_rank, dim3(nb), dim3(256), 0, c->stream, n, flag, w.idx_b, rank);
     LAUNCHCHK(c, "flag_rank");
-    HIPCHK(c, hipMemcpyAsync(total, w.idx_b + nb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return SPH_OK;
+    const Readback rb{total, w.idx_b + nb, 4};
+    return readback(c, &rb, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,11 +392,68 @@ __global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double 
     B[i] = make_double4(s.u[i], s.v[i], s.p[i], s.rho[i]);
 }
 
+// The neighbours of each fluid row in the current positions, kept in
+// ascending column order: the entries of the (superset) row that pass the
+// pair predicate, self excluded, written from rp[i] on with their count in
+// rcnt[i].  Four lanes share a row; entry base + gl goes to lane gl, and
+// passing entries are ranked by lane, so the order is the row's.
+#define FG 4
+__global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32_t* __restrict__ kind,
+                                                      const double4* __restrict__ A,
+                                                      const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      int32_t* __restrict__ colf,
+                                                      int32_t* __restrict__ rcnt,
+                                                      const int32_t* __restrict__ order)
+{
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = tt / FG, gl = tt % FG;
+    if (t >= n) return;
+    const int i = order ? order[t] : t;
+    if (kind && kind[i] != SPH_FLUID) {
+        if (gl == 0) rcnt[i] = 0;
+        return;
+    }
+    const double4 ai = A[i];
+    const double xi = ai.x, yi = ai.y, hi = ai.z;
+    const int64_t b0 = rp[i], e = rp[i + 1];
+    int cnt = 0;
+    for (int64_t base = b0; base < e; base += 4 * FG) {
+        int j[4];
+        double4 aj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = base + FG * u + gl;
+            j[u] = k < e ? col[k] : i;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) aj[u] = A[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double dx = mi_axis(g, 0, xi - aj[u].x);
+            const double dy = mi_axis(g, 1, yi - aj[u].y);
+            const double r2 = dx * dx + dy * dy;
+            const double RR = 3.0 * (hi > aj[u].z ? hi : aj[u].z);
+            // r = sqrt(r2) > 0 exactly when r2 > 0
+            const bool pass = base + FG * u + gl < e && r2 < RR * RR && r2 > 0.0;
+            int tot;
+            const int k = cnt + group_rank<FG>(pass, gl, &tot);
+            if (pass) colf[b0 + k] = j[u];
+            cnt += tot;
+        }
+    }
+    if (gl == 0) rcnt[i] = cnt;
+}
+
+// EXACT: rows hold exactly the neighbours (from k_shift_filter), counts in
+// rcnt; otherwise rows may be a superset, re-tested entry by entry.
+template <bool EXACT>
 __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32_t* __restrict__ kind,
                                                       const double4* __restrict__ A,
                                                       const double4* __restrict__ B,
                                                       const int64_t* __restrict__ rp,
                                                       const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ rcnt,
                                                       double rho0, double* ddx_o, double* ddy_o,
                                                       double* nu_o, double* nv_o, double* np_o,
                                                       const int32_t* __restrict__ order)
@@ -425,10 +481,14 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
         const double dy = mi_axis(g, 1, yi - aj.y);
         const double r2 = dx * dx + dy * dy;
         const double hj = aj.z;
-        const double RR = 3.0 * (hi > hj ? hi : hj);
-        if (!(r2 < RR * RR)) return;  // the row may be a superset of N(i)
+        if constexpr (!EXACT) {
+            const double RR = 3.0 * (hi > hj ? hi : hj);
+            if (!(r2 < RR * RR)) return;  // the row may be a superset of N(i)
+        }
         const double r = sqrt(r2);
-        if (r <= 0.0) return;
+        if constexpr (!EXACT) {
+            if (r <= 0.0) return;
+        }
         const double mj = aj.w;
         // shifting term at h_ij
         const double hij = 0.5 * (hi + hj);
@@ -449,7 +509,7 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
     // four entries' loads are issued before their terms, which are then
     // added one by one in column order
     int64_t k = rp[i];
-    const int64_t e = rp[i + 1];
+    const int64_t e = EXACT ? rp[i] + rcnt[i] : rp[i + 1];
     for (; k + 4 <= e; k += 4) {
         int j[4];
         double4 aj[4], bj[4];
@@ -688,6 +748,9 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (rc == SPH_OK) super = true;
         else if (rc != SPH_E_CAPACITY) return rc;
     }
+    // each shift first filters its rows into the rate-list buffer (free
+    // here; it is rebuilt after adaptation) when that holds every row
+    const bool filt = w.cnt_ex && (int64_t)w.nl_k * w.capacity >= w.col_cap;
     for (int it = 0; it < cf.shift_iters; ++it) {
         if (n == 0) break;
         if (!super) {
@@ -699,10 +762,20 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         // rows in the sorted order of the last build (slots unchanged since)
         double4 *pA = w.pa, *pB = (double4*)w.pf;
         hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, pA, pB);
-        hipLaunchKernelGGL(k_shift_taylor, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
-                           (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
-                           w.col_tmp, cf.rho0, w.tmp_d[0], w.tmp_d[1], w.tmp_d[2], w.tmp_d[3],
-                           w.tmp_d[4], (const int32_t*)w.vals_a);
+        if (filt) {
+            hipLaunchKernelGGL(k_shift_filter, dim3((unsigned)cdiv((int64_t)n * FG, 256)), dim3(256), 0,
+                               c->stream, c->grid, n, (const int32_t*)s.kind, (const double4*)pA,
+                               w.rp_tmp, w.col_tmp, w.nl_idx, w.cnt_ex, (const int32_t*)w.vals_a);
+            hipLaunchKernelGGL(k_shift_taylor<true>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
+                               (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
+                               w.nl_idx, (const int32_t*)w.cnt_ex, cf.rho0, w.tmp_d[0], w.tmp_d[1],
+                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
+        } else {
+            hipLaunchKernelGGL(k_shift_taylor<false>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
+                               (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
+                               w.col_tmp, (const int32_t*)nullptr, cf.rho0, w.tmp_d[0], w.tmp_d[1],
+                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
+        }
         hipLaunchKernelGGL(k_shift_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.tmp_d[0],
                            w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4]);
         LAUNCHCHK(c, "shift");
@@ -1024,10 +1097,9 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     const bool checked = precheck && launch_list_check(c, n, ps->x, ps->y, ps->h);
     unsigned long long h3[3] = {0, 0, 0};
     int32_t lflag = 1;
-    HIPCHK(c, hipMemcpyAsync(h3, cnt, sizeof(h3), hipMemcpyDeviceToHost, c->stream));
-    if (checked)
-        HIPCHK(c, hipMemcpyAsync(&lflag, w.list_flag, sizeof(lflag), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Readback rb[2] = {{h3, cnt, (int)sizeof(h3)}, {&lflag, w.list_flag, 4}};
+    int rc = readback(c, rb, checked ? 2 : 1);
+    if (rc) return rc;
     const int32_t nto = (int32_t)(h3[0] - c->io_last[0]);
     const int32_t nap = (int32_t)(h3[1] - c->io_last[1]);
     const int32_t ndel = (int32_t)(h3[2] - c->io_last[2]);
@@ -1048,7 +1120,7 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
         return SPH_OK;
     }
     int32_t nkeep = 0, na = 0;
-    int rc = compact_ranks(c, n, keep, rk, &nkeep);
+    rc = compact_ranks(c, n, keep, rk, &nkeep);
     if (rc) return rc;
     rc = compact_ranks(c, n, app, ra, &na);
     if (rc) return rc;

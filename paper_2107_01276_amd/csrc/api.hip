@@ -140,6 +140,74 @@ __global__ void k_init_counters(int32_t* status, unsigned long long* ctr)
     if (t < 8) ctr[t] = 0ull;
 }
 
+// ---- host readbacks through the pinned mailbox ------------------------------
+
+#define MBOX_WORDS 64
+
+struct RbArgs {
+    const uint32_t* src[4];
+    int words[4];
+    int n;
+};
+
+// One lane copies the words, then publishes the sequence number with a
+// system-scope release, so the host sees the payload once it sees `seq`.
+__global__ void k_readback(RbArgs a, uint32_t* mbox, uint32_t seq)
+{
+    if (threadIdx.x != 0) return;
+    int o = 1;
+    for (int k = 0; k < a.n; ++k)
+        for (int w = 0; w < a.words[k]; ++w) mbox[o++] = a.src[k][w];
+    __threadfence_system();
+    __hip_atomic_store(mbox, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+int readback(sph_ctx* c, const Readback* items, int n)
+{
+    if (n < 0 || n > 4) {
+        set_err(c, "readback of %d items", n);
+        return SPH_E_INVAL;
+    }
+    RbArgs a{};
+    int tot = 0;
+    for (int k = 0; k < n; ++k) {
+        if (items[k].bytes % 4 || items[k].bytes < 0) {
+            set_err(c, "readback of %d bytes", items[k].bytes);
+            return SPH_E_INVAL;
+        }
+        a.src[k] = (const uint32_t*)items[k].src;
+        a.words[k] = items[k].bytes / 4;
+        tot += a.words[k];
+    }
+    a.n = n;
+    if (tot > MBOX_WORDS - 4) {
+        set_err(c, "readback of %d words", tot);
+        return SPH_E_INVAL;
+    }
+    uint32_t seq = ++c->mbox_seq;
+    if (seq == 0) seq = ++c->mbox_seq;
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, c->stream, a, c->mbox_dev, seq);
+    LAUNCHCHK(c, "readback");
+    // poll the mailbox; every few hundred polls ask the stream whether it
+    // failed (or finished without publishing, which would be a fault)
+    for (unsigned spin = 1;; ++spin) {
+        if (__atomic_load_n(&c->mbox[0], __ATOMIC_ACQUIRE) == seq) break;
+        if ((spin & 255) == 0) {
+            const hipError_t e = hipStreamQuery(c->stream);
+            if (e == hipErrorNotReady) continue;
+            if (e == hipSuccess && __atomic_load_n(&c->mbox[0], __ATOMIC_ACQUIRE) == seq) break;
+            set_err(c, "readback: %s", e == hipSuccess ? "mailbox not written" : hipGetErrorString(e));
+            return SPH_E_DEVICE;
+        }
+    }
+    int o = 1;
+    for (int k = 0; k < n; ++k) {
+        memcpy(items[k].dst, (const void*)(c->mbox + o), (size_t)items[k].bytes);
+        o += a.words[k];
+    }
+    return SPH_OK;
+}
+
 extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspace,
                           size_t workspace_bytes, void* stream, sph_ctx** out)
 {
@@ -159,6 +227,16 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
         return SPH_E_NOMEM;
     }
     carve(&c->w, (char*)workspace, c->grid, capacity, cfg->lean, lk);
+    void* mb = nullptr;
+    if (hipHostMalloc(&mb, MBOX_WORDS * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->mbox_dev, mb, 0) != hipSuccess) {
+        if (mb) hipHostFree(mb);
+        free(c);
+        return SPH_E_DEVICE;
+    }
+    c->mbox = (uint32_t*)mb;
+    memset(mb, 0, MBOX_WORDS * sizeof(uint32_t));
     c->prof[SPH_PROF_PASS_A].name = "pass_a";
     c->prof[SPH_PROF_PASS_B].name = "pass_b";
     c->prof[SPH_PROF_BUILD].name = "build";
@@ -167,6 +245,7 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->list_valid = 0;
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c->stream, c->w.status, c->w.ctr);
     if (hipGetLastError() != hipSuccess) {
+        hipHostFree(c->mbox);
         free(c);
         return SPH_E_DEVICE;
     }
@@ -189,6 +268,7 @@ extern "C" void sph_destroy(sph_ctx* c)
 {
     if (!c) return;
     prof_free(c);
+    hipHostFree(c->mbox);
     free(c);
 }
 

@@ -679,9 +679,9 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     if (rc) return rc;
     int64_t tot = 0;
     int32_t st[4] = {0, 0, 0, 0};
-    HIPCHK(c, hipMemcpyAsync(&tot, row_ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
-    if (n > 0) HIPCHK(c, hipMemcpyAsync(st, w.status, sizeof(st), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const Readback rb[2] = {{&tot, row_ptr + n, 8}, {st, w.status, (int)sizeof(st)}};
+    rc = readback(c, rb, n > 0 ? 2 : 1);
+    if (rc) return rc;
     *nnz = tot;
     if (tot > cap) {
         set_err(c, "neighbour list needs %lld entries, capacity %lld", (long long)tot, (long long)cap);

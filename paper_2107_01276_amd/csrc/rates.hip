@@ -639,8 +639,9 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
                            w.yref, w.href, 1.5 * c->skin, w.list_flag);
         LAUNCHCHK(c, "list_check");
         int32_t f = 1;
-        HIPCHK(c, hipMemcpyAsync(&f, w.list_flag, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        const Readback rb{&f, w.list_flag, 4};
+        int rc = readback(c, &rb, 1);
+        if (rc) return rc;
         reuse = (f == 0);
     }
     c->precheck_valid = 0;

@@ -136,7 +136,24 @@ struct sph_ctx {
     // step call) for the next evaluation: valid flag and outcome
     int precheck_valid, precheck_ok;
     unsigned long long io_last[3];  // inlet/outlet event counters at the last update
+    // small host readbacks: pinned, device-coherent words written by a
+    // one-lane kernel; word 0 carries the sequence number of the last one
+    uint32_t* mbox;       // host address
+    uint32_t* mbox_dev;   // the same memory as the device sees it
+    uint32_t mbox_seq;
 };
+
+// One value to bring to the host: `bytes` (a multiple of 4) from device
+// address src to host address dst.
+struct Readback {
+    void* dst;
+    const void* src;
+    int bytes;
+};
+// Copies up to 4 items (at most 240 bytes in all) once the stream's earlier
+// work is complete, and returns then (the stream is idle at that point).
+// Not for use while the stream is being captured.
+int readback(sph_ctx* c, const Readback* items, int n);
 
 // ---- host-side launch wrappers (implemented in the .hip files) ----------
 
