@@ -30,7 +30,12 @@ int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
 // ---------------------------------------------------------------------------
 
 // lanes per particle in the cell walks of the m_ref lookup and the merge search
+#ifndef WG
 #define WG 4
+#endif
+#ifndef MG
+#define MG 4
+#endif
 
 __global__ __launch_bounds__(256) void k_flag_count(int n, const int32_t* __restrict__ flag,
                                                     int32_t* bcount)
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
                                                        double q, double mmax_f, int32_t* closest)
 {
     const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int sp = tt / WG, gl = tt % WG;
+    const int sp = tt / MG, gl = tt % MG;
     if (sp >= n) return;
     const int i = nv.perm[sp];
     const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     if (ki == SPH_FLUID && !(mi > mmi)) {
         // a merge partner lies within (h_i + h_j)/2 <= max(h_i, h_j): a third
         // of the support radius (0.34 leaves margin for rounding) bounds it
-        group_walk<WG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+        group_walk<MG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double dx, double dy, double r2, double hj) {
             if (!pass) return;
             const int j = nv.perm[js];
             if (j == i) return;
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     }
     // the group's closest (ties to the lower slot), independent of order
 #pragma unroll
-    for (int o = 1; o < WG; o <<= 1) {
+    for (int o = 1; o < MG; o <<= 1) {
         const int bo = __shfl_xor(best, o, 64);
         const double ro = __shfl_xor(br, o, 64);
         if (bo >= 0 && (best < 0 || ro < br || (ro == br && bo < best))) {
@@ -717,7 +722,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (rc) return rc;
         NbrView nv = nbr_view(c);
         unsigned nb = (unsigned)cdiv(n, 256);
-        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * WG, 256)), dim3(256), 0, c->stream, c->grid, nv, n, s,
+        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * MG, 256)), dim3(256), 0, c->stream, c->grid, nv, n, s,
                            cf.mass_q, cf.mmax_f, w.closest);
         hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, w.closest, w.flag);
         LAUNCHCHK(c, "merge_closest");

@@ -301,6 +301,7 @@ extern "C" int sph_build_neighbors(sph_ctx* c, const sph_particles* ps, sph_csr*
 {
     if (!c) return SPH_E_INVAL;
     if (!check_ps(c, ps, 0)) return SPH_E_INVAL;
+    c->fused_x = nullptr;
     int rc = nbr_build(c, (int)ps->n, ps->x, ps->y, ps->h);
     if (rc || !out) return rc;
     if (!out->row_ptr || (!out->col && out->nnz_cap > 0)) {
@@ -316,6 +317,7 @@ extern "C" int sph_rates(sph_ctx* c, const sph_particles* ps, double dt, sph_rat
     if (!check_ps(c, ps, 1)) return SPH_E_INVAL;
     if (!(dt > 0)) { set_err(c, "dt must be > 0"); return SPH_E_INVAL; }
     if (ps->kind && !ps->rho) { set_err(c, "boundary particles need rho"); return SPH_E_INVAL; }
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return rates_eval(c, (int)ps->n, ps, dt, out);
 }
 
@@ -324,6 +326,7 @@ extern "C" int sph_step(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps
     if (!c) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
     if (!(dt > 0) || nsteps < 0) { set_err(c, "dt must be > 0, nsteps >= 0"); return SPH_E_INVAL; }
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return step_run(c, ps, dt, nsteps);
 }
 
@@ -331,6 +334,7 @@ extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* ou
 {
     if (!c || !out) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return diag_run(c, ps, out);
 }
 
@@ -357,6 +361,7 @@ extern "C" int sph_mref_lookup(sph_ctx* c, const sph_particles* ps, const sph_ba
     }
     if (!c || !bg) return SPH_E_INVAL;
     if (!check_ps(c, ps, 0) || !ps->mref || !check_bg(c, bg)) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return mref_lookup_run(c, ps, bg);
 }
 
@@ -369,6 +374,7 @@ extern "C" int sph_adapt(sph_ctx* c, sph_particles* ps, const sph_background* bg
     if (!c || !map) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho || !ps->mref) return SPH_E_INVAL;
     if (bg && !check_bg(c, bg)) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return adapt_run(c, ps, bg, map);
 }
 
@@ -391,6 +397,7 @@ extern "C" int sph_step_inout(sph_ctx* c, sph_particles* ps, double dt, int32_t 
         set_err(c, "inout zones must be finite with non-negative lengths");
         return SPH_E_INVAL;
     }
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return step_inout_run(c, ps, dt, nsteps, io, map);
 }
 
@@ -398,6 +405,7 @@ extern "C" int sph_vorticity(sph_ctx* c, const sph_particles* ps, double* omega)
 {
     if (!c || !omega) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return vorticity_run(c, ps, omega);
 }
 
@@ -412,6 +420,7 @@ extern "C" int sph_bg_update_solution(sph_ctx* c, sph_background* bg, const sph_
     if (!c || !bg || !solids || !fluid || !nsplit || passes < 0) return SPH_E_INVAL;
     if (!(k_frac >= 0.0) || !isfinite(k_frac)) { set_err(c, "k_frac must be finite and >= 0"); return SPH_E_INVAL; }
     if (!check_bg(c, bg) || !check_ps(c, fluid, 1) || !fluid->rho) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return bg_solution_run(c, bg, solids, fluid, k_frac, passes, nsplit, omega_max);
 }
 
@@ -432,6 +441,7 @@ extern "C" int sph_inout(sph_ctx* c, sph_particles* ps, const sph_inout_params* 
         set_err(c, "inout zones must be finite with non-negative lengths");
         return SPH_E_INVAL;
     }
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return inout_run(c, ps, io, map);
 }
 
@@ -444,6 +454,7 @@ extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles
     }
     if (!c || !bg || !solids || !nsplit || passes < 0) return SPH_E_INVAL;
     if (!check_bg(c, bg)) return SPH_E_INVAL;
+    c->fused_x = nullptr;  // positions may have changed since the last call
     return bg_update_run(c, bg, solids, phi, phi_thresh, passes, nsplit);
 }
 

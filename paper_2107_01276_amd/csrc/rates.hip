@@ -600,6 +600,11 @@ __global__ __launch_bounds__(256) void k_list_check(Grid g, int n, const double*
 bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h)
 {
     if (!(c->list_valid && c->list_n == n && c->skin > 0 && n > 0)) return false;
+    if (c->fused_x == x) {
+        // the corrector that wrote x already ran the check
+        c->fused_x = nullptr;
+        return true;
+    }
     Work& w = c->w;
     hipLaunchKernelGGL(k_list_check, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid, n,
                        x, y, h, w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag);
@@ -635,9 +640,11 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
         // checked on these very positions already (combined step call)
         reuse = c->precheck_ok != 0;
     } else if (reuse) {
-        hipLaunchKernelGGL(k_list_check, dim3(nb), dim3(256), 0, c->stream, c->grid, n, x, y, h, w.xref,
-                           w.yref, w.href, 1.5 * c->skin, w.list_flag);
-        LAUNCHCHK(c, "list_check");
+        if (c->fused_x != x) {
+            hipLaunchKernelGGL(k_list_check, dim3(nb), dim3(256), 0, c->stream, c->grid, n, x, y, h,
+                               w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag);
+            LAUNCHCHK(c, "list_check");
+        }
         int32_t f = 1;
         const Readback rb{&f, w.list_flag, 4};
         int rc = readback(c, &rb, 1);
@@ -645,6 +652,7 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
         reuse = (f == 0);
     }
     c->precheck_valid = 0;
+    c->fused_x = nullptr;
     if (reuse) {
         // the sorted positions are refreshed by the evaluation's gather
         c->list_reuses++;
@@ -766,6 +774,25 @@ int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_
 // Predict-evaluate-correct, eqs. (int-pre) and (int-cor), in double.
 // ---------------------------------------------------------------------------
 
+// The list check of the next evaluation, fused into the kernel that writes
+// its positions: flag[0] is set when particle i moved by lim h_i or more
+// since the list was built, or h_i changed (flag == nullptr: no list held).
+struct ListCheck {
+    const double *xref, *yref, *href;
+    double lim;
+    int32_t* flag;
+};
+
+__device__ __forceinline__ void list_check_at(const Grid& g, const ListCheck& lc, int i, double x,
+                                              double y, double h)
+{
+    if (!lc.flag) return;
+    const double dx = mi_axis(g, 0, x - lc.xref[i]);
+    const double dy = mi_axis(g, 1, y - lc.yref[i]);
+    const double r = lc.lim * lc.href[i];
+    if (!(dx * dx + dy * dy < r * r) || h != lc.href[i]) lc.flag[0] = 1;
+}
+
 __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* __restrict__ kind,
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ y,
@@ -778,27 +805,32 @@ __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* _
                                                  const double* __restrict__ dxs,
                                                  const double* __restrict__ dys, double dt,
                                                  double* xh, double* yh, double* uh, double* vh,
-                                                 double* ph)
+                                                 double* ph, const double* __restrict__ h,
+                                                 ListCheck lc)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double xn, yn;
     if (kind && kind[i] != SPH_FLUID) {
         // inlet and outlet particles move with their own velocity; solids stay
         const bool adv = kind[i] == SPH_INLET || kind[i] == SPH_OUTLET;
-        xh[i] = adv ? wrap_axis(g, 0, x[i] + 0.5 * dt * u[i]) : x[i];
-        yh[i] = adv ? wrap_axis(g, 1, y[i] + 0.5 * dt * v[i]) : y[i];
+        xn = adv ? wrap_axis(g, 0, x[i] + 0.5 * dt * u[i]) : x[i];
+        yn = adv ? wrap_axis(g, 1, y[i] + 0.5 * dt * v[i]) : y[i];
         uh[i] = u[i]; vh[i] = v[i]; ph[i] = p[i];
-        return;
+    } else {
+        double un = u[i] + 0.5 * dt * au[i];
+        double vn = v[i] + 0.5 * dt * av[i];
+        double tu = un + dxs[i] / dt;
+        double tv = vn + dys[i] / dt;
+        xn = wrap_axis(g, 0, x[i] + 0.5 * dt * tu);
+        yn = wrap_axis(g, 1, y[i] + 0.5 * dt * tv);
+        uh[i] = un;
+        vh[i] = vn;
+        ph[i] = p[i] + 0.5 * dt * ap[i];
     }
-    double un = u[i] + 0.5 * dt * au[i];
-    double vn = v[i] + 0.5 * dt * av[i];
-    double tu = un + dxs[i] / dt;
-    double tv = vn + dys[i] / dt;
-    xh[i] = wrap_axis(g, 0, x[i] + 0.5 * dt * tu);
-    yh[i] = wrap_axis(g, 1, y[i] + 0.5 * dt * tv);
-    uh[i] = un;
-    vh[i] = vn;
-    ph[i] = p[i] + 0.5 * dt * ap[i];
+    xh[i] = xn;
+    yh[i] = yn;
+    list_check_at(g, lc, i, xn, yn, h[i]);
 }
 
 __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* __restrict__ kind,
@@ -810,31 +842,38 @@ __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* _
                                                  const double* __restrict__ dys, double dt,
                                                  const double* __restrict__ uh,
                                                  const double* __restrict__ vh,
-                                                 const double* __restrict__ ph)
+                                                 const double* __restrict__ ph,
+                                                 const double* __restrict__ h, ListCheck lc)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    double xn = x[i], yn = y[i];
     if (kind && kind[i] != SPH_FLUID) {
         // boundary particles keep the half-step boundary values; inlet and
         // outlet particles advance with the half-step velocity
         if (kind[i] == SPH_INLET || kind[i] == SPH_OUTLET) {
-            x[i] = wrap_axis(g, 0, x[i] + dt * uh[i]);
-            y[i] = wrap_axis(g, 1, y[i] + dt * vh[i]);
+            xn = wrap_axis(g, 0, xn + dt * uh[i]);
+            yn = wrap_axis(g, 1, yn + dt * vh[i]);
+            x[i] = xn;
+            y[i] = yn;
         }
         u[i] = uh[i];
         v[i] = vh[i];
         p[i] = ph[i];
-        return;
+    } else {
+        double un = u[i] + dt * au[i];
+        double vn = v[i] + dt * av[i];
+        double tu = un + dxs[i] / dt;
+        double tv = vn + dys[i] / dt;
+        xn = wrap_axis(g, 0, xn + dt * tu);
+        yn = wrap_axis(g, 1, yn + dt * tv);
+        x[i] = xn;
+        y[i] = yn;
+        u[i] = un;
+        v[i] = vn;
+        p[i] = p[i] + dt * ap[i];
     }
-    double un = u[i] + dt * au[i];
-    double vn = v[i] + dt * av[i];
-    double tu = un + dxs[i] / dt;
-    double tv = vn + dys[i] / dt;
-    x[i] = wrap_axis(g, 0, x[i] + dt * tu);
-    y[i] = wrap_axis(g, 1, y[i] + dt * tv);
-    u[i] = un;
-    v[i] = vn;
-    p[i] = p[i] + dt * ap[i];
+    list_check_at(g, lc, i, xn, yn, h[i]);
 }
 
 int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
@@ -846,22 +885,34 @@ int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
     // every evaluation stores its summation density: the next boundary pass
     // reads it, and the caller gets the last one
     PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // the list check of each evaluation runs inside the kernel that writes
+    // its positions while a reusable list is held
+    auto check = [&]() {
+        const bool held = c->list_valid && c->list_n == n && c->skin > 0;
+        return held ? ListCheck{w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag}
+                    : ListCheck{nullptr, nullptr, nullptr, 0.0, nullptr};
+    };
+    c->fused_x = nullptr;
     for (int s = 0; s < nsteps; ++s) {
         int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, dt,
                       withrho, w.r_dpdt, w.r_dudt, w.r_dvdt);
         if (rc) return rc;
+        ListCheck lc = check();
         hipLaunchKernelGGL(k_predict, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
                            ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
-                           w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph);
+                           w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph, (const double*)ps->h, lc);
         LAUNCHCHK(c, "predict");
+        c->fused_x = lc.flag ? w.xh : nullptr;
         rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, ps->kind, ps->rho, dt, withrho,
                   w.r_dpdt, w.r_dudt, w.r_dvdt);
         if (rc) return rc;
+        lc = check();
         hipLaunchKernelGGL(k_correct, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
                            ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
                            w.r_dys, dt, (const double*)w.uh, (const double*)w.vh,
-                           (const double*)w.ph);
+                           (const double*)w.ph, (const double*)ps->h, lc);
         LAUNCHCHK(c, "correct");
+        c->fused_x = lc.flag ? ps->x : nullptr;
     }
     return SPH_OK;
 }

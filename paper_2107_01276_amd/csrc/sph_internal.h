@@ -135,6 +135,9 @@ struct sph_ctx {
     // a list check already done (with the inlet/outlet update of a combined
     // step call) for the next evaluation: valid flag and outcome
     int precheck_valid, precheck_ok;
+    // positions on which a fused list check (in the predictor or corrector)
+    // has already been launched in this library call, or nullptr
+    const double* fused_x;
     unsigned long long io_last[3];  // inlet/outlet event counters at the last update
     // small host readbacks: pinned, device-coherent words written by a
     // one-lane kernel; word 0 carries the sequence number of the last one
