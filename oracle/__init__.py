@@ -84,6 +84,7 @@ def lib():
             "or_pass_b": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 7),
             "or_boundary": (None, [P, P, P, I64] + [P] * 12),
             "or_rates_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 9),
+            "or_body_force": (C.c_int, [P, P, P, I64] + [P] * 10),
             "or_step_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D, I64]),
             "or_inout": (I64, [P, I64, I64] + [P] * 12),
             "or_rates": (C.c_int, [P, P, I64] + [P] * 7 + [D] + [P] * 9),
@@ -313,6 +314,31 @@ def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0)):
         raise RuntimeError(f"oracle rates failed: {rc}")
     out["u_bc"], out["v_bc"], out["p_bc"] = st["u"], st["v"], st["p"]
     return out
+
+
+def body_force(dom: Dom, prm: Prm, state: dict, aw=(0.0, 0.0)):
+    """Force on the solid particles, eq. (force-sph) of section 2.3, from one
+    evaluation's state (boundary pass and pass A on copies).  Returns
+    {"fp": (x, y), "fvisc": (x, y), "abs_p": (x, y), "abs_visc": (x, y)}: the
+    pressure and viscous totals and the sums of their terms' magnitudes."""
+    st = {k: _f64(state[k]).copy() for k in ("x", "y", "u", "v", "p", "h", "m", "rho")}
+    kind = _i32(state["kind"])
+    n = st["x"].size
+    out = np.zeros(8)
+    bc = Bc(float(aw[0]), float(aw[1]))
+    rc = lib().or_body_force(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
+                             *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
+                             _p(st["rho"]), _p(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle body force failed: {rc}")
+    return {"fp": (out[0], out[1]), "fvisc": (out[2], out[3]), "abs_p": (out[4], out[5]),
+            "abs_visc": (out[6], out[7])}
+
+
+def force_coefficients(f: dict, rho0: float, U: float, L: float):
+    """c_d (pressure), c_d (skin friction) and c_l (pressure), eq. (cdcl)."""
+    q = 0.5 * rho0 * U * U * L
+    return {"cd_p": f["fp"][0] / q, "cd_visc": f["fvisc"][0] / q, "cl": f["fp"][1] / q}
 
 
 def step_k(dom: Dom, prm: Prm, state: dict, dt: float, nsteps: int, aw=(0.0, 0.0)):

@@ -732,6 +732,94 @@ int or_rates_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n
     return OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Force on the solid (dummy wall) particles, section 2.3, eq. (force-sph):  */
+/* for every solid particle i, over its fluid neighbours j,                  */
+/*   f_p,i    = -m_i sum_j m_j (P_i gradW(r_ij, h_i) + P_j gradW(r_ij, h_j))  */
+/*   f_visc,i =  m_i (1/beta_i) sum_j m_j 4 nu/(rho_i + rho_j)              */
+/*                 (r_ij . gradW_ij)/(r_ij^2 + eta_i) u_ij                   */
+/* and the totals over all solid particles.  eta_i, beta_i and u_ij (with    */
+/* the ghost velocity of the solid particle) are those of the momentum       */
+/* equation in pass B above.                                                  */
+/* READING: P_i = p_i/(rho_i^2 beta_i), P_j = p_j/(rho_j^2 beta_j), without  */
+/* the pressure reduction of eq. (mom:pre).  The reduction removes the local */
+/* mean pressure, which has no net effect inside the fluid; over the one-    */
+/* sided sums at a body surface it removes the pressure the force integrates */
+/* (with it, a body in a linear pressure field feels a force that vanishes   */
+/* like h instead of -grad p times its area).                                 */
+/* READING: gradW_ij, the kernel gradient at h_ij in the viscous sum, is the  */
+/* average of the gradients at h_i and h_j (eq. dw-avg), as in the momentum  */
+/* equation, so the force is m_i times the fluid part of the solid           */
+/* particle's own momentum sums.                                              */
+/* One evaluation's state is formed first as in or_rates_k: neighbours, the  */
+/* boundary pass (on u, v, p in place), pass A.                               */
+/* out[0..3] = f_p,x, f_p,y, f_visc,x, f_visc,y; out[4..7] = the sums of the  */
+/* absolute values of the pair terms of each (for rounding bounds).          */
+/* ------------------------------------------------------------------------ */
+int or_body_force(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+                  const double* x, const double* y, double* u, double* v, double* p,
+                  const double* h, const double* m, const int32_t* kind, const double* rho_in,
+                  double* out)
+{
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    int64_t* rp = NULL;
+    int32_t* col = NULL;
+    int64_t nnz = or_nbr_cells_alloc(d, n, x, y, h, &rp, &col);
+    if (nnz < 0) return (int)nnz;
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double* buf = malloc(sz * 8);
+    if (!buf) {
+        free(rp); free(col);
+        return OR_E_NOMEM;
+    }
+    double *ug = buf, *vg = buf + n, *rho = buf + 2 * n, *beta = buf + 3 * n, *nnb = buf + 4 * n,
+           *pavg = buf + 5 * n, *dxs = buf + 6 * n, *dys = buf + 7 * n;
+    or_boundary(d, P, B, n, x, y, h, rho_in, kind, rp, col, u, v, p, ug, vg);
+    or_pass_a(d, P, n, x, y, h, m, p, rp, col, rho, beta, nnb, pavg, dxs, dys);
+    const double nu = P->nu;
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] != OR_SOLID) continue;
+        const double Pi = beta[i] > 0.0 ? p[i] / (rho[i] * rho[i] * beta[i]) : 0.0;
+        const double eta = 0.001 * h[i] * h[i];
+        double fpx = 0.0, fpy = 0.0, fvx = 0.0, fvy = 0.0;
+        double apx = 0.0, apy = 0.0, avx = 0.0, avy = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int64_t j = col[k];
+            if (kind[j] != OR_FLUID) continue;
+            const double dx = mi_axis(d, 0, x[i] - x[j]);
+            const double dy = mi_axis(d, 1, y[i] - y[j]);
+            const double r2 = dx * dx + dy * dy;
+            const double r = sqrt(r2);
+            double gix = 0.0, giy = 0.0, gjx = 0.0, gjy = 0.0;
+            if (r > 0.0) {
+                const double fi = or_dwdr(r, h[i]) / r;
+                const double fj = or_dwdr(r, h[j]) / r;
+                gix = fi * dx; giy = fi * dy;
+                gjx = fj * dx; gjy = fj * dy;
+            }
+            const double Pj = beta[j] <= 0.0 ? 0.0 : p[j] / (rho[j] * rho[j] * beta[j]);
+            const double tpx = -m[i] * m[j] * (Pi * gix + Pj * gjx);
+            const double tpy = -m[i] * m[j] * (Pi * giy + Pj * gjy);
+            fpx += tpx; fpy += tpy;
+            apx += fabs(tpx); apy += fabs(tpy);
+            if (beta[i] > 0.0) {
+                const double rdotg = dx * 0.5 * (gix + gjx) + dy * 0.5 * (giy + gjy);
+                const double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
+                const double tvx = m[i] * cvis * (ug[i] - ug[j]) / beta[i];
+                const double tvy = m[i] * cvis * (vg[i] - vg[j]) / beta[i];
+                fvx += tvx; fvy += tvy;
+                avx += fabs(tvx); avy += fabs(tvy);
+            }
+        }
+        out[0] += fpx; out[1] += fpy; out[2] += fvx; out[3] += fvy;
+        out[4] += apx; out[5] += apy; out[6] += avx; out[7] += avy;
+    }
+    free(buf);
+    free(rp);
+    free(col);
+    return OR_OK;
+}
+
 int or_rates(const or_domain* d, const or_params* P, int64_t n, const double* x,
              const double* y, const double* u, const double* v, const double* p,
              const double* h, const double* m, double dt, double* rho, double* beta,
