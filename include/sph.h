@@ -334,6 +334,25 @@ int sph_pool_info(sph_pool *pool, sph_pool_stats *out);
 int sph_step_inout(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps,
                    const sph_inout_params *io, sph_inout_map *map);
 
+/* Force on the solid particles, section 2.3, eq. (force-sph): one
+ * evaluation of the current state (neighbours, the boundary pass, which
+ * writes p, and u, v of outlet particles, of the non-fluid slots in place
+ * as sph_rates does, and pass A), then, over every solid particle i and its
+ * fluid neighbours j, in FP64:
+ *   f_p    = -sum_i m_i sum_j m_j (P_i gradW(r_ij, h_i) + P_j gradW(r_ij, h_j))
+ *   f_visc =  sum_i m_i (1/beta_i) sum_j m_j 4 nu / (rho_i + rho_j)
+ *                       (r_ij . gradW_ij) / (r_ij^2 + eta_i) (u~_i - u_j)
+ * with P = p / (rho^2 beta) (the unreduced pressure), gradW_ij the average
+ * of the gradients at h_i and h_j, and u~_i the solid's ghost velocity.
+ * The densities, beta and masses come from pass A in the context's
+ * precision.  force (host, 8 doubles): f_p,x, f_p,y, f_visc,x, f_visc,y,
+ * then the sums of the magnitudes of their terms (a scale for rounding
+ * errors).  Drag and lift coefficients, eq. (cdcl), are these forces
+ * divided by rho0 U^2 L / 2.  Needs kind and rho (the stored density);
+ * SPH_E_INVAL otherwise.  The totals are summed in a fixed order (the same
+ * bits on every call with the same input).  Synchronises. */
+int sph_body_force(sph_ctx *ctx, sph_particles *ps, double *force);
+
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 

@@ -102,7 +102,8 @@ class sph_diag(C.Structure):
 
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
-           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_profile_enable",
+           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force",
+           "sph_profile_enable",
            "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
            "sph_pool_footprint", "sph_pool_create",
            "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
@@ -138,6 +139,7 @@ def load_library(path: str = LIB_PATH):
         "sph_step_inout": (C.c_int, [P, P, D, I32, P, P]),
         "sph_bg_update_solution": (C.c_int, [P, P, P, P, D, I32, P, P]),
         "sph_diagnostics": (C.c_int, [P, P, P]),
+        "sph_body_force": (C.c_int, [P, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
         "sph_profile_reset": (C.c_int, [P]),
@@ -451,6 +453,15 @@ class Context:
                                            float(phi_thresh), int(passes), C.byref(ns)))
         bg.n = int(bs.n)
         return int(ns.value)
+
+    def body_force(self, P: Particles) -> dict:
+        """Force on the solid particles (sph_body_force): pressure and
+        viscous totals and the magnitude sums of their terms."""
+        f = (C.c_double * 8)()
+        ps = P.c()
+        self._check(self.lib.sph_body_force(self._h, C.byref(ps), f))
+        return {"fp": (f[0], f[1]), "fvisc": (f[2], f[3]), "abs_p": (f[4], f[5]),
+                "abs_visc": (f[6], f[7])}
 
     def diagnostics(self, P: Particles) -> dict:
         d = sph_diag()

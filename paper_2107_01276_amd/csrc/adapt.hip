@@ -86,14 +86,22 @@ static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, 
 // ---------------------------------------------------------------------------
 
 // Queries run in `order` (a spatial order of the fluid slots) when given.
+__global__ __launch_bounds__(256) void k_gather_f64(int n, const int32_t* __restrict__ perm,
+                                                    const double* __restrict__ src, double* dst)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) dst[s] = src[perm[s]];
+}
+
 __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ y,
                                                      const double* __restrict__ h,
-                                                     const double* __restrict__ bmref,
+                                                     const double* __restrict__ bms,
                                                      double* mref_out, int32_t* none,
                                                      const int32_t* __restrict__ order)
 {
+    // bms: the background's m_ref in its sorted order
     const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int t = tt / WG, gl = tt % WG;
     if (t >= n) return;
@@ -104,7 +112,7 @@ __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
     int found = 0;
     group_walk<WG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double, double, double, double) {
         if (!pass) return;
-        double v = bmref[nv.perm[js]];
+        double v = bms[js];
         if (!found || v < mn) mn = v;
         found = 1;
     });
@@ -161,8 +169,13 @@ static int mref_lookup_into(sph_ctx* c, const sph_particles* ps, const sph_backg
     int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
     if (rc) return rc;
     NbrView nv = nbr_view(c);
+    // m_ref of the background in its sorted order (the rate passes' record
+    // buffer is free here), so that the walk reads it next to the positions
+    double* bms = (double*)w.pa;
+    hipLaunchKernelGGL(k_gather_f64, dim3((unsigned)cdiv(nb, 256)), dim3(256), 0, c->stream, nb,
+                       (const int32_t*)nv.perm, bg->mref, bms);
     hipLaunchKernelGGL(k_mref_lookup, dim3((unsigned)cdiv((int64_t)n * WG, 256)), dim3(256), 0, c->stream, c->grid,
-                       nv, n, ps->x, ps->y, ps->h, bg->mref, mref_out, w.flag, order);
+                       nv, n, ps->x, ps->y, ps->h, (const double*)bms, mref_out, w.flag, order);
     hipLaunchKernelGGL(k_mref_nearest, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
                        n, ps->x, ps->y, w.flag, nb, bg->x, bg->y, bg->mref, mref_out);
     LAUNCHCHK(c, "mref_lookup");
@@ -241,8 +254,30 @@ __global__ __launch_bounds__(256) void k_split_apply(Grid g, int n, FluidState s
 // Merge
 // ---------------------------------------------------------------------------
 
+// Per sorted particle: m_max (the split threshold mmax_f m_ref), or -1 for
+// a particle that is not fluid, and its mass quanta.
+struct __align__(16) MergeRec {
+    double mm;
+    int64_t mq;
+};
+
+__global__ __launch_bounds__(256) void k_merge_pack(int n, const int32_t* __restrict__ perm,
+                                                   FluidState s, double mmax_f, MergeRec* rec)
+{
+    int js = blockIdx.x * blockDim.x + threadIdx.x;
+    if (js >= n) return;
+    const int j = perm[js];
+    const bool fl = !s.kind || s.kind[j] == SPH_FLUID;
+    MergeRec r;
+    r.mm = fl ? mmax_f * s.mref[j] : -1.0;
+    r.mq = s.mq[j];
+    rec[js] = r;
+}
+
 __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n, FluidState s,
-                                                       double q, double mmax_f, int32_t* closest)
+                                                       double q, double mmax_f,
+                                                       const MergeRec* __restrict__ rec,
+                                                       int32_t* closest)
 {
     const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int sp = tt / MG, gl = tt % MG;
@@ -250,7 +285,8 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     const int i = nv.perm[sp];
     const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
     const int li = key_level(g, nv.keys[sp]);
-    const double mi = (double)s.mq[i] * q;
+    const int64_t mqi = s.mq[i];
+    const double mi = (double)mqi * q;
     const double mmi = mmax_f * s.mref[i];
     const int ki = s.kind ? s.kind[i] : SPH_FLUID;
     int best = -1;
@@ -259,19 +295,21 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
         // a merge partner lies within (h_i + h_j)/2 <= max(h_i, h_j): a third
         // of the support radius (0.34 leaves margin for rounding) bounds it
         group_walk<MG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double dx, double dy, double r2, double hj) {
-            if (!pass) return;
-            const int j = nv.perm[js];
-            if (j == i) return;
-            if (s.kind && s.kind[j] != SPH_FLUID) return;
-            const double mj = (double)s.mq[j] * q;
-            const double mmj = mmax_f * s.mref[j];
+            if (!pass || js == sp) return;
+            if (best >= 0 && r2 > br) return;  // cannot beat the current best
+            const MergeRec rj = rec[js];
+            if (!(rj.mm >= 0.0)) return;       // not fluid
+            const int64_t mqj = rj.mq;
+            const double mj = (double)mqj * q;
+            const double mmj = rj.mm;
             if (mj > mmj) return;
             const double hh = 0.5 * (hi + hj);
             if (!(r2 < hh * hh)) return;
-            const double msum = (double)(s.mq[i] + s.mq[j]) * q;
+            const double msum = (double)(mqi + mqj) * q;
             const double mm = mmi > mmj ? mmi : mmj;
             if (!(msum < mm)) return;
-            if (best < 0 || r2 < br || (r2 == br && j < best)) {
+            const int j = nv.perm[js];
+            if (best < 0 || r2 < br || j < best) {
                 best = j;
                 br = r2;
             }
@@ -722,8 +760,14 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (rc) return rc;
         NbrView nv = nbr_view(c);
         unsigned nb = (unsigned)cdiv(n, 256);
-        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * MG, 256)), dim3(256), 0, c->stream, c->grid, nv, n, s,
-                           cf.mass_q, cf.mmax_f, w.closest);
+        // sorted-order records of the mergeability data (the rate passes'
+        // record buffer is free during adaptation)
+        MergeRec* mrec = (MergeRec*)w.pa;
+        hipLaunchKernelGGL(k_merge_pack, dim3(nb), dim3(256), 0, c->stream, n, (const int32_t*)nv.perm, s,
+                           cf.mmax_f, mrec);
+        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * MG, 256)), dim3(256), 0,
+                           c->stream, c->grid, nv, n, s, cf.mass_q, cf.mmax_f, (const MergeRec*)mrec,
+                           w.closest);
         hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, w.closest, w.flag);
         LAUNCHCHK(c, "merge_closest");
         // number of pairs = number of deleted slots

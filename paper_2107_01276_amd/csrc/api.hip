@@ -330,6 +330,17 @@ extern "C" int sph_step(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps
     return step_run(c, ps, dt, nsteps);
 }
 
+extern "C" int sph_body_force(sph_ctx* c, sph_particles* ps, double* force)
+{
+    if (!c || !force) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho || !ps->kind) {
+        set_err(c, "body force needs kind and rho (the stored density)");
+        return SPH_E_INVAL;
+    }
+    c->fused_x = nullptr;  // positions may have changed since the last call
+    return body_force_run(c, ps, force);
+}
+
 extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* out)
 {
     if (!c || !out) return SPH_E_INVAL;

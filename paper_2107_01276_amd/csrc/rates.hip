@@ -923,6 +923,153 @@ int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
 
 #define DIAG_BLOCKS 256
 
+// ---------------------------------------------------------------------------
+// Force on the solid particles, eq. (force-sph) of section 2.3, from the state
+// the last evaluation left in the workspace (sorted records, pass A's
+// density, beta and mass, the solids' ghost velocities).  For every solid
+// particle i and fluid neighbour j (in FP64):
+//   f_p    += -m_i m_j (P_i gradW(r_ij, h_i) + P_j gradW(r_ij, h_j)),
+//             P = p / (rho^2 beta), the unreduced pressure;
+//   f_visc += m_i (1/beta_i) m_j 4 nu/(rho_i + rho_j) (r_ij . gradW_ij)
+//             / (r_ij^2 + eta_i) (u~_i - u_j), gradW_ij the average of the
+//             gradients at h_i and h_j, u~_i the ghost velocity.
+// Each thread takes a fixed set of sorted particles and each block reduces
+// in a fixed tree, so the totals do not depend on scheduling.
+// ---------------------------------------------------------------------------
+
+#define FORCE_BLOCKS 256
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_body_force(Grid g, NbrView nv, NbrList nl, int n,
+                                                    const int32_t* __restrict__ kind,
+                                                    const double4* __restrict__ pa,
+                                                    const double2* __restrict__ puv,
+                                                    const typename Vec4<T>::type* __restrict__ pf,
+                                                    const T* __restrict__ beta,
+                                                    const double* __restrict__ ugs,
+                                                    const double* __restrict__ vgs, double nu,
+                                                    double* part)
+{
+    __shared__ double sh[8][256];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        if (kind[nv.perm[s]] != SPH_SOLID) continue;
+        const double4 ai = pa[s];
+        const typename Vec4<T>::type fi = pf[s];
+        const double hi = ai.z, rhoi = (double)fi.z, mi = (double)fi.w, bi = (double)beta[s];
+        const double Pi = bi > 0.0 ? ai.w / (rhoi * rhoi * bi) : 0.0;
+        const double eta = 0.001 * hi * hi;
+        const double ugi = ugs[s], vgi = vgs[s];
+        auto term = [&](int js, double dx, double dy, double r2, double hj) {
+            if (kind[nv.perm[js]] != SPH_FLUID) return;
+            const double r = sqrt(r2);
+            double gix = 0.0, giy = 0.0, gjx = 0.0, gjy = 0.0;
+            if (r > 0.0) {
+                const double fa = kern_dw64(r, hi) / r, fb = kern_dw64(r, hj) / r;
+                gix = fa * dx; giy = fa * dy;
+                gjx = fb * dx; gjy = fb * dy;
+            }
+            const double pj = pa[js].w;
+            const typename Vec4<T>::type fj = pf[js];
+            const double rhoj = (double)fj.z, mj = (double)fj.w, bj = (double)beta[js];
+            const double Pj = bj > 0.0 ? pj / (rhoj * rhoj * bj) : 0.0;
+            const double tpx = -mi * mj * (Pi * gix + Pj * gjx);
+            const double tpy = -mi * mj * (Pi * giy + Pj * gjy);
+            acc[0] += tpx; acc[1] += tpy;
+            acc[4] += fabs(tpx); acc[5] += fabs(tpy);
+            if (bi > 0.0) {
+                const double2 uvj = puv[js];
+                const double rdotg = dx * 0.5 * (gix + gjx) + dy * 0.5 * (giy + gjy);
+                const double cv = mj * (4.0 * nu / (rhoi + rhoj)) * rdotg / (r2 + eta);
+                const double tvx = mi * cv * (ugi - uvj.x) / bi;
+                const double tvy = mi * cv * (vgi - uvj.y) / bi;
+                acc[2] += tvx; acc[3] += tvy;
+                acc[6] += fabs(tvx); acc[7] += fabs(tvy);
+            }
+        };
+        const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
+        if (cnt <= nl.K) {
+            const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
+            for (int k = 0; k < cnt; ++k) {
+                const int js = nl.idx[(int64_t)k * nl.stride + s];
+                const double4 a = pa[js];
+                const double dx = mi_axis(g, 0, ai.x - a.x);
+                const double dy = mi_axis(g, 1, ai.y - a.y);
+                const double r2 = dx * dx + dy * dy;
+                const double rj3 = 3.0 * a.z;
+                if (r2 < fmax(ri2, rj3 * rj3)) term(js, dx, dy, r2, a.z);
+            }
+        } else {
+            for_each_neighbor(g, nv, ai.x, ai.y, hi, key_level(g, nv.keys[s]),
+                              [&](int js, double dx, double dy, double r2, double hj) {
+                                  term(js, dx, dy, r2, hj);
+                              });
+        }
+    }
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o)
+            for (int k = 0; k < 8; ++k) sh[k][t] += sh[k][t + o];
+        __syncthreads();
+    }
+    if (t < 8) part[t * FORCE_BLOCKS + blockIdx.x] = sh[t][0];
+}
+
+// The FORCE_BLOCKS partial sums of each component, in a fixed tree.
+__global__ __launch_bounds__(256) void k_force_total(const double* __restrict__ part, double* tot)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < 8; ++k) {
+        sh[t] = part[k * FORCE_BLOCKS + t];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) sh[t] += sh[t + o];
+            __syncthreads();
+        }
+        if (t == 0) tot[k] = sh[0];
+        __syncthreads();
+    }
+}
+
+int body_force_run(sph_ctx* c, sph_particles* ps, double* force)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    for (int k = 0; k < 8; ++k) force[k] = 0.0;
+    if (n == 0) return SPH_OK;
+    // one evaluation (its pass B output is not needed; dt only scales it)
+    PassAOut none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, 1.0,
+                  none, w.r_dpdt, w.r_dudt, w.r_dvdt);
+    if (rc) return rc;
+    NbrView nv = nbr_view(c);
+    NbrList nl{w.nl_idx, w.nl_cnt, w.nl_k, n, w.list_flag};
+    if (!(c->list_valid && c->list_n == n)) nl.idx = nullptr;
+    double* part = (double*)w.red;   // 8 FORCE_BLOCKS doubles
+    double* tot = w.sc9;
+    if (c->cfg.precision == SPH_FP32) {
+        RatesBufs<float> b = rbufs<float>(c);
+        hipLaunchKernelGGL(k_body_force<float>, dim3(FORCE_BLOCKS), dim3(256), 0, c->stream, c->grid, nv,
+                           nl, n, (const int32_t*)ps->kind, (const double4*)w.pa,
+                           (const double2*)w.puv, (const float4*)w.pf, (const float*)b.beta,
+                           (const double*)w.ugs, (const double*)w.vgs, c->cfg.nu, part);
+    } else {
+        RatesBufs<double> b = rbufs<double>(c);
+        hipLaunchKernelGGL(k_body_force<double>, dim3(FORCE_BLOCKS), dim3(256), 0, c->stream, c->grid, nv,
+                           nl, n, (const int32_t*)ps->kind, (const double4*)w.pa,
+                           (const double2*)w.puv, (const double4*)w.pf, (const double*)b.beta,
+                           (const double*)w.ugs, (const double*)w.vgs, c->cfg.nu, part);
+    }
+    hipLaunchKernelGGL(k_force_total, dim3(1), dim3(256), 0, c->stream, (const double*)part, tot);
+    LAUNCHCHK(c, "body_force");
+    const Readback rb{force, tot, 64};
+    return readback(c, &rb, 1);
+}
+
 __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __restrict__ u,
                                                       const double* __restrict__ v,
                                                       const double* __restrict__ rho,

@@ -175,6 +175,8 @@ size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* 
 // rates.hip
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out);
 int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps);
+// force on the solid particles (8 doubles to the host, see sph_body_force)
+int body_force_run(sph_ctx* c, sph_particles* ps, double* force);
 bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
 
