@@ -104,21 +104,36 @@ def serving_bench(SPH, W, args):
     return res
 
 
+def pass_b_source_hash():
+    """sha256 of the source pass B is compiled from: the kernel function, the
+    pair-arithmetic helpers and lane-group size above it in rates.hip, and
+    the device header."""
+    import hashlib
+    rates = open(os.path.join(ROOT, KERNEL_SOURCES[0])).read()
+    k0 = rates.index("template <typename T, bool GH>\n__global__ __launch_bounds__(256) void k_pass_b(")
+    k1 = rates.index("\n}\n", k0)
+    h0 = rates.index("#define RATES_FP_CONTRACT")
+    h1 = rates.index("template <typename T>\nstruct RatesBufs", h0)
+    g0 = rates.index("#define RGB ")
+    h = hashlib.sha256()
+    h.update(rates[g0:rates.index("\n", g0)].encode())
+    h.update(rates[h0:h1].encode())
+    h.update(rates[k0:k1].encode())
+    with open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per pass-B launch from the committed counter summary, or
-    None when the kernel's sources changed since the counters were taken."""
-    import hashlib
+    None when the kernel's source changed since the counters were taken."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines()
                   if line.startswith(("traffic_bytes_per_launch: ", "kernel_source_sha256: ")))
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+    if fields.get("kernel_source_sha256", "").strip() != pass_b_source_hash():
         return None
     return float(fields["traffic_bytes_per_launch"])
 
