@@ -1051,11 +1051,14 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
 // Flags of the update and their counts, added to cumulative counters (the
 // host takes differences): cnt[0] fluid -> outlet, cnt[1] inlet copies,
 // cnt[2] deletions (one atomic per wave and counter).
+// In a run of steps (gd.trip set) a slot change trips the run: the host
+// applies it, the rest of the run is skipped.
 __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restrict__ x,
                                                   const int32_t* __restrict__ kind,
                                                   sph_inout_params io, int32_t* keep, int32_t* app,
-                                                  unsigned long long* cnt)
+                                                  unsigned long long* cnt, Guard gd)
 {
+    if (guard_stop(gd)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k = i < n ? kind[i] : -1;
     const double xi = i < n ? x[i] : 0.0;
@@ -1067,6 +1070,7 @@ __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restric
         if (b0) atomicAdd(cnt + 0, (unsigned long long)__popcll(b0));
         if (b1) atomicAdd(cnt + 1, (unsigned long long)__popcll(b1));
         if (b2) atomicAdd(cnt + 2, (unsigned long long)__popcll(b2));
+        if (b1 | b2) guard_trip(gd);
     }
     if (i >= n) return;
     keep[i] = !del;
@@ -1075,8 +1079,9 @@ __global__ __launch_bounds__(256) void k_io_flags(int n, const double* __restric
 
 // Kind changes only (no copy, no deletion): fluid past x_out becomes outlet.
 __global__ __launch_bounds__(256) void k_io_kinds(int n, const double* __restrict__ x, int32_t* kind,
-                                                  sph_inout_params io)
+                                                  sph_inout_params io, Guard gd)
 {
+    if (guard_stop(gd)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && kind[i] == SPH_FLUID && x[i] >= io.x_out) kind[i] = SPH_OUTLET;
 }
@@ -1140,7 +1145,7 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
     int32_t *keep = w.flag, *rk = w.idx_a, *app = w.tmp_i32[1], *ra = w.closest;
     unsigned long long* cnt = w.ctr;
     hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
-                       (const int32_t*)ps->kind, *io, keep, app, cnt);
+                       (const int32_t*)ps->kind, *io, keep, app, cnt, Guard{nullptr, 0});
     LAUNCHCHK(c, "io_flags");
     // the list check of the next evaluation rides on the same round trip
     const bool checked = precheck && launch_list_check(c, n, ps->x, ps->y, ps->h);
@@ -1159,7 +1164,7 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
         map->n_to_outlet = nto;
         if (nto > 0) {
             hipLaunchKernelGGL(k_io_kinds, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
-                               ps->kind, *io);
+                               ps->kind, *io, Guard{nullptr, 0});
             LAUNCHCHK(c, "io_kinds");
         }
         if (checked) {
@@ -1168,8 +1173,21 @@ int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_ino
         }
         return SPH_OK;
     }
+    return inout_apply(c, ps, io, map, nto);
+}
+
+// The slot changes of an inlet/outlet update whose flags (keep, append)
+// k_io_flags has left in the workspace: stable compaction of the kept
+// slots, the appended copies after them.
+int inout_apply(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map,
+                int32_t nto)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    const unsigned nb = (unsigned)cdiv(n, 256);
+    int32_t *keep = w.flag, *rk = w.idx_a, *app = w.tmp_i32[1], *ra = w.closest;
     int32_t nkeep = 0, na = 0;
-    rc = compact_ranks(c, n, keep, rk, &nkeep);
+    int rc = compact_ranks(c, n, keep, rk, &nkeep);
     if (rc) return rc;
     rc = compact_ranks(c, n, app, ra, &na);
     if (rc) return rc;
@@ -1347,6 +1365,17 @@ __global__ __launch_bounds__(256) void k_copy_i64(int n, const int64_t* __restri
 // nsteps of (PEC step, inlet/outlet update).  Counters add up over the
 // steps; map->origin is the composition of the steps' maps (left unwritten
 // when no step moved a slot).
+__global__ void k_set_trip(int32_t* trip)
+{
+    if (threadIdx.x == 0) trip[0] = SPH_NOTRIP;
+}
+
+// nsteps of { step, inlet/outlet update }.  With a list skin the remaining
+// steps are enqueued as one guarded run with a single host readback at its
+// end: the list checks (in the predictor and corrector) and slot changes of
+// the update trip the run, the kernels after the tripping one return at
+// once, and the host finishes that step on the ordinary path and starts a
+// new run.  The results are those of the steps taken one by one.
 int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const sph_inout_params* io,
                    sph_inout_map* map)
 {
@@ -1355,32 +1384,96 @@ int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const s
     bool moved = false;
     int64_t* comp = w.tmp_i64[2];  // composed map so far
     int rc = SPH_OK;
-    for (int s = 0; s < nsteps && rc == SPH_OK; ++s) {
-        rc = step_run(c, ps, dt, 1);
-        if (rc) break;
-        const int n_before = (int)ps->n;
-        sph_inout_map m{w.i64_b, 0, 0, 0, 0};
-        rc = inout_run(c, ps, io, &m, s + 1 < nsteps);
-        if (rc) break;
+    const Guard none{nullptr, 0};
+    // adds one update's counters and slot map to the totals
+    auto account = [&](const sph_inout_map& m) {
         tot_app += m.n_appended;
         tot_del += m.n_deleted;
         tot_out += m.n_to_outlet;
-        if (m.n_appended || m.n_deleted) {
-            const int nn = (int)ps->n;
-            const unsigned nb = (unsigned)cdiv(nn > 0 ? nn : 1, 256);
-            if (!moved) {
-                hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
-                                   (const int64_t*)w.i64_b, comp);
-            } else {
-                hipLaunchKernelGGL(k_compose, dim3(nb), dim3(256), 0, c->stream, nn,
-                                   (const int64_t*)comp, (const int64_t*)w.i64_b, w.i64_a);
-                hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
-                                   (const int64_t*)w.i64_a, comp);
-            }
-            LAUNCHCHK(c, "compose");
-            moved = true;
+        if (!(m.n_appended || m.n_deleted)) return;
+        const int nn = (int)ps->n;
+        const unsigned nb = (unsigned)cdiv(nn > 0 ? nn : 1, 256);
+        if (!moved) {
+            hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
+                               (const int64_t*)w.i64_b, comp);
+        } else {
+            hipLaunchKernelGGL(k_compose, dim3(nb), dim3(256), 0, c->stream, nn,
+                               (const int64_t*)comp, (const int64_t*)w.i64_b, w.i64_a);
+            hipLaunchKernelGGL(k_copy_i64, dim3(nb), dim3(256), 0, c->stream, nn,
+                               (const int64_t*)w.i64_a, comp);
         }
-        (void)n_before;
+        moved = true;
+    };
+    int s = 0;
+    while (s < nsteps && rc == SPH_OK) {
+        const int n = (int)ps->n;
+        if (!(n > 0 && c->skin > 0 && nsteps - s > 1)) {
+            // one step exactly as the separate calls take it
+            rc = step_run(c, ps, dt, 1);
+            if (rc) break;
+            sph_inout_map m{w.i64_b, 0, 0, 0, 0};
+            rc = inout_run(c, ps, io, &m, s + 1 < nsteps);
+            if (rc) break;
+            account(m);
+            ++s;
+            continue;
+        }
+        rc = list_ready(c, ps);
+        if (rc) break;
+        int32_t* trip = w.status + 24;
+        hipLaunchKernelGGL(k_set_trip, dim3(1), dim3(64), 0, c->stream, trip);
+        const unsigned nb = (unsigned)cdiv(n, 256);
+        for (int k = s; k < nsteps && rc == SPH_OK; ++k) {
+            const int32_t b = 8 * (k - s);
+            rc = step_half1(c, ps, dt, Guard{trip, b + 1}, Guard{trip, b + 2});
+            if (rc) break;
+            rc = step_half2(c, ps, dt, Guard{trip, b + 3}, Guard{trip, b + 4});
+            if (rc) break;
+            hipLaunchKernelGGL(k_io_flags, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
+                               (const int32_t*)ps->kind, *io, w.flag, w.tmp_i32[1], w.ctr,
+                               Guard{trip, b + 5});
+            hipLaunchKernelGGL(k_io_kinds, dim3(nb), dim3(256), 0, c->stream, n, (const double*)ps->x,
+                               ps->kind, *io, Guard{trip, b + 6});
+            LAUNCHCHK(c, "run_io");
+        }
+        if (rc) break;
+        int32_t tr = SPH_NOTRIP;
+        unsigned long long h3[3] = {0, 0, 0};
+        const Readback rb[2] = {{&tr, trip, 4}, {h3, w.ctr, (int)sizeof(h3)}};
+        rc = readback(c, rb, 2);
+        if (rc) break;
+        // fluid turned outlet in the steps that ran (their kinds are set)
+        tot_out += (int64_t)(h3[0] - c->io_last[0]);
+        for (int k = 0; k < 3; ++k) c->io_last[k] = h3[k];
+        c->fused_x = nullptr;
+        c->precheck_valid = 0;
+        if (tr == SPH_NOTRIP) {
+            s = nsteps;
+            break;
+        }
+        // a kernel of the run tripped; the state is as that kernel left it
+        reset_bcounters(c);
+        const int kk = s + tr / 8, ph = tr % 8;
+        sph_inout_map m{w.i64_b, 0, 0, 0, 0};
+        if (ph == 2) {
+            // the list expired at step kk's predicted positions
+            c->list_valid = 0;
+            rc = step_half2(c, ps, dt, none, none);
+            if (rc == SPH_OK) rc = inout_run(c, ps, io, &m, kk + 1 < nsteps);
+        } else if (ph == 4) {
+            // the corrector of step kk found the list expired
+            c->list_valid = 0;
+            rc = inout_run(c, ps, io, &m, false);
+        } else if (ph == 5) {
+            // step kk's update moves slots; its flags and counters are taken
+            rc = inout_apply(c, ps, io, &m, 0);
+        } else {
+            set_err(c, "run of steps: unexpected trip %d", tr);
+            rc = SPH_E_DEVICE;
+        }
+        if (rc) break;
+        account(m);
+        s = kk + 1;
     }
     c->precheck_valid = 0;
     map->n_appended = tot_app;

@@ -100,8 +100,9 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
                                                       double2* puv, T* ms,
                                                       const double* __restrict__ ug,
                                                       const double* __restrict__ vg, double* ugs,
-                                                      double* vgs, const int32_t* __restrict__ kind)
+                                                      double* vgs, const int32_t* __restrict__ kind, Guard gd)
 {
+    if (guard_stop(gd)) return;
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
     int i = perm[s];
@@ -139,8 +140,9 @@ struct PassAOut {
 // fluid slots are read, so waves do not race.
 __global__ __launch_bounds__(256) void k_bmark(int n, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ kind, int32_t* list,
-                                               int32_t* count)
+                                               int32_t* count, Guard gd)
 {
+    if (guard_stop(gd)) return;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     const bool bnd = s < n && kind[perm[s]] != SPH_FLUID;
     const uint64_t m = __ballot(bnd);
@@ -175,8 +177,9 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
                                                   const double* __restrict__ h,
                                                   const double* __restrict__ rho, double* u,
                                                   double* v, double* p, double* ug, double* vg,
-                                                  double gx, double gy)
+                                                  double gx, double gy, Guard gd)
 {
+    if (guard_stop(gd)) return;
     const int lane = __lane_id();
     const int nw = (gridDim.x * blockDim.x) >> 6;
     if (blockIdx.x == 0 && threadIdx.x == 0) next_count[0] = 0;
@@ -263,8 +266,9 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
                                                 NbrList nl, const double4* __restrict__ pa,
                                                 typename Vec4<T>::type* pf, double rho0,
                                                 PassAOut out, double* r_dxs, double* r_dys,
-                                                const int32_t* __restrict__ kind, NbrList ex)
+                                                const int32_t* __restrict__ kind, NbrList ex, Guard gd)
 {
+    if (guard_stop(gd)) return;
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int s = t / RGA, gl = t % RGA;
     if (s >= n) return;
@@ -417,8 +421,9 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
                                                 const typename Vec4<T>::type* __restrict__ pf,
                                                 const double* __restrict__ ugs,
                                                 const double* __restrict__ vgs, PassBParams P,
-                                                double* dpdt, double* dudt, double* dvdt)
+                                                double* dpdt, double* dudt, double* dvdt, Guard gd)
 {
+    if (guard_stop(gd)) return;
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int s = t / RGB, gl = t % RGB;
     if (s >= n) return;
@@ -563,8 +568,9 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
 // (|N(i)| - 1), to *acc (one atomic per block).
 template <typename T>
 __global__ __launch_bounds__(256) void k_count_pairs(int n, const T* __restrict__ nnb,
-                                                     unsigned long long* acc)
+                                                     unsigned long long* acc, Guard gd)
 {
+    if (guard_stop(gd)) return;
     __shared__ int part[4];
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     int v = s < n ? (int)nnb[s] - 1 : 0;
@@ -678,10 +684,12 @@ template <typename T>
 static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u, double* v,
                   double* p, const double* h, const int64_t* mq, const int32_t* kind,
                   const double* rho_in, double dt, PassAOut aout, double* dpdt, double* dudt,
-                  double* dvdt)
+                  double* dvdt, Guard gd)
 {
     Work& w = c->w;
-    int rc = ensure_list(c, n, x, y, h);
+    // in a run of steps the caller holds a valid list; its checks run on
+    // the device and trip the run when the list expires
+    int rc = gd.trip ? SPH_OK : ensure_list(c, n, x, y, h);
     if (rc) return rc;
     if (n == 0) return SPH_OK;
     NbrView nv = nbr_view(c);
@@ -698,12 +706,12 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
         int32_t* bnext = w.status + 16 + (c->bparity ^ 1);
         c->bparity ^= 1;
         hipLaunchKernelGGL(k_bmark, dim3(nb), dim3(256), 0, c->stream, n, (const int32_t*)nv.perm, kind,
-                           blist, bcount);
+                           blist, bcount, gd);
         const unsigned nbw = (unsigned)(nb < 512 ? nb : 512);
         hipLaunchKernelGGL(k_boundary, dim3(nbw), dim3(256), 0, c->stream, c->grid, nv, nl, n,
                            (const int32_t*)blist, (const int32_t*)bcount, bnext, kind, x, y, h,
                            rho_in, u, v, p, w.ug, w.vg, cf.body_force[0] - cf.wall_accel[0],
-                           cf.body_force[1] - cf.wall_accel[1]);
+                           cf.body_force[1] - cf.wall_accel[1], gd);
         LAUNCHCHK(c, "boundary");
     }
     using T4 = typename Vec4<T>::type;
@@ -711,7 +719,7 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     hipLaunchKernelGGL(k_gather_state<T>, dim3(nb), dim3(256), 0, c->stream, n, nv.perm, u, v, p, mq,
                        cf.mass_q, x, y, h, w.xs, w.ys, w.hs, w.xyh, w.pa, w.puv, b.m,
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
-                       w.ugs, w.vgs, kind);
+                       w.ugs, w.vgs, kind, gd);
     LAUNCHCHK(c, "gather_state");
     prof_begin(c, SPH_PROF_PASS_A);
     // exact rows for pass B in the adaptation CSR buffer (free during the
@@ -719,7 +727,7 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     NbrList ex{w.col_tmp, w.cnt_ex, EX_K, n, nullptr};
     if (!w.col_tmp || !w.cnt_ex || w.col_cap < (int64_t)EX_K * n) ex.idx = nullptr;
     hipLaunchKernelGGL(k_pass_a<T>, dim3((unsigned)cdiv((int64_t)n * RGA, 256)), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex);
+                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex, gd);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
     const unsigned nbb = (unsigned)cdiv((int64_t)n * RGB, 256);
@@ -728,16 +736,16 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     if (gh)
         hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                            ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
-                           (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt);
+                           (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt, gd);
     else
         hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
                            ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
-                           (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt);
+                           (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt, gd);
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");
     if (c->pair_acc) {
         hipLaunchKernelGGL(k_count_pairs<T>, dim3(nb), dim3(256), 0, c->stream, n, (const T*)b.nnb,
-                           c->pair_acc);
+                           c->pair_acc, gd);
         LAUNCHCHK(c, "count_pairs");
     }
     return SPH_OK;
@@ -745,11 +753,12 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
 
 static int eval(sph_ctx* c, int n, const double* x, const double* y, double* u, double* v, double* p,
                 const double* h, const int64_t* mq, const int32_t* kind, const double* rho_in,
-                double dt, PassAOut aout, double* dpdt, double* dudt, double* dvdt)
+                double dt, PassAOut aout, double* dpdt, double* dudt, double* dvdt,
+                Guard gd = Guard{nullptr, 0})
 {
     if (c->cfg.precision == SPH_FP32)
-        return eval_T<float>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt);
-    return eval_T<double>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt);
+        return eval_T<float>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt, gd);
+    return eval_T<double>(c, n, x, y, u, v, p, h, mq, kind, rho_in, dt, aout, dpdt, dudt, dvdt, gd);
 }
 
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out)
@@ -783,14 +792,17 @@ struct ListCheck {
     int32_t* flag;
 };
 
-__device__ __forceinline__ void list_check_at(const Grid& g, const ListCheck& lc, int i, double x,
-                                              double y, double h)
+__device__ __forceinline__ void list_check_at(const Grid& g, const ListCheck& lc, const Guard& gd,
+                                              int i, double x, double y, double h)
 {
     if (!lc.flag) return;
     const double dx = mi_axis(g, 0, x - lc.xref[i]);
     const double dy = mi_axis(g, 1, y - lc.yref[i]);
     const double r = lc.lim * lc.href[i];
-    if (!(dx * dx + dy * dy < r * r) || h != lc.href[i]) lc.flag[0] = 1;
+    if (!(dx * dx + dy * dy < r * r) || h != lc.href[i]) {
+        lc.flag[0] = 1;
+        guard_trip(gd);  // in a run of steps the next evaluation waits for the host
+    }
 }
 
 __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* __restrict__ kind,
@@ -806,8 +818,9 @@ __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* _
                                                  const double* __restrict__ dys, double dt,
                                                  double* xh, double* yh, double* uh, double* vh,
                                                  double* ph, const double* __restrict__ h,
-                                                 ListCheck lc)
+                                                 ListCheck lc, Guard gd)
 {
+    if (guard_stop(gd)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double xn, yn;
@@ -830,7 +843,7 @@ __global__ __launch_bounds__(256) void k_predict(Grid g, int n, const int32_t* _
     }
     xh[i] = xn;
     yh[i] = yn;
-    list_check_at(g, lc, i, xn, yn, h[i]);
+    list_check_at(g, lc, gd, i, xn, yn, h[i]);
 }
 
 __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* __restrict__ kind,
@@ -843,8 +856,9 @@ __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* _
                                                  const double* __restrict__ uh,
                                                  const double* __restrict__ vh,
                                                  const double* __restrict__ ph,
-                                                 const double* __restrict__ h, ListCheck lc)
+                                                 const double* __restrict__ h, ListCheck lc, Guard gd)
 {
+    if (guard_stop(gd)) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double xn = x[i], yn = y[i];
@@ -873,48 +887,95 @@ __global__ __launch_bounds__(256) void k_correct(Grid g, int n, const int32_t* _
         v[i] = vn;
         p[i] = p[i] + dt * ap[i];
     }
-    list_check_at(g, lc, i, xn, yn, h[i]);
+    list_check_at(g, lc, gd, i, xn, yn, h[i]);
+}
+
+// The list check of an evaluation runs inside the kernel that writes its
+// positions while a reusable list is held.
+static ListCheck list_check_for(sph_ctx* c, int n)
+{
+    Work& w = c->w;
+    const bool held = c->list_valid && c->list_n == n && c->skin > 0;
+    return held ? ListCheck{w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag}
+                : ListCheck{nullptr, nullptr, nullptr, 0.0, nullptr};
+}
+
+// First half of a PEC step: the evaluation at the current state, then the
+// predictor (eq. int-pre).  gd1 guards the evaluation, gd2 the predictor
+// (which trips the run when the list expires at the predicted positions).
+int step_half1(sph_ctx* c, sph_particles* ps, double dt, Guard gd1, Guard gd2)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    const unsigned nb = (unsigned)cdiv(n, 256);
+    // every evaluation stores its summation density: the next boundary pass
+    // reads it, and the caller gets the last one
+    PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, dt,
+                  withrho, w.r_dpdt, w.r_dudt, w.r_dvdt, gd1);
+    if (rc) return rc;
+    ListCheck lc = list_check_for(c, n);
+    hipLaunchKernelGGL(k_predict, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
+                       ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
+                       w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph, (const double*)ps->h, lc, gd2);
+    LAUNCHCHK(c, "predict");
+    c->fused_x = (lc.flag && !gd2.trip) ? w.xh : nullptr;
+    return SPH_OK;
+}
+
+// Second half: the evaluation at the predicted state, then the corrector
+// (eq. int-cor), whose list check is for the next step's first evaluation.
+int step_half2(sph_ctx* c, sph_particles* ps, double dt, Guard gd3, Guard gd4)
+{
+    Work& w = c->w;
+    const int n = (int)ps->n;
+    const unsigned nb = (unsigned)cdiv(n, 256);
+    PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, ps->kind, ps->rho, dt, withrho,
+                  w.r_dpdt, w.r_dudt, w.r_dvdt, gd3);
+    if (rc) return rc;
+    ListCheck lc = list_check_for(c, n);
+    hipLaunchKernelGGL(k_correct, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
+                       ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
+                       w.r_dys, dt, (const double*)w.uh, (const double*)w.vh,
+                       (const double*)w.ph, (const double*)ps->h, lc, gd4);
+    LAUNCHCHK(c, "correct");
+    c->fused_x = (lc.flag && !gd4.trip) ? ps->x : nullptr;
+    return SPH_OK;
 }
 
 int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
 {
-    Work& w = c->w;
     const int n = (int)ps->n;
     if (n == 0) return SPH_OK;
-    unsigned nb = (unsigned)cdiv(n, 256);
-    // every evaluation stores its summation density: the next boundary pass
-    // reads it, and the caller gets the last one
-    PassAOut withrho{ps->rho, nullptr, nullptr, nullptr, nullptr, nullptr};
-    // the list check of each evaluation runs inside the kernel that writes
-    // its positions while a reusable list is held
-    auto check = [&]() {
-        const bool held = c->list_valid && c->list_n == n && c->skin > 0;
-        return held ? ListCheck{w.xref, w.yref, w.href, 1.5 * c->skin, w.list_flag}
-                    : ListCheck{nullptr, nullptr, nullptr, 0.0, nullptr};
-    };
+    const Guard none{nullptr, 0};
     c->fused_x = nullptr;
     for (int s = 0; s < nsteps; ++s) {
-        int rc = eval(c, n, ps->x, ps->y, ps->u, ps->v, ps->p, ps->h, ps->mq, ps->kind, ps->rho, dt,
-                      withrho, w.r_dpdt, w.r_dudt, w.r_dvdt);
+        int rc = step_half1(c, ps, dt, none, none);
         if (rc) return rc;
-        ListCheck lc = check();
-        hipLaunchKernelGGL(k_predict, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
-                           ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
-                           w.r_dys, dt, w.xh, w.yh, w.uh, w.vh, w.ph, (const double*)ps->h, lc);
-        LAUNCHCHK(c, "predict");
-        c->fused_x = lc.flag ? w.xh : nullptr;
-        rc = eval(c, n, w.xh, w.yh, w.uh, w.vh, w.ph, ps->h, ps->mq, ps->kind, ps->rho, dt, withrho,
-                  w.r_dpdt, w.r_dudt, w.r_dvdt);
+        rc = step_half2(c, ps, dt, none, none);
         if (rc) return rc;
-        lc = check();
-        hipLaunchKernelGGL(k_correct, dim3(nb), dim3(256), 0, c->stream, c->grid, n, ps->kind, ps->x,
-                           ps->y, ps->u, ps->v, ps->p, w.r_dpdt, w.r_dudt, w.r_dvdt, w.r_dxs,
-                           w.r_dys, dt, (const double*)w.uh, (const double*)w.vh,
-                           (const double*)w.ph, (const double*)ps->h, lc);
-        LAUNCHCHK(c, "correct");
-        c->fused_x = lc.flag ? ps->x : nullptr;
     }
     return SPH_OK;
+}
+
+// Clears the boundary-list counters (after skipped evaluations of a run of
+// steps the alternation of the two counters no longer holds).
+__global__ void k_reset_bcounters(int32_t* st)
+{
+    if (threadIdx.x < 2) st[threadIdx.x] = 0;
+}
+
+void reset_bcounters(sph_ctx* c)
+{
+    hipLaunchKernelGGL(k_reset_bcounters, dim3(1), dim3(64), 0, c->stream, c->w.status + 16);
+    c->bparity = 0;
+}
+
+// Makes the list valid for the current positions (building or checking it).
+int list_ready(sph_ctx* c, const sph_particles* ps)
+{
+    return ensure_list(c, (int)ps->n, ps->x, ps->y, ps->h);
 }
 
 // ---------------------------------------------------------------------------

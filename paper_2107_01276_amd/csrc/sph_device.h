@@ -429,6 +429,13 @@ __device__ __forceinline__ int group_rank(bool pass, int gl, int* total)
     return __popc(gm & ((1u << gl) - 1u));
 }
 
+// A guarded kernel stops when a kernel enqueued before it has tripped.
+__device__ __forceinline__ bool guard_stop(const Guard& gd) { return gd.trip && *gd.trip < gd.seq; }
+__device__ __forceinline__ void guard_trip(const Guard& gd)
+{
+    if (gd.trip) atomicMin(gd.trip, gd.seq);
+}
+
 // ---- XCD-aware block order -----------------------------------------------------
 // Workgroups are dispatched to the 8 XCDs round-robin (XCD = blockIdx % 8),
 // and each XCD has its own L2.  Renumbering so that XCD x runs a contiguous

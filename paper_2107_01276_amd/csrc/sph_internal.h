@@ -21,6 +21,18 @@
 
 #define SPH_MAXL 16
 
+// Speculatively enqueued runs of steps: every guarded kernel carries the
+// sequence number of its place in the run; a kernel that finds a condition
+// the host must handle (an expired neighbour list, an inlet/outlet slot
+// change) lowers *trip to its own number, and every kernel with a larger
+// number returns at once, leaving the state as it was after the tripping
+// kernel.  trip == nullptr: not in such a run (always executes).
+#define SPH_NOTRIP 0x7fffffff
+struct Guard {
+    int32_t* trip;
+    int32_t seq;
+};
+
 struct Grid {
     double org[2];      // origin of the level-0 grid per axis
     double cw0[2];      // level-0 cell width per axis
@@ -175,6 +187,12 @@ size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* 
 // rates.hip
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out);
 int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps);
+// the two halves of a PEC step, each an evaluation then the predictor or
+// corrector, guarded in a speculatively enqueued run of steps
+int step_half1(sph_ctx* c, sph_particles* ps, double dt, Guard gd1, Guard gd2);
+int step_half2(sph_ctx* c, sph_particles* ps, double dt, Guard gd3, Guard gd4);
+void reset_bcounters(sph_ctx* c);
+int list_ready(sph_ctx* c, const sph_particles* ps);
 // force on the solid particles (8 doubles to the host, see sph_body_force)
 int body_force_run(sph_ctx* c, sph_particles* ps, double* force);
 bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h);
@@ -182,6 +200,8 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);
 
 // adapt.hip
 int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt_map* map);
+int inout_apply(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map,
+                int32_t nto);
 int inout_run(sph_ctx* c, sph_particles* ps, const sph_inout_params* io, sph_inout_map* map,
               bool precheck = false);
 int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const sph_inout_params* io,

@@ -147,10 +147,14 @@ def test_couette_startup_fp32():
     assert err < 0.01
 
 
-def test_step_inout_equals_separate_calls():
+@pytest.mark.parametrize("skin", [0.02, 0.1, 0.3])
+def test_step_inout_equals_separate_calls(skin):
     """sph_step_inout: the same state as sph_step + sph_inout called step by
     step (bit for bit), with the counters summed and the origin maps
-    composed, over enough steps for inlet particles to enter the fluid."""
+    composed, over enough steps for inlet particles to enter the fluid.
+    sph_step_inout enqueues its steps as guarded runs; the skins make the
+    list expire at predicted and corrected positions at different steps, and
+    the inlet crossings move slots, so every way a run stops is taken."""
     P = lib()
     s = _io_case()
     s["u"] = np.where(s["kind"] == W.INLET, 1.0, s["u"])
@@ -158,7 +162,8 @@ def test_step_inout_equals_separate_calls():
     nsteps = 40
     n = s["x"].size
     cap = 2 * n
-    ctx_a = ctx_for(P, s, P.SPH_FP64, capacity=cap)
+    print(f"[step_inout] skin={skin}", flush=True)
+    ctx_a = ctx_for(P, s, P.SPH_FP64, capacity=cap, list_skin=skin)
     A = particles(P, s, capacity=cap)
     comp = np.arange(n)
     tot = {"appended": 0, "deleted": 0, "to_outlet": 0}
@@ -168,7 +173,7 @@ def test_step_inout_equals_separate_calls():
         for k in tot:
             tot[k] += info[k]
         comp = comp[info["origin"].cpu().numpy()]
-    ctx_b = ctx_for(P, s, P.SPH_FP64, capacity=cap)
+    ctx_b = ctx_for(P, s, P.SPH_FP64, capacity=cap, list_skin=skin)
     B = particles(P, s, capacity=cap)
     ib = ctx_b.step_inout(B, dt, nsteps, s["io"])
     print(f"[step_inout] n {A.n} {B.n} counts {tot} {ib}", flush=True)
