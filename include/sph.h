@@ -356,11 +356,13 @@ int sph_body_force(sph_ctx *ctx, sph_particles *ps, double *force);
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 
-/* Profiling: `on` is a bit mask of the kernels to bracket with HIP events
+/* Profiling: bits 0-3 of `on` select the kernels to bracket with HIP events
  * on the context's stream (1 "pass_a", 2 "pass_b", 4 "build" (neighbour
- * sort and tables), 8 "list" (rate-pass list)); 0 turns profiling off.
- * sph_profile_read synchronises and returns total milliseconds and launch
- * count of the named kernel since the last reset. */
+ * sort and tables), 8 "list" (rate-pass list)); bits 8-15 give a sampling
+ * period p (0 or 1: every launch; p: every p-th launch of each selected
+ * kernel); 0 turns profiling off.  sph_profile_read synchronises and
+ * returns the total milliseconds and the count of the bracketed launches of
+ * the named kernel since the last reset. */
 int sph_profile_enable(sph_ctx *ctx, int32_t on);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, double *ms, int64_t *launches);
 int sph_profile_reset(sph_ctx *ctx);

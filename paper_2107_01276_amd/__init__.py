@@ -473,8 +473,11 @@ class Context:
 
     PROFILE_BITS = {"pass_a": 1, "pass_b": 2, "build": 4, "list": 8}
 
-    def profile(self, on: bool = True, kernels=("pass_a", "pass_b", "build", "list")):
-        mask = sum(self.PROFILE_BITS[k] for k in kernels) if on else 0
+    def profile(self, on: bool = True, kernels=("pass_a", "pass_b", "build", "list"), every: int = 1):
+        """Brackets every `every`-th launch of the named kernels with events."""
+        if not 1 <= every <= 255:
+            raise ValueError("every must be in [1, 255]")
+        mask = (sum(self.PROFILE_BITS[k] for k in kernels) | (every << 8)) if on else 0
         self._check(self.lib.sph_profile_enable(self._h, int(mask)))
 
     def profile_reset(self):

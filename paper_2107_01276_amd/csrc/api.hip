@@ -484,10 +484,15 @@ static void prof_flush(sph_ctx* c, int slot)
     s.count = 0;
 }
 
+// Every prof_every-th launch of a selected kernel is bracketed (the event
+// markers keep consecutive kernels from overlapping, so sparse sampling
+// disturbs the timed work less).
 void prof_begin(sph_ctx* c, int slot)
 {
     if (!c->prof_on || !(c->prof_mask & (1 << slot))) return;
     ProfSlot& s = c->prof[slot];
+    s.skip = (s.tick++ % (uint32_t)c->prof_every) != 0;
+    if (s.skip) return;
     if (s.count == 512) prof_flush(c, slot);
     hipEventRecord(s.ev[0][s.count], c->stream);
 }
@@ -496,6 +501,7 @@ void prof_end(sph_ctx* c, int slot)
 {
     if (!c->prof_on || !(c->prof_mask & (1 << slot))) return;
     ProfSlot& s = c->prof[slot];
+    if (s.skip) return;
     hipEventRecord(s.ev[1][s.count], c->stream);
     s.count++;
 }
@@ -504,6 +510,9 @@ extern "C" int sph_profile_enable(sph_ctx* c, int32_t on)
 {
     if (!c) return SPH_E_INVAL;
     c->prof_mask = on & 15;
+    c->prof_every = (on >> 8) & 255;
+    if (c->prof_every < 1) c->prof_every = 1;
+    for (int s = 0; s < 4; ++s) c->prof[s].tick = 0;
     if (on && !c->prof_on) {
         for (int s = 0; s < 4; ++s) {
             for (int k = 0; k < 512; ++k) {

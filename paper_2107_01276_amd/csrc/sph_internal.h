@@ -118,7 +118,9 @@ struct ProfSlot {
     hipEvent_t ev[2][512];
     int32_t count;
     double ms;
-    int64_t launches;
+    int64_t launches;   // bracketed launches
+    uint32_t tick;      // launches seen (bracketed or not)
+    int32_t skip;       // the current launch is not bracketed
 };
 
 struct sph_ctx {
@@ -131,6 +133,7 @@ struct sph_ctx {
     char err[512];
     int32_t prof_on;
     int32_t prof_mask;  // which slots are bracketed (bit = slot)
+    int32_t prof_every; // bracket every prof_every-th launch of a slot
     ProfSlot prof[4];
     int built_n;       // particle count of the last build
     // Neighbour-list reuse: the list holds every pair closer than
