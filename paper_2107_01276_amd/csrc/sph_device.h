@@ -391,6 +391,39 @@ __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& n
             }
         }
     };
+    const int x0n = xr.b0 - xr.a0 + 1, y0n = yr.b0 - yr.a0 + 1;
+    const int nxc = x0n + (xr.n == 2 ? xr.b1 - xr.a1 + 1 : 0);
+    const int nyc = y0n + (yr.n == 2 ? yr.b1 - yr.a1 + 1 : 0);
+    constexpr int CPL = (16 + G - 1) / G;  // cells per lane in the batched case
+    if (nxc * nyc <= 16) {
+        // up to 4 x 4 cells (the usual case): the lanes of the group share
+        // the cells' gap tests and table loads (cell k on lane k % G), all
+        // issued before any run is walked; runs are then taken in cell order
+        int2 own[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int k = gl + G * t;
+            own[t] = make_int2(0, 0);
+            if (k < nxc * nyc) {
+                const int kx = k % nxc, ky = k / nxc;
+                const int cx = kx < x0n ? xr.a0 + kx : xr.a1 + (kx - x0n);
+                const int cy = ky < y0n ? yr.a0 + ky : yr.a1 + (ky - y0n);
+                const double gx = cell_gap(g, 0, xi, cx, Q), gy = cell_gap(g, 1, yi, cy, Q);
+                if (gx * gx + gy * gy <= Rs2) own[t] = tab[(int64_t)cy * nq + cx];
+            }
+        }
+        const int base = __lane_id() & ~(G - 1);
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (G * t + q >= nxc * nyc) break;
+                const int2 se = make_int2(__shfl(own[t].x, base + q, 64), __shfl(own[t].y, base + q, 64));
+                run(se);
+            }
+        }
+        return;
+    }
     for (int ty = 0; ty < yr.n; ++ty) {
         const int cy0 = ty ? yr.a1 : yr.a0, cy1 = ty ? yr.b1 : yr.b0;
         for (int cy = cy0; cy <= cy1; ++cy) {
