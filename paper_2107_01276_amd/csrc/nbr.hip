@@ -97,7 +97,7 @@ size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* 
     int64_t nb = cdiv(capacity > 0 ? capacity : 1, RS_TILE);
     size_t b = 0;
     b += (size_t)g->tab_total * sizeof(int2) + 256;
-    b += (size_t)256 * nb * sizeof(uint32_t) + 256;
+    b += (size_t)RS_BINS * nb * sizeof(uint32_t) + 256;
     return b;
 }
 
@@ -241,26 +241,26 @@ __global__ void k_zero_int2(int2* p, int64_t n)
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort, 8-bit digits.  Each block owns RS_TILE consecutive
+// Stable LSD radix sort, RS_BITS-bit digits.  Each block owns RS_TILE consecutive
 // keys; each wave owns a contiguous quarter of the tile and ranks its keys
-// with 8 ballots per 64-key chunk (lanes with equal digits), so the order of
+// with one ballot per digit bit per 64-key chunk (lanes with equal digits), so the order of
 // equal digits is the input order.
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int n,
                                                         int shift, uint32_t* hist, int nblk)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    __shared__ uint32_t h[RS_BINS];
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) h[d] = 0;
     __syncthreads();
     const int base = blockIdx.x * RS_TILE;
 #pragma unroll
     for (int k = 0; k < RS_ITEMS; ++k) {
         int i = base + k * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RS_BINS - 1u)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
@@ -272,9 +272,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
                                                            int nblk)
 {
     constexpr int NW = RS_THREADS / 64;
-    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint32_t wcnt[NW][RS_BINS];
     const int lane = __lane_id(), w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < NW * 256; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
+    for (int d = threadIdx.x; d < NW * RS_BINS; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int wbase = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS);
@@ -286,10 +286,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
         int i = wbase + it * 64 + lane;
         bool valid = i < n;
         uint64_t k = valid ? kin[i] : 0ull;
-        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint32_t d = (uint32_t)(k >> shift) & (RS_BINS - 1u);
         uint64_t mask = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < RS_BITS; ++b) {
             bool bit = (d >> b) & 1u;
             uint64_t bal = __ballot(bit);
             mask &= bit ? bal : ~bal;
@@ -304,16 +304,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
         __builtin_amdgcn_wave_barrier();
         kk[it] = k;
         vv[it] = valid ? vin[i] : 0;
-        dd[it] = valid ? d : 256u;
+        dd[it] = valid ? d : (uint32_t)RS_BINS;
         rk[it] = old + before;
     }
     __syncthreads();
-    if (threadIdx.x < 256) {
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) {
         uint32_t s = 0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            uint32_t t = wcnt[q][threadIdx.x];
-            wcnt[q][threadIdx.x] = s;
+            uint32_t t = wcnt[q][d];
+            wcnt[q][d] = s;
             s += t;
         }
     }
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         uint32_t d = dd[it];
-        if (d < 256u) {
+        if (d < (uint32_t)RS_BINS) {
             uint32_t pos = offs[(int64_t)d * nblk + blockIdx.x] + wcnt[w][d] + rk[it];
             kout[pos] = kk[it];
             vout[pos] = vv[it];
@@ -334,15 +334,15 @@ static int radix_sort(sph_ctx* c, int n, int keybits)
 {
     Work& w = c->w;
     int nblk = (int)cdiv(n, RS_TILE);
-    int npass = (keybits + 7) / 8;
+    int npass = (keybits + RS_BITS - 1) / RS_BITS;
     uint64_t *ka = w.keys_a, *kb = w.keys_b;
     int32_t *va = w.vals_a, *vb = w.vals_b;
     for (int p = 0; p < npass; ++p) {
-        int shift = 8 * p;
+        int shift = RS_BITS * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, n, shift,
                            w.hist, nblk);
         LAUNCHCHK(c, "rs_hist");
-        int rc = scan_rec<uint32_t>(c, w.hist, w.hist, (int64_t)256 * nblk, (int64_t)256 * nblk,
+        int rc = scan_rec<uint32_t>(c, w.hist, w.hist, (int64_t)RS_BINS * nblk, (int64_t)RS_BINS * nblk,
                                     (uint32_t*)w.scan_tmp);
         if (rc) return rc;
         hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, va, kb,

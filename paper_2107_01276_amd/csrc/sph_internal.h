@@ -245,6 +245,10 @@ void prof_end(sph_ctx* c, int slot);
 #define RS_THREADS 256
 #define RS_ITEMS 8
 #define RS_TILE (RS_THREADS * RS_ITEMS)
+#ifndef RS_BITS
+#define RS_BITS 12           // digit width of the LSD radix sort
+#endif
+#define RS_BINS (1 << RS_BITS)
 #define SCAN_T 256
 #define SCAN_E 8
 #define SCAN_TILE (SCAN_T * SCAN_E)
