@@ -77,6 +77,16 @@ struct CSum {
         c += co;
     }
 };
+// Plain running sum, for sums whose terms share one sign (no cancellation).
+template <typename T>
+struct PSum {
+    T s;
+    __device__ __forceinline__ PSum() : s(T(0)) {}
+    __device__ __forceinline__ void add(T x) { s += x; }
+    __device__ __forceinline__ T get() const { return s; }
+    __device__ __forceinline__ void merge_xor(int o) { s += __shfl_xor(s, o, 64); }
+};
+
 template <>
 struct CSum<double> {
     double s;
