@@ -441,6 +441,17 @@ __global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double 
 // rcnt[i].  Four lanes share a row; entry base + gl goes to lane gl, and
 // passing entries are ranked by lane, so the order is the row's.
 #define FG 4
+// Radius of the first superset CSR of an adaptation beyond the support
+// (fraction of it); the shifts' measured displacements decide whether it
+// still covers their rows.
+#ifndef SHIFT_SKIN
+#define SHIFT_SKIN 0.15
+#endif
+
+__global__ void k_clear_u64(unsigned long long* p)
+{
+    if (threadIdx.x == 0) p[0] = 0ull;
+}
 __global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32_t* __restrict__ kind,
                                                       const double4* __restrict__ A,
                                                       const int64_t* __restrict__ rp,
@@ -490,29 +501,17 @@ __global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32
 
 // EXACT: rows hold exactly the neighbours (from k_shift_filter), counts in
 // rcnt; otherwise rows may be a superset, re-tested entry by entry.
+// One fluid row of the shift and Taylor correction; returns |dr_i| / h_i.
 template <bool EXACT>
-__global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32_t* __restrict__ kind,
-                                                      const double4* __restrict__ A,
-                                                      const double4* __restrict__ B,
-                                                      const int64_t* __restrict__ rp,
-                                                      const int32_t* __restrict__ col,
-                                                      const int32_t* __restrict__ rcnt,
-                                                      double rho0, double* ddx_o, double* ddy_o,
-                                                      double* nu_o, double* nv_o, double* np_o,
-                                                      const int32_t* __restrict__ order)
+__device__ __forceinline__ double shift_row(const Grid& g, const double4* __restrict__ A,
+                                            const double4* __restrict__ B,
+                                            const int64_t* __restrict__ rp,
+                                            const int32_t* __restrict__ col,
+                                            const int32_t* __restrict__ rcnt, double rho0, int i,
+                                            double4 ai, double4 bi, double* ddx_o, double* ddy_o,
+                                            double* nu_o, double* nv_o, double* np_o)
 {
-    // rows are taken in `order` (a spatial order of the slots) when given,
-    // so that a wave's neighbours share cache lines
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const int i = order ? order[t] : t;
-    const double4 ai = A[i], bi = B[i];
     const double ui = bi.x, vi = bi.y, pi = bi.z;
-    if (kind && kind[i] != SPH_FLUID) {
-        ddx_o[i] = 0.0; ddy_o[i] = 0.0;
-        nu_o[i] = ui; nv_o[i] = vi; np_o[i] = pi;
-        return;
-    }
     // shift sums and the Taylor gradients share one sweep over the row; every
     // accumulator still adds its terms in ascending column order
     const double fxi = kern_f<double>(SPH_XI);
@@ -584,6 +583,44 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
     nu_o[i] = ui + (gux * ddx + guy * ddy);
     nv_o[i] = vi + (gvx * ddx + gvy * ddy);
     np_o[i] = pi + (gpx * ddx + gpy * ddy);
+    return sqrt(ddx * ddx + ddy * ddy) / hi;
+}
+
+template <bool EXACT>
+__global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32_t* __restrict__ kind,
+                                                      const double4* __restrict__ A,
+                                                      const double4* __restrict__ B,
+                                                      const int64_t* __restrict__ rp,
+                                                      const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ rcnt,
+                                                      double rho0, double* ddx_o, double* ddy_o,
+                                                      double* nu_o, double* nv_o, double* np_o,
+                                                      const int32_t* __restrict__ order,
+                                                      unsigned long long* dmax)
+{
+    // rows are taken in `order` (a spatial order of the slots) when given,
+    // so that a wave's neighbours share cache lines
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double rel = 0.0;  // |dr_i| / h_i
+    if (t < n) {
+        const int i = order ? order[t] : t;
+        const double4 ai = A[i], bi = B[i];
+        const double ui = bi.x, vi = bi.y, pi = bi.z;
+        if (kind && kind[i] != SPH_FLUID) {
+            ddx_o[i] = 0.0; ddy_o[i] = 0.0;
+            nu_o[i] = ui; nv_o[i] = vi; np_o[i] = pi;
+        } else {
+            rel = shift_row<EXACT>(g, A, B, rp, col, rcnt, rho0, i, ai, bi, ddx_o, ddy_o, nu_o,
+                                   nv_o, np_o);
+        }
+    }
+    // dmax (when given) receives the largest |dr_i| / h_i of the launch:
+    // every lane of the wave is here (no early exit above)
+    if (dmax) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) rel = fmax(rel, __shfl_xor(rel, o, 64));
+        if (__lane_id() == 0 && rel > 0.0) atomicMax(dmax, (unsigned long long)__double_as_longlong(rel));
+    }
 }
 
 __global__ __launch_bounds__(256) void k_shift_apply(Grid g, int n, FluidState s,
@@ -790,13 +827,29 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
     // kernels re-apply the exact predicate to the ascending rows, so the
     // sums are those of a fresh neighbour list.  If that superset does not
     // fit the internal buffer, each pass builds its own exact list.
+    //
+    // The superset is first built tighter than that worst case: with radius
+    // factor sf it covers every later pair while the shifts so far moved
+    // the particles by sum_k D_k <= 1.5 (sf - 1), D_k the largest |dr|/h of
+    // shift k (a pair's distance changes by at most 2 D_k max(h_i, h_j) per
+    // shift).  Each shift publishes its D_k; once the sum would leave the
+    // allowance the superset is rebuilt with the worst-case factor for the
+    // shifts that remain.
     bool super = false;
+    double allow = 0.0, spent = 0.0;  // allow < 0: worst-case rows, no check
+    auto build_super = [&](int remaining, bool tight) -> int {
+        const double sf = tight ? 1.0 + SHIFT_SKIN : 1.0 + remaining / 6.0;
+        int r = internal_csr(c, n, ps->x, ps->y, ps->h, sf + 1e-9);
+        allow = tight ? 1.5 * SHIFT_SKIN : -1.0;
+        spent = 0.0;
+        return r;
+    };
     if (n > 0) {
-        const double sf = 1.0 + cf.shift_iters / 6.0 + 1e-9;
-        rc = internal_csr(c, n, ps->x, ps->y, ps->h, sf);
+        rc = build_super(cf.shift_iters, cf.shift_iters > 0);
         if (rc == SPH_OK) super = true;
         else if (rc != SPH_E_CAPACITY) return rc;
     }
+    unsigned long long* dmax = (unsigned long long*)(w.ctr + 4);
     // each shift first filters its rows into the rate-list buffer (free
     // here; it is rebuilt after adaptation) when that holds every row
     const bool filt = w.cnt_ex && (int64_t)w.nl_k * w.capacity >= w.col_cap;
@@ -805,7 +858,12 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (!super) {
             rc = internal_csr(c, n, ps->x, ps->y, ps->h);
             if (rc) return rc;
+        } else if (allow >= 0.0 && spent > allow) {
+            rc = build_super(cf.shift_iters - it, false);
+            if (rc) return rc;
         }
+        const bool measure = super && allow >= 0.0;
+        if (measure) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->stream, dmax);
         unsigned nb = (unsigned)cdiv(n, 256);
         // packed records in the rate passes' buffers (free during adaptation);
         // rows in the sorted order of the last build (slots unchanged since)
@@ -818,19 +876,35 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             hipLaunchKernelGGL(k_shift_taylor<true>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
                                (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
                                w.nl_idx, (const int32_t*)w.cnt_ex, cf.rho0, w.tmp_d[0], w.tmp_d[1],
-                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
+                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a,
+                               measure ? dmax : nullptr);
         } else {
             hipLaunchKernelGGL(k_shift_taylor<false>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
                                (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
                                w.col_tmp, (const int32_t*)nullptr, cf.rho0, w.tmp_d[0], w.tmp_d[1],
-                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a);
+                               w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a,
+                               measure ? dmax : nullptr);
         }
         hipLaunchKernelGGL(k_shift_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, w.tmp_d[0],
                            w.tmp_d[1], w.tmp_d[2], w.tmp_d[3], w.tmp_d[4]);
         LAUNCHCHK(c, "shift");
+        if (measure) {
+            unsigned long long bits = 0;
+            const Readback rb{&bits, dmax, 8};
+            rc = readback(c, &rb, 1);
+            if (rc) return rc;
+            double d = 0.0;
+            memcpy(&d, &bits, sizeof(d));
+            // bound taken with a margin for the rounding of |dr| / h
+            spent += d * (1.0 + 1e-12) + 1e-15;
+        }
     }
     if (n > 0) {
         if (!super) {
+            rc = internal_csr(c, n, ps->x, ps->y, ps->h);
+            if (rc) return rc;
+        } else if (allow >= 0.0 && spent > allow) {
+            // the h update needs the neighbours of the final positions
             rc = internal_csr(c, n, ps->x, ps->y, ps->h);
             if (rc) return rc;
         }
