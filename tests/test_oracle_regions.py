@@ -1,0 +1,116 @@
+"""Pins of the oracle's background update used as a user-defined refinement
+region and with moving bodies (section 3.3), and of the adaptation it drives
+on the Taylor-Green vortex with an inner zone twice as fine (section 4.1)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.lib()
+    return oracle
+
+
+@pytest.fixture(scope="module")
+def zone(orc):
+    s = W.tgv_zone(50)
+    bp = s["bg_params"]
+    bg = s["background"]
+    prm = orc.BgPrm(cr=bp["cr"], ds_min=bp["ds_min"], ds_max=bp["ds_max"], mass_q=bg["mass_q"])
+    dom = orc.Dom((0.0, 0.0), (1.0, 1.0), (True, True))
+    out, nsplit = orc.bg_update(dom, prm, bg, s["markers"], bp["passes"], cap=200000)
+    return s, out, nsplit, dom
+
+
+def _zone_dist(x, y, zone):
+    (x0, y0), (x1, y1) = zone
+    return np.hypot(np.maximum(np.maximum(x0 - x, x - x1), 0.0),
+                    np.maximum(np.maximum(y0 - y, y - y1), 0.0))
+
+
+def test_zone_background(zone):
+    """Markers filling [0.1, 0.5]^2 at ds_min = dx/2 act as a body: every
+    background particle in the zone asks for ds_min, sizes grow by C_r per
+    level away from it up to ds_max, and the background mass is conserved."""
+    s, out, nsplit, _ = zone
+    bp = s["bg_params"]
+    ds, x, y = out["ds"], out["x"], out["y"]
+    assert bp["passes"] == 12 and nsplit > 0
+    assert out["mq"].sum() == s["background"]["mq"].sum()
+    d = _zone_dist(x, y, s["zone"])
+    assert np.all(ds[d == 0.0] == bp["ds_min"]) and np.all(out["mask"][d == 0.0] == 1)
+    lev = np.unique(np.round(np.log(ds / bp["ds_min"]) / math.log(bp["cr"]), 9))
+    # levels C_r^k ds_min, k = 0..3, and the clamp at ds_max = 2 ds_min
+    assert np.array_equal(lev[:4], np.arange(4)) and lev.size == 5
+    assert lev[4] == pytest.approx(math.log(2.0) / math.log(1.2))
+    assert np.corrcoef(d, ds)[0, 1] > 0.7
+    assert ds.max() == bp["ds_max"] and np.all(out["mref"] == ds * ds)
+    # the marked particles are exactly those within 3 max(h_b, h_s) of a marker
+    m = s["markers"]
+    near = np.zeros(x.size, bool)
+    for k in range(m["x"].size):
+        dx = x - m["x"][k]; dx -= np.round(dx)
+        dy = y - m["y"][k]; dy -= np.round(dy)
+        R = 3.0 * np.maximum(out["h"], m["h"][k])
+        near |= dx * dx + dy * dy < R * R
+    # h changes in the smoothing step after the mark, so compare away from the edge of the reach
+    assert np.all(out["mask"][d < 0.02] == 1)
+    assert np.mean(near == (out["mask"] == 1)) > 0.97
+
+
+def test_zone_adaptation(orc, zone):
+    """One adaptation of the plain lattice with the zone background: the zone
+    is refined (its particles split into seven), particles far outside keep
+    their mass, the ledger is exact, and no particle stays heavier than
+    1.05 m_ref."""
+    s, out, _, dom = zone
+    st = {k: s[k].copy() for k in ("x", "y", "u", "v", "p", "rho", "h", "mq", "kind")}
+    st["mref"] = orc.mref_lookup(dom, st["x"], st["y"], st["h"], out["x"], out["y"], out["h"],
+                                 out["mref"])
+    q = s["mass_q"]
+    o, info = orc.adapt(dom, orc.Prm(mass_q=q, hdx=1.0, nu=0.005), st, cap=8 * s["x"].size)
+    m = o["mq"] * q
+    assert o["mq"].sum() == s["mq"].sum()
+    # the split flags come from the state before the call
+    assert info["n_split"] == int(np.sum(s["mq"] * q > 1.05 * st["mref"])) > 0
+    d = _zone_dist(o["x"], o["y"], s["zone"])
+    m0 = s["mq"][0] * q
+    assert np.all(m[d == 0.0] < m0 / 3)
+    assert (d == 0.0).sum() > 5 * 400  # about 0.16 of the square, refined sevenfold
+
+
+def test_two_bodies_moving(orc):
+    """The moving-geometry example of section 3.3, scaled to a smaller box:
+    two unit squares move apart by 0.05 per step with one background pass per
+    step.  The fine background follows them: ds_min around the new
+    positions, coarse again where they started, mask exactly at the bodies'
+    reach, mass conserved."""
+    D = W.Domain((-6.0, -3.0), (6.0, 3.0), (False, False))
+    dom = orc.Dom(D.lo, D.hi, D.periodic)
+    bg = W.background_lattice(D, 0.4, 1.2, 1.0)
+    bp = orc.BgPrm(cr=1.2, ds_min=0.1, ds_max=0.4, mass_q=bg["mass_q"])
+    b, _ = orc.bg_update(dom, bp, bg, W.two_squares(0.0), 24, cap=200000)
+    steps = 30
+    for k in range(1, steps + 1):
+        b, _ = orc.bg_update(dom, bp, b, W.two_squares(0.05 * k), 1, cap=200000)
+    assert b["mq"].sum() == bg["mq"].sum()
+    x, y, ds = b["x"], b["y"], b["ds"]
+    end = 1.5 + 0.05 * steps
+    for cx in (-end, end):
+        r = np.maximum(np.abs(x - cx), np.abs(y))
+        assert ds[r < 0.8].min() == 0.1 and ds[r < 0.8].max() <= 0.1 * 1.2 + 1e-12
+    for cx in (-1.5, 1.5):  # where the bodies started: coarsened by two levels or more
+        r = np.maximum(np.abs(x - cx), np.abs(y))
+        assert ds[r < 0.4].min() >= 0.1 * 1.2 ** 2 - 1e-12
+    assert ds[np.maximum(np.abs(x), np.abs(y)) < 0.4].min() > 2.5 * 0.1
+    sol = W.two_squares(0.05 * steps)
+    near = np.zeros(x.size, bool)
+    for k in range(sol["x"].size):
+        R = 3.0 * np.maximum(b["h"], sol["h"][k])
+        near |= (x - sol["x"][k]) ** 2 + (y - sol["y"][k]) ** 2 < R * R
+    assert np.mean(near == (b["mask"] == 1)) > 0.97 and np.all(ds[b["mask"] == 1] == 0.1)

@@ -495,6 +495,49 @@ def square_solid(cx: float, cy: float, side: float, ds: float, hdx: float, layer
     return {"x": pts[:, 0].copy(), "y": pts[:, 1].copy(), "h": np.full(len(pts), hdx * ds)}
 
 
+def region_markers(lo, hi, ds: float, hdx: float = 1.0):
+    """A user-defined refinement region (section 3.3): marker particles on a
+    lattice of spacing ds filling the rectangle [lo, hi], handed to the
+    background update as a solid body.  They only mark the background
+    particles near them and take no part in the flow."""
+    nx = max(int(round((hi[0] - lo[0]) / ds)), 1)
+    ny = max(int(round((hi[1] - lo[1]) / ds)), 1)
+    gi, gj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="ij")
+    x = lo[0] + (gi.ravel() + 0.5) * (hi[0] - lo[0]) / nx
+    y = lo[1] + (gj.ravel() + 0.5) * (hi[1] - lo[1]) / ny
+    return {"x": x.astype(np.float64), "y": y.astype(np.float64), "h": np.full(x.size, hdx * ds)}
+
+
+def tgv_zone(nx: int = 50, re: float = 200.0, zone=((0.1, 0.1), (0.5, 0.5)), ratio: float = 2.0,
+             cr: float = 1.2, cs: float = 10.0, rho0: float = 1.0):
+    """Taylor-Green vortex with an inner refinement zone (section 4.1): the
+    fluid starts on the plain nx*nx lattice (dx_max = 1/nx, h = dx) with the
+    exact fields; the background starts as a lattice at dx_max over the
+    periodic square, and marker particles filling the zone at dx_max/ratio
+    ask for ds_min = dx_max/ratio there.  `bg_params` holds C_r, ds_min,
+    ds_max and the number of background passes of the initialisation,
+    3 ceil(ln(ds_max/ds_min)/ln C_r) (three passes per size level)."""
+    s = tgv(nx, jitter=0.0, perturb=False, re=re, cs=cs, rho0=rho0)
+    dx = 1.0 / nx
+    s["background"] = background_lattice(s["domain"], dx, 1.2, rho0)
+    s["markers"] = region_markers(zone[0], zone[1], dx / ratio)
+    s["zone"] = zone
+    s["bg_params"] = {"cr": cr, "ds_min": dx / ratio, "ds_max": dx,
+                      "passes": 3 * math.ceil(math.log(ratio) / math.log(cr) - 1e-12)}
+    return s
+
+
+def two_squares(t: float, gap: float = 3.0, side: float = 1.0, ds: float = 0.1, speed: float = 1.0,
+                hdx: float = 1.2):
+    """The two square bodies of the moving-geometry example of section 3.3 at
+    time t: unit squares centred at (-(gap/2 + speed t), 0) and
+    (gap/2 + speed t, 0), each moving away from the other."""
+    off = 0.5 * gap + speed * t
+    a = square_solid(-off, 0.0, side, ds, hdx)
+    b = square_solid(off, 0.0, side, ds, hdx)
+    return {k: np.concatenate([a[k], b[k]]) for k in ("x", "y", "h")}
+
+
 # ---------------------------------------------------------------------------
 # Serving mix: independent periodic vortex instances
 # ---------------------------------------------------------------------------
