@@ -48,7 +48,16 @@ class Params(C.Structure):
 
 
 class Bc(C.Structure):
-    _fields_ = [("awx", C.c_double), ("awy", C.c_double)]
+    _fields_ = [("awx", C.c_double), ("awy", C.c_double), ("io_mode", C.c_int32),
+                ("ur", C.c_double), ("vr", C.c_double), ("pr", C.c_double)]
+
+
+def _bc(aw, io):
+    """Wall acceleration and the inlet/outlet rule: io = None (zero-gradient)
+    or (u_r, v_r, p_r), the reference state of the characteristic rule."""
+    if io is None:
+        return Bc(float(aw[0]), float(aw[1]), 0, 0.0, 0.0, 0.0)
+    return Bc(float(aw[0]), float(aw[1]), 1, float(io[0]), float(io[1]), float(io[2]))
 
 
 class Io(C.Structure):
@@ -282,7 +291,7 @@ def pass_b(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col, ug=None, vg=
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 
 
-def boundary(dom: Dom, prm: Prm, x, y, h, rho, kind, u, v, p, rp, col, aw=(0.0, 0.0)):
+def boundary(dom: Dom, prm: Prm, x, y, h, rho, kind, u, v, p, rp, col, aw=(0.0, 0.0), io=None):
     """Boundary pass of section 2.2 on copies of u, v, p.
     Returns (u, v, p, ug, vg)."""
     x, y, h, rho = map(_f64, (x, y, h, rho))
@@ -290,13 +299,13 @@ def boundary(dom: Dom, prm: Prm, x, y, h, rho, kind, u, v, p, rp, col, aw=(0.0, 
     kind, rp, col = _i32(kind), _i64(rp), _i32(col)
     n = x.size
     ug, vg = np.zeros(n), np.zeros(n)
-    bc = Bc(float(aw[0]), float(aw[1]))
+    bc = _bc(aw, io)
     lib().or_boundary(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n, _p(x), _p(y), _p(h),
                       _p(rho), _p(kind), _p(rp), _p(col), _p(u), _p(v), _p(p), _p(ug), _p(vg))
     return u, v, p, ug, vg
 
 
-def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0)):
+def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0), io=None):
     """One evaluation with boundary particles (state needs 'kind' and 'rho',
     the stored density).  Returns the fields plus the state's u, v, p after
     the boundary pass."""
@@ -304,7 +313,7 @@ def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0)):
     kind = _i32(state["kind"])
     n = st["x"].size
     out = {k: np.zeros(n) for k in ("rho", "beta", "nnb", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")}
-    bc = Bc(float(aw[0]), float(aw[1]))
+    bc = _bc(aw, io)
     rc = lib().or_rates_k(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
                           *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
                           _p(st["rho"]), float(dt),
@@ -316,7 +325,7 @@ def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0)):
     return out
 
 
-def body_force(dom: Dom, prm: Prm, state: dict, aw=(0.0, 0.0)):
+def body_force(dom: Dom, prm: Prm, state: dict, aw=(0.0, 0.0), io=None):
     """Force on the solid particles, eq. (force-sph) of section 2.3, from one
     evaluation's state (boundary pass and pass A on copies).  Returns
     {"fp": (x, y), "fvisc": (x, y), "abs_p": (x, y), "abs_visc": (x, y)}: the
@@ -325,7 +334,7 @@ def body_force(dom: Dom, prm: Prm, state: dict, aw=(0.0, 0.0)):
     kind = _i32(state["kind"])
     n = st["x"].size
     out = np.zeros(8)
-    bc = Bc(float(aw[0]), float(aw[1]))
+    bc = _bc(aw, io)
     rc = lib().or_body_force(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
                              *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
                              _p(st["rho"]), _p(out))
@@ -341,13 +350,13 @@ def force_coefficients(f: dict, rho0: float, U: float, L: float):
     return {"cd_p": f["fp"][0] / q, "cd_visc": f["fvisc"][0] / q, "cl": f["fp"][1] / q}
 
 
-def step_k(dom: Dom, prm: Prm, state: dict, dt: float, nsteps: int, aw=(0.0, 0.0)):
+def step_k(dom: Dom, prm: Prm, state: dict, dt: float, nsteps: int, aw=(0.0, 0.0), io=None):
     """PEC steps with boundary particles on copies; state needs 'kind' and
     'rho' (stored density, updated to the latest summation)."""
     s = {k: _f64(state[k]).copy() for k in ("x", "y", "u", "v", "p", "h", "m", "rho")}
     kind = _i32(state["kind"])
     n = s["x"].size
-    bc = Bc(float(aw[0]), float(aw[1]))
+    bc = _bc(aw, io)
     rc = lib().or_step_k(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
                          *[_p(s[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
                          _p(s["rho"]), float(dt), int(nsteps))

@@ -638,11 +638,24 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
 /*           acceleration; ghost velocity 2 u_b - u^_b (eq. bc-wall), used    */
 /*           in the viscous term; u_b (the prescribed wall velocity) stays   */
 /*           and is the one the pressure equation sees (no penetration);     */
-/*   inlet:  u_b prescribed; p_b = Shepard average of the fluid pressure;    */
-/*   outlet: u_b, v_b, p_b = Shepard averages of the fluid values.           */
-/* READING (the paper uses the characteristic variables of Lastiwka et al.   */
-/* at inlet and outlet): a zero-gradient Shepard extrapolation of p (and of  */
-/* u at the outlet) with the inlet velocity held at its prescribed value.    */
+/*   inlet and outlet, io_mode 0: the inlet keeps its prescribed velocity    */
+/*     and takes p_b = Shepard average of the fluid pressure; the outlet     */
+/*     takes u_b, v_b, p_b = Shepard averages of the fluid values (a zero-   */
+/*     gradient extrapolation);                                              */
+/*   inlet and outlet, io_mode 1 (the non-reflecting condition of Lastiwka   */
+/*     et al. that the paper uses): the characteristic variables of the      */
+/*     Euler equations linearised about the reference state (u_r, v_r, p_r,  */
+/*     rho0) along the flow direction +x,                                    */
+/*       J2 = rho0 c (u - u_r) + (p - p_r)   (carried with u + c),           */
+/*       J3 = -rho0 c (u - u_r) + (p - p_r)  (carried with u - c),           */
+/*     are Shepard-averaged from the fluid where they leave the domain and   */
+/*     set to 0 where they enter it: at the (upstream) inlet J2 = 0 and J3   */
+/*     is extrapolated, v = v_r; at the (downstream) outlet J3 = 0 and J2    */
+/*     is extrapolated, v is extrapolated.  Then p = p_r + (J2 + J3)/2 and   */
+/*     u = u_r + (J2 - J3)/(2 rho0 c).  The Shepard average is linear, so    */
+/*     the extrapolated J is that of the averaged u and p.  READING: the     */
+/*     entropy variable J1 = -c^2 (rho - rho0) + (p - p_r) only fixes the    */
+/*     density, which the summation density supplies, so it is not used.    */
 /* READING: rho_f in eq. (bc-pre) is the stored density (the one from the    */
 /* latest summation).  A particle with no fluid neighbour keeps u, v, p and  */
 /* its ghost velocity is u; by the symmetry of N no fluid particle sees it.  */
@@ -651,7 +664,9 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
 enum { OR_FLUID = 0, OR_SOLID = 1, OR_INLET = 2, OR_OUTLET = 3 };
 
 typedef struct {
-    double awx, awy;  /* wall acceleration a_w of eq. (bc-pre) */
+    double awx, awy;   /* wall acceleration a_w of eq. (bc-pre) */
+    int32_t io_mode;   /* inlet/outlet rule: 0 zero-gradient, 1 characteristic */
+    double ur, vr, pr; /* reference (prescribed inlet) state of io_mode 1 */
 } or_bc;
 
 void or_boundary(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
@@ -686,6 +701,23 @@ void or_boundary(const or_domain* d, const or_params* P, const or_bc* B, int64_t
             p[b] = (sp + ((P->fx - B->awx) * srx + (P->fy - B->awy) * sry)) / S;
             ug[b] = 2.0 * u[b] - su / S;
             vg[b] = 2.0 * v[b] - sv / S;
+        } else if (B->io_mode == 1) {
+            double zc = P->rho0 * P->cs;
+            double du = su / S - B->ur;
+            double dp = sp / S - B->pr;
+            if (kind[b] == OR_INLET) {
+                double j3 = dp - zc * du;
+                u[b] = B->ur - j3 / (2.0 * zc);
+                v[b] = B->vr;
+                p[b] = B->pr + 0.5 * j3;
+            } else {
+                double j2 = dp + zc * du;
+                u[b] = B->ur + j2 / (2.0 * zc);
+                v[b] = sv / S;
+                p[b] = B->pr + 0.5 * j2;
+            }
+            ug[b] = u[b];
+            vg[b] = v[b];
         } else if (kind[b] == OR_INLET) {
             p[b] = sp / S;
         } else {
