@@ -88,6 +88,22 @@ typedef struct sph_config {
                                1.5 skin h_i (results are unchanged: the exact
                                predicate is re-applied); 0 rebuilds it at
                                every evaluation without a host round trip */
+    int32_t io_mode;        /* inlet/outlet rule of the boundary pass
+                               (section 2.2): 0 = the inlet keeps its
+                               velocity and takes the Shepard average of the
+                               fluid pressure, the outlet takes the Shepard
+                               averages of u, v, p (zero gradient);
+                               1 = the non-reflecting characteristic rule of
+                               Lastiwka et al.: about the reference state
+                               io_ref = (u_r, v_r, p_r) and rho0 c_s, with
+                               J2 = rho0 c (u - u_r) + (p - p_r) and
+                               J3 = -rho0 c (u - u_r) + (p - p_r), the inlet
+                               (upstream, flow along +x) takes J2 = 0, J3 and
+                               v = v_r; the outlet takes J3 = 0, J2 and v
+                               from the Shepard averages of the fluid; then
+                               p = p_r + (J2 + J3)/2 and
+                               u = u_r + (J2 - J3)/(2 rho0 c) */
+    double io_ref[3];       /* (u_r, v_r, p_r) of io_mode 1 */
 } sph_config;
 
 /* Caller-owned particle set (device pointers, see conventions). kind may be

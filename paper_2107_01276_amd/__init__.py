@@ -48,7 +48,7 @@ class sph_config(C.Structure):
                 ("cr", C.c_double), ("ds_min", C.c_double), ("ds_max", C.c_double),
                 ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double),
                 ("wall_accel", C.c_double * 2), ("list_k", C.c_int32), ("lean", C.c_int32),
-                ("list_skin", C.c_double)]
+                ("list_skin", C.c_double), ("io_mode", C.c_int32), ("io_ref", C.c_double * 3)]
 
 
 class sph_particles(C.Structure):
@@ -198,6 +198,8 @@ class Config:
     list_k: int = 0
     lean: int = 0
     list_skin: float = 0.1
+    io_mode: int = 0
+    io_ref: tuple = (0.0, 0.0, 0.0)
 
     def c(self) -> sph_config:
         s = sph_config()
@@ -207,9 +209,11 @@ class Config:
         s.hi[0], s.hi[1] = self.hi
         s.body_force[0], s.body_force[1] = self.body_force
         s.wall_accel[0], s.wall_accel[1] = self.wall_accel
+        s.io_ref[0], s.io_ref[1], s.io_ref[2] = self.io_ref
         for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
                   "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
-                  "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q", "list_k", "lean", "list_skin"):
+                  "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q", "list_k", "lean", "list_skin",
+                  "io_mode"):
             setattr(s, k, getattr(self, k))
         return s
 
@@ -564,7 +568,11 @@ class Pool:
 
 def config_for(domain, params: dict, h_lo: float, h_hi: float, precision=SPH_FP64,
                mass_q: float = 2.0 ** -60, **kw) -> Config:
-    """Config from a workload's domain/params (see the workloads module)."""
+    """Config from a workload's domain/params (see the workloads module);
+    params may also name the inlet/outlet rule (io_mode, io_ref)."""
+    for k in ("io_mode", "io_ref"):
+        if k in params and k not in kw:
+            kw[k] = params[k]
     return Config(lo=tuple(domain.lo), hi=tuple(domain.hi), periodic=tuple(domain.periodic),
                   h_lo=h_lo, h_hi=h_hi, precision=precision, rho0=params["rho0"],
                   cs=params["cs"], nu=params["nu"], hdx=params["hdx"], mass_q=mass_q, **kw)

@@ -119,6 +119,10 @@ static int check_cfg(const sph_config* cfg)
     if (!isfinite(cfg->wall_accel[0]) || !isfinite(cfg->wall_accel[1])) return 0;
     if (cfg->list_k < 0 || cfg->list_k > 1024 || (cfg->lean != 0 && cfg->lean != 1)) return 0;
     if (!(cfg->list_skin >= 0.0 && cfg->list_skin <= 1.0)) return 0;
+    if (cfg->io_mode != 0 && cfg->io_mode != 1) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(cfg->io_ref[a])) return 0;
+    if (cfg->io_mode == 1 && !(cfg->cs > 0)) return 0;
     return 1;
 }
 

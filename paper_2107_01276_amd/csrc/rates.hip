@@ -123,6 +123,12 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     }
 }
 
+// Inlet/outlet rule of the boundary pass: mode, reference state, rho0 c.
+struct IoRule {
+    int mode;
+    double ur, vr, pr, z;
+};
+
 struct PassAOut {
     double *rho, *beta, *pavg, *nnb, *dxs, *dys; // slot order, optional
 };
@@ -135,8 +141,15 @@ struct PassAOut {
 // and of rho_f (r_b - r_f), which gives the wall pressure of eq. (bc-pre)
 // (g the body force, a_w the wall acceleration).  Solids keep their own
 // (prescribed) velocity and get the no-slip ghost velocity 2 u_b - u^ of
-// eq. (bc-wall) for the viscous term; inlet particles get p; outlet
-// particles get u, v and p.  Only boundary slots are written and only
+// eq. (bc-wall) for the viscous term.  Inlet and outlet, rule 0: inlet
+// particles get p, outlet particles get u, v and p (zero gradient).  Rule 1,
+// the non-reflecting condition of Lastiwka et al.: the acoustic
+// characteristic variables about the reference state (u_r, v_r, p_r),
+// J2 = z (u - u_r) + (p - p_r) and J3 = -z (u - u_r) + (p - p_r) with
+// z = rho0 c, are taken from the averaged fluid where they leave (J3 at the
+// upstream inlet, J2 at the downstream outlet) and are 0 where they enter;
+// p = p_r + (J2 + J3)/2, u = u_r + (J2 - J3)/(2z), v = v_r at the inlet and
+// the average at the outlet.  Only boundary slots are written and only
 // fluid slots are read, so waves do not race.
 __global__ __launch_bounds__(256) void k_bmark(int n, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ kind, int32_t* list,
@@ -177,7 +190,7 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
                                                   const double* __restrict__ h,
                                                   const double* __restrict__ rho, double* u,
                                                   double* v, double* p, double* ug, double* vg,
-                                                  double gx, double gy, Guard gd)
+                                                  double gx, double gy, IoRule io, Guard gd)
 {
     if (guard_stop(gd)) return;
     const int lane = __lane_id();
@@ -243,7 +256,25 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
                 vg[b] = 2.0 * vb - sv / S;
                 continue;
             }
-            if (kb == SPH_INLET) {
+            if (io.mode == 1) {
+                const double du = su / S - io.ur;
+                const double dp = sp / S - io.pr;
+                double pb;
+                if (kb == SPH_INLET) {
+                    const double j3 = dp - io.z * du;
+                    ub = io.ur - j3 / (2.0 * io.z);
+                    vb = io.vr;
+                    pb = io.pr + 0.5 * j3;
+                } else {
+                    const double j2 = dp + io.z * du;
+                    ub = io.ur + j2 / (2.0 * io.z);
+                    vb = sv / S;
+                    pb = io.pr + 0.5 * j2;
+                }
+                u[b] = ub;
+                v[b] = vb;
+                p[b] = pb;
+            } else if (kb == SPH_INLET) {
                 p[b] = sp / S;
             } else {
                 ub = su / S;
@@ -714,7 +745,10 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
         hipLaunchKernelGGL(k_boundary, dim3(nbw), dim3(256), 0, c->stream, c->grid, nv, nl, n,
                            (const int32_t*)blist, (const int32_t*)bcount, bnext, kind, x, y, h,
                            rho_in, u, v, p, w.ug, w.vg, cf.body_force[0] - cf.wall_accel[0],
-                           cf.body_force[1] - cf.wall_accel[1], gd);
+                           cf.body_force[1] - cf.wall_accel[1],
+                           IoRule{cf.io_mode, cf.io_ref[0], cf.io_ref[1], cf.io_ref[2],
+                                  cf.rho0 * cf.cs},
+                           gd);
         LAUNCHCHK(c, "boundary");
     }
     using T4 = typename Vec4<T>::type;

@@ -50,19 +50,30 @@ def _prm(s, body=(0.0, 0.0)):
                       fx=body[0], fy=body[1])
 
 
-@pytest.mark.parametrize("case", ["wall", "inout"])
+IO_REF = (1.0, 0.0, 0.05)
+
+
+def _io_kw(case):
+    """Library and oracle arguments of the inlet/outlet rule of a case."""
+    if case == "inout_char":
+        return {"io_mode": 1, "io_ref": IO_REF}, IO_REF
+    return {}, None
+
+
+@pytest.mark.parametrize("case", ["wall", "inout", "inout_char"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_boundary_rates_vs_oracle(case, prec):
     P = lib()
     s = _wall_case() if case == "wall" else _io_case()
     body = (0.0, -2.0) if case == "wall" else (0.0, 0.0)
+    kw, io = _io_kw(case)
     dt = 1e-4
     precision = P.SPH_FP64 if prec == "fp64" else P.SPH_FP32
     print(f"[boundary] case={case} prec={prec} n={s['x'].size}", flush=True)
-    ctx = ctx_for(P, s, precision, body_force=body)
+    ctx = ctx_for(P, s, precision, body_force=body, **kw)
     ps = particles(P, s)
     r = ctx.rates(ps, dt)
-    o = oracle.rates_k(odom(s["domain"]), _prm(s, body), s, dt)
+    o = oracle.rates_k(odom(s["domain"]), _prm(s, body), s, dt, io=io)
     tol = 1e-12 if prec == "fp64" else 1e-5
     errs = {k: rel_norm(r[k].cpu().numpy(), o[k]) for k in FIELDS}
     print(f"[boundary] errors={errs}", flush=True)
@@ -74,18 +85,19 @@ def test_boundary_rates_vs_oracle(case, prec):
         assert rel_norm(st[k], o[ok]) < 1e-13, k
 
 
-@pytest.mark.parametrize("case", ["wall", "inout"])
+@pytest.mark.parametrize("case", ["wall", "inout", "inout_char"])
 def test_boundary_steps_vs_oracle(case):
     P = lib()
     s = _wall_case() if case == "wall" else _io_case()
     body = (0.0, -2.0) if case == "wall" else (0.0, 0.0)
+    kw, io = _io_kw(case)
     dt = 2e-4
     print(f"[boundary-steps] case={case} n={s['x'].size}", flush=True)
-    ctx = ctx_for(P, s, P.SPH_FP64, body_force=body)
+    ctx = ctx_for(P, s, P.SPH_FP64, body_force=body, **kw)
     ps = particles(P, s)
     ctx.step(ps, dt, 10)
     g = ps.numpy()
-    o = oracle.step_k(odom(s["domain"]), _prm(s, body), s, dt, 10)
+    o = oracle.step_k(odom(s["domain"]), _prm(s, body), s, dt, 10, io=io)
     for k in ("x", "y", "u", "v", "p", "rho"):
         e = rel_norm(g[k], o[k])
         print(f"[boundary-steps] {k} {e:.2e}", flush=True)
@@ -185,3 +197,35 @@ def test_step_inout_equals_separate_calls(skin):
     ga, gb = A.numpy(), B.numpy()
     for k in ("x", "y", "u", "v", "p", "rho", "h", "mq", "kind"):
         assert np.array_equal(ga[k], gb[k]), k
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_pulse_reflection_fp32(rule):
+    """An acoustic pulse (p' = -rho0 c u', running upstream) in a flowing
+    strip, U = 1, c = 10, on the FP32 path: with the characteristic
+    inlet/outlet it leaves the channel (under 3% of its energy stays);
+    with the inlet velocity held (rule 0) more than a third reflects."""
+    P = lib()
+    nx, ny = 80, 16
+    s = W.inout_strip(nx=nx, ny=ny, n_in=6, n_out=6, U=1.0)
+    L = nx * s["dx"]
+    fl = s["kind"] == W.FLUID
+    pp = 0.5 * np.exp(-((s["x"] - 0.5 * L) / (0.08 * L)) ** 2) * fl
+    s["p"] = pp.copy()
+    s["u"] = 1.0 - pp / 10.0
+    s["params"] = {"rho0": 1.0, "cs": 10.0, "nu": 0.002, "hdx": 1.2}
+    kw = {"io_mode": 1, "io_ref": (1.0, 0.0, 0.0)} if rule == 1 else {}
+    ctx = ctx_for(P, s, P.SPH_FP32, **kw)
+    ps = particles(P, s)
+    dt = 0.25 * s["h"][0] / 11.0
+    nsteps = int(0.35 / dt)
+    print(f"[pulse] rule={rule} n={s['x'].size} steps={nsteps}", flush=True)
+    ctx.step(ps, dt, nsteps)
+    g = ps.numpy()
+    mid = (g["kind"] == W.FLUID) & (g["x"] > 0.1 * L) & (g["x"] < 0.9 * L)
+    ratio = float(np.sum(g["p"][mid] ** 2)) / float(np.sum(pp ** 2))
+    print(f"[pulse] rule={rule} energy left {ratio:.4f}", flush=True)
+    if rule == 1:
+        assert ratio < 0.03
+    else:
+        assert ratio > 0.3

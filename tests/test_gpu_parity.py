@@ -186,7 +186,8 @@ def test_channel_full_size_sampled():
     # the cylinder's solid particles take the wall boundary pass of section 2.2
     prm = oracle.Prm(rho0=1.0, cs=s["params"]["cs"], nu=s["params"]["nu"],
                      hdx=s["params"]["hdx"], mass_q=s["mass_q"])
-    o = oracle.rates_k(odom(s["domain"]), prm, s, dt)
+    # and its inlet/outlet particles the characteristic rule
+    o = oracle.rates_k(odom(s["domain"]), prm, s, dt, io=s["params"]["io_ref"])
     for prec, tol in ((P.SPH_FP64, 1e-12), (P.SPH_FP32, 1e-5)):
         c2 = ctx_for(P, s, prec)
         r = c2.rates(particles(P, s), dt)

@@ -358,7 +358,7 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
                          (hi[0] + len_out + 2 * s.ds_min * s.ratio, hi[1]), (False, True)),
         "io": {"x_in": lo[0], "len_in": len_in, "x_out": hi[0], "len_out": len_out},
         "params": {"rho0": s.rho0, "cs": s.cs, "nu": nu, "hdx": s.hdx, "re": s.re,
-                   "u_inf": s.u_inf},
+                   "u_inf": s.u_inf, "io_mode": 1, "io_ref": (s.u_inf, 0.0, 0.0)},
         "dt": dt, "spec": s,
     }
 
