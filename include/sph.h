@@ -369,6 +369,18 @@ int sph_step_inout(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps,
  * bits on every call with the same input).  Synchronises. */
 int sph_body_force(sph_ctx *ctx, sph_particles *ps, double *force);
 
+/* Prescribed rigid motion of a body between steps (moving bodies, section
+ * 3.3; the wall acceleration a_w of eq. bc-pre): every solid particle
+ * (kind 1) is translated by disp (wrapped on periodic axes) and takes the
+ * velocity vel, and the boundary passes of later evaluations use acc as the
+ * wall acceleration a_w (it replaces the config's wall_accel for this
+ * context).  disp, vel, acc: host arrays of two doubles.  Needs kind;
+ * SPH_E_INVAL without it or with non-finite values.  Does not synchronise.
+ * A neighbour list held across calls is re-checked at the next evaluation,
+ * so moved solids are seen. */
+int sph_move_solids(sph_ctx *ctx, sph_particles *ps, const double disp[2], const double vel[2],
+                    const double acc[2]);
+
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 

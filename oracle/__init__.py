@@ -94,6 +94,7 @@ def lib():
             "or_boundary": (None, [P, P, P, I64] + [P] * 12),
             "or_rates_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 9),
             "or_body_force": (C.c_int, [P, P, P, I64] + [P] * 10),
+            "or_move_solids": (None, [P, I64, P, D, D, D, D, P, P, P, P]),
             "or_step_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D, I64]),
             "or_inout": (I64, [P, I64, I64] + [P] * 12),
             "or_rates": (C.c_int, [P, P, I64] + [P] * 7 + [D] + [P] * 9),
@@ -363,6 +364,19 @@ def step_k(dom: Dom, prm: Prm, state: dict, dt: float, nsteps: int, aw=(0.0, 0.0
     if rc != 0:
         raise RuntimeError(f"oracle step failed: {rc}")
     s["kind"] = kind
+    return s
+
+
+def move_solids(dom: Dom, state: dict, disp, vel):
+    """Rigid motion of the solid particles (kind 1) on a copy of the state:
+    translated by disp (wrapped on periodic axes), velocity set to vel."""
+    s = dict(state)
+    for k in ("x", "y", "u", "v"):
+        s[k] = _f64(state[k]).copy()
+    kind = _i32(state["kind"])
+    lib().or_move_solids(C.byref(dom.c()), kind.size, _p(kind), float(disp[0]), float(disp[1]),
+                         float(vel[0]), float(vel[1]), _p(s["x"]), _p(s["y"]), _p(s["u"]),
+                         _p(s["v"]))
     return s
 
 

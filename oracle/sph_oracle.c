@@ -957,6 +957,25 @@ int or_step(const or_domain* d, const or_params* P, int64_t n, double* x, double
 }
 
 /* ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------ */
+/* A body with prescribed rigid motion (the moving bodies of section 3.3):   */
+/* every solid particle (kind 1) is translated by (dx, dy), wrapped on       */
+/* periodic axes, and takes the body's velocity (vx, vy).  The wall          */
+/* acceleration a_w of eq. (bc-pre) is the caller's (or_bc).                 */
+/* ------------------------------------------------------------------------ */
+
+void or_move_solids(const or_domain* d, int64_t n, const int32_t* kind, double dx, double dy,
+                    double vx, double vy, double* x, double* y, double* u, double* v)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (kind[i] != OR_SOLID) continue;
+        x[i] = wrap_axis(d, 0, x[i] + dx);
+        y[i] = wrap_axis(d, 1, y[i] + dy);
+        u[i] = vx;
+        v[i] = vy;
+    }
+}
+
 /* Inlet and outlet (section 2.2): after a step, on the pre-update kinds,    */
 /*   an inlet particle at x >= x_in becomes fluid and a copy of it (same y,  */
 /*   h, mass, m_ref, u, v, p, rho) re-enters the inlet at x - len_in;        */

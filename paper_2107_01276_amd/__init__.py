@@ -102,7 +102,7 @@ class sph_diag(C.Structure):
 
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
-           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force",
+           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force", "sph_move_solids",
            "sph_profile_enable",
            "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
            "sph_pool_footprint", "sph_pool_create",
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH):
         "sph_bg_update_solution": (C.c_int, [P, P, P, P, D, I32, P, P]),
         "sph_diagnostics": (C.c_int, [P, P, P]),
         "sph_body_force": (C.c_int, [P, P, P]),
+        "sph_move_solids": (C.c_int, [P, P, P, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
         "sph_profile_reset": (C.c_int, [P]),
@@ -466,6 +467,13 @@ class Context:
         self._check(self.lib.sph_body_force(self._h, C.byref(ps), f))
         return {"fp": (f[0], f[1]), "fvisc": (f[2], f[3]), "abs_p": (f[4], f[5]),
                 "abs_visc": (f[6], f[7])}
+
+    def move_solids(self, P: Particles, disp, vel, acc=(0.0, 0.0)):
+        """Prescribed rigid motion of the solids (sph_move_solids): translate
+        by disp, set their velocity to vel and the wall acceleration to acc."""
+        D2 = C.c_double * 2
+        ps = P.c()
+        self._check(self.lib.sph_move_solids(self._h, C.byref(ps), D2(*disp), D2(*vel), D2(*acc)))
 
     def diagnostics(self, P: Particles) -> dict:
         d = sph_diag()

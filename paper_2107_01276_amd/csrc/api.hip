@@ -345,6 +345,25 @@ extern "C" int sph_body_force(sph_ctx* c, sph_particles* ps, double* force)
     return body_force_run(c, ps, force);
 }
 
+extern "C" int sph_move_solids(sph_ctx* c, sph_particles* ps, const double disp[2],
+                               const double vel[2], const double acc[2])
+{
+    if (!c || !disp || !vel || !acc) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->kind) {
+        set_err(c, "moving the solids needs kind");
+        return SPH_E_INVAL;
+    }
+    for (int a = 0; a < 2; ++a)
+        if (!isfinite(disp[a]) || !isfinite(vel[a]) || !isfinite(acc[a])) {
+            set_err(c, "non-finite body motion");
+            return SPH_E_INVAL;
+        }
+    c->cfg.wall_accel[0] = acc[0];
+    c->cfg.wall_accel[1] = acc[1];
+    c->fused_x = nullptr;
+    return move_solids_run(c, ps, disp, vel);
+}
+
 extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* out)
 {
     if (!c || !out) return SPH_E_INVAL;

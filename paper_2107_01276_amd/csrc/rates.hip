@@ -1133,6 +1133,32 @@ __global__ __launch_bounds__(256) void k_force_total(const double* __restrict__ 
     }
 }
 
+// Rigid motion of the solid particles between steps: translation (wrapped
+// on periodic axes) and the body's velocity.
+__global__ __launch_bounds__(256) void k_move_solids(Grid g, int n,
+                                                     const int32_t* __restrict__ kind, double dx,
+                                                     double dy, double vx, double vy, double* x,
+                                                     double* y, double* u, double* v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || kind[i] != SPH_SOLID) return;
+    x[i] = wrap_axis(g, 0, x[i] + dx);
+    y[i] = wrap_axis(g, 1, y[i] + dy);
+    u[i] = vx;
+    v[i] = vy;
+}
+
+int move_solids_run(sph_ctx* c, sph_particles* ps, const double* disp, const double* vel)
+{
+    const int n = (int)ps->n;
+    if (n == 0) return SPH_OK;
+    hipLaunchKernelGGL(k_move_solids, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, c->grid,
+                       n, (const int32_t*)ps->kind, disp[0], disp[1], vel[0], vel[1], ps->x, ps->y,
+                       ps->u, ps->v);
+    LAUNCHCHK(c, "move_solids");
+    return SPH_OK;
+}
+
 int body_force_run(sph_ctx* c, sph_particles* ps, double* force)
 {
     Work& w = c->w;

@@ -197,6 +197,7 @@ int step_half2(sph_ctx* c, sph_particles* ps, double dt, Guard gd3, Guard gd4);
 void reset_bcounters(sph_ctx* c);
 int list_ready(sph_ctx* c, const sph_particles* ps);
 // force on the solid particles (8 doubles to the host, see sph_body_force)
+int move_solids_run(sph_ctx* c, sph_particles* ps, const double* disp, const double* vel);
 int body_force_run(sph_ctx* c, sph_particles* ps, double* force);
 bool launch_list_check(sph_ctx* c, int n, const double* x, const double* y, const double* h);
 int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out);

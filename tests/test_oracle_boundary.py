@@ -352,3 +352,23 @@ def test_characteristic_io_pulse_reflection(orc):
     held = _pulse(orc, None, -1)
     assert back_in < 0.03 and back_out < 0.03, (back_in, back_out)
     assert held > 0.3, held
+
+
+def test_move_solids(orc):
+    """Prescribed rigid motion: solids translate by exactly the displacement
+    (wrapped on the periodic axis), take the body velocity, and nothing else
+    changes."""
+    s = W.wall_box(nx=10, ny=10, layers=2, jitter=0.1)
+    dom = _dom(orc, s["domain"])
+    st = dict(s, u=np.full(s["x"].size, 0.3), v=np.zeros(s["x"].size))
+    out = orc.move_solids(dom, st, (0.25, 0.125), (0.7, -0.2))
+    sol = s["kind"] == W.SOLID
+    assert sol.sum() > 0
+    L = dom.hi[0] - dom.lo[0]
+    ex = s["x"][sol] + 0.25
+    ex = np.where(ex >= dom.hi[0], ex - L, ex)
+    assert np.array_equal(out["x"][sol], ex)
+    assert np.array_equal(out["y"][sol], s["y"][sol] + 0.125)
+    assert np.all(out["u"][sol] == 0.7) and np.all(out["v"][sol] == -0.2)
+    for k in ("x", "y", "u", "v"):
+        assert np.array_equal(out[k][~sol], st[k][~sol]), k

@@ -31,3 +31,40 @@ def test_channel_background_seeded():
     a = W.channel_background(seed=3)
     b = W.channel_background(seed=3)
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["y"], b["y"])
+
+
+def test_channel_wake_levels_and_band():
+    """The wake-refined channel (small spec): spacings on the sqrt(2)
+    levels, the finest level fills the wake band, sizes grow away from it,
+    no fluid inside the cylinder, and a ratio that is not a power of two
+    is generated (its ring grading stops at the cap)."""
+    import math
+    spec = W.ChannelSpec(length=6.0, height=4.0, cyl_x=2.0, ds_min=0.02, ratio=25, re=1000.0,
+                         io_layers=2)
+    s = W.channel_wake(spec, wake=(2.5, 4.5, 0.4), vortices=3)
+    fl = s["kind"] == W.FLUID
+    ds = s["h"][fl] / spec.hdx
+    lev = np.log(ds / spec.ds_min) / math.log(math.sqrt(2.0))
+    assert np.allclose(lev, np.round(lev), atol=1e-9) and lev.max() <= 2 * math.log2(25)
+    x, y = s["x"][fl], s["y"][fl]
+    band = (x > 2.6) & (x < 4.4) & (np.abs(y) < 0.3)
+    assert band.sum() > 0 and np.all(ds[band] == spec.ds_min)
+    assert np.corrcoef(np.abs(y[x > 5.0]), ds[x > 5.0])[0, 1] > 0.5
+    assert np.all(np.hypot(x - spec.cyl_x, y - spec.cyl_y) > 0.5)
+    assert s["n_solid"] > 0 and (s["kind"] == W.INLET).sum() > 0
+    c = W.channel_cylinder(W.ChannelSpec(length=6.0, height=4.0, cyl_x=2.0, ds_min=0.02,
+                                         ratio=25), seed=2)
+    assert c["x"].size > 0
+
+
+def test_body_motion():
+    """y = A sin(wt): velocity and acceleration are its derivatives."""
+    import math
+    A, T = 0.5, 5.0
+    for t in (0.0, 0.7, 1.25, 3.1):
+        y, v, a = W.body_motion(t, A, T)
+        e = 1e-6
+        yp, vp, _ = W.body_motion(t + e, A, T)
+        ym, vm, _ = W.body_motion(t - e, A, T)
+        assert abs((yp - ym) / (2 * e) - v) < 1e-8 and abs((vp - vm) / (2 * e) - a) < 1e-7
+        assert abs(y - A * math.sin(2 * math.pi * t / T)) < 1e-15

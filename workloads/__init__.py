@@ -257,7 +257,7 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
         k = int(np.searchsorted(lev_ds, target * (1 + 1e-12), side="right") - 1)
         k = max(0, min(k, nlev))
         ds = lev_ds[k]
-        if k == nlev:
+        if k == nlev or target >= ds_max:
             break
         px, py = _ring_points(rng, r, ds, s.cyl_x, s.cyl_y)
         xs.append(px); ys.append(py); dss.append(np.full(px.size, ds))
@@ -279,13 +279,27 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
     inside = (x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1])
     x, y, ds = x[inside], y[inside], ds[inside]
 
-    # potential flow past the cylinder
+    u, v, p = _potential_flow(s, x, y)
+    return _assemble_channel(s, rng, x, y, ds, u, v, p, lev_ds, nlev, slope, lo, hi)
+
+
+def _potential_flow(s, x, y):
+    """Potential flow past the cylinder, pressure from Bernoulli."""
     X, Y = x - s.cyl_x, y - s.cyl_y
     r2 = X * X + Y * Y
-    R2 = R * R
+    R2 = (0.5 * s.diameter) ** 2
     u = s.u_inf * (1.0 - R2 * (X * X - Y * Y) / (r2 * r2))
     v = -s.u_inf * 2.0 * R2 * X * Y / (r2 * r2)
     p = 0.5 * s.rho0 * (s.u_inf ** 2 - (u * u + v * v))
+    return u, v, p
+
+
+def _assemble_channel(s, rng, x, y, ds, u, v, p, lev_ds, nlev, slope, lo, hi):
+    """Adds the inlet and outlet columns and the solid layers of the
+    cylinder to graded fluid particles (x, y, spacing ds, fields u, v, p)
+    and returns the state dict of a channel workload."""
+    R = 0.5 * s.diameter
+    ds_max = s.ds_min * s.ratio
 
     # inlet buffer columns left of x = 0 (prescribed u_inf) and outlet
     # columns right of x = length, each a lattice at the graded spacing the
@@ -361,6 +375,99 @@ def channel_cylinder(spec: ChannelSpec | None = None, seed: int = 2):
                    "u_inf": s.u_inf, "io_mode": 1, "io_ref": (s.u_inf, 0.0, 0.0)},
         "dt": dt, "spec": s,
     }
+
+
+def channel_wake(spec: ChannelSpec | None = None, seed: int = 2, wake=(10.5, 18.5, 0.6),
+                 vortices: int = 8, gamma: float = 2.0, core: float = 0.2):
+    """The channel after its wake has been refined by the vorticity criterion
+    (the 1:250, Re = 1000 channel): the target size is graded by the
+    distance d to the nearer of the cylinder and the wake band
+    [x0, x1] x [-w, w], s(d) = ds_min + d ln(C_r)/rows_per_layer (capped at
+    ds_max), snapped to the levels ds_min 2^(k/2).  Each level fills the
+    points where it is the snapped size with a lattice of its spacing
+    (jittered by U(-jitter, jitter) of it), which leaves seams of at most one
+    spacing between levels.  The velocity is the potential flow plus a
+    street of `vortices` Lamb-Oseen vortices of alternating sign along the
+    band (circulation gamma, core radius `core`, at y = +-0.3, one D apart),
+    so that |vorticity| peaks in the wake.  Inlet, outlet and solids as in
+    `channel_cylinder`."""
+    s = spec or ChannelSpec(ds_min=1.0 / 250.0, ratio=250, re=1000.0)
+    rng = np.random.default_rng(seed)
+    R = 0.5 * s.diameter
+    ds_max = s.ds_min * s.ratio
+    nlev = int(math.floor(2 * math.log2(s.ratio) + 1e-9))
+    lev_ds = s.ds_min * np.sqrt(2.0) ** np.arange(nlev + 1)
+    lo = (0.0, s.cyl_y - 0.5 * s.height)
+    hi = (s.length, s.cyl_y + 0.5 * s.height)
+    slope = math.log(s.cr) / s.rows_per_layer
+    x0, x1, w = wake
+
+    def dist(px, py):
+        dc = np.maximum(np.hypot(px - s.cyl_x, py - s.cyl_y) - R, 0.0)
+        dwx = np.maximum(np.maximum(x0 - px, px - x1), 0.0)
+        dwy = np.maximum(np.abs(py - s.cyl_y) - w, 0.0)
+        return np.minimum(dc, np.hypot(dwx, dwy))
+
+    def level(px, py):
+        target = np.minimum(s.ds_min + dist(px, py) * slope, ds_max)
+        k = np.floor(np.log(target * (1 + 1e-12) / s.ds_min) / math.log(math.sqrt(2.0)))
+        return np.clip(k, 0, nlev).astype(np.int64)
+
+    xs, ys, dss = [], [], []
+    for k in range(nlev + 1):
+        a = float(lev_ds[k])
+        reach = (float(lev_ds[k + 1]) - s.ds_min) / slope if k < nlev else math.inf
+        bx0 = max(lo[0], min(s.cyl_x - R, x0) - reach)
+        bx1 = min(hi[0], max(s.cyl_x + R, x1) + reach)
+        by0 = max(lo[1], s.cyl_y - max(R, w) - reach)
+        by1 = min(hi[1], s.cyl_y + max(R, w) + reach)
+        i0, i1 = int(math.floor((bx0 - lo[0]) / a)), int(math.ceil((bx1 - lo[0]) / a))
+        j0, j1 = int(math.floor((by0 - lo[1]) / a)), int(math.ceil((by1 - lo[1]) / a))
+        gi, gj = np.meshgrid(np.arange(i0, i1), np.arange(j0, j1), indexing="ij")
+        px = lo[0] + (gi.ravel() + 0.5) * a
+        py = lo[1] + (gj.ravel() + 0.5) * a
+        keep = (level(px, py) == k) & (np.hypot(px - s.cyl_x, py - s.cyl_y) >= R + 0.5 * s.ds_min)
+        keep &= (px >= lo[0]) & (px < hi[0]) & (py >= lo[1]) & (py < hi[1])
+        xs.append(px[keep]); ys.append(py[keep]); dss.append(np.full(int(keep.sum()), a))
+    x = np.concatenate(xs); y = np.concatenate(ys); ds = np.concatenate(dss)
+    x = x + rng.uniform(-s.jitter, s.jitter, x.size) * ds
+    y = y + rng.uniform(-s.jitter, s.jitter, y.size) * ds
+    inside = (x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1])
+    x, y, ds = x[inside], y[inside], ds[inside]
+    u, v, p = _potential_flow(s, x, y)
+    for n in range(vortices):
+        vx = x0 + 0.5 + n * 1.0
+        vy = s.cyl_y + (0.3 if n % 2 == 0 else -0.3)
+        g = gamma if n % 2 == 0 else -gamma
+        X, Y = x - vx, y - vy
+        r2 = np.maximum(X * X + Y * Y, 1e-300)
+        ut = g / (2 * math.pi * r2) * (1.0 - np.exp(-r2 / (core * core)))
+        u += -ut * Y
+        v += ut * X
+    return _assemble_channel(s, rng, x, y, ds, u, v, p, lev_ds, nlev, slope, lo, hi)
+
+
+def oscillating_cylinder(spec: ChannelSpec | None = None, seed: int = 2, amp: float = 0.5,
+                         period: float = 5.0):
+    """The channel with a cylinder oscillating across the stream,
+    y_c(t) = amp D sin(2 pi t / period), at t = 0: 1:100, Re = 200, D/400,
+    refined to ds_min over the band the body sweeps
+    ([x_c - 0.6 D, x_c + 0.6 D] x [-(amp + 0.6) D, (amp + 0.6) D]) and graded
+    around it as `channel_wake` grades (no vortex street).  `motion` holds
+    the amplitude and period for `body_motion`."""
+    s = spec or ChannelSpec(ds_min=1.0 / 400.0, ratio=100, re=200.0)
+    D = s.diameter
+    st = channel_wake(s, seed, wake=(s.cyl_x - 0.6 * D, s.cyl_x + 0.6 * D, (amp + 0.6) * D),
+                      vortices=0)
+    st["motion"] = {"amp": amp * D, "period": period}
+    return st
+
+
+def body_motion(t: float, amp: float, period: float):
+    """Transverse position, velocity and acceleration of the oscillating
+    body at time t."""
+    w = 2.0 * math.pi / period
+    return amp * math.sin(w * t), amp * w * math.cos(w * t), -amp * w * w * math.sin(w * t)
 
 
 def channel_background(spec: ChannelSpec | None = None, seed: int = 3, sparsity: float = 2.0):
