@@ -310,9 +310,9 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     const T sig = T(SPH_SIGMA2) * ih * ih;
     const T irho0 = T(1.0 / rho0);
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
-    // rho and beta add terms of one sign each: plain sums suffice; p_avg
-    // and the shift add terms of both signs: compensated
-    PSum<T> sr, sb;
+    // compensated sums: Kahan for rho and beta (terms of one sign each),
+    // Neumaier for p_avg and the shift (terms of both signs)
+    KSum<T> sr, sb;
     CSum<T> sp, sx, sy;
     int nn = 0;  // |N(i)|
     // one pair's terms; r = 0 (the self pair, or coincident particles)

@@ -77,13 +77,35 @@ struct CSum {
         c += co;
     }
 };
-// Plain running sum, for sums whose terms share one sign (no cancellation).
+// Kahan-compensated sum (FP32 path), for the density sums, whose terms
+// share one sign: the running correction c (the low-order part lost so far,
+// negated) is fed back into the next term; plain sum in double.
 template <typename T>
-struct PSum {
-    T s;
-    __device__ __forceinline__ PSum() : s(T(0)) {}
-    __device__ __forceinline__ void add(T x) { s += x; }
-    __device__ __forceinline__ T get() const { return s; }
+struct KSum {
+    T s, c;
+    __device__ __forceinline__ KSum() : s(T(0)), c(T(0)) {}
+    __device__ __forceinline__ void add(T x)
+    {
+        const T y = x - c;
+        const T t = s + y;
+        c = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ T get() const { return s - c; }
+    // adds the sum held by lane (this lane ^ o) of the wave
+    __device__ __forceinline__ void merge_xor(int o)
+    {
+        const T so = __shfl_xor(s, o, 64), co = __shfl_xor(c, o, 64);
+        add(so);
+        c += co;
+    }
+};
+template <>
+struct KSum<double> {
+    double s;
+    __device__ __forceinline__ KSum() : s(0.0) {}
+    __device__ __forceinline__ void add(double x) { s += x; }
+    __device__ __forceinline__ double get() const { return s; }
     __device__ __forceinline__ void merge_xor(int o) { s += __shfl_xor(s, o, 64); }
 };
 
