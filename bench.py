@@ -106,18 +106,19 @@ def serving_bench(SPH, W, args):
 
 
 def pass_b_source_hash():
-    """sha256 of the source pass B is compiled from: the kernel function, the
-    pair-arithmetic helpers and lane-group size above it in rates.hip, and
-    the device header."""
+    """sha256 of the source pass B is compiled from: its body and kernels,
+    the pair-arithmetic helpers, lane-group size and pass-B tuning macros
+    above them in rates.hip, and the device header."""
     import hashlib
     rates = open(os.path.join(ROOT, KERNEL_SOURCES[0])).read()
-    k0 = rates.index("template <typename T, bool GH>\n__global__ __launch_bounds__(256) void k_pass_b(")
-    k1 = rates.index("\n}\n", k0)
+    k0 = rates.index("#define PASS_B_PARAMS(T)")
+    k1 = rates.index("\n}\n", rates.index("void k_pass_b<float, false>", k0))
     h0 = rates.index("#define RATES_FP_CONTRACT")
     h1 = rates.index("template <typename T>\nstruct RatesBufs", h0)
     g0 = rates.index("#define RGB ")
+    g1 = rates.index("#define RATES_FP_CONTRACT")
     h = hashlib.sha256()
-    h.update(rates[g0:rates.index("\n", g0)].encode())
+    h.update(rates[g0:g1].encode())
     h.update(rates[h0:h1].encode())
     h.update(rates[k0:k1].encode())
     with open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb") as fh:

@@ -26,6 +26,29 @@
 // lanes per particle in pass A and in pass B
 #define RGA 4
 #define RGB 2
+// pass B, FP32 kernels: exact-row entries loaded ahead per lane, and the
+// minimum number of waves per SIMD their register allocation must allow
+// (0: the compiler's choice)
+#ifndef PB_UNROLL
+#define PB_UNROLL 2
+#endif
+#ifndef PB_WAVES
+#define PB_WAVES 4
+#endif
+#if PB_WAVES > 0
+#define PB_ATTR __attribute__((amdgpu_waves_per_eu(PB_WAVES)))
+#else
+#define PB_ATTR
+#endif
+// pass A, FP32 kernel: the same register budget knob
+#ifndef PA_WAVES
+#define PA_WAVES 5
+#endif
+#if PA_WAVES > 0
+#define PA_ATTR __attribute__((amdgpu_waves_per_eu(PA_WAVES)))
+#else
+#define PA_ATTR
+#endif
 // Pair arithmetic of the rate passes: FMA contraction is allowed inside it
 // (the neighbour predicate, outside it, stays uncontracted).
 #define RATES_FP_CONTRACT _Pragma("clang fp contract(fast)")
@@ -292,12 +315,14 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
 // When ex.idx is set, pass A also writes the exact neighbours of each row
 // (self excluded), column-major with K columns, for pass B; a row with more
 // gets count K + 1 and pass B uses the skin list for it.
+#define PASS_A_PARAMS(T)                                                                     \
+    Grid g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,   \
+        typename Vec4<T>::type *pf, double rho0, PassAOut out, double *r_dxs, double *r_dys,  \
+        const int32_t *__restrict__ kind, NbrList ex, Guard gd
+#define PASS_A_ARGS g, nv, n, b, nl, pa, pf, rho0, out, r_dxs, r_dys, kind, ex, gd
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                NbrList nl, const double4* __restrict__ pa,
-                                                typename Vec4<T>::type* pf, double rho0,
-                                                PassAOut out, double* r_dxs, double* r_dys,
-                                                const int32_t* __restrict__ kind, NbrList ex, Guard gd)
+__device__ __forceinline__ void pass_a_body(PASS_A_PARAMS(T))
 {
     if (guard_stop(gd)) return;
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -441,6 +466,18 @@ __global__ __launch_bounds__(256) void k_pass_a(Grid g, NbrView nv, int n, Rates
     if (out.dys) out.dys[slot] = (double)ddy;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass_a(PASS_A_PARAMS(T))
+{
+    pass_a_body<T>(PASS_A_ARGS);
+}
+// FP32: more waves per SIMD than the compiler picks (latency-bound gathers)
+template <>
+__global__ __launch_bounds__(256) PA_ATTR void k_pass_a<float>(PASS_A_PARAMS(float))
+{
+    pass_a_body<float>(PASS_A_ARGS);
+}
+
 struct PassBParams {
     double rho0, cs, nu, alpha_e, fx, fy, dt;
 };
@@ -448,14 +485,16 @@ struct PassBParams {
 // GH: boundary particles present; the viscous term then takes the velocity
 // difference of (ugs, vgs), which holds the ghost velocity of solids and u
 // of everything else.
+#define PASS_B_PARAMS(T)                                                                     \
+    Grid g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, NbrList ex,                        \
+        const double4 *__restrict__ pa, const double2 *__restrict__ puv,                      \
+        const typename Vec4<T>::type *__restrict__ pf, const double *__restrict__ ugs,        \
+        const double *__restrict__ vgs, PassBParams P, double *dpdt, double *dudt,            \
+        double *dvdt, Guard gd
+#define PASS_B_ARGS g, nv, n, b, nl, ex, pa, puv, pf, ugs, vgs, P, dpdt, dudt, dvdt, gd
+
 template <typename T, bool GH>
-__global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, RatesBufs<T> b,
-                                                NbrList nl, NbrList ex, const double4* __restrict__ pa,
-                                                const double2* __restrict__ puv,
-                                                const typename Vec4<T>::type* __restrict__ pf,
-                                                const double* __restrict__ ugs,
-                                                const double* __restrict__ vgs, PassBParams P,
-                                                double* dpdt, double* dudt, double* dvdt, Guard gd)
+__device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
 {
     if (guard_stop(gd)) return;
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -536,18 +575,19 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
     const int cnt = nl.cnt[s];
     // the lanes of the group take every RGB-th entry of the row
     if (ecnt <= ex.K) {
-        // the exact neighbours pass A found (self excluded), four per lane
-        // loaded at a time
+        // the exact neighbours pass A found (self excluded), UN per lane
+        // loaded at a time (PB_UNROLL in float, four in double)
+        constexpr int UN = sizeof(T) == 4 ? PB_UNROLL : 4;
         int k = gl;
-        for (; k + 3 * RGB < ecnt; k += 4 * RGB) {
-            int j[4];
-            double4 a[4];
+        for (; k + (UN - 1) * RGB < ecnt; k += UN * RGB) {
+            int j[UN];
+            double4 a[UN];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) j[u] = ex.idx[(int64_t)(k + RGB * u) * ex.stride + s];
+            for (int u = 0; u < UN; ++u) j[u] = ex.idx[(int64_t)(k + RGB * u) * ex.stride + s];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+            for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UN; ++u) {
                 const double dx = mi_axis(g, 0, xi - a[u].x);
                 const double dy = mi_axis(g, 1, yi - a[u].y);
                 body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w);
@@ -596,6 +636,24 @@ __global__ __launch_bounds__(256) void k_pass_b(Grid g, NbrView nv, int n, Rates
                  (dxs / P.dt) * (double)gx + (dys / P.dt) * (double)gy;
     dudt[slot] = (double)(-gx + vx * ib) + P.fx;
     dvdt[slot] = (double)(-gy + vy * ib) + P.fy;
+}
+
+template <typename T, bool GH>
+__global__ __launch_bounds__(256) void k_pass_b(PASS_B_PARAMS(T))
+{
+    pass_b_body<T, GH>(PASS_B_ARGS);
+}
+// The FP32 kernels are latency-bound on their gathers: they ask for more
+// waves per SIMD (the register budget that allows) than the compiler picks.
+template <>
+__global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, true>(PASS_B_PARAMS(float))
+{
+    pass_b_body<float, true>(PASS_B_ARGS);
+}
+template <>
+__global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, false>(PASS_B_PARAMS(float))
+{
+    pass_b_body<float, false>(PASS_B_ARGS);
 }
 
 // Adds the evaluation's interacting ordered pairs, sum over i of
