@@ -530,12 +530,20 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
         RATES_FP_CONTRACT
-        const T r = fsqrt<T>((T)r2);
+        // r and 1/r; r = 0 (the self pair, or coincident particles): every
+        // term below carries a factor 1/r * r-free gradient or r itself, and
+        // is zero.  In float both come from one reciprocal square root.
+        T r, ir;
+        if constexpr (sizeof(T) == 4) {
+            const T r2f = (T)r2;
+            ir = r2f > T(0) ? __builtin_amdgcn_rsqf(r2f) : T(0);
+            r = r2f * ir;
+        } else {
+            r = fsqrt<T>((T)r2);
+            ir = r > T(0) ? rcp<T>(r) : T(0);
+        }
         const double2 uvj = puv[js];
         const typename Vec4<T>::type fj4 = pf[js];
-        // r = 0 (the self pair, or coincident particles): every term below
-        // carries a factor 1/r * r-free gradient or r itself, and is zero
-        const T ir = r > T(0) ? rcp<T>(r) : T(0);
         const T ihj = rcp<T>((T)hj);
         const T dwi = sigi * rate_kern_fp<T>(r * ih);
         const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * rate_kern_fp<T>(r * ihj);
@@ -547,15 +555,26 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
         const T Vj = GH ? fabs(Vraw) : Vraw;
         const T Pj = (-dpij - dpav) * fj4.y;
         const T nuj = aecs8 * (T)hj;
-        const T nuij = T(4) * nui * nuj * rcp<T>(nui + nuj);
         const T rdotg = T(0.5) * (dwi + dwj) * r;
-        const T iden = rcp<T>((T)r2 + eta);
+        // the denominators nu_i + nu_j (harmonic EDAC viscosity), r^2 + eta
+        // and rho_i + rho_j; in float from one reciprocal of their product
+        T nuij_iden, cv_den;  // nu_ij / (r^2 + eta), 1 / ((rho_i + rho_j)(r^2 + eta))
+        if constexpr (sizeof(T) == 4) {
+            const T da = nui + nuj, db = (T)r2 + eta, dc = rhoi + fj4.z;
+            const T inv = rcp<T>(da * db * dc);
+            nuij_iden = T(4) * nui * nuj * (inv * dc);
+            cv_den = inv * da;
+        } else {
+            const T iden = rcp<T>((T)r2 + eta);
+            nuij_iden = T(4) * nui * nuj * rcp<T>(nui + nuj) * iden;
+            cv_den = rcp<T>(rhoi + fj4.z) * iden;
+        }
         sdiv.add(Vj * (fi * (uij * dxT + vij * dyT)));
-        sdif.add(Vj * nuij * dpij * rdotg * iden);
+        sdif.add(Vj * nuij_iden * dpij * rdotg);
         const T gf = mj * (Pi * fi + Pj * fj);
         gx += gf * dxT;
         gy += gf * dyT;
-        const T cv = mj * nu4 * rcp<T>(rhoi + fj4.z) * rdotg * iden;
+        const T cv = mj * nu4 * cv_den * rdotg;
         if constexpr (GH) {
             if (solid_i || Vraw < T(0)) {
                 const double ugj = Vraw < T(0) ? ugs[js] : uvj.x;
