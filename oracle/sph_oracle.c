@@ -1563,7 +1563,8 @@ int64_t or_bg_update(const or_domain* d, const or_bgparams* B, int64_t nb, int64
 
 /* Vorticity magnitude used by solution adaptivity (section 3.3):
  * omega_i = sum_j (m_j/rho_j) [(v_j - v_i) dW/dx - (u_j - u_i) dW/dy] at h_i.
- * Parity unpinned beyond the solid-body-rotation closed form in the tests. */
+ * Pinned by closed forms: 2 Omega for a rigid rotation, the Taylor-Green
+ * vorticity 4 pi cos(2 pi x) cos(2 pi y), and 0 for a uniform translation. */
 void or_vorticity(const or_domain* d, int64_t n, const double* x, const double* y,
                   const double* u, const double* v, const double* h, const double* m,
                   const double* rho, const int64_t* rp, const int32_t* col, double* omega)
