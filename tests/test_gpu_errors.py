@@ -1,0 +1,66 @@
+"""Argument checks of the C ABI: invalid configurations are refused at
+creation, and calls with missing arrays, non-finite values or sizes beyond
+the capacity return SPH_E_INVAL (or SPH_E_CAPACITY) without touching the
+state.  Every case here is refused on the host before any kernel runs."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import ctx_for, lib, particles
+
+pytestmark = pytest.mark.gpu
+
+
+def test_config_rejections():
+    P = lib()
+    base = dict(lo=(0.0, 0.0), hi=(1.0, 1.0), periodic=(1, 1), h_lo=0.01, h_hi=0.02)
+    bad = ({"io_mode": 2}, {"io_ref": (math.nan, 0.0, 0.0)}, {"io_mode": 1, "cs": 0.0},
+           {"hi": (0.0, 1.0)}, {"h_lo": 0.0}, {"list_skin": 1.5}, {"precision": 7},
+           {"wall_accel": (math.inf, 0.0)}, {"merge_iters": 9}, {"lean": 2})
+    for b in bad:
+        with pytest.raises(P.SphError) as e:
+            P.Context(P.Config(**{**base, **b}), 16)
+        assert e.value.code == P.SPH_E_INVAL, b
+    P.Context(P.Config(**base, io_mode=1, io_ref=(1.0, 0.0, 0.0)), 16)  # a valid one
+
+
+def test_call_rejections_leave_state():
+    P = lib()
+    s = W.wall_box(nx=8, ny=8, layers=2, jitter=0.1)
+    s["u"] = np.zeros(s["x"].size)
+    s["v"] = np.zeros(s["x"].size)
+    s["p"] = np.zeros(s["x"].size)
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    ps = particles(P, s)
+    before = ps.numpy()
+    D2 = C.c_double * 2
+    # non-finite body motion
+    with pytest.raises(P.SphError) as e:
+        ctx.move_solids(ps, (math.nan, 0.0), (0.0, 0.0))
+    assert e.value.code == P.SPH_E_INVAL
+    # no kind array: moving the solids and the body force need it
+    c = ps.c()
+    c.kind = None
+    assert ctx.lib.sph_move_solids(ctx._h, C.byref(c), D2(0.1, 0.0), D2(0.0, 0.0),
+                                   D2(0.0, 0.0)) == P.SPH_E_INVAL
+    f = (C.c_double * 8)()
+    assert ctx.lib.sph_body_force(ctx._h, C.byref(c), f) == P.SPH_E_INVAL
+    # n beyond the capacity, and a step with dt <= 0
+    c = ps.c()
+    c.n = c.capacity + 1
+    assert ctx.lib.sph_step(ctx._h, C.byref(c), 1e-4, 1) == P.SPH_E_INVAL
+    with pytest.raises(P.SphError) as e:
+        ctx.step(ps, 0.0, 1)
+    assert e.value.code == P.SPH_E_INVAL
+    after = ps.numpy()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+    # a valid call still works and moves the solids only
+    ctx.move_solids(ps, (0.125, 0.0), (0.5, 0.0))
+    g = ps.numpy()
+    sol = g["kind"] == W.SOLID
+    assert np.all(g["u"][sol] == 0.5) and np.array_equal(g["y"], before["y"])
+    assert np.array_equal(g["x"][~sol], before["x"][~sol])
