@@ -228,16 +228,17 @@ __global__ void k_zero_i32(int32_t* p, int64_t n)
     if (i < n) p[i] = 0;
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int64_t n)
+// Clears what a build accumulates into: the cell-run table and the
+// per-level h maxima and counts (one launch).
+__global__ void k_zero_build(int2* tab, int64_t ntab, unsigned long long* hmax, int32_t* lcount,
+                             int nl)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
-
-__global__ void k_zero_int2(int2* p, int64_t n)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = make_int2(0, 0);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ntab) tab[i] = make_int2(0, 0);
+    if (i < nl) {
+        hmax[i] = 0ull;
+        lcount[i] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -364,13 +365,23 @@ static int radix_sort(sph_ctx* c, int n, int keybits)
 
 // Run boundaries per (level, resolution Q): consecutive sorted particles of
 // one level share a Q-cell iff their curve indices agree above bit 2Q.  The
-// cell's coordinates come from the particle's position.
+// cell's coordinates come from the particle's position, which is copied to
+// the sorted shadows (xs, ys, hs and the packed xyh) on the way.
 __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* __restrict__ keys,
-                                                const double* __restrict__ xs,
-                                                const double* __restrict__ ys, int2* tab)
+                                                const int32_t* __restrict__ perm,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ y,
+                                                const double* __restrict__ h, double* xs,
+                                                double* ys, double* hs, double4* xyh, int2* tab)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= n) return;
+    const int i = perm[s];
+    const double xi = x[i], yi = y[i], hi = h[i];
+    xs[s] = xi;
+    ys[s] = yi;
+    hs[s] = hi;
+    xyh[s] = make_double4(xi, yi, hi, 0.0);
     const int sh = 2 * g.bits;
     const uint64_t mmask = (sh >= 64) ? ~0ull : ((1ull << sh) - 1ull);
     uint64_t key = keys[s];
@@ -380,7 +391,7 @@ __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* _
     uint64_t kn = s < n - 1 ? keys[s + 1] : ~0ull;
     bool lp = s > 0 && (int)(kp >> sh) == l;
     bool ln = s < n - 1 && (int)(kn >> sh) == l;
-    const int kx0 = cell0(g, 0, xs[s]), ky0 = cell0(g, 1, ys[s]);
+    const int kx0 = cell0(g, 0, xi), ky0 = cell0(g, 1, yi);
     for (int Q = l; Q < g.nlev; ++Q) {
         uint64_t cell = m >> (2 * Q);
         bool sp = lp && ((kp & mmask) >> (2 * Q)) == cell;
@@ -393,43 +404,27 @@ __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* _
     }
 }
 
-__global__ __launch_bounds__(256) void k_gather_pos(int n, const int32_t* __restrict__ perm,
-                                                    const double* __restrict__ x,
-                                                    const double* __restrict__ y,
-                                                    const double* __restrict__ h, double* xs,
-                                                    double* ys, double* hs, double4* xyh)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    int i = perm[s];
-    const double xi = x[i], yi = y[i], hi = h[i];
-    xs[s] = xi;
-    ys[s] = yi;
-    hs[s] = hi;
-    xyh[s] = make_double4(xi, yi, hi, 0.0);
-}
-
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h)
 {
     Work& w = c->w;
     const Grid& g = c->grid;
     c->list_valid = 0;  // a new sorted order invalidates any reusable list
     prof_begin(c, SPH_PROF_BUILD);
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, w.hmax_bits, (int64_t)SPH_MAXL);
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, c->stream, w.lcount, (int64_t)SPH_MAXL);
-    hipLaunchKernelGGL(k_zero_int2, dim3((unsigned)cdiv(g.tab_total, 256)), dim3(256), 0, c->stream,
-                       w.tab, g.tab_total);
-    LAUNCHCHK(c, "zero");
+    {
+        const int64_t nz = g.tab_total > SPH_MAXL ? g.tab_total : (int64_t)SPH_MAXL;
+        hipLaunchKernelGGL(k_zero_build, dim3((unsigned)cdiv(nz, 256)), dim3(256), 0, c->stream, w.tab,
+                           g.tab_total, w.hmax_bits, w.lcount, (int)SPH_MAXL);
+        LAUNCHCHK(c, "zero");
+    }
     if (n > 0) {
         hipLaunchKernelGGL(k_keys, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n, x, y,
                            h, w.keys_a, w.vals_a, w.hmax_bits, w.lcount);
         LAUNCHCHK(c, "keys");
         int rc = radix_sort(c, n, key_bits(&g));
         if (rc) return rc;
-        hipLaunchKernelGGL(k_gather_pos, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, n,
-                           w.vals_a, x, y, h, w.xs, w.ys, w.hs, w.xyh);
         hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
-                           w.keys_a, w.xs, w.ys, w.tab);
+                           w.keys_a, (const int32_t*)w.vals_a, x, y, h, w.xs, w.ys, w.hs, w.xyh,
+                           w.tab);
         LAUNCHCHK(c, "tables");
     }
     prof_end(c, SPH_PROF_BUILD);
