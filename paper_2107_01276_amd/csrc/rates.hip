@@ -49,6 +49,23 @@
 #else
 #define PA_ATTR
 #endif
+// the same knobs for the FP64 kernels
+#ifndef PB64_WAVES
+#define PB64_WAVES 0
+#endif
+#if PB64_WAVES > 0
+#define PB64_ATTR __attribute__((amdgpu_waves_per_eu(PB64_WAVES)))
+#else
+#define PB64_ATTR
+#endif
+#ifndef PA64_WAVES
+#define PA64_WAVES 4
+#endif
+#if PA64_WAVES > 0
+#define PA64_ATTR __attribute__((amdgpu_waves_per_eu(PA64_WAVES)))
+#else
+#define PA64_ATTR
+#endif
 // Pair arithmetic of the rate passes: FMA contraction is allowed inside it
 // (the neighbour predicate, outside it, stays uncontracted).
 #define RATES_FP_CONTRACT _Pragma("clang fp contract(fast)")
@@ -477,6 +494,11 @@ __global__ __launch_bounds__(256) PA_ATTR void k_pass_a<float>(PASS_A_PARAMS(flo
 {
     pass_a_body<float>(PASS_A_ARGS);
 }
+template <>
+__global__ __launch_bounds__(256) PA64_ATTR void k_pass_a<double>(PASS_A_PARAMS(double))
+{
+    pass_a_body<double>(PASS_A_ARGS);
+}
 
 struct PassBParams {
     double rho0, cs, nu, alpha_e, fx, fy, dt;
@@ -673,6 +695,16 @@ template <>
 __global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, false>(PASS_B_PARAMS(float))
 {
     pass_b_body<float, false>(PASS_B_ARGS);
+}
+template <>
+__global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, true>(PASS_B_PARAMS(double))
+{
+    pass_b_body<double, true>(PASS_B_ARGS);
+}
+template <>
+__global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, false>(PASS_B_PARAMS(double))
+{
+    pass_b_body<double, false>(PASS_B_ARGS);
 }
 
 // Adds the evaluation's interacting ordered pairs, sum over i of
