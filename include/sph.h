@@ -381,6 +381,30 @@ int sph_body_force(sph_ctx *ctx, sph_particles *ps, double *force);
 int sph_move_solids(sph_ctx *ctx, sph_particles *ps, const double disp[2], const double vel[2],
                     const double acc[2]);
 
+/* Checkpoint and resume.  A checkpoint is a host byte buffer: a 64-byte
+ * header (bytes 0-7 "SPHCKPT1"; int32 version 1 at 8; int32 0 at 12; int64 n
+ * at 16; double mass quantum at 24; int64 step and double time, the
+ * caller's, at 32 and 40; zeros to 64), then over [0, n) the arrays x, y,
+ * u, v, p, rho, h, mref (double), mq (int64) and kind (int32), each
+ * contiguous, in that order (mref and kind are zero when ps has none).
+ * Little-endian, as on the device.  A state resumed from it steps exactly
+ * as the original (with list_skin 0 bit for bit; a reusable list may
+ * otherwise order the pair sums differently). */
+size_t sph_export_bytes(int64_t n);
+/* Writes ps (x, y, u, v, p, rho, h, mq required) with step and time into
+ * host_buf (>= sph_export_bytes(ps->n) bytes).  Synchronises. */
+int sph_export(sph_ctx *ctx, const sph_particles *ps, int64_t step, double time, void *host_buf,
+               size_t bytes);
+/* Reads a checkpoint into ps and sets ps->n; *step and *time (may be NULL)
+ * receive the caller's values.  Everything is checked before anything is
+ * written: SPH_E_INVAL for a bad header, a buffer shorter than its n needs,
+ * a mass quantum other than the context's (the ledger's quanta would mean
+ * other masses) or non-fluid kinds when ps has no kind array;
+ * SPH_E_CAPACITY when n exceeds ps->capacity; SPH_E_NONFINITE when a value
+ * is NaN or infinite.  Synchronises. */
+int sph_import(sph_ctx *ctx, sph_particles *ps, const void *host_buf, size_t bytes,
+               int64_t *step, double *time);
+
 /* Scalar diagnostics over [0, n).  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 

@@ -103,6 +103,7 @@ class sph_diag(C.Structure):
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
            "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force", "sph_move_solids",
+           "sph_export_bytes", "sph_export", "sph_import",
            "sph_profile_enable",
            "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
            "sph_pool_footprint", "sph_pool_create",
@@ -141,6 +142,9 @@ def load_library(path: str = LIB_PATH):
         "sph_diagnostics": (C.c_int, [P, P, P]),
         "sph_body_force": (C.c_int, [P, P, P]),
         "sph_move_solids": (C.c_int, [P, P, P, P, P]),
+        "sph_export_bytes": (C.c_size_t, [I64]),
+        "sph_export": (C.c_int, [P, P, I64, D, P, C.c_size_t]),
+        "sph_import": (C.c_int, [P, P, P, C.c_size_t, P, P]),
         "sph_profile_enable": (C.c_int, [P, I32]),
         "sph_profile_read": (C.c_int, [P, C.c_char_p, P, P]),
         "sph_profile_reset": (C.c_int, [P]),
@@ -474,6 +478,27 @@ class Context:
         D2 = C.c_double * 2
         ps = P.c()
         self._check(self.lib.sph_move_solids(self._h, C.byref(ps), D2(*disp), D2(*vel), D2(*acc)))
+
+    def export(self, P: Particles, step: int = 0, time: float = 0.0):
+        """Checkpoint of P (sph_export) as a numpy uint8 array; write it with
+        `arr.tofile(path)` and read it back with `numpy.fromfile(path, numpy.uint8)`."""
+        import numpy as np
+        buf = np.empty(self.lib.sph_export_bytes(int(P.n)), dtype=np.uint8)
+        ps = P.c()
+        self._check(self.lib.sph_export(self._h, C.byref(ps), int(step), float(time),
+                                        buf.ctypes.data_as(C.c_void_p), buf.size))
+        return buf
+
+    def import_(self, P: Particles, buf):
+        """Restores a checkpoint into P (sph_import); returns (step, time)."""
+        import numpy as np
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        ps = P.c()
+        st, tm = C.c_int64(0), C.c_double(0.0)
+        self._check(self.lib.sph_import(self._h, C.byref(ps), buf.ctypes.data_as(C.c_void_p),
+                                        buf.size, C.byref(st), C.byref(tm)))
+        P.n = int(ps.n)
+        return int(st.value), float(tm.value)
 
     def diagnostics(self, P: Particles) -> dict:
         d = sph_diag()

@@ -364,6 +364,131 @@ extern "C" int sph_move_solids(sph_ctx* c, sph_particles* ps, const double disp[
     return move_solids_run(c, ps, disp, vel);
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint / resume (host buffer; layout in the header)
+// ---------------------------------------------------------------------------
+
+static const char CKPT_MAGIC[8] = {'S', 'P', 'H', 'C', 'K', 'P', 'T', '1'};
+static const size_t CKPT_HEAD = 64;
+static const int CKPT_NF64 = 8;  // x y u v p rho h mref
+
+extern "C" size_t sph_export_bytes(int64_t n)
+{
+    if (n < 0) return 0;
+    return CKPT_HEAD + (size_t)n * (8 * CKPT_NF64 + 8 + 4);
+}
+
+extern "C" int sph_export(sph_ctx* c, const sph_particles* ps, int64_t step, double time,
+                          void* host_buf, size_t bytes)
+{
+    if (!c || !host_buf) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho) {
+        set_err(c, "export needs x, y, u, v, p, rho, h and mq");
+        return SPH_E_INVAL;
+    }
+    const int64_t n = ps->n;
+    if (bytes < sph_export_bytes(n)) {
+        set_err(c, "checkpoint buffer of %zu bytes, %zu needed", bytes, sph_export_bytes(n));
+        return SPH_E_INVAL;
+    }
+    unsigned char* b = (unsigned char*)host_buf;
+    memset(b, 0, CKPT_HEAD);
+    memcpy(b, CKPT_MAGIC, 8);
+    const int32_t ver = 1;
+    memcpy(b + 8, &ver, 4);
+    memcpy(b + 16, &n, 8);
+    memcpy(b + 24, &c->cfg.mass_q, 8);
+    memcpy(b + 32, &step, 8);
+    memcpy(b + 40, &time, 8);
+    const double* f[CKPT_NF64] = {ps->x, ps->y, ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mref};
+    unsigned char* o = b + CKPT_HEAD;
+    const size_t s8 = 8 * (size_t)n, s4 = 4 * (size_t)n;
+    for (int k = 0; k < CKPT_NF64; ++k, o += s8) {
+        if (n == 0) continue;
+        if (f[k]) HIPCHK(c, hipMemcpyAsync(o, f[k], s8, hipMemcpyDeviceToHost, c->stream));
+        else memset(o, 0, s8);
+    }
+    if (n > 0) HIPCHK(c, hipMemcpyAsync(o, ps->mq, s8, hipMemcpyDeviceToHost, c->stream));
+    o += s8;
+    if (n > 0) {
+        if (ps->kind) HIPCHK(c, hipMemcpyAsync(o, ps->kind, s4, hipMemcpyDeviceToHost, c->stream));
+        else memset(o, 0, s4);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SPH_OK;
+}
+
+extern "C" int sph_import(sph_ctx* c, sph_particles* ps, const void* host_buf, size_t bytes,
+                          int64_t* step, double* time)
+{
+    if (!c || !host_buf || !ps) return SPH_E_INVAL;
+    const unsigned char* b = (const unsigned char*)host_buf;
+    int32_t ver = 0;
+    int64_t n = -1;
+    double q = 0.0;
+    if (bytes >= CKPT_HEAD) {
+        memcpy(&ver, b + 8, 4);
+        memcpy(&n, b + 16, 8);
+        memcpy(&q, b + 24, 8);
+    }
+    if (bytes < CKPT_HEAD || memcmp(b, CKPT_MAGIC, 8) != 0 || ver != 1 || n < 0 ||
+        bytes < sph_export_bytes(n)) {
+        set_err(c, "not a checkpoint of this format, or truncated");
+        return SPH_E_INVAL;
+    }
+    if (memcmp(&q, &c->cfg.mass_q, 8) != 0) {
+        set_err(c, "checkpoint mass quantum %.17g differs from the context's %.17g", q,
+                c->cfg.mass_q);
+        return SPH_E_INVAL;
+    }
+    if (!ps->x || !ps->y || !ps->u || !ps->v || !ps->p || !ps->rho || !ps->h || !ps->mq ||
+        ps->capacity > c->capacity || ps->capacity < 0) {
+        set_err(c, "import needs x, y, u, v, p, rho, h and mq within the context capacity");
+        return SPH_E_INVAL;
+    }
+    if (n > ps->capacity) {
+        set_err(c, "checkpoint of %lld particles, capacity %lld", (long long)n,
+                (long long)ps->capacity);
+        return SPH_E_CAPACITY;
+    }
+    const unsigned char* in = b + CKPT_HEAD;
+    const size_t s8 = 8 * (size_t)n, s4 = 4 * (size_t)n;
+    for (int k = 0; k < CKPT_NF64; ++k)
+        for (int64_t i = 0; i < n; ++i) {
+            double v;
+            memcpy(&v, in + k * s8 + 8 * (size_t)i, 8);
+            if (!isfinite(v)) {
+                set_err(c, "checkpoint holds a non-finite value (array %d, particle %lld)", k,
+                        (long long)i);
+                return SPH_E_NONFINITE;
+            }
+        }
+    const unsigned char* kin = in + CKPT_NF64 * s8 + s8;
+    if (!ps->kind)
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t kd;
+            memcpy(&kd, kin + 4 * (size_t)i, 4);
+            if (kd != SPH_FLUID) {
+                set_err(c, "checkpoint has non-fluid kinds and the particles have no kind array");
+                return SPH_E_INVAL;
+            }
+        }
+    double* f[CKPT_NF64] = {ps->x, ps->y, ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mref};
+    if (n > 0) {
+        for (int k = 0; k < CKPT_NF64; ++k)
+            if (f[k]) HIPCHK(c, hipMemcpyAsync(f[k], in + k * s8, s8, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(ps->mq, in + CKPT_NF64 * s8, s8, hipMemcpyHostToDevice, c->stream));
+        if (ps->kind) HIPCHK(c, hipMemcpyAsync(ps->kind, kin, s4, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    ps->n = n;
+    if (step) memcpy(step, b + 32, 8);
+    if (time) memcpy(time, b + 40, 8);
+    c->list_valid = 0;  // a new state: no reusable list
+    c->fused_x = nullptr;
+    return SPH_OK;
+}
+
 extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* out)
 {
     if (!c || !out) return SPH_E_INVAL;

@@ -51,3 +51,17 @@ def test_workspace_bytes_and_invalid_config():
     h = ctypes.c_void_p()
     # a workspace that is too small is rejected before any device work
     assert lib.sph_create(ctypes.byref(c), 1000, None, 0, None, ctypes.byref(h)) == P.SPH_E_NOMEM
+
+
+def test_checkpoint_size():
+    """sph_export_bytes: a 64-byte header, then eight double arrays, the
+    int64 ledger and the int32 kinds per particle; negative n is refused."""
+    lib_path = os.path.join(ROOT, "paper_2107_01276_amd", "libsph.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsph.so not built")
+    lib = ctypes.CDLL(lib_path)
+    lib.sph_export_bytes.restype = ctypes.c_size_t
+    lib.sph_export_bytes.argtypes = [ctypes.c_int64]
+    for n in (0, 1, 1000, 123457):
+        assert lib.sph_export_bytes(n) == 64 + n * (8 * 8 + 8 + 4)
+    assert lib.sph_export_bytes(-1) == 0
