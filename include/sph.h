@@ -405,7 +405,9 @@ int sph_export(sph_ctx *ctx, const sph_particles *ps, int64_t step, double time,
 int sph_import(sph_ctx *ctx, sph_particles *ps, const void *host_buf, size_t bytes,
                int64_t *step, double *time);
 
-/* Scalar diagnostics over [0, n).  Synchronises. */
+/* Scalar diagnostics over [0, n).  Returns SPH_E_NONFINITE (with *out still
+ * written) when a particle holds a NaN or infinite x, y, u, v, p, rho or h:
+ * the check for a state that has blown up.  Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 
 /* Profiling: bits 0-3 of `on` select the kernels to bracket with HIP events

@@ -1303,17 +1303,23 @@ int body_force_run(sph_ctx* c, sph_particles* ps, double* force)
     return readback(c, &rb, 1);
 }
 
-__global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __restrict__ u,
+// Also counts the particles holding a NaN or infinite value in x, y, u, v,
+// p, rho or h (the host reports them as SPH_E_NONFINITE).
+__global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ u,
                                                       const double* __restrict__ v,
+                                                      const double* __restrict__ p,
                                                       const double* __restrict__ rho,
+                                                      const double* __restrict__ h,
                                                       const int64_t* __restrict__ mq,
                                                       double mass_q, double* part,
                                                       int64_t* partq)
 {
     __shared__ double sh[5][256];
-    __shared__ int64_t sq[256];
+    __shared__ int64_t sq[256], snf[256];
     double ke = 0, vol = 0, mx = 0, my = 0, um = 0;
-    int64_t q = 0;
+    int64_t q = 0, nf = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double m = (double)mq[i] * mass_q;
         double s2 = u[i] * u[i] + v[i] * v[i];
@@ -1323,21 +1329,27 @@ __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __res
         my += m * v[i];
         um = fmax(um, sqrt(s2));
         q += mq[i];
+        const bool fin = isfinite(x[i]) && isfinite(y[i]) && isfinite(u[i]) && isfinite(v[i]) &&
+                         isfinite(p[i]) && isfinite(rho[i]) && isfinite(h[i]);
+        nf += fin ? 0 : 1;
     }
     int t = threadIdx.x;
     sh[0][t] = ke; sh[1][t] = vol; sh[2][t] = mx; sh[3][t] = my; sh[4][t] = um; sq[t] = q;
+    snf[t] = nf;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (t < o) {
             for (int k = 0; k < 4; ++k) sh[k][t] += sh[k][t + o];
             sh[4][t] = fmax(sh[4][t], sh[4][t + o]);
             sq[t] += sq[t + o];
+            snf[t] += snf[t + o];
         }
         __syncthreads();
     }
     if (t == 0) {
         for (int k = 0; k < 5; ++k) part[k * DIAG_BLOCKS + blockIdx.x] = sh[k][0];
         partq[blockIdx.x] = sq[0];
+        partq[DIAG_BLOCKS + blockIdx.x] = snf[0];
     }
 }
 
@@ -1347,20 +1359,21 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out)
     const int n = (int)ps->n;
     double* part = w.sc9;  // 5 * DIAG_BLOCKS doubles
     int64_t* partq = w.red;
-    hipLaunchKernelGGL(k_diag_partial, dim3(DIAG_BLOCKS), dim3(256), 0, c->stream, n, ps->u, ps->v,
-                       ps->rho, ps->mq, c->cfg.mass_q, part, partq);
+    hipLaunchKernelGGL(k_diag_partial, dim3(DIAG_BLOCKS), dim3(256), 0, c->stream, n, ps->x, ps->y,
+                       ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mq, c->cfg.mass_q, part, partq);
     LAUNCHCHK(c, "diag");
     double hp[5 * DIAG_BLOCKS];
-    int64_t hq[DIAG_BLOCKS];
+    int64_t hq[2 * DIAG_BLOCKS];
     HIPCHK(c, hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(hq, partq, sizeof(hq), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double r[5] = {0, 0, 0, 0, 0};
-    int64_t q = 0;
+    int64_t q = 0, nf = 0;
     for (int b = 0; b < DIAG_BLOCKS; ++b) {
         for (int k = 0; k < 4; ++k) r[k] += hp[k * DIAG_BLOCKS + b];
         r[4] = r[4] > hp[4 * DIAG_BLOCKS + b] ? r[4] : hp[4 * DIAG_BLOCKS + b];
         q += hq[b];
+        nf += hq[DIAG_BLOCKS + b];
     }
     out->ke = r[0];
     out->vol = r[1];
@@ -1369,5 +1382,9 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out)
     out->umax = r[4];
     out->mq_total = q;
     out->n = n;
+    if (nf > 0) {
+        set_err(c, "%lld particles hold NaN or infinite values", (long long)nf);
+        return SPH_E_NONFINITE;
+    }
     return SPH_OK;
 }

@@ -64,3 +64,24 @@ def test_call_rejections_leave_state():
     sol = g["kind"] == W.SOLID
     assert np.all(g["u"][sol] == 0.5) and np.array_equal(g["y"], before["y"])
     assert np.array_equal(g["x"][~sol], before["x"][~sol])
+
+
+def test_nonfinite_state_reported():
+    """A NaN or infinite value anywhere in the state (set from the host; no
+    step runs on it) makes the diagnostics return SPH_E_NONFINITE, with the
+    sums still written; a finite state passes."""
+    P = lib()
+    s = W.wall_box(nx=8, ny=8, layers=2, jitter=0.1)
+    n = s["x"].size
+    s["u"] = np.zeros(n)
+    s["v"] = np.zeros(n)
+    s["p"] = np.zeros(n)
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    ps = particles(P, s)
+    d = ctx.diagnostics(ps)
+    assert d["n"] == n and math.isfinite(d["ke"])
+    for field, val in (("p", math.nan), ("u", math.inf), ("rho", math.nan), ("h", -math.inf)):
+        q = particles(P, dict(s, **{field: np.where(np.arange(n) == 5, val, s.get(field, np.ones(n)))}))
+        with pytest.raises(P.SphError) as e:
+            ctx.diagnostics(q)
+        assert e.value.code == P.SPH_E_NONFINITE, field
