@@ -22,10 +22,12 @@ import numpy as np
 
 
 def mass_quantum(m_cap: float) -> float:
-    """Power-of-two mass quantum so that every mass up to m_cap is an integer
-    number of quanta below 2**53, hence exactly representable as mq * q."""
+    """Power-of-two mass quantum: every mass up to m_cap is an integer number
+    of quanta below 2**41, so mq * q is exact in double and the int64 ledger
+    total of up to 2**22 particles at the cap cannot overflow; the resolution,
+    2**-40 of the cap, is far below any mass difference the method makes."""
     e = math.floor(math.log2(m_cap))
-    return math.ldexp(1.0, e - 51)
+    return math.ldexp(1.0, e - 40)
 
 
 def quantize_mass(m: np.ndarray, q: float) -> np.ndarray:
