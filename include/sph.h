@@ -70,7 +70,11 @@ typedef struct sph_config {
     double rho0, cs, nu, alpha_e, hdx, u_ref;
     double body_force[2];
     double split_alpha, split_eps, mmax_f, mmin_f;
-    double mass_q;          /* fluid mass quantum */
+    double mass_q;          /* fluid mass quantum: masses are mq * mass_q with
+                               int64 mq; choose it so that every mq stays
+                               below 2^53 (exact in double) and the sum over
+                               all particles below 2^63, e.g. 2^-40 of the
+                               largest mass */
     int32_t merge_iters, shift_iters;
     double cr, ds_min, ds_max, n_r;
     int32_t bg_smooth_iters;
