@@ -289,6 +289,7 @@ def main():
         torch.cuda.empty_cache()
 
     cpu = None
+    rerr = None
     if not args.no_cpu_baseline:
         import oracle
         prm = oracle.Prm(rho0=1.0, cs=s["params"]["cs"], nu=s["params"]["nu"],
@@ -297,7 +298,7 @@ def main():
         t0 = time.perf_counter()
         opairs = 0
         for _ in range(args.cpu_evals):
-            o = oracle.rates_k(dom, prm, s, dt)
+            o = oracle.rates_k(dom, prm, s, dt, io=s["params"]["io_ref"])
             opairs += int(o["nnb"].sum()) - n0
         t = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -306,6 +307,16 @@ def main():
                          f"pass A + pass B, FP64, OpenMP over rows) of the initial "
                          f"{n0}-particle channel state",
                "seconds": t}
+        # the GPU paths' rates on the same state against the oracle's:
+        # normwise relative error per field
+        rerr = {"state": f"initial {n0}-particle channel state, one evaluation"}
+        for name, prec in (("fp32", SPH.SPH_FP32), ("fp64", SPH.SPH_FP64)):
+            cfg = SPH.config_for(s["domain"], s["params"], float(s["h"].min()),
+                                 float(s["h"].max()), precision=prec, mass_q=s["mass_q"])
+            r = SPH.Context(cfg, n0).rates(SPH.Particles.from_arrays(s), dt)
+            rerr[name] = {k: float(torch.linalg.norm(r[k].cpu() - torch.as_tensor(o[k])) /
+                                   max(float(torch.linalg.norm(torch.as_tensor(o[k]))), 1e-300))
+                          for k in ("rho", "beta", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")}
 
     out = {
         "metric": METRIC,
@@ -331,6 +342,7 @@ def main():
         "kernel_launches": {k: v[1] for k, v in r32["prof"].items() if v[1]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "rates_error_vs_oracle": rerr,
         "serving": serve,
         "list_skin_tuning": tuning,
     }
