@@ -142,6 +142,48 @@ def test_edac_diffusion(orc):
     assert np.allclose(r["dpdt"][inner], 2 * nu_e, rtol=2e-2)
 
 
+def test_transport_velocity_term(orc):
+    """The shifting-transport term of eq. (edac:sph), (u~_i - u_i) . G_i with
+    u~ - u = dr_i / dt (eq. shift-tvf) and G_i = sum_j m_j (P_i gradW_i +
+    P_j gradW_j), which approximates grad p / rho.  On a particle set at rest
+    (no divergence, no viscous term) in a linear pressure field p = g . r,
+    slightly off a lattice so that the shifting displacement dr_i is not
+    zero, the pressure rate is dominated by this term for a small dt:
+    dp/dt_i ~ (dr_i / dt) . g / rho0.  The EDAC diffusion of a linear field
+    is only a discretisation residue, and the term alone scales as 1/dt, so
+    the difference of two evaluations at dt and 2 dt isolates it exactly:
+    dp/dt(dt) - dp/dt(2 dt) = (dr_i / (2 dt)) . G_i ~ (dr_i / (2 dt)) . g.
+    A flipped sign gives twice the term as error and a missing 1/dt makes
+    the difference vanish."""
+    x, y, h, m, dx = lattice(48, 1.2, jitter=0.05, seed=11)
+    dom = orc.Dom((0, 0), (1, 1), (False, False))
+    prm = orc.Prm(hdx=1.2, nu=0.0)
+    g = np.array([2.0, -0.5])
+    p = g[0] * x + g[1] * y
+    z = np.zeros_like(x)
+    inner = (x > 0.3) & (x < 0.7) & (y > 0.3) & (y < 0.7)
+    dt = 1e-4
+    r1 = orc.rates(dom, prm, x, y, z, z, p, h, m, dt)
+    r2 = orc.rates(dom, prm, x, y, z, z, p, h, m, 2 * dt)
+    dr = np.stack([r1["dxs"], r1["dys"]])
+    assert np.all(dr == np.stack([r2["dxs"], r2["dys"]]))
+    drn = np.hypot(*dr)[inner]
+    # the displacement is not zero anywhere inside (else the pin is void)
+    assert drn.min() > 1e-3 * h[0]
+    tvf = (g @ dr)[inner] / dt            # (dr/dt) . grad p / rho0, rho0 = 1
+    scale = drn / dt * np.hypot(*g)       # |dr/dt| |grad p|
+    err = r1["dpdt"][inner] - tvf
+    # G_i approximates grad p within a few per cent on this jitter
+    assert np.abs(err / scale).max() < 0.1
+    assert np.linalg.norm(err) / np.linalg.norm(tvf) < 0.04
+    d = (r1["dpdt"] - r2["dpdt"])[inner]
+    err2 = d - 0.5 * tvf
+    assert np.abs(err2 / (0.5 * scale)).max() < 0.06
+    assert np.linalg.norm(err2) / np.linalg.norm(0.5 * tvf) < 0.03
+    # the momentum rate sees the same G: du/dt = -G ~ -grad p
+    assert np.abs(r1["dudt"][inner] + g[0]).max() < 0.1 * np.hypot(*g)
+
+
 def test_rest_state_exact(orc):
     s = W.tgv(20, seed=9)
     dom = orc.Dom()
