@@ -93,6 +93,8 @@ def lib():
             "or_pass_b": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 7),
             "or_boundary": (None, [P, P, P, I64] + [P] * 12),
             "or_rates_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 9),
+            "or_rates_k_scaled": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 10),
+            "or_rate_scales": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 5),
             "or_body_force": (C.c_int, [P, P, P, I64] + [P] * 10),
             "or_move_solids": (None, [P, I64, P, D, D, D, D, P, P, P, P]),
             "or_step_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D, I64]),
@@ -289,6 +291,40 @@ def pass_b(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col, ug=None, vg=
     return out
 
 
+RATE_FIELDS = ("rho", "beta", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")
+
+
+def rate_scales(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col, ug=None, vg=None):
+    """Per-particle scales of the rates (or_rate_scales): for every field the
+    sum of the magnitudes of its pair terms.  a: pass A outputs.  Returns
+    {field: array}."""
+    x, y, u, v, p, h, m = map(_f64, (x, y, u, v, p, h, m))
+    ug = None if ug is None else _f64(ug)
+    vg = None if vg is None else _f64(vg)
+    rp, col = _i64(rp), _i32(col)
+    n = x.size
+    sc = np.zeros(8 * max(n, 1))
+    lib().or_rate_scales(C.byref(dom.c()), C.byref(prm.c()), n, _p(x), _p(y), _p(u), _p(v),
+                         _p(p), _p(h), _p(m), _p(_f64(a["rho"])), _p(_f64(a["beta"])),
+                         _p(_f64(a["pavg"])), _p(_f64(a["dxs"])), _p(_f64(a["dys"])), float(dt),
+                         _p(rp), _p(col), _p(ug), _p(vg), _p(sc))
+    return {k: sc[f * n:(f + 1) * n].copy() for f, k in enumerate(RATE_FIELDS)}
+
+
+def cond_error(a, b, scale):
+    """max_i |a_i - b_i| / scale_i (0 where a_i == b_i): the error of a
+    against the oracle's b relative to the size of the terms b_i sums."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    d = np.abs(a - b)
+    if d.size == 0:
+        return 0.0
+    sc = np.asarray(scale, np.float64)
+    r = np.where(d == 0, 0.0, d / np.where(sc > 0, sc, np.inf))
+    r = np.where((d > 0) & ~(sc > 0), np.inf, r)
+    return float(r.max())
+
+
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
 
 
@@ -314,15 +350,17 @@ def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0), io=None):
     kind = _i32(state["kind"])
     n = st["x"].size
     out = {k: np.zeros(n) for k in ("rho", "beta", "nnb", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")}
+    sc = np.zeros(8 * max(n, 1))
     bc = _bc(aw, io)
-    rc = lib().or_rates_k(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
-                          *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")], _p(kind),
-                          _p(st["rho"]), float(dt),
-                          *[_p(out[k]) for k in ("rho", "beta", "nnb", "pavg", "dxs", "dys",
-                                                 "dpdt", "dudt", "dvdt")])
+    rc = lib().or_rates_k_scaled(C.byref(dom.c()), C.byref(prm.c()), C.byref(bc), n,
+                                 *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")],
+                                 _p(kind), _p(st["rho"]), float(dt),
+                                 *[_p(out[k]) for k in ("rho", "beta", "nnb", "pavg", "dxs",
+                                                        "dys", "dpdt", "dudt", "dvdt")], _p(sc))
     if rc != 0:
         raise RuntimeError(f"oracle rates failed: {rc}")
     out["u_bc"], out["v_bc"], out["p_bc"] = st["u"], st["v"], st["p"]
+    out["scale"] = {k: sc[f * n:(f + 1) * n].copy() for f, k in enumerate(RATE_FIELDS)}
     return out
 
 
@@ -412,6 +450,7 @@ def rates(dom: Dom, prm: Prm, x, y, u, v, p, h, m, dt, method: str = "cells"):
     rp, col = neighbors(dom, x, y, h, method)
     a = pass_a(dom, prm, x, y, h, m, p, rp, col)
     b = pass_b(dom, prm, x, y, u, v, p, h, m, a, dt, rp, col)
+    a["scale"] = rate_scales(dom, prm, x, y, u, v, p, h, m, a, dt, rp, col)
     a.update(b)
     a["row_ptr"], a["col"] = rp, col
     return a

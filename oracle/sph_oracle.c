@@ -629,6 +629,108 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
     }
 }
 
+/* Per-particle scales of the rates for condition-aware comparisons: for
+ * every field, the sum over j of the magnitudes of its pair terms, as
+ * pass A and pass B above form them (the size of the quantity a rounding
+ * error in those terms is relative to).  Fields, n entries each, in this
+ * order: rho, beta, pavg, dxs, dys, dpdt, dudt, dvdt.
+ *   rho:  sum |m_j W(r_ij, h_i)|;
+ *   beta: sum |m_j r_ij dW/dr(r_ij, h_i)| / (2 rho_i);
+ *   pavg: sum |p_j| / N_i;
+ *   dxs, dys: theta (h_i^2 / 2) sum |t_j| (|dx_j| + |dy_j|), t_j the scalar
+ *         factor of the shifting sum of eq. (shift-deltar) and theta the
+ *         limiter of eq. (shift-limit) (both components, because the limiter
+ *         couples them);
+ *   dpdt: (rho0 c^2 / |beta_i|) sum V_j (|u_ij gradW_i,x| + |v_ij gradW_i,y|)
+ *         + sum V_j |nu_ij (p_i - p_j) r_ij . gradW_ij| / ((r_ij^2 + eta_i) |beta_i|)
+ *         + (|dxs_i| S_x + |dys_i| S_y) / dt + (s_dxs |G_x| + s_dys |G_y|) / dt,
+ *         S_x = sum m_j (|P_i gradW_i,x| + |P_j gradW_j,x|), G the signed
+ *         pressure-gradient sum and s_dxs, s_dys the shift scales (the error
+ *         of the shift enters through the transport-velocity term);
+ *   dudt: S_x + sum |c_ij (ug_i - ug_j)| / |beta_i| + |f_x|, c_ij the
+ *         viscous factor of eq. (mom-sph); dvdt likewise.
+ * Sums scaled by 1/beta_i are dropped where beta_i <= 0, as in pass B. */
+void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const double* x,
+                    const double* y, const double* u, const double* v, const double* p,
+                    const double* h, const double* m, const double* rho,
+                    const double* beta, const double* pavg, const double* dxs,
+                    const double* dys, double dt, const int64_t* rp, const int32_t* col,
+                    const double* ug, const double* vg, double* sc)
+{
+    const double rho0 = P->rho0, cs = P->cs, nu = P->nu, ae = P->alpha_e;
+    if (!ug) ug = u;
+    if (!vg) vg = v;
+    const double fxi = or_kf(OR_XI);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        double s_rho = 0.0, s_beta = 0.0, s_p = 0.0, s_sh = 0.0, sx = 0.0, sy = 0.0;
+        double s_div = 0.0, s_dif = 0.0, Sx = 0.0, Sy = 0.0, Gx = 0.0, Gy = 0.0;
+        double s_vx = 0.0, s_vy = 0.0;
+        double Pi = beta[i] > 0.0 ? (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]) : 0.0;
+        double nui = ae * cs * h[i] / 8.0;
+        double eta = 0.001 * h[i] * h[i];
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            int64_t j = col[k];
+            double dx = mi_axis(d, 0, x[i] - x[j]);
+            double dy = mi_axis(d, 1, y[i] - y[j]);
+            double r2 = dx * dx + dy * dy;
+            double r = sqrt(r2);
+            s_rho += fabs(m[j] * or_w(r, h[i]));
+            s_beta += fabs(m[j] * r * or_dwdr(r, h[i]));
+            s_p += fabs(p[j]);
+            double gix = 0.0, giy = 0.0, gjx = 0.0, gjy = 0.0;
+            if (r > 0.0) {
+                double hij = 0.5 * (h[i] + h[j]);
+                double wr = or_kf(r / hij) / fxi;
+                double t = (m[j] / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr))) *
+                           (or_dwdr(r, hij) / r);
+                sx += t * dx;
+                sy += t * dy;
+                s_sh += fabs(t) * (fabs(dx) + fabs(dy));
+                double fi = or_dwdr(r, h[i]) / r;
+                double fj = or_dwdr(r, h[j]) / r;
+                gix = fi * dx; giy = fi * dy;
+                gjx = fj * dx; gjy = fj * dy;
+            }
+            double gbx = 0.5 * (gix + gjx), gby = 0.5 * (giy + gjy);
+            double Vj = m[j] / rho[j];
+            double Pj = beta[j] <= 0.0 ? 0.0
+                      : P->pref_mode ? (p[j] - pavg[i]) / (rho[j] * rho[j] * beta[j])
+                                     : (p[j] - pavg[j]) / (rho[j] * rho[j] * beta[j]);
+            double nuj = ae * cs * h[j] / 8.0;
+            double nuij = 4.0 * nui * nuj / (nui + nuj);
+            double rdotg = dx * gbx + dy * gby;
+            s_div += Vj * (fabs((u[i] - u[j]) * gix) + fabs((v[i] - v[j]) * giy));
+            s_dif += Vj * fabs(nuij * (p[i] - p[j]) * rdotg) / (r2 + eta);
+            Sx += m[j] * (fabs(Pi * gix) + fabs(Pj * gjx));
+            Sy += m[j] * (fabs(Pi * giy) + fabs(Pj * gjy));
+            Gx += m[j] * (Pi * gix + Pj * gjx);
+            Gy += m[j] * (Pi * giy + Pj * gjy);
+            double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
+            s_vx += fabs(cvis * (ug[i] - ug[j]));
+            s_vy += fabs(cvis * (vg[i] - vg[j]));
+        }
+        double N = (double)(rp[i + 1] - rp[i]);
+        double pref = 0.5 * (h[i] * h[i]);
+        double mag = pref * sqrt(sx * sx + sy * sy);
+        double lim = 0.25 * h[i];
+        double th = mag > lim ? lim / mag : 1.0;
+        double s_shift = th * pref * s_sh;
+        double b = beta[i];
+        double ib = b > 0.0 ? 1.0 / b : 0.0;
+        sc[0 * n + i] = s_rho;
+        sc[1 * n + i] = s_beta / (2.0 * fabs(rho[i]));
+        sc[2 * n + i] = N > 0 ? s_p / N : 0.0;
+        sc[3 * n + i] = s_shift;
+        sc[4 * n + i] = s_shift;
+        sc[5 * n + i] = rho0 * cs * cs * ib * s_div + s_dif * ib +
+                        (fabs(dxs[i]) * Sx + fabs(dys[i]) * Sy) / dt +
+                        s_shift * (fabs(Gx) + fabs(Gy)) / dt;
+        sc[6 * n + i] = Sx + s_vx * ib + fabs(P->fx);
+        sc[7 * n + i] = Sy + s_vy * ib + fabs(P->fy);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Boundary particles, section 2.2.  Kinds: 0 fluid, 1 solid (dummy wall     */
 /* particles of Adami et al.), 2 inlet, 3 outlet.  For every non-fluid       */
@@ -733,11 +835,14 @@ void or_boundary(const or_domain* d, const or_params* P, const or_bc* B, int64_t
 /* One full rate evaluation: neighbours (cell list), the boundary pass when
  * kind is given (it overwrites p, and u, v of outlet particles, in place;
  * rho_in is the stored density it uses), pass A, pass B. */
-int or_rates_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
-               const double* x, const double* y, double* u, double* v, double* p,
-               const double* h, const double* m, const int32_t* kind, const double* rho_in,
-               double dt, double* rho, double* beta, double* nnb, double* pavg, double* dxs,
-               double* dys, double* dpdt, double* dudt, double* dvdt)
+/* The same, also writing the per-particle scales of or_rate_scales (8 n
+ * doubles) when sc is not NULL. */
+int or_rates_k_scaled(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+                      const double* x, const double* y, double* u, double* v, double* p,
+                      const double* h, const double* m, const int32_t* kind,
+                      const double* rho_in, double dt, double* rho, double* beta, double* nnb,
+                      double* pavg, double* dxs, double* dys, double* dpdt, double* dudt,
+                      double* dvdt, double* sc)
 {
     int64_t* rp = NULL;
     int32_t* col = NULL;
@@ -757,11 +862,24 @@ int or_rates_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n
     or_pass_a(d, P, n, x, y, h, m, p, rp, col, rho, beta, nnb, pavg, dxs, dys);
     or_pass_b(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug, vg,
               dpdt, dudt, dvdt);
+    if (sc)
+        or_rate_scales(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug,
+                       vg, sc);
     free(ug);
     free(vg);
     free(rp);
     free(col);
     return OR_OK;
+}
+
+int or_rates_k(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+               const double* x, const double* y, double* u, double* v, double* p,
+               const double* h, const double* m, const int32_t* kind, const double* rho_in,
+               double dt, double* rho, double* beta, double* nnb, double* pavg, double* dxs,
+               double* dys, double* dpdt, double* dudt, double* dvdt)
+{
+    return or_rates_k_scaled(d, P, B, n, x, y, u, v, p, h, m, kind, rho_in, dt, rho, beta, nnb,
+                             pavg, dxs, dys, dpdt, dudt, dvdt, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

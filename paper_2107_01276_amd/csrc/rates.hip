@@ -13,10 +13,12 @@
 // (the remark after eq. mom-corr); both P_i and P_j subtract p_avg,i.
 //
 // Pair arithmetic is templated on T (float or double).  Position, velocity
-// and pressure differences are always formed in double and then converted,
-// and the density, pressure, beta, shifting and divergence sums use
-// Neumaier compensation in float.  The neighbour predicate is always the
-// double-precision one.
+// and pressure differences are always formed in double and then converted.
+// In float every pair sum is compensated: Kahan for the density and beta
+// sums of pass A (terms of one sign), Neumaier for the average pressure and
+// the shift in pass A and for all four sums of pass B (divergence, EDAC
+// diffusion, pressure gradient, viscous term).  The neighbour predicate is
+// always the double-precision one.
 #include <math.h>
 
 #include "sph_device.h"
@@ -547,8 +549,10 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
     const T nui = aecs8 * (T)hi;
     const T eta = (T)(0.001 * hi * hi);
     const T nu4 = (T)(4.0 * P.nu);
-    CSum<T> sdiv, sdif;
-    T gx = 0, gy = 0, vx = 0, vy = 0;
+    // every pair sum is Neumaier-compensated in float (terms of both signs:
+    // the divergence, the diffusion, the pressure gradient G and the
+    // viscous term all cancel between neighbours)
+    CSum<T> sdiv, sdif, gx, gy, vx, vy;
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
         __attribute__((always_inline)) {
         RATES_FP_CONTRACT
@@ -594,22 +598,22 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
         sdiv.add(Vj * (fi * (uij * dxT + vij * dyT)));
         sdif.add(Vj * nuij_iden * dpij * rdotg);
         const T gf = mj * (Pi * fi + Pj * fj);
-        gx += gf * dxT;
-        gy += gf * dyT;
+        gx.add(gf * dxT);
+        gy.add(gf * dyT);
         const T cv = mj * nu4 * cv_den * rdotg;
         if constexpr (GH) {
             if (solid_i || Vraw < T(0)) {
                 const double ugj = Vraw < T(0) ? ugs[js] : uvj.x;
                 const double vgj = Vraw < T(0) ? vgs[js] : uvj.y;
-                vx += cv * (T)(ugi - ugj);
-                vy += cv * (T)(vgi - vgj);
+                vx.add(cv * (T)(ugi - ugj));
+                vy.add(cv * (T)(vgi - vgj));
             } else {
-                vx += cv * uij;
-                vy += cv * vij;
+                vx.add(cv * uij);
+                vy.add(cv * vij);
             }
         } else {
-            vx += cv * uij;
-            vy += cv * vij;
+            vx.add(cv * uij);
+            vy.add(cv * vij);
         }
     };
     const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
@@ -663,20 +667,21 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
     for (int o = 1; o < RGB; o <<= 1) {
         sdiv.merge_xor(o);
         sdif.merge_xor(o);
-        gx += __shfl_xor(gx, o, 64);
-        gy += __shfl_xor(gy, o, 64);
-        vx += __shfl_xor(vx, o, 64);
-        vy += __shfl_xor(vy, o, 64);
+        gx.merge_xor(o);
+        gy.merge_xor(o);
+        vx.merge_xor(o);
+        vy.merge_xor(o);
     }
     if (gl) return;
     const T beta = b.beta[s];
     const T ib = beta > T(0) ? T(1) / beta : T(0);
     const double dxs = (double)b.dxs[s], dys = (double)b.dys[s];
     const int slot = nv.perm[s];
+    const T Gx = gx.get(), Gy = gy.get();
     dpdt[slot] = (double)((T)(P.rho0 * P.cs * P.cs) * ib * sdiv.get() + sdif.get() * ib) +
-                 (dxs / P.dt) * (double)gx + (dys / P.dt) * (double)gy;
-    dudt[slot] = (double)(-gx + vx * ib) + P.fx;
-    dvdt[slot] = (double)(-gy + vy * ib) + P.fy;
+                 (dxs / P.dt) * (double)Gx + (dys / P.dt) * (double)Gy;
+    dudt[slot] = (double)(-Gx + vx.get() * ib) + P.fx;
+    dvdt[slot] = (double)(-Gy + vy.get() * ib) + P.fy;
 }
 
 template <typename T, bool GH>

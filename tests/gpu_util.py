@@ -58,3 +58,44 @@ def with_fields(s, seed=0):
     out["m"] = out["mq"] * q
     out["params"] = {"rho0": 1.0, "cs": 10.0, "nu": 0.01, "hdx": 1.0}
     return out
+
+
+RATE_FIELDS = ("rho", "beta", "pavg", "dxs", "dys", "dpdt", "dudt", "dvdt")
+# Bounds of the rate parity tests.  Normwise: ||a - b||_2 / ||b||_2 per
+# field.  Per particle (condition-aware): max_i |a_i - b_i| / s_i, with s_i the
+# oracle's sum of the magnitudes of the terms b_i adds up (oracle.rate_scales).
+# FP64 pair arithmetic: both 1e-12.  FP32 pair arithmetic: the target's 1e-5
+# normwise; per particle 1e-5 as well, which leaves room for about 160 ulp
+# (2^-24) of the terms: a pair term takes some 10-20 roundings, and the
+# quintic's derivative loses up to a factor 10 to cancellation at the
+# distances of split children (q ~ 0.4), while every sum is compensated.
+TOL = {"fp64": {"norm": 1e-12, "cond": 1e-12}, "fp32": {"norm": 1e-5, "cond": 1e-5}}
+
+
+def rate_errors(r, o, fields=RATE_FIELDS):
+    """Per field: normwise relative error, the condition-aware per-particle
+    error against o["scale"], and max |a - b| / max |b|."""
+    out = {}
+    for k in fields:
+        a = r[k].cpu().numpy() if hasattr(r[k], "cpu") else np.asarray(r[k])
+        b = np.asarray(o[k], np.float64)
+        mb = float(np.abs(b).max()) if b.size else 0.0
+        mx = float(np.abs(a - b).max()) if b.size else 0.0
+        out[k] = {"norm": rel_norm(a, b), "cond": oracle.cond_error(a, b, o["scale"][k]),
+                  "maxabs": mx / mb if mb > 0 else mx}
+    return out
+
+
+def check_rates(r, o, prec, label="", fields=RATE_FIELDS, tol=None):
+    """Asserts the normwise and per-particle bounds of TOL[prec] on every
+    field; prints the errors first."""
+    t = dict(TOL[prec])
+    if tol:
+        t.update(tol)
+    e = rate_errors(r, o, fields)
+    worst = {k: (f"{v['norm']:.2e}", f"{v['cond']:.2e}") for k, v in e.items()}
+    print(f"[rates] {label} {prec} (norm, cond) {worst}", flush=True)
+    for k, v in e.items():
+        assert v["norm"] < t["norm"], (label, prec, k, "norm", v["norm"])
+        assert v["cond"] < t["cond"], (label, prec, k, "cond", v["cond"])
+    return e

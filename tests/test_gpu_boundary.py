@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -74,11 +74,7 @@ def test_boundary_rates_vs_oracle(case, prec):
     ps = particles(P, s)
     r = ctx.rates(ps, dt)
     o = oracle.rates_k(odom(s["domain"]), _prm(s, body), s, dt, io=io)
-    tol = 1e-12 if prec == "fp64" else 1e-5
-    errs = {k: rel_norm(r[k].cpu().numpy(), o[k]) for k in FIELDS}
-    print(f"[boundary] errors={errs}", flush=True)
-    for k in FIELDS:
-        assert errs[k] < tol, (k, errs[k])
+    check_rates(r, o, prec, case)
     # the boundary values written into the state (double in both paths)
     st = ps.numpy()
     for k, ok in (("p", "p_bc"), ("u", "u_bc"), ("v", "v_bc")):

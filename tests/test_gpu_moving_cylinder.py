@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -114,16 +114,13 @@ def test_moving_cylinder_full_size():
     yq, vq, aq = W.body_motion(0.25 * mo["period"], mo["amp"], mo["period"])
     o = oracle.move_solids(d, s, (0.0, yq), (0.0, vq))
     r_o = oracle.rates_k(d, _prm(s), o, s["dt"], aw=(0.0, aq), io=s["params"]["io_ref"])
-    for prec, tol in ((P.SPH_FP64, 1e-12), (P.SPH_FP32, 1e-5)):
+    for prec, name in ((P.SPH_FP64, "fp64"), (P.SPH_FP32, "fp32")):
         ctx = ctx_for(P, s, prec)
         ps = particles(P, s)
         ctx.move_solids(ps, (0.0, yq), (0.0, vq), (0.0, aq))
         r = ctx.rates(ps, s["dt"])
         assert np.array_equal(r["nnb"].cpu().numpy(), r_o["nnb"])
-        errs = {k: rel_norm(r[k].cpu().numpy(), r_o[k]) for k in FIELDS}
-        print(f"[osc] prec={prec} errors={errs}", flush=True)
-        for k in FIELDS:
-            assert errs[k] < tol, (prec, k, errs[k])
+        check_rates(r, r_o, name, "oscillating cylinder")
     # the whole loop on the FP32 path: body motion and a background pass
     # every step, adaptation every 10 steps, inlet/outlet zones updated
     bg = W.channel_background(spec)

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -40,14 +40,11 @@ def test_wake_channel_neighbors_and_rates(wake):
     assert np.array_equal(rp.cpu().numpy(), orp) and np.array_equal(col.cpu().numpy(), ocol)
     del rp, col, orp, ocol
     o = oracle.rates_k(d, _prm(s), s, s["dt"], io=s["params"]["io_ref"])
-    for prec, tol in ((P.SPH_FP64, 1e-12), (P.SPH_FP32, 1e-5)):
+    for prec, name in ((P.SPH_FP64, "fp64"), (P.SPH_FP32, "fp32")):
         c = ctx if prec == P.SPH_FP64 else ctx_for(P, s, prec)
         r = c.rates(particles(P, s), s["dt"])
         assert np.array_equal(r["nnb"].cpu().numpy(), o["nnb"])
-        errs = {k: rel_norm(r[k].cpu().numpy(), o[k]) for k in FIELDS}
-        print(f"[wake] prec={prec} errors={errs}", flush=True)
-        for k in FIELDS:
-            assert errs[k] < tol, (prec, k, errs[k])
+        check_rates(r, o, name, "wake channel")
 
 
 def test_wake_channel_solution_background_and_adapt(wake):

@@ -256,3 +256,39 @@ def test_pec_constant_velocity_translation(orc):
     assert np.allclose(out["x"], np.mod(x + 4 * dt * 0.5, 1.0), atol=1e-14)
     assert np.allclose(out["y"], np.mod(y + 4 * dt * 0.25, 1.0), atol=1e-14)
     assert np.all(out["u"] == 0.5) and np.all(out["v"] == 0.25)
+
+
+def test_rate_scales_bound_the_rates(orc):
+    """The per-particle scales of the condition-aware comparisons are sums
+    of the magnitudes of the terms each rate adds up, so (triangle
+    inequality) every rate is at most its scale in magnitude, and the
+    density, whose terms are all positive, equals its scale; the same holds
+    with boundary particles in the sums."""
+    rng = np.random.default_rng(12)
+    s = W.random_varh(1500, seed=12, h_lo=0.012, ratio=4)
+    n = s["x"].size
+    u = np.sin(2 * np.pi * s["x"]) + 0.05 * rng.standard_normal(n)
+    v = np.cos(2 * np.pi * s["y"])
+    p = 3.0 + 0.2 * rng.standard_normal(n)
+    m = 2.0 * s["h"] ** 2
+    dom = orc.Dom(tuple(s["domain"].lo), tuple(s["domain"].hi), tuple(s["domain"].periodic))
+    prm = orc.Prm(nu=0.01, fx=0.3)
+    r = orc.rates(dom, prm, s["x"], s["y"], u, v, p, s["h"], m, 1e-4)
+    w = W.wall_box(nx=16, ny=14, layers=3, jitter=0.1, seed=13)
+    nw = w["x"].size
+    fl = w["kind"] == W.FLUID
+    w["u"] = np.where(fl, 0.3 * np.sin(2 * np.pi * w["x"]), 0.0)
+    w["v"] = np.where(fl, 0.1 * rng.standard_normal(nw), 0.0)
+    w["p"] = np.where(fl, 1.0 - 2.0 * w["y"], 0.0)
+    w["rho"] = np.ones(nw)
+    w["m"] = w["mq"] * w["mass_q"]
+    dw = orc.Dom(tuple(w["domain"].lo), tuple(w["domain"].hi), tuple(w["domain"].periodic))
+    rk = orc.rates_k(dw, orc.Prm(nu=0.01, fy=-2.0, mass_q=w["mass_q"]), w, 1e-4)
+    for out in (r, rk):
+        sc = out["scale"]
+        for k in orc.RATE_FIELDS:
+            assert np.all(np.abs(out[k]) <= sc[k] * (1 + 1e-12) + 1e-300), k
+        assert np.allclose(sc["rho"], out["rho"], rtol=1e-14, atol=0)
+        # a scale does not vanish where its rate does not
+        for k in ("dpdt", "dudt", "dvdt"):
+            assert np.all((out[k] == 0) | (sc[k] > 0)), k
