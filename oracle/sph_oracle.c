@@ -530,6 +530,11 @@ static void shift_one(const or_domain* d, double rho0, int64_t i, const double* 
     *dys = ddy;
 }
 
+/* READING: the average pressure of eq. (pavg) is formed as
+ * p_i + (1/N_i) sum_j (p_j - p_i), the same mean written about p_i, so that a
+ * uniform pressure gives p_avg = p exactly and the reduced pressure of eq.
+ * (mom:pre) removes it exactly (a plain sum of N copies of a non-dyadic p
+ * rounds, which would leave a force of rounding size on fluid at rest). */
 void or_pass_a(const or_domain* d, const or_params* P, int64_t n, const double* x,
                const double* y, const double* h, const double* m, const double* p,
                const int64_t* rp, const int32_t* col, double* rho, double* beta,
@@ -545,13 +550,13 @@ void or_pass_a(const or_domain* d, const or_params* P, int64_t n, const double* 
             double r = sqrt(dx * dx + dy * dy);
             sr += m[j] * or_w(r, h[i]);
             sb += m[j] * r * or_dwdr(r, h[i]);
-            sp += p[j];
+            sp += p[j] - p[i];
         }
         double N = (double)(rp[i + 1] - rp[i]);
         rho[i] = sr;
         beta[i] = -sb / (2.0 * sr);
         nnb[i] = N;
-        pavg[i] = sp / N;
+        pavg[i] = p[i] + sp / N;
         shift_one(d, P->rho0, i, x, y, h, m, rp, col, &dxs[i], &dys[i]);
     }
 }

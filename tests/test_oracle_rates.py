@@ -193,6 +193,21 @@ def test_rest_state_exact(orc):
     assert np.all(r["dpdt"] == 0) and np.all(r["dudt"] == 0) and np.all(r["dvdt"] == 0)
 
 
+def test_uniform_pressure_no_force(orc):
+    """Eq. (mom:pre) subtracts the average pressure of eq. (pavg), so a
+    uniform pressure exerts no force and has no rate, exactly, whatever its
+    value: p_avg equals p and P_i = P_j = 0.  The value is not dyadic, so a
+    mean that rounds would leave a residue."""
+    s = W.tgv(20, seed=9)
+    dom = orc.Dom()
+    n = s["x"].size
+    p0 = 5.0 + 4.0 * math.log(2.0) - 2.0
+    r = orc.rates(dom, orc.Prm(), s["x"], s["y"], np.zeros(n), np.zeros(n), np.full(n, p0),
+                  s["h"], s["m"], s["dt"])
+    assert np.all(r["pavg"] == p0)
+    assert np.all(r["dpdt"] == 0) and np.all(r["dudt"] == 0) and np.all(r["dvdt"] == 0)
+
+
 def test_pairwise_antisymmetry(orc):
     # with p_avg subtracted per particle as printed (reading 0) the pressure
     # pair term is antisymmetric over the symmetric neighbour set, so it
