@@ -649,7 +649,12 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
  *   dpdt: (rho0 c^2 / |beta_i|) sum V_j (|u_ij gradW_i,x| + |v_ij gradW_i,y|)
  *         + sum V_j |nu_ij (p_i - p_j) r_ij . gradW_ij| / ((r_ij^2 + eta_i) |beta_i|)
  *         + (|dxs_i| S_x + |dys_i| S_y) / dt + (s_dxs |G_x| + s_dys |G_y|) / dt,
- *         S_x = sum m_j (|P_i gradW_i,x| + |P_j gradW_j,x|), G the signed
+ *         S_x = sum m_j (|P_i| |gradW_i,x| + |P_j| |gradW_j,x|) with the
+ *         reduced pressures of eq. (mom:pre) taken at the size of what they
+ *         are formed from, |P_i| = (|p_i| + |p_avg,i|) / (rho_i^2 |beta_i|)
+ *         and |P_j| = (|p_j| + |p_avg|) / (rho_j^2 |beta_j|) (p - p_avg
+ *         cancels where the pressure is nearly uniform about an offset, and
+ *         a rounding of p_avg at that offset is then all of it), G the signed
  *         pressure-gradient sum and s_dxs, s_dys the shift scales (the error
  *         of the shift enters through the transport-velocity term);
  *   dudt: S_x + sum |c_ij (ug_i - ug_j)| / |beta_i| + |f_x|, c_ij the
@@ -672,6 +677,7 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
         double s_div = 0.0, s_dif = 0.0, Sx = 0.0, Sy = 0.0, Gx = 0.0, Gy = 0.0;
         double s_vx = 0.0, s_vy = 0.0;
         double Pi = beta[i] > 0.0 ? (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]) : 0.0;
+        double Pai = beta[i] > 0.0 ? (fabs(p[i]) + fabs(pavg[i])) / (rho[i] * rho[i] * beta[i]) : 0.0;
         double nui = ae * cs * h[i] / 8.0;
         double eta = 0.001 * h[i] * h[i];
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
@@ -699,16 +705,17 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
             }
             double gbx = 0.5 * (gix + gjx), gby = 0.5 * (giy + gjy);
             double Vj = m[j] / rho[j];
-            double Pj = beta[j] <= 0.0 ? 0.0
-                      : P->pref_mode ? (p[j] - pavg[i]) / (rho[j] * rho[j] * beta[j])
-                                     : (p[j] - pavg[j]) / (rho[j] * rho[j] * beta[j]);
+            double pref_j = P->pref_mode ? pavg[i] : pavg[j];
+            double Pj = beta[j] <= 0.0 ? 0.0 : (p[j] - pref_j) / (rho[j] * rho[j] * beta[j]);
+            double Paj = beta[j] <= 0.0 ? 0.0
+                       : (fabs(p[j]) + fabs(pref_j)) / (rho[j] * rho[j] * beta[j]);
             double nuj = ae * cs * h[j] / 8.0;
             double nuij = 4.0 * nui * nuj / (nui + nuj);
             double rdotg = dx * gbx + dy * gby;
             s_div += Vj * (fabs((u[i] - u[j]) * gix) + fabs((v[i] - v[j]) * giy));
             s_dif += Vj * fabs(nuij * (p[i] - p[j]) * rdotg) / (r2 + eta);
-            Sx += m[j] * (fabs(Pi * gix) + fabs(Pj * gjx));
-            Sy += m[j] * (fabs(Pi * giy) + fabs(Pj * gjy));
+            Sx += m[j] * (Pai * fabs(gix) + Paj * fabs(gjx));
+            Sy += m[j] * (Pai * fabs(giy) + Paj * fabs(gjy));
             Gx += m[j] * (Pi * gix + Pj * gjx);
             Gy += m[j] * (Pi * giy + Pj * gjy);
             double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
