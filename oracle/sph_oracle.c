@@ -641,7 +641,7 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
  * order: rho, beta, pavg, dxs, dys, dpdt, dudt, dvdt.
  *   rho:  sum |m_j W(r_ij, h_i)|;
  *   beta: sum |m_j r_ij dW/dr(r_ij, h_i)| / (2 rho_i);
- *   pavg: sum |p_j| / N_i;
+ *   pavg: |p_i| + sum |p_j - p_i| / N_i (the terms of p_i + mean(p_j - p_i));
  *   dxs, dys: theta (h_i^2 / 2) sum |t_j| (|dx_j| + |dy_j|), t_j the scalar
  *         factor of the shifting sum of eq. (shift-deltar) and theta the
  *         limiter of eq. (shift-limit) (both components, because the limiter
@@ -659,13 +659,17 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
  *         of the shift enters through the transport-velocity term);
  *   dudt: S_x + sum |c_ij (ug_i - ug_j)| / |beta_i| + |f_x|, c_ij the
  *         viscous factor of eq. (mom-sph); dvdt likewise.
- * Sums scaled by 1/beta_i are dropped where beta_i <= 0, as in pass B. */
+ * Sums scaled by 1/beta_i are dropped where beta_i <= 0, as in pass B.
+ * kind (may be NULL: all fluid): the boundary pass computes u, v, p and the
+ * ghost velocity of non-fluid particles as Shepard averages, which carry
+ * their own rounding, so a difference a_i - a_j of those values over a pair
+ * with a non-fluid member is taken at |a_i| + |a_j|. */
 void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const double* x,
                     const double* y, const double* u, const double* v, const double* p,
                     const double* h, const double* m, const double* rho,
                     const double* beta, const double* pavg, const double* dxs,
                     const double* dys, double dt, const int64_t* rp, const int32_t* col,
-                    const double* ug, const double* vg, double* sc)
+                    const double* ug, const double* vg, const int32_t* kind, double* sc)
 {
     const double rho0 = P->rho0, cs = P->cs, nu = P->nu, ae = P->alpha_e;
     if (!ug) ug = u;
@@ -686,9 +690,12 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
             double dy = mi_axis(d, 1, y[i] - y[j]);
             double r2 = dx * dx + dy * dy;
             double r = sqrt(r2);
+            /* |a_i - a_j|, or |a_i| + |a_j| over a pair with a boundary member */
+            const int bnd = kind && (kind[i] != 0 || kind[j] != 0);
+#define OR_DABS(a) (bnd ? fabs((a)[i]) + fabs((a)[j]) : fabs((a)[i] - (a)[j]))
             s_rho += fabs(m[j] * or_w(r, h[i]));
             s_beta += fabs(m[j] * r * or_dwdr(r, h[i]));
-            s_p += fabs(p[j]);
+            s_p += OR_DABS(p);
             double gix = 0.0, giy = 0.0, gjx = 0.0, gjy = 0.0;
             if (r > 0.0) {
                 double hij = 0.5 * (h[i] + h[j]);
@@ -712,15 +719,16 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
             double nuj = ae * cs * h[j] / 8.0;
             double nuij = 4.0 * nui * nuj / (nui + nuj);
             double rdotg = dx * gbx + dy * gby;
-            s_div += Vj * (fabs((u[i] - u[j]) * gix) + fabs((v[i] - v[j]) * giy));
-            s_dif += Vj * fabs(nuij * (p[i] - p[j]) * rdotg) / (r2 + eta);
+            s_div += Vj * (OR_DABS(u) * fabs(gix) + OR_DABS(v) * fabs(giy));
+            s_dif += Vj * fabs(nuij * rdotg) * OR_DABS(p) / (r2 + eta);
             Sx += m[j] * (Pai * fabs(gix) + Paj * fabs(gjx));
             Sy += m[j] * (Pai * fabs(giy) + Paj * fabs(gjy));
             Gx += m[j] * (Pi * gix + Pj * gjx);
             Gy += m[j] * (Pi * giy + Pj * gjy);
             double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
-            s_vx += fabs(cvis * (ug[i] - ug[j]));
-            s_vy += fabs(cvis * (vg[i] - vg[j]));
+            s_vx += fabs(cvis) * OR_DABS(ug);
+            s_vy += fabs(cvis) * OR_DABS(vg);
+#undef OR_DABS
         }
         double N = (double)(rp[i + 1] - rp[i]);
         double pref = 0.5 * (h[i] * h[i]);
@@ -732,7 +740,7 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
         double ib = b > 0.0 ? 1.0 / b : 0.0;
         sc[0 * n + i] = s_rho;
         sc[1 * n + i] = s_beta / (2.0 * fabs(rho[i]));
-        sc[2 * n + i] = N > 0 ? s_p / N : 0.0;
+        sc[2 * n + i] = fabs(p[i]) + (N > 0 ? s_p / N : 0.0);
         sc[3 * n + i] = s_shift;
         sc[4 * n + i] = s_shift;
         sc[5 * n + i] = rho0 * cs * cs * ib * s_div + s_dif * ib +
@@ -876,7 +884,7 @@ int or_rates_k_scaled(const or_domain* d, const or_params* P, const or_bc* B, in
               dpdt, dudt, dvdt);
     if (sc)
         or_rate_scales(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug,
-                       vg, sc);
+                       vg, kind, sc);
     free(ug);
     free(vg);
     free(rp);
