@@ -94,7 +94,7 @@ def lib():
             "or_boundary": (None, [P, P, P, I64] + [P] * 12),
             "or_rates_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 9),
             "or_rates_k_scaled": (C.c_int, [P, P, P, I64] + [P] * 9 + [D] + [P] * 10),
-            "or_rate_scales": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 6),
+            "or_rate_scales": (None, [P, P, I64] + [P] * 12 + [D] + [P] * 7),
             "or_body_force": (C.c_int, [P, P, P, I64] + [P] * 10),
             "or_move_solids": (None, [P, I64, P, D, D, D, D, P, P, P, P]),
             "or_step_k": (C.c_int, [P, P, P, I64] + [P] * 9 + [D, I64]),
@@ -307,7 +307,7 @@ def rate_scales(dom: Dom, prm: Prm, x, y, u, v, p, h, m, a, dt, rp, col, ug=None
     lib().or_rate_scales(C.byref(dom.c()), C.byref(prm.c()), n, _p(x), _p(y), _p(u), _p(v),
                          _p(p), _p(h), _p(m), _p(_f64(a["rho"])), _p(_f64(a["beta"])),
                          _p(_f64(a["pavg"])), _p(_f64(a["dxs"])), _p(_f64(a["dys"])), float(dt),
-                         _p(rp), _p(col), _p(ug), _p(vg), None, _p(sc))
+                         _p(rp), _p(col), _p(ug), _p(vg), None, None, _p(sc))
     return {k: sc[f * n:(f + 1) * n].copy() for f, k in enumerate(RATE_FIELDS)}
 
 

@@ -661,15 +661,18 @@ void or_pass_b(const or_domain* d, const or_params* P, int64_t n, const double* 
  *         viscous factor of eq. (mom-sph); dvdt likewise.
  * Sums scaled by 1/beta_i are dropped where beta_i <= 0, as in pass B.
  * kind (may be NULL: all fluid): the boundary pass computes u, v, p and the
- * ghost velocity of non-fluid particles as Shepard averages, which carry
+ * ghost velocity of non-fluid particles from Shepard averages, which carry
  * their own rounding, so a difference a_i - a_j of those values over a pair
- * with a non-fluid member is taken at |a_i| + |a_j|. */
+ * with a non-fluid member is taken at mag_i + mag_j, mag being the size of
+ * what each value is formed from: mag (5 n doubles: p, u, v, ug, vg) as
+ * or_boundary_mags writes it, or |a| where mag is NULL. */
 void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const double* x,
                     const double* y, const double* u, const double* v, const double* p,
                     const double* h, const double* m, const double* rho,
                     const double* beta, const double* pavg, const double* dxs,
                     const double* dys, double dt, const int64_t* rp, const int32_t* col,
-                    const double* ug, const double* vg, const int32_t* kind, double* sc)
+                    const double* ug, const double* vg, const int32_t* kind,
+                    const double* mag, double* sc)
 {
     const double rho0 = P->rho0, cs = P->cs, nu = P->nu, ae = P->alpha_e;
     if (!ug) ug = u;
@@ -681,7 +684,8 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
         double s_div = 0.0, s_dif = 0.0, Sx = 0.0, Sy = 0.0, Gx = 0.0, Gy = 0.0;
         double s_vx = 0.0, s_vy = 0.0;
         double Pi = beta[i] > 0.0 ? (p[i] - pavg[i]) / (rho[i] * rho[i] * beta[i]) : 0.0;
-        double Pai = beta[i] > 0.0 ? (fabs(p[i]) + fabs(pavg[i])) / (rho[i] * rho[i] * beta[i]) : 0.0;
+        const double pmi = mag ? mag[i] : fabs(p[i]);
+        double Pai = beta[i] > 0.0 ? (pmi + fabs(pavg[i])) / (rho[i] * rho[i] * beta[i]) : 0.0;
         double nui = ae * cs * h[i] / 8.0;
         double eta = 0.001 * h[i] * h[i];
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
@@ -692,10 +696,11 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
             double r = sqrt(r2);
             /* |a_i - a_j|, or |a_i| + |a_j| over a pair with a boundary member */
             const int bnd = kind && (kind[i] != 0 || kind[j] != 0);
-#define OR_DABS(a) (bnd ? fabs((a)[i]) + fabs((a)[j]) : fabs((a)[i] - (a)[j]))
+#define OR_MAG(a, f, q) (mag ? mag[(f) * n + (q)] : fabs((a)[q]))
+#define OR_DABS_F(a, f) (bnd ? OR_MAG(a, f, i) + OR_MAG(a, f, j) : fabs((a)[i] - (a)[j]))
             s_rho += fabs(m[j] * or_w(r, h[i]));
             s_beta += fabs(m[j] * r * or_dwdr(r, h[i]));
-            s_p += OR_DABS(p);
+            s_p += OR_DABS_F(p, 0);
             double gix = 0.0, giy = 0.0, gjx = 0.0, gjy = 0.0;
             if (r > 0.0) {
                 double hij = 0.5 * (h[i] + h[j]);
@@ -715,20 +720,19 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
             double pref_j = P->pref_mode ? pavg[i] : pavg[j];
             double Pj = beta[j] <= 0.0 ? 0.0 : (p[j] - pref_j) / (rho[j] * rho[j] * beta[j]);
             double Paj = beta[j] <= 0.0 ? 0.0
-                       : (fabs(p[j]) + fabs(pref_j)) / (rho[j] * rho[j] * beta[j]);
+                       : ((mag ? mag[j] : fabs(p[j])) + fabs(pref_j)) / (rho[j] * rho[j] * beta[j]);
             double nuj = ae * cs * h[j] / 8.0;
             double nuij = 4.0 * nui * nuj / (nui + nuj);
             double rdotg = dx * gbx + dy * gby;
-            s_div += Vj * (OR_DABS(u) * fabs(gix) + OR_DABS(v) * fabs(giy));
-            s_dif += Vj * fabs(nuij * rdotg) * OR_DABS(p) / (r2 + eta);
+            s_div += Vj * (OR_DABS_F(u, 1) * fabs(gix) + OR_DABS_F(v, 2) * fabs(giy));
+            s_dif += Vj * fabs(nuij * rdotg) * OR_DABS_F(p, 0) / (r2 + eta);
             Sx += m[j] * (Pai * fabs(gix) + Paj * fabs(gjx));
             Sy += m[j] * (Pai * fabs(giy) + Paj * fabs(gjy));
             Gx += m[j] * (Pi * gix + Pj * gjx);
             Gy += m[j] * (Pi * giy + Pj * gjy);
             double cvis = m[j] * (4.0 * nu / (rho[i] + rho[j])) * rdotg / (r2 + eta);
-            s_vx += fabs(cvis) * OR_DABS(ug);
-            s_vy += fabs(cvis) * OR_DABS(vg);
-#undef OR_DABS
+            s_vx += fabs(cvis) * OR_DABS_F(ug, 3);
+            s_vy += fabs(cvis) * OR_DABS_F(vg, 4);
         }
         double N = (double)(rp[i + 1] - rp[i]);
         double pref = 0.5 * (h[i] * h[i]);
@@ -740,7 +744,9 @@ void or_rate_scales(const or_domain* d, const or_params* P, int64_t n, const dou
         double ib = b > 0.0 ? 1.0 / b : 0.0;
         sc[0 * n + i] = s_rho;
         sc[1 * n + i] = s_beta / (2.0 * fabs(rho[i]));
-        sc[2 * n + i] = fabs(p[i]) + (N > 0 ? s_p / N : 0.0);
+        sc[2 * n + i] = pmi + (N > 0 ? s_p / N : 0.0);
+#undef OR_MAG
+#undef OR_DABS_F
         sc[3 * n + i] = s_shift;
         sc[4 * n + i] = s_shift;
         sc[5 * n + i] = rho0 * cs * cs * ib * s_div + s_dif * ib +
@@ -855,6 +861,71 @@ void or_boundary(const or_domain* d, const or_params* P, const or_bc* B, int64_t
 /* One full rate evaluation: neighbours (cell list), the boundary pass when
  * kind is given (it overwrites p, and u, v of outlet particles, in place;
  * rho_in is the stored density it uses), pass A, pass B. */
+/* Sizes of the values the boundary pass forms (for or_rate_scales): for
+ * every particle, mag[f n + i] with f = 0..4 for p, u, v, ug, vg.  Fluid
+ * particles and boundary particles without fluid neighbours: |value|.
+ * Boundary particles: the same Shepard sums as or_boundary with every term
+ * taken in magnitude, e.g. for a solid (sum |p_f| w + |g_x| sum |rho_f dx| w
+ * + |g_y| sum |rho_f dy| w) / S for p and 2 |u_b| + sum |u_f| w / S for its
+ * ghost velocity; for the characteristic rule, |p_r| + |J|_mag / 2 and
+ * |u_r| + |J|_mag / (2 rho0 c) with |J|_mag = sum |p_f| w / S + |p_r| +
+ * rho0 c (sum |u_f| w / S + |u_r|).  u, v, p, ug, vg: the values after the
+ * boundary pass. */
+static void or_boundary_mags(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
+                             const double* x, const double* y, const double* h,
+                             const double* rho, const int32_t* kind, const int64_t* rp,
+                             const int32_t* col, const double* u0, const double* v0,
+                             const double* u, const double* v, const double* p,
+                             const double* ug, const double* vg, double* mag)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < n; ++b) {
+        mag[0 * n + b] = fabs(p[b]);
+        mag[1 * n + b] = fabs(u[b]);
+        mag[2 * n + b] = fabs(v[b]);
+        mag[3 * n + b] = fabs(ug[b]);
+        mag[4 * n + b] = fabs(vg[b]);
+        if (kind[b] == OR_FLUID) continue;
+        double S = 0.0, su = 0.0, sv = 0.0, sp = 0.0, srx = 0.0, sry = 0.0;
+        for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+            int64_t f = col[k];
+            if (kind[f] != OR_FLUID) continue;
+            double dx = mi_axis(d, 0, x[b] - x[f]);
+            double dy = mi_axis(d, 1, y[b] - y[f]);
+            double r = sqrt(dx * dx + dy * dy);
+            double w = or_w(r, 0.5 * (h[b] + h[f]));
+            S += w;
+            su += fabs(u[f]) * w;
+            sv += fabs(v[f]) * w;
+            sp += fabs(p[f]) * w;
+            srx += fabs(rho[f] * dx) * w;
+            sry += fabs(rho[f] * dy) * w;
+        }
+        if (!(S > 0.0)) continue;
+        if (kind[b] == OR_SOLID) {
+            mag[0 * n + b] = (sp + fabs(P->fx - B->awx) * srx + fabs(P->fy - B->awy) * sry) / S;
+            mag[3 * n + b] = 2.0 * fabs(u0[b]) + su / S;
+            mag[4 * n + b] = 2.0 * fabs(v0[b]) + sv / S;
+        } else if (B->io_mode == 1) {
+            double zc = P->rho0 * P->cs;
+            double jm = sp / S + fabs(B->pr) + zc * (su / S + fabs(B->ur));
+            mag[0 * n + b] = fabs(B->pr) + 0.5 * jm;
+            mag[1 * n + b] = fabs(B->ur) + jm / (2.0 * zc);
+            mag[2 * n + b] = kind[b] == OR_INLET ? fabs(B->vr) : sv / S;
+            mag[3 * n + b] = mag[1 * n + b];
+            mag[4 * n + b] = mag[2 * n + b];
+        } else if (kind[b] == OR_INLET) {
+            mag[0 * n + b] = sp / S;
+        } else {
+            mag[0 * n + b] = sp / S;
+            mag[1 * n + b] = su / S;
+            mag[2 * n + b] = sv / S;
+            mag[3 * n + b] = su / S;
+            mag[4 * n + b] = sv / S;
+        }
+    }
+}
+
 /* The same, also writing the per-particle scales of or_rate_scales (8 n
  * doubles) when sc is not NULL. */
 int or_rates_k_scaled(const or_domain* d, const or_params* P, const or_bc* B, int64_t n,
@@ -868,25 +939,40 @@ int or_rates_k_scaled(const or_domain* d, const or_params* P, const or_bc* B, in
     int32_t* col = NULL;
     int64_t nnz = or_nbr_cells_alloc(d, n, x, y, h, &rp, &col);
     if (nnz < 0) return (int)nnz;
-    double *ug = NULL, *vg = NULL;
+    double *ug = NULL, *vg = NULL, *mag = NULL, *u0 = NULL, *v0 = NULL;
     if (kind) {
         size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
         ug = malloc(sz);
         vg = malloc(sz);
-        if (!ug || !vg) {
-            free(ug); free(vg); free(rp); free(col);
+        if (sc) {
+            mag = malloc(5 * sz);
+            u0 = malloc(sz);
+            v0 = malloc(sz);
+        }
+        if (!ug || !vg || (sc && (!mag || !u0 || !v0))) {
+            free(ug); free(vg); free(mag); free(u0); free(v0); free(rp); free(col);
             return OR_E_NOMEM;
         }
+        if (sc) {
+            memcpy(u0, u, sizeof(double) * (size_t)n);
+            memcpy(v0, v, sizeof(double) * (size_t)n);
+        }
         or_boundary(d, P, B, n, x, y, h, rho_in, kind, rp, col, u, v, p, ug, vg);
+        if (sc)
+            or_boundary_mags(d, P, B, n, x, y, h, rho_in, kind, rp, col, u0, v0, u, v, p, ug,
+                             vg, mag);
     }
     or_pass_a(d, P, n, x, y, h, m, p, rp, col, rho, beta, nnb, pavg, dxs, dys);
     or_pass_b(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug, vg,
               dpdt, dudt, dvdt);
     if (sc)
         or_rate_scales(d, P, n, x, y, u, v, p, h, m, rho, beta, pavg, dxs, dys, dt, rp, col, ug,
-                       vg, kind, sc);
+                       vg, kind, mag, sc);
     free(ug);
     free(vg);
+    free(mag);
+    free(u0);
+    free(v0);
     free(rp);
     free(col);
     return OR_OK;
