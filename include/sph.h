@@ -191,6 +191,8 @@ size_t sph_workspace_bytes(const sph_config *cfg, int64_t capacity);
 int sph_create(const sph_config *cfg, int64_t capacity, void *workspace,
                size_t workspace_bytes, void *stream, sph_ctx **out);
 void sph_destroy(sph_ctx *ctx);
+/* Message of the last error of ctx; with ctx NULL, that of the calling
+ * thread's last failed sph_rates_noalloc. */
 const char *sph_last_error(const sph_ctx *ctx);
 int sph_set_stream(sph_ctx *ctx, void *stream);
 
@@ -424,6 +426,30 @@ int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 int sph_profile_enable(sph_ctx *ctx, int32_t on);
 int sph_profile_read(sph_ctx *ctx, const char *kernel, double *ms, int64_t *launches);
 int sph_profile_reset(sph_ctx *ctx);
+
+/* ---- Rate evaluation that allocates nothing -----------------------------
+ * For callers that cannot allocate device memory or create a context: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same evaluation as sph_rates (same kernels and results as
+ * a context created with lean = 1 and list_skin = 0; the configuration's
+ * lean and list_skin are ignored), on the current HIP device, enqueued on
+ * `stream` (a hipStream_t of that device, NULL = default stream).  The
+ * caller passes the particles and the outputs (as for sph_rates); scratch
+ * memory is a static device array of SPH_NOALLOC_SCRATCH_BYTES that every
+ * GPU the library runs on holds until the process ends.  The call
+ * allocates nothing (no hipMalloc or hipFree, no host mailbox) and does not
+ * synchronise.  Calls on one GPU share its array: calls that overlap on
+ * the device (other streams, other threads) race; calls on one stream are
+ * ordered.  Errors: SPH_E_NOMEM when the particles need more scratch than
+ * the array holds (sph_rates_noalloc_bytes gives the need; about 1.5 KB
+ * per particle at the default list width plus the cell tables, so some
+ * 40,000 particles fit), SPH_E_INVAL for bad arguments, SPH_E_DEVICE for a
+ * HIP error; sph_last_error(NULL) then gives the message (per thread).  On
+ * error nothing has been written. */
+#define SPH_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+size_t sph_rates_noalloc_bytes(const sph_config *cfg, int64_t n);
+int sph_rates_noalloc(const sph_config *cfg, const sph_particles *ps, double dt,
+                      sph_rates_out *out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -108,7 +108,8 @@ EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "s
            "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
            "sph_pool_footprint", "sph_pool_create",
            "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
-           "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info")
+           "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info",
+           "sph_rates_noalloc_bytes", "sph_rates_noalloc")
 
 _lib = None
 
@@ -158,6 +159,8 @@ def load_library(path: str = LIB_PATH):
         "sph_pool_read": (C.c_int, [P, I32, P]),
         "sph_pool_retire": (C.c_int, [P, I32]),
         "sph_pool_info": (C.c_int, [P, P]),
+        "sph_rates_noalloc_bytes": (C.c_size_t, [P, I64]),
+        "sph_rates_noalloc": (C.c_int, [P, P, D, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -309,6 +312,35 @@ class Background:
         out["mask"] = self.mask[:n].cpu().numpy()
         out["mq"] = self.mq[:n].cpu().numpy()
         return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def rates_noalloc_bytes(cfg: "Config", n: int) -> int:
+    """Scratch bytes sph_rates_noalloc needs for n particles."""
+    return int(load_library().sph_rates_noalloc_bytes(C.byref(cfg.c()), int(n)))
+
+
+def rates_noalloc(cfg: "Config", P: "Particles", dt: float, out: dict | None = None, stream=None):
+    """One rate evaluation through sph_rates_noalloc (no context, no
+    allocation inside the library; scratch is its static device array).
+    `out` may hold preallocated float64 tensors of the fields."""
+    lib = load_library()
+    n = P.n
+    if out is None:
+        out = {k: torch.empty(max(n, 1), dtype=torch.float64, device=P.device)
+               for k in ("rho", "beta", "pavg", "nnb", "dxs", "dys", "dpdt", "dudt", "dvdt")}
+    ro = sph_rates_out(**{k: _ptr(v).value for k, v in out.items()})
+    st = stream if stream is not None else torch.cuda.current_stream(P.device)
+    ps = P.c()
+    c = cfg.c()
+    rc = lib.sph_rates_noalloc(C.byref(c), C.byref(ps), float(dt), C.byref(ro),
+                               C.c_void_p(st.cuda_stream))
+    if rc != SPH_OK:
+        msg = lib.sph_last_error(None)
+        raise SphError(rc, msg.decode() if msg else "")
+    return {k: v[:n] for k, v in out.items()}
 
 
 class Context:

@@ -6,6 +6,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "sph_internal.h"
 
 #define SPH_VERSION 10000
@@ -168,6 +170,10 @@ __global__ void k_readback(RbArgs a, uint32_t* mbox, uint32_t seq)
 
 int readback(sph_ctx* c, const Readback* items, int n)
 {
+    if (!c->mbox) {
+        set_err(c, "this evaluation has no host mailbox (no readback is possible)");
+        return SPH_E_INVAL;
+    }
     if (n < 0 || n > 4) {
         set_err(c, "readback of %d items", n);
         return SPH_E_INVAL;
@@ -276,7 +282,10 @@ extern "C" void sph_destroy(sph_ctx* c)
     free(c);
 }
 
-extern "C" const char* sph_last_error(const sph_ctx* c) { return c ? c->err : "no context"; }
+// message of the last failed sph_rates_noalloc call of this thread
+static thread_local char t_noalloc_err[512] = "no context";
+
+extern "C" const char* sph_last_error(const sph_ctx* c) { return c ? c->err : t_noalloc_err; }
 
 extern "C" int sph_set_stream(sph_ctx* c, void* stream)
 {
@@ -704,4 +713,105 @@ extern "C" int sph_profile_read(sph_ctx* c, const char* kernel, double* ms, int6
     }
     set_err(c, "unknown kernel name %s", kernel);
     return SPH_E_INVAL;
+}
+
+// ---------------------------------------------------------------------------
+// Rate evaluation without allocation.  The scratch memory is a file-scope
+// device array: every GPU the library runs on holds its own copy (at its own
+// address) from the moment the library's code is loaded on it until the
+// process ends.  On host, `scratch` names only a host-side stand-in, so host
+// code never passes it to a kernel: the device address is looked up once
+// per device with hipGetSymbolAddress and kept in g_scratch.
+// ---------------------------------------------------------------------------
+
+#define SPH_NOALLOC_MAX_DEV 64
+
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_SCRATCH_BYTES];
+static void* g_scratch[SPH_NOALLOC_MAX_DEV];
+static std::mutex g_scratch_mu;
+
+static int noalloc_err(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_noalloc_err, sizeof(t_noalloc_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+// Device address of this device's scratch array (looked up on first use).
+static int scratch_address(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return noalloc_err(SPH_E_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= SPH_NOALLOC_MAX_DEV)
+        return noalloc_err(SPH_E_DEVICE, "device %d beyond the supported %d", dev, SPH_NOALLOC_MAX_DEV);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return noalloc_err(SPH_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                               hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return SPH_OK;
+}
+
+extern "C" size_t sph_rates_noalloc_bytes(const sph_config* cfg, int64_t n)
+{
+    if (!check_cfg(cfg) || n < 0) return 0;
+    sph_config lc = *cfg;
+    lc.lean = 1;
+    lc.list_skin = 0.0;
+    Grid g;
+    grid_setup(&lc, &g);
+    Work w;
+    return carve(&w, nullptr, g, n, 1, lc.list_k > 0 ? lc.list_k : NL_K);
+}
+
+extern "C" int sph_rates_noalloc(const sph_config* cfg, const sph_particles* ps, double dt,
+                                 sph_rates_out* out, void* stream)
+{
+    if (!cfg || !ps || !out) return noalloc_err(SPH_E_INVAL, "NULL argument");
+    sph_config lc = *cfg;
+    lc.lean = 1;        // no adaptation buffers
+    lc.list_skin = 0.0; // the list is built afresh: no host round trip
+    if (!check_cfg(&lc)) return noalloc_err(SPH_E_INVAL, "invalid configuration");
+    if (!(dt > 0)) return noalloc_err(SPH_E_INVAL, "dt must be > 0");
+    const int64_t n = ps->n;
+    if (n < 0 || n > ps->capacity || n > (int64_t)INT32_MAX - 1)
+        return noalloc_err(SPH_E_INVAL, "n=%lld capacity=%lld", (long long)n, (long long)ps->capacity);
+    if (!ps->x || !ps->y || !ps->h || !ps->u || !ps->v || !ps->p || !ps->mq)
+        return noalloc_err(SPH_E_INVAL, "x, y, u, v, p, h, mq must be set");
+    if (ps->kind && !ps->rho) return noalloc_err(SPH_E_INVAL, "boundary particles need rho");
+    const int lk = lc.list_k > 0 ? lc.list_k : NL_K;
+    // static: the context is host bookkeeping only, and large (profiling
+    // slots); one per thread, reused
+    static thread_local sph_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.cfg = lc;
+    grid_setup(&lc, &c.grid);
+    const size_t need = carve(&c.w, nullptr, c.grid, n, 1, lk);
+    if (need > SPH_NOALLOC_SCRATCH_BYTES)
+        return noalloc_err(SPH_E_NOMEM,
+                           "%lld particles need %zu bytes of scratch; the static scratch holds %zu",
+                           (long long)n, need, (size_t)SPH_NOALLOC_SCRATCH_BYTES);
+    void* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    carve(&c.w, (char*)base, c.grid, n, 1, lk);
+    c.capacity = n > 0 ? n : 1;
+    c.stream = (hipStream_t)stream;
+    c.skin = 0.0;
+    c.mbox = nullptr;  // no readback happens on this path
+    // the array keeps the last call's contents: clear the counters
+    hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c.stream, c.w.status, c.w.ctr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return noalloc_err(SPH_E_DEVICE, "init: %s", hipGetErrorString(e));
+    rc = rates_eval(&c, (int)n, ps, dt, out);
+    if (rc) return noalloc_err(rc, "%s", c.err);
+    return SPH_OK;
 }
