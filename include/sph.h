@@ -108,6 +108,19 @@ typedef struct sph_config {
                                p = p_r + (J2 + J3)/2 and
                                u = u_r + (J2 - J3)/(2 rho0 c) */
     double io_ref[3];       /* (u_r, v_r, p_r) of io_mode 1 */
+    /* The per-iteration schedule of sph_step (the algorithm of section 3.4): */
+    double dt;              /* time step; 0 = eq. (timestep) with h_min = h_lo,
+                               U = u_ref (sph_timestep) */
+    double sol_k;           /* solution adaptivity (section 3.3): background
+                               particles with Shepard-averaged |omega| above
+                               sol_k max|omega| are refined at every
+                               background update; 0 = off */
+    int32_t n_adapt;        /* split, merge, shift and h update every n_adapt
+                               iterations (0 = never) */
+    int32_t n_bg;           /* background update every n_bg iterations (0 =
+                               never) */
+    int32_t bg_passes;      /* passes of each background update (1 suffices
+                               for small motions, section 3.3) */
 } sph_config;
 
 /* Caller-owned particle set (device pointers, see conventions). kind may be
@@ -223,6 +236,12 @@ int sph_build_neighbors(sph_ctx *ctx, const sph_particles *ps, sph_csr *out);
  * particle with no fluid neighbour keeps its values. */
 int sph_rates(sph_ctx *ctx, const sph_particles *ps, double dt, sph_rates_out *out);
 
+/* Time step of eq. (timestep): min(0.25 h_min / (U + c_s), 0.125 h_min^2 /
+ * nu) with U = cfg->u_ref, c_s = cfg->cs, nu = cfg->nu (the second bound
+ * is dropped for nu = 0); h_min <= 0 takes cfg->h_lo.  Returns 0 for an
+ * invalid configuration. */
+double sph_timestep(const sph_config *cfg, double h_min);
+
 /* nsteps predict-evaluate-correct steps (eqs. int-pre, int-cor) of size dt,
  * neighbours rebuilt before each of the two evaluations per step.  Fluid
  * particles are integrated; solid particles stay in place; inlet and outlet
@@ -231,7 +250,35 @@ int sph_rates(sph_ctx *ctx, const sph_particles *ps, double dt, sph_rates_out *o
  * boundary pass of sph_rates and stores its summation density in ps->rho,
  * which the next boundary pass reads.  Updates x, y, u, v, p and rho in
  * place; non-fluid particles end with their half-step boundary values. */
-int sph_step(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps);
+int sph_pec(sph_ctx *ctx, sph_particles *ps, double dt, int32_t nsteps);
+
+/* nsteps iterations of the algorithm of section 3.4.  Before iteration it
+ * (the context's counter, 0 at creation; sph_set_iteration sets it, and
+ * sph_import sets it to the checkpoint's step), when it > 0:
+ *   (i)  every cfg->n_bg iterations, when bg and solids are given, the
+ *        background is updated (cfg->bg_passes passes of sph_bg_update with
+ *        solids; with cfg->sol_k > 0 those of sph_bg_update_solution over
+ *        ps, which refine the background where the fluid's vorticity is
+ *        above sol_k of its maximum);
+ *   (ii) every cfg->n_adapt iterations, when bg is given, the fluid is
+ *        adapted as sph_adapt does (m_ref from the background, which the
+ *        update of (i) already moved; split, merge, shift and Taylor
+ *        correction, h update).
+ * Then the iteration takes one predict-evaluate-correct step of size
+ * cfg->dt (eq. timestep when 0), followed, when io is given, by the
+ * inlet/outlet update of sph_inout.  The initialisation (items 1 and 2 of
+ * the algorithm: the background's initial passes and the first
+ * adaptations) is the caller's, with sph_bg_update and sph_adapt.  Runs of
+ * steps between updates are enqueued at once with the guards of
+ * sph_step_inout (one host round trip per run).  Needs a workspace with
+ * the adaptation buffers when bg or io is given.  diag (may be NULL)
+ * receives sph_diagnostics of the final state.  The results are those of
+ * the separate calls in that order.  On error the iterations before the
+ * failing one stay applied.  Synchronises. */
+int sph_step(sph_ctx *ctx, sph_particles *ps, sph_background *bg, const sph_particles *solids,
+             const sph_inout_params *io, int32_t nsteps, sph_diag *diag);
+int sph_set_iteration(sph_ctx *ctx, int64_t it);
+int64_t sph_iteration(const sph_ctx *ctx);
 
 /* Fluid reference mass from the background (section 3.3 and the algorithm of
  * section 3.4, item 4): m_ref,i = min of the background m_ref within
@@ -291,57 +338,77 @@ int sph_bg_update_solution(sph_ctx *ctx, sph_background *bg, const sph_particles
 int sph_inout(sph_ctx *ctx, sph_particles *ps, const sph_inout_params *io, sph_inout_map *map);
 
 /* ---- Serving pool: continuous batching of independent simulations ------
- * A pool owns nothing but host bookkeeping and a few streams; its device
- * memory is the caller's arena.  Each admitted simulation takes one block
- * of it (its state, a pair counter and a lean context workspace: the
- * simulation is stepped, never adapted).  sph_pool_step advances every
- * resident simulation by nsteps of its own dt with the step of sph_step
- * (neighbour list rebuilt at every evaluation), captured once per
- * simulation into a HIP graph and replayed; simulations are spread over the
- * pool's streams by resident particle count so that their graphs overlap
- * on the device.  Admission and retirement may happen between any two
- * steps.  Single-threaded use. */
+ * Beyond the paper, which runs one simulation at a time: many independent
+ * fluid-only simulations (periodic or open boxes, no boundary particles, no
+ * adaptation) resident on one GPU and advanced together.  A pool owns host
+ * bookkeeping, one stream and its graph; its device memory is the caller's
+ * arena.  The resident simulations share one set of structure-of-arrays
+ * buffers carved from the arena: each holds a contiguous range of particle
+ * slots and a range of the cell-table region (first fit; freed ranges
+ * coalesce).  sph_pool_step advances every resident simulation by one
+ * predict-evaluate-correct step of its own dt (eqs. int-pre, int-cor, the
+ * rates of section 2, the neighbour list rebuilt at every evaluation) with
+ * one launch per kernel for all of them: each launch's blocks are dealt to
+ * the simulations, and each block reads its simulation's descriptor (grid,
+ * dt, rho0, c_s, nu, alpha_e, body force, mass quantum).  The step of the
+ * resident set is captured into one HIP graph when the set changes and
+ * replayed.  FP64 and FP32 simulations are two groups in the same graph.
+ * A simulation's result is bit for bit that of sph_step on a context with
+ * lean = 1, list_skin = 0 and list_k = 64, alone or in any mix.
+ * Admission and retirement happen between steps.  Single-threaded use. */
 typedef struct sph_pool sph_pool;
 
 typedef struct sph_pool_stats {
-    int64_t bytes_total, bytes_used, largest_free;
-    int64_t resident;   /* simulations */
-    int64_t particles;  /* resident particles */
+    int64_t slots_total, slots_used, largest_free; /* particle slots */
+    int64_t tables_total, tables_used;             /* cell-table entries */
+    int64_t resident;      /* simulations */
+    int64_t particles;     /* resident particles */
+    int64_t max_resident;  /* simulations the pool can hold at once */
+    double last_step_ms;   /* device time per step of the last sph_pool_step */
 } sph_pool_stats;
 
-/* Arena bytes one simulation of n particles with this configuration needs. */
+/* Arena bytes one simulation of n particles with this configuration takes
+ * (its particle slots, cell tables and digit-histogram tile). */
 size_t sph_pool_footprint(const sph_config *cfg, int64_t n);
 
-/* arena: device memory (256-byte aligned) owned by the caller, outliving the
- * pool; nstreams in [1, 8].  Errors: SPH_E_INVAL, SPH_E_DEVICE. */
-int sph_pool_create(void *arena, size_t arena_bytes, int32_t nstreams, sph_pool **out);
+/* arena: device memory (256-byte aligned, at least 1 MiB) owned by the
+ * caller, outliving the pool; max_sims in [1, 1024] simulations resident at
+ * once.  About 1/16 of the arena holds cell tables and the rest particle
+ * slots of about 600 bytes each.  Errors: SPH_E_INVAL, SPH_E_NOMEM (arena
+ * too small for max_sims), SPH_E_DEVICE. */
+int sph_pool_create(void *arena, size_t arena_bytes, int32_t max_sims, sph_pool **out);
 void sph_pool_destroy(sph_pool *pool);
 const char *sph_pool_last_error(const sph_pool *pool);
 
-/* Admits a simulation whose initial state is `init` (device arrays, copied
- * before the call returns; x, y, u, v, p, rho, h, mq required, mref and
- * kind optional) with time step dt.  SPH_E_AGAIN (nothing changed) when no
- * free block of the arena holds sph_pool_footprint(cfg, init->n).  Writes
- * the simulation's id.  Waits for all work on the device before copying. */
+/* Admits a simulation whose initial state is `init` (device arrays x, y, u,
+ * v, p, rho, h, mq; kind must be NULL) with time step dt and the
+ * configuration's constants.  The copies are enqueued on the pool's stream
+ * after the work enqueued on `stream` (a hipStream_t, NULL = default) before
+ * the call; init's arrays must stay unchanged until the next sph_pool_step
+ * returns.  SPH_E_AGAIN (nothing changed) when no free range holds the
+ * particles or the cell tables, or max_sims are resident.  Writes the
+ * simulation's id. */
 int sph_pool_admit(sph_pool *pool, const sph_config *cfg, const sph_particles *init, double dt,
-                   int32_t *sim_id);
+                   void *stream, int32_t *sim_id);
 
-/* Advances every resident simulation by nsteps steps (eqs. int-pre and
- * int-cor, with the rates of section 2).  Returns when all are done. */
+/* Advances every resident simulation by nsteps steps.  Returns when they
+ * are done. */
 int sph_pool_step(sph_pool *pool, int32_t nsteps);
 
-/* Per simulation: the time from the start of the last sph_pool_step to the
- * end of its work (ms, device clock), steps taken, and interacting ordered
- * pairs evaluated so far (sum over evaluations of |N(i)| - 1).
- * Any pointer may be NULL. */
+/* Per simulation: the device time per step of the last sph_pool_step (every
+ * resident simulation advanced in it), steps taken, and interacting ordered
+ * pairs evaluated (sum over evaluations of |N(i)| - 1; for a retired
+ * simulation, the total at retirement).  Any pointer may be NULL. */
 int sph_pool_sim_stats(sph_pool *pool, int32_t sim_id, double *last_ms, int64_t *steps,
                        int64_t *pair_evals);
 
-/* Copies a simulation's state into dst (device arrays, capacity >= n).
- * Waits for all work on the device first, and for the copy. */
-int sph_pool_read(sph_pool *pool, int32_t sim_id, sph_particles *dst);
+/* Copies a simulation's state (x, y, u, v, p, rho, h, mq; NULL fields are
+ * skipped) into dst (device arrays, capacity >= n), on the pool's stream
+ * after the work enqueued on `stream` before the call; later work on
+ * `stream` sees the copies. */
+int sph_pool_read(sph_pool *pool, int32_t sim_id, sph_particles *dst, void *stream);
 
-/* Removes a simulation and returns its block to the arena. */
+/* Removes a simulation; later admissions reuse its ranges. */
 int sph_pool_retire(sph_pool *pool, int32_t sim_id);
 
 int sph_pool_info(sph_pool *pool, sph_pool_stats *out);

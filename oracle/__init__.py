@@ -342,10 +342,11 @@ def boundary(dom: Dom, prm: Prm, x, y, h, rho, kind, u, v, p, rp, col, aw=(0.0, 
     return u, v, p, ug, vg
 
 
-def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0), io=None):
+def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0), io=None, scales=True):
     """One evaluation with boundary particles (state needs 'kind' and 'rho',
     the stored density).  Returns the fields plus the state's u, v, p after
-    the boundary pass."""
+    the boundary pass, and the per-particle scales (rate_scales) unless
+    scales is False."""
     st = {k: _f64(state[k]).copy() for k in ("x", "y", "u", "v", "p", "h", "m", "rho")}
     kind = _i32(state["kind"])
     n = st["x"].size
@@ -356,12 +357,19 @@ def rates_k(dom: Dom, prm: Prm, state: dict, dt: float, aw=(0.0, 0.0), io=None):
                                  *[_p(st[k]) for k in ("x", "y", "u", "v", "p", "h", "m")],
                                  _p(kind), _p(st["rho"]), float(dt),
                                  *[_p(out[k]) for k in ("rho", "beta", "nnb", "pavg", "dxs",
-                                                        "dys", "dpdt", "dudt", "dvdt")], _p(sc))
+                                                        "dys", "dpdt", "dudt", "dvdt")],
+                                 _p(sc) if scales else None)
     if rc != 0:
         raise RuntimeError(f"oracle rates failed: {rc}")
     out["u_bc"], out["v_bc"], out["p_bc"] = st["u"], st["v"], st["p"]
-    out["scale"] = {k: sc[f * n:(f + 1) * n].copy() for f, k in enumerate(RATE_FIELDS)}
+    if scales:
+        out["scale"] = {k: sc[f * n:(f + 1) * n].copy() for f, k in enumerate(RATE_FIELDS)}
     return out
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's row loops."""
+    C.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
 
 
 def body_force(dom: Dom, prm: Prm, state: dict, aw=(0.0, 0.0), io=None):
@@ -623,6 +631,15 @@ def shepard_to_bg(dom: Dom, bx, by, bh, x, y, h, f, kind=None):
 def timestep(hmin, U, cs, nu):
     """eq. (timestep)."""
     return lib().or_timestep(float(hmin), float(U), float(cs), float(nu))
+
+
+def dt_for(state: dict) -> float:
+    """The time step of a workload: its explicit "dt" if it names one, else
+    eq. (timestep) from its smallest smoothing length and reference speed."""
+    if "dt" in state:
+        return float(state["dt"])
+    prm = state["params"]
+    return timestep(state["h_min"], state["u_ref"], prm["cs"], prm["nu"])
 
 
 def kinetic_energy(m, u, v):

@@ -48,7 +48,9 @@ class sph_config(C.Structure):
                 ("cr", C.c_double), ("ds_min", C.c_double), ("ds_max", C.c_double),
                 ("n_r", C.c_double), ("bg_smooth_iters", C.c_int32), ("bg_mass_q", C.c_double),
                 ("wall_accel", C.c_double * 2), ("list_k", C.c_int32), ("lean", C.c_int32),
-                ("list_skin", C.c_double), ("io_mode", C.c_int32), ("io_ref", C.c_double * 3)]
+                ("list_skin", C.c_double), ("io_mode", C.c_int32), ("io_ref", C.c_double * 3),
+                ("dt", C.c_double), ("sol_k", C.c_double), ("n_adapt", C.c_int32),
+                ("n_bg", C.c_int32), ("bg_passes", C.c_int32)]
 
 
 class sph_particles(C.Structure):
@@ -84,8 +86,10 @@ class sph_inout_map(C.Structure):
 
 
 class sph_pool_stats(C.Structure):
-    _fields_ = [("bytes_total", C.c_int64), ("bytes_used", C.c_int64), ("largest_free", C.c_int64),
-                ("resident", C.c_int64), ("particles", C.c_int64)]
+    _fields_ = [("slots_total", C.c_int64), ("slots_used", C.c_int64),
+                ("largest_free", C.c_int64), ("tables_total", C.c_int64),
+                ("tables_used", C.c_int64), ("resident", C.c_int64), ("particles", C.c_int64),
+                ("max_resident", C.c_int64), ("last_step_ms", C.c_double)]
 
 
 class sph_background(C.Structure):
@@ -101,7 +105,8 @@ class sph_diag(C.Structure):
 
 
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
-           "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_step", "sph_mref_lookup",
+           "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_pec", "sph_step",
+           "sph_timestep", "sph_set_iteration", "sph_iteration", "sph_mref_lookup",
            "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force", "sph_move_solids",
            "sph_export_bytes", "sph_export", "sph_import",
            "sph_profile_enable",
@@ -132,7 +137,11 @@ def load_library(path: str = LIB_PATH):
         "sph_set_stream": (C.c_int, [P, P]),
         "sph_build_neighbors": (C.c_int, [P, P, P]),
         "sph_rates": (C.c_int, [P, P, D, P]),
-        "sph_step": (C.c_int, [P, P, D, I32]),
+        "sph_pec": (C.c_int, [P, P, D, I32]),
+        "sph_step": (C.c_int, [P, P, P, P, P, I32, P]),
+        "sph_timestep": (D, [P, D]),
+        "sph_set_iteration": (C.c_int, [P, I64]),
+        "sph_iteration": (I64, [P]),
         "sph_mref_lookup": (C.c_int, [P, P, P]),
         "sph_adapt": (C.c_int, [P, P, P, P]),
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
@@ -153,10 +162,10 @@ def load_library(path: str = LIB_PATH):
         "sph_pool_create": (C.c_int, [P, C.c_size_t, I32, P]),
         "sph_pool_destroy": (None, [P]),
         "sph_pool_last_error": (C.c_char_p, [P]),
-        "sph_pool_admit": (C.c_int, [P, P, P, D, P]),
+        "sph_pool_admit": (C.c_int, [P, P, P, D, P, P]),
         "sph_pool_step": (C.c_int, [P, I32]),
         "sph_pool_sim_stats": (C.c_int, [P, I32, P, P, P]),
-        "sph_pool_read": (C.c_int, [P, I32, P]),
+        "sph_pool_read": (C.c_int, [P, I32, P, P]),
         "sph_pool_retire": (C.c_int, [P, I32]),
         "sph_pool_info": (C.c_int, [P, P]),
         "sph_rates_noalloc_bytes": (C.c_size_t, [P, I64]),
@@ -208,6 +217,11 @@ class Config:
     list_skin: float = 0.1
     io_mode: int = 0
     io_ref: tuple = (0.0, 0.0, 0.0)
+    dt: float = 0.0
+    sol_k: float = 0.0
+    n_adapt: int = 0
+    n_bg: int = 0
+    bg_passes: int = 1
 
     def c(self) -> sph_config:
         s = sph_config()
@@ -221,7 +235,7 @@ class Config:
         for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
                   "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
                   "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q", "list_k", "lean", "list_skin",
-                  "io_mode"):
+                  "io_mode", "dt", "sol_k", "n_adapt", "n_bg", "bg_passes"):
             setattr(s, k, getattr(self, k))
         return s
 
@@ -404,8 +418,42 @@ class Context:
         return {k: v[:n] for k, v in out.items()}
 
     def step(self, P: Particles, dt: float, nsteps: int = 1):
+        """nsteps plain PEC steps (sph_pec)."""
         ps = P.c()
-        self._check(self.lib.sph_step(self._h, C.byref(ps), float(dt), int(nsteps)))
+        self._check(self.lib.sph_pec(self._h, C.byref(ps), float(dt), int(nsteps)))
+
+    def run(self, P: Particles, nsteps: int, bg: "Background | None" = None,
+            solids: "Particles | None" = None, io: dict | None = None, diag: bool = False):
+        """nsteps iterations of the schedule of section 3.4 (sph_step): the
+        background update every cfg.n_bg and the adaptation every
+        cfg.n_adapt iterations, then the step (dt = cfg.dt, or eq. timestep)
+        and the inlet/outlet update when io is given.  Returns the
+        diagnostics of the final state when diag is set."""
+        ps = P.c()
+        bs = bg.c() if bg is not None else None
+        ss = solids.c() if solids is not None else None
+        prm = (sph_inout_params(float(io["x_in"]), float(io["len_in"]), float(io["x_out"]),
+                                float(io["len_out"])) if io is not None else None)
+        d = sph_diag()
+        rc = self.lib.sph_step(self._h, C.byref(ps), C.byref(bs) if bs is not None else None,
+                               C.byref(ss) if ss is not None else None,
+                               C.byref(prm) if prm is not None else None, int(nsteps),
+                               C.byref(d) if diag else None)
+        P.n = int(ps.n)
+        if bg is not None:
+            bg.n = int(bs.n)
+        self._check(rc)
+        if diag:
+            return {k: getattr(d, k) for k, _ in sph_diag._fields_}
+        return None
+
+    @property
+    def iteration(self) -> int:
+        return int(self.lib.sph_iteration(self._h))
+
+    @iteration.setter
+    def iteration(self, it: int):
+        self._check(self.lib.sph_set_iteration(self._h, int(it)))
 
     def mref_lookup(self, P: Particles, bg: Background):
         ps, bs = P.c(), bg.c()
@@ -558,43 +606,51 @@ class Context:
         return ms.value, cnt.value
 
 
-class Pool:
-    """Serving pool (sph_pool_*): independent simulations resident in one
-    device arena, stepped together; admission by footprint."""
+def footprint(cfg: Config, n: int) -> int:
+    """Arena bytes one simulation of n particles takes in a serving pool."""
+    return int(load_library().sph_pool_footprint(C.byref(cfg.c()), int(n)))
 
-    def __init__(self, arena_bytes: int, nstreams: int = 4, device="cuda"):
+
+class Pool:
+    """Serving pool (sph_pool_*): independent fluid-only simulations resident
+    in one device arena, advanced together by one batched step."""
+
+    def __init__(self, arena_bytes: int, max_sims: int = 256, device="cuda"):
         self.lib = load_library()
         self.device = torch.device(device)
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
-        rc = self.lib.sph_pool_create(_ptr(self.arena), int(arena_bytes), int(nstreams), C.byref(h))
+        rc = self.lib.sph_pool_create(_ptr(self.arena), int(arena_bytes), int(max_sims), C.byref(h))
         if rc != SPH_OK:
             raise SphError(rc, "pool creation failed")
         self._h = h
+        self._inputs = []   # initial states read by copies not yet known to be done
 
     def _check(self, rc):
         if rc != SPH_OK:
             raise SphError(rc, self.lib.sph_pool_last_error(self._h).decode())
 
     def footprint(self, cfg: Config, n: int) -> int:
-        c = cfg.c()
-        return int(self.lib.sph_pool_footprint(C.byref(c), int(n)))
+        return footprint(cfg, n)
 
-    def admit(self, cfg: Config, P: Particles, dt: float, with_kind: bool = False):
+    def admit(self, cfg: Config, P: Particles, dt: float):
         """Returns the simulation id, or None when the arena has no room."""
         c = cfg.c()
         ps = P.c()
-        if not with_kind:
-            ps.kind = None
+        ps.kind = None
         sid = C.c_int32(-1)
-        rc = self.lib.sph_pool_admit(self._h, C.byref(c), C.byref(ps), float(dt), C.byref(sid))
+        st = torch.cuda.current_stream(self.device)
+        rc = self.lib.sph_pool_admit(self._h, C.byref(c), C.byref(ps), float(dt),
+                                     C.c_void_p(st.cuda_stream), C.byref(sid))
         if rc == SPH_E_AGAIN:
             return None
         self._check(rc)
+        self._inputs.append(P)   # kept alive until the next step has copied it
         return int(sid.value)
 
     def step(self, nsteps: int = 1):
         self._check(self.lib.sph_pool_step(self._h, int(nsteps)))
+        self._inputs.clear()
 
     def stats(self, sim_id: int, pairs: bool = False) -> dict:
         ms, st, pe = C.c_double(0), C.c_int64(0), C.c_int64(0)
@@ -607,7 +663,9 @@ class Pool:
 
     def read(self, sim_id: int, P: Particles):
         ps = P.c()
-        self._check(self.lib.sph_pool_read(self._h, int(sim_id), C.byref(ps)))
+        ps.mref, ps.kind = None, None
+        st = torch.cuda.current_stream(self.device)
+        self._check(self.lib.sph_pool_read(self._h, int(sim_id), C.byref(ps), C.c_void_p(st.cuda_stream)))
         P.n = int(ps.n)
         return P
 
@@ -629,6 +687,12 @@ class Pool:
             self.close()
         except Exception:
             pass
+
+
+def timestep(cfg: Config, h_min: float = 0.0) -> float:
+    """eq. (timestep) for the configuration (sph_timestep); h_min <= 0 takes
+    cfg.h_lo."""
+    return float(load_library().sph_timestep(C.byref(cfg.c()), float(h_min)))
 
 
 def config_for(domain, params: dict, h_lo: float, h_hi: float, precision=SPH_FP64,

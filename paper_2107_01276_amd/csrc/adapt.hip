@@ -1561,3 +1561,61 @@ int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const s
     }
     return rc;
 }
+
+// ---------------------------------------------------------------------------
+// The per-iteration schedule of section 3.4.  Before iteration it > 0: the
+// background update every n_bg iterations, then the adaptation every n_adapt
+// iterations (its m_ref lookup sees the updated background); then one step,
+// with the inlet/outlet update when zones are given.  The iterations between
+// two updates go to the step runs in one call (enqueued at once, one host
+// round trip per run), so the results are those of the separate calls.
+// ---------------------------------------------------------------------------
+int schedule_run(sph_ctx* c, sph_particles* ps, sph_background* bg, const sph_particles* solids,
+                 const sph_inout_params* io, int nsteps, sph_diag* diag)
+{
+    const sph_config& cf = c->cfg;
+    Work& w = c->w;
+    const double dt = cf.dt > 0 ? cf.dt : timestep_of(cf, 0.0);
+    int done = 0;
+    while (done < nsteps) {
+        const int64_t it = c->iter;
+        if (it > 0 && bg) {
+            if (cf.n_bg > 0 && it % cf.n_bg == 0) {
+                int64_t nsplit = 0;
+                const int rc = cf.sol_k > 0
+                                   ? bg_solution_run(c, bg, solids, ps, cf.sol_k, cf.bg_passes, &nsplit,
+                                                     nullptr)
+                                   : bg_update_run(c, bg, solids, nullptr, 0.0, cf.bg_passes, &nsplit);
+                if (rc) return rc;
+            }
+            if (cf.n_adapt > 0 && it % cf.n_adapt == 0) {
+                sph_adapt_map m{w.sched_origin, w.sched_sat, 0, 0, {0, 0, 0, 0, 0, 0, 0, 0}};
+                const int rc = adapt_run(c, ps, bg, &m);
+                if (rc) return rc;
+            }
+        }
+        // iterations up to the next update
+        int64_t k = nsteps - done;
+        auto upto = [&](int32_t per) {
+            if (per <= 0) return;
+            const int64_t nx = (it / per + 1) * per;
+            if (nx - it < k) k = nx - it;
+        };
+        if (bg) {
+            upto(cf.n_adapt);
+            upto(cf.n_bg);
+        }
+        int rc;
+        if (io) {
+            sph_inout_map m{w.sched_origin, 0, 0, 0, 0};
+            rc = step_inout_run(c, ps, dt, (int)k, io, &m);
+        } else {
+            rc = step_run(c, ps, dt, (int)k);
+        }
+        if (rc) return rc;
+        c->iter += k;
+        done += (int)k;
+    }
+    if (diag) return diag_run(c, ps, diag);
+    return SPH_OK;
+}

@@ -106,6 +106,8 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     w->pa = (double4*)take(32 * C);
     w->puv = (double2*)take(16 * C);
     w->pf = take(32 * C);
+    w->sched_origin = lean ? nullptr : (int64_t*)take(8 * C);
+    w->sched_sat = lean ? nullptr : (int32_t*)take(4 * C);
     return off + 256;
 }
 
@@ -125,7 +127,28 @@ static int check_cfg(const sph_config* cfg)
     for (int a = 0; a < 3; ++a)
         if (!isfinite(cfg->io_ref[a])) return 0;
     if (cfg->io_mode == 1 && !(cfg->cs > 0)) return 0;
+    if (!(cfg->dt >= 0.0) || !isfinite(cfg->dt) || !(cfg->sol_k >= 0.0) || !isfinite(cfg->sol_k))
+        return 0;
+    if (cfg->n_adapt < 0 || cfg->n_bg < 0 || cfg->bg_passes < 0) return 0;
     return 1;
+}
+
+// eq. (timestep)
+double timestep_of(const sph_config& cfg, double h_min)
+{
+    const double h = h_min > 0 ? h_min : cfg.h_lo;
+    double dt = 0.25 * h / (cfg.u_ref + cfg.cs);
+    if (cfg.nu > 0) {
+        const double dv = 0.125 * h * h / cfg.nu;
+        if (dv < dt) dt = dv;
+    }
+    return dt;
+}
+
+extern "C" double sph_timestep(const sph_config* cfg, double h_min)
+{
+    if (!check_cfg(cfg) || !(cfg->u_ref + cfg->cs > 0)) return 0.0;
+    return timestep_of(*cfg, h_min);
 }
 
 extern "C" int sph_version(void) { return SPH_VERSION; }
@@ -294,6 +317,8 @@ extern "C" int sph_set_stream(sph_ctx* c, void* stream)
     return SPH_OK;
 }
 
+static bool check_bg(sph_ctx* c, const sph_background* bg);
+
 static int check_ps(sph_ctx* c, const sph_particles* ps, int need_state)
 {
     if (!ps) { set_err(c, "particles is NULL"); return 0; }
@@ -334,7 +359,50 @@ extern "C" int sph_rates(sph_ctx* c, const sph_particles* ps, double dt, sph_rat
     return rates_eval(c, (int)ps->n, ps, dt, out);
 }
 
-extern "C" int sph_step(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps)
+extern "C" int sph_set_iteration(sph_ctx* c, int64_t it)
+{
+    if (!c || it < 0) return SPH_E_INVAL;
+    c->iter = it;
+    return SPH_OK;
+}
+
+extern "C" int64_t sph_iteration(const sph_ctx* c) { return c ? c->iter : -1; }
+
+extern "C" int sph_step(sph_ctx* c, sph_particles* ps, sph_background* bg, const sph_particles* solids,
+                        const sph_inout_params* io, int32_t nsteps, sph_diag* diag)
+{
+    if (!c) return SPH_E_INVAL;
+    if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
+    if (nsteps < 0) { set_err(c, "nsteps >= 0"); return SPH_E_INVAL; }
+    if ((bg || io) && c->cfg.lean) {
+        set_err(c, "the schedule with a background or inlet/outlet zones needs the adaptation buffers");
+        return SPH_E_INVAL;
+    }
+    if (bg && (!check_bg(c, bg) || !ps->mref)) {
+        set_err(c, "adaptation needs mref and a background within the context capacity");
+        return SPH_E_INVAL;
+    }
+    if (bg && c->cfg.n_bg > 0 && !solids) {
+        set_err(c, "a background update every n_bg iterations needs the solids");
+        return SPH_E_INVAL;
+    }
+    if (io) {
+        if (!ps->kind || !ps->mref) { set_err(c, "inlet/outlet zones need kind and mref"); return SPH_E_INVAL; }
+        if (!isfinite(io->x_in) || !isfinite(io->x_out) || !(io->len_in >= 0) || !(io->len_out >= 0) ||
+            !isfinite(io->len_in) || !isfinite(io->len_out)) {
+            set_err(c, "inout zones must be finite with non-negative lengths");
+            return SPH_E_INVAL;
+        }
+    }
+    if (!(c->cfg.dt > 0) && !(timestep_of(c->cfg, 0.0) > 0)) {
+        set_err(c, "no time step: set dt, or h_lo, u_ref + c_s > 0");
+        return SPH_E_INVAL;
+    }
+    c->fused_x = nullptr;  // positions may have changed since the last call
+    return schedule_run(c, ps, bg, solids, io, nsteps, diag);
+}
+
+extern "C" int sph_pec(sph_ctx* c, sph_particles* ps, double dt, int32_t nsteps)
 {
     if (!c) return SPH_E_INVAL;
     if (!check_ps(c, ps, 1) || !ps->rho) return SPH_E_INVAL;
@@ -493,6 +561,8 @@ extern "C" int sph_import(sph_ctx* c, sph_particles* ps, const void* host_buf, s
     ps->n = n;
     if (step) memcpy(step, b + 32, 8);
     if (time) memcpy(time, b + 40, 8);
+    memcpy(&c->iter, b + 32, 8);
+    if (c->iter < 0) c->iter = 0;
     c->list_valid = 0;  // a new state: no reusable list
     c->fused_x = nullptr;
     return SPH_OK;

@@ -90,6 +90,8 @@ static int key_bits(const Grid* g)
     return 2 * g->bits + lb;
 }
 
+int batch_key_bits(const Grid* g) { return key_bits(g); }
+
 
 size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g)
 {
@@ -161,19 +163,26 @@ __global__ void k_scan_add(T* out, int64_t n_out, const T* boff)
 // Exclusive scan of in[0, n_in) into out[0, n_out) (n_out >= n_in; entries
 // past n_in scan zeros).  tmp needs about 2 * n_out / SCAN_TILE + 64 entries.
 template <typename T>
-static int scan_rec(sph_ctx* c, const T* in, T* out, int64_t n_in, int64_t n_out, T* tmp)
+static hipError_t scan_rec_s(hipStream_t st, const T* in, T* out, int64_t n_in, int64_t n_out,
+                             T* tmp)
 {
     int64_t nb = cdiv(n_out, SCAN_TILE);
-    hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, c->stream, in, out,
-                       n_in, n_out, tmp);
-    LAUNCHCHK(c, "scan_block");
-    if (nb > 1) {
-        int rc = scan_rec<T>(c, tmp, tmp, nb, nb, tmp + nb);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)cdiv(n_out, 256)), dim3(256), 0, c->stream,
-                           out, n_out, tmp);
-        LAUNCHCHK(c, "scan_add");
-    }
+    hipLaunchKernelGGL(k_scan_block<T>, dim3((unsigned)nb), dim3(SCAN_T), 0, st, in, out, n_in,
+                       n_out, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nb <= 1) return e;
+    e = scan_rec_s<T>(st, tmp, tmp, nb, nb, tmp + nb);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)cdiv(n_out, 256)), dim3(256), 0, st, out,
+                       n_out, tmp);
+    return hipGetLastError();
+}
+
+template <typename T>
+static int scan_rec(sph_ctx* c, const T* in, T* out, int64_t n_in, int64_t n_out, T* tmp)
+{
+    const hipError_t e = scan_rec_s<T>(c->stream, in, out, n_in, n_out, tmp);
+    if (e != hipSuccess) return check_hip(c, e, "scan");
     return SPH_OK;
 }
 
@@ -191,11 +200,14 @@ int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n)
 // Keys
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __restrict__ x,
-                                              const double* __restrict__ y,
-                                              const double* __restrict__ h, uint64_t* keys,
-                                              int32_t* vals, unsigned long long* hmax_bits,
-                                              int32_t* lcount)
+// Key and slot of particle i (when valid), and the block's per-level maxima
+// of h and counts; every thread of the block calls it.
+__device__ __forceinline__ void keys_body(const Grid& g, bool valid, int i,
+                                          const double* __restrict__ x,
+                                          const double* __restrict__ y,
+                                          const double* __restrict__ h, uint64_t* keys,
+                                          int32_t* vals, unsigned long long* hmax_bits,
+                                          int32_t* lcount)
 {
     __shared__ unsigned long long s_h[SPH_MAXL];
     __shared__ int32_t s_c[SPH_MAXL];
@@ -204,8 +216,7 @@ __global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __res
         s_c[threadIdx.x] = 0;
     }
     __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
+    if (valid) {
         double hi = h[i];
         int l = level_of(g, hi);
         uint32_t kx = (uint32_t)cell0(g, 0, x[i]);
@@ -220,6 +231,16 @@ __global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __res
         atomicMax(&hmax_bits[threadIdx.x], s_h[threadIdx.x]);
         atomicAdd(&lcount[threadIdx.x], s_c[threadIdx.x]);
     }
+}
+
+__global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              const double* __restrict__ h, uint64_t* keys,
+                                              int32_t* vals, unsigned long long* hmax_bits,
+                                              int32_t* lcount)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    keys_body(g, i < n, i, x, y, h, keys, vals, hmax_bits, lcount);
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n)
@@ -248,29 +269,39 @@ __global__ void k_zero_build(int2* tab, int64_t ntab, unsigned long long* hmax, 
 // equal digits is the input order.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int n,
-                                                        int shift, uint32_t* hist, int nblk)
+// Digit counts of one tile: keys [base, base + tn) of the tile; hist gets
+// the count of digit d at hist[d * hstride].
+__device__ __forceinline__ void rs_hist_tile(const uint64_t* __restrict__ keys, int64_t base, int tn,
+                                             int shift, uint32_t* hist, int64_t hstride)
 {
     __shared__ uint32_t h[RS_BINS];
     for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) h[d] = 0;
     __syncthreads();
-    const int base = blockIdx.x * RS_TILE;
 #pragma unroll
     for (int k = 0; k < RS_ITEMS; ++k) {
-        int i = base + k * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (RS_BINS - 1u)], 1u);
+        const int i = k * RS_THREADS + threadIdx.x;
+        if (i < tn) atomicAdd(&h[(keys[base + i] >> shift) & (RS_BINS - 1u)], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * nblk + blockIdx.x] = h[d];
+    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * hstride] = h[d];
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                           const int32_t* __restrict__ vin,
-                                                           uint64_t* __restrict__ kout,
-                                                           int32_t* __restrict__ vout, int n,
-                                                           int shift,
-                                                           const uint32_t* __restrict__ offs,
-                                                           int nblk)
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int n,
+                                                        int shift, uint32_t* hist, int nblk)
+{
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int tn = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+    rs_hist_tile(keys, base, tn, shift, hist + blockIdx.x, nblk);
+}
+
+// Scatter of one tile: keys [base, base + tn); digit d of the tile starts
+// at offs[d * ostride] + padj of the output.
+__device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin,
+                                                const int32_t* __restrict__ vin,
+                                                uint64_t* __restrict__ kout,
+                                                int32_t* __restrict__ vout, int64_t base, int tn,
+                                                int shift, const uint32_t* __restrict__ offs,
+                                                int64_t ostride, int64_t padj)
 {
     constexpr int NW = RS_THREADS / 64;
     __shared__ uint32_t wcnt[NW][RS_BINS];
@@ -278,14 +309,15 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
     for (int d = threadIdx.x; d < NW * RS_BINS; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
     __syncthreads();
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int wbase = blockIdx.x * RS_TILE + w * (64 * RS_ITEMS);
+    const int wbase = w * (64 * RS_ITEMS);
     uint64_t kk[RS_ITEMS];
     int32_t vv[RS_ITEMS];
     uint32_t dd[RS_ITEMS], rk[RS_ITEMS];
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
-        int i = wbase + it * 64 + lane;
-        bool valid = i < n;
+        const int il = wbase + it * 64 + lane;
+        const bool valid = il < tn;
+        const int64_t i = base + il;
         uint64_t k = valid ? kin[i] : 0ull;
         uint32_t d = (uint32_t)(k >> shift) & (RS_BINS - 1u);
         uint64_t mask = __ballot(valid);
@@ -323,11 +355,24 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __res
     for (int it = 0; it < RS_ITEMS; ++it) {
         uint32_t d = dd[it];
         if (d < (uint32_t)RS_BINS) {
-            uint32_t pos = offs[(int64_t)d * nblk + blockIdx.x] + wcnt[w][d] + rk[it];
+            const int64_t pos = (int64_t)offs[(int64_t)d * ostride] + padj + wcnt[w][d] + rk[it];
             kout[pos] = kk[it];
             vout[pos] = vv[it];
         }
     }
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                           const int32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout,
+                                                           int32_t* __restrict__ vout, int n,
+                                                           int shift,
+                                                           const uint32_t* __restrict__ offs,
+                                                           int nblk)
+{
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const int tn = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+    rs_scatter_tile(kin, vin, kout, vout, base, tn, shift, offs + blockIdx.x, nblk, 0);
 }
 
 // Sorts (keys, vals) of length n; the result ends in (keys_a, vals_a).
@@ -367,30 +412,34 @@ static int radix_sort(sph_ctx* c, int n, int keybits)
 // one level share a Q-cell iff their curve indices agree above bit 2Q.  The
 // cell's coordinates come from the particle's position, which is copied to
 // the sorted shadows (xs, ys, hs and the packed xyh) on the way.
-__global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* __restrict__ keys,
-                                                const int32_t* __restrict__ perm,
-                                                const double* __restrict__ x,
-                                                const double* __restrict__ y,
-                                                const double* __restrict__ h, double* xs,
-                                                double* ys, double* hs, double4* xyh, int2* tab)
+// Sorted particle s of the segment [lo, hi) (its simulation's particles):
+// run boundaries into tab (the simulation's tables), shadows (xs, ys, hs may
+// be NULL).
+__device__ __forceinline__ void tables_body(const Grid& g, int s, int lo, int hi,
+                                            const uint64_t* __restrict__ keys,
+                                            const int32_t* __restrict__ perm,
+                                            const double* __restrict__ x,
+                                            const double* __restrict__ y,
+                                            const double* __restrict__ h, double* xs, double* ys,
+                                            double* hs, double4* xyh, int2* tab)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n) return;
     const int i = perm[s];
-    const double xi = x[i], yi = y[i], hi = h[i];
-    xs[s] = xi;
-    ys[s] = yi;
-    hs[s] = hi;
-    xyh[s] = make_double4(xi, yi, hi, 0.0);
+    const double xi = x[i], yi = y[i], hi_ = h[i];
+    if (xs) {
+        xs[s] = xi;
+        ys[s] = yi;
+        hs[s] = hi_;
+    }
+    xyh[s] = make_double4(xi, yi, hi_, 0.0);
     const int sh = 2 * g.bits;
     const uint64_t mmask = (sh >= 64) ? ~0ull : ((1ull << sh) - 1ull);
     uint64_t key = keys[s];
     int l = (int)(key >> sh);
     uint64_t m = key & mmask;
-    uint64_t kp = s > 0 ? keys[s - 1] : ~0ull;
-    uint64_t kn = s < n - 1 ? keys[s + 1] : ~0ull;
-    bool lp = s > 0 && (int)(kp >> sh) == l;
-    bool ln = s < n - 1 && (int)(kn >> sh) == l;
+    uint64_t kp = s > lo ? keys[s - 1] : ~0ull;
+    uint64_t kn = s < hi - 1 ? keys[s + 1] : ~0ull;
+    bool lp = s > lo && (int)(kp >> sh) == l;
+    bool ln = s < hi - 1 && (int)(kn >> sh) == l;
     const int kx0 = cell0(g, 0, xi), ky0 = cell0(g, 1, yi);
     for (int Q = l; Q < g.nlev; ++Q) {
         uint64_t cell = m >> (2 * Q);
@@ -402,6 +451,18 @@ __global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* _
         if (!sp) tab[idx].x = s;
         if (!sn) tab[idx].y = s + 1;
     }
+}
+
+__global__ __launch_bounds__(256) void k_tables(Grid g, int n, const uint64_t* __restrict__ keys,
+                                                const int32_t* __restrict__ perm,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ y,
+                                                const double* __restrict__ h, double* xs,
+                                                double* ys, double* hs, double4* xyh, int2* tab)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    tables_body(g, s, 0, n, keys, perm, x, y, h, xs, ys, hs, xyh, tab);
 }
 
 int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double* h)
@@ -458,12 +519,9 @@ NbrView nbr_view(sph_ctx* c)
 // Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate); LG lanes
 // per row walk the cells together.
 #define LG 4
-__global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int n, NbrList nl,
-                                                         double sf)
+__device__ __forceinline__ void build_list_body(const Grid& g, const NbrView& nv, const NbrList& nl,
+                                                int s, int gl, double sf)
 {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int s = t / LG, gl = t % LG;
-    if (s >= n) return;
     const double4 a = nv.xyh[s];
     const int li = key_level(g, nv.keys[s]);
     int cnt = 0;
@@ -480,6 +538,15 @@ __global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int
         nl.cnt[s] = cnt;
         if (cnt > nl.K) nl.flag[0] = 1;
     }
+}
+
+__global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int n, NbrList nl,
+                                                         double sf)
+{
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int s = t / LG, gl = t % LG;
+    if (s >= n) return;
+    build_list_body(g, nv, nl, s, gl, sf);
 }
 
 int nbr_build_list(sph_ctx* c, int n, double skin)
@@ -697,5 +764,121 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     hipLaunchKernelGGL(k_sort_long_rows, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream,
                        row_ptr, col, w.long_rows, w.status);
     LAUNCHCHK(c, "csr_fill");
+    return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched neighbour build: keys, segmented radix sort, cell tables and the
+// rate-pass list of every simulation of a batch, one launch per kernel.  The
+// digit histogram is laid out simulation by simulation ([simulation][digit]
+// [tile]), so one exclusive scan over it gives, for every simulation, the
+// packed prefix of the simulations before it plus its own digit offsets:
+// the same result as sorting the batch by (simulation, key) with the
+// simulation as the most significant digit, without sorting that digit.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_keys_b(Batch B, const double* __restrict__ x,
+                                                const double* __restrict__ y,
+                                                const double* __restrict__ h, uint64_t* keys,
+                                                int32_t* vals, unsigned long long* hmax,
+                                                int32_t* lcount)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    keys_body(sd.g, il < sd.n, (int)(sd.off + il), x, y, h, keys, vals, hmax + sid * SPH_MAXL,
+              lcount + sid * SPH_MAXL);
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist_b(Batch B, const uint64_t* __restrict__ keys,
+                                                          int shift, uint32_t* hist)
+{
+    int t;
+    const int sid = batch_find(B, BM_TILE, blockIdx.x, &t);
+    const SimDesc* d = B.sims + sid;
+    const int64_t rem = d->n - (int64_t)t * RS_TILE;
+    const int tn = (int)(rem < RS_TILE ? rem : RS_TILE);
+    rs_hist_tile(keys, d->off + (int64_t)t * RS_TILE, tn, shift, hist + d->hoff + t, d->ntile);
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter_b(Batch B, const uint64_t* __restrict__ kin,
+                                                             const int32_t* __restrict__ vin,
+                                                             uint64_t* __restrict__ kout,
+                                                             int32_t* __restrict__ vout, int shift,
+                                                             const uint32_t* __restrict__ offs)
+{
+    int t;
+    const int sid = batch_find(B, BM_TILE, blockIdx.x, &t);
+    const SimDesc* d = B.sims + sid;
+    const int64_t rem = d->n - (int64_t)t * RS_TILE;
+    const int tn = (int)(rem < RS_TILE ? rem : RS_TILE);
+    rs_scatter_tile(kin, vin, kout, vout, d->off + (int64_t)t * RS_TILE, tn, shift,
+                    offs + d->hoff + t, d->ntile, d->off - d->packed);
+}
+
+__global__ __launch_bounds__(256) void k_tables_b(Batch B, const uint64_t* __restrict__ keys,
+                                                  const int32_t* __restrict__ perm,
+                                                  const double* __restrict__ x,
+                                                  const double* __restrict__ y,
+                                                  const double* __restrict__ h, double4* xyh,
+                                                  int2* tab)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= sd.n) return;
+    tables_body(sd.g, (int)(sd.off + il), (int)sd.off, (int)(sd.off + sd.n), keys, perm, x, y, h,
+                nullptr, nullptr, nullptr, xyh, tab + sd.toff);
+}
+
+__global__ __launch_bounds__(256) void k_build_list_b(Batch B, NbrView nv0, NbrList nl, double sf)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P64, xcd_block(blockIdx.x, gridDim.x), &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int t = lb * 256 + threadIdx.x;
+    const int sl = t / LG, gl = t % LG;
+    if (sl >= sd.n) return;
+    build_list_body(sd.g, batch_view(nv0, sd, sid), nl, (int)(sd.off + sl), gl, sf);
+}
+
+int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const double* x,
+                const double* y, const double* h, const uint64_t** keys, const int32_t** perm)
+{
+    const int nsim = L.B.nsim;
+    const int64_t nl = (int64_t)nsim * SPH_MAXL;
+    const int64_t nz = L.tab_n > nl ? L.tab_n : nl;
+    hipLaunchKernelGGL(k_zero_build, dim3((unsigned)cdiv(nz, 256)), dim3(256), 0, st, b.tab, L.tab_n,
+                       b.hmax, b.lcount, (int)nl);
+    hipLaunchKernelGGL(k_keys_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B, x, y, h,
+                       b.keys_a, b.vals_a, b.hmax, b.lcount);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return SPH_E_DEVICE;
+    uint64_t *ka = b.keys_a, *kb = b.keys_b;
+    int32_t *va = b.vals_a, *vb = b.vals_b;
+    for (int p = 0; p < L.npass; ++p) {
+        const int shift = RS_BITS * p;
+        hipLaunchKernelGGL(k_rs_hist_b, dim3((unsigned)L.nblk[BM_TILE]), dim3(RS_THREADS), 0, st, L.B,
+                           (const uint64_t*)ka, shift, b.hist);
+        e = scan_rec_s<uint32_t>(st, b.hist, b.hist, L.hist_n, L.hist_n, b.scan_tmp);
+        if (e != hipSuccess) return SPH_E_DEVICE;
+        hipLaunchKernelGGL(k_rs_scatter_b, dim3((unsigned)L.nblk[BM_TILE]), dim3(RS_THREADS), 0, st,
+                           L.B, (const uint64_t*)ka, (const int32_t*)va, kb, vb, shift,
+                           (const uint32_t*)b.hist);
+        uint64_t* tk = ka; ka = kb; kb = tk;
+        int32_t* tv = va; va = vb; vb = tv;
+    }
+    hipLaunchKernelGGL(k_tables_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
+                       (const uint64_t*)ka, (const int32_t*)va, x, y, h, b.xyh, b.tab);
+    const NbrView nv{nullptr, nullptr, nullptr, b.xyh, va, ka, b.tab, b.hmax, b.lcount};
+    const NbrList nlst{b.nl_idx, b.nl_cnt, b.nl_k, (int)b.stride, b.list_flag};
+    hipLaunchKernelGGL(k_build_list_b, dim3((unsigned)L.nblk[BM_P64]), dim3(256), 0, st, L.B, nv,
+                       nlst, 1.0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return SPH_E_DEVICE;
+    *keys = ka;
+    *perm = va;
     return SPH_OK;
 }

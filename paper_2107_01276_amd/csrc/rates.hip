@@ -165,6 +165,31 @@ __global__ __launch_bounds__(256) void k_gather_state(int n, const int32_t* __re
     }
 }
 
+// Batched gather (fluid only): the packed records and masses of every
+// simulation of a batch, in sorted order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_state_b(Batch B, const int32_t* __restrict__ perm,
+                                                        const double* __restrict__ x,
+                                                        const double* __restrict__ y,
+                                                        const double* __restrict__ h,
+                                                        const double* __restrict__ u,
+                                                        const double* __restrict__ v,
+                                                        const double* __restrict__ p,
+                                                        const int64_t* __restrict__ mq,
+                                                        double4* pa, double2* puv, T* ms)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc* d = B.sims + sid;
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= d->n) return;
+    const int s = (int)(d->off + il);
+    const int i = perm[s];
+    pa[s] = make_double4(x[i], y[i], h[i], p[i]);
+    puv[s] = make_double2(u[i], v[i]);
+    ms[s] = (T)((double)mq[i] * d->mass_q);
+}
+
 // Inlet/outlet rule of the boundary pass: mode, reference state, rho0 c.
 struct IoRule {
     int mode;
@@ -256,7 +281,7 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
             srx += rho[f] * dx * w;
             sry += rho[f] * dy * w;
         };
-        const int cnt = nl.cnt[s];
+        const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
         if (cnt <= nl.K) {
             const double rb3 = 3.0 * hb, rb2 = rb3 * rb3;
             for (int k = lane; k < cnt; k += 64) {
@@ -333,20 +358,22 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
 
 // When ex.idx is set, pass A also writes the exact neighbours of each row
 // (self excluded), column-major with K columns, for pass B; a row with more
-// gets count K + 1 and pass B uses the skin list for it.
-#define PASS_A_PARAMS(T)                                                                     \
-    Grid g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,   \
+// gets count K + 1 and pass B uses the skin list (or the cell walk) for it.
+// Without a list (nl.idx NULL) pass A walks the cells.
+// GT: Grid for a kernel's parameter list, const Grid& for the body (a
+// by-value Grid in a device function with indexed tables goes to scratch)
+#define PASS_A_PARAMS_(GT, T)                                                                \
+    GT g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,     \
         typename Vec4<T>::type *pf, double rho0, PassAOut out, double *r_dxs, double *r_dys,  \
         const int32_t *__restrict__ kind, NbrList ex, Guard gd
+#define PASS_A_PARAMS(T) PASS_A_PARAMS_(Grid, T)
 #define PASS_A_ARGS g, nv, n, b, nl, pa, pf, rho0, out, r_dxs, r_dys, kind, ex, gd
 
+// Sorted particle s, lane gl of its group of RGA lanes (all lanes of the
+// group call it together).
 template <typename T>
-__device__ __forceinline__ void pass_a_body(PASS_A_PARAMS(T))
+__device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int s, int gl)
 {
-    if (guard_stop(gd)) return;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int s = t / RGA, gl = t % RGA;
-    if (s >= n) return;
     const double4 ai = pa[s];
     const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
     const int li = key_level(g, nv.keys[s]);
@@ -381,8 +408,8 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS(T))
         sx.add(t * (T)dx);
         sy.add(t * (T)dy);
     };
-    const int cnt = nl.cnt[s];
-    int32_t* exo = (ex.idx && cnt <= nl.K) ? ex.idx : nullptr;
+    const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
+    int32_t* const exo = ex.idx;
     int ne = 0;  // exact entries of the row (the same in every lane of the group)
     // called by all lanes of the group together; `pass` marks a neighbour
     auto body = [&](int js, bool pass, double dx, double dy, double r2, double hj, double pj)
@@ -421,15 +448,13 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS(T))
                 body(j[u], pass, dx, dy, r2, a[u].z, a[u].w);
             }
         }
-        if (exo && gl == 0) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     } else {
-        if (ex.idx && gl == 0) ex.cnt[s] = ex.K + 1;
-        exo = nullptr;
         group_walk<RGA>(g, nv, xi, yi, hi, li, gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
                            body(js, pass, dx, dy, r2, hj, pass ? pa[js].w : 0.0);
                        });
     }
+    if (exo && gl == 0) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     // the group's partial sums, combined in every lane
 #pragma unroll
     for (int o = 1; o < RGA; o <<= 1) {
@@ -485,21 +510,58 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS(T))
     if (out.dys) out.dys[slot] = (double)ddy;
 }
 
+#define PASS_A_SINGLE(T)                                                                     \
+    if (guard_stop(gd)) return;                                                              \
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;               \
+    const int s = t / RGA, gl = t % RGA;                                                     \
+    if (s >= n) return;                                                                      \
+    pass_a_body<T>(PASS_A_ARGS, s, gl);
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(PASS_A_PARAMS(T))
 {
-    pass_a_body<T>(PASS_A_ARGS);
+    PASS_A_SINGLE(T)
 }
 // FP32: more waves per SIMD than the compiler picks (latency-bound gathers)
 template <>
 __global__ __launch_bounds__(256) PA_ATTR void k_pass_a<float>(PASS_A_PARAMS(float))
 {
-    pass_a_body<float>(PASS_A_ARGS);
+    PASS_A_SINGLE(float)
 }
 template <>
 __global__ __launch_bounds__(256) PA64_ATTR void k_pass_a<double>(PASS_A_PARAMS(double))
 {
-    pass_a_body<double>(PASS_A_ARGS);
+    PASS_A_SINGLE(double)
+}
+
+// Batched pass A: every simulation of a batch (fluid only, no exact rows),
+// its grid, tables and rho0 from its descriptor.
+#define PASS_A_BATCH(T)                                                                      \
+    int lb;                                                                                  \
+    const int sid = batch_find(B, BM_P64, xcd_block(blockIdx.x, gridDim.x), &lb);            \
+    const SimDesc& sd = batch_desc(B, sid);                                                  \
+    const int t = lb * 256 + threadIdx.x;                                                    \
+    const int sl = t / RGA, gl = t % RGA;                                                    \
+    if (sl >= sd.n) return;                                                                  \
+    const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
+    const Guard gd{nullptr, 0};                                                              \
+    pass_a_body<T>(sd.g, batch_view(nv, sd, sid), 0, b, nl, pa, pf, sd.rho0, out, r_dxs,     \
+                   r_dys, nullptr, ex, gd, (int)(sd.off + sl), gl);
+
+#define PASS_A_BATCH_PARAMS(T)                                                               \
+    Batch B, NbrView nv, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,          \
+        typename Vec4<T>::type *pf, PassAOut out, double *r_dxs, double *r_dys
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass_a_b(PASS_A_BATCH_PARAMS(T));
+template <>
+__global__ __launch_bounds__(256) PA_ATTR void k_pass_a_b<float>(PASS_A_BATCH_PARAMS(float))
+{
+    PASS_A_BATCH(float)
+}
+template <>
+__global__ __launch_bounds__(256) PA64_ATTR void k_pass_a_b<double>(PASS_A_BATCH_PARAMS(double))
+{
+    PASS_A_BATCH(double)
 }
 
 struct PassBParams {
@@ -509,21 +571,18 @@ struct PassBParams {
 // GH: boundary particles present; the viscous term then takes the velocity
 // difference of (ugs, vgs), which holds the ghost velocity of solids and u
 // of everything else.
-#define PASS_B_PARAMS(T)                                                                     \
-    Grid g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, NbrList ex,                        \
+#define PASS_B_PARAMS_(GT, T)                                                                \
+    GT g, NbrView nv, int n, RatesBufs<T> b, NbrList nl, NbrList ex,                          \
         const double4 *__restrict__ pa, const double2 *__restrict__ puv,                      \
         const typename Vec4<T>::type *__restrict__ pf, const double *__restrict__ ugs,        \
         const double *__restrict__ vgs, PassBParams P, double *dpdt, double *dudt,            \
         double *dvdt, Guard gd
+#define PASS_B_PARAMS(T) PASS_B_PARAMS_(Grid, T)
 #define PASS_B_ARGS g, nv, n, b, nl, ex, pa, puv, pf, ugs, vgs, P, dpdt, dudt, dvdt, gd
 
 template <typename T, bool GH>
-__device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
+__device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int s, int gl)
 {
-    if (guard_stop(gd)) return;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int s = t / RGB, gl = t % RGB;
-    if (s >= n) return;
     const double4 ai = pa[s];
     const double xi = ai.x, yi = ai.y, hi = ai.z, pi = ai.w;
     const double2 uvi = puv[s];
@@ -617,7 +676,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
         }
     };
     const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
-    const int cnt = nl.cnt[s];
+    const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
     // the lanes of the group take every RGB-th entry of the row
     if (ecnt <= ex.K) {
         // the exact neighbours pass A found (self excluded), UN per lane
@@ -684,32 +743,71 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS(T))
     dvdt[slot] = (double)(-Gy + vy.get() * ib) + P.fy;
 }
 
+#define PASS_B_SINGLE(T, GH)                                                                 \
+    if (guard_stop(gd)) return;                                                              \
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;               \
+    const int s = t / RGB, gl = t % RGB;                                                     \
+    if (s >= n) return;                                                                      \
+    pass_b_body<T, GH>(PASS_B_ARGS, s, gl);
+
 template <typename T, bool GH>
 __global__ __launch_bounds__(256) void k_pass_b(PASS_B_PARAMS(T))
 {
-    pass_b_body<T, GH>(PASS_B_ARGS);
+    PASS_B_SINGLE(T, GH)
 }
 // The FP32 kernels are latency-bound on their gathers: they ask for more
 // waves per SIMD (the register budget that allows) than the compiler picks.
 template <>
 __global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, true>(PASS_B_PARAMS(float))
 {
-    pass_b_body<float, true>(PASS_B_ARGS);
+    PASS_B_SINGLE(float, true)
 }
 template <>
 __global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, false>(PASS_B_PARAMS(float))
 {
-    pass_b_body<float, false>(PASS_B_ARGS);
+    PASS_B_SINGLE(float, false)
 }
 template <>
 __global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, true>(PASS_B_PARAMS(double))
 {
-    pass_b_body<double, true>(PASS_B_ARGS);
+    PASS_B_SINGLE(double, true)
 }
 template <>
 __global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, false>(PASS_B_PARAMS(double))
 {
-    pass_b_body<double, false>(PASS_B_ARGS);
+    PASS_B_SINGLE(double, false)
+}
+
+// Batched pass B (fluid only, the list re-tested): every simulation of a
+// batch, its grid, tables and constants from its descriptor.
+#define PASS_B_BATCH(T)                                                                      \
+    int lb;                                                                                  \
+    const int sid = batch_find(B, BM_P128, xcd_block(blockIdx.x, gridDim.x), &lb);           \
+    const SimDesc& sd = batch_desc(B, sid);                                                  \
+    const int t = lb * 256 + threadIdx.x;                                                    \
+    const int sl = t / RGB, gl = t % RGB;                                                    \
+    if (sl >= sd.n) return;                                                                  \
+    const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
+    const Guard gd{nullptr, 0};                                                              \
+    const PassBParams P{sd.rho0, sd.cs, sd.nu, sd.alpha_e, sd.fx, sd.fy, sd.dt};             \
+    pass_b_body<T, false>(sd.g, batch_view(nv, sd, sid), 0, b, nl, ex, pa, puv, pf, nullptr, \
+                          nullptr, P, dpdt, dudt, dvdt, gd, (int)(sd.off + sl), gl);
+
+#define PASS_B_BATCH_PARAMS(T)                                                               \
+    Batch B, NbrView nv, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,          \
+        const double2 *__restrict__ puv, const typename Vec4<T>::type *__restrict__ pf,       \
+        double *dpdt, double *dudt, double *dvdt
+template <typename T>
+__global__ __launch_bounds__(256) void k_pass_b_b(PASS_B_BATCH_PARAMS(T));
+template <>
+__global__ __launch_bounds__(256) PB_ATTR void k_pass_b_b<float>(PASS_B_BATCH_PARAMS(float))
+{
+    PASS_B_BATCH(float)
+}
+template <>
+__global__ __launch_bounds__(256) PB64_ATTR void k_pass_b_b<double>(PASS_B_BATCH_PARAMS(double))
+{
+    PASS_B_BATCH(double)
 }
 
 // Adds the evaluation's interacting ordered pairs, sum over i of
@@ -836,7 +934,10 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
 {
     Work& w = c->w;
     // in a run of steps the caller holds a valid list; its checks run on
-    // the device and trip the run when the list expires
+    // the device and trip the run when the list expires.  (A cell walk inside
+    // pass A, with no list, was measured slower than the list build plus a
+    // list-driven pass A: in the walk most lanes carry a rejected candidate
+    // through the pair terms.)
     int rc = gd.trip ? SPH_OK : ensure_list(c, n, x, y, h);
     if (rc) return rc;
     if (n == 0) return SPH_OK;
@@ -1108,6 +1209,152 @@ int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
         if (rc) return rc;
     }
     return SPH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: one predict-evaluate-correct step of every simulation of a
+// batch (fluid only, periodic or open boxes, each with its own grid, dt and
+// constants), with one launch per kernel for the whole batch.  Each
+// simulation sees exactly what a lone context with a lean workspace and the
+// list rebuilt at every evaluation computes: its particles are sorted within
+// its own range, its tables and per-level data are its own, and every pair
+// sum runs in the same order.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_count_pairs_b(Batch B, const T* __restrict__ nnb,
+                                                       unsigned long long* acc)
+{
+    __shared__ int part[4];
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc* d = B.sims + sid;
+    const int il = lb * 256 + threadIdx.x;
+    int v = il < d->n ? (int)nnb[d->off + il] - 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(acc + d->slot, (unsigned long long)((long long)part[0] + part[1] + part[2] + part[3]));
+}
+
+// Predictor (eq. int-pre) and corrector (eq. int-cor) of the batch, each
+// particle with its simulation's dt and box.
+__global__ __launch_bounds__(256) void k_predict_b(Batch B, const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ p,
+                                                   const double* __restrict__ ap,
+                                                   const double* __restrict__ au,
+                                                   const double* __restrict__ av,
+                                                   const double* __restrict__ dxs,
+                                                   const double* __restrict__ dys, double* xh,
+                                                   double* yh, double* uh, double* vh, double* ph)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= sd.n) return;
+    const int64_t i = sd.off + il;
+    const double dt = sd.dt;
+    const double un = u[i] + 0.5 * dt * au[i];
+    const double vn = v[i] + 0.5 * dt * av[i];
+    const double tu = un + dxs[i] / dt;
+    const double tv = vn + dys[i] / dt;
+    xh[i] = wrap_axis(sd.g, 0, x[i] + 0.5 * dt * tu);
+    yh[i] = wrap_axis(sd.g, 1, y[i] + 0.5 * dt * tv);
+    uh[i] = un;
+    vh[i] = vn;
+    ph[i] = p[i] + 0.5 * dt * ap[i];
+}
+
+__global__ __launch_bounds__(256) void k_correct_b(Batch B, double* x, double* y, double* u,
+                                                   double* v, double* p,
+                                                   const double* __restrict__ ap,
+                                                   const double* __restrict__ au,
+                                                   const double* __restrict__ av,
+                                                   const double* __restrict__ dxs,
+                                                   const double* __restrict__ dys)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= sd.n) return;
+    const int64_t i = sd.off + il;
+    const double dt = sd.dt;
+    const double un = u[i] + dt * au[i];
+    const double vn = v[i] + dt * av[i];
+    const double tu = un + dxs[i] / dt;
+    const double tv = vn + dys[i] / dt;
+    x[i] = wrap_axis(sd.g, 0, x[i] + dt * tu);
+    y[i] = wrap_axis(sd.g, 1, y[i] + dt * tv);
+    u[i] = un;
+    v[i] = vn;
+    p[i] = p[i] + dt * ap[i];
+}
+
+// One evaluation of the batch at (x, y, u, v, p); the summation density
+// goes to b.rho (the state's), the rates to b.r_*.
+template <typename T>
+static int batch_eval_T(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const double* x,
+                        const double* y, const double* u, const double* v, const double* p)
+{
+    const uint64_t* keys = nullptr;
+    const int32_t* perm = nullptr;
+    int rc = batch_build(st, b, L, x, y, b.h, &keys, &perm);
+    if (rc) return rc;
+    RatesBufs<T> rb;
+    rb.m = (T*)b.m;
+    rb.rho = (T*)b.brho;
+    rb.beta = (T*)b.beta;
+    rb.dpav = (T*)b.dpav;
+    rb.dxs = (T*)b.dxs;
+    rb.dys = (T*)b.dys;
+    rb.nnb = (T*)b.nnb;
+    rb.V = rb.B = rb.ih = nullptr;
+    rb.ps = nullptr;
+    using T4 = typename Vec4<T>::type;
+    hipLaunchKernelGGL(k_gather_state_b<T>, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
+                       perm, x, y, b.h, u, v, p, (const int64_t*)b.mq, b.pa, b.puv, rb.m);
+    const NbrView nv{nullptr, nullptr, nullptr, b.xyh, perm, keys, b.tab, b.hmax, b.lcount};
+    const NbrList nl{b.nl_idx, b.nl_cnt, b.nl_k, (int)b.stride, b.list_flag};
+    const PassAOut aout{b.rho, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(k_pass_a_b<T>, dim3((unsigned)L.nblk[BM_P64]), dim3(256), 0, st, L.B, nv, rb, nl,
+                       (const double4*)b.pa, (T4*)b.pf, aout, b.r_dxs, b.r_dys);
+    hipLaunchKernelGGL(k_pass_b_b<T>, dim3((unsigned)L.nblk[BM_P128]), dim3(256), 0, st, L.B, nv, rb,
+                       nl, (const double4*)b.pa, (const double2*)b.puv, (const T4*)b.pf, b.r_dpdt,
+                       b.r_dudt, b.r_dvdt);
+    hipLaunchKernelGGL(k_count_pairs_b<T>, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
+                       (const T*)rb.nnb, b.pairs);
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_DEVICE;
+}
+
+int batch_step(hipStream_t st, const BatchBufs& b, const BatchLaunch& L)
+{
+    if (L.B.nsim == 0) return SPH_OK;
+    auto eval = [&](const double* x, const double* y, const double* u, const double* v,
+                    const double* p) {
+        return L.precision == SPH_FP32 ? batch_eval_T<float>(st, b, L, x, y, u, v, p)
+                                       : batch_eval_T<double>(st, b, L, x, y, u, v, p);
+    };
+    int rc = eval(b.x, b.y, b.u, b.v, b.p);
+    if (rc) return rc;
+    const unsigned nb = (unsigned)L.nblk[BM_P256];
+    hipLaunchKernelGGL(k_predict_b, dim3(nb), dim3(256), 0, st, L.B, (const double*)b.x,
+                       (const double*)b.y, (const double*)b.u, (const double*)b.v,
+                       (const double*)b.p, (const double*)b.r_dpdt, (const double*)b.r_dudt,
+                       (const double*)b.r_dvdt, (const double*)b.r_dxs, (const double*)b.r_dys, b.xh,
+                       b.yh, b.uh, b.vh, b.ph);
+    rc = eval(b.xh, b.yh, b.uh, b.vh, b.ph);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_correct_b, dim3(nb), dim3(256), 0, st, L.B, b.x, b.y, b.u, b.v, b.p,
+                       (const double*)b.r_dpdt, (const double*)b.r_dudt, (const double*)b.r_dvdt,
+                       (const double*)b.r_dxs, (const double*)b.r_dys);
+    return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_DEVICE;
 }
 
 // Clears the boundary-list counters (after skipped evaluations of a run of

@@ -513,6 +513,43 @@ __device__ __forceinline__ int xcd_block(int b, int nb)
     return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
 }
 
+// ---- batched launches ------------------------------------------------------
+// Simulation of block b in block map `map` (binary search over the block
+// starts; b is uniform over the block, so is the result), and the block's
+// index within that simulation.
+__device__ __forceinline__ int batch_find(const Batch& B, int map, int b, int* local)
+{
+    const int32_t* st = B.bstart + map * (B.nsim + 1);
+    int lo = 0, hi = B.nsim - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    *local = b - st[lo];
+    return lo;
+}
+
+// Descriptor s of a batch read through the constant address space: its
+// address is uniform over the block and nothing in a kernel writes it, so
+// its fields are scalar loads kept in scalar registers (as a kernel
+// argument's are); a copy in LDS would hold them in vector registers.
+typedef __attribute__((address_space(4))) const SimDesc SimDescK;
+__device__ __forceinline__ const SimDesc& batch_desc(const Batch& B, int s)
+{
+    return *(const SimDesc*)(SimDescK*)(B.sims + s);
+}
+
+// The neighbour view of simulation s of a batch: its own tables and
+// per-level maxima and counts; the sorted arrays are the batch's.
+__device__ __forceinline__ NbrView batch_view(NbrView nv, const SimDesc& sd, int s)
+{
+    nv.tab += sd.toff;
+    nv.hmax_bits += s * SPH_MAXL;
+    nv.lcount += s * SPH_MAXL;
+    return nv;
+}
+
 // ---- wave64 helpers ----------------------------------------------------------
 
 __device__ __forceinline__ double wave_min_d(double v)

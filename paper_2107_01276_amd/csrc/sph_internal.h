@@ -67,6 +67,30 @@ struct NbrView {
     const int32_t* lcount;               // per-level particle count
 };
 
+// ---- batched launches over many independent simulations ------------------
+// The simulations of a batch hold disjoint particle ranges of one set of
+// global arrays (and disjoint ranges of one cell-table array).  Every hot
+// kernel is launched once for the whole batch: block b belongs to the
+// simulation s with start[s] <= b < start[s + 1] in the block map of its
+// launch shape, and reads that simulation's descriptor.
+struct SimDesc {
+    Grid g;
+    int64_t off, n;     // particles [off, off + n) of the batch arrays
+    int64_t toff;       // first entry of its cell tables
+    int64_t hoff;       // first entry of its radix digit histogram
+    int64_t packed;     // sum of n over the simulations before it
+    int32_t ntile;      // radix-sort tiles (RS_TILE particles each)
+    int32_t slot;       // its pair counter
+    double dt, rho0, cs, nu, alpha_e, fx, fy, mass_q;
+};
+// Block maps: particles per block of each launch shape.
+enum { BM_P256 = 0, BM_P64 = 1, BM_P128 = 2, BM_TILE = 3, BM_COUNT = 4 };
+struct Batch {
+    const SimDesc* sims;    // nsim descriptors
+    const int32_t* bstart;  // bstart[map * (nsim + 1) + s]: first block of s
+    int32_t nsim;
+};
+
 // Workspace carve-out (device pointers).
 struct Work {
     uint64_t *keys_a, *keys_b;
@@ -109,6 +133,8 @@ struct Work {
     double2* puv;
     void* pf;
     int32_t* list_flag;         // [0]: rebuild needed (moved / h changed / overflow)
+    int64_t* sched_origin;      // map storage of the schedule's adaptations and
+    int32_t* sched_sat;         // inlet/outlet updates (not in a lean workspace)
     int32_t lean;               // 1: the adaptation buffers below are not carved
     int64_t capacity;
 };
@@ -156,6 +182,7 @@ struct sph_ctx {
     unsigned long long io_last[3];  // inlet/outlet event counters at the last update
     // small host readbacks: pinned, device-coherent words written by a
     // one-lane kernel; word 0 carries the sequence number of the last one
+    int64_t iter;         // iteration counter of the schedule (sph_step)
     uint32_t* mbox;       // host address
     uint32_t* mbox_dev;   // the same memory as the device sees it
     uint32_t mbox_seq;
@@ -186,6 +213,42 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
 int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void grid_setup(const sph_config* cfg, Grid* g);
 size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g);
+
+// batched step (nbr.hip, rates.hip): global arrays of a batch
+struct BatchBufs {
+    double *x, *y, *u, *v, *p, *rho, *h;  // state, slot order
+    int64_t* mq;
+    uint64_t *keys_a, *keys_b;
+    int32_t *vals_a, *vals_b;
+    uint32_t *hist, *scan_tmp;
+    int2* tab;
+    unsigned long long* hmax;             // SPH_MAXL per simulation of a batch
+    int32_t* lcount;
+    double4 *xyh, *pa;
+    double2* puv;
+    void* pf;                             // float4 / double4 records
+    void *m, *brho, *beta, *dpav, *dxs, *dys, *nnb;  // per particle, 8 bytes each
+    int32_t *nl_idx, *nl_cnt, *list_flag;
+    int32_t nl_k;
+    int64_t stride;                       // particles of the arrays (list stride)
+    double *r_dpdt, *r_dudt, *r_dvdt, *r_dxs, *r_dys;
+    double *xh, *yh, *uh, *vh, *ph;
+    unsigned long long* pairs;            // per counter slot
+};
+struct BatchLaunch {
+    Batch B;
+    int32_t nblk[BM_COUNT];   // blocks of each launch shape
+    int64_t hist_n;           // digit-histogram entries of the batch
+    int64_t tab_n;            // cell-table entries to clear (the used extent)
+    int32_t npass;            // radix passes (the widest key of the batch)
+    int32_t precision;
+};
+// One predict-evaluate-correct step of every simulation of the batch.
+int batch_step(hipStream_t st, const BatchBufs& b, const BatchLaunch& L);
+// the neighbour structure of a batch at positions (x, y, h) and its list
+int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const double* x,
+                const double* y, const double* h, const uint64_t** keys, const int32_t** perm);
+int batch_key_bits(const Grid* g);
 
 // rates.hip
 int rates_eval(sph_ctx* c, int n, const sph_particles* ps, double dt, const sph_rates_out* out);
@@ -218,7 +281,12 @@ int mref_lookup_run(sph_ctx* c, const sph_particles* ps, const sph_background* b
 int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, const double* phi,
                   double phi_thresh, int passes, int64_t* nsplit);
 
+// the per-iteration schedule of section 3.4 (sph_step)
+int schedule_run(sph_ctx* c, sph_particles* ps, sph_background* bg, const sph_particles* solids,
+                 const sph_inout_params* io, int nsteps, sph_diag* diag);
+
 // api.hip
+double timestep_of(const sph_config& cfg, double h_min);
 void set_err(sph_ctx* c, const char* fmt, ...);
 int check_hip(sph_ctx* c, hipError_t e, const char* what);
 void prof_begin(sph_ctx* c, int slot);

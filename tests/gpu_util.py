@@ -6,6 +6,12 @@ import oracle
 import workloads as W
 
 
+def dt_of(s):
+    """The time step of a workload (oracle.dt_for: eq. timestep from its
+    h_min and U unless it names a dt)."""
+    return oracle.dt_for(s)
+
+
 def lib():
     import paper_2107_01276_amd as P
     P.load_library()

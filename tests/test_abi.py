@@ -65,3 +65,32 @@ def test_checkpoint_size():
     for n in (0, 1, 1000, 123457):
         assert lib.sph_export_bytes(n) == 64 + n * (8 * 8 + 8 + 4)
     assert lib.sph_export_bytes(-1) == 0
+
+
+def test_timestep_matches_oracle(orc):
+    """sph_timestep (eq. timestep in the library, a host computation) equals
+    the oracle's for the configurations of the workloads, to the last bit or
+    one rounding of the quotients; h_min <= 0 takes the config's h_lo."""
+    import numpy as np
+
+    import paper_2107_01276_amd as P
+    import workloads as W
+    lib_path = os.path.join(ROOT, "paper_2107_01276_amd", "libsph.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsph.so not built")
+    for s in (W.tgv(50, seed=1), W.tgv(30, re=1000.0), W.gresho_chan(40)):
+        prm = s["params"]
+        cfg = P.Config(h_lo=s["h_min"], h_hi=s["h_min"], cs=prm["cs"], nu=prm["nu"],
+                       u_ref=s["u_ref"])
+        ref = orc.timestep(s["h_min"], s["u_ref"], prm["cs"], prm["nu"])
+        assert P.timestep(cfg) == pytest.approx(ref, rel=4e-16, abs=0)
+        assert P.timestep(cfg, 2 * s["h_min"]) == pytest.approx(
+            orc.timestep(2 * s["h_min"], s["u_ref"], prm["cs"], prm["nu"]), rel=4e-16, abs=0)
+    # the channel of the benchmark: the paper's cylinder runs give
+    # dt = 0.25 h_min / (U + c_s) (the viscous bound is looser there)
+    s = W.channel_cylinder(seed=2)
+    prm = s["params"]
+    cfg = P.Config(h_lo=s["h_min"], h_hi=s["h_min"], cs=prm["cs"], nu=prm["nu"], u_ref=s["u_ref"])
+    assert P.timestep(cfg) == pytest.approx(0.25 * s["h_min"] / (s["u_ref"] + prm["cs"]),
+                                            rel=4e-16)
+    assert P.timestep(P.Config(h_lo=0.01, h_hi=0.01, cs=-1.0, u_ref=1.0)) == 0.0

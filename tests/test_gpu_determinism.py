@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_util import lib
+from gpu_util import dt_of, lib
 
 pytestmark = pytest.mark.gpu
 
@@ -25,7 +25,7 @@ def _run(P, prec):
     B = P.Background.from_arrays(bg, cap)
     ctx.adapt(ps, B)
     for _ in range(2):
-        ctx.step_inout(ps, s["dt"], 10, s["io"])
+        ctx.step_inout(ps, dt_of(s), 10, s["io"])
         ctx.adapt(ps, B)
     return ps.numpy()
 

@@ -3,6 +3,7 @@ creation, and calls with missing arrays, non-finite values or sizes beyond
 the capacity return SPH_E_INVAL (or SPH_E_CAPACITY) without touching the
 state.  Every case here is refused on the host before any kernel runs."""
 import ctypes as C
+import dataclasses
 import math
 
 import numpy as np
@@ -19,7 +20,8 @@ def test_config_rejections():
     base = dict(lo=(0.0, 0.0), hi=(1.0, 1.0), periodic=(1, 1), h_lo=0.01, h_hi=0.02)
     bad = ({"io_mode": 2}, {"io_ref": (math.nan, 0.0, 0.0)}, {"io_mode": 1, "cs": 0.0},
            {"hi": (0.0, 1.0)}, {"h_lo": 0.0}, {"list_skin": 1.5}, {"precision": 7},
-           {"wall_accel": (math.inf, 0.0)}, {"merge_iters": 9}, {"lean": 2})
+           {"wall_accel": (math.inf, 0.0)}, {"merge_iters": 9}, {"lean": 2}, {"n_adapt": -1},
+           {"n_bg": -2}, {"dt": -1e-4}, {"sol_k": math.nan}, {"bg_passes": -1})
     for b in bad:
         with pytest.raises(P.SphError) as e:
             P.Context(P.Config(**{**base, **b}), 16)
@@ -51,9 +53,18 @@ def test_call_rejections_leave_state():
     # n beyond the capacity, and a step with dt <= 0
     c = ps.c()
     c.n = c.capacity + 1
-    assert ctx.lib.sph_step(ctx._h, C.byref(c), 1e-4, 1) == P.SPH_E_INVAL
+    assert ctx.lib.sph_pec(ctx._h, C.byref(c), 1e-4, 1) == P.SPH_E_INVAL
+    assert ctx.lib.sph_step(ctx._h, C.byref(c), None, None, None, 1, None) == P.SPH_E_INVAL
     with pytest.raises(P.SphError) as e:
         ctx.step(ps, 0.0, 1)
+    assert e.value.code == P.SPH_E_INVAL
+    # the schedule: a background update every n_bg iterations needs the solids
+    c2 = P.Context(dataclasses.replace(ctx.cfg, n_bg=5), ps.capacity)
+    bgd = W.background_lattice(s["domain"], 0.25, 1.2, 1.0)
+    assert bgd["x"].size <= ps.capacity
+    B = P.Background.from_arrays(bgd, ps.capacity)
+    with pytest.raises(P.SphError) as e:
+        c2.run(ps, 1, bg=B)
     assert e.value.code == P.SPH_E_INVAL
     after = ps.numpy()
     for k in before:

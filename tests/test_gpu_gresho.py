@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, dt_of, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -45,13 +45,13 @@ def test_rates_vs_oracle_and_centripetal(prec):
     s = _jittered(s0)
     print(f"[gresho] rates n={s['x'].size} prec={prec}", flush=True)
     ctx = ctx_for(P, s, P.SPH_FP64 if prec == "fp64" else P.SPH_FP32)
-    r = ctx.rates(particles(P, s), s["dt"])
+    r = ctx.rates(particles(P, s), dt_of(s))
     o = oracle.rates(odom(s["domain"]), _prm(s), s["x"], s["y"], s["u"], s["v"], s["p"], s["h"],
-                     s["mq"] * s["mass_q"], s["dt"])
+                     s["mq"] * s["mass_q"], dt_of(s))
     assert np.array_equal(r["nnb"].cpu().numpy(), o["nnb"])
     check_rates(r, o, prec, "gresho")
     # the centripetal acceleration of the exact steady state, on the lattice
-    r = ctx.rates(particles(P, s0), s0["dt"])
+    r = ctx.rates(particles(P, s0), dt_of(s0))
     x, y = s0["x"], s0["y"]
     r2 = np.maximum(x * x + y * y, 1e-300)
     _, _, _, uphi = W.gresho_chan_fields(x, y)

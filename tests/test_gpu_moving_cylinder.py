@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, dt_of, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +49,7 @@ def test_moving_cylinder_small_vs_oracle():
     mo = s["motion"]
     d = odom(s["domain"])
     n = s["x"].size
-    dt = s["dt"]
+    dt = dt_of(s)
     print(f"[osc-small] n={n} dt={dt}", flush=True)
     ctx = ctx_for(P, s, P.SPH_FP64, capacity=4 * n, cr=spec.cr, ds_min=spec.ds_min,
                   ds_max=spec.ds_min * spec.ratio)
@@ -113,12 +113,12 @@ def test_moving_cylinder_full_size():
     # the body at a quarter period: displaced by the amplitude, at rest, decelerating
     yq, vq, aq = W.body_motion(0.25 * mo["period"], mo["amp"], mo["period"])
     o = oracle.move_solids(d, s, (0.0, yq), (0.0, vq))
-    r_o = oracle.rates_k(d, _prm(s), o, s["dt"], aw=(0.0, aq), io=s["params"]["io_ref"])
+    r_o = oracle.rates_k(d, _prm(s), o, dt_of(s), aw=(0.0, aq), io=s["params"]["io_ref"])
     for prec, name in ((P.SPH_FP64, "fp64"), (P.SPH_FP32, "fp32")):
         ctx = ctx_for(P, s, prec)
         ps = particles(P, s)
         ctx.move_solids(ps, (0.0, yq), (0.0, vq), (0.0, aq))
-        r = ctx.rates(ps, s["dt"])
+        r = ctx.rates(ps, dt_of(s))
         assert np.array_equal(r["nnb"].cpu().numpy(), r_o["nnb"])
         check_rates(r, r_o, name, "oscillating cylinder")
     # the whole loop on the FP32 path: body motion and a background pass
@@ -134,7 +134,7 @@ def test_moving_cylinder_full_size():
     sol0 = s["kind"] == W.SOLID
     ys = s["y"][sol0].copy()
     M0 = int(s["mq"].sum())
-    dt, t, y0 = s["dt"], 0.0, 0.0
+    dt, t, y0 = dt_of(s), 0.0, 0.0
     steps = 20
     ctx.adapt(ps, B)
     t0 = time.perf_counter()

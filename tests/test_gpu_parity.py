@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import check_rates, csr_np, ctx_for, lib, odom, particles, rel_norm, with_fields
+from gpu_util import check_rates, csr_np, ctx_for, dt_of, lib, odom, particles, rel_norm, with_fields
 
 pytestmark = pytest.mark.gpu
 
@@ -134,9 +134,9 @@ def test_pec_steps_vs_oracle():
     ctx = ctx_for(P, s, P.SPH_FP64)
     ps = particles(P, s)
     print("[step] tgv 50x50 fp64 20 steps", flush=True)
-    ctx.step(ps, s["dt"], 20)
+    ctx.step(ps, dt_of(s), 20)
     g = ps.numpy()
-    o = oracle.step(oracle.Dom(), oracle.Prm(mass_q=s["mass_q"]), s, s["dt"], 20)
+    o = oracle.step(oracle.Dom(), oracle.Prm(mass_q=s["mass_q"]), s, dt_of(s), 20)
     for k in ("x", "y"):
         d = g[k] - o[k]
         d = d - np.round(d)
@@ -153,9 +153,9 @@ def test_tgv_decay_gpu_fp32():
     ctx = ctx_for(P, s, P.SPH_FP32)
     ps = particles(P, s)
     ke0 = ctx.diagnostics(ps)["ke"]
-    ctx.step(ps, s["dt"], 100)
+    ctx.step(ps, dt_of(s), 100)
     d = ctx.diagnostics(ps)
-    T = 100 * s["dt"]
+    T = 100 * dt_of(s)
     assert d["ke"] / ke0 == pytest.approx(math.exp(-16 * math.pi ** 2 * T / 100), rel=1e-3)
     assert d["mq_total"] == int(s["mq"].sum())
 
@@ -178,7 +178,7 @@ def test_channel_full_size_sampled():
                                        s["x"], s["y"], s["h"], "brute")
     for k, i in enumerate(sample):
         assert np.array_equal(col[rp[i]:rp[i + 1]], ocol[orp[k]:orp[k + 1]])
-    dt = s["dt"]
+    dt = dt_of(s)
     # the cylinder's solid particles take the wall boundary pass of section 2.2
     prm = oracle.Prm(rho0=1.0, cs=s["params"]["cs"], nu=s["params"]["nu"],
                      hdx=s["params"]["hdx"], mass_q=s["mass_q"])

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import check_rates, ctx_for, lib, odom, particles, rel_norm
+from gpu_util import check_rates, ctx_for, dt_of, lib, odom, particles, rel_norm
 
 pytestmark = pytest.mark.gpu
 
@@ -39,10 +39,10 @@ def test_wake_channel_neighbors_and_rates(wake):
     print(f"[wake] nnz gpu={col.numel()} oracle={ocol.size}", flush=True)
     assert np.array_equal(rp.cpu().numpy(), orp) and np.array_equal(col.cpu().numpy(), ocol)
     del rp, col, orp, ocol
-    o = oracle.rates_k(d, _prm(s), s, s["dt"], io=s["params"]["io_ref"])
+    o = oracle.rates_k(d, _prm(s), s, dt_of(s), io=s["params"]["io_ref"])
     for prec, name in ((P.SPH_FP64, "fp64"), (P.SPH_FP32, "fp32")):
         c = ctx if prec == P.SPH_FP64 else ctx_for(P, s, prec)
-        r = c.rates(particles(P, s), s["dt"])
+        r = c.rates(particles(P, s), dt_of(s))
         assert np.array_equal(r["nnb"].cpu().numpy(), o["nnb"])
         check_rates(r, o, name, "wake channel")
 

@@ -15,7 +15,7 @@ def _rel_err(nx):
     s = W.gresho_chan(nx)
     prm = oracle.Prm(rho0=1.0, cs=10.0, nu=0.0, hdx=1.0, mass_q=s["mass_q"])
     o = oracle.rates(odom(s["domain"]), prm, s["x"], s["y"], s["u"], s["v"], s["p"], s["h"], s["m"],
-                     s["dt"])
+                     oracle.dt_for(s))
     x, y = s["x"], s["y"]
     r2 = np.maximum(x * x + y * y, 1e-300)
     _, _, _, uphi = W.gresho_chan_fields(x, y)

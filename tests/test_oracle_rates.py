@@ -119,8 +119,8 @@ def test_pressure_offset_invariance(orc):
     s = W.tgv(24, seed=3)
     dom = orc.Dom()
     prm = orc.Prm(nu=0.0)
-    r1 = orc.rates(dom, prm, s["x"], s["y"], s["u"], s["v"], s["p"], s["h"], s["m"], s["dt"])
-    r2 = orc.rates(dom, prm, s["x"], s["y"], s["u"], s["v"], s["p"] + 50.0, s["h"], s["m"], s["dt"])
+    r1 = orc.rates(dom, prm, s["x"], s["y"], s["u"], s["v"], s["p"], s["h"], s["m"], orc.dt_for(s))
+    r2 = orc.rates(dom, prm, s["x"], s["y"], s["u"], s["v"], s["p"] + 50.0, s["h"], s["m"], orc.dt_for(s))
     for k in ("dudt", "dvdt"):
         assert np.allclose(r1[k], r2[k], atol=1e-9 * np.abs(r1[k]).max())
 
@@ -189,7 +189,7 @@ def test_rest_state_exact(orc):
     dom = orc.Dom()
     n = s["x"].size
     r = orc.rates(dom, orc.Prm(), s["x"], s["y"], np.full(n, 0.3), np.full(n, -0.2),
-                  np.full(n, 2.0), s["h"], s["m"], s["dt"])
+                  np.full(n, 2.0), s["h"], s["m"], orc.dt_for(s))
     assert np.all(r["dpdt"] == 0) and np.all(r["dudt"] == 0) and np.all(r["dvdt"] == 0)
 
 
@@ -203,7 +203,7 @@ def test_uniform_pressure_no_force(orc):
     n = s["x"].size
     p0 = 5.0 + 4.0 * math.log(2.0) - 2.0
     r = orc.rates(dom, orc.Prm(), s["x"], s["y"], np.zeros(n), np.zeros(n), np.full(n, p0),
-                  s["h"], s["m"], s["dt"])
+                  s["h"], s["m"], orc.dt_for(s))
     assert np.all(r["pavg"] == p0)
     assert np.all(r["dpdt"] == 0) and np.all(r["dudt"] == 0) and np.all(r["dvdt"] == 0)
 
@@ -219,7 +219,7 @@ def test_pairwise_antisymmetry(orc):
     rp, col = orc.neighbors(dom, x, y, h)
     prm0 = orc.Prm(nu=0.0, pref_mode=0)
     a = orc.pass_a(dom, prm0, x, y, h, m, p, rp, col)
-    b = orc.pass_b(dom, prm0, x, y, u, v, p, h, m, a, s["dt"], rp, col)
+    b = orc.pass_b(dom, prm0, x, y, u, v, p, h, m, a, orc.dt_for(s), rp, col)
     for k in ("dudt", "dvdt"):
         tot = np.abs(m * b[k]).sum()
         assert abs(np.sum(m * b[k])) < 1e-13 * tot
@@ -227,7 +227,7 @@ def test_pairwise_antisymmetry(orc):
     a1 = dict(a)
     a1["beta"] = np.ones_like(a["beta"])
     a1["pavg"] = p.copy()  # P_i = 0: pressure term off
-    b = orc.pass_b(dom, prm, x, y, u, v, p, h, m, a1, s["dt"], rp, col)
+    b = orc.pass_b(dom, prm, x, y, u, v, p, h, m, a1, orc.dt_for(s), rp, col)
     for k in ("dudt", "dvdt"):
         tot = np.abs(m * b[k]).sum()
         assert abs(np.sum(m * b[k])) < 1e-13 * tot
@@ -240,8 +240,8 @@ def test_tgv_decay_closed_form(orc):
     s = W.tgv(50, seed=1)
     dom = orc.Dom()
     prm = orc.Prm(mass_q=s["mass_q"])
-    out = orc.step(dom, prm, s, s["dt"], 100)
-    T = 100 * s["dt"]
+    out = orc.step(dom, prm, s, orc.dt_for(s), 100)
+    T = 100 * orc.dt_for(s)
     assert T == pytest.approx(0.0454545, rel=1e-5)
     ke = orc.kinetic_energy(out["m"], out["u"], out["v"]) / orc.kinetic_energy(s["m"], s["u"], s["v"])
     assert math.exp(-16 * math.pi ** 2 * T / 100) == pytest.approx(0.930737, abs=1e-6)
@@ -253,7 +253,7 @@ def test_tgv_decay_closed_form(orc):
     assert l1 < 0.01
     # the reading kept for the pressure reduction is the one that reproduces
     # the exact solution; the printed per-particle form does not
-    out0 = orc.step(dom, orc.Prm(mass_q=s["mass_q"], pref_mode=0), s, s["dt"], 100)
+    out0 = orc.step(dom, orc.Prm(mass_q=s["mass_q"], pref_mode=0), s, orc.dt_for(s), 100)
     ue, ve, _ = W.tgv_fields(out0["x"], out0["y"], T, 100.0)
     assert np.mean(np.hypot(out0["u"] - ue, out0["v"] - ve)) > 5 * l1
     # volume error stays small (section 4.1)

@@ -78,8 +78,6 @@ def tgv(nx: int = 50, seed: int = 1, jitter: float = 0.05, hdx: float = 1.0,
     mq = quantize_mass(m, q)
     h = np.full(x.size, hdx * dx)
     nu = 1.0 / re
-    hmin = hdx * dx
-    dt = min(0.25 * hmin / (1.0 + cs), 0.125 * hmin * hmin / nu)
     return {
         "x": x, "y": y, "u": u, "v": v, "p": p, "h": h,
         "mq": mq, "mass_q": q, "m": mq.astype(np.float64) * q,
@@ -87,7 +85,7 @@ def tgv(nx: int = 50, seed: int = 1, jitter: float = 0.05, hdx: float = 1.0,
         "kind": np.zeros(x.size, np.int32),
         "domain": Domain((0.0, 0.0), (1.0, 1.0), (True, True)),
         "params": {"rho0": rho0, "cs": cs, "nu": nu, "hdx": hdx, "re": re},
-        "dt": dt, "dx": dx,
+        "h_min": hdx * dx, "u_ref": 1.0, "dx": dx,
     }
 
 
@@ -131,14 +129,13 @@ def gresho_chan(nx: int = 50, hdx: float = 1.0, rho0: float = 1.0, cs: float = 1
     q = mass_quantum(1.05 * m.max())
     mq = quantize_mass(m, q)
     h = np.full(x.size, hdx * dx)
-    dt = 0.25 * hdx * dx / (1.0 + cs)
     return {
         "x": x, "y": y, "u": u, "v": v, "p": p, "h": h,
         "mq": mq, "mass_q": q, "m": mq.astype(np.float64) * q,
         "rho": np.full(x.size, rho0), "mref": m.copy(), "kind": np.zeros(x.size, np.int32),
         "domain": Domain((-0.5, -0.5), (0.5, 0.5), (True, True)),
         "params": {"rho0": rho0, "cs": cs, "nu": 0.0, "hdx": hdx},
-        "dt": dt, "dx": dx,
+        "h_min": hdx * dx, "u_ref": 1.0, "dx": dx,
     }
 
 
@@ -364,8 +361,6 @@ def _assemble_channel(s, rng, x, y, ds, u, v, p, lev_ds, nlev, slope, lo, hi):
     P = np.concatenate([p, np.zeros(ns)])
     kind = np.concatenate([kind_f, np.full(ns, SOLID, np.int32)])
     nu = s.u_inf * s.diameter / s.re
-    hmin = s.hdx * s.ds_min
-    dt = min(0.25 * hmin / (s.u_inf + s.cs), 0.125 * hmin * hmin / nu)
     return {
         "x": X, "y": Yv, "u": U, "v": V, "p": P, "h": H, "mq": mq, "mass_q": q,
         "m": mq.astype(np.float64) * q, "rho": np.full(X.size, s.rho0),
@@ -375,7 +370,7 @@ def _assemble_channel(s, rng, x, y, ds, u, v, p, lev_ds, nlev, slope, lo, hi):
         "io": {"x_in": lo[0], "len_in": len_in, "x_out": hi[0], "len_out": len_out},
         "params": {"rho0": s.rho0, "cs": s.cs, "nu": nu, "hdx": s.hdx, "re": s.re,
                    "u_inf": s.u_inf, "io_mode": 1, "io_ref": (s.u_inf, 0.0, 0.0)},
-        "dt": dt, "spec": s,
+        "h_min": s.hdx * s.ds_min, "u_ref": s.u_inf, "spec": s,
     }
 
 
