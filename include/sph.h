@@ -14,8 +14,9 @@
  *   - Positions, velocities, pressure, density, smoothing length and
  *     reference mass are double.  Mass is an int64 number of quanta `mq`;
  *     the mass of a particle is mq * mass_q exactly (mass_q is a power of
- *     two chosen so every mq < 2^53), which keeps total mass exactly
- *     conserved through splits and merges.
+ *     two chosen so that every mq stays below 2^53 and the total over all
+ *     particles below 2^63), which keeps total mass exactly conserved
+ *     through splits and merges.
  *   - All work is issued on the context's stream in order.  Calls that
  *     return counts to the host (nnz, new particle count) synchronise that
  *     stream before returning; the others only enqueue work.
@@ -480,7 +481,10 @@ int sph_import(sph_ctx *ctx, sph_particles *ps, const void *host_buf, size_t byt
 
 /* Scalar diagnostics over [0, n).  Returns SPH_E_NONFINITE (with *out still
  * written) when a particle holds a NaN or infinite x, y, u, v, p, rho or h:
- * the check for a state that has blown up.  Synchronises. */
+ * the check for a state that has blown up; SPH_E_INVAL (with *out written,
+ * mq_total not meaningful) when a mass is negative or the ledger total
+ * does not fit int64 (a mass quantum too fine for this many particles).
+ * Synchronises. */
 int sph_diagnostics(sph_ctx *ctx, const sph_particles *ps, sph_diag *out);
 
 /* Profiling: bits 0-3 of `on` select the kernels to bracket with HIP events

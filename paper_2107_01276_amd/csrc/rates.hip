@@ -1569,9 +1569,11 @@ __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __res
                                                       int64_t* partq)
 {
     __shared__ double sh[5][256];
-    __shared__ int64_t sq[256], snf[256];
+    __shared__ int64_t sq[256], snf[256], sbad[256];
     double ke = 0, vol = 0, mx = 0, my = 0, um = 0;
-    int64_t q = 0, nf = 0;
+    // the ledger total is summed in int64 with overflow checks: an overflow
+    // (or a negative mass) is counted in bad
+    int64_t q = 0, nf = 0, bad = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         double m = (double)mq[i] * mass_q;
         double s2 = u[i] * u[i] + v[i] * v[i];
@@ -1580,7 +1582,8 @@ __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __res
         mx += m * u[i];
         my += m * v[i];
         um = fmax(um, sqrt(s2));
-        q += mq[i];
+        const int64_t mi = mq[i];
+        if (mi < 0 || __builtin_add_overflow(q, mi, &q)) bad = 1;
         const bool fin = isfinite(x[i]) && isfinite(y[i]) && isfinite(u[i]) && isfinite(v[i]) &&
                          isfinite(p[i]) && isfinite(rho[i]) && isfinite(h[i]);
         nf += fin ? 0 : 1;
@@ -1588,12 +1591,14 @@ __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __res
     int t = threadIdx.x;
     sh[0][t] = ke; sh[1][t] = vol; sh[2][t] = mx; sh[3][t] = my; sh[4][t] = um; sq[t] = q;
     snf[t] = nf;
+    sbad[t] = bad;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (t < o) {
             for (int k = 0; k < 4; ++k) sh[k][t] += sh[k][t + o];
             sh[4][t] = fmax(sh[4][t], sh[4][t + o]);
-            sq[t] += sq[t + o];
+            if (__builtin_add_overflow(sq[t], sq[t + o], &sq[t])) sbad[t] = 1;
+            sbad[t] |= sbad[t + o];
             snf[t] += snf[t + o];
         }
         __syncthreads();
@@ -1602,6 +1607,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(int n, const double* __res
         for (int k = 0; k < 5; ++k) part[k * DIAG_BLOCKS + blockIdx.x] = sh[k][0];
         partq[blockIdx.x] = sq[0];
         partq[DIAG_BLOCKS + blockIdx.x] = snf[0];
+        partq[2 * DIAG_BLOCKS + blockIdx.x] = sbad[0];
     }
 }
 
@@ -1615,17 +1621,19 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out)
                        ps->u, ps->v, ps->p, ps->rho, ps->h, ps->mq, c->cfg.mass_q, part, partq);
     LAUNCHCHK(c, "diag");
     double hp[5 * DIAG_BLOCKS];
-    int64_t hq[2 * DIAG_BLOCKS];
+    int64_t hq[3 * DIAG_BLOCKS];
     HIPCHK(c, hipMemcpyAsync(hp, part, sizeof(hp), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(hq, partq, sizeof(hq), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     double r[5] = {0, 0, 0, 0, 0};
     int64_t q = 0, nf = 0;
+    bool bad = false;
     for (int b = 0; b < DIAG_BLOCKS; ++b) {
         for (int k = 0; k < 4; ++k) r[k] += hp[k * DIAG_BLOCKS + b];
         r[4] = r[4] > hp[4 * DIAG_BLOCKS + b] ? r[4] : hp[4 * DIAG_BLOCKS + b];
-        q += hq[b];
+        if (__builtin_add_overflow(q, hq[b], &q)) bad = true;
         nf += hq[DIAG_BLOCKS + b];
+        bad = bad || hq[2 * DIAG_BLOCKS + b] != 0;
     }
     out->ke = r[0];
     out->vol = r[1];
@@ -1637,6 +1645,11 @@ int diag_run(sph_ctx* c, const sph_particles* ps, sph_diag* out)
     if (nf > 0) {
         set_err(c, "%lld particles hold NaN or infinite values", (long long)nf);
         return SPH_E_NONFINITE;
+    }
+    if (bad) {
+        set_err(c, "the mass ledger total does not fit int64 (or a mass is negative): "
+                   "choose a coarser mass quantum");
+        return SPH_E_INVAL;
     }
     return SPH_OK;
 }

@@ -96,3 +96,22 @@ def test_nonfinite_state_reported():
         with pytest.raises(P.SphError) as e:
             ctx.diagnostics(q)
         assert e.value.code == P.SPH_E_NONFINITE, field
+
+
+def test_ledger_overflow_reported():
+    """The diagnostics sum the mass ledger in checked int64: quanta whose
+    total does not fit are reported (SPH_E_INVAL) instead of wrapping; a
+    total just below 2^63 is summed exactly.  Only the reduction runs."""
+    P = lib()
+    s = W.tgv(8, seed=2)
+    n = s["x"].size
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    ps = particles(P, s)
+    big = (2 ** 63 - 1) // n
+    ps.mq[:n] = big
+    d = ctx.diagnostics(ps)
+    assert d["mq_total"] == big * n
+    ps.mq[:n] = 2 ** 62
+    with pytest.raises(P.SphError) as e:
+        ctx.diagnostics(ps)
+    assert e.value.code == P.SPH_E_INVAL and "ledger" in str(e.value)

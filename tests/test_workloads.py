@@ -68,3 +68,17 @@ def test_body_motion():
         ym, vm, _ = W.body_motion(t - e, A, T)
         assert abs((yp - ym) / (2 * e) - v) < 1e-8 and abs((vp - vm) / (2 * e) - a) < 1e-7
         assert abs(y - A * math.sin(2 * math.pi * t / T)) < 1e-15
+
+
+def test_mass_ledgers_fit_int64():
+    """Every workload's ledger total, summed exactly with Python integers,
+    stays below 2^63 (the diagnostics sum it in checked int64) and equals
+    numpy's int64 sum (which would wrap silently otherwise)."""
+    cases = [W.tgv(50, seed=1), W.channel_cylinder(seed=2), W.channel_wake(),
+             W.oscillating_cylinder(), W.gresho_chan(80)]
+    for s in cases:
+        mq = s["mq"]
+        exact = sum(int(v) for v in mq.tolist())
+        assert 0 < exact < 2 ** 63
+        assert exact == int(mq.sum(dtype=np.int64))
+        assert int(mq.max()) < 2 ** 53
