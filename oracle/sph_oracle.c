@@ -381,14 +381,15 @@ int64_t or_nbr_cells_alloc(const or_domain* d, int64_t n, const double* x,
     }
     free(cellid);
 
-    /* pair emission: pass 0 counts per row, pass 1 writes */
+    /* pair emission: pass 0 counts per row, pass 1 writes.  Rows are shared
+     * (a pair found from the finer side is written to both rows), so the
+     * threads bump the counts and fill cursors atomically; the order within
+     * a row is then arbitrary and every row is sorted at the end. */
     int32_t* col = NULL;
     int64_t* fillp = NULL;
     int maxk = 0;
     for (int l = 0; l < nlev; ++l)
         for (int a = 0; a < 2; ++a) if (L[l].nc[a] > maxk) maxk = L[l].nc[a];
-    int* kx = (int*)malloc(sizeof(int) * (size_t)(maxk + 8));
-    int* ky = (int*)malloc(sizeof(int) * (size_t)(maxk + 8));
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 1) {
             for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
@@ -396,6 +397,11 @@ int64_t or_nbr_cells_alloc(const or_domain* d, int64_t n, const double* x,
             fillp = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
             for (int64_t i = 0; i < n; ++i) fillp[i] = rp[i];
         }
+#pragma omp parallel
+        {
+        int* kx = (int*)malloc(sizeof(int) * (size_t)(maxk + 8));
+        int* ky = (int*)malloc(sizeof(int) * (size_t)(maxk + 8));
+#pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < n; ++i) {
             for (int l = lev[i]; l < nlev; ++l) {
                 or_level* lv = &L[l];
@@ -410,20 +416,33 @@ int64_t or_nbr_cells_alloc(const or_domain* d, int64_t n, const double* x,
                             int64_t j = lv->items[t];
                             if (!is_nbr(d, x[i], y[i], h[i], x[j], y[j], h[j])) continue;
                             if (pass == 0) {
+#pragma omp atomic
                                 rp[i + 1]++;
-                                if (l != lev[i]) rp[j + 1]++;
+                                if (l != lev[i]) {
+#pragma omp atomic
+                                    rp[j + 1]++;
+                                }
                             } else {
-                                col[fillp[i]++] = (int32_t)j;
-                                if (l != lev[i]) col[fillp[j]++] = (int32_t)i;
+                                int64_t at;
+#pragma omp atomic capture
+                                at = fillp[i]++;
+                                col[at] = (int32_t)j;
+                                if (l != lev[i]) {
+#pragma omp atomic capture
+                                    at = fillp[j]++;
+                                    col[at] = (int32_t)i;
+                                }
                             }
                         }
                     }
             }
         }
+        free(kx);
+        free(ky);
+        }
     }
-    free(kx);
-    free(ky);
     free(fillp);
+#pragma omp parallel for schedule(dynamic, 1024)
     for (int64_t i = 0; i < n; ++i)
         qsort(col + rp[i], (size_t)(rp[i + 1] - rp[i]), sizeof(int32_t), cmp_i32);
     for (int l = 0; l < nlev; ++l) { free(L[l].start); free(L[l].items); }
@@ -1668,6 +1687,60 @@ int or_mref_lookup(const or_domain* d, int64_t n, const double* x, const double*
  *   the Lind shift (eq. shift-deltar, volume m_b / rho_0), both from the
  *   same neighbour set, applied together.
  * Returns the new background count or a negative error. */
+/* Compensated sum (a cascade of Knuth's TwoSum): s holds the rounded running
+ * sum, c the rounded sum of the exact rounding errors of every addition, and
+ * s + c is the exact sum rounded once except within about n u^2 sum|t| of a
+ * rounding midpoint, so it does not depend on the order of the terms.
+ * READING: the background update's sums over neighbours (the logarithms of
+ * the sizes in the grading, h_j and the shift terms in the smoothing) are set
+ * sums; they are taken this way so that the update is a function of the
+ * particle set alone, whatever the slot order. */
+typedef struct { double s, c; } or_sum2;
+
+static void sum2_add(or_sum2* a, double x)
+{
+    double t = a->s + x;
+    double z = t - a->s;
+    a->c += (a->s - (t - z)) + (x - z);
+    a->s = t;
+}
+
+static double sum2_get(const or_sum2* a) { return a->s + a->c; }
+
+/* The limited shift of background particle b (eqs. shift-deltar and
+ * shift-limit, the same terms as shift_one) with the sums compensated. */
+static void bg_shift_one(const or_domain* d, double rho0, int64_t b, const double* x,
+                         const double* y, const double* h, const double* m,
+                         const int64_t* rp, const int32_t* col, double* dxs, double* dys)
+{
+    double fxi = or_kf(OR_XI);
+    or_sum2 sx = {0.0, 0.0}, sy = {0.0, 0.0};
+    for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+        int64_t j = col[k];
+        double dx = mi_axis(d, 0, x[b] - x[j]);
+        double dy = mi_axis(d, 1, y[b] - y[j]);
+        double r = sqrt(dx * dx + dy * dy);
+        if (r <= 0.0) continue;
+        double hij = 0.5 * (h[b] + h[j]);
+        double wr = or_kf(r / hij) / fxi;
+        double coef = (m[j] / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+        double t = coef * (or_dwdr(r, hij) / r);
+        sum2_add(&sx, t * dx);
+        sum2_add(&sy, t * dy);
+    }
+    double pref = -0.5 * (h[b] * h[b]);
+    double ddx = pref * sum2_get(&sx), ddy = pref * sum2_get(&sy);
+    double mag = sqrt(ddx * ddx + ddy * ddy);
+    double lim = 0.25 * h[b];
+    if (mag > lim) {
+        double th = lim / mag;
+        ddx = ddx * th;
+        ddy = ddy * th;
+    }
+    *dxs = ddx;
+    *dys = ddy;
+}
+
 static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb, int64_t cap,
                            double* bx, double* by, double* bh, double* bds, int32_t* bmask,
                            int64_t* bmq, double* bmref, int64_t ns, const double* sx,
@@ -1693,16 +1766,18 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
     if (nnz < 0) return nnz;
     double* nds = malloc(sz8);
     double cr3 = B->cr * B->cr * B->cr;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t b = 0; b < nb; ++b) {
         if (bmask[b]) { nds[b] = bds[b]; continue; }
-        double mn = bds[col[rp[b]]], mx = mn, sl = 0.0;
+        double mn = bds[col[rp[b]]], mx = mn;
+        or_sum2 sl = {0.0, 0.0};
         for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
             double s = bds[col[k]];
             if (s < mn) mn = s;
             if (s > mx) mx = s;
-            sl += log(s);
+            sum2_add(&sl, log(s));
         }
-        double geo = exp(sl / (double)(rp[b + 1] - rp[b]));
+        double geo = exp(sum2_get(&sl) / (double)(rp[b + 1] - rp[b]));
         double nv = (mx / mn < cr3) ? B->cr * mn : geo;
         if (nv < B->ds_min) nv = B->ds_min;
         if (nv > B->ds_max) nv = B->ds_max;
@@ -1751,12 +1826,13 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
         for (int64_t b = 0; b < nb; ++b) m[b] = (double)bmq[b] * B->mass_q;
         nnz = or_nbr_cells_alloc(d, nb, bx, by, bh, &rp, &col);
         if (nnz < 0) { free(m); free(nh); free(ddx); free(ddy); return nnz; }
+#pragma omp parallel for schedule(dynamic, 256)
         for (int64_t b = 0; b < nb; ++b) {
             double N = (double)(rp[b + 1] - rp[b]);
-            double sh_ = 0.0;
-            for (int64_t k = rp[b]; k < rp[b + 1]; ++k) sh_ += bh[col[k]];
-            nh[b] = 0.5 * ((bh[b] / 2.0) * (1.0 + sqrt(B->n_r / N)) + sh_ / N);
-            shift_one(d, B->rho0, b, bx, by, bh, m, rp, col, &ddx[b], &ddy[b]);
+            or_sum2 sh_ = {0.0, 0.0};
+            for (int64_t k = rp[b]; k < rp[b + 1]; ++k) sum2_add(&sh_, bh[col[k]]);
+            nh[b] = 0.5 * ((bh[b] / 2.0) * (1.0 + sqrt(B->n_r / N)) + sum2_get(&sh_) / N);
+            bg_shift_one(d, B->rho0, b, bx, by, bh, m, rp, col, &ddx[b], &ddy[b]);
         }
         for (int64_t b = 0; b < nb; ++b) {
             bh[b] = nh[b];
