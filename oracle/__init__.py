@@ -12,6 +12,7 @@ the C source names the equation or section each one follows.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -111,6 +112,7 @@ def lib():
             "or_vorticity": (None, [P, I64] + [P] * 10),
             "or_shepard_to_bg": (C.c_int, [P, I64, P, P, P, I64, P, P, P, P, P, P]),
             "or_timestep": (D, [D, D, D, D]),
+            "or_exact_sum": (D, [I64, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -577,6 +579,13 @@ def mref_lookup(dom: Dom, x, y, h, bx, by, bh, bmref):
     return out
 
 
+def bg_init_passes(ds_min: float, ds_max: float, cr: float) -> int:
+    """Passes of the background initialisation of section 3.3: three per
+    size level between ds_max and ds_min, 3 ceil(log_{C_r}(ds_max/ds_min))
+    (the 1e-12 keeps an exact power of C_r from rounding up a level)."""
+    return 3 * math.ceil(math.log(ds_max / ds_min) / math.log(cr) - 1e-12)
+
+
 def bg_update(dom: Dom, bp: BgPrm, bg: dict, solids: dict, passes: int, cap: int | None = None,
               phi=None, phi_thresh: float = 0.0):
     """Background passes (section 3.3).  bg: x y h ds (f64), mask (i32), mq (i64), mref (f64)."""
@@ -627,6 +636,13 @@ def shepard_to_bg(dom: Dom, bx, by, bh, x, y, h, f, kind=None):
 # --------------------------------------------------------------------------
 # diagnostics (section 4.1): kinetic energy, volume error, momentum
 # --------------------------------------------------------------------------
+
+def exact_sum(x) -> float:
+    """The exact sum of the doubles x rounded once, ties to even (the long
+    accumulator of the background update's sums)."""
+    x = _f64(x)
+    return float(lib().or_exact_sum(x.size, _p(x)))
+
 
 def timestep(hmin, U, cs, nu):
     """eq. (timestep)."""

@@ -1687,34 +1687,104 @@ int or_mref_lookup(const or_domain* d, int64_t n, const double* x, const double*
  *   the Lind shift (eq. shift-deltar, volume m_b / rho_0), both from the
  *   same neighbour set, applied together.
  * Returns the new background count or a negative error. */
-/* Compensated sum (a cascade of Knuth's TwoSum): s holds the rounded running
- * sum, c the rounded sum of the exact rounding errors of every addition, and
- * s + c is the exact sum rounded once except within about n u^2 sum|t| of a
- * rounding midpoint, so it does not depend on the order of the terms.
+/* Exact sum of doubles, rounded once (a long accumulator).  Every finite
+ * double is an integer multiple of 2^-1074, so a sum of them is V 2^-1074
+ * with V an integer; V is held in base-2^32 digits (int64 cells with room
+ * for the carries of 2^30 additions), and the result is V rounded to 53
+ * significant bits, ties to even, times 2^-1074: the correctly rounded sum,
+ * the same whatever the order of the terms.
  * READING: the background update's sums over neighbours (the logarithms of
  * the sizes in the grading, h_j and the shift terms in the smoothing) are set
- * sums; they are taken this way so that the update is a function of the
- * particle set alone, whatever the slot order. */
-typedef struct { double s, c; } or_sum2;
+ * sums.  They are taken correctly rounded, so that the update is a function
+ * of the particle set alone, whatever the slot order: near-cancelling shift
+ * terms (a particle on a symmetry line) round differently in different
+ * orders even when compensated, and the repeated update can amplify that. */
+#define OR_XS_N 70
+typedef struct { int64_t d[OR_XS_N]; } or_xsum;
 
-static void sum2_add(or_sum2* a, double x)
+static void xsum_init(or_xsum* a) { memset(a->d, 0, sizeof(a->d)); }
+
+static void xsum_add(or_xsum* a, double x)
 {
-    double t = a->s + x;
-    double z = t - a->s;
-    a->c += (a->s - (t - z)) + (x - z);
-    a->s = t;
+    if (x == 0.0) return;
+    uint64_t bits;
+    memcpy(&bits, &x, sizeof(bits));
+    int neg = (int)(bits >> 63);
+    int E = (int)((bits >> 52) & 0x7ff);
+    uint64_t m = bits & ((1ull << 52) - 1);
+    int p = 0;                   /* x = m 2^(p - 1074) */
+    if (E > 0) { m |= 1ull << 52; p = E - 1; }
+    int k = p / 32, sft = p % 32;
+    uint64_t lo = (m & 0xffffffffull) << sft;  /* < 2^63 */
+    uint64_t hi = (m >> 32) << sft;            /* < 2^52 */
+    int64_t c0 = (int64_t)(lo & 0xffffffffull);
+    int64_t c1 = (int64_t)(lo >> 32) + (int64_t)(hi & 0xffffffffull);
+    int64_t c2 = (int64_t)(hi >> 32);
+    if (neg) { c0 = -c0; c1 = -c1; c2 = -c2; }
+    a->d[k] += c0;
+    a->d[k + 1] += c1;
+    a->d[k + 2] += c2;
 }
 
-static double sum2_get(const or_sum2* a) { return a->s + a->c; }
+/* digits to [0, 2^32) from the bottom up, the top cell keeping the sign */
+static void xsum_carry(int64_t* d)
+{
+    for (int k = 0; k < OR_XS_N - 1; ++k) {
+        int64_t c = d[k] >> 32;  /* floor(d / 2^32) */
+        d[k] -= c * 4294967296LL;
+        d[k + 1] += c;
+    }
+}
+
+static int xsum_bit(const int64_t* d, int i) { return (int)((d[i / 32] >> (i % 32)) & 1); }
+
+static double xsum_get(const or_xsum* a)
+{
+    int64_t d[OR_XS_N];
+    memcpy(d, a->d, sizeof(d));
+    xsum_carry(d);
+    int neg = d[OR_XS_N - 1] < 0;
+    if (neg) {  /* |V| */
+        for (int k = 0; k < OR_XS_N; ++k) d[k] = -d[k];
+        xsum_carry(d);
+    }
+    int nb = 0;  /* bit length of |V| */
+    for (int i = 32 * OR_XS_N - 1; i >= 0; --i)
+        if (xsum_bit(d, i)) { nb = i + 1; break; }
+    if (nb == 0) return 0.0;
+    int drop = nb > 53 ? nb - 53 : 0;
+    double t = 0.0;  /* the kept 53 (or fewer) bits, exact */
+    for (int i = nb - 1; i >= drop; --i) t = 2.0 * t + (double)xsum_bit(d, i);
+    if (drop > 0 && xsum_bit(d, drop - 1)) {
+        int sticky = 0;
+        for (int i = 0; i < drop - 1 && !sticky; ++i) sticky = xsum_bit(d, i);
+        if (sticky || fmod(t, 2.0) == 1.0) t += 1.0;  /* above half, or a tie to even */
+    }
+    double r = ldexp(t, drop - 1074);
+    return neg ? -r : r;
+}
+
+/* The exact sum of n doubles, rounded once (pinned against Python's
+ * correctly rounded math.fsum). */
+double or_exact_sum(int64_t n, const double* x)
+{
+    or_xsum a;
+    xsum_init(&a);
+    for (int64_t i = 0; i < n; ++i) xsum_add(&a, x[i]);
+    return xsum_get(&a);
+}
 
 /* The limited shift of background particle b (eqs. shift-deltar and
- * shift-limit, the same terms as shift_one) with the sums compensated. */
+ * shift-limit, the same terms as shift_one) with the sums correctly
+ * rounded. */
 static void bg_shift_one(const or_domain* d, double rho0, int64_t b, const double* x,
                          const double* y, const double* h, const double* m,
                          const int64_t* rp, const int32_t* col, double* dxs, double* dys)
 {
     double fxi = or_kf(OR_XI);
-    or_sum2 sx = {0.0, 0.0}, sy = {0.0, 0.0};
+    or_xsum sx, sy;
+    xsum_init(&sx);
+    xsum_init(&sy);
     for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
         int64_t j = col[k];
         double dx = mi_axis(d, 0, x[b] - x[j]);
@@ -1725,11 +1795,11 @@ static void bg_shift_one(const or_domain* d, double rho0, int64_t b, const doubl
         double wr = or_kf(r / hij) / fxi;
         double coef = (m[j] / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
         double t = coef * (or_dwdr(r, hij) / r);
-        sum2_add(&sx, t * dx);
-        sum2_add(&sy, t * dy);
+        xsum_add(&sx, t * dx);
+        xsum_add(&sy, t * dy);
     }
     double pref = -0.5 * (h[b] * h[b]);
-    double ddx = pref * sum2_get(&sx), ddy = pref * sum2_get(&sy);
+    double ddx = pref * xsum_get(&sx), ddy = pref * xsum_get(&sy);
     double mag = sqrt(ddx * ddx + ddy * ddy);
     double lim = 0.25 * h[b];
     if (mag > lim) {
@@ -1770,14 +1840,15 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
     for (int64_t b = 0; b < nb; ++b) {
         if (bmask[b]) { nds[b] = bds[b]; continue; }
         double mn = bds[col[rp[b]]], mx = mn;
-        or_sum2 sl = {0.0, 0.0};
+        or_xsum sl;
+        xsum_init(&sl);
         for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
             double s = bds[col[k]];
             if (s < mn) mn = s;
             if (s > mx) mx = s;
-            sum2_add(&sl, log(s));
+            xsum_add(&sl, log(s));
         }
-        double geo = exp(sum2_get(&sl) / (double)(rp[b + 1] - rp[b]));
+        double geo = exp(xsum_get(&sl) / (double)(rp[b + 1] - rp[b]));
         double nv = (mx / mn < cr3) ? B->cr * mn : geo;
         if (nv < B->ds_min) nv = B->ds_min;
         if (nv > B->ds_max) nv = B->ds_max;
@@ -1829,9 +1900,10 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
 #pragma omp parallel for schedule(dynamic, 256)
         for (int64_t b = 0; b < nb; ++b) {
             double N = (double)(rp[b + 1] - rp[b]);
-            or_sum2 sh_ = {0.0, 0.0};
-            for (int64_t k = rp[b]; k < rp[b + 1]; ++k) sum2_add(&sh_, bh[col[k]]);
-            nh[b] = 0.5 * ((bh[b] / 2.0) * (1.0 + sqrt(B->n_r / N)) + sum2_get(&sh_) / N);
+            or_xsum sh_;
+            xsum_init(&sh_);
+            for (int64_t k = rp[b]; k < rp[b + 1]; ++k) xsum_add(&sh_, bh[col[k]]);
+            nh[b] = 0.5 * ((bh[b] / 2.0) * (1.0 + sqrt(B->n_r / N)) + xsum_get(&sh_) / N);
             bg_shift_one(d, B->rho0, b, bx, by, bh, m, rp, col, &ddx[b], &ddy[b]);
         }
         for (int64_t b = 0; b < nb; ++b) {

@@ -23,7 +23,8 @@ def zone(orc):
     bg = s["background"]
     prm = orc.BgPrm(cr=bp["cr"], ds_min=bp["ds_min"], ds_max=bp["ds_max"], mass_q=bg["mass_q"])
     dom = orc.Dom((0.0, 0.0), (1.0, 1.0), (True, True))
-    out, nsplit = orc.bg_update(dom, prm, bg, s["markers"], bp["passes"], cap=200000)
+    passes = orc.bg_init_passes(bp["ds_min"], bp["ds_max"], bp["cr"])
+    out, nsplit = orc.bg_update(dom, prm, bg, s["markers"], passes, cap=200000)
     return s, out, nsplit, dom
 
 
@@ -33,14 +34,15 @@ def _zone_dist(x, y, zone):
                     np.maximum(np.maximum(y0 - y, y - y1), 0.0))
 
 
-def test_zone_background(zone):
+def test_zone_background(orc, zone):
     """Markers filling [0.1, 0.5]^2 at ds_min = dx/2 act as a body: every
     background particle in the zone asks for ds_min, sizes grow by C_r per
     level away from it up to ds_max, and the background mass is conserved."""
     s, out, nsplit, _ = zone
     bp = s["bg_params"]
     ds, x, y = out["ds"], out["x"], out["y"]
-    assert bp["passes"] == 12 and nsplit > 0
+    # ln 2 / ln 1.2 = 3.80: four size levels, three passes each
+    assert orc.bg_init_passes(bp["ds_min"], bp["ds_max"], bp["cr"]) == 12 and nsplit > 0
     assert out["mq"].sum() == s["background"]["mq"].sum()
     d = _zone_dist(x, y, s["zone"])
     assert np.all(ds[d == 0.0] == bp["ds_min"]) and np.all(out["mask"][d == 0.0] == 1)
