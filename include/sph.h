@@ -122,6 +122,12 @@ typedef struct sph_config {
                                never) */
     int32_t bg_passes;      /* passes of each background update (1 suffices
                                for small motions, section 3.3) */
+    int32_t csr_k;          /* entries per particle of capacity of the
+                               internal neighbour lists of the adaptation
+                               (0 = 160); a call that needs more returns
+                               SPH_E_NOMEM and names the csr_k that fits.
+                               The background update walks the cells and has
+                               no such limit. */
 } sph_config;
 
 /* Caller-owned particle set (device pointers, see conventions). kind may be
@@ -294,6 +300,9 @@ int sph_mref_lookup(sph_ctx *ctx, const sph_particles *ps, const sph_background 
  * neighbour mass.  If bg is non-NULL, m_ref is looked up first.
  * Two-phase: when the split needs more than ps->capacity slots, returns
  * SPH_E_CAPACITY with map->n_required set and the state untouched.
+ * SPH_E_NOMEM when the neighbour list of a shift or of the h update needs
+ * more than cfg->csr_k entries per particle of capacity (the message names
+ * the csr_k that fits); the split and merges have then been applied.
  * Updates ps->n on the host.  Synchronises. */
 int sph_adapt(sph_ctx *ctx, sph_particles *ps, const sph_background *bg, sph_adapt_map *map);
 
@@ -305,9 +314,21 @@ int sph_adapt(sph_ctx *ctx, sph_particles *ps, const sph_background *bg, sph_ada
  * children keep it) and are refined like particles near a body; without
  * phi no particle is marked.  mask becomes 0, 1 (near a solid) or 3
  * (marked).  Updates bg->n.  *nsplit receives the number of splits.
+ * The sweeps walk the cells of the background's own neighbour build, so a
+ * background particle may have any number of neighbours; their sums over
+ * neighbours (log-sizes, h_j, shift terms) are compensated (a TwoSum
+ * cascade), which makes the update a function of the particle set, not of
+ * the slot order.  SPH_E_CAPACITY when a split needs more than
+ * bg->capacity slots (bg->n then holds the count before that split).
  * Synchronises. */
 int sph_bg_update(sph_ctx *ctx, sph_background *bg, const sph_particles *solids,
                   const double *phi, double phi_thresh, int32_t passes, int64_t *nsplit);
+
+/* Passes of the background initialisation of section 3.3: from particles
+ * at ds_max, the update is repeated 3 ceil(ln(ds_max / ds_min) / ln C_r)
+ * times (three per size level).  Returns 0 for a configuration without a
+ * valid range (ds_min <= 0, ds_max < ds_min or C_r <= 1). */
+int32_t sph_bg_init_passes(const sph_config *cfg);
 
 /* Vorticity of every particle (solution adaptivity, section 3.3):
  * omega_i = sum_j (m_j/rho_j) [(v_j - v_i) dW/dx - (u_j - u_i) dW/dy] at

@@ -50,7 +50,7 @@ class sph_config(C.Structure):
                 ("wall_accel", C.c_double * 2), ("list_k", C.c_int32), ("lean", C.c_int32),
                 ("list_skin", C.c_double), ("io_mode", C.c_int32), ("io_ref", C.c_double * 3),
                 ("dt", C.c_double), ("sol_k", C.c_double), ("n_adapt", C.c_int32),
-                ("n_bg", C.c_int32), ("bg_passes", C.c_int32)]
+                ("n_bg", C.c_int32), ("bg_passes", C.c_int32), ("csr_k", C.c_int32)]
 
 
 class sph_particles(C.Structure):
@@ -107,7 +107,7 @@ class sph_diag(C.Structure):
 EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "sph_last_error",
            "sph_set_stream", "sph_build_neighbors", "sph_rates", "sph_pec", "sph_step",
            "sph_timestep", "sph_set_iteration", "sph_iteration", "sph_mref_lookup",
-           "sph_adapt", "sph_bg_update", "sph_inout", "sph_diagnostics", "sph_body_force", "sph_move_solids",
+           "sph_adapt", "sph_bg_update", "sph_bg_init_passes", "sph_inout", "sph_diagnostics", "sph_body_force", "sph_move_solids",
            "sph_export_bytes", "sph_export", "sph_import",
            "sph_profile_enable",
            "sph_profile_read", "sph_profile_reset", "sph_vorticity", "sph_bg_update_solution", "sph_step_inout",
@@ -145,6 +145,7 @@ def load_library(path: str = LIB_PATH):
         "sph_mref_lookup": (C.c_int, [P, P, P]),
         "sph_adapt": (C.c_int, [P, P, P, P]),
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
+        "sph_bg_init_passes": (I32, [P]),
         "sph_inout": (C.c_int, [P, P, P, P]),
         "sph_vorticity": (C.c_int, [P, P, P]),
         "sph_step_inout": (C.c_int, [P, P, D, I32, P, P]),
@@ -222,6 +223,7 @@ class Config:
     n_adapt: int = 0
     n_bg: int = 0
     bg_passes: int = 1
+    csr_k: int = 0
 
     def c(self) -> sph_config:
         s = sph_config()
@@ -235,7 +237,7 @@ class Config:
         for k in ("h_lo", "h_hi", "rho0", "cs", "nu", "alpha_e", "hdx", "u_ref", "split_alpha",
                   "split_eps", "mmax_f", "mmin_f", "mass_q", "merge_iters", "shift_iters", "cr",
                   "ds_min", "ds_max", "n_r", "bg_smooth_iters", "bg_mass_q", "list_k", "lean", "list_skin",
-                  "io_mode", "dt", "sol_k", "n_adapt", "n_bg", "bg_passes"):
+                  "io_mode", "dt", "sol_k", "n_adapt", "n_bg", "bg_passes", "csr_k"):
             setattr(s, k, getattr(self, k))
         return s
 
@@ -693,6 +695,12 @@ def timestep(cfg: Config, h_min: float = 0.0) -> float:
     """eq. (timestep) for the configuration (sph_timestep); h_min <= 0 takes
     cfg.h_lo."""
     return float(load_library().sph_timestep(C.byref(cfg.c()), float(h_min)))
+
+
+def bg_init_passes(cfg: Config) -> int:
+    """Passes of the background initialisation from ds_max (section 3.3,
+    sph_bg_init_passes): 3 ceil(ln(ds_max/ds_min) / ln C_r)."""
+    return int(load_library().sph_bg_init_passes(C.byref(cfg.c())))
 
 
 def config_for(domain, params: dict, h_lo: float, h_hi: float, precision=SPH_FP64,

@@ -384,45 +384,6 @@ __global__ __launch_bounds__(256) void k_merge_apply(Grid g, int n, FluidState s
 // Shift + Taylor correction, h update (CSR rows in ascending slot order)
 // ---------------------------------------------------------------------------
 
-// Limited Lind shift of particle i over its row, eqs. (shift-deltar) and
-// (shift-limit), with volume m_j / rho0 and the gradient at h_ij.
-__device__ __forceinline__ void shift_row(const Grid& g, int i, const int64_t* __restrict__ rp,
-                                          const int32_t* __restrict__ col,
-                                          const double* __restrict__ x,
-                                          const double* __restrict__ y,
-                                          const double* __restrict__ h,
-                                          const int64_t* __restrict__ mq, double q, double rho0,
-                                          double* ox, double* oy)
-{
-    const double fxi = kern_f<double>(SPH_XI);
-    double sx = 0.0, sy = 0.0;
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-        const int j = col[k];
-        const double dx = mi_axis(g, 0, x[i] - x[j]);
-        const double dy = mi_axis(g, 1, y[i] - y[j]);
-        const double r = sqrt(dx * dx + dy * dy);
-        if (r <= 0.0) continue;
-        const double hij = 0.5 * (h[i] + h[j]);
-        const double wr = kern_f<double>(r / hij) / fxi;
-        const double mj = (double)mq[j] * q;
-        const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
-        const double t = coef * (kern_dw64(r, hij) / r);
-        sx = sx + t * dx;
-        sy = sy + t * dy;
-    }
-    const double pref = -0.5 * (h[i] * h[i]);
-    double ddx = pref * sx, ddy = pref * sy;
-    const double mag = sqrt(ddx * ddx + ddy * ddy);
-    const double lim = 0.25 * h[i];
-    if (mag > lim) {
-        const double th = lim / mag;
-        ddx = ddx * th;
-        ddy = ddy * th;
-    }
-    *ox = ddx;
-    *oy = ddy;
-}
-
 // Per-slot records for the shift and h-update sweeps, so that a neighbour
 // costs two 32-byte loads: A = {x, y, h, m}, B = {u, v, p, rho} (m = mq q,
 // the same double the oracle uses).
@@ -697,9 +658,15 @@ static int internal_csr(sph_ctx* c, int n, const double* x, const double* y, con
     if (rc) return rc;
     int64_t nnz = 0;
     rc = nbr_export_csr(c, n, w.rp_tmp, w.col_tmp, w.col_cap, &nnz, sf);
-    if (rc == SPH_E_CAPACITY)
-        set_err(c, "internal neighbour list needs %lld entries (limit %lld)", (long long)nnz,
-                (long long)w.col_cap);
+    if (rc == SPH_E_CAPACITY) {
+        // the count pass gave the size: the workspace is short of that
+        const int64_t k = cdiv(nnz, w.capacity > 0 ? w.capacity : 1);
+        set_err(c,
+                "internal neighbour list needs %lld entries (%lld bytes), the workspace holds "
+                "%lld: create the context with csr_k >= %lld",
+                (long long)nnz, (long long)(4 * nnz), (long long)w.col_cap, (long long)k);
+        rc = SPH_E_NOMEM;
+    }
     return rc;
 }
 
@@ -847,7 +814,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
     if (n > 0) {
         rc = build_super(cf.shift_iters, cf.shift_iters > 0);
         if (rc == SPH_OK) super = true;
-        else if (rc != SPH_E_CAPACITY) return rc;
+        else if (rc != SPH_E_NOMEM) return rc;  // a superset that does not fit: exact lists
     }
     unsigned long long* dmax = (unsigned long long*)(w.ctr + 4);
     // each shift first filters its rows into the rate-list buffer (free
@@ -951,6 +918,95 @@ __global__ __launch_bounds__(256) void k_bg_mask(Grid g, NbrView nv, int nb,
     if (m) ds[b] = ds_min;
 }
 
+// Long accumulator: the exact sum of doubles, rounded once.  A finite
+// double is an integer multiple of 2^-1074, so the sum is V 2^-1074 with V
+// an integer, kept here as signed base-2^32 digits in int64 cells (each
+// addition puts at most 2^33 into a cell, so 2^30 additions never overflow
+// one).  get() returns V rounded to 53 significant bits, ties to even, times
+// 2^-1074: the correctly rounded sum, the same in any order of the terms.
+// The cells live in private memory (about 560 bytes per accumulator); the
+// background sweeps that use it are not on the stepping path.
+struct XSum {
+    static constexpr int NC = 70;
+    long long d[NC];
+    __device__ __forceinline__ XSum()
+    {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) d[i] = 0;
+    }
+    __device__ __forceinline__ void add(double x)
+    {
+        if (x == 0.0) return;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+        const int ex = (int)((bits >> 52) & 0x7ff);
+        unsigned long long m = bits & 0xfffffffffffffull;
+        int p = 0;  // x = m 2^(p - 1074)
+        if (ex != 0) {
+            m |= 1ull << 52;
+            p = ex - 1;
+        }
+        const int k = p >> 5, sh = p & 31;
+        const unsigned long long a = (m & 0xffffffffull) << sh, b = (m >> 32) << sh;
+        long long c0 = (long long)(a & 0xffffffffull);
+        long long c1 = (long long)((a >> 32) + (b & 0xffffffffull));
+        long long c2 = (long long)(b >> 32);
+        if (bits >> 63) {
+            c0 = -c0;
+            c1 = -c1;
+            c2 = -c2;
+        }
+        d[k] += c0;
+        d[k + 1] += c1;
+        d[k + 2] += c2;
+    }
+    // cells to digits in [0, 2^32), the last cell keeping the sign
+    __device__ __forceinline__ void normalise()
+    {
+        for (int i = 0; i < NC - 1; ++i) {
+            const long long c = d[i] >> 32;
+            d[i] &= 0xffffffffll;
+            d[i + 1] += c;
+        }
+    }
+    __device__ double get()
+    {
+        normalise();
+        const bool neg = d[NC - 1] < 0;
+        if (neg) {
+            for (int i = 0; i < NC; ++i) d[i] = -d[i];
+            normalise();
+        }
+        int t = NC - 1;
+        while (t >= 0 && d[t] == 0) --t;
+        if (t < 0) return 0.0;
+        const unsigned long long top = (unsigned long long)d[t];
+        const int bl = 64 - __clzll(top);  // bits of the top digit
+        const int nb = 32 * t + bl;         // bits of |V|
+        double r;
+        if (nb <= 53) {
+            const unsigned long long v = (t > 0 ? (unsigned long long)d[1] << 32 : 0ull) |
+                                         (unsigned long long)d[0];
+            r = ldexp((double)v, -1074);
+        } else {
+            // 96-bit window of the top three digits; what lies below it only
+            // decides a tie
+            const unsigned long long w_hi = top;
+            const unsigned long long d1 = t >= 1 ? (unsigned long long)d[t - 1] : 0ull;
+            const unsigned long long d2 = t >= 2 ? (unsigned long long)d[t - 2] : 0ull;
+            const unsigned long long w_lo = (d1 << 32) | d2;
+            const int cut = bl + 11;  // window bits below the 53 kept
+            unsigned long long kept = (w_hi << (64 - cut)) | (w_lo >> cut);
+            const unsigned long long rem = w_lo & ((1ull << cut) - 1);
+            const unsigned long long half = 1ull << (cut - 1);
+            bool below = false;
+            for (int i = 0; i < t - 2 && !below; ++i) below = d[i] != 0;
+            if (rem > half || (rem == half && (below || (kept & 1ull)))) ++kept;
+            r = ldexp((double)kept, nb - 53 - 1074);
+        }
+        return neg ? -r : r;
+    }
+};
+
 __global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
                                                   const int32_t* __restrict__ mask,
                                                   const double* __restrict__ ds, double cr,
@@ -963,18 +1019,19 @@ __global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
         nds[b] = ds[b];
         return;
     }
-    double mn = 0.0, mx = 0.0, sl = 0.0;
+    double mn = 0.0, mx = 0.0;
+    XSum sl;  // the walk is not in slot order: the sum of logs is rounded once
     int cnt = 0;
     for_each_neighbor(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]),
                       [&](int js, double, double, double, double) {
                           const double v = ds[nv.perm[js]];
                           if (cnt == 0 || v < mn) mn = v;
                           if (cnt == 0 || v > mx) mx = v;
-                          sl += log(v);
+                          sl.add(log(v));
                           ++cnt;
                       });
     const double cr3 = cr * cr * cr;
-    const double geo = exp(sl / (double)cnt);
+    const double geo = exp(sl.get() / (double)cnt);
     double v = (mx / mn < cr3) ? cr * mn : geo;
     if (v < ds_min) v = ds_min;
     if (v > ds_max) v = ds_max;
@@ -1026,19 +1083,54 @@ __global__ __launch_bounds__(256) void k_bg_split_apply(Grid g, int nb, sph_back
     B.h[b] = hc;
 }
 
-__global__ __launch_bounds__(256) void k_bg_smooth(Grid g, int nb, sph_background B,
-                                                   const int64_t* __restrict__ rp,
-                                                   const int32_t* __restrict__ col, double q,
-                                                   double rho0, double n_r, double* nh,
-                                                   double* ddx, double* ddy)
+// Background h smoothing and shifting, section 3.3: the new h is the mean of
+// the target from the neighbour count and the neighbours' mean h; the shift
+// is the limited Lind shift of eqs. (shift-deltar) and (shift-limit) with
+// volume m_j / rho0 and the gradient at h_ij.  One thread per particle in the
+// sorted order sp (slot b) of the background's own build, walking its cells:
+// no neighbour list, so a particle may have any number of neighbours (a
+// coarse particle among fine ones early in the initial passes has
+// thousands).  The walk order is not the slot order, so the sums over
+// neighbours (of h_j and of the shift terms) are exact sums rounded once
+// (XSum): their results follow from the neighbour set alone.
+__global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int nb, sph_background B,
+                                                        double q, double rho0, double n_r, double* nh,
+                                                        double* ddx, double* ddy)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const double N = (double)(rp[b + 1] - rp[b]);
-    double sh = 0.0;
-    for (int64_t k = rp[b]; k < rp[b + 1]; ++k) sh += B.h[col[k]];
-    nh[b] = 0.5 * ((B.h[b] / 2.0) * (1.0 + sqrt(n_r / N)) + sh / N);
-    shift_row(g, b, rp, col, B.x, B.y, B.h, B.mq, q, rho0, &ddx[b], &ddy[b]);
+    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (sp >= nb) return;
+    const int b = nv.perm[sp];
+    const double xb = nv.xs[sp], yb = nv.ys[sp], hb = nv.hs[sp];
+    const double fxi = kern_f<double>(SPH_XI);
+    XSum sh, sx, sy;
+    int cnt = 0;
+    for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[sp]),
+                      [&](int js, double dx, double dy, double r2, double hj) {
+                          ++cnt;
+                          sh.add(hj);
+                          const double r = sqrt(r2);
+                          if (r <= 0.0) return;
+                          const double hij = 0.5 * (hb + hj);
+                          const double wr = kern_f<double>(r / hij) / fxi;
+                          const double mj = (double)B.mq[nv.perm[js]] * q;
+                          const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+                          const double t = coef * (kern_dw64(r, hij) / r);
+                          sx.add(t * dx);
+                          sy.add(t * dy);
+                      });
+    const double N = (double)cnt;
+    nh[b] = 0.5 * ((hb / 2.0) * (1.0 + sqrt(n_r / N)) + sh.get() / N);
+    const double pref = -0.5 * (hb * hb);
+    double dxs = pref * sx.get(), dys = pref * sy.get();
+    const double mag = sqrt(dxs * dxs + dys * dys);
+    const double lim = 0.25 * hb;
+    if (mag > lim) {
+        const double th = lim / mag;
+        dxs = dxs * th;
+        dys = dys * th;
+    }
+    ddx[b] = dxs;
+    ddy[b] = dys;
 }
 
 __global__ __launch_bounds__(256) void k_bg_smooth_apply(Grid g, int nb, sph_background B,
@@ -1100,13 +1192,13 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
         LAUNCHCHK(c, "bg_split");
         *nsplit += cnt;
         nb += 6 * cnt;
-        // step 4: h smoothing + shifting
+        // step 4: h smoothing + shifting (a cell walk: rows of any length)
         for (int it = 0; it < cf.bg_smooth_iters; ++it) {
-            rc = internal_csr(c, nb, bg->x, bg->y, bg->h);
+            rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
             if (rc) return rc;
             unsigned nbk2 = (unsigned)cdiv(nb, 256);
-            hipLaunchKernelGGL(k_bg_smooth, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
-                               w.rp_tmp, w.col_tmp, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
+            hipLaunchKernelGGL(k_bg_smooth_walk, dim3(nbk2), dim3(256), 0, c->stream, c->grid,
+                               nbr_view(c), nb, *bg, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
                                w.tmp_d[1], w.tmp_d[2]);
             hipLaunchKernelGGL(k_bg_smooth_apply, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
                                w.tmp_d[0], w.tmp_d[1], w.tmp_d[2]);

@@ -30,7 +30,8 @@ int check_hip(sph_ctx* c, hipError_t e, const char* what)
 }
 
 // Carves the workspace.  With base == NULL only the size is computed.
-static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, int list_k)
+static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, int list_k,
+                    int csr_k = COL_PER_PARTICLE)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void* {
@@ -79,7 +80,7 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
     // adaptation, background and inlet/outlet buffers (not in a lean workspace)
     const int64_t CA = lean ? 0 : C;
     w->rp_tmp = lean ? nullptr : (int64_t*)take(8 * (C + 1));
-    w->col_cap = COL_PER_PARTICLE * CA;
+    w->col_cap = (int64_t)csr_k * CA;
     w->col_tmp = lean ? nullptr : (int32_t*)take(4 * w->col_cap);
     w->flag = lean ? nullptr : (int32_t*)take(4 * (C + 1));
     w->closest = lean ? nullptr : (int32_t*)take(4 * C);
@@ -130,6 +131,7 @@ static int check_cfg(const sph_config* cfg)
     if (!(cfg->dt >= 0.0) || !isfinite(cfg->dt) || !(cfg->sol_k >= 0.0) || !isfinite(cfg->sol_k))
         return 0;
     if (cfg->n_adapt < 0 || cfg->n_bg < 0 || cfg->bg_passes < 0) return 0;
+    if (cfg->csr_k < 0 || cfg->csr_k > 65536) return 0;
     return 1;
 }
 
@@ -145,11 +147,20 @@ double timestep_of(const sph_config& cfg, double h_min)
     return dt;
 }
 
+extern "C" int32_t sph_bg_init_passes(const sph_config* cfg)
+{
+    if (!cfg || !(cfg->ds_min > 0.0) || !(cfg->ds_max >= cfg->ds_min) || !(cfg->cr > 1.0)) return 0;
+    const double levels = log(cfg->ds_max / cfg->ds_min) / log(cfg->cr);
+    return 3 * (int32_t)ceil(levels - 1e-12);
+}
+
 extern "C" double sph_timestep(const sph_config* cfg, double h_min)
 {
     if (!check_cfg(cfg) || !(cfg->u_ref + cfg->cs > 0)) return 0.0;
     return timestep_of(*cfg, h_min);
 }
+
+static int csr_k_of(const sph_config* cfg) { return cfg->csr_k > 0 ? cfg->csr_k : COL_PER_PARTICLE; }
 
 extern "C" int sph_version(void) { return SPH_VERSION; }
 
@@ -159,7 +170,8 @@ extern "C" size_t sph_workspace_bytes(const sph_config* cfg, int64_t capacity)
     Grid g;
     grid_setup(cfg, &g);
     Work w;
-    return carve(&w, nullptr, g, capacity, cfg->lean, cfg->list_k > 0 ? cfg->list_k : NL_K);
+    return carve(&w, nullptr, g, capacity, cfg->lean, cfg->list_k > 0 ? cfg->list_k : NL_K,
+                 csr_k_of(cfg));
 }
 
 __global__ void k_init_counters(int32_t* status, unsigned long long* ctr)
@@ -254,12 +266,12 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->capacity = capacity;
     c->stream = (hipStream_t)stream;
     const int lk = cfg->list_k > 0 ? cfg->list_k : NL_K;
-    size_t need = carve(&c->w, nullptr, c->grid, capacity, cfg->lean, lk);
+    size_t need = carve(&c->w, nullptr, c->grid, capacity, cfg->lean, lk, csr_k_of(cfg));
     if (!workspace || workspace_bytes < need || ((uintptr_t)workspace & 255)) {
         free(c);
         return SPH_E_NOMEM;
     }
-    carve(&c->w, (char*)workspace, c->grid, capacity, cfg->lean, lk);
+    carve(&c->w, (char*)workspace, c->grid, capacity, cfg->lean, lk, csr_k_of(cfg));
     void* mb = nullptr;
     if (hipHostMalloc(&mb, MBOX_WORDS * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess ||

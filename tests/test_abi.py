@@ -94,3 +94,23 @@ def test_timestep_matches_oracle(orc):
     assert P.timestep(cfg) == pytest.approx(0.25 * s["h_min"] / (s["u_ref"] + prm["cs"]),
                                             rel=4e-16)
     assert P.timestep(P.Config(h_lo=0.01, h_hi=0.01, cs=-1.0, u_ref=1.0)) == 0.0
+
+
+def test_bg_init_passes_matches_oracle(orc):
+    """sph_bg_init_passes (the initialisation's pass count of section 3.3, a
+    host computation) equals the oracle's: 3 per size level, an exact power
+    of C_r not rounded up a level, and 0 without a valid range."""
+    import paper_2107_01276_amd as P
+    lib_path = os.path.join(ROOT, "paper_2107_01276_amd", "libsph.so")
+    if not os.path.exists(lib_path):
+        pytest.skip("libsph.so not built")
+    for ds_min, ds_max, cr in ((0.01, 0.64, 1.05), (0.0025, 0.25, 1.05), (0.01, 2.5, 1.05),
+                               (0.1, 0.4, 1.2), (0.01, 0.02, 1.2), (0.1, 0.1, 1.2)):
+        cfg = P.Config(h_lo=0.01, h_hi=0.01, ds_min=ds_min, ds_max=ds_max, cr=cr)
+        assert P.bg_init_passes(cfg) == orc.bg_init_passes(ds_min, ds_max, cr), (ds_min, ds_max)
+    # ln 64 / ln 1.05 = 85.24: 86 levels; 1.2^2 = 1.44 exactly two levels
+    assert P.bg_init_passes(P.Config(h_lo=0.01, h_hi=0.01, ds_min=0.01, ds_max=0.64, cr=1.05)) == 258
+    assert P.bg_init_passes(P.Config(h_lo=0.01, h_hi=0.01, ds_min=0.25, ds_max=0.36, cr=1.2)) == 6
+    for bad in (dict(ds_min=0.0, ds_max=1.0, cr=1.05), dict(ds_min=0.5, ds_max=0.1, cr=1.05),
+                dict(ds_min=0.1, ds_max=1.0, cr=1.0)):
+        assert P.bg_init_passes(P.Config(h_lo=0.01, h_hi=0.01, **bad)) == 0

@@ -21,7 +21,8 @@ def test_config_rejections():
     bad = ({"io_mode": 2}, {"io_ref": (math.nan, 0.0, 0.0)}, {"io_mode": 1, "cs": 0.0},
            {"hi": (0.0, 1.0)}, {"h_lo": 0.0}, {"list_skin": 1.5}, {"precision": 7},
            {"wall_accel": (math.inf, 0.0)}, {"merge_iters": 9}, {"lean": 2}, {"n_adapt": -1},
-           {"n_bg": -2}, {"dt": -1e-4}, {"sol_k": math.nan}, {"bg_passes": -1})
+           {"n_bg": -2}, {"dt": -1e-4}, {"sol_k": math.nan}, {"bg_passes": -1},
+           {"csr_k": -1}, {"csr_k": 70000})
     for b in bad:
         with pytest.raises(P.SphError) as e:
             P.Context(P.Config(**{**base, **b}), 16)
@@ -115,3 +116,26 @@ def test_ledger_overflow_reported():
     with pytest.raises(P.SphError) as e:
         ctx.diagnostics(ps)
     assert e.value.code == P.SPH_E_INVAL and "ledger" in str(e.value)
+
+
+def test_internal_list_width_reported():
+    """The adaptation's internal neighbour lists hold csr_k entries per
+    particle of capacity: with room for 4, a shift's list does not fit and
+    the call returns SPH_E_NOMEM naming the csr_k that does; the default
+    width adapts the same state."""
+    P = lib()
+    s = W.tgv(20, seed=3)
+    n = s["x"].size
+    s["mref"] = np.full(n, float(s["mq"][0]) * s["mass_q"])
+    print(f"[errors] csr_k n={n}", flush=True)
+    ctx = ctx_for(P, s, P.SPH_FP64, capacity=2 * n, csr_k=4)
+    ps = particles(P, s, capacity=2 * n)
+    with pytest.raises(P.SphError) as e:
+        ctx.adapt(ps)
+    assert e.value.code == P.SPH_E_NOMEM and "csr_k >=" in str(e.value)
+    k = int(str(e.value).split("csr_k >= ")[1].split()[0])
+    assert 5 <= k <= 200
+    ctx = ctx_for(P, s, P.SPH_FP64, capacity=2 * n, csr_k=k)
+    ps = particles(P, s, capacity=2 * n)
+    ctx.adapt(ps)
+    assert ps.n == n

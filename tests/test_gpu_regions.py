@@ -40,14 +40,17 @@ def test_zone_background_and_adaptation():
     P = lib()
     s = W.tgv_zone(50)
     bp, bg, dom = s["bg_params"], s["background"], s["domain"]
-    print(f"[zone] bg n={bg['x'].size} markers={s['markers']['x'].size} passes={bp['passes']}",
+    cfg = _bg_cfg(P, dom, bp, bg["mass_q"], s["mass_q"], 0.003, 0.05, hdx=1.0)
+    passes = oracle.bg_init_passes(bp["ds_min"], bp["ds_max"], bp["cr"])
+    assert P.bg_init_passes(cfg) == passes
+    print(f"[zone] bg n={bg['x'].size} markers={s['markers']['x'].size} passes={passes}",
           flush=True)
     obp = oracle.BgPrm(cr=bp["cr"], ds_min=bp["ds_min"], ds_max=bp["ds_max"], mass_q=bg["mass_q"])
-    ob, onsplit = oracle.bg_update(odom(dom), obp, bg, s["markers"], bp["passes"], cap=200000)
+    ob, onsplit = oracle.bg_update(odom(dom), obp, bg, s["markers"], passes, cap=200000)
     cap = 8 * s["x"].size
-    ctx = P.Context(_bg_cfg(P, dom, bp, bg["mass_q"], s["mass_q"], 0.003, 0.05, hdx=1.0), cap)
+    ctx = P.Context(cfg, cap)
     B = P.Background.from_arrays(bg, cap)
-    nsplit = ctx.bg_update(B, _solids(P, s["markers"]), bp["passes"])
+    nsplit = ctx.bg_update(B, _solids(P, s["markers"]), P.bg_init_passes(cfg))
     print(f"[zone] gpu bg n={B.n} splits={nsplit}; oracle n={ob['x'].size} splits={onsplit}",
           flush=True)
     assert nsplit == onsplit and B.n == ob["x"].size
@@ -122,7 +125,7 @@ def _tgv_run(P, nx, adaptive, T, re, every=10):
     M0 = int(s["mq"].sum())
     if adaptive:
         B = P.Background.from_arrays(s["background"], cap)
-        ctx.bg_update(B, _solids(P, s["markers"]), bp["passes"])
+        ctx.bg_update(B, _solids(P, s["markers"]), P.bg_init_passes(cfg))
         ctx.adapt(ps, B)
         ctx.adapt(ps, B)
     hm = float(ps.numpy()["h"].min())

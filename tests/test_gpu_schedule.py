@@ -76,7 +76,7 @@ def test_zone_schedule_with_background_updates():
         M = P.Particles.from_arrays({"x": s["markers"]["x"], "y": s["markers"]["y"],
                                      "h": s["markers"]["h"],
                                      "mq": np.ones(s["markers"]["x"].size, np.int64)})
-        ctx.bg_update(B, M, bp["passes"])
+        ctx.bg_update(B, M, P.bg_init_passes(cfg))
         ps = P.Particles.from_arrays(dict(s), cap)
         ctx.adapt(ps, B)
         return ctx, ps, B, M

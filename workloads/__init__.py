@@ -618,16 +618,14 @@ def tgv_zone(nx: int = 50, re: float = 200.0, zone=((0.1, 0.1), (0.5, 0.5)), rat
     fluid starts on the plain nx*nx lattice (dx_max = 1/nx, h = dx) with the
     exact fields; the background starts as a lattice at dx_max over the
     periodic square, and marker particles filling the zone at dx_max/ratio
-    ask for ds_min = dx_max/ratio there.  `bg_params` holds C_r, ds_min,
-    ds_max and the number of background passes of the initialisation,
-    3 ceil(ln(ds_max/ds_min)/ln C_r) (three passes per size level)."""
+    ask for ds_min = dx_max/ratio there.  `bg_params` holds C_r, ds_min and
+    ds_max."""
     s = tgv(nx, jitter=0.0, perturb=False, re=re, cs=cs, rho0=rho0)
     dx = 1.0 / nx
     s["background"] = background_lattice(s["domain"], dx, 1.2, rho0)
     s["markers"] = region_markers(zone[0], zone[1], dx / ratio)
     s["zone"] = zone
-    s["bg_params"] = {"cr": cr, "ds_min": dx / ratio, "ds_max": dx,
-                      "passes": 3 * math.ceil(math.log(ratio) / math.log(cr) - 1e-12)}
+    s["bg_params"] = {"cr": cr, "ds_min": dx / ratio, "ds_max": dx}
     return s
 
 
