@@ -6,9 +6,13 @@ Main workload (synthetic, seeded): the channel with a circular cylinder (D = 1,
 30D x 20D, periodic in y, inflow U = 1 through an inlet buffer with the
 characteristic inlet/outlet rule, finest spacing D/100, sizes graded by
 C_r = 1.05 per layer, h/dx = 1.2, Re = 100, wall particles inside the
-cylinder), ~2e5 particles, with a prescribed background (section 3.3) that
-sets the reference mass.  Before timing, the fluid is adapted four times to
-the background.  The timed loop is the library's per-iteration schedule
+cylinder), ~2e5 particles, with a prescribed background (section 3.3 lets
+the reference mass be assigned directly) that follows the fluid's grading.
+Before timing, the fluid is adapted four times to the background.  The
+configuration lines add the same channel adapted to the background the
+library builds from ds_max (3 ceil(ln 64 / ln C_r) = 258 passes of the
+background update; its grading is steeper and the fluid ends near 2.5e4
+particles), and the oscillating cylinder starting from its built background.  The timed loop is the library's per-iteration schedule
 (sph_step, the algorithm of section 3.4): one predict-evaluate-correct step
 (two rate evaluations) and the inlet/outlet update per iteration, and every
 `--adapt-every` iterations the adaptation (m_ref from the background, split,
@@ -46,6 +50,7 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
 ADAPT_WARM = 4
 PROF_EVERY = 4
+BG_CAPACITY = 4_000_000
 
 
 def parse():
@@ -112,6 +117,44 @@ def cpu_model():
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+def procedure_background(SPH, W, s, torch):
+    """The background of section 3.3 as the library builds it: a lattice at
+    ds_max, then sph_bg_init_passes passes of sph_bg_update around the
+    body's solid particles.  Returns the background (host arrays) and what
+    the build took."""
+    spec = s["spec"]
+    ds_max = spec.ds_min * spec.ratio
+    bg0 = W.background_lattice(s["domain"], ds_max, 1.2, spec.rho0)
+    d = s["domain"]
+    cfg = SPH.Config(lo=d.lo, hi=d.hi, periodic=d.periodic, h_lo=0.25 * spec.ds_min,
+                     h_hi=2.5 * ds_max, cr=spec.cr, ds_min=spec.ds_min, ds_max=ds_max,
+                     bg_mass_q=bg0["mass_q"], mass_q=s["mass_q"])
+    ctx = SPH.Context(cfg, BG_CAPACITY)
+    B = SPH.Background.from_arrays(bg0, BG_CAPACITY)
+    sol = s["kind"] == W.SOLID
+    S = SPH.Particles.from_arrays({k: s[k][sol] for k in ("x", "y", "h", "mq")})
+    passes = SPH.bg_init_passes(cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nsplit = ctx.bg_update(B, S, passes)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    bg = B.numpy()
+    bg["mass_q"] = bg0["mass_q"]
+    del ctx, B, S
+    torch.cuda.empty_cache()
+    return bg, {"passes": passes, "n_start": int(bg0["x"].size), "n": int(bg["x"].size),
+                "splits": nsplit, "build_ms": ms, "ds_min": spec.ds_min, "ds_max": ds_max,
+                "cr": spec.cr}
+
+
+def fluid_size_ratio(P, W):
+    """Largest over smallest fluid spacing sqrt(m / rho0) of the state."""
+    st = P.numpy()
+    m = st["mq"][st["kind"] == W.FLUID].astype(float)
+    return float((m.max() / m.min()) ** 0.5)
 
 
 def channel_cfg(SPH, s, bg, prec, skin, adapt_every):
@@ -254,7 +297,9 @@ def config_lines(SPH, W, torch):
     """The other configurations: C1 (2,500-particle Taylor-Green, FP64, 100
     steps, one simulation's latency), the 1.5e6-particle wake-refined 1:250
     channel (PEC steps with the characteristic inlet/outlet, both
-    precisions), and the oscillating cylinder (9.6e5 particles at the start;
+    precisions), the channel adapted to the background the library builds
+    from ds_max (the build timed; FP32 and FP64 steps), and the oscillating
+    cylinder (9.6e5 particles generated, adapted to its built background;
     the whole loop: body motion and a background pass every step,
     adaptation every 10 steps, inlet/outlet update)."""
     out = {}
@@ -295,23 +340,57 @@ def config_lines(SPH, W, torch):
                                           "pair_evals_per_s": 2.0 * pairs * steps / t}
         del ctx, P
         torch.cuda.empty_cache()
+    # C2 on the background the library builds from ds_max
+    s = W.channel_cylinder(seed=2)
+    bg, bgi = procedure_background(SPH, W, s, torch)
+    # the m_ref lookup builds the background's cells in the same context
+    cap = max(int(1.6 * s["x"].size), bg["x"].size)
+    line = {"background": bgi, "n_particles_generated": int(s["x"].size)}
+    for name, prec, steps in (("fp32", SPH.SPH_FP32, 40), ("fp64", SPH.SPH_FP64, 20)):
+        ctx, P, B = prepare(SPH, s, bg, prec, cap, 0.2, 10)
+        n_ad, ratio = P.n, fluid_size_ratio(P, W)
+        ctx.run(P, 5, bg=B, io=s["io"])
+        torch.cuda.synchronize()
+        pairs = count_pairs(ctx, P)
+        t0 = time.perf_counter()
+        ctx.run(P, steps, bg=B, io=s["io"])
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        line[name] = {"n_particles_adapted": n_ad, "n_particles": P.n, "fluid_size_ratio": ratio,
+                      "ms_per_step": t * 1e3 / steps, "pair_evals_per_s": 2.0 * pairs * steps / t}
+        del ctx, P, B
+        torch.cuda.empty_cache()
+    out["c2_channel_procedure_background"] = line
+    del bg
     # C5: the oscillating cylinder, whole loop
     s = W.oscillating_cylinder()
     mo = s["motion"]
-    bg = W.channel_background(s["spec"])
+    bg, bg5 = procedure_background(SPH, W, s, torch)
     cap = int(1.5 * s["x"].size)
     h_hi = max(float(s["h"].max()), float(bg["h"].max()))
     cfg = SPH.config_for(s["domain"], s["params"], float(s["h"].min()), h_hi,
                          precision=SPH.SPH_FP32, mass_q=s["mass_q"], list_skin=0.3, n_adapt=10,
                          n_bg=1, cr=s["spec"].cr, ds_min=s["spec"].ds_min,
                          ds_max=s["spec"].ds_min * s["spec"].ratio, bg_mass_q=bg["mass_q"])
-    ctx = SPH.Context(cfg, cap)
+    # the context also runs the per-step background pass: room for both sets
+    bcap = max(cap, int(1.2 * bg["x"].size))
+    ctx = SPH.Context(cfg, bcap)
     P = SPH.Particles.from_arrays(s, cap)
-    B = SPH.Background.from_arrays(bg, cap)
+    B = SPH.Background.from_arrays(bg, bcap)
     sol = s["kind"] == W.SOLID
     S = SPH.Particles.from_arrays({k: s[k][sol] for k in ("x", "y", "h", "mq")})
     dt = SPH.timestep(cfg)
     y0, t_sim = 0.0, 0.0
+    n_gen = P.n
+    for _ in range(ADAPT_WARM):
+        ctx.adapt(P, B)
+    n_ad = P.n
+    # one background pass alone (the loop runs one every step)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.bg_update(B, S, 1)
+    torch.cuda.synchronize()
+    bg_pass_ms = (time.perf_counter() - t0) * 1e3
 
     def advance(k):
         nonlocal y0, t_sim
@@ -330,9 +409,13 @@ def config_lines(SPH, W, torch):
     advance(steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    out["c5_oscillating_cylinder_fp32"] = {"n_particles_start": n0, "n_particles_end": P.n,
+    out["c5_oscillating_cylinder_fp32"] = {"n_particles_generated": n_gen,
+                                           "n_particles_adapted": n_ad,
+                                           "n_particles_start": n0, "n_particles_end": P.n,
                                            "ms_per_step": t * 1e3 / steps,
-                                           "background_n": B.n}
+                                           "background_pass_ms": bg_pass_ms,
+                                           "background_n_start": bg5["n"],
+                                           "background_n": B.n, "background": bg5}
     del ctx, P, B
     torch.cuda.empty_cache()
     return out
@@ -438,10 +521,13 @@ def main():
         else:
             tuning[name] = {"best": args.list_skin, "ms_per_step": None}
         ctx, P, B = prepare(SPH, s, bg, prec, cap, tuning[name]["best"], args.adapt_every)
+        n_adapted = P.n
+        ratio = fluid_size_ratio(P, W)
         ms, prof, pairs = run(ctx, P, B, s["io"], steps, args.warmup, torch)
         ms_step = ms / steps
         results[name] = {"ms_per_step": ms_step, "pairs": pairs, "n": P.n, "prof": prof,
-                         "pair_evals_per_s": 2.0 * pairs / (ms_step * 1e-3)}
+                         "pair_evals_per_s": 2.0 * pairs / (ms_step * 1e-3),
+                         "n_adapted": n_adapted, "size_ratio": ratio}
         del ctx, P, B
         torch.cuda.empty_cache()
 
@@ -474,12 +560,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "channel with cylinder, D/100, graded by C_r 1.05 (realised "
-                               "ratio about 1:22 inside the box, 1:64 cap), Re 100, adapt every "
-                               "10 steps from a prescribed background, characteristic "
-                               "inlet/outlet",
-                   "n_particles": r32["n"], "pairs_per_eval": r32["pairs"],
+        "config": {"workload": "channel 30D x 20D with cylinder, D/100, graded by C_r 1.05 per "
+                               "5 rows (1:64 cap), Re 100, adapt every 10 steps to a prescribed "
+                               "background, characteristic inlet/outlet",
+                   "n_particles": r32["n"], "n_particles_generated": n0,
+                   "n_particles_adapted": r32["n_adapted"],
+                   "fluid_size_ratio": r32["size_ratio"], "pairs_per_eval": r32["pairs"],
                    "adapt_every": args.adapt_every, "dt": dt},
+
         "fp64": {"value": results["fp64"]["pair_evals_per_s"],
                  "ms_per_step": results["fp64"]["ms_per_step"], "steps": args.fp64_steps},
         "fp32_over_fp64": r32["pair_evals_per_s"] / results["fp64"]["pair_evals_per_s"],

@@ -968,7 +968,7 @@ struct XSum {
             d[i + 1] += c;
         }
     }
-    __device__ double get()
+    __device__ bool get(double& out)
     {
         normalise();
         const bool neg = d[NC - 1] < 0;
@@ -978,7 +978,10 @@ struct XSum {
         }
         int t = NC - 1;
         while (t >= 0 && d[t] == 0) --t;
-        if (t < 0) return 0.0;
+        if (t < 0) {
+            out = 0.0;
+            return true;
+        }
         const unsigned long long top = (unsigned long long)d[t];
         const int bl = 64 - __clzll(top);  // bits of the top digit
         const int nb = 32 * t + bl;         // bits of |V|
@@ -1003,24 +1006,77 @@ struct XSum {
             if (rem > half || (rem == half && (below || (kept & 1ull)))) ++kept;
             r = ldexp((double)kept, nb - 53 - 1074);
         }
-        return neg ? -r : r;
+        out = neg ? -r : r;
+        return true;
     }
 };
 
-__global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
-                                                  const int32_t* __restrict__ mask,
-                                                  const double* __restrict__ ds, double cr,
-                                                  double ds_min, double ds_max, double* nds)
+// Smallest spacing of the doubles next to v (below |v| when |v| is a power
+// of two): 2^-1074 at zero and among the subnormals.
+__device__ __forceinline__ double spacing_min(double v)
 {
-    int sp = blockIdx.x * blockDim.x + threadIdx.x;
-    if (sp >= nb) return;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v) & 0x7fffffffffffffffull;
+    const int be = (int)(b >> 52);
+    if (be == 0) return ldexp(1.0, -1074);
+    const bool pow2 = (b & 0xfffffffffffffull) == 0;
+    return ldexp(1.0, (pow2 && be > 1) ? be - 1076 : be - 1075);
+}
+
+// The fast path to the same result: a TwoSum cascade that also adds up the
+// magnitudes of the exact errors it carries.  With S the exact sum, s the
+// running sum and c the rounded sum of the n errors e_k (S = s + sum e_k),
+// |S - (s + c)| <= gamma_{n-1} sum|e_k| (recursive summation), and
+// (res, r) = TwoSum(s, c) is exact, so |S - res| <= |r| + that bound.  When
+// twice the bound (taken with margins for its own rounding) is below the
+// spacing of the doubles at res, S lies strictly inside res's rounding
+// interval and res is the correctly rounded sum; get() then returns true.
+// It returns false when the terms cancel almost completely (a particle in a
+// symmetric neighbourhood), and the row is summed again with XSum.
+struct FSum {
+    double s = 0.0, c = 0.0, a = 0.0;
+    int n = 0;
+    __device__ __forceinline__ void add(double x)
+    {
+        const double t = s + x;
+        const double z = t - s;
+        const double e = (s - (t - z)) + (x - z);
+        s = t;
+        c += e;
+        a += fabs(e);
+        ++n;
+    }
+    __device__ __forceinline__ bool get(double& out) const
+    {
+        const double res = s + c;
+        const double z = res - s;
+        const double r = (s - (res - z)) + (c - z);
+        const double g = 2.0 * (double)(n + 2) * 0x1p-53;  // >= gamma_{n-1} / (1 - gamma_{n-1})
+        const double bound = (fabs(r) + g * a) * (1.0 + 0x1p-40);
+        if (2.0 * bound < spacing_min(res)) {
+            out = res;
+            return true;
+        }
+        return false;
+    }
+};
+
+// Size grading of background particle b (sorted position sp) over its
+// neighbours, step 2 of section 3.3.  Acc sums the logarithms of the sizes
+// (the walk is not in slot order; the sum is rounded once); returns false
+// when Acc cannot prove its sum, and then writes nothing.
+template <class Acc>
+__device__ __forceinline__ bool bg_grade_row(const Grid& g, const NbrView& nv, int sp,
+                                             const int32_t* __restrict__ mask,
+                                             const double* __restrict__ ds, double cr,
+                                             double ds_min, double ds_max, double* nds)
+{
     const int b = nv.perm[sp];
     if (mask[b]) {
         nds[b] = ds[b];
-        return;
+        return true;
     }
     double mn = 0.0, mx = 0.0;
-    XSum sl;  // the walk is not in slot order: the sum of logs is rounded once
+    Acc sl;
     int cnt = 0;
     for_each_neighbor(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]),
                       [&](int js, double, double, double, double) {
@@ -1031,11 +1087,41 @@ __global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
                           ++cnt;
                       });
     const double cr3 = cr * cr * cr;
-    const double geo = exp(sl.get() / (double)cnt);
-    double v = (mx / mn < cr3) ? cr * mn : geo;
+    double v;
+    if (mx / mn < cr3) {
+        v = cr * mn;
+    } else {
+        double sum;
+        if (!sl.get(sum)) return false;
+        v = exp(sum / (double)cnt);
+    }
     if (v < ds_min) v = ds_min;
     if (v > ds_max) v = ds_max;
     nds[b] = v;
+    return true;
+}
+
+// fast path; redo[sp] = 1 where the exact sum is needed
+__global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
+                                                  const int32_t* __restrict__ mask,
+                                                  const double* __restrict__ ds, double cr,
+                                                  double ds_min, double ds_max, double* nds,
+                                                  int32_t* redo)
+{
+    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (sp >= nb) return;
+    redo[sp] = bg_grade_row<FSum>(g, nv, sp, mask, ds, cr, ds_min, ds_max, nds) ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_bg_grade_exact(Grid g, NbrView nv, int nb,
+                                                        const int32_t* __restrict__ mask,
+                                                        const double* __restrict__ ds, double cr,
+                                                        double ds_min, double ds_max, double* nds,
+                                                        const int32_t* __restrict__ redo)
+{
+    const int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nb || !redo[sp]) return;
+    bg_grade_row<XSum>(g, nv, sp, mask, ds, cr, ds_min, ds_max, nds);
 }
 
 __global__ __launch_bounds__(256) void k_bg_setds(int nb, const double* __restrict__ nds,
@@ -1093,16 +1179,15 @@ __global__ __launch_bounds__(256) void k_bg_split_apply(Grid g, int nb, sph_back
 // thousands).  The walk order is not the slot order, so the sums over
 // neighbours (of h_j and of the shift terms) are exact sums rounded once
 // (XSum): their results follow from the neighbour set alone.
-__global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int nb, sph_background B,
-                                                        double q, double rho0, double n_r, double* nh,
-                                                        double* ddx, double* ddy)
+template <class Acc>
+__device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, int sp,
+                                              const sph_background& B, double q, double rho0,
+                                              double n_r, double* nh, double* ddx, double* ddy)
 {
-    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (sp >= nb) return;
     const int b = nv.perm[sp];
     const double xb = nv.xs[sp], yb = nv.ys[sp], hb = nv.hs[sp];
     const double fxi = kern_f<double>(SPH_XI);
-    XSum sh, sx, sy;
+    Acc sh, sx, sy;
     int cnt = 0;
     for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[sp]),
                       [&](int js, double dx, double dy, double r2, double hj) {
@@ -1118,10 +1203,12 @@ __global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int 
                           sx.add(t * dx);
                           sy.add(t * dy);
                       });
+    double vsh, vsx, vsy;
+    if (!sh.get(vsh) || !sx.get(vsx) || !sy.get(vsy)) return false;
     const double N = (double)cnt;
-    nh[b] = 0.5 * ((hb / 2.0) * (1.0 + sqrt(n_r / N)) + sh.get() / N);
+    nh[b] = 0.5 * ((hb / 2.0) * (1.0 + sqrt(n_r / N)) + vsh / N);
     const double pref = -0.5 * (hb * hb);
-    double dxs = pref * sx.get(), dys = pref * sy.get();
+    double dxs = pref * vsx, dys = pref * vsy;
     const double mag = sqrt(dxs * dxs + dys * dys);
     const double lim = 0.25 * hb;
     if (mag > lim) {
@@ -1131,6 +1218,27 @@ __global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int 
     }
     ddx[b] = dxs;
     ddy[b] = dys;
+    return true;
+}
+
+// fast path; redo[sp] = 1 where an exact sum is needed
+__global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int nb, sph_background B,
+                                                        double q, double rho0, double n_r, double* nh,
+                                                        double* ddx, double* ddy, int32_t* redo)
+{
+    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (sp >= nb) return;
+    redo[sp] = bg_smooth_row<FSum>(g, nv, sp, B, q, rho0, n_r, nh, ddx, ddy) ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_bg_smooth_exact(Grid g, NbrView nv, int nb, sph_background B,
+                                                         double q, double rho0, double n_r,
+                                                         double* nh, double* ddx, double* ddy,
+                                                         const int32_t* __restrict__ redo)
+{
+    const int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nb || !redo[sp]) return;
+    bg_smooth_row<XSum>(g, nv, sp, B, q, rho0, n_r, nh, ddx, ddy);
 }
 
 __global__ __launch_bounds__(256) void k_bg_smooth_apply(Grid g, int nb, sph_background B,
@@ -1171,7 +1279,9 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
         if (rc) return rc;
         NbrView nv = nbr_view(c);
         hipLaunchKernelGGL(k_bg_grade, dim3(nbk), dim3(256), 0, c->stream, c->grid, nv, nb, bg->mask,
-                           bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0]);
+                           bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
+        hipLaunchKernelGGL(k_bg_grade_exact, dim3(nbk), dim3(256), 0, c->stream, c->grid, nv, nb,
+                           bg->mask, bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
         hipLaunchKernelGGL(k_bg_setds, dim3(nbk), dim3(256), 0, c->stream, nb, w.tmp_d[0], cf.rho0,
                            bg->ds, bg->mref);
         LAUNCHCHK(c, "bg_grade");
@@ -1199,7 +1309,10 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
             unsigned nbk2 = (unsigned)cdiv(nb, 256);
             hipLaunchKernelGGL(k_bg_smooth_walk, dim3(nbk2), dim3(256), 0, c->stream, c->grid,
                                nbr_view(c), nb, *bg, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
-                               w.tmp_d[1], w.tmp_d[2]);
+                               w.tmp_d[1], w.tmp_d[2], w.tmp_i32[0]);
+            hipLaunchKernelGGL(k_bg_smooth_exact, dim3(nbk2), dim3(256), 0, c->stream, c->grid,
+                               nbr_view(c), nb, *bg, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
+                               w.tmp_d[1], w.tmp_d[2], w.tmp_i32[0]);
             hipLaunchKernelGGL(k_bg_smooth_apply, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
                                w.tmp_d[0], w.tmp_d[1], w.tmp_d[2]);
             LAUNCHCHK(c, "bg_smooth");

@@ -330,6 +330,7 @@ extern "C" int sph_set_stream(sph_ctx* c, void* stream)
 }
 
 static bool check_bg(sph_ctx* c, const sph_background* bg);
+static bool check_solids(sph_ctx* c, const sph_particles* s);
 
 static int check_ps(sph_ctx* c, const sph_particles* ps, int need_state)
 {
@@ -398,6 +399,7 @@ extern "C" int sph_step(sph_ctx* c, sph_particles* ps, sph_background* bg, const
         set_err(c, "a background update every n_bg iterations needs the solids");
         return SPH_E_INVAL;
     }
+    if (bg && c->cfg.n_bg > 0 && !check_solids(c, solids)) return SPH_E_INVAL;
     if (io) {
         if (!ps->kind || !ps->mref) { set_err(c, "inlet/outlet zones need kind and mref"); return SPH_E_INVAL; }
         if (!isfinite(io->x_in) || !isfinite(io->x_out) || !(io->len_in >= 0) || !(io->len_out >= 0) ||
@@ -589,6 +591,22 @@ extern "C" int sph_diagnostics(sph_ctx* c, const sph_particles* ps, sph_diag* ou
 }
 
 // The background shares the context's search workspace: it must fit it.
+// solid particles handed to a background update: only x, y, h are read, and
+// the update builds their cells in this context
+static bool check_solids(sph_ctx* c, const sph_particles* s)
+{
+    if (s->n < 0 || s->n > c->capacity) {
+        set_err(c, "solids n=%lld beyond the context capacity %lld", (long long)s->n,
+                (long long)c->capacity);
+        return false;
+    }
+    if (s->n > 0 && (!s->x || !s->y || !s->h)) {
+        set_err(c, "solids x, y, h must be set");
+        return false;
+    }
+    return true;
+}
+
 static bool check_bg(sph_ctx* c, const sph_background* bg)
 {
     if (bg->n < 0 || bg->n > bg->capacity || bg->capacity > c->capacity) {
@@ -669,7 +687,8 @@ extern "C" int sph_bg_update_solution(sph_ctx* c, sph_background* bg, const sph_
     }
     if (!c || !bg || !solids || !fluid || !nsplit || passes < 0) return SPH_E_INVAL;
     if (!(k_frac >= 0.0) || !isfinite(k_frac)) { set_err(c, "k_frac must be finite and >= 0"); return SPH_E_INVAL; }
-    if (!check_bg(c, bg) || !check_ps(c, fluid, 1) || !fluid->rho) return SPH_E_INVAL;
+    if (!check_bg(c, bg) || !check_solids(c, solids) || !check_ps(c, fluid, 1) || !fluid->rho)
+        return SPH_E_INVAL;
     c->fused_x = nullptr;  // positions may have changed since the last call
     return bg_solution_run(c, bg, solids, fluid, k_frac, passes, nsplit, omega_max);
 }
@@ -703,7 +722,7 @@ extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles
         return SPH_E_INVAL;
     }
     if (!c || !bg || !solids || !nsplit || passes < 0) return SPH_E_INVAL;
-    if (!check_bg(c, bg)) return SPH_E_INVAL;
+    if (!check_bg(c, bg) || !check_solids(c, solids)) return SPH_E_INVAL;
     c->fused_x = nullptr;  // positions may have changed since the last call
     return bg_update_run(c, bg, solids, phi, phi_thresh, passes, nsplit);
 }

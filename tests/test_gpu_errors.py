@@ -118,6 +118,28 @@ def test_ledger_overflow_reported():
     assert e.value.code == P.SPH_E_INVAL and "ledger" in str(e.value)
 
 
+def test_background_update_rejections():
+    """A background update refuses solids beyond the context capacity or
+    without positions, before any kernel runs."""
+    P = lib()
+    bg = W.background_lattice(W.Domain((0.0, 0.0), (1.0, 1.0), (True, True)), 0.1, 1.2, 1.0)
+    cfg = P.Config(lo=(0.0, 0.0), hi=(1.0, 1.0), periodic=(1, 1), h_lo=0.01, h_hi=0.2, cr=1.2,
+                   ds_min=0.05, ds_max=0.1, bg_mass_q=bg["mass_q"])
+    ctx = P.Context(cfg, 200)
+    B = P.Background.from_arrays(bg, 200)
+    big = P.Particles.from_arrays({"x": np.full(300, 0.5), "y": np.full(300, 0.5),
+                                   "h": np.full(300, 0.05), "mq": np.ones(300, np.int64)})
+    with pytest.raises(P.SphError) as e:
+        ctx.bg_update(B, big, 1)
+    assert e.value.code == P.SPH_E_INVAL and "solids" in str(e.value)
+    s = big.c()
+    s.n, s.x = 10, None
+    ns = C.c_int64(0)
+    assert ctx.lib.sph_bg_update(ctx._h, C.byref(B.c()), C.byref(s), None, 0.0, 1,
+                                 C.byref(ns)) == P.SPH_E_INVAL
+    assert B.n == bg["x"].size
+
+
 def test_internal_list_width_reported():
     """The adaptation's internal neighbour lists hold csr_k entries per
     particle of capacity: with room for 4, a shift's list does not fit and
