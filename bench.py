@@ -44,7 +44,6 @@ METRIC = "pair evals/s per step, FP32 vs FP64 plain; batched-serve p50/p99 step 
 # and 68 bytes per particle.
 PASS_FLOPS_PER_PAIR = {"pass_a": 105, "pass_b": 125}
 PASS_BYTES_PER_PARTICLE = {"pass_a": 52, "pass_b": 68}
-PASS_KERNEL = {"pass_a": "k_pass_a<float>", "pass_b": "k_pass_b<float, true>"}
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0
@@ -69,6 +68,11 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the C1 latency and the 1.5e6 / 9.6e5 particle lines")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="a_lanes,a_waves,b_lanes,b_unroll,b_waves,list_lanes for the FP32 "
+                         "run instead of tuning (for profiled runs)")
+    ap.add_argument("--no-tune-cache", action="store_true",
+                    help="time the kernel schedules even when the tuning cache holds a pick")
     ap.add_argument("--list-skin", type=float, default=None,
                     help="use this list skin for both precisions instead of timing the "
                          "candidates first (for profiled runs)")
@@ -202,7 +206,7 @@ def run(ctx, P, B, io, steps, warmup, torch):
     return ms, prof, 0.5 * (pairs0 + pairs1)
 
 
-def pmc_sample(SPH, W, torch, skin, adapt_every):
+def pmc_sample(SPH, W, torch, skin, adapt_every, sched=None):
     """One plain device copy of CALIB_BYTES (its FETCH_SIZE / WRITE_SIZE give
     the counter-to-bytes factor), then 10 iterations of the timed loop (FP32)
     on the adapted channel: the rate-pass dispatches whose traffic is
@@ -215,12 +219,28 @@ def pmc_sample(SPH, W, torch, skin, adapt_every):
     s = W.channel_cylinder(seed=2)
     bg = W.channel_background(s["spec"], seed=3)
     ctx, P, B = prepare(SPH, s, bg, SPH.SPH_FP32, int(1.6 * s["x"].size), skin, adapt_every)
+    if sched:
+        ctx.set_schedule(**sched)
     ctx.run(P, 10, bg=B, io=s["io"])
     torch.cuda.synchronize()
     print(json.dumps({"pmc_sample": True, "calib_bytes": CALIB_BYTES, "n": P.n, "skin": skin}))
 
 
-def roofline_line(r32, traffic):
+def parse_schedule(SPH, text):
+    vals = [int(v) for v in text.split(",")]
+    if len(vals) != len(SPH.SCHEDULE_FIELDS):
+        raise SystemExit(f"--schedule needs {len(SPH.SCHEDULE_FIELDS)} integers")
+    return dict(zip(SPH.SCHEDULE_FIELDS, vals))
+
+
+def kernel_names(sched):
+    """Device-kernel names of the FP32 rate passes under a schedule."""
+    return {"pass_a": f"k_pass_a_f<{sched['a_lanes']}, {sched['a_waves']}>",
+            "pass_b": f"k_pass_b_f<true, {sched['b_lanes']}, {sched['b_unroll']}, "
+                      f"{sched['b_waves']}>"}
+
+
+def roofline_line(r32, traffic, sched):
     """Roofline of the rate pass with the larger share of the FP32 step,
     from its live-measured average launch time and the algorithmic work."""
     per = {}
@@ -236,7 +256,7 @@ def roofline_line(r32, traffic):
     intensity = flops / byts
     ridge = PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBPS * 1e9)
     alu = intensity >= ridge
-    roof = {"bound": "alu" if alu else "hbm", "kernel": PASS_KERNEL[dom],
+    roof = {"bound": "alu" if alu else "hbm", "kernel": kernel_names(sched)[dom],
             "achieved": achieved if alu else byts / (avg * 1e-3) / 1e9,
             "peak": PEAK_FP32_TFLOPS if alu else PEAK_HBM_GBPS,
             "unit": "TFLOP/s" if alu else "GB/s"}
@@ -491,7 +511,7 @@ def main():
     torch.cuda.set_device(0)
     if args.pmc_sample:
         pmc_sample(SPH, W, torch, args.list_skin if args.list_skin is not None else 0.3,
-                   args.adapt_every)
+                   args.adapt_every, parse_schedule(SPH, args.schedule) if args.schedule else None)
         return
     s = W.channel_cylinder(seed=2)
     bg = W.channel_background(s["spec"], seed=3)
@@ -520,7 +540,20 @@ def main():
                                                steps=2 * max(args.adapt_every, 10))
         else:
             tuning[name] = {"best": args.list_skin, "ms_per_step": None}
+        if name == "fp32" and args.schedule:
+            sched_tuning = {"schedule": parse_schedule(SPH, args.schedule), "source": "--schedule"}
+        elif name == "fp32":
+            # kernel schedules timed on a copy of the same loop, then set on
+            # the fresh context that is timed
+            tc, tP, tB = prepare(SPH, s, bg, prec, cap, tuning[name]["best"], args.adapt_every)
+            sched_tuning = tune.tune_schedule(
+                tc, lambda k: tc.run(tP, k, bg=tB, io=s["io"]), n=tP.n, precision=name,
+                use_cache=not args.no_tune_cache)
+            del tc, tP, tB
+            torch.cuda.empty_cache()
         ctx, P, B = prepare(SPH, s, bg, prec, cap, tuning[name]["best"], args.adapt_every)
+        if name == "fp32":
+            ctx.set_schedule(**sched_tuning["schedule"])
         n_adapted = P.n
         ratio = fluid_size_ratio(P, W)
         ms, prof, pairs = run(ctx, P, B, s["io"], steps, args.warmup, torch)
@@ -532,7 +565,7 @@ def main():
         torch.cuda.empty_cache()
 
     r32 = results["fp32"]
-    roof = roofline_line(r32, measured_traffic())
+    roof = roofline_line(r32, measured_traffic(), sched_tuning["schedule"])
 
     serve = None
     if not args.no_serve:
@@ -582,6 +615,7 @@ def main():
             if serve else None),
         "configs": configs,
         "list_skin_tuning": tuning,
+        "schedule_tuning": sched_tuning,
     }
     print(json.dumps(out))
 

@@ -243,6 +243,28 @@ int sph_build_neighbors(sph_ctx *ctx, const sph_particles *ps, sph_csr *out);
  * particle with no fluid neighbour keeps its values. */
 int sph_rates(sph_ctx *ctx, const sph_particles *ps, double dt, sph_rates_out *out);
 
+/* Launch schedule of the FP32 rate passes and of the neighbour-list build:
+ * the variants compiled into the library, picked at run time (by a tuner
+ * that times them on the caller's workload).  The results do not depend on
+ * it beyond the order of the FP32 partial sums.  A new context starts with
+ * {4, 5, 2, 2, 4, 4}.  The FP64 passes keep one fixed schedule. */
+typedef struct sph_schedule {
+    int32_t a_lanes;    /* pass A work-items per particle: 2, 4 or 8 */
+    int32_t a_waves;    /* pass A minimum waves per SIMD the register
+                           allocation must allow: 1 (the compiler's choice),
+                           4 or 5 (the last spills to scratch) */
+    int32_t b_lanes;    /* pass B work-items per particle: 1, 2 or 4 */
+    int32_t b_unroll;   /* pass B row entries loaded ahead per lane: 2 or 4 */
+    int32_t b_waves;    /* pass B minimum waves per SIMD: 1 or 4 */
+    int32_t list_lanes; /* list build work-items per particle: 2, 4 or 8 */
+} sph_schedule;
+
+/* Sets the context's schedule; SPH_E_INVAL (schedule unchanged) for a
+ * combination that is not compiled in. */
+int sph_set_schedule(sph_ctx *ctx, const sph_schedule *sched);
+/* Writes the context's schedule to *sched. */
+int sph_get_schedule(const sph_ctx *ctx, sph_schedule *sched);
+
 /* Time step of eq. (timestep): min(0.25 h_min / (U + c_s), 0.125 h_min^2 /
  * nu) with U = cfg->u_ref, c_s = cfg->cs, nu = cfg->nu (the second bound
  * is dropped for nu = 0); h_min <= 0 takes cfg->h_lo.  Returns 0 for an

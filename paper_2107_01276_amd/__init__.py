@@ -98,6 +98,18 @@ class sph_background(C.Structure):
                 ("mref", C.c_void_p), ("mask", C.c_void_p), ("mq", C.c_void_p)]
 
 
+SCHEDULE_FIELDS = ("a_lanes", "a_waves", "b_lanes", "b_unroll", "b_waves", "list_lanes")
+# the launch-schedule variants compiled into the library (sph_set_schedule)
+SCHEDULE_CHOICES = {"a_lanes": (2, 4, 8), "a_waves": (1, 4, 5), "b_lanes": (1, 2, 4),
+                    "b_unroll": (2, 4), "b_waves": (1, 4), "list_lanes": (2, 4, 8)}
+DEFAULT_SCHEDULE = {"a_lanes": 4, "a_waves": 5, "b_lanes": 2, "b_unroll": 2, "b_waves": 4,
+                    "list_lanes": 4}
+
+
+class sph_schedule(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in SCHEDULE_FIELDS]
+
+
 class sph_diag(C.Structure):
     _fields_ = [("ke", C.c_double), ("vol", C.c_double), ("mom_x", C.c_double),
                 ("mom_y", C.c_double), ("umax", C.c_double), ("mq_total", C.c_int64),
@@ -114,7 +126,7 @@ EXPORTS = ("sph_version", "sph_workspace_bytes", "sph_create", "sph_destroy", "s
            "sph_pool_footprint", "sph_pool_create",
            "sph_pool_destroy", "sph_pool_last_error", "sph_pool_admit", "sph_pool_step",
            "sph_pool_sim_stats", "sph_pool_read", "sph_pool_retire", "sph_pool_info",
-           "sph_rates_noalloc_bytes", "sph_rates_noalloc")
+           "sph_rates_noalloc_bytes", "sph_rates_noalloc", "sph_set_schedule", "sph_get_schedule")
 
 _lib = None
 
@@ -146,6 +158,8 @@ def load_library(path: str = LIB_PATH):
         "sph_adapt": (C.c_int, [P, P, P, P]),
         "sph_bg_update": (C.c_int, [P, P, P, P, D, I32, P]),
         "sph_bg_init_passes": (I32, [P]),
+        "sph_set_schedule": (C.c_int, [P, P]),
+        "sph_get_schedule": (C.c_int, [P, P]),
         "sph_inout": (C.c_int, [P, P, P, P]),
         "sph_vorticity": (C.c_int, [P, P, P]),
         "sph_step_inout": (C.c_int, [P, P, D, I32, P, P]),
@@ -591,6 +605,25 @@ class Context:
     # -- profiling ---------------------------------------------------------
 
     PROFILE_BITS = {"pass_a": 1, "pass_b": 2, "build": 4, "list": 8}
+
+    @property
+    def schedule(self) -> dict:
+        """The context's launch schedule (sph_get_schedule)."""
+        sc = sph_schedule()
+        self._check(self.lib.sph_get_schedule(self._h, C.byref(sc)))
+        return {k: int(getattr(sc, k)) for k in SCHEDULE_FIELDS}
+
+    def set_schedule(self, **kw) -> dict:
+        """Changes the named fields of the launch schedule (sph_set_schedule);
+        SphError for a combination not compiled in."""
+        cur = self.schedule
+        unknown = set(kw) - set(SCHEDULE_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown schedule fields {sorted(unknown)}")
+        cur.update({k: int(v) for k, v in kw.items()})
+        sc = sph_schedule(**cur)
+        self._check(self.lib.sph_set_schedule(self._h, C.byref(sc)))
+        return cur
 
     def profile(self, on: bool = True, kernels=("pass_a", "pass_b", "build", "list"), every: int = 1):
         """Brackets every `every`-th launch of the named kernels with events."""

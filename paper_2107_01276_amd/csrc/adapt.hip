@@ -1701,6 +1701,7 @@ int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const s
         if (rc) break;
         int32_t* trip = w.status + 24;
         hipLaunchKernelGGL(k_set_trip, dim3(1), dim3(64), 0, c->stream, trip);
+        prof_run_begin(c);
         const unsigned nb = (unsigned)cdiv(n, 256);
         for (int k = s; k < nsteps && rc == SPH_OK; ++k) {
             const int32_t b = 8 * (k - s);
@@ -1721,6 +1722,7 @@ int step_inout_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps, const s
         const Readback rb[2] = {{&tr, trip, 4}, {h3, w.ctr, (int)sizeof(h3)}};
         rc = readback(c, rb, 2);
         if (rc) break;
+        prof_run_end(c, tr);  // brackets of the kernels skipped after the trip are dropped
         // fluid turned outlet in the steps that ran (their kinds are set)
         tot_out += (int64_t)(h3[0] - c->io_last[0]);
         for (int k = 0; k < 3; ++k) c->io_last[k] = h3[k];

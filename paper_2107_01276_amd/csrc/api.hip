@@ -147,6 +147,28 @@ double timestep_of(const sph_config& cfg, double h_min)
     return dt;
 }
 
+extern "C" int sph_set_schedule(sph_ctx* c, const sph_schedule* s)
+{
+    if (!c || !s) return SPH_E_INVAL;
+    if (!rate_schedule_valid(*s) || !list_lanes_valid(s->list_lanes)) {
+        set_err(c,
+                "schedule {%d, %d, %d, %d, %d, %d} is not compiled in (a_lanes 2/4/8, a_waves 1/4/5, "
+                "b_lanes 1/2/4, b_unroll 2/4, b_waves 1/4, list_lanes 2/4/8)",
+                s->a_lanes, s->a_waves, s->b_lanes, s->b_unroll, s->b_waves, s->list_lanes);
+        return SPH_E_INVAL;
+    }
+    if (s->list_lanes != c->sched.list_lanes) c->list_valid = 0;  // rebuilt with the new lanes
+    c->sched = *s;
+    return SPH_OK;
+}
+
+extern "C" int sph_get_schedule(const sph_ctx* c, sph_schedule* s)
+{
+    if (!c || !s) return SPH_E_INVAL;
+    *s = c->sched;
+    return SPH_OK;
+}
+
 extern "C" int32_t sph_bg_init_passes(const sph_config* cfg)
 {
     if (!cfg || !(cfg->ds_min > 0.0) || !(cfg->ds_max >= cfg->ds_min) || !(cfg->cr > 1.0)) return 0;
@@ -288,6 +310,7 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->prof[SPH_PROF_LIST].name = "list";
     c->skin = cfg->list_skin;
     c->list_valid = 0;
+    c->sched = sph_schedule{4, 5, 2, 2, 4, 4};
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c->stream, c->w.status, c->w.ctr);
     if (hipGetLastError() != hipSuccess) {
         hipHostFree(c->mbox);
@@ -729,30 +752,70 @@ extern "C" int sph_bg_update(sph_ctx* c, sph_background* bg, const sph_particles
 
 // ---- profiling -------------------------------------------------------------
 
-static void prof_flush(sph_ctx* c, int slot)
+// Adds the brackets [0, upto) to the totals (void ones excepted) and moves
+// the rest to the front.
+static void prof_flush_to(sph_ctx* c, int slot, int upto)
 {
     ProfSlot& s = c->prof[slot];
-    if (s.count == 0) return;
-    hipEventSynchronize(s.ev[1][s.count - 1]);
-    for (int k = 0; k < s.count; ++k) {
+    if (upto <= 0) return;
+    hipEventSynchronize(s.ev[1][upto - 1]);
+    for (int k = 0; k < upto; ++k) {
+        if (s.seq[k] == -2) continue;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, s.ev[0][k], s.ev[1][k]) == hipSuccess) s.ms += ms;
+        s.launches++;
     }
-    s.launches += s.count;
-    s.count = 0;
+    for (int k = upto; k < s.count; ++k) {
+        const int d = k - upto;
+        for (int e = 0; e < 2; ++e) {
+            hipEvent_t t = s.ev[e][d];
+            s.ev[e][d] = s.ev[e][k];
+            s.ev[e][k] = t;
+        }
+        s.seq[d] = s.seq[k];
+    }
+    s.count -= upto;
+    if (s.run_lo >= 0) s.run_lo = s.run_lo > upto ? s.run_lo - upto : 0;
 }
+
+static void prof_flush(sph_ctx* c, int slot) { prof_flush_to(c, slot, c->prof[slot].count); }
 
 // Every prof_every-th launch of a selected kernel is bracketed (the event
 // markers keep consecutive kernels from overlapping, so sparse sampling
-// disturbs the timed work less).
-void prof_begin(sph_ctx* c, int slot)
+// disturbs the timed work less).  A launch in a guarded run records its
+// sequence number: if the run trips before it, the kernel returns at once
+// and the bracket is dropped when the run ends.
+void prof_begin(sph_ctx* c, int slot, const Guard* gd)
 {
     if (!c->prof_on || !(c->prof_mask & (1 << slot))) return;
     ProfSlot& s = c->prof[slot];
     s.skip = (s.tick++ % (uint32_t)c->prof_every) != 0;
     if (s.skip) return;
-    if (s.count == 512) prof_flush(c, slot);
+    if (s.count == 512) {
+        // keep the brackets of the run in flight unless they fill the buffer
+        prof_flush_to(c, slot, s.run_lo > 0 ? s.run_lo : s.count);
+        if (s.count == 512) prof_flush(c, slot);
+    }
+    s.seq[s.count] = (gd && gd->trip) ? gd->seq : -1;
     hipEventRecord(s.ev[0][s.count], c->stream);
+}
+
+void prof_run_begin(sph_ctx* c)
+{
+    if (!c->prof_on) return;
+    for (int k = 0; k < 4; ++k) c->prof[k].run_lo = c->prof[k].count;
+}
+
+void prof_run_end(sph_ctx* c, int32_t tr)
+{
+    if (!c->prof_on) return;
+    for (int k = 0; k < 4; ++k) {
+        ProfSlot& s = c->prof[k];
+        if (s.run_lo < 0) continue;
+        for (int i = s.run_lo; i < s.count; ++i)
+            if (s.seq[i] >= 0 && s.seq[i] > tr) s.seq[i] = -2;
+        s.run_lo = -1;
+    }
 }
 
 void prof_end(sph_ctx* c, int slot)
@@ -780,6 +843,7 @@ extern "C" int sph_profile_enable(sph_ctx* c, int32_t on)
             c->prof[s].count = 0;
             c->prof[s].ms = 0;
             c->prof[s].launches = 0;
+            c->prof[s].run_lo = -1;
         }
         c->prof_on = 1;
     } else if (!on) {

@@ -516,9 +516,11 @@ NbrView nbr_view(sph_ctx* c)
 // walk the cells again for that row).
 // ---------------------------------------------------------------------------
 
-// Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate); LG lanes
-// per row walk the cells together.
+// Every j with |r_i - r_j| < sf 3 max(h_i, h_j) (FP64 predicate); G lanes
+// per row walk the cells together (LG for the export and the batched build;
+// the single-context list build takes the context's schedule).
 #define LG 4
+template <int G>
 __device__ __forceinline__ void build_list_body(const Grid& g, const NbrView& nv, const NbrList& nl,
                                                 int s, int gl, double sf)
 {
@@ -526,10 +528,10 @@ __device__ __forceinline__ void build_list_body(const Grid& g, const NbrView& nv
     const int li = key_level(g, nv.keys[s]);
     int cnt = 0;
     int32_t* const row = nl.idx + s;
-    group_walk<LG>(g, nv, a.x, a.y, a.z, li, gl,
+    group_walk<G>(g, nv, a.x, a.y, a.z, li, gl,
                    [&](int js, bool pass, double, double, double, double) {
                        int tot;
-                       const int k = cnt + group_rank<LG>(pass, gl, &tot);
+                       const int k = cnt + group_rank<G>(pass, gl, &tot);
                        if (pass && k < nl.K) row[(int64_t)k * nl.stride] = js;
                        cnt += tot;
                    },
@@ -540,14 +542,28 @@ __device__ __forceinline__ void build_list_body(const Grid& g, const NbrView& nv
     }
 }
 
+template <int G>
 __global__ __launch_bounds__(256) void k_build_list_lane(Grid g, NbrView nv, int n, NbrList nl,
                                                          double sf)
 {
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    const int s = t / LG, gl = t % LG;
+    const int s = t / G, gl = t % G;
     if (s >= n) return;
-    build_list_body(g, nv, nl, s, gl, sf);
+    build_list_body<G>(g, nv, nl, s, gl, sf);
 }
+
+using BuildListFn = void (*)(Grid, NbrView, int, NbrList, double);
+static BuildListFn build_list_variant(int G)
+{
+    switch (G) {
+    case 2: return k_build_list_lane<2>;
+    case 4: return k_build_list_lane<4>;
+    case 8: return k_build_list_lane<8>;
+    default: return nullptr;
+    }
+}
+
+bool list_lanes_valid(int G) { return build_list_variant(G) != nullptr; }
 
 int nbr_build_list(sph_ctx* c, int n, double skin)
 {
@@ -557,8 +573,9 @@ int nbr_build_list(sph_ctx* c, int n, double skin)
     prof_begin(c, SPH_PROF_LIST);
     const Grid& g = c->grid;
     const double sf = 1.0 + skin;
-    hipLaunchKernelGGL(k_build_list_lane, dim3((unsigned)cdiv((int64_t)n * LG, 256)), dim3(256), 0, c->stream, g,
-                       nbr_view(c), n, nl, sf);
+    const int G = c->sched.list_lanes;
+    hipLaunchKernelGGL(build_list_variant(G), dim3((unsigned)cdiv((int64_t)n * G, 256)), dim3(256), 0,
+                       c->stream, g, nbr_view(c), n, nl, sf);
     prof_end(c, SPH_PROF_LIST);
     LAUNCHCHK(c, "build_list");
     return SPH_OK;
@@ -841,7 +858,7 @@ __global__ __launch_bounds__(256) void k_build_list_b(Batch B, NbrView nv0, NbrL
     const int t = lb * 256 + threadIdx.x;
     const int sl = t / LG, gl = t % LG;
     if (sl >= sd.n) return;
-    build_list_body(sd.g, batch_view(nv0, sd, sid), nl, (int)(sd.off + sl), gl, sf);
+    build_list_body<LG>(sd.g, batch_view(nv0, sd, sid), nl, (int)(sd.off + sl), gl, sf);
 }
 
 int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const double* x,

@@ -369,9 +369,9 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
 #define PASS_A_PARAMS(T) PASS_A_PARAMS_(Grid, T)
 #define PASS_A_ARGS g, nv, n, b, nl, pa, pf, rho0, out, r_dxs, r_dys, kind, ex, gd
 
-// Sorted particle s, lane gl of its group of RGA lanes (all lanes of the
+// Sorted particle s, lane gl of its group of G lanes (all lanes of the
 // group call it together).
-template <typename T>
+template <typename T, int G>
 __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int s, int gl)
 {
     const double4 ai = pa[s];
@@ -416,7 +416,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         __attribute__((always_inline)) {
         const bool ext = pass && js != s;
         int tot;
-        const int k = ne + group_rank<RGA>(ext, gl, &tot);
+        const int k = ne + group_rank<G>(ext, gl, &tot);
         if (exo && ext && k < ex.K) exo[(int64_t)k * ex.stride + s] = js;
         ne += tot;
         if (pass) {
@@ -425,15 +425,15 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         }
     };
     if (cnt <= nl.K) {
-        // the lanes of the group take every RGA-th entry of the row; four
+        // the lanes of the group take every G-th entry of the row; four
         // entries' loads are issued before their tests
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
-        for (int base = 0; base < cnt; base += 4 * RGA) {
+        for (int base = 0; base < cnt; base += 4 * G) {
             int j[4];
             double4 a[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int k = base + gl + RGA * u;
+                const int k = base + gl + G * u;
                 j[u] = k < cnt ? nl.idx[(int64_t)k * nl.stride + s] : s;
             }
 #pragma unroll
@@ -444,12 +444,12 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
                 const double dy = mi_axis(g, 1, yi - a[u].y);
                 const double r2 = dx * dx + dy * dy;
                 const double rj3 = 3.0 * a[u].z;
-                const bool pass = base + gl + RGA * u < cnt && r2 < fmax(ri2, rj3 * rj3);
+                const bool pass = base + gl + G * u < cnt && r2 < fmax(ri2, rj3 * rj3);
                 body(j[u], pass, dx, dy, r2, a[u].z, a[u].w);
             }
         }
     } else {
-        group_walk<RGA>(g, nv, xi, yi, hi, li, gl,
+        group_walk<G>(g, nv, xi, yi, hi, li, gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
                            body(js, pass, dx, dy, r2, hj, pass ? pa[js].w : 0.0);
                        });
@@ -457,7 +457,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
     if (exo && gl == 0) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
     // the group's partial sums, combined in every lane
 #pragma unroll
-    for (int o = 1; o < RGA; o <<= 1) {
+    for (int o = 1; o < G; o <<= 1) {
         sr.merge_xor(o);
         sb.merge_xor(o);
         sp.merge_xor(o);
@@ -510,28 +510,31 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
     if (out.dys) out.dys[slot] = (double)ddy;
 }
 
-#define PASS_A_SINGLE(T)                                                                     \
+#define PASS_A_SINGLE(T, G)                                                                  \
     if (guard_stop(gd)) return;                                                              \
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;               \
-    const int s = t / RGA, gl = t % RGA;                                                     \
+    const int s = t / (G), gl = t % (G);                                                     \
     if (s >= n) return;                                                                      \
-    pass_a_body<T>(PASS_A_ARGS, s, gl);
+    pass_a_body<T, G>(PASS_A_ARGS, s, gl);
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a(PASS_A_PARAMS(T))
 {
-    PASS_A_SINGLE(T)
-}
-// FP32: more waves per SIMD than the compiler picks (latency-bound gathers)
-template <>
-__global__ __launch_bounds__(256) PA_ATTR void k_pass_a<float>(PASS_A_PARAMS(float))
-{
-    PASS_A_SINGLE(float)
+    PASS_A_SINGLE(T, RGA)
 }
 template <>
 __global__ __launch_bounds__(256) PA64_ATTR void k_pass_a<double>(PASS_A_PARAMS(double))
 {
-    PASS_A_SINGLE(double)
+    PASS_A_SINGLE(double, RGA)
+}
+// FP32 schedule variants: G lanes per particle, and the minimum waves per
+// SIMD W that the register allocation must allow (1: the compiler's choice;
+// more waves hide more of the gathers' latency)
+template <int G, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_pass_a_f(
+    PASS_A_PARAMS(float))
+{
+    PASS_A_SINGLE(float, G)
 }
 
 // Batched pass A: every simulation of a batch (fluid only, no exact rows),
@@ -545,8 +548,8 @@ __global__ __launch_bounds__(256) PA64_ATTR void k_pass_a<double>(PASS_A_PARAMS(
     if (sl >= sd.n) return;                                                                  \
     const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
     const Guard gd{nullptr, 0};                                                              \
-    pass_a_body<T>(sd.g, batch_view(nv, sd, sid), 0, b, nl, pa, pf, sd.rho0, out, r_dxs,     \
-                   r_dys, nullptr, ex, gd, (int)(sd.off + sl), gl);
+    pass_a_body<T, RGA>(sd.g, batch_view(nv, sd, sid), 0, b, nl, pa, pf, sd.rho0, out,      \
+                        r_dxs, r_dys, nullptr, ex, gd, (int)(sd.off + sl), gl);
 
 #define PASS_A_BATCH_PARAMS(T)                                                               \
     Batch B, NbrView nv, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,          \
@@ -580,7 +583,9 @@ struct PassBParams {
 #define PASS_B_PARAMS(T) PASS_B_PARAMS_(Grid, T)
 #define PASS_B_ARGS g, nv, n, b, nl, ex, pa, puv, pf, ugs, vgs, P, dpdt, dudt, dvdt, gd
 
-template <typename T, bool GH>
+// Sorted particle s, lane gl of its group of G lanes; UN exact-row entries
+// loaded ahead per lane.
+template <typename T, bool GH, int G, int UN>
 __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int s, int gl)
 {
     const double4 ai = pa[s];
@@ -677,17 +682,16 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
     };
     const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
     const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
-    // the lanes of the group take every RGB-th entry of the row
+    // the lanes of the group take every G-th entry of the row
     if (ecnt <= ex.K) {
         // the exact neighbours pass A found (self excluded), UN per lane
-        // loaded at a time (PB_UNROLL in float, four in double)
-        constexpr int UN = sizeof(T) == 4 ? PB_UNROLL : 4;
+        // loaded at a time
         int k = gl;
-        for (; k + (UN - 1) * RGB < ecnt; k += UN * RGB) {
+        for (; k + (UN - 1) * G < ecnt; k += UN * G) {
             int j[UN];
             double4 a[UN];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) j[u] = ex.idx[(int64_t)(k + RGB * u) * ex.stride + s];
+            for (int u = 0; u < UN; ++u) j[u] = ex.idx[(int64_t)(k + G * u) * ex.stride + s];
 #pragma unroll
             for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
 #pragma unroll
@@ -697,7 +701,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
                 body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w);
             }
         }
-        for (; k < ecnt; k += RGB) {
+        for (; k < ecnt; k += G) {
             const int js = ex.idx[(int64_t)k * ex.stride + s];
             const double4 a = pa[js];
             const double dx = mi_axis(g, 0, xi - a.x);
@@ -706,7 +710,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
         }
     } else if (cnt <= nl.K) {
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
-        for (int k = gl; k < cnt; k += RGB) {
+        for (int k = gl; k < cnt; k += G) {
             const int js = nl.idx[(int64_t)k * nl.stride + s];
             const double4 a = pa[js];
             const double dx = mi_axis(g, 0, xi - a.x);
@@ -716,14 +720,14 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             if (r2 < fmax(ri2, rj3 * rj3)) body(js, dx, dy, r2, a.z, a.w);
         }
     } else {
-        group_walk<RGB>(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), gl,
+        group_walk<G>(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
                            if (pass) body(js, dx, dy, r2, hj, pa[js].w);
                        });
     }
     // the group's partial sums, combined in every lane
 #pragma unroll
-    for (int o = 1; o < RGB; o <<= 1) {
+    for (int o = 1; o < G; o <<= 1) {
         sdiv.merge_xor(o);
         sdif.merge_xor(o);
         gx.merge_xor(o);
@@ -743,39 +747,35 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
     dvdt[slot] = (double)(-Gy + vy.get() * ib) + P.fy;
 }
 
-#define PASS_B_SINGLE(T, GH)                                                                 \
+#define PASS_B_SINGLE(T, GH, G, UN)                                                          \
     if (guard_stop(gd)) return;                                                              \
     const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;               \
-    const int s = t / RGB, gl = t % RGB;                                                     \
+    const int s = t / (G), gl = t % (G);                                                     \
     if (s >= n) return;                                                                      \
-    pass_b_body<T, GH>(PASS_B_ARGS, s, gl);
+    pass_b_body<T, GH, G, UN>(PASS_B_ARGS, s, gl);
 
 template <typename T, bool GH>
 __global__ __launch_bounds__(256) void k_pass_b(PASS_B_PARAMS(T))
 {
-    PASS_B_SINGLE(T, GH)
-}
-// The FP32 kernels are latency-bound on their gathers: they ask for more
-// waves per SIMD (the register budget that allows) than the compiler picks.
-template <>
-__global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, true>(PASS_B_PARAMS(float))
-{
-    PASS_B_SINGLE(float, true)
-}
-template <>
-__global__ __launch_bounds__(256) PB_ATTR void k_pass_b<float, false>(PASS_B_PARAMS(float))
-{
-    PASS_B_SINGLE(float, false)
+    PASS_B_SINGLE(T, GH, RGB, 4)
 }
 template <>
 __global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, true>(PASS_B_PARAMS(double))
 {
-    PASS_B_SINGLE(double, true)
+    PASS_B_SINGLE(double, true, RGB, 4)
 }
 template <>
 __global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, false>(PASS_B_PARAMS(double))
 {
-    PASS_B_SINGLE(double, false)
+    PASS_B_SINGLE(double, false, RGB, 4)
+}
+// FP32 schedule variants: G lanes per particle, UN row entries loaded ahead
+// per lane, at least W waves per SIMD (1: the compiler's choice)
+template <bool GH, int G, int UN, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_pass_b_f(
+    PASS_B_PARAMS(float))
+{
+    PASS_B_SINGLE(float, GH, G, UN)
 }
 
 // Batched pass B (fluid only, the list re-tested): every simulation of a
@@ -790,8 +790,9 @@ __global__ __launch_bounds__(256) PB64_ATTR void k_pass_b<double, false>(PASS_B_
     const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
     const Guard gd{nullptr, 0};                                                              \
     const PassBParams P{sd.rho0, sd.cs, sd.nu, sd.alpha_e, sd.fx, sd.fy, sd.dt};             \
-    pass_b_body<T, false>(sd.g, batch_view(nv, sd, sid), 0, b, nl, ex, pa, puv, pf, nullptr, \
-                          nullptr, P, dpdt, dudt, dvdt, gd, (int)(sd.off + sl), gl);
+    pass_b_body<T, false, RGB, (sizeof(T) == 4 ? PB_UNROLL : 4)>(                            \
+        sd.g, batch_view(nv, sd, sid), 0, b, nl, ex, pa, puv, pf, nullptr, nullptr, P, dpdt,  \
+        dudt, dvdt, gd, (int)(sd.off + sl), gl);
 
 #define PASS_B_BATCH_PARAMS(T)                                                               \
     Batch B, NbrView nv, RatesBufs<T> b, NbrList nl, const double4 *__restrict__ pa,          \
@@ -926,6 +927,38 @@ static int ensure_list(sph_ctx* c, int n, const double* x, const double* y, cons
 // One evaluation on (x, y, u, v, p, h, mq): neighbours, the boundary pass
 // when kinds are given (it writes p, and u, v of outlet particles, of the
 // boundary slots; rho_in is the stored density it reads), pass A, pass B.
+// The FP32 schedule variants compiled in, by (lanes, waves) for pass A and
+// (solid ghosts, lanes, unroll, waves) for pass B.
+using PassAF = void (*)(PASS_A_PARAMS(float));
+using PassBF = void (*)(PASS_B_PARAMS(float));
+
+static PassAF pass_a_variant(int G, int W)
+{
+#define PA_V(g, w) \
+    if (G == g && W == w) return k_pass_a_f<g, w>;
+    PA_V(2, 1) PA_V(2, 4) PA_V(2, 5) PA_V(4, 1) PA_V(4, 4) PA_V(4, 5)
+    PA_V(8, 1) PA_V(8, 4) PA_V(8, 5)
+#undef PA_V
+    return nullptr;
+}
+
+template <bool GH>
+static PassBF pass_b_variant(int G, int U, int W)
+{
+#define PB_V(g, u, w) \
+    if (G == g && U == u && W == w) return k_pass_b_f<GH, g, u, w>;
+    PB_V(1, 2, 1) PB_V(1, 2, 4) PB_V(1, 4, 1) PB_V(1, 4, 4)
+    PB_V(2, 2, 1) PB_V(2, 2, 4) PB_V(2, 4, 1) PB_V(2, 4, 4)
+    PB_V(4, 2, 1) PB_V(4, 2, 4) PB_V(4, 4, 1) PB_V(4, 4, 4)
+#undef PB_V
+    return nullptr;
+}
+
+bool rate_schedule_valid(const sph_schedule& s)
+{
+    return pass_a_variant(s.a_lanes, s.a_waves) && pass_b_variant<false>(s.b_lanes, s.b_unroll, s.b_waves);
+}
+
 template <typename T>
 static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u, double* v,
                   double* p, const double* h, const int64_t* mq, const int32_t* kind,
@@ -973,26 +1006,49 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
                        gh ? (const double*)w.ug : nullptr, gh ? (const double*)w.vg : nullptr,
                        w.ugs, w.vgs, kind, gd);
     LAUNCHCHK(c, "gather_state");
-    prof_begin(c, SPH_PROF_PASS_A);
+    prof_begin(c, SPH_PROF_PASS_A, &gd);
     // exact rows for pass B in the adaptation CSR buffer (free during the
     // rate passes; absent from a lean workspace)
     NbrList ex{w.col_tmp, w.cnt_ex, EX_K, n, nullptr};
     if (!w.col_tmp || !w.cnt_ex || w.col_cap < (int64_t)EX_K * n) ex.idx = nullptr;
-    hipLaunchKernelGGL(k_pass_a<T>, dim3((unsigned)cdiv((int64_t)n * RGA, 256)), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                       (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex, gd);
+    const sph_schedule& sc = c->sched;
+    // FP32: the context's schedule; FP64: the fixed plain schedule
+    const int ga = sizeof(T) == 4 ? sc.a_lanes : RGA;
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL(pass_a_variant(sc.a_lanes, sc.a_waves), dim3((unsigned)cdiv((int64_t)n * ga, 256)),
+                           dim3(256), 0, c->stream, c->grid, nv, n, b, nl, (const double4*)w.pa, pf,
+                           cf.rho0, aout, w.r_dxs, w.r_dys, kind, ex, gd);
+    else
+        hipLaunchKernelGGL(k_pass_a<T>, dim3((unsigned)cdiv((int64_t)n * ga, 256)), dim3(256), 0, c->stream,
+                           c->grid, nv, n, b, nl, (const double4*)w.pa, pf, cf.rho0, aout, w.r_dxs,
+                           w.r_dys, kind, ex, gd);
     prof_end(c, SPH_PROF_PASS_A);
     LAUNCHCHK(c, "pass_a");
-    const unsigned nbb = (unsigned)cdiv((int64_t)n * RGB, 256);
+    const int gb = sizeof(T) == 4 ? sc.b_lanes : RGB;
+    const unsigned nbb = (unsigned)cdiv((int64_t)n * gb, 256);
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
-    prof_begin(c, SPH_PROF_PASS_B);
-    if (gh)
-        hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
-                           (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt, gd);
-    else
-        hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
-                           ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
-                           (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt, gd);
+    prof_begin(c, SPH_PROF_PASS_B, &gd);
+    if constexpr (sizeof(T) == 4) {
+        if (gh)
+            hipLaunchKernelGGL(pass_b_variant<true>(sc.b_lanes, sc.b_unroll, sc.b_waves), dim3(nbb), dim3(256),
+                               0, c->stream, c->grid, nv, n, b, nl, ex, (const double4*)w.pa,
+                               (const double2*)w.puv, (const T4*)pf, (const double*)w.ugs,
+                               (const double*)w.vgs, P, dpdt, dudt, dvdt, gd);
+        else
+            hipLaunchKernelGGL(pass_b_variant<false>(sc.b_lanes, sc.b_unroll, sc.b_waves), dim3(nbb), dim3(256),
+                               0, c->stream, c->grid, nv, n, b, nl, ex, (const double4*)w.pa,
+                               (const double2*)w.puv, (const T4*)pf, (const double*)nullptr,
+                               (const double*)nullptr, P, dpdt, dudt, dvdt, gd);
+    } else {
+        if (gh)
+            hipLaunchKernelGGL((k_pass_b<T, true>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+                               ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                               (const double*)w.ugs, (const double*)w.vgs, P, dpdt, dudt, dvdt, gd);
+        else
+            hipLaunchKernelGGL((k_pass_b<T, false>), dim3(nbb), dim3(256), 0, c->stream, c->grid, nv, n, b, nl,
+                               ex, (const double4*)w.pa, (const double2*)w.puv, (const T4*)pf,
+                               (const double*)nullptr, (const double*)nullptr, P, dpdt, dudt, dvdt, gd);
+    }
     prof_end(c, SPH_PROF_PASS_B);
     LAUNCHCHK(c, "pass_b");
     if (c->pair_acc) {

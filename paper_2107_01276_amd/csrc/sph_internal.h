@@ -142,12 +142,20 @@ struct Work {
 struct ProfSlot {
     const char* name;
     hipEvent_t ev[2][512];
+    // guard sequence number of each bracketed launch (-1: unguarded; -2:
+    // void, a launch of a guarded run after its trip, which returned at once)
+    int32_t seq[512];
+    int32_t run_lo;     // first bracket of the guarded run in flight, or -1
     int32_t count;
     double ms;
     int64_t launches;   // bracketed launches
     uint32_t tick;      // launches seen (bracketed or not)
     int32_t skip;       // the current launch is not bracketed
 };
+
+// schedule variants compiled in (rates.hip, nbr.hip)
+bool rate_schedule_valid(const sph_schedule& s);
+bool list_lanes_valid(int lanes);
 
 struct sph_ctx {
     sph_config cfg;
@@ -183,6 +191,7 @@ struct sph_ctx {
     // small host readbacks: pinned, device-coherent words written by a
     // one-lane kernel; word 0 carries the sequence number of the last one
     int64_t iter;         // iteration counter of the schedule (sph_step)
+    sph_schedule sched;   // launch schedule of the FP32 rate passes and the list build
     uint32_t* mbox;       // host address
     uint32_t* mbox_dev;   // the same memory as the device sees it
     uint32_t mbox_seq;
@@ -289,7 +298,10 @@ int schedule_run(sph_ctx* c, sph_particles* ps, sph_background* bg, const sph_pa
 double timestep_of(const sph_config& cfg, double h_min);
 void set_err(sph_ctx* c, const char* fmt, ...);
 int check_hip(sph_ctx* c, hipError_t e, const char* what);
-void prof_begin(sph_ctx* c, int slot);
+void prof_begin(sph_ctx* c, int slot, const Guard* gd = nullptr);
+// a guarded run starts / ended with trip sequence tr (SPH_NOTRIP: none)
+void prof_run_begin(sph_ctx* c);
+void prof_run_end(sph_ctx* c, int32_t tr);
 void prof_end(sph_ctx* c, int slot);
 
 #define SPH_PROF_PASS_A 0
