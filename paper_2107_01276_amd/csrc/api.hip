@@ -310,7 +310,7 @@ extern "C" int sph_create(const sph_config* cfg, int64_t capacity, void* workspa
     c->prof[SPH_PROF_LIST].name = "list";
     c->skin = cfg->list_skin;
     c->list_valid = 0;
-    c->sched = sph_schedule{4, 5, 2, 2, 4, 4};
+    c->sched = default_schedule();
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c->stream, c->w.status, c->w.ctr);
     if (hipGetLastError() != hipSuccess) {
         hipHostFree(c->mbox);
@@ -971,6 +971,7 @@ extern "C" int sph_rates_noalloc(const sph_config* cfg, const sph_particles* ps,
     c.capacity = n > 0 ? n : 1;
     c.stream = (hipStream_t)stream;
     c.skin = 0.0;
+    c.sched = default_schedule();
     c.mbox = nullptr;  // no readback happens on this path
     // the array keeps the last call's contents: clear the counters
     hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, c.stream, c.w.status, c.w.ctr);

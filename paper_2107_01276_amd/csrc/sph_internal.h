@@ -153,9 +153,11 @@ struct ProfSlot {
     int32_t skip;       // the current launch is not bracketed
 };
 
-// schedule variants compiled in (rates.hip, nbr.hip)
+// schedule variants compiled in (rates.hip, nbr.hip); every context starts
+// with the default
 bool rate_schedule_valid(const sph_schedule& s);
 bool list_lanes_valid(int lanes);
+inline sph_schedule default_schedule() { return sph_schedule{4, 5, 2, 2, 4, 4}; }
 
 struct sph_ctx {
     sph_config cfg;
