@@ -549,132 +549,6 @@ static void shift_one(const or_domain* d, double rho0, int64_t i, const double* 
     *dys = ddy;
 }
 
-/* Exact sum of doubles, rounded once (a long accumulator).  Every finite
- * double is an integer multiple of 2^-1074, so a sum of them is V 2^-1074
- * with V an integer; V is held in base-2^32 digits (int64 cells with room
- * for the carries of 2^30 additions), and the result is V rounded to 53
- * significant bits, ties to even, times 2^-1074: the correctly rounded sum,
- * the same whatever the order of the terms.
- * READING: the sums over neighbours of the adaptation's shift (the shift
- * terms and the gradients of the Taylor correction) and of the background
- * update (the logarithms of the sizes in the grading, h_j and the shift
- * terms in the smoothing) are set sums.  They are taken correctly rounded,
- * so that these passes are functions of the particle set alone, whatever
- * the slot order: near-cancelling terms (a particle on a symmetry line)
- * round differently in different orders even when compensated, and repeated
- * passes can amplify that. */
-#define OR_XS_N 70
-typedef struct { int64_t d[OR_XS_N]; } or_xsum;
-
-static void xsum_init(or_xsum* a) { memset(a->d, 0, sizeof(a->d)); }
-
-static void xsum_add(or_xsum* a, double x)
-{
-    if (x == 0.0) return;
-    uint64_t bits;
-    memcpy(&bits, &x, sizeof(bits));
-    int neg = (int)(bits >> 63);
-    int E = (int)((bits >> 52) & 0x7ff);
-    uint64_t m = bits & ((1ull << 52) - 1);
-    int p = 0;                   /* x = m 2^(p - 1074) */
-    if (E > 0) { m |= 1ull << 52; p = E - 1; }
-    int k = p / 32, sft = p % 32;
-    uint64_t lo = (m & 0xffffffffull) << sft;  /* < 2^63 */
-    uint64_t hi = (m >> 32) << sft;            /* < 2^52 */
-    int64_t c0 = (int64_t)(lo & 0xffffffffull);
-    int64_t c1 = (int64_t)(lo >> 32) + (int64_t)(hi & 0xffffffffull);
-    int64_t c2 = (int64_t)(hi >> 32);
-    if (neg) { c0 = -c0; c1 = -c1; c2 = -c2; }
-    a->d[k] += c0;
-    a->d[k + 1] += c1;
-    a->d[k + 2] += c2;
-}
-
-/* digits to [0, 2^32) from the bottom up, the top cell keeping the sign */
-static void xsum_carry(int64_t* d)
-{
-    for (int k = 0; k < OR_XS_N - 1; ++k) {
-        int64_t c = d[k] >> 32;  /* floor(d / 2^32) */
-        d[k] -= c * 4294967296LL;
-        d[k + 1] += c;
-    }
-}
-
-static int xsum_bit(const int64_t* d, int i) { return (int)((d[i / 32] >> (i % 32)) & 1); }
-
-static double xsum_get(const or_xsum* a)
-{
-    int64_t d[OR_XS_N];
-    memcpy(d, a->d, sizeof(d));
-    xsum_carry(d);
-    int neg = d[OR_XS_N - 1] < 0;
-    if (neg) {  /* |V| */
-        for (int k = 0; k < OR_XS_N; ++k) d[k] = -d[k];
-        xsum_carry(d);
-    }
-    int nb = 0;  /* bit length of |V| */
-    for (int i = 32 * OR_XS_N - 1; i >= 0; --i)
-        if (xsum_bit(d, i)) { nb = i + 1; break; }
-    if (nb == 0) return 0.0;
-    int drop = nb > 53 ? nb - 53 : 0;
-    double t = 0.0;  /* the kept 53 (or fewer) bits, exact */
-    for (int i = nb - 1; i >= drop; --i) t = 2.0 * t + (double)xsum_bit(d, i);
-    if (drop > 0 && xsum_bit(d, drop - 1)) {
-        int sticky = 0;
-        for (int i = 0; i < drop - 1 && !sticky; ++i) sticky = xsum_bit(d, i);
-        if (sticky || fmod(t, 2.0) == 1.0) t += 1.0;  /* above half, or a tie to even */
-    }
-    double r = ldexp(t, drop - 1074);
-    return neg ? -r : r;
-}
-
-/* The exact sum of n doubles, rounded once (pinned against Python's
- * correctly rounded math.fsum). */
-double or_exact_sum(int64_t n, const double* x)
-{
-    or_xsum a;
-    xsum_init(&a);
-    for (int64_t i = 0; i < n; ++i) xsum_add(&a, x[i]);
-    return xsum_get(&a);
-}
-
-/* The limited shift of particle b (eqs. shift-deltar and shift-limit, the
- * same terms as shift_one) with the sums correctly rounded: the shift of
- * the adaptation and of the background update. */
-static void shift_one_exact(const or_domain* d, double rho0, int64_t b, const double* x,
-                         const double* y, const double* h, const double* m,
-                         const int64_t* rp, const int32_t* col, double* dxs, double* dys)
-{
-    double fxi = or_kf(OR_XI);
-    or_xsum sx, sy;
-    xsum_init(&sx);
-    xsum_init(&sy);
-    for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
-        int64_t j = col[k];
-        double dx = mi_axis(d, 0, x[b] - x[j]);
-        double dy = mi_axis(d, 1, y[b] - y[j]);
-        double r = sqrt(dx * dx + dy * dy);
-        if (r <= 0.0) continue;
-        double hij = 0.5 * (h[b] + h[j]);
-        double wr = or_kf(r / hij) / fxi;
-        double coef = (m[j] / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
-        double t = coef * (or_dwdr(r, hij) / r);
-        xsum_add(&sx, t * dx);
-        xsum_add(&sy, t * dy);
-    }
-    double pref = -0.5 * (h[b] * h[b]);
-    double ddx = pref * xsum_get(&sx), ddy = pref * xsum_get(&sy);
-    double mag = sqrt(ddx * ddx + ddy * ddy);
-    double lim = 0.25 * h[b];
-    if (mag > lim) {
-        double th = lim / mag;
-        ddx = ddx * th;
-        ddy = ddy * th;
-    }
-    *dxs = ddx;
-    *dys = ddy;
-}
-
 /* READING: the average pressure of eq. (pavg) is formed as
  * p_i + (1/N_i) sum_j (p_j - p_i), the same mean written about p_i, so that a
  * uniform pressure gives p_avg = p exactly and the reduced pressure of eq.
@@ -1601,10 +1475,8 @@ static int shift_pass(const or_domain* d, const or_params* P, int64_t n, or_stat
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; ++i) {
         if (s->kind[i] != 0) { ddx[i] = ddy[i] = 0.0; nu[i] = s->u[i]; nv[i] = s->v[i]; np[i] = s->p[i]; continue; }
-        shift_one_exact(d, P->rho0, i, s->x, s->y, s->h, m, rp, col, &ddx[i], &ddy[i]);
-        /* gradients of u, v, p for the Taylor correction (sums rounded once) */
-        or_xsum g[6];
-        for (int q = 0; q < 6; ++q) xsum_init(&g[q]);
+        shift_one(d, P->rho0, i, s->x, s->y, s->h, m, rp, col, &ddx[i], &ddy[i]);
+        double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
             int64_t j = col[k];
             double dx = mi_axis(d, 0, s->x[i] - s->x[j]);
@@ -1615,12 +1487,10 @@ static int shift_pass(const or_domain* d, const or_params* P, int64_t n, or_stat
             double wx = f * dx, wy = f * dy;
             double Vj = m[j] / s->rho[j];
             double du = s->u[j] - s->u[i], dv = s->v[j] - s->v[i], dp = s->p[j] - s->p[i];
-            xsum_add(&g[0], Vj * du * wx); xsum_add(&g[1], Vj * du * wy);
-            xsum_add(&g[2], Vj * dv * wx); xsum_add(&g[3], Vj * dv * wy);
-            xsum_add(&g[4], Vj * dp * wx); xsum_add(&g[5], Vj * dp * wy);
+            gux += Vj * du * wx; guy += Vj * du * wy;
+            gvx += Vj * dv * wx; gvy += Vj * dv * wy;
+            gpx += Vj * dp * wx; gpy += Vj * dp * wy;
         }
-        double gux = xsum_get(&g[0]), guy = xsum_get(&g[1]), gvx = xsum_get(&g[2]);
-        double gvy = xsum_get(&g[3]), gpx = xsum_get(&g[4]), gpy = xsum_get(&g[5]);
         nu[i] = s->u[i] + (gux * ddx[i] + guy * ddy[i]);
         nv[i] = s->v[i] + (gvx * ddx[i] + gvy * ddy[i]);
         np[i] = s->p[i] + (gpx * ddx[i] + gpy * ddy[i]);
@@ -1647,10 +1517,9 @@ static int hupdate_pass(const or_domain* d, const or_params* P, int64_t n, or_st
     double* nh = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) {
         if (s->kind[i] != 0) { nh[i] = s->h[i]; continue; }
-        or_xsum sm;
-        xsum_init(&sm);
-        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) xsum_add(&sm, (double)s->mq[col[k]] * P->mass_q);
-        double mbar = xsum_get(&sm) / (double)(rp[i + 1] - rp[i]);
+        double sm = 0.0;
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) sm += (double)s->mq[col[k]] * P->mass_q;
+        double mbar = sm / (double)(rp[i + 1] - rp[i]);
         nh[i] = P->hdx * sqrt(mbar / s->rho[i]);
     }
     memcpy(s->h, nh, sizeof(double) * (size_t)n);
@@ -1818,6 +1687,130 @@ int or_mref_lookup(const or_domain* d, int64_t n, const double* x, const double*
  *   the Lind shift (eq. shift-deltar, volume m_b / rho_0), both from the
  *   same neighbour set, applied together.
  * Returns the new background count or a negative error. */
+/* Exact sum of doubles, rounded once (a long accumulator).  Every finite
+ * double is an integer multiple of 2^-1074, so a sum of them is V 2^-1074
+ * with V an integer; V is held in base-2^32 digits (int64 cells with room
+ * for the carries of 2^30 additions), and the result is V rounded to 53
+ * significant bits, ties to even, times 2^-1074: the correctly rounded sum,
+ * the same whatever the order of the terms.
+ * READING: the background update's sums over neighbours (the logarithms of
+ * the sizes in the grading, h_j and the shift terms in the smoothing) are set
+ * sums.  They are taken correctly rounded, so that the update is a function
+ * of the particle set alone, whatever the slot order: near-cancelling shift
+ * terms (a particle on a symmetry line) round differently in different
+ * orders even when compensated, and the repeated update can amplify that. */
+#define OR_XS_N 70
+typedef struct { int64_t d[OR_XS_N]; } or_xsum;
+
+static void xsum_init(or_xsum* a) { memset(a->d, 0, sizeof(a->d)); }
+
+static void xsum_add(or_xsum* a, double x)
+{
+    if (x == 0.0) return;
+    uint64_t bits;
+    memcpy(&bits, &x, sizeof(bits));
+    int neg = (int)(bits >> 63);
+    int E = (int)((bits >> 52) & 0x7ff);
+    uint64_t m = bits & ((1ull << 52) - 1);
+    int p = 0;                   /* x = m 2^(p - 1074) */
+    if (E > 0) { m |= 1ull << 52; p = E - 1; }
+    int k = p / 32, sft = p % 32;
+    uint64_t lo = (m & 0xffffffffull) << sft;  /* < 2^63 */
+    uint64_t hi = (m >> 32) << sft;            /* < 2^52 */
+    int64_t c0 = (int64_t)(lo & 0xffffffffull);
+    int64_t c1 = (int64_t)(lo >> 32) + (int64_t)(hi & 0xffffffffull);
+    int64_t c2 = (int64_t)(hi >> 32);
+    if (neg) { c0 = -c0; c1 = -c1; c2 = -c2; }
+    a->d[k] += c0;
+    a->d[k + 1] += c1;
+    a->d[k + 2] += c2;
+}
+
+/* digits to [0, 2^32) from the bottom up, the top cell keeping the sign */
+static void xsum_carry(int64_t* d)
+{
+    for (int k = 0; k < OR_XS_N - 1; ++k) {
+        int64_t c = d[k] >> 32;  /* floor(d / 2^32) */
+        d[k] -= c * 4294967296LL;
+        d[k + 1] += c;
+    }
+}
+
+static int xsum_bit(const int64_t* d, int i) { return (int)((d[i / 32] >> (i % 32)) & 1); }
+
+static double xsum_get(const or_xsum* a)
+{
+    int64_t d[OR_XS_N];
+    memcpy(d, a->d, sizeof(d));
+    xsum_carry(d);
+    int neg = d[OR_XS_N - 1] < 0;
+    if (neg) {  /* |V| */
+        for (int k = 0; k < OR_XS_N; ++k) d[k] = -d[k];
+        xsum_carry(d);
+    }
+    int nb = 0;  /* bit length of |V| */
+    for (int i = 32 * OR_XS_N - 1; i >= 0; --i)
+        if (xsum_bit(d, i)) { nb = i + 1; break; }
+    if (nb == 0) return 0.0;
+    int drop = nb > 53 ? nb - 53 : 0;
+    double t = 0.0;  /* the kept 53 (or fewer) bits, exact */
+    for (int i = nb - 1; i >= drop; --i) t = 2.0 * t + (double)xsum_bit(d, i);
+    if (drop > 0 && xsum_bit(d, drop - 1)) {
+        int sticky = 0;
+        for (int i = 0; i < drop - 1 && !sticky; ++i) sticky = xsum_bit(d, i);
+        if (sticky || fmod(t, 2.0) == 1.0) t += 1.0;  /* above half, or a tie to even */
+    }
+    double r = ldexp(t, drop - 1074);
+    return neg ? -r : r;
+}
+
+/* The exact sum of n doubles, rounded once (pinned against Python's
+ * correctly rounded math.fsum). */
+double or_exact_sum(int64_t n, const double* x)
+{
+    or_xsum a;
+    xsum_init(&a);
+    for (int64_t i = 0; i < n; ++i) xsum_add(&a, x[i]);
+    return xsum_get(&a);
+}
+
+/* The limited shift of background particle b (eqs. shift-deltar and
+ * shift-limit, the same terms as shift_one) with the sums correctly
+ * rounded. */
+static void bg_shift_one(const or_domain* d, double rho0, int64_t b, const double* x,
+                         const double* y, const double* h, const double* m,
+                         const int64_t* rp, const int32_t* col, double* dxs, double* dys)
+{
+    double fxi = or_kf(OR_XI);
+    or_xsum sx, sy;
+    xsum_init(&sx);
+    xsum_init(&sy);
+    for (int64_t k = rp[b]; k < rp[b + 1]; ++k) {
+        int64_t j = col[k];
+        double dx = mi_axis(d, 0, x[b] - x[j]);
+        double dy = mi_axis(d, 1, y[b] - y[j]);
+        double r = sqrt(dx * dx + dy * dy);
+        if (r <= 0.0) continue;
+        double hij = 0.5 * (h[b] + h[j]);
+        double wr = or_kf(r / hij) / fxi;
+        double coef = (m[j] / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+        double t = coef * (or_dwdr(r, hij) / r);
+        xsum_add(&sx, t * dx);
+        xsum_add(&sy, t * dy);
+    }
+    double pref = -0.5 * (h[b] * h[b]);
+    double ddx = pref * xsum_get(&sx), ddy = pref * xsum_get(&sy);
+    double mag = sqrt(ddx * ddx + ddy * ddy);
+    double lim = 0.25 * h[b];
+    if (mag > lim) {
+        double th = lim / mag;
+        ddx = ddx * th;
+        ddy = ddy * th;
+    }
+    *dxs = ddx;
+    *dys = ddy;
+}
+
 static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb, int64_t cap,
                            double* bx, double* by, double* bh, double* bds, int32_t* bmask,
                            int64_t* bmq, double* bmref, int64_t ns, const double* sx,
@@ -1911,7 +1904,7 @@ static int64_t bg_one_pass(const or_domain* d, const or_bgparams* B, int64_t nb,
             xsum_init(&sh_);
             for (int64_t k = rp[b]; k < rp[b + 1]; ++k) xsum_add(&sh_, bh[col[k]]);
             nh[b] = 0.5 * ((bh[b] / 2.0) * (1.0 + sqrt(B->n_r / N)) + xsum_get(&sh_) / N);
-            shift_one_exact(d, B->rho0, b, bx, by, bh, m, rp, col, &ddx[b], &ddy[b]);
+            bg_shift_one(d, B->rho0, b, bx, by, bh, m, rp, col, &ddx[b], &ddy[b]);
         }
         for (int64_t b = 0; b < nb; ++b) {
             bh[b] = nh[b];

@@ -248,29 +248,3 @@ def test_background_square_levels(orc):
     assert np.corrcoef(dist, ds)[0, 1] > 0.7
     assert out["mask"].sum() > 0 and np.all(ds[out["mask"] == 1] == 0.1)
     assert np.all(out["mref"] == 1.0 * ds * ds)
-
-
-def test_shift_and_h_update_are_order_free(orc):
-    """The adaptation's shift (with the Taylor correction) and h update are
-    functions of the particle set: with the slots permuted, every particle
-    ends bit for bit where it did, with the same corrected u, v, p and h.
-    Their sums over neighbours are rounded once (the plain sums in slot
-    order fail this on positions and fields)."""
-    st, s = tgv_state(40, seed=12)
-    n = s["x"].size
-    rng = np.random.default_rng(13)
-    st["u"] = st["u"] + 0.1 * rng.standard_normal(n)
-    st["p"] = 1.0 + 0.3 * rng.standard_normal(n)
-    st["rho"] = 1.0 + 0.02 * rng.standard_normal(n)
-    dom = orc.Dom((0, 0), (1, 1), (True, True))
-    prm = orc.Prm(mass_q=s["mass_q"], shift_iters=1)
-    perm = rng.permutation(n)
-    stp = {k: (np.asarray(v)[perm] if isinstance(v, np.ndarray) and np.asarray(v).shape[:1] == (n,)
-               else v) for k, v in st.items()}
-    a = orc.shift_only(dom, prm, st)
-    b = orc.shift_only(dom, prm, stp)
-    for k in ("x", "y", "u", "v", "p"):
-        assert np.array_equal(a[k][perm], b[k]), k
-    ha = orc.hupdate_only(dom, prm, a)
-    hb = orc.hupdate_only(dom, prm, b)
-    assert np.array_equal(ha[perm], hb)
