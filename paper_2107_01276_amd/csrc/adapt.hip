@@ -922,17 +922,29 @@ __global__ __launch_bounds__(256) void k_bg_mask(Grid g, NbrView nv, int nb,
 // double is an integer multiple of 2^-1074, so the sum is V 2^-1074 with V
 // an integer, kept here as signed base-2^32 digits in int64 cells (each
 // addition puts at most 2^33 into a cell, so 2^30 additions never overflow
-// one).  get() returns V rounded to 53 significant bits, ties to even, times
+// one).  Only the cells lo..hi that the terms reached are kept (the others
+// are zero), so a row whose terms span a few binades costs a few cells.
+// get() returns V rounded to 53 significant bits, ties to even, times
 // 2^-1074: the correctly rounded sum, the same in any order of the terms.
-// The cells live in private memory (about 560 bytes per accumulator); the
-// background sweeps that use it are not on the stepping path.
+// The cells live in private memory; it is used only for the rows the fast
+// path below cannot prove.
 struct XSum {
-    static constexpr int NC = 70;
+    static constexpr int NC = 72;  // a double reaches cells 0..65; three above for carries
     long long d[NC];
-    __device__ __forceinline__ XSum()
+    int lo = NC, hi = -1;
+    // cells a..b valid, the new ones zero
+    __device__ __forceinline__ void touch(int a, int b)
     {
-#pragma unroll
-        for (int i = 0; i < NC; ++i) d[i] = 0;
+        if (hi < lo) {
+            for (int i = a; i <= b; ++i) d[i] = 0;
+            lo = a;
+            hi = b;
+            return;
+        }
+        for (int i = a; i < lo; ++i) d[i] = 0;
+        for (int i = hi + 1; i <= b; ++i) d[i] = 0;
+        if (a < lo) lo = a;
+        if (b > hi) hi = b;
     }
     __device__ __forceinline__ void add(double x)
     {
@@ -955,14 +967,15 @@ struct XSum {
             c1 = -c1;
             c2 = -c2;
         }
+        touch(k, k + 2);
         d[k] += c0;
         d[k + 1] += c1;
         d[k + 2] += c2;
     }
-    // cells to digits in [0, 2^32), the last cell keeping the sign
-    __device__ __forceinline__ void normalise()
+    // cells lo..top-1 to digits in [0, 2^32), cell top keeping the sign
+    __device__ __forceinline__ void normalise(int top)
     {
-        for (int i = 0; i < NC - 1; ++i) {
+        for (int i = lo; i < top; ++i) {
             const long long c = d[i] >> 32;
             d[i] &= 0xffffffffll;
             d[i + 1] += c;
@@ -970,39 +983,43 @@ struct XSum {
     }
     __device__ bool get(double& out)
     {
-        normalise();
-        const bool neg = d[NC - 1] < 0;
-        if (neg) {
-            for (int i = 0; i < NC; ++i) d[i] = -d[i];
-            normalise();
-        }
-        int t = NC - 1;
-        while (t >= 0 && d[t] == 0) --t;
-        if (t < 0) {
+        if (hi < lo) {
             out = 0.0;
             return true;
         }
-        const unsigned long long top = (unsigned long long)d[t];
-        const int bl = 64 - __clzll(top);  // bits of the top digit
-        const int nb = 32 * t + bl;         // bits of |V|
+        const int top = hi + 3;  // <= 68: room for the carries out of hi
+        touch(lo, top);
+        normalise(top);
+        const bool neg = d[top] < 0;
+        if (neg) {
+            for (int i = lo; i <= top; ++i) d[i] = -d[i];
+            normalise(top);
+        }
+        int t = top;
+        while (t >= lo && d[t] == 0) --t;
+        if (t < lo) {
+            out = 0.0;
+            return true;
+        }
+        auto cell = [&](int i) -> unsigned long long {
+            return (i >= lo && i <= top) ? (unsigned long long)d[i] : 0ull;
+        };
+        const unsigned long long w_hi = cell(t);
+        const int bl = 64 - __clzll(w_hi);  // bits of the top digit
+        const int nb = 32 * t + bl;          // bits of |V|
         double r;
         if (nb <= 53) {
-            const unsigned long long v = (t > 0 ? (unsigned long long)d[1] << 32 : 0ull) |
-                                         (unsigned long long)d[0];
-            r = ldexp((double)v, -1074);
+            r = ldexp((double)((cell(1) << 32) | cell(0)), -1074);
         } else {
             // 96-bit window of the top three digits; what lies below it only
             // decides a tie
-            const unsigned long long w_hi = top;
-            const unsigned long long d1 = t >= 1 ? (unsigned long long)d[t - 1] : 0ull;
-            const unsigned long long d2 = t >= 2 ? (unsigned long long)d[t - 2] : 0ull;
-            const unsigned long long w_lo = (d1 << 32) | d2;
+            const unsigned long long w_lo = (cell(t - 1) << 32) | cell(t - 2);
             const int cut = bl + 11;  // window bits below the 53 kept
             unsigned long long kept = (w_hi << (64 - cut)) | (w_lo >> cut);
             const unsigned long long rem = w_lo & ((1ull << cut) - 1);
             const unsigned long long half = 1ull << (cut - 1);
             bool below = false;
-            for (int i = 0; i < t - 2 && !below; ++i) below = d[i] != 0;
+            for (int i = lo; i < t - 2 && !below; ++i) below = d[i] != 0;
             if (rem > half || (rem == half && (below || (kept & 1ull)))) ++kept;
             r = ldexp((double)kept, nb - 53 - 1074);
         }
@@ -1022,36 +1039,66 @@ __device__ __forceinline__ double spacing_min(double v)
     return ldexp(1.0, (pow2 && be > 1) ? be - 1076 : be - 1075);
 }
 
-// The fast path to the same result: a TwoSum cascade that also adds up the
-// magnitudes of the exact errors it carries.  With S the exact sum, s the
-// running sum and c the rounded sum of the n errors e_k (S = s + sum e_k),
-// |S - (s + c)| <= gamma_{n-1} sum|e_k| (recursive summation), and
-// (res, r) = TwoSum(s, c) is exact, so |S - res| <= |r| + that bound.  When
-// twice the bound (taken with margins for its own rounding) is below the
-// spacing of the doubles at res, S lies strictly inside res's rounding
-// interval and res is the correctly rounded sum; get() then returns true.
-// It returns false when the terms cancel almost completely (a particle in a
-// symmetric neighbourhood), and the row is summed again with XSum.
+__device__ __forceinline__ void two_sum(double x, double y, double& t, double& e)
+{
+    t = x + y;
+    const double z = t - x;
+    e = (x - (t - z)) + (y - z);
+}
+
+// The fast path to the same result: a two-level cascade of Knuth's TwoSum.
+// The running sum s takes each term, the first-level sum c1 takes each exact
+// error of s (again by TwoSum), and c2 adds up the exact errors e_k of c1
+// with their magnitudes in a; so the exact sum is S = s + c1 + sum e_k, and
+// |c2 - sum e_k| <= gamma_{n-1} sum |e_k| (recursive summation, any order
+// or grouping).  get() forms res = s + c1 + c2 by exact steps up to one
+// rounding, whose exact error is kept: when the known errors plus that bound
+// (with margins for its own rounding) are below half the spacing of the
+// doubles at res, S lies strictly inside res's rounding interval and res is
+// the correctly rounded sum.  The bound is about n^2 u^3 sum|x|, so sums that
+// cancel down to about 1e-30 of their terms are proven; get() returns false
+// for the rest, and the row is summed again with XSum.  Partial sums of a
+// lane group merge by the same steps.
 struct FSum {
-    double s = 0.0, c = 0.0, a = 0.0;
+    double s = 0.0, c1 = 0.0, c2 = 0.0, a = 0.0;
     int n = 0;
     __device__ __forceinline__ void add(double x)
     {
-        const double t = s + x;
-        const double z = t - s;
-        const double e = (s - (t - z)) + (x - z);
-        s = t;
-        c += e;
-        a += fabs(e);
+        double e1, e2;
+        two_sum(s, x, s, e1);
+        two_sum(c1, e1, c1, e2);
+        c2 += e2;
+        a += fabs(e2);
         ++n;
+    }
+    // adds the partial sum held by lane (this lane ^ o) of the wave; both
+    // lanes of the pair end with the same value
+    __device__ __forceinline__ void merge_xor(int o)
+    {
+        const double s2 = __shfl_xor(s, o, 64), c12 = __shfl_xor(c1, o, 64);
+        const double c22 = __shfl_xor(c2, o, 64), a2 = __shfl_xor(a, o, 64);
+        const int n2 = __shfl_xor(n, o, 64);
+        add(s2);
+        add(c12);
+        c2 += c22;
+        a += a2;
+        n += n2;
     }
     __device__ __forceinline__ bool get(double& out) const
     {
-        const double res = s + c;
-        const double z = res - s;
-        const double r = (s - (res - z)) + (c - z);
+        double u1, v1, u2, v2, res, v3;
+        two_sum(s, c1, u1, v1);
+        two_sum(v1, c2, u2, v2);
+        two_sum(u1, u2, res, v3);
+        // S = res + v3 + v2 + (sum e_k - c2)
+        if (v2 == 0.0 && a == 0.0) {
+            // every e_k is zero and u2 = v1 + c2 exactly: S = u1 + u2, and
+            // res is its round-to-nearest-even, ties included
+            out = res;
+            return true;
+        }
         const double g = 2.0 * (double)(n + 2) * 0x1p-53;  // >= gamma_{n-1} / (1 - gamma_{n-1})
-        const double bound = (fabs(r) + g * a) * (1.0 + 0x1p-40);
+        const double bound = (fabs(v3) + fabs(v2) + g * a) * (1.0 + 0x1p-40);
         if (2.0 * bound < spacing_min(res)) {
             out = res;
             return true;
@@ -1060,32 +1107,61 @@ struct FSum {
     }
 };
 
-// Size grading of background particle b (sorted position sp) over its
-// neighbours, step 2 of section 3.3.  Acc sums the logarithms of the sizes
-// (the walk is not in slot order; the sum is rounded once); returns false
-// when Acc cannot prove its sum, and then writes nothing.
-template <class Acc>
-__device__ __forceinline__ bool bg_grade_row(const Grid& g, const NbrView& nv, int sp,
+// lanes per particle of the background sweeps
+#define BG_G 4
+
+// Sorted copies for the background sweeps, so that a cell run's records are
+// consecutive: ds_s[sp] = ds[perm[sp]], m_s[sp] = mq[perm[sp]] q.
+__global__ __launch_bounds__(256) void k_bg_pack(int nb, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ ds,
+                                                 const int64_t* __restrict__ mq, double q,
+                                                 double* ds_s, double* m_s)
+{
+    const int sp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sp >= nb) return;
+    const int b = perm[sp];
+    if (ds_s) ds_s[sp] = ds[b];
+    if (m_s) m_s[sp] = (double)mq[b] * q;
+}
+
+// Size grading of background particle b (sorted position sp, lane gl of its
+// group of G) over its neighbours, step 2 of section 3.3.  Acc sums the
+// logarithms of the sizes (the walk is not in slot order; the sum is
+// rounded once); returns false when Acc cannot prove its sum, and then
+// writes nothing.  Every lane of the group returns the same.
+template <int G, class Acc>
+__device__ __forceinline__ bool bg_grade_row(const Grid& g, const NbrView& nv, int sp, int gl,
                                              const int32_t* __restrict__ mask,
-                                             const double* __restrict__ ds, double cr,
+                                             const double* __restrict__ ds,
+                                             const double* __restrict__ ds_s, double cr,
                                              double ds_min, double ds_max, double* nds)
 {
     const int b = nv.perm[sp];
     if (mask[b]) {
-        nds[b] = ds[b];
+        if (gl == 0) nds[b] = ds[b];
         return true;
     }
-    double mn = 0.0, mx = 0.0;
+    double mn = HUGE_VAL, mx = -HUGE_VAL;
     Acc sl;
     int cnt = 0;
-    for_each_neighbor(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]),
-                      [&](int js, double, double, double, double) {
-                          const double v = ds[nv.perm[js]];
-                          if (cnt == 0 || v < mn) mn = v;
-                          if (cnt == 0 || v > mx) mx = v;
-                          sl.add(log(v));
-                          ++cnt;
-                      });
+    group_walk<G>(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]), gl,
+                  [&](int js, bool pass, double, double, double, double) {
+                      if (!pass) return;
+                      const double v = ds_s[js];
+                      mn = fmin(mn, v);
+                      mx = fmax(mx, v);
+                      sl.add(log(v));
+                      ++cnt;
+                  });
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, 64));
+            mx = fmax(mx, __shfl_xor(mx, o, 64));
+            cnt += __shfl_xor(cnt, o, 64);
+            sl.merge_xor(o);
+        }
+    }
     const double cr3 = cr * cr * cr;
     double v;
     if (mx / mn < cr3) {
@@ -1097,31 +1173,35 @@ __device__ __forceinline__ bool bg_grade_row(const Grid& g, const NbrView& nv, i
     }
     if (v < ds_min) v = ds_min;
     if (v > ds_max) v = ds_max;
-    nds[b] = v;
+    if (gl == 0) nds[b] = v;
     return true;
 }
 
-// fast path; redo[sp] = 1 where the exact sum is needed
+// fast path, BG_G lanes per particle; redo[sp] = 1 where the exact sum is needed
 __global__ __launch_bounds__(256) void k_bg_grade(Grid g, NbrView nv, int nb,
                                                   const int32_t* __restrict__ mask,
-                                                  const double* __restrict__ ds, double cr,
+                                                  const double* __restrict__ ds,
+                                                  const double* __restrict__ ds_s, double cr,
                                                   double ds_min, double ds_max, double* nds,
                                                   int32_t* redo)
 {
-    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int sp = t / BG_G, gl = t % BG_G;
     if (sp >= nb) return;
-    redo[sp] = bg_grade_row<FSum>(g, nv, sp, mask, ds, cr, ds_min, ds_max, nds) ? 0 : 1;
+    const bool ok = bg_grade_row<BG_G, FSum>(g, nv, sp, gl, mask, ds, ds_s, cr, ds_min, ds_max, nds);
+    if (gl == 0) redo[sp] = ok ? 0 : 1;
 }
 
 __global__ __launch_bounds__(256) void k_bg_grade_exact(Grid g, NbrView nv, int nb,
                                                         const int32_t* __restrict__ mask,
-                                                        const double* __restrict__ ds, double cr,
+                                                        const double* __restrict__ ds,
+                                                        const double* __restrict__ ds_s, double cr,
                                                         double ds_min, double ds_max, double* nds,
                                                         const int32_t* __restrict__ redo)
 {
     const int sp = blockIdx.x * blockDim.x + threadIdx.x;
     if (sp >= nb || !redo[sp]) return;
-    bg_grade_row<XSum>(g, nv, sp, mask, ds, cr, ds_min, ds_max, nds);
+    bg_grade_row<1, XSum>(g, nv, sp, 0, mask, ds, ds_s, cr, ds_min, ds_max, nds);
 }
 
 __global__ __launch_bounds__(256) void k_bg_setds(int nb, const double* __restrict__ nds,
@@ -1172,16 +1252,16 @@ __global__ __launch_bounds__(256) void k_bg_split_apply(Grid g, int nb, sph_back
 // Background h smoothing and shifting, section 3.3: the new h is the mean of
 // the target from the neighbour count and the neighbours' mean h; the shift
 // is the limited Lind shift of eqs. (shift-deltar) and (shift-limit) with
-// volume m_j / rho0 and the gradient at h_ij.  One thread per particle in the
-// sorted order sp (slot b) of the background's own build, walking its cells:
-// no neighbour list, so a particle may have any number of neighbours (a
-// coarse particle among fine ones early in the initial passes has
-// thousands).  The walk order is not the slot order, so the sums over
-// neighbours (of h_j and of the shift terms) are exact sums rounded once
-// (XSum): their results follow from the neighbour set alone.
-template <class Acc>
-__device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, int sp,
-                                              const sph_background& B, double q, double rho0,
+// volume m_j / rho0 and the gradient at h_ij.  Particle sp (slot b) of the
+// background's own build, lane gl of its group of G, walking its cells: no
+// neighbour list, so a particle may have any number of neighbours (a coarse
+// particle among fine ones early in the initial passes has thousands).  The
+// walk order is not the slot order, so the sums over neighbours (of h_j and
+// of the shift terms) are exact sums rounded once: their results follow from
+// the neighbour set alone.  Every lane of the group returns the same.
+template <int G, class Acc>
+__device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, int sp, int gl,
+                                              const double* __restrict__ m_s, double rho0,
                                               double n_r, double* nh, double* ddx, double* ddy)
 {
     const int b = nv.perm[sp];
@@ -1189,22 +1269,34 @@ __device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, 
     const double fxi = kern_f<double>(SPH_XI);
     Acc sh, sx, sy;
     int cnt = 0;
-    for_each_neighbor(g, nv, xb, yb, hb, key_level(g, nv.keys[sp]),
-                      [&](int js, double dx, double dy, double r2, double hj) {
-                          ++cnt;
-                          sh.add(hj);
-                          const double r = sqrt(r2);
-                          if (r <= 0.0) return;
-                          const double hij = 0.5 * (hb + hj);
-                          const double wr = kern_f<double>(r / hij) / fxi;
-                          const double mj = (double)B.mq[nv.perm[js]] * q;
-                          const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
-                          const double t = coef * (kern_dw64(r, hij) / r);
-                          sx.add(t * dx);
-                          sy.add(t * dy);
-                      });
+    group_walk<G>(g, nv, xb, yb, hb, key_level(g, nv.keys[sp]), gl,
+                  [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+                      if (!pass) return;
+                      ++cnt;
+                      sh.add(hj);
+                      const double r = sqrt(r2);
+                      if (r <= 0.0) return;
+                      const double hij = 0.5 * (hb + hj);
+                      const double wr = kern_f<double>(r / hij) / fxi;
+                      const double mj = m_s[js];
+                      const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+                      const double t = coef * (kern_dw64(r, hij) / r);
+                      sx.add(t * dx);
+                      sy.add(t * dy);
+                  });
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1) {
+            cnt += __shfl_xor(cnt, o, 64);
+            sh.merge_xor(o);
+            sx.merge_xor(o);
+            sy.merge_xor(o);
+        }
+    }
     double vsh, vsx, vsy;
-    if (!sh.get(vsh) || !sx.get(vsx) || !sy.get(vsy)) return false;
+    const bool ok = sh.get(vsh) & sx.get(vsx) & sy.get(vsy);
+    if (!ok) return false;
+    if (gl) return true;
     const double N = (double)cnt;
     nh[b] = 0.5 * ((hb / 2.0) * (1.0 + sqrt(n_r / N)) + vsh / N);
     const double pref = -0.5 * (hb * hb);
@@ -1221,24 +1313,67 @@ __device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, 
     return true;
 }
 
-// fast path; redo[sp] = 1 where an exact sum is needed
-__global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int nb, sph_background B,
-                                                        double q, double rho0, double n_r, double* nh,
-                                                        double* ddx, double* ddy, int32_t* redo)
+// fast path, BG_G lanes per particle; redo[sp] = 1 where an exact sum is needed
+__global__ __launch_bounds__(256) void k_bg_smooth_walk(Grid g, NbrView nv, int nb,
+                                                        const double* __restrict__ m_s, double rho0,
+                                                        double n_r, double* nh, double* ddx,
+                                                        double* ddy, int32_t* redo)
 {
-    const int sp = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int sp = t / BG_G, gl = t % BG_G;
     if (sp >= nb) return;
-    redo[sp] = bg_smooth_row<FSum>(g, nv, sp, B, q, rho0, n_r, nh, ddx, ddy) ? 0 : 1;
+    const bool ok = bg_smooth_row<BG_G, FSum>(g, nv, sp, gl, m_s, rho0, n_r, nh, ddx, ddy);
+    if (gl == 0) redo[sp] = ok ? 0 : 1;
 }
 
-__global__ __launch_bounds__(256) void k_bg_smooth_exact(Grid g, NbrView nv, int nb, sph_background B,
-                                                         double q, double rho0, double n_r,
-                                                         double* nh, double* ddx, double* ddy,
-                                                         const int32_t* __restrict__ redo)
+// The rows the fast path could not prove: each of the three sums in a walk
+// of its own with one long accumulator (one accumulator keeps the private
+// memory per lane, and with it the launch, small).
+__global__ __launch_bounds__(256) void k_bg_smooth_exact(Grid g, NbrView nv, int nb,
+                                                         const double* __restrict__ m_s, double rho0,
+                                                         double n_r, double* nh, double* ddx,
+                                                         double* ddy, const int32_t* __restrict__ redo)
 {
     const int sp = blockIdx.x * blockDim.x + threadIdx.x;
     if (sp >= nb || !redo[sp]) return;
-    bg_smooth_row<XSum>(g, nv, sp, B, q, rho0, n_r, nh, ddx, ddy);
+    const int b = nv.perm[sp];
+    const double xb = nv.xs[sp], yb = nv.ys[sp], hb = nv.hs[sp];
+    const int lb = key_level(g, nv.keys[sp]);
+    const double fxi = kern_f<double>(SPH_XI);
+    double v[3];
+    int cnt = 0;
+    for (int which = 0; which < 3; ++which) {
+        XSum acc;
+        for_each_neighbor(g, nv, xb, yb, hb, lb, [&](int js, double dx, double dy, double r2, double hj) {
+            if (which == 0) {
+                ++cnt;
+                acc.add(hj);
+                return;
+            }
+            const double r = sqrt(r2);
+            if (r <= 0.0) return;
+            const double hij = 0.5 * (hb + hj);
+            const double wr = kern_f<double>(r / hij) / fxi;
+            const double mj = m_s[js];
+            const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+            const double t = coef * (kern_dw64(r, hij) / r);
+            acc.add(t * (which == 1 ? dx : dy));
+        });
+        acc.get(v[which]);
+    }
+    const double N = (double)cnt;
+    nh[b] = 0.5 * ((hb / 2.0) * (1.0 + sqrt(n_r / N)) + v[0] / N);
+    const double pref = -0.5 * (hb * hb);
+    double dxs = pref * v[1], dys = pref * v[2];
+    const double mag = sqrt(dxs * dxs + dys * dys);
+    const double lim = 0.25 * hb;
+    if (mag > lim) {
+        const double th = lim / mag;
+        dxs = dxs * th;
+        dys = dys * th;
+    }
+    ddx[b] = dxs;
+    ddy[b] = dys;
 }
 
 __global__ __launch_bounds__(256) void k_bg_smooth_apply(Grid g, int nb, sph_background B,
@@ -1278,10 +1413,14 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
         int rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
         if (rc) return rc;
         NbrView nv = nbr_view(c);
-        hipLaunchKernelGGL(k_bg_grade, dim3(nbk), dim3(256), 0, c->stream, c->grid, nv, nb, bg->mask,
-                           bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
+        hipLaunchKernelGGL(k_bg_pack, dim3(nbk), dim3(256), 0, c->stream, nb, nv.perm, (const double*)bg->ds,
+                           (const int64_t*)nullptr, 0.0, w.tmp_d[3], (double*)nullptr);
+        hipLaunchKernelGGL(k_bg_grade, dim3((unsigned)cdiv((int64_t)nb * BG_G, 256)), dim3(256), 0, c->stream,
+                           c->grid, nv, nb, bg->mask, bg->ds, (const double*)w.tmp_d[3], cf.cr, cf.ds_min,
+                           cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
         hipLaunchKernelGGL(k_bg_grade_exact, dim3(nbk), dim3(256), 0, c->stream, c->grid, nv, nb,
-                           bg->mask, bg->ds, cf.cr, cf.ds_min, cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
+                           bg->mask, bg->ds, (const double*)w.tmp_d[3], cf.cr, cf.ds_min, cf.ds_max,
+                           w.tmp_d[0], w.tmp_i32[0]);
         hipLaunchKernelGGL(k_bg_setds, dim3(nbk), dim3(256), 0, c->stream, nb, w.tmp_d[0], cf.rho0,
                            bg->ds, bg->mref);
         LAUNCHCHK(c, "bg_grade");
@@ -1307,12 +1446,16 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
             rc = nbr_build(c, nb, bg->x, bg->y, bg->h);
             if (rc) return rc;
             unsigned nbk2 = (unsigned)cdiv(nb, 256);
-            hipLaunchKernelGGL(k_bg_smooth_walk, dim3(nbk2), dim3(256), 0, c->stream, c->grid,
-                               nbr_view(c), nb, *bg, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
-                               w.tmp_d[1], w.tmp_d[2], w.tmp_i32[0]);
-            hipLaunchKernelGGL(k_bg_smooth_exact, dim3(nbk2), dim3(256), 0, c->stream, c->grid,
-                               nbr_view(c), nb, *bg, cf.bg_mass_q, cf.rho0, cf.n_r, w.tmp_d[0],
-                               w.tmp_d[1], w.tmp_d[2], w.tmp_i32[0]);
+            const NbrView nv2 = nbr_view(c);
+            hipLaunchKernelGGL(k_bg_pack, dim3(nbk2), dim3(256), 0, c->stream, nb, nv2.perm,
+                               (const double*)nullptr, (const int64_t*)bg->mq, cf.bg_mass_q,
+                               (double*)nullptr, w.tmp_d[3]);
+            hipLaunchKernelGGL(k_bg_smooth_walk, dim3((unsigned)cdiv((int64_t)nb * BG_G, 256)), dim3(256), 0,
+                               c->stream, c->grid, nv2, nb, (const double*)w.tmp_d[3], cf.rho0, cf.n_r,
+                               w.tmp_d[0], w.tmp_d[1], w.tmp_d[2], w.tmp_i32[0]);
+            hipLaunchKernelGGL(k_bg_smooth_exact, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nv2, nb,
+                               (const double*)w.tmp_d[3], cf.rho0, cf.n_r, w.tmp_d[0], w.tmp_d[1],
+                               w.tmp_d[2], w.tmp_i32[0]);
             hipLaunchKernelGGL(k_bg_smooth_apply, dim3(nbk2), dim3(256), 0, c->stream, c->grid, nb, *bg,
                                w.tmp_d[0], w.tmp_d[1], w.tmp_d[2]);
             LAUNCHCHK(c, "bg_smooth");
