@@ -76,6 +76,12 @@ def parse():
     ap.add_argument("--list-skin", type=float, default=None,
                     help="use this list skin for both precisions instead of timing the "
                          "candidates first (for profiled runs)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="for profiled runs: only the serving loop (saturated), printing its "
+                         "figures")
+    ap.add_argument("--bg-pass-only", action="store_true",
+                    help="for profiled runs: build the oscillating cylinder's background and "
+                         "time five background passes, printing their figures")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="for hardware-counter runs: a calibration copy of known size, then "
                          "the timed loop's first steps (FP32, --list-skin); prints nothing else")
@@ -512,6 +518,47 @@ def main():
     if args.pmc_sample:
         pmc_sample(SPH, W, torch, args.list_skin if args.list_skin is not None else 0.3,
                    args.adapt_every, parse_schedule(SPH, args.schedule) if args.schedule else None)
+        return
+    if args.serve_only:
+        from paper_2107_01276_amd import serving
+        reqs = W.serving_requests(n_req=args.serve_requests, seed=4, rate=1.0)
+        built = {}
+
+        def make(req):
+            key = (req["side"], req["seed"])
+            if key not in built:
+                st = W.tgv(req["side"], seed=req["seed"], re=req["re"])
+                cfg = SPH.config_for(st["domain"], st["params"], float(st["h"].min()),
+                                     float(st["h"].max()), precision=SPH.SPH_FP32,
+                                     mass_q=st["mass_q"], list_skin=0.0, lean=1, list_k=64)
+                built[key] = (cfg, st, SPH.timestep(cfg))
+            return built[key]
+
+        res = serving.serve([dict(r, arrival=0.0) for r in reqs], make,
+                            int(args.serve_arena_gib * (1 << 30)), steps=args.serve_steps)
+        print(json.dumps({"serve_only": True, "saturated": res}))
+        return
+    if args.bg_pass_only:
+        s = W.oscillating_cylinder()
+        bg, info = procedure_background(SPH, W, s, torch)
+        spec, d = s["spec"], s["domain"]
+        cfg = SPH.Config(lo=d.lo, hi=d.hi, periodic=d.periodic, h_lo=0.25 * spec.ds_min,
+                         h_hi=2.5 * spec.ds_min * spec.ratio, cr=spec.cr, ds_min=spec.ds_min,
+                         ds_max=spec.ds_min * spec.ratio, bg_mass_q=bg["mass_q"],
+                         mass_q=s["mass_q"])
+        bcap = int(1.2 * bg["x"].size)
+        ctx = SPH.Context(cfg, bcap)
+        B = SPH.Background.from_arrays(bg, bcap)
+        sol = s["kind"] == W.SOLID
+        S = SPH.Particles.from_arrays({k: s[k][sol] for k in ("x", "y", "h", "mq")})
+        ms = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.bg_update(B, S, 1)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        print(json.dumps({"bg_pass_only": True, "build": info, "pass_ms": ms, "n": B.n}))
         return
     s = W.channel_cylinder(seed=2)
     bg = W.channel_background(s["spec"], seed=3)
