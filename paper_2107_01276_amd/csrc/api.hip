@@ -41,14 +41,14 @@ static size_t carve(Work* w, char* base, const Grid& g, int64_t cap, int lean, i
         return p;
     };
     int64_t C = cap > 0 ? cap : 1;
-    int64_t nblk = cdiv(C, RS_TILE);
-    int64_t scan_n = (C + 1) > RS_BINS * nblk ? (C + 1) : RS_BINS * nblk;
+    const int64_t scan_n = C + 1;
     w->capacity = C;
     w->keys_a = (uint64_t*)take(8 * C);
     w->keys_b = (uint64_t*)take(8 * C);
     w->vals_a = (int32_t*)take(4 * C);
     w->vals_b = (int32_t*)take(4 * C);
-    w->hist = (uint32_t*)take(4 * RS_BINS * nblk);
+    w->os_look = (uint32_t*)take(4 * (OS_MAXPASS * OS_BINS * cdiv(C, OS_TILE) + OS_MAXPASS * OS_BINS +
+                                      OS_MAXPASS));
     w->scan_tmp = (int64_t*)take(8 * (2 * cdiv(scan_n, SCAN_TILE) + 256));
     w->tab = (int2*)take(sizeof(int2) * (g.tab_total > 0 ? g.tab_total : 1));
     w->hmax_bits = (unsigned long long*)take(8 * SPH_MAXL);

@@ -93,16 +93,6 @@ static int key_bits(const Grid* g)
 int batch_key_bits(const Grid* g) { return key_bits(g); }
 
 
-size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g)
-{
-    (void)cfg;
-    int64_t nb = cdiv(capacity > 0 ? capacity : 1, RS_TILE);
-    size_t b = 0;
-    b += (size_t)g->tab_total * sizeof(int2) + 256;
-    b += (size_t)RS_BINS * nb * sizeof(uint32_t) + 256;
-    return b;
-}
-
 // ---------------------------------------------------------------------------
 // Scans (exclusive; output has n + 1 entries, out[n] = total)
 // ---------------------------------------------------------------------------
@@ -200,6 +190,17 @@ int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n)
 // Keys
 // ---------------------------------------------------------------------------
 
+// Sort key of a particle: its level above the Hilbert index of its
+// level-0 cell.
+__device__ __forceinline__ uint64_t key_of(const Grid& g, double xi, double yi, double hi, int* lev)
+{
+    const int l = level_of(g, hi);
+    const uint32_t kx = (uint32_t)cell0(g, 0, xi);
+    const uint32_t ky = (uint32_t)cell0(g, 1, yi);
+    *lev = l;
+    return ((uint64_t)l << (2 * g.bits)) | hilbert_d(kx, ky, g.bits);
+}
+
 // Key and slot of particle i (when valid), and the block's per-level maxima
 // of h and counts; every thread of the block calls it.
 __device__ __forceinline__ void keys_body(const Grid& g, bool valid, int i,
@@ -218,10 +219,8 @@ __device__ __forceinline__ void keys_body(const Grid& g, bool valid, int i,
     __syncthreads();
     if (valid) {
         double hi = h[i];
-        int l = level_of(g, hi);
-        uint32_t kx = (uint32_t)cell0(g, 0, x[i]);
-        uint32_t ky = (uint32_t)cell0(g, 1, y[i]);
-        keys[i] = ((uint64_t)l << (2 * g.bits)) | hilbert_d(kx, ky, g.bits);
+        int l;
+        keys[i] = key_of(g, x[i], y[i], hi, &l);
         vals[i] = i;
         atomicMax(&s_h[l], (unsigned long long)__double_as_longlong(hi));
         atomicAdd(&s_c[l], 1);
@@ -233,26 +232,16 @@ __device__ __forceinline__ void keys_body(const Grid& g, bool valid, int i,
     }
 }
 
-__global__ __launch_bounds__(256) void k_keys(Grid g, int n, const double* __restrict__ x,
-                                              const double* __restrict__ y,
-                                              const double* __restrict__ h, uint64_t* keys,
-                                              int32_t* vals, unsigned long long* hmax_bits,
-                                              int32_t* lcount)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    keys_body(g, i < n, i, x, y, h, keys, vals, hmax_bits, lcount);
-}
-
 __global__ void k_zero_i32(int32_t* p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
 }
 
-// Clears what a build accumulates into: the cell-run table and the
-// per-level h maxima and counts (one launch).
+// Clears what a build accumulates into: the cell-run table, the per-level
+// h maxima and counts, and the sort's counters z[0, nz) (one launch).
 __global__ void k_zero_build(int2* tab, int64_t ntab, unsigned long long* hmax, int32_t* lcount,
-                             int nl)
+                             int nl, uint32_t* z, int64_t nz)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ntab) tab[i] = make_int2(0, 0);
@@ -260,6 +249,7 @@ __global__ void k_zero_build(int2* tab, int64_t ntab, unsigned long long* hmax, 
         hmax[i] = 0ull;
         lcount[i] = 0;
     }
+    if (i < nz) z[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,12 +276,65 @@ __device__ __forceinline__ void rs_hist_tile(const uint64_t* __restrict__ keys, 
     for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * hstride] = h[d];
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t* __restrict__ keys, int n,
-                                                        int shift, uint32_t* hist, int nblk)
+// Stable ranking of one tile's keys [base, base + tn) by their BITS-bit
+// digit at `shift`: wave w owns the contiguous keys [w 64 ITEMS, (w + 1) 64
+// ITEMS) of the tile and ranks each 64-key chunk with one ballot per digit
+// bit (the lanes with equal digits), so equal digits keep the input order.
+// On return wcnt[w][d] holds the offset of wave w's first digit-d key among
+// the tile's digit-d keys, cnt[d] (when given) the tile's count of digit d,
+// and each lane's items their key, value, digit (BINS past the end) and
+// rank within the wave's digit-d keys.
+template <int BITS, int ITEMS>
+__device__ __forceinline__ void tile_rank(const uint64_t* __restrict__ kin,
+                                          const int32_t* __restrict__ vin, int64_t base, int tn,
+                                          int shift, uint32_t (*wcnt)[1 << BITS], uint32_t* cnt,
+                                          uint64_t* kk, int32_t* vv, uint32_t* dd, uint32_t* rk)
 {
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    const int tn = (int)(n - base < RS_TILE ? n - base : RS_TILE);
-    rs_hist_tile(keys, base, tn, shift, hist + blockIdx.x, nblk);
+    constexpr int NW = RS_THREADS / 64, BINS = 1 << BITS;
+    const int lane = __lane_id(), w = threadIdx.x >> 6;
+    for (int d = threadIdx.x; d < NW * BINS; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int wbase = w * (64 * ITEMS);
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+        const int il = wbase + it * 64 + lane;
+        const bool valid = il < tn;
+        const int64_t i = base + il;
+        uint64_t k = valid ? kin[i] : 0ull;
+        uint32_t d = (uint32_t)(k >> shift) & (BINS - 1u);
+        uint64_t mask = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = __ballot(bit);
+            mask &= bit ? bal : ~bal;
+        }
+        uint32_t before = (uint32_t)__popcll(mask & lt_mask);
+        uint32_t c = (uint32_t)__popcll(mask);
+        uint32_t old = valid ? wcnt[w][d] : 0u;
+        // all lanes have read the running count before the group leader
+        // (lowest lane of its digit group) advances it
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) wcnt[w][d] = old + c;
+        __builtin_amdgcn_wave_barrier();
+        kk[it] = k;
+        vv[it] = valid ? vin[i] : 0;
+        dd[it] = valid ? d : (uint32_t)BINS;
+        rk[it] = old + before;
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < BINS; d += RS_THREADS) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            uint32_t t = wcnt[q][d];
+            wcnt[q][d] = s;
+            s += t;
+        }
+        if (cnt) cnt[d] = s;
+    }
+    __syncthreads();
 }
 
 // Scatter of one tile: keys [base, base + tn); digit d of the tile starts
@@ -305,52 +348,11 @@ __device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin
 {
     constexpr int NW = RS_THREADS / 64;
     __shared__ uint32_t wcnt[NW][RS_BINS];
-    const int lane = __lane_id(), w = threadIdx.x >> 6;
-    for (int d = threadIdx.x; d < NW * RS_BINS; d += RS_THREADS) (&wcnt[0][0])[d] = 0;
-    __syncthreads();
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int wbase = w * (64 * RS_ITEMS);
+    const int w = threadIdx.x >> 6;
     uint64_t kk[RS_ITEMS];
     int32_t vv[RS_ITEMS];
     uint32_t dd[RS_ITEMS], rk[RS_ITEMS];
-#pragma unroll
-    for (int it = 0; it < RS_ITEMS; ++it) {
-        const int il = wbase + it * 64 + lane;
-        const bool valid = il < tn;
-        const int64_t i = base + il;
-        uint64_t k = valid ? kin[i] : 0ull;
-        uint32_t d = (uint32_t)(k >> shift) & (RS_BINS - 1u);
-        uint64_t mask = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < RS_BITS; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bal = __ballot(bit);
-            mask &= bit ? bal : ~bal;
-        }
-        uint32_t before = (uint32_t)__popcll(mask & lt_mask);
-        uint32_t cnt = (uint32_t)__popcll(mask);
-        uint32_t old = valid ? wcnt[w][d] : 0u;
-        // all lanes have read the running count before the group leader
-        // (lowest lane of its digit group) advances it
-        __builtin_amdgcn_wave_barrier();
-        if (valid && before == 0) wcnt[w][d] = old + cnt;
-        __builtin_amdgcn_wave_barrier();
-        kk[it] = k;
-        vv[it] = valid ? vin[i] : 0;
-        dd[it] = valid ? d : (uint32_t)RS_BINS;
-        rk[it] = old + before;
-    }
-    __syncthreads();
-    for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) {
-        uint32_t s = 0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) {
-            uint32_t t = wcnt[q][d];
-            wcnt[q][d] = s;
-            s += t;
-        }
-    }
-    __syncthreads();
+    tile_rank<RS_BITS, RS_ITEMS>(kin, vin, base, tn, shift, wcnt, nullptr, kk, vv, dd, rk);
 #pragma unroll
     for (int it = 0; it < RS_ITEMS; ++it) {
         uint32_t d = dd[it];
@@ -362,46 +364,166 @@ __device__ __forceinline__ void rs_scatter_tile(const uint64_t* __restrict__ kin
     }
 }
 
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                           const int32_t* __restrict__ vin,
-                                                           uint64_t* __restrict__ kout,
-                                                           int32_t* __restrict__ vout, int n,
-                                                           int shift,
-                                                           const uint32_t* __restrict__ offs,
-                                                           int nblk)
+// ---------------------------------------------------------------------------
+// One-sweep LSD radix sort of a context's keys: 8-bit digits, one kernel per
+// digit.  The key kernel also counts every pass's digits over all keys, so a
+// pass knows each digit's start; within a digit, a tile's keys follow those
+// of the tiles before it.  Workgroups take tiles in order from a ticket
+// counter, rank their keys (stable), publish each digit's count and find
+// the count of that digit in the tiles before theirs by looking back: a
+// tile's word holds either its own count (OS_AGG) or the inclusive prefix
+// through it (OS_INC); the walk adds counts back to the nearest prefix,
+// OS_WIN tiles per load round.  A workgroup waits only on tiles taken before
+// its own, whose workgroups are running, so every wait ends; the wait is
+// still bounded, and a wait that runs out sets a failure flag.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t os_load(const uint32_t* p)
 {
-    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
-    const int tn = (int)(n - base < RS_TILE ? n - base : RS_TILE);
-    rs_scatter_tile(kin, vin, kout, vout, base, tn, shift, offs + blockIdx.x, nblk, 0);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void os_store(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sorts (keys, vals) of length n; the result ends in (keys_a, vals_a).
-static int radix_sort(sph_ctx* c, int n, int keybits)
+// Keys, slots and level statistics as keys_body, OS_KEYS_ITEMS particles per
+// thread, and the counts of every pass's digits into ghist[p][d].
+#define OS_KEYS_ITEMS 8
+__global__ __launch_bounds__(256) void k_keys_os(Grid g, int n, const double* __restrict__ x,
+                                                 const double* __restrict__ y,
+                                                 const double* __restrict__ h, uint64_t* keys,
+                                                 int32_t* vals, unsigned long long* hmax_bits,
+                                                 int32_t* lcount, int npass, uint32_t* ghist)
 {
-    Work& w = c->w;
-    int nblk = (int)cdiv(n, RS_TILE);
-    int npass = (keybits + RS_BITS - 1) / RS_BITS;
-    uint64_t *ka = w.keys_a, *kb = w.keys_b;
-    int32_t *va = w.vals_a, *vb = w.vals_b;
-    for (int p = 0; p < npass; ++p) {
-        int shift = RS_BITS * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, n, shift,
-                           w.hist, nblk);
-        LAUNCHCHK(c, "rs_hist");
-        int rc = scan_rec<uint32_t>(c, w.hist, w.hist, (int64_t)RS_BINS * nblk, (int64_t)RS_BINS * nblk,
-                                    (uint32_t*)w.scan_tmp);
-        if (rc) return rc;
-        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(RS_THREADS), 0, c->stream, ka, va, kb,
-                           vb, n, shift, w.hist, nblk);
-        LAUNCHCHK(c, "rs_scatter");
-        uint64_t* tk = ka; ka = kb; kb = tk;
-        int32_t* tv = va; va = vb; vb = tv;
+    __shared__ unsigned long long s_h[SPH_MAXL];
+    __shared__ int32_t s_c[SPH_MAXL];
+    __shared__ uint32_t s_g[OS_MAXPASS * OS_BINS];
+    const int t = threadIdx.x;
+    if (t < SPH_MAXL) {
+        s_h[t] = 0ull;
+        s_c[t] = 0;
     }
-    if (ka != w.keys_a) {
-        HIPCHK(c, hipMemcpyAsync(w.keys_a, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(w.vals_a, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c->stream));
+    for (int e = t; e < npass * OS_BINS; e += 256) s_g[e] = 0u;
+    __syncthreads();
+    const int64_t b0 = (int64_t)blockIdx.x * (256 * OS_KEYS_ITEMS);
+#pragma unroll
+    for (int k = 0; k < OS_KEYS_ITEMS; ++k) {
+        const int64_t i = b0 + k * 256 + t;
+        if (i < n) {
+            const double hi = h[i];
+            int l;
+            const uint64_t key = key_of(g, x[i], y[i], hi, &l);
+            keys[i] = key;
+            vals[i] = (int32_t)i;
+            atomicMax(&s_h[l], (unsigned long long)__double_as_longlong(hi));
+            atomicAdd(&s_c[l], 1);
+            for (int p = 0; p < npass; ++p)
+                atomicAdd(&s_g[p * OS_BINS + ((key >> (OS_BITS * p)) & (OS_BINS - 1u))], 1u);
+        }
     }
-    return SPH_OK;
+    __syncthreads();
+    if (t < g.nlev && s_c[t] > 0) {
+        atomicMax(&hmax_bits[t], s_h[t]);
+        atomicAdd(&lcount[t], s_c[t]);
+    }
+    for (int e = t; e < npass * OS_BINS; e += 256)
+        if (s_g[e]) atomicAdd(&ghist[e], s_g[e]);
+}
+
+// One pass: keys and values from (kin, vin) to their places in (kout, vout)
+// by the digit at bit OS_BITS * pass; ghist, look and ticket are the pass's
+// digit counts, look-back words (ntile x OS_BINS) and ticket counter.
+__global__ __launch_bounds__(RS_THREADS) void k_os_pass(const uint64_t* __restrict__ kin,
+                                                        const int32_t* __restrict__ vin,
+                                                        uint64_t* __restrict__ kout,
+                                                        int32_t* __restrict__ vout, int n, int pass,
+                                                        const uint32_t* __restrict__ ghist,
+                                                        uint32_t* look, uint32_t* ticket,
+                                                        int32_t* fail)
+{
+    static_assert(RS_THREADS == OS_BINS, "one thread per digit");
+    constexpr int NW = RS_THREADS / 64;
+    __shared__ uint32_t wcnt[NW][OS_BINS];
+    __shared__ uint32_t cnt[OS_BINS];
+    __shared__ uint32_t goff[OS_BINS];
+    __shared__ uint32_t wsum[NW];
+    __shared__ int s_tile;
+    const int t = threadIdx.x, lane = __lane_id(), w = t >> 6;
+    if (t == 0) s_tile = (int)atomicAdd(ticket, 1u);
+    // start of digit t in the output: exclusive scan of the digit counts
+    const uint32_t gc = ghist[t];
+    const uint32_t gi = wave_incl_scan<uint32_t>(gc);
+    if (lane == 63) wsum[w] = gi;
+    __syncthreads();
+    uint32_t gb = gi - gc;
+    for (int q = 0; q < w; ++q) gb += wsum[q];
+    const int tile = s_tile;
+    const int64_t base = (int64_t)tile * OS_TILE;
+    const int tn = (int)(n - base < OS_TILE ? n - base : OS_TILE);
+    uint64_t kk[OS_ITEMS];
+    int32_t vv[OS_ITEMS];
+    uint32_t dd[OS_ITEMS], rk[OS_ITEMS];
+    tile_rank<OS_BITS, OS_ITEMS>(kin, vin, base, tn, OS_BITS * pass, wcnt, cnt, kk, vv, dd, rk);
+    {
+        // thread t: digit t of this tile
+        const uint32_t own = cnt[t];
+        uint32_t* colw = look + t;  // word of tile q: colw[q * OS_BINS]
+        uint32_t excl = 0;
+        if (tile == 0) {
+            os_store(colw, OS_INC | own);
+        } else {
+            os_store(colw + (int64_t)tile * OS_BINS, OS_AGG | own);
+            int p = tile - 1, spin = 0;
+            for (;;) {
+                uint32_t v[OS_WIN];
+#pragma unroll
+                for (int q = 0; q < OS_WIN; ++q)
+                    v[q] = p - q >= 0 ? os_load(colw + (int64_t)(p - q) * OS_BINS) : OS_INC;
+                int q = 0;
+                bool done = false;
+                for (; q < OS_WIN; ++q) {
+                    if (!(v[q] & (OS_AGG | OS_INC))) break;  // not published yet
+                    excl += v[q] & OS_VAL;
+                    if (v[q] & OS_INC) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (done) break;
+                p -= q;
+                if (q < OS_WIN) {
+                    if (++spin > OS_SPIN) {
+                        atomicOr(fail, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            os_store(colw + (int64_t)tile * OS_BINS, OS_INC | (excl + own));
+        }
+        goff[t] = gb + excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < OS_ITEMS; ++it) {
+        const uint32_t d = dd[it];
+        if (d < (uint32_t)OS_BINS) {
+            const int64_t pos = (int64_t)goff[d] + wcnt[w][d] + rk[it];
+            kout[pos] = kk[it];
+            vout[pos] = vv[it];
+        }
+    }
+}
+
+// Words the one-sweep sort of n keys of keybits bits clears before it runs
+// (look-back words, digit counts, tickets), from w.os_look on.
+static int64_t os_words(int n, int keybits, int* npass, int* ntile)
+{
+    *npass = (keybits + OS_BITS - 1) / OS_BITS;
+    if (*npass < 1) *npass = 1;
+    *ntile = (int)cdiv(n > 0 ? n : 1, OS_TILE);
+    return (int64_t)*npass * (*ntile) * OS_BINS;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,19 +592,44 @@ int nbr_build(sph_ctx* c, int n, const double* x, const double* y, const double*
     Work& w = c->w;
     const Grid& g = c->grid;
     c->list_valid = 0;  // a new sorted order invalidates any reusable list
+    if (n >= (1 << 30)) {
+        set_err(c, "%d particles: the neighbour sort takes fewer than 2^30", n);
+        return SPH_E_INVAL;
+    }
     prof_begin(c, SPH_PROF_BUILD);
+    int npass = 1, ntile = 1;
+    const int64_t nlook = n > 0 ? os_words(n, key_bits(&g), &npass, &ntile) : 0;
+    if (npass > OS_MAXPASS) {
+        set_err(c, "sort keys of %d bits exceed %d", key_bits(&g), OS_MAXPASS * OS_BITS);
+        return SPH_E_INVAL;
+    }
+    // look-back words, then the digit counts and tickets of every pass
+    uint32_t* ghist = w.os_look + nlook;
+    uint32_t* ticket = ghist + OS_MAXPASS * OS_BINS;
+    const int64_t nclr = n > 0 ? nlook + OS_MAXPASS * OS_BINS + OS_MAXPASS : 0;
     {
-        const int64_t nz = g.tab_total > SPH_MAXL ? g.tab_total : (int64_t)SPH_MAXL;
+        int64_t nz = g.tab_total > SPH_MAXL ? g.tab_total : (int64_t)SPH_MAXL;
+        if (nclr > nz) nz = nclr;
         hipLaunchKernelGGL(k_zero_build, dim3((unsigned)cdiv(nz, 256)), dim3(256), 0, c->stream, w.tab,
-                           g.tab_total, w.hmax_bits, w.lcount, (int)SPH_MAXL);
+                           g.tab_total, w.hmax_bits, w.lcount, (int)SPH_MAXL, w.os_look, nclr);
         LAUNCHCHK(c, "zero");
     }
     if (n > 0) {
-        hipLaunchKernelGGL(k_keys, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n, x, y,
-                           h, w.keys_a, w.vals_a, w.hmax_bits, w.lcount);
+        // the passes alternate between the two buffers and end in keys_a
+        uint64_t *ka = (npass & 1) ? w.keys_b : w.keys_a, *kb = (npass & 1) ? w.keys_a : w.keys_b;
+        int32_t *va = (npass & 1) ? w.vals_b : w.vals_a, *vb = (npass & 1) ? w.vals_a : w.vals_b;
+        hipLaunchKernelGGL(k_keys_os, dim3((unsigned)cdiv(n, 256 * OS_KEYS_ITEMS)), dim3(256), 0, c->stream,
+                           g, n, x, y, h, ka, va, w.hmax_bits, w.lcount, npass, ghist);
         LAUNCHCHK(c, "keys");
-        int rc = radix_sort(c, n, key_bits(&g));
-        if (rc) return rc;
+        for (int p = 0; p < npass; ++p) {
+            hipLaunchKernelGGL(k_os_pass, dim3((unsigned)ntile), dim3(RS_THREADS), 0, c->stream,
+                               (const uint64_t*)ka, (const int32_t*)va, kb, vb, n, p,
+                               (const uint32_t*)(ghist + p * OS_BINS), w.os_look + (int64_t)p * ntile * OS_BINS,
+                               ticket + p, w.status + SPH_STATUS_SORT);
+            LAUNCHCHK(c, "sort");
+            uint64_t* tk = ka; ka = kb; kb = tk;
+            int32_t* tv = va; va = vb; vb = tv;
+        }
         hipLaunchKernelGGL(k_tables, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, c->stream, g, n,
                            w.keys_a, (const int32_t*)w.vals_a, x, y, h, w.xs, w.ys, w.hs, w.xyh,
                            w.tab);
@@ -757,10 +904,14 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
     int rc = scan_exclusive_i64(c, w.cnt64, row_ptr, n);
     if (rc) return rc;
     int64_t tot = 0;
-    int32_t st[4] = {0, 0, 0, 0};
+    int32_t st[SPH_STATUS_SORT + 1] = {0};
     const Readback rb[2] = {{&tot, row_ptr + n, 8}, {st, w.status, (int)sizeof(st)}};
     rc = readback(c, rb, n > 0 ? 2 : 1);
     if (rc) return rc;
+    if (st[SPH_STATUS_SORT]) {
+        set_err(c, "neighbour sort: a look-back wait ran out");
+        return SPH_E_DEVICE;
+    }
     *nnz = tot;
     if (tot > cap) {
         set_err(c, "neighbour list needs %lld entries, capacity %lld", (long long)tot, (long long)cap);
@@ -868,7 +1019,7 @@ int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const 
     const int64_t nl = (int64_t)nsim * SPH_MAXL;
     const int64_t nz = L.tab_n > nl ? L.tab_n : nl;
     hipLaunchKernelGGL(k_zero_build, dim3((unsigned)cdiv(nz, 256)), dim3(256), 0, st, b.tab, L.tab_n,
-                       b.hmax, b.lcount, (int)nl);
+                       b.hmax, b.lcount, (int)nl, (uint32_t*)nullptr, (int64_t)0);
     hipLaunchKernelGGL(k_keys_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B, x, y, h,
                        b.keys_a, b.vals_a, b.hmax, b.lcount);
     hipError_t e = hipGetLastError();

@@ -95,7 +95,7 @@ struct Batch {
 struct Work {
     uint64_t *keys_a, *keys_b;
     int32_t *vals_a, *vals_b;
-    uint32_t* hist;        // radix digit counts
+    uint32_t* os_look;     // sort look-back words, digit counts, tickets
     int64_t* scan_tmp;     // block sums for scans
     int2* tab;
     unsigned long long* hmax_bits;
@@ -223,7 +223,6 @@ int nbr_export_csr(sph_ctx* c, int n, int64_t* row_ptr, int32_t* col, int64_t ca
                    double sf = 1.0);
 int scan_exclusive_i64(sph_ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void grid_setup(const sph_config* cfg, Grid* g);
-size_t nbr_workspace_bytes(const sph_config* cfg, int64_t capacity, const Grid* g);
 
 // batched step (nbr.hip, rates.hip): global arrays of a batch
 struct BatchBufs {
@@ -326,12 +325,30 @@ void prof_end(sph_ctx* c, int slot);
 // Radix-sort tiles (keys per workgroup) and scan tiles; the workspace carve
 // sizes the digit histograms and the scan block sums from them.
 #define RS_THREADS 256
+#ifndef RS_ITEMS
 #define RS_ITEMS 8
+#endif
 #define RS_TILE (RS_THREADS * RS_ITEMS)
 #ifndef RS_BITS
 #define RS_BITS 12           // digit width of the LSD radix sort
 #endif
 #define RS_BINS (1 << RS_BITS)
+// One-sweep sort of a context's keys: digit width, keys per tile, look-back
+// window, spin bound, look-back word flags and value mask; status word that
+// records a look-back wait that ran out.
+#define OS_BITS 8
+#define OS_BINS (1 << OS_BITS)
+#ifndef OS_ITEMS
+#define OS_ITEMS 8
+#endif
+#define OS_TILE (RS_THREADS * OS_ITEMS)
+#define OS_MAXPASS 8
+#define OS_WIN 16
+#define OS_SPIN (1 << 16)
+#define OS_AGG (1u << 30)
+#define OS_INC (2u << 30)
+#define OS_VAL ((1u << 30) - 1u)
+#define SPH_STATUS_SORT 8
 #define SCAN_T 256
 #define SCAN_E 8
 #define SCAN_TILE (SCAN_T * SCAN_E)
