@@ -21,6 +21,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "sph_device.h"
 
 int scan_exclusive_i32(sph_ctx* c, const int32_t* in, int32_t* out, int64_t n);
@@ -460,17 +462,62 @@ __global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32
     if (gl == 0) rcnt[i] = cnt;
 }
 
+// Lanes per row of the shift and h-update sweeps (1, 2 or 4) and entries
+// each lane loads ahead.  The lanes of a row compute the terms of every G-th
+// entry and the group adds them in column order (a DPP broadcast per term),
+// so each sum is the one sequential evaluation gives; the wider group keeps
+// more rows' gathers in flight.
+#ifndef SHIFT_G
+#define SHIFT_G 2
+#endif
+#ifndef SHIFT_U
+#define SHIFT_U 2
+#endif
+
+// Value of lane Q of the group (the lane itself when G = 1).
+template <int G, int Q>
+__device__ __forceinline__ double grp_val(double v)
+{
+    if constexpr (G == 1) return v;
+    else return grp_bcast<G, Q>(v);
+}
+template <int G, int Q>
+__device__ __forceinline__ int grp_val_i(int v)
+{
+    if constexpr (G == 1) return v;
+    else return grp_bcast_i<G, Q>(v);
+}
+// f(integral_constant<int, Q>) for Q = 0 .. G-1, in that order.
+template <int G, int Q = 0, class F>
+__device__ __forceinline__ void grp_each(F&& f)
+{
+    if constexpr (Q < G) {
+        f(std::integral_constant<int, Q>{});
+        grp_each<G, Q + 1>(f);
+    }
+}
+
+// One entry's shift and Taylor-correction terms, each formed as the
+// sequential loop forms it before adding.
+struct ShiftTerms {
+    double sx, sy, gux, guy, gvx, gvy, gpx, gpy;
+    int ok;
+};
+
 // EXACT: rows hold exactly the neighbours (from k_shift_filter), counts in
 // rcnt; otherwise rows may be a superset, re-tested entry by entry.
-// One fluid row of the shift and Taylor correction; returns |dr_i| / h_i.
-template <bool EXACT>
+// One fluid row of the shift and Taylor correction, lane gl of its group of
+// G (every lane of the group calls it and gets the same sums); returns
+// |dr_i| / h_i.  Lane 0 of the group writes the row's results.
+template <bool EXACT, int G, int U>
 __device__ __forceinline__ double shift_row(const Grid& g, const double4* __restrict__ A,
                                             const double4* __restrict__ B,
                                             const int64_t* __restrict__ rp,
                                             const int32_t* __restrict__ col,
                                             const int32_t* __restrict__ rcnt, double rho0, int i,
-                                            double4 ai, double4 bi, double* ddx_o, double* ddy_o,
-                                            double* nu_o, double* nv_o, double* np_o)
+                                            int gl, double4 ai, double4 bi, double* ddx_o,
+                                            double* ddy_o, double* nu_o, double* nv_o,
+                                            double* np_o)
 {
     const double ui = bi.x, vi = bi.y, pi = bi.z;
     // shift sums and the Taylor gradients share one sweep over the row; every
@@ -479,18 +526,20 @@ __device__ __forceinline__ double shift_row(const Grid& g, const double4* __rest
     double sx = 0.0, sy = 0.0;
     double gux = 0, guy = 0, gvx = 0, gvy = 0, gpx = 0, gpy = 0;
     const double xi = ai.x, yi = ai.y, hi = ai.z;
-    auto term = [&](const double4& aj, const double4& bj) __attribute__((always_inline)) {
+    auto term = [&](const double4& aj, const double4& bj, bool valid) __attribute__((always_inline)) {
+        ShiftTerms o{0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (!valid) return o;
         const double dx = mi_axis(g, 0, xi - aj.x);
         const double dy = mi_axis(g, 1, yi - aj.y);
         const double r2 = dx * dx + dy * dy;
         const double hj = aj.z;
         if constexpr (!EXACT) {
             const double RR = 3.0 * (hi > hj ? hi : hj);
-            if (!(r2 < RR * RR)) return;  // the row may be a superset of N(i)
+            if (!(r2 < RR * RR)) return o;  // the row may be a superset of N(i)
         }
         const double r = sqrt(r2);
         if constexpr (!EXACT) {
-            if (r <= 0.0) return;
+            if (r <= 0.0) return o;
         }
         const double mj = aj.w;
         // shifting term at h_ij
@@ -498,37 +547,56 @@ __device__ __forceinline__ double shift_row(const Grid& g, const double4* __rest
         const double wr = kern_f<double>(r / hij) / fxi;
         const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
         const double tt = coef * (kern_dw64(r, hij) / r);
-        sx = sx + tt * dx;
-        sy = sy + tt * dy;
+        o.sx = tt * dx;
+        o.sy = tt * dy;
         // gradients at h_i
         const double f = kern_dw64(r, hi) / r;
         const double wx = f * dx, wy = f * dy;
         const double Vj = mj / bj.w;
         const double du = bj.x - ui, dv = bj.y - vi, dp = bj.z - pi;
-        gux += Vj * du * wx; guy += Vj * du * wy;
-        gvx += Vj * dv * wx; gvy += Vj * dv * wy;
-        gpx += Vj * dp * wx; gpy += Vj * dp * wy;
+        o.gux = Vj * du * wx; o.guy = Vj * du * wy;
+        o.gvx = Vj * dv * wx; o.gvy = Vj * dv * wy;
+        o.gpx = Vj * dp * wx; o.gpy = Vj * dp * wy;
+        o.ok = 1;
+        return o;
     };
-    // four entries' loads are issued before their terms, which are then
-    // added one by one in column order
-    int64_t k = rp[i];
-    const int64_t e = EXACT ? rp[i] + rcnt[i] : rp[i + 1];
-    for (; k + 4 <= e; k += 4) {
-        int j[4];
-        double4 aj[4], bj[4];
+    auto add = [&](const ShiftTerms& o) __attribute__((always_inline)) {
+        sx = sx + o.sx; sy = sy + o.sy;
+        gux = gux + o.gux; guy = guy + o.guy;
+        gvx = gvx + o.gvx; gvy = gvy + o.gvy;
+        gpx = gpx + o.gpx; gpy = gpy + o.gpy;
+    };
+    // lane gl takes entries base + u G + gl; U entries' loads are issued
+    // before their terms, which are then added one by one in column order
+    const int64_t b0 = rp[i];
+    const int64_t e = EXACT ? b0 + rcnt[i] : rp[i + 1];
+    for (int64_t base = b0; base < e; base += G * U) {
+        int j[U];
+        double4 aj[U], bj[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) j[u] = col[k + u];
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = base + u * G + gl;
+            j[u] = k < e ? col[k] : i;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < U; ++u) {
             aj[u] = A[j[u]];
             bj[u] = B[j[u]];
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) term(aj[u], bj[u]);
-    }
-    for (; k < e; ++k) {
-        const int j = col[k];
-        term(A[j], B[j]);
+        for (int u = 0; u < U; ++u) {
+            const ShiftTerms o = term(aj[u], bj[u], base + u * G + gl < e);
+            grp_each<G>([&](auto q) __attribute__((always_inline)) {
+                constexpr int Q = decltype(q)::value;
+                ShiftTerms b;
+                b.ok = grp_val_i<G, Q>(o.ok);
+                b.sx = grp_val<G, Q>(o.sx); b.sy = grp_val<G, Q>(o.sy);
+                b.gux = grp_val<G, Q>(o.gux); b.guy = grp_val<G, Q>(o.guy);
+                b.gvx = grp_val<G, Q>(o.gvx); b.gvy = grp_val<G, Q>(o.gvy);
+                b.gpx = grp_val<G, Q>(o.gpx); b.gpy = grp_val<G, Q>(o.gpy);
+                if (b.ok) add(b);
+            });
+        }
     }
     const double pref = -0.5 * (hi * hi);
     double ddx = pref * sx, ddy = pref * sy;
@@ -539,11 +607,13 @@ __device__ __forceinline__ double shift_row(const Grid& g, const double4* __rest
         ddx = ddx * th;
         ddy = ddy * th;
     }
-    ddx_o[i] = ddx;
-    ddy_o[i] = ddy;
-    nu_o[i] = ui + (gux * ddx + guy * ddy);
-    nv_o[i] = vi + (gvx * ddx + gvy * ddy);
-    np_o[i] = pi + (gpx * ddx + gpy * ddy);
+    if (gl == 0) {
+        ddx_o[i] = ddx;
+        ddy_o[i] = ddy;
+        nu_o[i] = ui + (gux * ddx + guy * ddy);
+        nv_o[i] = vi + (gvx * ddx + gvy * ddy);
+        np_o[i] = pi + (gpx * ddx + gpy * ddy);
+    }
     return sqrt(ddx * ddx + ddy * ddy) / hi;
 }
 
@@ -561,18 +631,21 @@ __global__ __launch_bounds__(256) void k_shift_taylor(Grid g, int n, const int32
 {
     // rows are taken in `order` (a spatial order of the slots) when given,
     // so that a wave's neighbours share cache lines
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = tt / SHIFT_G, gl = tt % SHIFT_G;
     double rel = 0.0;  // |dr_i| / h_i
     if (t < n) {
         const int i = order ? order[t] : t;
         const double4 ai = A[i], bi = B[i];
         const double ui = bi.x, vi = bi.y, pi = bi.z;
         if (kind && kind[i] != SPH_FLUID) {
-            ddx_o[i] = 0.0; ddy_o[i] = 0.0;
-            nu_o[i] = ui; nv_o[i] = vi; np_o[i] = pi;
+            if (gl == 0) {
+                ddx_o[i] = 0.0; ddy_o[i] = 0.0;
+                nu_o[i] = ui; nv_o[i] = vi; np_o[i] = pi;
+            }
         } else {
-            rel = shift_row<EXACT>(g, A, B, rp, col, rcnt, rho0, i, ai, bi, ddx_o, ddy_o, nu_o,
-                                   nv_o, np_o);
+            rel = shift_row<EXACT, SHIFT_G, SHIFT_U>(g, A, B, rp, col, rcnt, rho0, i, gl, ai, bi,
+                                                     ddx_o, ddy_o, nu_o, nv_o, np_o);
         }
     }
     // dmax (when given) receives the largest |dr_i| / h_i of the launch:
@@ -602,6 +675,7 @@ __global__ __launch_bounds__(256) void k_shift_apply(Grid g, int n, FluidState s
 
 // h = C sqrt(m_bar / rho) with m_bar the mean mass over N(i), self
 // included; the row may be a superset of N(i), filtered by the predicate.
+// SHIFT_G lanes per row, the masses added in column order as in the shift.
 __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* __restrict__ rp,
                                                  const int32_t* __restrict__ col,
                                                  const double4* __restrict__ A,
@@ -609,35 +683,44 @@ __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* _
                                                  const int32_t* __restrict__ kind, double hdx,
                                                  double* nh, const int32_t* __restrict__ order)
 {
-    const int t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int G = SHIFT_G, U = SHIFT_U;
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int t = tt / G, gl = tt % G;
     if (t >= n) return;
     const int i = order ? order[t] : t;
     const double4 ai = A[i];
     if (kind && kind[i] != SPH_FLUID) {
-        nh[i] = ai.z;
+        if (gl == 0) nh[i] = ai.z;
         return;
     }
     const double xi = ai.x, yi = ai.y, hi = ai.z;
     double sm = 0.0;
     int64_t cnt = 0;
-    auto term = [&](const double4& aj) __attribute__((always_inline)) {
-        const double dx = mi_axis(g, 0, xi - aj.x);
-        const double dy = mi_axis(g, 1, yi - aj.y);
-        const double RR = 3.0 * (hi > aj.z ? hi : aj.z);
-        if (!(dx * dx + dy * dy < RR * RR)) return;
-        sm += aj.w;
-        ++cnt;
-    };
-    int64_t k = rp[i];
     const int64_t e = rp[i + 1];
-    for (; k + 4 <= e; k += 4) {
-        double4 aj[4];
+    for (int64_t base = rp[i]; base < e; base += G * U) {
+        double4 aj[U];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) aj[u] = A[col[k + u]];
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = base + u * G + gl;
+            aj[u] = A[k < e ? col[k] : i];
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) term(aj[u]);
+        for (int u = 0; u < U; ++u) {
+            const double dx = mi_axis(g, 0, xi - aj[u].x);
+            const double dy = mi_axis(g, 1, yi - aj[u].y);
+            const double RR = 3.0 * (hi > aj[u].z ? hi : aj[u].z);
+            const int ok = base + u * G + gl < e && dx * dx + dy * dy < RR * RR;
+            grp_each<G>([&](auto q) __attribute__((always_inline)) {
+                constexpr int Q = decltype(q)::value;
+                const double m = grp_val<G, Q>(aj[u].w);
+                if (grp_val_i<G, Q>(ok)) {
+                    sm += m;
+                    ++cnt;
+                }
+            });
+        }
     }
-    for (; k < e; ++k) term(A[col[k]]);
+    if (gl) return;
     const double mbar = sm / (double)cnt;
     nh[i] = hdx * sqrt(mbar / rho[i]);
 }
@@ -831,7 +914,8 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         }
         const bool measure = super && allow >= 0.0;
         if (measure) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->stream, dmax);
-        unsigned nb = (unsigned)cdiv(n, 256);
+        const unsigned nb = (unsigned)cdiv(n, 256);
+        const unsigned nbg = (unsigned)cdiv((int64_t)n * SHIFT_G, 256);
         // packed records in the rate passes' buffers (free during adaptation);
         // rows in the sorted order of the last build (slots unchanged since)
         double4 *pA = w.pa, *pB = (double4*)w.pf;
@@ -840,13 +924,13 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             hipLaunchKernelGGL(k_shift_filter, dim3((unsigned)cdiv((int64_t)n * FG, 256)), dim3(256), 0,
                                c->stream, c->grid, n, (const int32_t*)s.kind, (const double4*)pA,
                                w.rp_tmp, w.col_tmp, w.nl_idx, w.cnt_ex, (const int32_t*)w.vals_a);
-            hipLaunchKernelGGL(k_shift_taylor<true>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
+            hipLaunchKernelGGL(k_shift_taylor<true>, dim3(nbg), dim3(256), 0, c->stream, c->grid, n,
                                (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
                                w.nl_idx, (const int32_t*)w.cnt_ex, cf.rho0, w.tmp_d[0], w.tmp_d[1],
                                w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a,
                                measure ? dmax : nullptr);
         } else {
-            hipLaunchKernelGGL(k_shift_taylor<false>, dim3(nb), dim3(256), 0, c->stream, c->grid, n,
+            hipLaunchKernelGGL(k_shift_taylor<false>, dim3(nbg), dim3(256), 0, c->stream, c->grid, n,
                                (const int32_t*)s.kind, (const double4*)pA, (const double4*)pB, w.rp_tmp,
                                w.col_tmp, (const int32_t*)nullptr, cf.rho0, w.tmp_d[0], w.tmp_d[1],
                                w.tmp_d[2], w.tmp_d[3], w.tmp_d[4], (const int32_t*)w.vals_a,
@@ -878,7 +962,8 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         unsigned nb = (unsigned)cdiv(n, 256);
         hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, w.pa,
                            (double4*)w.pf);
-        hipLaunchKernelGGL(k_hupdate, dim3(nb), dim3(256), 0, c->stream, c->grid, n, w.rp_tmp, w.col_tmp,
+        hipLaunchKernelGGL(k_hupdate, dim3((unsigned)cdiv((int64_t)n * SHIFT_G, 256)), dim3(256), 0,
+                           c->stream, c->grid, n, w.rp_tmp, w.col_tmp,
                            (const double4*)w.pa, (const double*)ps->rho, (const int32_t*)ps->kind,
                            cf.hdx, w.tmp_d[0], (const int32_t*)w.vals_a);
         hipLaunchKernelGGL(k_copy_f64, dim3(nb), dim3(256), 0, c->stream, n, w.tmp_d[0], ps->h);

@@ -494,6 +494,26 @@ __device__ __forceinline__ int group_rank(bool pass, int gl, int* total)
     return __popc(gm & ((1u << gl) - 1u));
 }
 
+// Lane Q of this lane's group of G (G = 2 or 4 adjacent lanes, inside one
+// quad), through a DPP quad permutation: one VALU move per dword, no LDS.
+// Every lane of the quad must be active or inactive together.
+template <int G, int Q>
+__device__ __forceinline__ int grp_bcast_i(int v)
+{
+    static_assert((G == 2 || G == 4) && Q >= 0 && Q < G, "groups of 2 or 4 lanes");
+    constexpr int ctrl = G == 4 ? (Q | (Q << 2) | (Q << 4) | (Q << 6))
+                                : (Q | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6));
+    return __builtin_amdgcn_mov_dpp(v, ctrl, 0xF, 0xF, true);
+}
+template <int G, int Q>
+__device__ __forceinline__ double grp_bcast(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = grp_bcast_i<G, Q>((int)b);
+    const int hi = grp_bcast_i<G, Q>((int)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // A guarded kernel stops when a kernel enqueued before it has tripped.
 __device__ __forceinline__ bool guard_stop(const Guard& gd) { return gd.trip && *gd.trip < gd.seq; }
 __device__ __forceinline__ void guard_trip(const Guard& gd)
