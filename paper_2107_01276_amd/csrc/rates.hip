@@ -685,15 +685,26 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
     // the lanes of the group take every G-th entry of the row
     if (ecnt <= ex.K) {
         // the exact neighbours pass A found (self excluded), UN per lane
-        // loaded at a time
+        // loaded at a time; the next UN indices are read before this
+        // chunk's terms, so their latency overlaps the gathers and the math
         int k = gl;
+        int jn[UN];
+        if (k + (UN - 1) * G < ecnt) {
+#pragma unroll
+            for (int u = 0; u < UN; ++u) jn[u] = ex.idx[(int64_t)(k + G * u) * ex.stride + s];
+        }
         for (; k + (UN - 1) * G < ecnt; k += UN * G) {
             int j[UN];
             double4 a[UN];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) j[u] = ex.idx[(int64_t)(k + G * u) * ex.stride + s];
+            for (int u = 0; u < UN; ++u) j[u] = jn[u];
 #pragma unroll
             for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
+            if (k + UN * G + (UN - 1) * G < ecnt) {
+#pragma unroll
+                for (int u = 0; u < UN; ++u)
+                    jn[u] = ex.idx[(int64_t)(k + UN * G + G * u) * ex.stride + s];
+            }
 #pragma unroll
             for (int u = 0; u < UN; ++u) {
                 const double dx = mi_axis(g, 0, xi - a[u].x);
