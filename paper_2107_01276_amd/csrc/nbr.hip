@@ -389,7 +389,9 @@ __device__ __forceinline__ void os_store(uint32_t* p, uint32_t v)
 
 // Keys, slots and level statistics as keys_body, OS_KEYS_ITEMS particles per
 // thread, and the counts of every pass's digits into ghist[p][d].
+#ifndef OS_KEYS_ITEMS
 #define OS_KEYS_ITEMS 8
+#endif
 __global__ __launch_bounds__(256) void k_keys_os(Grid g, int n, const double* __restrict__ x,
                                                  const double* __restrict__ y,
                                                  const double* __restrict__ h, uint64_t* keys,

@@ -64,6 +64,38 @@ def test_neighbors_edge_cases():
     assert e.value.code == P.SPH_E_CAPACITY
 
 
+# Particle counts around the neighbour sort's tile of 2,048 keys (one
+# workgroup per tile and digit pass): below, at and just past a tile, and a
+# ragged count of several tiles.
+@pytest.mark.parametrize("n", [1, 2047, 2048, 2049, 6145])
+def test_neighbors_sort_tile_counts(n):
+    P = lib()
+    s = W.random_varh(n, seed=300 + n % 97, h_lo=0.006, ratio=4)
+    print(f"[neighbors] tile counts n={n}", flush=True)
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    rp, col = csr_np(*ctx.build_neighbors(particles(P, s)))
+    orp, ocol = oracle.neighbors(odom(s["domain"]), s["x"], s["y"], s["h"])
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+
+
+def test_neighbors_sort_skewed_digits():
+    """Most keys in a few digit buckets: 11,000 of 12,000 particles packed in
+    a square of side 0.05 (one level, a handful of level-0 cells, so every
+    sort pass sees long runs of equal digits across several tiles), the rest
+    with larger h in a band beyond the reach of the square."""
+    P = lib()
+    rng = np.random.default_rng(311)
+    nd, ns = 11000, 1000
+    x = np.concatenate([0.4 + 0.05 * rng.random(nd), 0.7 + 0.3 * rng.random(ns)])
+    y = np.concatenate([0.6 + 0.05 * rng.random(nd), rng.random(ns)])
+    h = np.concatenate([np.full(nd, 0.0006), 0.02 * np.exp(rng.uniform(0, 1, ns))])
+    s = {"x": x, "y": y, "h": h, "domain": W.Domain((0.0, 0.0), (1.0, 1.0), (True, True))}
+    ctx = ctx_for(P, s, P.SPH_FP64)
+    rp, col = csr_np(*ctx.build_neighbors(particles(P, s)))
+    orp, ocol = oracle.neighbors(odom(s["domain"]), s["x"], s["y"], s["h"])
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+
+
 def _rates_case(name):
     if name == "tgv":
         s = W.tgv(50, seed=1)
