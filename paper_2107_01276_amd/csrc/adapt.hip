@@ -269,6 +269,10 @@ __global__ __launch_bounds__(256) void k_merge_pack(int n, const int32_t* __rest
     int js = blockIdx.x * blockDim.x + threadIdx.x;
     if (js >= n) return;
     const int j = perm[js];
+    if (j < 0) {  // merged away since the build
+        rec[js] = MergeRec{-1.0, 0};
+        return;
+    }
     const bool fl = !s.kind || s.kind[j] == SPH_FLUID;
     MergeRec r;
     r.mm = fl ? mmax_f * s.mref[j] : -1.0;
@@ -276,16 +280,23 @@ __global__ __launch_bounds__(256) void k_merge_pack(int n, const int32_t* __rest
     rec[js] = r;
 }
 
+// Closest allowed partner of every sorted particle (or, when `affected` is
+// given, of the affected ones only); the walk pads each level's radius by
+// `pad` (particles moved since the build).
 __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n, FluidState s,
                                                        double q, double mmax_f,
                                                        const MergeRec* __restrict__ rec,
-                                                       int32_t* closest)
+                                                       int32_t* closest,
+                                                       const int32_t* __restrict__ affected,
+                                                       const unsigned long long* __restrict__ pad)
 {
     const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int sp = tt / MG, gl = tt % MG;
     if (sp >= n) return;
     const int i = nv.perm[sp];
-    const double xi = nv.xs[sp], yi = nv.ys[sp], hi = nv.hs[sp];
+    if (i < 0 || (affected && !affected[i])) return;
+    const double4 ai = nv.xyh[sp];  // the current position and h
+    const double xi = ai.x, yi = ai.y, hi = ai.z;
     const int li = key_level(g, nv.keys[sp]);
     const int64_t mqi = s.mq[i];
     const double mi = (double)mqi * q;
@@ -315,7 +326,7 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
                 best = j;
                 br = r2;
             }
-        }, 0.34);
+        }, 0.34, pad);
     }
     // the group's closest (ties to the lower slot), independent of order
 #pragma unroll
@@ -382,6 +393,102 @@ __global__ __launch_bounds__(256) void k_merge_apply(Grid g, int n, FluidState s
     d.mq[t] = mqm;
 }
 
+// Merge iterations after the first reuse the first iteration's neighbour
+// structure.  Only merged pairs change: the slot that absorbed its partner
+// moves to the merged position and takes the merged h, the other slot goes.
+// The sorted records are updated in place (slots renumbered by the
+// compaction, removed ones marked -1, a merged particle's record moved), and
+// each level's search radius grows by the largest distance a particle filed
+// in it has moved since the build.  A particle keeps its last closest
+// partner unless it merged, its partner merged or went, or a merged particle
+// now lies within its merge reach; only those search again.  The argmin and
+// its tie order (the lower slot; the compaction keeps slot order) are those
+// of a search from scratch.
+
+// Sorted position js: the slot after the compaction, and for a particle that
+// absorbed its partner the moved record, the level's pad and h maximum, and
+// an entry in the list of merged particles.
+__global__ __launch_bounds__(256) void k_merge_remap_sorted(Grid g, int nsorted, int32_t* perm,
+                                                            const uint64_t* __restrict__ keys,
+                                                            const double* __restrict__ xs,
+                                                            const double* __restrict__ ys,
+                                                            double4* xyh, unsigned long long* hmax,
+                                                            unsigned long long* pad, FluidState s,
+                                                            const int32_t* __restrict__ keep,
+                                                            const int32_t* __restrict__ rank,
+                                                            const int32_t* __restrict__ closest,
+                                                            int32_t* mlist, int32_t* mcount)
+{
+    const int js = blockIdx.x * blockDim.x + threadIdx.x;
+    if (js >= nsorted) return;
+    const int i = perm[js];
+    if (i < 0) return;
+    if (!keep[i]) {
+        perm[js] = -1;
+        return;
+    }
+    const int t = rank[i];
+    perm[js] = t;
+    const int j = closest[i];
+    if (!(j >= 0 && closest[j] == i)) return;  // not merged
+    const double x = s.x[t], y = s.y[t], h = s.h[t];
+    xyh[js] = make_double4(x, y, h, 0.0);
+    // distance from the position the particle was filed at (the build's)
+    const double dx = mi_axis(g, 0, x - xs[js]), dy = mi_axis(g, 1, y - ys[js]);
+    const double d = sqrt(dx * dx + dy * dy);
+    const int l = key_level(g, keys[js]);
+    atomicMax(&pad[l], (unsigned long long)__double_as_longlong(d));
+    atomicMax(&hmax[l], (unsigned long long)__double_as_longlong(h));
+    mlist[atomicAdd(mcount, 1)] = js;
+}
+
+// Old slot i (kept): its new slot's last closest partner, renumbered, or the
+// mark that it searches again (it merged, or its partner merged or went).
+__global__ __launch_bounds__(256) void k_merge_remap_slots(int nprev, const int32_t* __restrict__ keep,
+                                                           const int32_t* __restrict__ rank,
+                                                           const int32_t* __restrict__ closest,
+                                                           int32_t* closest_new, int32_t* affected)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nprev || !keep[i]) return;
+    const int t = rank[i];
+    const int j = closest[i];
+    int aff = 0, cn = -1;
+    if (j >= 0) {
+        if (closest[j] == i) {
+            aff = 1;  // i absorbed j
+        } else {
+            const int jj = closest[j];
+            const bool jmerged = keep[j] && jj >= 0 && closest[jj] == j;
+            if (!keep[j] || jmerged) aff = 1;
+            else cn = rank[j];
+        }
+    }
+    affected[t] = aff;
+    closest_new[t] = cn;
+}
+
+// Every particle within merge reach of a merged one searches again.
+__global__ __launch_bounds__(256) void k_merge_mark(Grid g, NbrView nv, int count,
+                                                    const int32_t* __restrict__ mlist,
+                                                    int32_t* affected,
+                                                    const unsigned long long* __restrict__ pad)
+{
+    const int tt = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int k = tt / MG, gl = tt % MG;
+    if (k >= count) return;
+    const int jm = mlist[k];
+    const double4 a = nv.xyh[jm];
+    const int lm = key_level(g, nv.keys[jm]);
+    // a partner lies within (h_i + h_j) / 2 <= max(h_i, h_j): a third of the
+    // support radius, as in the search
+    group_walk<MG>(g, nv, a.x, a.y, a.z, lm, gl, [&](int js, bool pass, double, double, double, double) {
+        if (!pass) return;
+        const int j = nv.perm[js];
+        if (j >= 0) affected[j] = 1;
+    }, 0.34, pad);
+}
+
 // ---------------------------------------------------------------------------
 // Shift + Taylor correction, h update (CSR rows in ascending slot order)
 // ---------------------------------------------------------------------------
@@ -411,9 +518,13 @@ __global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double 
 #define SHIFT_SKIN 0.15
 #endif
 
-__global__ void k_clear_u64(unsigned long long* p)
+__global__ void k_clear_u64(unsigned long long* p, int k)
 {
-    if (threadIdx.x == 0) p[0] = 0ull;
+    if ((int)threadIdx.x < k) p[threadIdx.x] = 0ull;
+}
+__global__ void k_clear_i32_1(int32_t* p)
+{
+    if (threadIdx.x == 0) p[0] = 0;
 }
 __global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32_t* __restrict__ kind,
                                                       const double4* __restrict__ A,
@@ -841,21 +952,58 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
     n = n + 6 * ns;
 
     FluidState d = tmp_state(c, ps->kind != nullptr);
+    // the first iteration builds the neighbour structure, the later ones
+    // reuse it (see k_merge_remap_sorted); buffers free during adaptation:
+    // closest partners alternate between w.closest and i64_a, the affected
+    // marks in i64_b, the merged particles' sorted positions in tmp_i64[2],
+    // the per-level pads in red, their count in status[32]
+    int32_t* cur = w.closest;
+    int32_t* nxt = (int32_t*)w.i64_a;
+    int32_t* affected = (int32_t*)w.i64_b;
+    int32_t* mlist = (int32_t*)w.tmp_i64[2];
+    int32_t* mcount = w.status + 32;
+    unsigned long long* pad = (unsigned long long*)w.red;
+    int nsorted = 0, nprev = 0, nmerged = 0;
     for (int it = 0; it < cf.merge_iters; ++it) {
         if (n == 0) break;
-        rc = nbr_build(c, n, ps->x, ps->y, ps->h);
-        if (rc) return rc;
-        NbrView nv = nbr_view(c);
-        unsigned nb = (unsigned)cdiv(n, 256);
+        if (it > 0 && nmerged == 0) break;  // the state did not change: nothing more merges
+        NbrView nv;
+        const bool reuse = it > 0;
+        if (!reuse) {
+            rc = nbr_build(c, n, ps->x, ps->y, ps->h);
+            if (rc) return rc;
+            nsorted = n;
+            hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->stream, pad, (int)SPH_MAXL);
+            nv = nbr_view(c);
+        } else {
+            const unsigned nbs = (unsigned)cdiv(nsorted, 256);
+            hipLaunchKernelGGL(k_clear_i32_1, dim3(1), dim3(64), 0, c->stream, mcount);
+            hipLaunchKernelGGL(k_merge_remap_sorted, dim3(nbs), dim3(256), 0, c->stream, c->grid, nsorted,
+                               w.vals_a, (const uint64_t*)w.keys_a, (const double*)w.xs, (const double*)w.ys,
+                               w.xyh, w.hmax_bits, pad, s, (const int32_t*)w.flag, (const int32_t*)w.idx_a,
+                               (const int32_t*)cur, mlist, mcount);
+            hipLaunchKernelGGL(k_merge_remap_slots, dim3((unsigned)cdiv(nprev, 256)), dim3(256), 0,
+                               c->stream, nprev, (const int32_t*)w.flag, (const int32_t*)w.idx_a,
+                               (const int32_t*)cur, nxt, affected);
+            nv = nbr_view(c);
+            hipLaunchKernelGGL(k_merge_mark, dim3((unsigned)cdiv((int64_t)nmerged * MG, 256)), dim3(256), 0,
+                               c->stream, c->grid, nv, nmerged, (const int32_t*)mlist, affected,
+                               (const unsigned long long*)pad);
+            LAUNCHCHK(c, "merge_remap");
+            int32_t* tsw = cur; cur = nxt; nxt = tsw;
+        }
+        const unsigned nbs = (unsigned)cdiv(nsorted, 256);
+        const unsigned nb = (unsigned)cdiv(n, 256);
         // sorted-order records of the mergeability data (the rate passes'
         // record buffer is free during adaptation)
         MergeRec* mrec = (MergeRec*)w.pa;
-        hipLaunchKernelGGL(k_merge_pack, dim3(nb), dim3(256), 0, c->stream, n, (const int32_t*)nv.perm, s,
-                           cf.mmax_f, mrec);
-        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)n * MG, 256)), dim3(256), 0,
-                           c->stream, c->grid, nv, n, s, cf.mass_q, cf.mmax_f, (const MergeRec*)mrec,
-                           w.closest);
-        hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, w.closest, w.flag);
+        hipLaunchKernelGGL(k_merge_pack, dim3(nbs), dim3(256), 0, c->stream, nsorted,
+                           (const int32_t*)nv.perm, s, cf.mmax_f, mrec);
+        hipLaunchKernelGGL(k_merge_closest, dim3((unsigned)cdiv((int64_t)nsorted * MG, 256)), dim3(256), 0,
+                           c->stream, c->grid, nv, nsorted, s, cf.mass_q, cf.mmax_f, (const MergeRec*)mrec,
+                           cur, reuse ? (const int32_t*)affected : (const int32_t*)nullptr,
+                           reuse ? (const unsigned long long*)pad : (const unsigned long long*)nullptr);
+        hipLaunchKernelGGL(k_merge_keep, dim3(nb), dim3(256), 0, c->stream, n, cur, w.flag);
         LAUNCHCHK(c, "merge_closest");
         // number of pairs = number of deleted slots
         int32_t nkeep = 0;
@@ -863,10 +1011,12 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         if (rc) return rc;
         map->n_merged[it] = n - nkeep;
         hipLaunchKernelGGL(k_merge_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, d,
-                           w.closest, w.flag, w.idx_a, cf.mass_q);
+                           cur, w.flag, w.idx_a, cf.mass_q);
         LAUNCHCHK(c, "merge_apply");
         rc = copy_state(c, d, s, nkeep);
         if (rc) return rc;
+        nprev = n;
+        nmerged = n - nkeep;
         n = nkeep;
     }
 
@@ -913,7 +1063,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             if (rc) return rc;
         }
         const bool measure = super && allow >= 0.0;
-        if (measure) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->stream, dmax);
+        if (measure) hipLaunchKernelGGL(k_clear_u64, dim3(1), dim3(64), 0, c->stream, dmax, 1);
         const unsigned nb = (unsigned)cdiv(n, 256);
         const unsigned nbg = (unsigned)cdiv((int64_t)n * SHIFT_G, 256);
         // packed records in the rate passes' buffers (free during adaptation);

@@ -388,13 +388,17 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& 
 // dy, r2, hj) is called by all G lanes together (the loop bounds depend only
 // on i), once per record slot: `pass` is false for a slot past the run's end
 // (whose js is not a record to use) and for a record outside the support.
+// pad (when given): per level, a distance added to the search radius for
+// particles that moved since the build (they stay filed in their old cells).
 template <int G, class F>
 __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& nv, double xi,
                                                  double yi, double hi, int li, int l, int gl,
-                                                 F&& f, double sf)
+                                                 F&& f, double sf,
+                                                 const unsigned long long* pad = nullptr)
 {
     const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
-    const double R = 3.0 * (hi > hl ? hi : hl) * sf;
+    double R = 3.0 * (hi > hl ? hi : hl) * sf;
+    if (pad) R += __longlong_as_double((long long)pad[l]);
     const double Rs = R * (1.0 + 1e-9) + 1e-12 * (fabs(xi) + fabs(yi) + R);
     const double Rs2 = Rs * Rs;
     const int Q = l > li ? l : li;
@@ -475,11 +479,12 @@ __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& n
 
 template <int G, class F>
 __device__ __forceinline__ void group_walk(const Grid& g, const NbrView& nv, double xi, double yi,
-                                           double hi, int li, int gl, F&& f, double sf = 1.0)
+                                           double hi, int li, int gl, F&& f, double sf = 1.0,
+                                           const unsigned long long* pad = nullptr)
 {
     for (int l = 0; l < g.nlev; ++l) {
         if (nv.lcount[l] == 0) continue;
-        group_walk_level<G>(g, nv, xi, yi, hi, li, l, gl, f, sf);
+        group_walk_level<G>(g, nv, xi, yi, hi, li, l, gl, f, sf, pad);
     }
 }
 
