@@ -503,6 +503,11 @@ def rates_errors(SPH, s, dt, n0, torch):
     return rerr
 
 
+
+def progress(msg):
+    """One line per finished phase on stderr, so a long run shows where it is."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -608,6 +613,7 @@ def main():
         results[name] = {"ms_per_step": ms_step, "pairs": pairs, "n": P.n, "prof": prof,
                          "pair_evals_per_s": 2.0 * pairs / (ms_step * 1e-3),
                          "n_adapted": n_adapted, "size_ratio": ratio}
+        progress(f"{name}: {ms_step:.4f} ms/step over {steps} steps, n={P.n}")
         del ctx, P, B
         torch.cuda.empty_cache()
 
@@ -618,13 +624,16 @@ def main():
     if not args.no_serve:
         serve = serving_bench(SPH, W, args)
         torch.cuda.empty_cache()
+        progress("serving done")
 
     configs = None if args.no_configs else config_lines(SPH, W, torch)
+    progress("config lines done")
 
     cpu = None
     rerr = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(SPH, W, s, dt, n0, args)
+        progress("cpu baseline done")
         rerr = rates_errors(SPH, s, dt, n0, torch)
 
     out = {
