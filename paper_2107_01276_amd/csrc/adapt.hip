@@ -496,13 +496,19 @@ __global__ __launch_bounds__(256) void k_merge_mark(Grid g, NbrView nv, int coun
 // Per-slot records for the shift and h-update sweeps, so that a neighbour
 // costs two 32-byte loads: A = {x, y, h, m}, B = {u, v, p, rho} (m = mq q,
 // the same double the oracle uses).
-__global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double q, double4* A,
-                                                    double4* B)
+// With rho0 > 0 (the shift sweeps) the last members are the quotients the
+// shift terms use, m / rho0 and V = m / rho: the same correctly rounded
+// divisions of the same operands, taken once per particle instead of once
+// per pair.
+__global__ __launch_bounds__(256) void k_pack_shift(int n, FluidState s, double q, double rho0,
+                                                    double4* A, double4* B)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    A[i] = make_double4(s.x[i], s.y[i], s.h[i], (double)s.mq[i] * q);
-    B[i] = make_double4(s.u[i], s.v[i], s.p[i], s.rho[i]);
+    const double m = (double)s.mq[i] * q;
+    const double rho = s.rho[i];
+    A[i] = make_double4(s.x[i], s.y[i], s.h[i], rho0 > 0.0 ? m / rho0 : m);
+    B[i] = make_double4(s.u[i], s.v[i], s.p[i], rho0 > 0.0 ? m / rho : rho);
 }
 
 // The neighbours of each fluid row in the current positions, kept in
@@ -652,18 +658,18 @@ __device__ __forceinline__ double shift_row(const Grid& g, const double4* __rest
         if constexpr (!EXACT) {
             if (r <= 0.0) return o;
         }
-        const double mj = aj.w;
+        // aj.w = m_j / rho0 and bj.w = V_j = m_j / rho_j (k_pack_shift)
         // shifting term at h_ij
         const double hij = 0.5 * (hi + hj);
         const double wr = kern_f<double>(r / hij) / fxi;
-        const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+        const double coef = aj.w * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
         const double tt = coef * (kern_dw64(r, hij) / r);
         o.sx = tt * dx;
         o.sy = tt * dy;
         // gradients at h_i
         const double f = kern_dw64(r, hi) / r;
         const double wx = f * dx, wy = f * dy;
-        const double Vj = mj / bj.w;
+        const double Vj = bj.w;
         const double du = bj.x - ui, dv = bj.y - vi, dp = bj.z - pi;
         o.gux = Vj * du * wx; o.guy = Vj * du * wy;
         o.gvx = Vj * dv * wx; o.gvy = Vj * dv * wy;
@@ -1069,7 +1075,8 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         // packed records in the rate passes' buffers (free during adaptation);
         // rows in the sorted order of the last build (slots unchanged since)
         double4 *pA = w.pa, *pB = (double4*)w.pf;
-        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, pA, pB);
+        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, cf.rho0, pA,
+                           pB);
         if (filt) {
             hipLaunchKernelGGL(k_shift_filter, dim3((unsigned)cdiv((int64_t)n * FG, 256)), dim3(256), 0,
                                c->stream, c->grid, n, (const int32_t*)s.kind, (const double4*)pA,
@@ -1110,7 +1117,7 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
             if (rc) return rc;
         }
         unsigned nb = (unsigned)cdiv(n, 256);
-        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, w.pa,
+        hipLaunchKernelGGL(k_pack_shift, dim3(nb), dim3(256), 0, c->stream, n, s, cf.mass_q, 0.0, w.pa,
                            (double4*)w.pf);
         hipLaunchKernelGGL(k_hupdate, dim3((unsigned)cdiv((int64_t)n * SHIFT_G, 256)), dim3(256), 0,
                            c->stream, c->grid, n, w.rp_tmp, w.col_tmp,

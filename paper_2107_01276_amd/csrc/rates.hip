@@ -86,8 +86,14 @@ __device__ __forceinline__ void rate_kern(T q, T& f, T& fp)
         f = a4 * a - T(6) * (b4 * b) + T(15) * (c4 * c);
         fp = T(-5) * a4 + T(30) * b4 - T(75) * c4;
     } else {
-        f = kern_f<T>(q);
-        fp = kern_fp<T>(q);
+        // every bracket clamped at zero and the powers shared between W
+        // and W', contracted into FMAs
+        RATES_FP_CONTRACT
+        const T a = fmaxf(T(3) - q, T(0)), b = fmaxf(T(2) - q, T(0)), c = fmaxf(T(1) - q, T(0));
+        const T a2 = a * a, b2 = b * b, c2 = c * c;
+        const T a4 = a2 * a2, b4 = b2 * b2, c4 = c2 * c2;
+        f = a4 * a - T(6) * (b4 * b) + T(15) * (c4 * c);
+        fp = T(-5) * a4 + T(30) * b4 - T(75) * c4;
     }
 }
 template <typename T>
@@ -99,7 +105,10 @@ __device__ __forceinline__ T rate_kern_fp(T q)
         const T a2 = a * a, b2 = b * b, c2 = c * c;
         return T(-5) * (a2 * a2) + T(30) * (b2 * b2) - T(75) * (c2 * c2);
     } else {
-        return kern_fp<T>(q);
+        RATES_FP_CONTRACT
+        const T a = fmaxf(T(3) - q, T(0)), b = fmaxf(T(2) - q, T(0)), c = fmaxf(T(1) - q, T(0));
+        const T a2 = a * a, b2 = b * b, c2 = c * c;
+        return T(-5) * (a2 * a2) + T(30) * (b2 * b2) - T(75) * (c2 * c2);
     }
 }
 
@@ -412,7 +421,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
     int32_t* const exo = ex.idx;
     int ne = 0;  // exact entries of the row (the same in every lane of the group)
     // called by all lanes of the group together; `pass` marks a neighbour
-    auto body = [&](int js, bool pass, double dx, double dy, double r2, double hj, double pj)
+    auto body = [&](int js, bool pass, double dx, double dy, double r2, double hj, double pj, T mj)
         __attribute__((always_inline)) {
         const bool ext = pass && js != s;
         int tot;
@@ -421,7 +430,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         ne += tot;
         if (pass) {
             ++nn;
-            terms(dx, dy, r2, hj, pj, b.m[js]);
+            terms(dx, dy, r2, hj, pj, mj);
         }
     };
     if (cnt <= nl.K) {
@@ -431,13 +440,17 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         for (int base = 0; base < cnt; base += 4 * G) {
             int j[4];
             double4 a[4];
+            T mj[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = base + gl + G * u;
                 j[u] = k < cnt ? nl.idx[(int64_t)k * nl.stride + s] : s;
             }
+            // records and masses requested together, before any test
 #pragma unroll
             for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mj[u] = b.m[j[u]];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const double dx = mi_axis(g, 0, xi - a[u].x);
@@ -445,13 +458,14 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
                 const double r2 = dx * dx + dy * dy;
                 const double rj3 = 3.0 * a[u].z;
                 const bool pass = base + gl + G * u < cnt && r2 < fmax(ri2, rj3 * rj3);
-                body(j[u], pass, dx, dy, r2, a[u].z, a[u].w);
+                body(j[u], pass, dx, dy, r2, a[u].z, a[u].w, mj[u]);
             }
         }
     } else {
         group_walk<G>(g, nv, xi, yi, hi, li, gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
-                           body(js, pass, dx, dy, r2, hj, pass ? pa[js].w : 0.0);
+                           body(js, pass, dx, dy, r2, hj, pass ? pa[js].w : 0.0,
+                                pass ? b.m[js] : T(0));
                        });
     }
     if (exo && gl == 0) ex.cnt[s] = ne <= ex.K ? ne : ex.K + 1;
@@ -617,8 +631,8 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
     // the divergence, the diffusion, the pressure gradient G and the
     // viscous term all cancel between neighbours)
     CSum<T> sdiv, sdif, gx, gy, vx, vy;
-    auto body = [&](int js, double dx, double dy, double r2, double hj, double pj)
-        __attribute__((always_inline)) {
+    auto body = [&](int js, double dx, double dy, double r2, double hj, double pj, double2 uvj,
+                    typename Vec4<T>::type fj4) __attribute__((always_inline)) {
         RATES_FP_CONTRACT
         // r and 1/r; r = 0 (the self pair, or coincident particles): every
         // term below carries a factor 1/r * r-free gradient or r itself, and
@@ -632,8 +646,6 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             r = fsqrt<T>((T)r2);
             ir = r > T(0) ? rcp<T>(r) : T(0);
         }
-        const double2 uvj = puv[js];
-        const typename Vec4<T>::type fj4 = pf[js];
         const T ihj = rcp<T>((T)hj);
         const T dwi = sigi * rate_kern_fp<T>(r * ih);
         const T dwj = T(SPH_SIGMA2) * ihj * ihj * ihj * rate_kern_fp<T>(r * ihj);
@@ -680,6 +692,9 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             vy.add(cv * vij);
         }
     };
+    // the body with the neighbour's velocity and factors read here
+    auto body_ld = [&](int js, double dx, double dy, double r2, double hj, double pj)
+        __attribute__((always_inline)) { body(js, dx, dy, r2, hj, pj, puv[js], pf[js]); };
     const int ecnt = ex.idx ? ex.cnt[s] : ex.K + 1;
     const int cnt = nl.idx ? nl.cnt[s] : nl.K + 1;
     // the lanes of the group take every G-th entry of the row
@@ -696,10 +711,17 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
         for (; k + (UN - 1) * G < ecnt; k += UN * G) {
             int j[UN];
             double4 a[UN];
+            double2 uv[UN];
+            typename Vec4<T>::type f4[UN];
 #pragma unroll
             for (int u = 0; u < UN; ++u) j[u] = jn[u];
+            // every record of the chunk is requested before any is used
 #pragma unroll
             for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) uv[u] = puv[j[u]];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) f4[u] = pf[j[u]];
             if (k + UN * G + (UN - 1) * G < ecnt) {
 #pragma unroll
                 for (int u = 0; u < UN; ++u)
@@ -709,7 +731,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             for (int u = 0; u < UN; ++u) {
                 const double dx = mi_axis(g, 0, xi - a[u].x);
                 const double dy = mi_axis(g, 1, yi - a[u].y);
-                body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w);
+                body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w, uv[u], f4[u]);
             }
         }
         for (; k < ecnt; k += G) {
@@ -717,7 +739,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             const double4 a = pa[js];
             const double dx = mi_axis(g, 0, xi - a.x);
             const double dy = mi_axis(g, 1, yi - a.y);
-            body(js, dx, dy, dx * dx + dy * dy, a.z, a.w);
+            body_ld(js, dx, dy, dx * dx + dy * dy, a.z, a.w);
         }
     } else if (cnt <= nl.K) {
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
@@ -728,12 +750,12 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             const double dy = mi_axis(g, 1, yi - a.y);
             const double r2 = dx * dx + dy * dy;
             const double rj3 = 3.0 * a.z;
-            if (r2 < fmax(ri2, rj3 * rj3)) body(js, dx, dy, r2, a.z, a.w);
+            if (r2 < fmax(ri2, rj3 * rj3)) body_ld(js, dx, dy, r2, a.z, a.w);
         }
     } else {
         group_walk<G>(g, nv, xi, yi, hi, key_level(g, nv.keys[s]), gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
-                           if (pass) body(js, dx, dy, r2, hj, pa[js].w);
+                           if (pass) body_ld(js, dx, dy, r2, hj, pa[js].w);
                        });
     }
     // the group's partial sums, combined in every lane
