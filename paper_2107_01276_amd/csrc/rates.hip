@@ -96,6 +96,13 @@ __device__ __forceinline__ void rate_kern(T q, T& f, T& fp)
         fp = T(-5) * a4 + T(30) * b4 - T(75) * c4;
     }
 }
+// q = r * (1/h), rounded before the spline's brackets use it (so the
+// brackets are plain subtractions, not contracted with the product)
+template <typename T>
+__device__ __forceinline__ T rate_q(T r, T ih)
+{
+    return r * ih;
+}
 template <typename T>
 __device__ __forceinline__ T rate_kern_fp(T q)
 {
@@ -390,10 +397,9 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
     const T sig = T(SPH_SIGMA2) * ih * ih;
     const T irho0 = T(1.0 / rho0);
     const T ifxi = T(1.0) / kern_f<T>(T(SPH_XI));
-    // compensated sums: Kahan for rho and beta (terms of one sign each),
-    // Neumaier for p_avg and the shift (terms of both signs)
-    KSum<T> sr, sb;
-    CSum<T> sp, sx, sy;
+    // Kahan-compensated sums (error within about 2 eps of the sum of the
+    // terms' magnitudes, for terms of either sign)
+    KSum<T> sr, sb, sp, sx, sy;
     int nn = 0;  // |N(i)|
     // one pair's terms; r = 0 (the self pair, or coincident particles)
     // adds nothing to the shift sums
@@ -408,7 +414,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         sp.add((T)(pj - pi));
         const T ihij = rcp<T>((T)(0.5 * (hi + hj)));
         T fij, fpij;
-        rate_kern<T>(r * ihij, fij, fpij);
+        rate_kern<T>(rate_q<T>(r, ihij), fij, fpij);
         const T wr = fij * ifxi;
         const T wr2 = wr * wr;
         const T coef = (mj * irho0) * (T(1) + T(0.24) * (wr2 * wr2));
@@ -437,30 +443,33 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         // the lanes of the group take every G-th entry of the row; four
         // entries' loads are issued before their tests
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
-        for (int base = 0; base < cnt; base += 4 * G) {
-            int j[4];
-            double4 a[4];
-            T mj[4];
+        with_periodicity(g, [&](auto pxc, auto pyc) __attribute__((always_inline)) {
+            constexpr bool PX = decltype(pxc)::value, PY = decltype(pyc)::value;
+            for (int base = 0; base < cnt; base += 4 * G) {
+                unsigned j[4];
+                double4 a[4];
+                T mj[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = base + gl + G * u;
-                j[u] = k < cnt ? nl.idx[(int64_t)k * nl.stride + s] : s;
+                for (int u = 0; u < 4; ++u) {
+                    const int k = base + gl + G * u;
+                    j[u] = (unsigned)(k < cnt ? nl.idx[(int64_t)k * nl.stride + s] : s);
+                }
+                // records and masses requested together, before any test
+#pragma unroll
+                for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) mj[u] = b.m[j[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double dx = mi_axis_c<PX>(g, 0, xi - a[u].x);
+                    const double dy = mi_axis_c<PY>(g, 1, yi - a[u].y);
+                    const double r2 = dx * dx + dy * dy;
+                    const double rj3 = 3.0 * a[u].z;
+                    const bool pass = base + gl + G * u < cnt && r2 < fmax(ri2, rj3 * rj3);
+                    body((int)j[u], pass, dx, dy, r2, a[u].z, a[u].w, mj[u]);
+                }
             }
-            // records and masses requested together, before any test
-#pragma unroll
-            for (int u = 0; u < 4; ++u) a[u] = pa[j[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) mj[u] = b.m[j[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double dx = mi_axis(g, 0, xi - a[u].x);
-                const double dy = mi_axis(g, 1, yi - a[u].y);
-                const double r2 = dx * dx + dy * dy;
-                const double rj3 = 3.0 * a[u].z;
-                const bool pass = base + gl + G * u < cnt && r2 < fmax(ri2, rj3 * rj3);
-                body(j[u], pass, dx, dy, r2, a[u].z, a[u].w, mj[u]);
-            }
-        }
+        });
     } else {
         group_walk<G>(g, nv, xi, yi, hi, li, gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
@@ -627,10 +636,11 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
     const T nui = aecs8 * (T)hi;
     const T eta = (T)(0.001 * hi * hi);
     const T nu4 = (T)(4.0 * P.nu);
-    // every pair sum is Neumaier-compensated in float (terms of both signs:
-    // the divergence, the diffusion, the pressure gradient G and the
-    // viscous term all cancel between neighbours)
-    CSum<T> sdiv, sdif, gx, gy, vx, vy;
+    // every pair sum is Kahan-compensated in float (the divergence, the
+    // diffusion, the pressure gradient G and the viscous term all cancel
+    // between neighbours; the error stays within about 2 eps of the sum of
+    // the terms' magnitudes)
+    KSum<T> sdiv, sdif, gx, gy, vx, vy;
     auto body = [&](int js, double dx, double dy, double r2, double hj, double pj, double2 uvj,
                     typename Vec4<T>::type fj4) __attribute__((always_inline)) {
         RATES_FP_CONTRACT
@@ -703,37 +713,41 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
         // loaded at a time; the next UN indices are read before this
         // chunk's terms, so their latency overlaps the gathers and the math
         int k = gl;
-        int jn[UN];
-        if (k + (UN - 1) * G < ecnt) {
-#pragma unroll
-            for (int u = 0; u < UN; ++u) jn[u] = ex.idx[(int64_t)(k + G * u) * ex.stride + s];
-        }
-        for (; k + (UN - 1) * G < ecnt; k += UN * G) {
-            int j[UN];
-            double4 a[UN];
-            double2 uv[UN];
-            typename Vec4<T>::type f4[UN];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) j[u] = jn[u];
-            // every record of the chunk is requested before any is used
-#pragma unroll
-            for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) uv[u] = puv[j[u]];
-#pragma unroll
-            for (int u = 0; u < UN; ++u) f4[u] = pf[j[u]];
-            if (k + UN * G + (UN - 1) * G < ecnt) {
+        with_periodicity(g, [&](auto pxc, auto pyc) __attribute__((always_inline)) {
+            constexpr bool PX = decltype(pxc)::value, PY = decltype(pyc)::value;
+            unsigned jn[UN];
+            if (k + (UN - 1) * G < ecnt) {
 #pragma unroll
                 for (int u = 0; u < UN; ++u)
-                    jn[u] = ex.idx[(int64_t)(k + UN * G + G * u) * ex.stride + s];
+                    jn[u] = (unsigned)ex.idx[(int64_t)(k + G * u) * ex.stride + s];
             }
+            for (; k + (UN - 1) * G < ecnt; k += UN * G) {
+                unsigned j[UN];
+                double4 a[UN];
+                double2 uv[UN];
+                typename Vec4<T>::type f4[UN];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                const double dx = mi_axis(g, 0, xi - a[u].x);
-                const double dy = mi_axis(g, 1, yi - a[u].y);
-                body(j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w, uv[u], f4[u]);
+                for (int u = 0; u < UN; ++u) j[u] = jn[u];
+                // every record of the chunk is requested before any is used
+#pragma unroll
+                for (int u = 0; u < UN; ++u) a[u] = pa[j[u]];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) uv[u] = puv[j[u]];
+#pragma unroll
+                for (int u = 0; u < UN; ++u) f4[u] = pf[j[u]];
+                if (k + UN * G + (UN - 1) * G < ecnt) {
+#pragma unroll
+                    for (int u = 0; u < UN; ++u)
+                        jn[u] = (unsigned)ex.idx[(int64_t)(k + UN * G + G * u) * ex.stride + s];
+                }
+#pragma unroll
+                for (int u = 0; u < UN; ++u) {
+                    const double dx = mi_axis_c<PX>(g, 0, xi - a[u].x);
+                    const double dy = mi_axis_c<PY>(g, 1, yi - a[u].y);
+                    body((int)j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w, uv[u], f4[u]);
+                }
             }
-        }
+        });
         for (; k < ecnt; k += G) {
             const int js = ex.idx[(int64_t)k * ex.stride + s];
             const double4 a = pa[js];

@@ -132,6 +132,30 @@ __device__ __forceinline__ double mi_axis(const Grid& g, int a, double d)
     return d;
 }
 
+// mi_axis on an axis whose periodicity P is known at compile time (an open
+// axis leaves d as mi_axis does), and f(integral_constant<bool, px>,
+// integral_constant<bool, py>) called for the grid's periodicity: one
+// uniform branch outside a pair loop instead of selects in every pair.
+template <bool P>
+__device__ __forceinline__ double mi_axis_c(const Grid& g, int a, double d)
+{
+    if constexpr (P) return mi_axis(g, a, d);
+    else return d;
+}
+template <class F>
+__device__ __forceinline__ void with_periodicity(const Grid& g, F&& f)
+{
+    using Y = std::integral_constant<bool, true>;
+    using N = std::integral_constant<bool, false>;
+    if (g.periodic[0]) {
+        if (g.periodic[1]) f(Y{}, Y{});
+        else f(Y{}, N{});
+    } else {
+        if (g.periodic[1]) f(N{}, Y{});
+        else f(N{}, N{});
+    }
+}
+
 __device__ __forceinline__ double wrap_axis(const Grid& g, int a, double x)
 {
     if (g.periodic[a]) {
