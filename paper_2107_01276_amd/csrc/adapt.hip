@@ -112,12 +112,12 @@ __global__ __launch_bounds__(256) void k_mref_lookup(Grid g, NbrView nv, int n,
     const int li = level_of(g, hi);
     double mn = 0.0;
     int found = 0;
-    group_walk<WG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double, double, double, double) {
-        if (!pass) return;
-        double v = bms[js];
-        if (!found || v < mn) mn = v;
-        found = 1;
-    });
+    group_walk_x<WG>(g, nv, bms, xi, yi, hi, li, gl,
+                     [&](int, bool pass, double, double, double, double, double v) {
+                         if (!pass) return;
+                         if (!found || v < mn) mn = v;
+                         found = 1;
+                     });
     // the minimum over the group's lanes (exact, independent of order)
 #pragma unroll
     for (int o = 1; o < WG; o <<= 1) {
@@ -307,10 +307,10 @@ __global__ __launch_bounds__(256) void k_merge_closest(Grid g, NbrView nv, int n
     if (ki == SPH_FLUID && !(mi > mmi)) {
         // a merge partner lies within (h_i + h_j)/2 <= max(h_i, h_j): a third
         // of the support radius (0.34 leaves margin for rounding) bounds it
-        group_walk<MG>(g, nv, xi, yi, hi, li, gl, [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+        group_walk_x<MG>(g, nv, rec, xi, yi, hi, li, gl,
+                         [&](int js, bool pass, double dx, double dy, double r2, double hj, MergeRec rj) {
             if (!pass || js == sp) return;
             if (best >= 0 && r2 > br) return;  // cannot beat the current best
-            const MergeRec rj = rec[js];
             if (!(rj.mm >= 0.0)) return;       // not fluid
             const int64_t mqj = rj.mq;
             const double mj = (double)mqj * q;
@@ -482,11 +482,10 @@ __global__ __launch_bounds__(256) void k_merge_mark(Grid g, NbrView nv, int coun
     const int lm = key_level(g, nv.keys[jm]);
     // a partner lies within (h_i + h_j) / 2 <= max(h_i, h_j): a third of the
     // support radius, as in the search
-    group_walk<MG>(g, nv, a.x, a.y, a.z, lm, gl, [&](int js, bool pass, double, double, double, double) {
-        if (!pass) return;
-        const int j = nv.perm[js];
-        if (j >= 0) affected[j] = 1;
-    }, 0.34, pad);
+    group_walk_x<MG>(g, nv, nv.perm, a.x, a.y, a.z, lm, gl,
+                     [&](int, bool pass, double, double, double, double, int32_t j) {
+                         if (pass && j >= 0) affected[j] = 1;
+                     }, 0.34, pad);
 }
 
 // ---------------------------------------------------------------------------

@@ -810,14 +810,14 @@ __global__ __launch_bounds__(256) void k_csr_stage(Grid g, NbrView nv, int n, in
     const int slot = nv.perm[s];
     int32_t* row = stage + (int64_t)slot * K;
     int k = 0;
-    group_walk<LG>(g, nv, xi, yi, hi, li, gl,
-                   [&](int js, bool pass, double, double, double, double) {
-                       int tot;
-                       const int e = k + group_rank<LG>(pass, gl, &tot);
-                       if (pass && e < K) row[e] = nv.perm[js];
-                       k += tot;
-                   },
-                   sf);
+    group_walk_x<LG>(g, nv, nv.perm, xi, yi, hi, li, gl,
+                     [&](int, bool pass, double, double, double, double, int32_t j) {
+                         int tot;
+                         const int e = k + group_rank<LG>(pass, gl, &tot);
+                         if (pass && e < K) row[e] = j;
+                         k += tot;
+                     },
+                     sf);
     if (gl == 0) {
         cnt[slot] = k;
         if (k > K) flag[0] = 1;

@@ -1,6 +1,8 @@
 // Device helpers: quintic spline kernel, minimum image, neighbour traversal.
 #pragma once
 
+#include <type_traits>
+
 #include "sph_internal.h"
 
 // 7 / (478 pi), the 2D normalisation of the quintic spline (eq. kernel).
@@ -414,12 +416,19 @@ __device__ __forceinline__ void for_each_neighbor(const Grid& g, const NbrView& 
 // (whose js is not a record to use) and for a record outside the support.
 // pad (when given): per level, a distance added to the search radius for
 // particles that moved since the build (they stay filed in their old cells).
-template <int G, class F>
-__device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& nv, double xi,
-                                                 double yi, double hi, int li, int l, int gl,
-                                                 F&& f, double sf,
-                                                 const unsigned long long* pad = nullptr)
+// With an array E ext (sorted order) the walk reads ext[js] beside each
+// record, before any test, and passes it to f as a seventh argument, so a
+// caller that needs it for passing neighbours waits for one load, not a
+// second one after its test.  NoExt: no array, f takes six arguments.
+struct NoExt {};
+template <int G, class E, class F>
+__device__ __forceinline__ void group_walk_level_x(const Grid& g, const NbrView& nv,
+                                                   const E* __restrict__ ext, double xi,
+                                                   double yi, double hi, int li, int l, int gl,
+                                                   F&& f, double sf,
+                                                   const unsigned long long* pad = nullptr)
 {
+    constexpr bool HX = !std::is_same<E, NoExt>::value;
     const double hl = __longlong_as_double((long long)nv.hmax_bits[l]);
     double R = 3.0 * (hi > hl ? hi : hl) * sf;
     if (pad) R += __longlong_as_double((long long)pad[l]);
@@ -434,11 +443,16 @@ __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& n
         for (int base = se.x; base < se.y; base += 4 * G) {
             int js[4];
             double4 a[4];
+            E ev[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 js[u] = base + gl + G * u;
                 // a slot past the end reads the run's first record (in bounds)
                 a[u] = nv.xyh[js[u] < se.y ? js[u] : se.x];
+            }
+            if constexpr (HX) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ev[u] = ext[js[u] < se.y ? js[u] : se.x];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -447,7 +461,8 @@ __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& n
                 const double r2 = dx * dx + dy * dy;
                 const double hm = hi > a[u].z ? hi : a[u].z;
                 const double RR = (3.0 * hm) * sf;
-                f(js[u], js[u] < se.y && r2 < RR * RR, dx, dy, r2, a[u].z);
+                if constexpr (HX) f(js[u], js[u] < se.y && r2 < RR * RR, dx, dy, r2, a[u].z, ev[u]);
+                else f(js[u], js[u] < se.y && r2 < RR * RR, dx, dy, r2, a[u].z);
             }
         }
     };
@@ -502,6 +517,15 @@ __device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& n
 }
 
 template <int G, class F>
+__device__ __forceinline__ void group_walk_level(const Grid& g, const NbrView& nv, double xi,
+                                                 double yi, double hi, int li, int l, int gl,
+                                                 F&& f, double sf,
+                                                 const unsigned long long* pad = nullptr)
+{
+    group_walk_level_x<G, NoExt>(g, nv, nullptr, xi, yi, hi, li, l, gl, f, sf, pad);
+}
+
+template <int G, class F>
 __device__ __forceinline__ void group_walk(const Grid& g, const NbrView& nv, double xi, double yi,
                                            double hi, int li, int gl, F&& f, double sf = 1.0,
                                            const unsigned long long* pad = nullptr)
@@ -509,6 +533,19 @@ __device__ __forceinline__ void group_walk(const Grid& g, const NbrView& nv, dou
     for (int l = 0; l < g.nlev; ++l) {
         if (nv.lcount[l] == 0) continue;
         group_walk_level<G>(g, nv, xi, yi, hi, li, l, gl, f, sf, pad);
+    }
+}
+
+// group_walk with ext[js] read beside every record (group_walk_level_x)
+template <int G, class E, class F>
+__device__ __forceinline__ void group_walk_x(const Grid& g, const NbrView& nv,
+                                             const E* __restrict__ ext, double xi, double yi,
+                                             double hi, int li, int gl, F&& f, double sf = 1.0,
+                                             const unsigned long long* pad = nullptr)
+{
+    for (int l = 0; l < g.nlev; ++l) {
+        if (nv.lcount[l] == 0) continue;
+        group_walk_level_x<G, E>(g, nv, ext, xi, yi, hi, li, l, gl, f, sf, pad);
     }
 }
 
