@@ -372,7 +372,7 @@ def config_lines(SPH, W, torch):
     # the m_ref lookup builds the background's cells in the same context
     cap = max(int(1.6 * s["x"].size), bg["x"].size)
     line = {"background": bgi, "n_particles_generated": int(s["x"].size)}
-    for name, prec, steps in (("fp32", SPH.SPH_FP32, 40), ("fp64", SPH.SPH_FP64, 20)):
+    for name, prec, steps in (("fp32", SPH.SPH_FP32, 40), ("fp64", SPH.SPH_FP64, 40)):
         ctx, P, B = prepare(SPH, s, bg, prec, cap, 0.2, 10)
         n_ad, ratio = P.n, fluid_size_ratio(P, W)
         ctx.run(P, 5, bg=B, io=s["io"])
