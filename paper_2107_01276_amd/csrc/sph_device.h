@@ -487,16 +487,76 @@ __device__ __forceinline__ void group_walk_level_x(const Grid& g, const NbrView&
                 if (gx * gx + gy * gy <= Rs2) own[t] = tab[(int64_t)cy * nq + cx];
             }
         }
-        const int base = __lane_id() & ~(G - 1);
+        // The runs are walked as one sequence in cell order: candidate kk of
+        // the group lies in the cell whose prefix (the lengths of the cells
+        // before it) is the largest not above kk, and each lane follows its
+        // candidates with a cursor over the group's cells.  A group's lanes
+        // take consecutive candidates as they did run by run, so f sees the
+        // same candidates in the same order, but a wave no longer steps
+        // through every cell slot as long as its longest run in that slot.
+        // The group's cell table sits in LDS (written and read by the
+        // group's own lanes; kernels calling this run 256 threads a block).
+        __shared__ int s_pre[(256 / G) * 17];
+        __shared__ int s_js0[(256 / G) * 16];
+        const int grp = (int)(threadIdx.x / G);
+        int* const gpre = s_pre + grp * 17;
+        int* const gjs0 = s_js0 + grp * 16;
+        const int gb = __lane_id() & ~(G - 1);
+        int carry = 0;
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
+            const int len = own[t].y - own[t].x;
+            int incl = len;
 #pragma unroll
-            for (int q = 0; q < G; ++q) {
-                if (G * t + q >= nxc * nyc) break;
-                const int2 se = make_int2(__shfl(own[t].x, base + q, 64), __shfl(own[t].y, base + q, 64));
-                run(se);
+            for (int o = 1; o < G; o <<= 1) {
+                const int v = __shfl(incl, gb + (gl >= o ? gl - o : gl), 64);
+                if (gl >= o) incl += v;
+            }
+            const int k = gl + G * t;
+            if (k < 16) {
+                gpre[k] = carry + incl - len;
+                gjs0[k] = own[t].x - (carry + incl - len);
+            }
+            carry += __shfl(incl, gb + G - 1, 64);
+        }
+        const int tot = carry;
+        if (gl == 0) gpre[16] = tot;
+        __builtin_amdgcn_wave_barrier();
+        int c = 0, cend = gpre[1], js0 = gjs0[0];
+        for (int base = 0; base < tot; base += 4 * G) {
+            int js[4];
+            bool ok[4];
+            double4 a[4];
+            E ev[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kk = base + gl + G * u;
+                ok[u] = kk < tot;
+                const int kq = ok[u] ? kk : tot - 1;
+                while (kq >= cend) {
+                    ++c;
+                    cend = gpre[c + 1];
+                    js0 = gjs0[c];
+                }
+                js[u] = kq + js0;
+                a[u] = nv.xyh[js[u]];
+            }
+            if constexpr (HX) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) ev[u] = ext[js[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double dx = mi_axis(g, 0, xi - a[u].x);
+                const double dy = mi_axis(g, 1, yi - a[u].y);
+                const double r2 = dx * dx + dy * dy;
+                const double hm = hi > a[u].z ? hi : a[u].z;
+                const double RR = (3.0 * hm) * sf;
+                if constexpr (HX) f(js[u], ok[u] && r2 < RR * RR, dx, dy, r2, a[u].z, ev[u]);
+                else f(js[u], ok[u] && r2 < RR * RR, dx, dy, r2, a[u].z);
             }
         }
+        __builtin_amdgcn_wave_barrier();
         return;
     }
     for (int ty = 0; ty < yr.n; ++ty) {
