@@ -523,6 +523,10 @@ __device__ __forceinline__ void group_walk_level_x(const Grid& g, const NbrView&
         if (gl == 0) gpre[16] = tot;
         __builtin_amdgcn_wave_barrier();
         int c = 0, cend = gpre[1], js0 = gjs0[0];
+        // the loop specialised on the grid's periodicity (no minimum image
+        // on open axes)
+        with_periodicity(g, [&](auto pxc, auto pyc) __attribute__((always_inline)) {
+        constexpr bool PX = decltype(pxc)::value, PY = decltype(pyc)::value;
         for (int base = 0; base < tot; base += 4 * G) {
             int js[4];
             bool ok[4];
@@ -547,8 +551,8 @@ __device__ __forceinline__ void group_walk_level_x(const Grid& g, const NbrView&
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double dx = mi_axis(g, 0, xi - a[u].x);
-                const double dy = mi_axis(g, 1, yi - a[u].y);
+                const double dx = mi_axis_c<PX>(g, 0, xi - a[u].x);
+                const double dy = mi_axis_c<PY>(g, 1, yi - a[u].y);
                 const double r2 = dx * dx + dy * dy;
                 const double hm = hi > a[u].z ? hi : a[u].z;
                 const double RR = (3.0 * hm) * sf;
@@ -556,6 +560,7 @@ __device__ __forceinline__ void group_walk_level_x(const Grid& g, const NbrView&
                 else f(js[u], ok[u] && r2 < RR * RR, dx, dy, r2, a[u].z);
             }
         }
+        });
         __builtin_amdgcn_wave_barrier();
         return;
     }
