@@ -387,7 +387,10 @@ __global__ __launch_bounds__(256) void k_boundary(Grid g, NbrView nv, NbrList nl
 
 // Sorted particle s, lane gl of its group of G lanes (all lanes of the
 // group call it together).
-template <typename T, int G>
+// SP: the pair loop specialised on the grid's periodicity (one copy per
+// case); the batched kernels keep one loop with the minimum image on both
+// axes (a minimum image leaves an open axis unchanged).
+template <typename T, int G, bool SP = true>
 __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int s, int gl)
 {
     const double4 ai = pa[s];
@@ -443,7 +446,7 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
         // the lanes of the group take every G-th entry of the row; four
         // entries' loads are issued before their tests
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
-        with_periodicity(g, [&](auto pxc, auto pyc) __attribute__((always_inline)) {
+        auto list_loop = [&](auto pxc, auto pyc) __attribute__((always_inline)) {
             constexpr bool PX = decltype(pxc)::value, PY = decltype(pyc)::value;
             for (int base = 0; base < cnt; base += 4 * G) {
                 unsigned j[4];
@@ -469,7 +472,9 @@ __device__ __forceinline__ void pass_a_body(PASS_A_PARAMS_(const Grid&, T), int 
                     body((int)j[u], pass, dx, dy, r2, a[u].z, a[u].w, mj[u]);
                 }
             }
-        });
+        };
+        if constexpr (SP) with_periodicity(g, list_loop);
+        else list_loop(std::true_type{}, std::true_type{});
     } else {
         group_walk<G>(g, nv, xi, yi, hi, li, gl,
                        [&](int js, bool pass, double dx, double dy, double r2, double hj) {
@@ -571,7 +576,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     if (sl >= sd.n) return;                                                                  \
     const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
     const Guard gd{nullptr, 0};                                                              \
-    pass_a_body<T, RGA>(sd.g, batch_view(nv, sd, sid), 0, b, nl, pa, pf, sd.rho0, out,      \
+    pass_a_body<T, RGA, false>(sd.g, batch_view(nv, sd, sid), 0, b, nl, pa, pf, sd.rho0, out,\
                         r_dxs, r_dys, nullptr, ex, gd, (int)(sd.off + sl), gl);
 
 #define PASS_A_BATCH_PARAMS(T)                                                               \
@@ -580,7 +585,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass_a_b(PASS_A_BATCH_PARAMS(T));
 template <>
-__global__ __launch_bounds__(256) PA_ATTR void k_pass_a_b<float>(PASS_A_BATCH_PARAMS(float))
+// four waves per SIMD: at five the register budget spills the list
+// addresses of the batched loop, and each list load then waits on a scratch load
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_pass_a_b<float>(
+    PASS_A_BATCH_PARAMS(float))
 {
     PASS_A_BATCH(float)
 }
@@ -608,7 +616,7 @@ struct PassBParams {
 
 // Sorted particle s, lane gl of its group of G lanes; UN exact-row entries
 // loaded ahead per lane.
-template <typename T, bool GH, int G, int UN>
+template <typename T, bool GH, int G, int UN, bool SP = true>
 __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int s, int gl)
 {
     const double4 ai = pa[s];
@@ -713,7 +721,7 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
         // loaded at a time; the next UN indices are read before this
         // chunk's terms, so their latency overlaps the gathers and the math
         int k = gl;
-        with_periodicity(g, [&](auto pxc, auto pyc) __attribute__((always_inline)) {
+        auto ex_loop = [&](auto pxc, auto pyc) __attribute__((always_inline)) {
             constexpr bool PX = decltype(pxc)::value, PY = decltype(pyc)::value;
             unsigned jn[UN];
             if (k + (UN - 1) * G < ecnt) {
@@ -747,7 +755,9 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
                     body((int)j[u], dx, dy, dx * dx + dy * dy, a[u].z, a[u].w, uv[u], f4[u]);
                 }
             }
-        });
+        };
+        if constexpr (SP) with_periodicity(g, ex_loop);
+        else ex_loop(std::true_type{}, std::true_type{});
         for (; k < ecnt; k += G) {
             const int js = ex.idx[(int64_t)k * ex.stride + s];
             const double4 a = pa[js];
@@ -837,7 +847,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
     const Guard gd{nullptr, 0};                                                              \
     const PassBParams P{sd.rho0, sd.cs, sd.nu, sd.alpha_e, sd.fx, sd.fy, sd.dt};             \
-    pass_b_body<T, false, RGB, (sizeof(T) == 4 ? PB_UNROLL : 4)>(                            \
+    pass_b_body<T, false, RGB, (sizeof(T) == 4 ? PB_UNROLL : 4), false>(                     \
         sd.g, batch_view(nv, sd, sid), 0, b, nl, ex, pa, puv, pf, nullptr, nullptr, P, dpdt,  \
         dudt, dvdt, gd, (int)(sd.off + sl), gl);
 
