@@ -844,7 +844,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     const int t = lb * 256 + threadIdx.x;                                                    \
     const int sl = t / RGB, gl = t % RGB;                                                    \
     if (sl >= sd.n) return;                                                                  \
-    const NbrList ex{nullptr, nullptr, EX_K, 0, nullptr};                                    \
+    /* a batch's lists are built with no skin: they are its exact rows (self  */            \
+    /* included, whose terms are zero), taken in chunks without the predicate */            \
+    const NbrList ex = nl;                                                                   \
     const Guard gd{nullptr, 0};                                                              \
     const PassBParams P{sd.rho0, sd.cs, sd.nu, sd.alpha_e, sd.fx, sd.fy, sd.dt};             \
     pass_b_body<T, false, RGB, (sizeof(T) == 4 ? PB_UNROLL : 4), false>(                     \
@@ -1083,6 +1085,12 @@ static int eval_T(sph_ctx* c, int n, const double* x, const double* y, double* u
     LAUNCHCHK(c, "pass_a");
     const int gb = sizeof(T) == 4 ? sc.b_lanes : RGB;
     const unsigned nbb = (unsigned)cdiv((int64_t)n * gb, 256);
+    // without exact rows from pass A (a lean workspace) a list built with no
+    // skin is itself the exact rows (self included, whose terms are zero):
+    // pass B takes it in chunks without the predicate, as the batched pass B
+    // does, so a lone simulation and a pool member add the same terms in
+    // the same order
+    if (!ex.idx && c->skin == 0.0 && nl.idx) ex = nl;
     PassBParams P{cf.rho0, cf.cs, cf.nu, cf.alpha_e, cf.body_force[0], cf.body_force[1], dt};
     prof_begin(c, SPH_PROF_PASS_B, &gd);
     if constexpr (sizeof(T) == 4) {
