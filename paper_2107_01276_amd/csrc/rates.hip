@@ -1343,21 +1343,33 @@ int step_run(sph_ctx* c, sph_particles* ps, double dt, int nsteps)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_count_pairs_b(Batch B, const T* __restrict__ nnb,
-                                                       unsigned long long* acc)
+__global__ __launch_bounds__(RS_THREADS) void k_count_pairs_b(Batch B, const T* __restrict__ nnb,
+                                                              unsigned long long* acc)
 {
-    __shared__ int part[4];
-    int lb;
-    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    // one block per sort tile (RS_TILE particles of one simulation), so that
+    // a simulation's counter takes one atomic per tile: the counters sit in
+    // device memory and atomics from every XCD on one address serialise
+    __shared__ int part[RS_THREADS / 64];
+    int t;
+    const int sid = batch_find(B, BM_TILE, blockIdx.x, &t);
     const SimDesc* d = B.sims + sid;
-    const int il = lb * 256 + threadIdx.x;
-    int v = il < d->n ? (int)nnb[d->off + il] - 1 : 0;
+    const int64_t beg = (int64_t)t * RS_TILE;
+    int v = 0;
+#pragma unroll
+    for (int k = 0; k < RS_ITEMS; ++k) {
+        const int64_t il = beg + (int64_t)k * RS_THREADS + threadIdx.x;
+        if (il < d->n) v += (int)nnb[d->off + il] - 1;
+    }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if (__lane_id() == 0) part[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0)
-        atomicAdd(acc + d->slot, (unsigned long long)((long long)part[0] + part[1] + part[2] + part[3]));
+    if (threadIdx.x == 0) {
+        long long tot = 0;
+#pragma unroll
+        for (int w = 0; w < RS_THREADS / 64; ++w) tot += part[w];
+        atomicAdd(acc + d->slot, (unsigned long long)tot);
+    }
 }
 
 // Predictor (eq. int-pre) and corrector (eq. int-cor) of the batch, each
@@ -1449,7 +1461,7 @@ static int batch_eval_T(hipStream_t st, const BatchBufs& b, const BatchLaunch& L
     hipLaunchKernelGGL(k_pass_b_b<T>, dim3((unsigned)L.nblk[BM_P128]), dim3(256), 0, st, L.B, nv, rb,
                        nl, (const double4*)b.pa, (const double2*)b.puv, (const T4*)b.pf, b.r_dpdt,
                        b.r_dudt, b.r_dvdt);
-    hipLaunchKernelGGL(k_count_pairs_b<T>, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
+    hipLaunchKernelGGL(k_count_pairs_b<T>, dim3((unsigned)L.nblk[BM_TILE]), dim3(RS_THREADS), 0, st, L.B,
                        (const T*)rb.nnb, b.pairs);
     return hipGetLastError() == hipSuccess ? SPH_OK : SPH_E_DEVICE;
 }
