@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=256)
     ap.add_argument("--serve-steps", type=int, default=1000)
     ap.add_argument("--serve-arena-gib", type=float, default=4.0)
+    ap.add_argument("--serve-skin", type=float, default=0.1,
+                    help="list skin of the served simulations (0: a list per evaluation)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the C1 latency and the 1.5e6 / 9.6e5 particle lines")
@@ -298,7 +300,7 @@ def serving_bench(SPH, W, args):
             st = W.tgv(req["side"], seed=req["seed"], re=req["re"])
             cfg = SPH.config_for(st["domain"], st["params"], float(st["h"].min()),
                                  float(st["h"].max()), precision=SPH.SPH_FP32,
-                                 mass_q=st["mass_q"], list_skin=0.0, lean=1, list_k=64)
+                                 mass_q=st["mass_q"], list_skin=args.serve_skin, lean=1, list_k=64)
             built[key] = (cfg, st, SPH.timestep(cfg))
         return built[key]
 
@@ -535,7 +537,7 @@ def main():
                 st = W.tgv(req["side"], seed=req["seed"], re=req["re"])
                 cfg = SPH.config_for(st["domain"], st["params"], float(st["h"].min()),
                                      float(st["h"].max()), precision=SPH.SPH_FP32,
-                                     mass_q=st["mass_q"], list_skin=0.0, lean=1, list_k=64)
+                                     mass_q=st["mass_q"], list_skin=args.serve_skin, lean=1, list_k=64)
                 built[key] = (cfg, st, SPH.timestep(cfg))
             return built[key]
 

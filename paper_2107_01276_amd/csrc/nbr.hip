@@ -951,24 +951,35 @@ __global__ __launch_bounds__(256) void k_keys_b(Batch B, const double* __restric
                                                 const double* __restrict__ y,
                                                 const double* __restrict__ h, uint64_t* keys,
                                                 int32_t* vals, unsigned long long* hmax,
-                                                int32_t* lcount)
+                                                int32_t* lcount, const int32_t* __restrict__ rebuild)
 {
     int lb;
     const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    if (!rebuild[sid]) return;  // the simulation keeps its structure
     const SimDesc& sd = batch_desc(B, sid);
     const int il = lb * 256 + threadIdx.x;
-    keys_body(sd.g, il < sd.n, (int)(sd.off + il), x, y, h, keys, vals, hmax + sid * SPH_MAXL,
-              lcount + sid * SPH_MAXL);
+    keys_body(sd.g, il < sd.n, (int)(sd.off + il), x, y, h, keys, vals,
+              hmax + (int64_t)sd.slot * SPH_MAXL, lcount + (int64_t)sd.slot * SPH_MAXL);
 }
 
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist_b(Batch B, const uint64_t* __restrict__ keys,
-                                                          int shift, uint32_t* hist)
+                                                          int shift, uint32_t* hist,
+                                                          const int32_t* __restrict__ rebuild)
 {
     int t;
     const int sid = batch_find(B, BM_TILE, blockIdx.x, &t);
     const SimDesc* d = B.sims + sid;
     const int64_t rem = d->n - (int64_t)t * RS_TILE;
     const int tn = (int)(rem < RS_TILE ? rem : RS_TILE);
+    if (!rebuild[sid]) {
+        // a kept simulation is not sorted, but its tiles still count their
+        // particles (all in digit 0): the scan over the whole batch then
+        // places the other simulations as when every one is sorted
+        uint32_t* hs = hist + d->hoff + t;
+        for (int dg = threadIdx.x; dg < RS_BINS; dg += RS_THREADS)
+            hs[(int64_t)dg * d->ntile] = dg == 0 ? (uint32_t)tn : 0u;
+        return;
+    }
     rs_hist_tile(keys, d->off + (int64_t)t * RS_TILE, tn, shift, hist + d->hoff + t, d->ntile);
 }
 
@@ -976,10 +987,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter_b(Batch B, const uint
                                                              const int32_t* __restrict__ vin,
                                                              uint64_t* __restrict__ kout,
                                                              int32_t* __restrict__ vout, int shift,
-                                                             const uint32_t* __restrict__ offs)
+                                                             const uint32_t* __restrict__ offs,
+                                                             const int32_t* __restrict__ rebuild)
 {
     int t;
     const int sid = batch_find(B, BM_TILE, blockIdx.x, &t);
+    if (!rebuild[sid]) return;
     const SimDesc* d = B.sims + sid;
     const int64_t rem = d->n - (int64_t)t * RS_TILE;
     const int tn = (int)(rem < RS_TILE ? rem : RS_TILE);
@@ -992,10 +1005,11 @@ __global__ __launch_bounds__(256) void k_tables_b(Batch B, const uint64_t* __res
                                                   const double* __restrict__ x,
                                                   const double* __restrict__ y,
                                                   const double* __restrict__ h, double4* xyh,
-                                                  int2* tab)
+                                                  int2* tab, const int32_t* __restrict__ rebuild)
 {
     int lb;
     const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    if (!rebuild[sid]) return;
     const SimDesc& sd = batch_desc(B, sid);
     const int il = lb * 256 + threadIdx.x;
     if (il >= sd.n) return;
@@ -1003,27 +1017,64 @@ __global__ __launch_bounds__(256) void k_tables_b(Batch B, const uint64_t* __res
                 nullptr, nullptr, nullptr, xyh, tab + sd.toff);
 }
 
-__global__ __launch_bounds__(256) void k_build_list_b(Batch B, NbrView nv0, NbrList nl, double sf)
+__global__ __launch_bounds__(256) void k_build_list_b(Batch B, NbrView nv0, NbrList nl,
+                                                      const int32_t* __restrict__ rebuild)
 {
     int lb;
     const int sid = batch_find(B, BM_P64, xcd_block(blockIdx.x, gridDim.x), &lb);
+    if (!rebuild[sid]) return;
     const SimDesc& sd = batch_desc(B, sid);
     const int t = lb * 256 + threadIdx.x;
     const int sl = t / LG, gl = t % LG;
     if (sl >= sd.n) return;
-    build_list_body<LG>(sd.g, batch_view(nv0, sd, sid), nl, (int)(sd.off + sl), gl, sf);
+    // every pair within (1 + skin) times the support, as a context's list
+    build_list_body<LG>(sd.g, batch_view(nv0, sd, sid), nl, (int)(sd.off + sl), gl, 1.0 + sd.skin);
+}
+
+// The cell tables, level maxima and counts of the simulations rebuilt in
+// this evaluation are cleared (blockIdx.y: the simulation).
+__global__ __launch_bounds__(256) void k_zero_build_b(Batch B, int2* tab, unsigned long long* hmax,
+                                                      int32_t* lcount, const int32_t* __restrict__ rebuild)
+{
+    const int sid = (int)blockIdx.y;
+    if (sid >= B.nsim || !rebuild[sid]) return;
+    const SimDesc& sd = batch_desc(B, sid);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sd.ntab;
+         i += (int64_t)gridDim.x * blockDim.x)
+        tab[sd.toff + i] = make_int2(0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < SPH_MAXL) {
+        hmax[(int64_t)sd.slot * SPH_MAXL + threadIdx.x] = 0ull;
+        lcount[(int64_t)sd.slot * SPH_MAXL + threadIdx.x] = 0;
+    }
+}
+
+// A rebuilt simulation's sorted keys and order, moved to the first buffer
+// when the passes ended in the second.
+__global__ __launch_bounds__(256) void k_keep_sorted_b(Batch B, const uint64_t* __restrict__ kin,
+                                                       const int32_t* __restrict__ vin, uint64_t* kout,
+                                                       int32_t* vout, const int32_t* __restrict__ rebuild)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    if (!rebuild[sid]) return;
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= sd.n) return;
+    const int64_t i = sd.off + il;
+    kout[i] = kin[i];
+    vout[i] = vin[i];
 }
 
 int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const double* x,
                 const double* y, const double* h, const uint64_t** keys, const int32_t** perm)
 {
+    // only the simulations whose rebuild flag is set (L.rebuild) are sorted,
+    // tabled and listed; the others keep their order, tables and list
     const int nsim = L.B.nsim;
-    const int64_t nl = (int64_t)nsim * SPH_MAXL;
-    const int64_t nz = L.tab_n > nl ? L.tab_n : nl;
-    hipLaunchKernelGGL(k_zero_build, dim3((unsigned)cdiv(nz, 256)), dim3(256), 0, st, b.tab, L.tab_n,
-                       b.hmax, b.lcount, (int)nl, (uint32_t*)nullptr, (int64_t)0);
+    hipLaunchKernelGGL(k_zero_build_b, dim3(64, (unsigned)nsim), dim3(256), 0, st, L.B, b.tab, b.hmax,
+                       b.lcount, (const int32_t*)L.rebuild);
     hipLaunchKernelGGL(k_keys_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B, x, y, h,
-                       b.keys_a, b.vals_a, b.hmax, b.lcount);
+                       b.keys_a, b.vals_a, b.hmax, b.lcount, (const int32_t*)L.rebuild);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return SPH_E_DEVICE;
     uint64_t *ka = b.keys_a, *kb = b.keys_b;
@@ -1031,21 +1082,31 @@ int batch_build(hipStream_t st, const BatchBufs& b, const BatchLaunch& L, const 
     for (int p = 0; p < L.npass; ++p) {
         const int shift = RS_BITS * p;
         hipLaunchKernelGGL(k_rs_hist_b, dim3((unsigned)L.nblk[BM_TILE]), dim3(RS_THREADS), 0, st, L.B,
-                           (const uint64_t*)ka, shift, b.hist);
+                           (const uint64_t*)ka, shift, b.hist, (const int32_t*)L.rebuild);
         e = scan_rec_s<uint32_t>(st, b.hist, b.hist, L.hist_n, L.hist_n, b.scan_tmp);
         if (e != hipSuccess) return SPH_E_DEVICE;
         hipLaunchKernelGGL(k_rs_scatter_b, dim3((unsigned)L.nblk[BM_TILE]), dim3(RS_THREADS), 0, st,
                            L.B, (const uint64_t*)ka, (const int32_t*)va, kb, vb, shift,
-                           (const uint32_t*)b.hist);
+                           (const uint32_t*)b.hist, (const int32_t*)L.rebuild);
         uint64_t* tk = ka; ka = kb; kb = tk;
         int32_t* tv = va; va = vb; vb = tv;
     }
+    if (ka != b.keys_a) {
+        // an odd number of passes: the sorted keys go back to the first
+        // buffer, where a kept simulation's keys stay between builds
+        hipLaunchKernelGGL(k_keep_sorted_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
+                           (const uint64_t*)ka, (const int32_t*)va, b.keys_a, b.vals_a,
+                           (const int32_t*)L.rebuild);
+        ka = b.keys_a;
+        va = b.vals_a;
+    }
     hipLaunchKernelGGL(k_tables_b, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
-                       (const uint64_t*)ka, (const int32_t*)va, x, y, h, b.xyh, b.tab);
+                       (const uint64_t*)ka, (const int32_t*)va, x, y, h, b.xyh, b.tab,
+                       (const int32_t*)L.rebuild);
     const NbrView nv{nullptr, nullptr, nullptr, b.xyh, va, ka, b.tab, b.hmax, b.lcount};
     const NbrList nlst{b.nl_idx, b.nl_cnt, b.nl_k, (int)b.stride, b.list_flag};
     hipLaunchKernelGGL(k_build_list_b, dim3((unsigned)L.nblk[BM_P64]), dim3(256), 0, st, L.B, nv,
-                       nlst, 1.0);
+                       nlst, (const int32_t*)L.rebuild);
     e = hipGetLastError();
     if (e != hipSuccess) return SPH_E_DEVICE;
     *keys = ka;

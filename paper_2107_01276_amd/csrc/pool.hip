@@ -109,7 +109,8 @@ size_t slot_bytes()
            + 7 * 8              // m, rho, beta, dpav, dxs, dys, nnb (pair precision, 8-byte slots)
            + 4 * POOL_LIST_K + 4  // list and its counts
            + 5 * 8 + 5 * 8      // rates, half-step state
-           + 2 * 4;             // digit histogram (RS_BINS / RS_TILE entries per particle)
+           + 2 * 4              // digit histogram (RS_BINS / RS_TILE entries per particle)
+           + 3 * 8;             // positions and h the list was built at
 }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -125,6 +126,7 @@ struct sph_pool {
     BatchBufs buf;
     SimDesc* d_desc[2];
     int32_t* d_bstart[2];
+    int32_t* d_rebuild[2];
     // pinned staging of the descriptors (two alternating buffers, each
     // reused once its last upload has run)
     SimDesc* h_desc[2];
@@ -184,6 +186,7 @@ static bool pool_carve(sph_pool* p)
     for (int k = 0; k < 2; ++k) {
         p->d_desc[k] = (SimDesc*)take(sizeof(SimDesc) * (size_t)S);
         p->d_bstart[k] = (int32_t*)take(4 * (size_t)BM_COUNT * (S + 1));
+        p->d_rebuild[k] = (int32_t*)take(4 * (size_t)S);
     }
     BatchBufs& b = p->buf;
     b.pairs = (unsigned long long*)take(8 * (size_t)S);
@@ -225,6 +228,9 @@ static bool pool_carve(sph_pool* p)
     double** r[10] = {&b.r_dpdt, &b.r_dudt, &b.r_dvdt, &b.r_dxs, &b.r_dys,
                       &b.xh,     &b.yh,     &b.uh,     &b.vh,    &b.ph};
     for (int k = 0; k < 10; ++k) *r[k] = (double*)take(8 * N);
+    b.xref = (double*)take(8 * N);
+    b.yref = (double*)take(8 * N);
+    b.href = (double*)take(8 * N);
     // digit histogram: one tile per RS_TILE particles plus one per simulation
     const int64_t hist_n = (int64_t)RS_BINS * (cdiv(n, RS_TILE) + S);
     b.hist = (uint32_t*)take(4 * (size_t)hist_n);
@@ -251,6 +257,14 @@ __global__ void k_pool_zero_u64(unsigned long long* a, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) a[i] = 0ull;
+}
+
+// h the list was built at, set to -1 for an admitted simulation: its first
+// evaluation builds its structure and list
+__global__ void k_pool_fill_f64(double* a, int64_t n, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
 }
 
 extern "C" int sph_pool_create(void* arena, size_t arena_bytes, int32_t max_sims, sph_pool** out)
@@ -363,6 +377,8 @@ extern "C" int sph_pool_admit(sph_pool* p, const sph_config* cfg, const sph_part
         e = hipMemcpyAsync(b.mq + s.off, init->mq, 8 * N, hipMemcpyDeviceToDevice, p->stream);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_pool_zero_u64, dim3(1), dim3(64), 0, p->stream, b.pairs + s.slot, 1);
+        hipLaunchKernelGGL(k_pool_fill_f64, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, p->stream,
+                           b.href + s.off, n, -1.0);
         e = hipGetLastError();
     }
     if (e != hipSuccess) {
@@ -426,6 +442,8 @@ static int pool_upload(sph_pool* p)
             d.fx = s.cfg.body_force[0];
             d.fy = s.cfg.body_force[1];
             d.mass_q = s.cfg.mass_q;
+            d.skin = s.cfg.list_skin;
+            d.ntab = s.ntab;
             hoff += (int64_t)RS_BINS * d.ntile;
             packed += s.n;
             for (int m = 0; m < BM_COUNT; ++m) {
@@ -443,6 +461,7 @@ static int pool_upload(sph_pool* p)
         L.npass = (maxbits + RS_BITS - 1) / RS_BITS;
         L.B.sims = p->d_desc[grp];
         L.B.bstart = p->d_bstart[grp];
+        L.rebuild = p->d_rebuild[grp];
         hipError_t e = hipMemcpyAsync(p->d_desc[grp], hd, sizeof(SimDesc) * (size_t)ns,
                                       hipMemcpyHostToDevice, p->stream);
         if (e == hipSuccess)

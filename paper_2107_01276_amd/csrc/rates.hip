@@ -192,7 +192,8 @@ __global__ __launch_bounds__(256) void k_gather_state_b(Batch B, const int32_t* 
                                                         const double* __restrict__ v,
                                                         const double* __restrict__ p,
                                                         const int64_t* __restrict__ mq,
-                                                        double4* pa, double2* puv, T* ms)
+                                                        double4* pa, double2* puv, T* ms,
+                                                        double4* xyh)
 {
     int lb;
     const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
@@ -201,9 +202,63 @@ __global__ __launch_bounds__(256) void k_gather_state_b(Batch B, const int32_t* 
     if (il >= d->n) return;
     const int s = (int)(d->off + il);
     const int i = perm[s];
-    pa[s] = make_double4(x[i], y[i], h[i], p[i]);
+    const double xi = x[i], yi = y[i], hi = h[i];
+    pa[s] = make_double4(xi, yi, hi, p[i]);
     puv[s] = make_double2(u[i], v[i]);
     ms[s] = (T)((double)mq[i] * d->mass_q);
+    // the sorted records of the cell walks, current also for a simulation
+    // that kept its structure
+    xyh[s] = make_double4(xi, yi, hi, 0.0);
+}
+
+// Rebuild flags of an evaluation.  A simulation without a list skin
+// rebuilds every time; one with a skin when some particle moved by 1.5 skin
+// h or more since its list was built, or changed h (the test a context
+// applies to its own list; the flags of the first evaluation after
+// admission are set by h = -1 at build).
+__global__ void k_rebuild_init_b(Batch B, int32_t* rebuild)
+{
+    const int sid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sid < B.nsim) rebuild[sid] = B.sims[sid].skin > 0.0 ? 0 : 1;
+}
+
+__global__ __launch_bounds__(256) void k_list_check_b(Batch B, const double* __restrict__ x,
+                                                      const double* __restrict__ y,
+                                                      const double* __restrict__ h,
+                                                      const double* __restrict__ xref,
+                                                      const double* __restrict__ yref,
+                                                      const double* __restrict__ href,
+                                                      int32_t* rebuild)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (!(sd.skin > 0.0) || il >= sd.n) return;
+    const int64_t i = sd.off + il;
+    const double dx = mi_axis(sd.g, 0, x[i] - xref[i]);
+    const double dy = mi_axis(sd.g, 1, y[i] - yref[i]);
+    const double r = (1.5 * sd.skin) * href[i];
+    if (!(dx * dx + dy * dy < r * r) || h[i] != href[i]) rebuild[sid] = 1;
+}
+
+// Positions and h a rebuilt simulation's list was built at.
+__global__ __launch_bounds__(256) void k_list_ref_b(Batch B, const double* __restrict__ x,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ h, double* xref,
+                                                    double* yref, double* href,
+                                                    const int32_t* __restrict__ rebuild)
+{
+    int lb;
+    const int sid = batch_find(B, BM_P256, blockIdx.x, &lb);
+    if (!rebuild[sid]) return;
+    const SimDesc& sd = batch_desc(B, sid);
+    const int il = lb * 256 + threadIdx.x;
+    if (il >= sd.n) return;
+    const int64_t i = sd.off + il;
+    xref[i] = x[i];
+    yref[i] = y[i];
+    href[i] = h[i];
 }
 
 // Inlet/outlet rule of the boundary pass: mode, reference state, rho0 c.
@@ -766,8 +821,11 @@ __device__ __forceinline__ void pass_b_body(PASS_B_PARAMS_(const Grid&, T), int 
             body_ld(js, dx, dy, dx * dx + dy * dy, a.z, a.w);
         }
     } else if (cnt <= nl.K) {
+        // a list with a skin, one entry per lane at a time (a context's pass B
+        // and the pool's add the same terms in the same order with this loop)
         const double ri3 = 3.0 * hi, ri2 = ri3 * ri3;
-        for (int k = gl; k < cnt; k += G) {
+        int k = gl;
+        for (; k < cnt; k += G) {
             const int js = nl.idx[(int64_t)k * nl.stride + s];
             const double4 a = pa[js];
             const double dx = mi_axis(g, 0, xi - a.x);
@@ -844,9 +902,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     const int t = lb * 256 + threadIdx.x;                                                    \
     const int sl = t / RGB, gl = t % RGB;                                                    \
     if (sl >= sd.n) return;                                                                  \
-    /* a batch's lists are built with no skin: they are its exact rows (self  */            \
+    /* a list built with no skin is the simulation's exact rows (self        */            \
     /* included, whose terms are zero), taken in chunks without the predicate */            \
-    const NbrList ex = nl;                                                                   \
+    const NbrList ex = sd.skin == 0.0 ? nl : NbrList{nullptr, nullptr, EX_K, 0, nullptr};   \
     const Guard gd{nullptr, 0};                                                              \
     const PassBParams P{sd.rho0, sd.cs, sd.nu, sd.alpha_e, sd.fx, sd.fy, sd.dt};             \
     pass_b_body<T, false, RGB, (sizeof(T) == 4 ? PB_UNROLL : 4), false>(                     \
@@ -1438,8 +1496,15 @@ static int batch_eval_T(hipStream_t st, const BatchBufs& b, const BatchLaunch& L
 {
     const uint64_t* keys = nullptr;
     const int32_t* perm = nullptr;
+    const unsigned nb = (unsigned)L.nblk[BM_P256];
+    hipLaunchKernelGGL(k_rebuild_init_b, dim3((unsigned)cdiv(L.B.nsim, 256)), dim3(256), 0, st, L.B,
+                       L.rebuild);
+    hipLaunchKernelGGL(k_list_check_b, dim3(nb), dim3(256), 0, st, L.B, x, y, (const double*)b.h,
+                       (const double*)b.xref, (const double*)b.yref, (const double*)b.href, L.rebuild);
     int rc = batch_build(st, b, L, x, y, b.h, &keys, &perm);
     if (rc) return rc;
+    hipLaunchKernelGGL(k_list_ref_b, dim3(nb), dim3(256), 0, st, L.B, x, y, (const double*)b.h, b.xref,
+                       b.yref, b.href, (const int32_t*)L.rebuild);
     RatesBufs<T> rb;
     rb.m = (T*)b.m;
     rb.rho = (T*)b.brho;
@@ -1452,7 +1517,7 @@ static int batch_eval_T(hipStream_t st, const BatchBufs& b, const BatchLaunch& L
     rb.ps = nullptr;
     using T4 = typename Vec4<T>::type;
     hipLaunchKernelGGL(k_gather_state_b<T>, dim3((unsigned)L.nblk[BM_P256]), dim3(256), 0, st, L.B,
-                       perm, x, y, b.h, u, v, p, (const int64_t*)b.mq, b.pa, b.puv, rb.m);
+                       perm, x, y, b.h, u, v, p, (const int64_t*)b.mq, b.pa, b.puv, rb.m, b.xyh);
     const NbrView nv{nullptr, nullptr, nullptr, b.xyh, perm, keys, b.tab, b.hmax, b.lcount};
     const NbrList nl{b.nl_idx, b.nl_cnt, b.nl_k, (int)b.stride, b.list_flag};
     const PassAOut aout{b.rho, nullptr, nullptr, nullptr, nullptr, nullptr};

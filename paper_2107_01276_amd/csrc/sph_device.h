@@ -693,11 +693,14 @@ __device__ __forceinline__ const SimDesc& batch_desc(const Batch& B, int s)
 
 // The neighbour view of simulation s of a batch: its own tables and
 // per-level maxima and counts; the sorted arrays are the batch's.
-__device__ __forceinline__ NbrView batch_view(NbrView nv, const SimDesc& sd, int s)
+// A simulation's level maxima and counts sit at its counter slot, which it
+// keeps while resident (its place in the batch changes with the resident
+// set; a simulation that keeps its structure keeps them).
+__device__ __forceinline__ NbrView batch_view(NbrView nv, const SimDesc& sd, int)
 {
     nv.tab += sd.toff;
-    nv.hmax_bits += s * SPH_MAXL;
-    nv.lcount += s * SPH_MAXL;
+    nv.hmax_bits += (int64_t)sd.slot * SPH_MAXL;
+    nv.lcount += (int64_t)sd.slot * SPH_MAXL;
     return nv;
 }
 

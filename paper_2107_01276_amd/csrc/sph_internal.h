@@ -82,6 +82,8 @@ struct SimDesc {
     int32_t ntile;      // radix-sort tiles (RS_TILE particles each)
     int32_t slot;       // its pair counter
     double dt, rho0, cs, nu, alpha_e, fx, fy, mass_q;
+    double skin;        // list skin (0: a list per evaluation)
+    int64_t ntab;       // entries of its cell tables
 };
 // Block maps: particles per block of each launch shape.
 enum { BM_P256 = 0, BM_P64 = 1, BM_P128 = 2, BM_TILE = 3, BM_COUNT = 4 };
@@ -244,6 +246,7 @@ struct BatchBufs {
     double *r_dpdt, *r_dudt, *r_dvdt, *r_dxs, *r_dys;
     double *xh, *yh, *uh, *vh, *ph;
     unsigned long long* pairs;            // per counter slot
+    double *xref, *yref, *href;           // positions and h each list was built at
 };
 struct BatchLaunch {
     Batch B;
@@ -252,6 +255,8 @@ struct BatchLaunch {
     int64_t tab_n;            // cell-table entries to clear (the used extent)
     int32_t npass;            // radix passes (the widest key of the batch)
     int32_t precision;
+    int32_t* rebuild;         // per simulation of the batch: its structure and
+                              // list are rebuilt in this evaluation
 };
 // One predict-evaluate-correct step of every simulation of the batch.
 int batch_step(hipStream_t st, const BatchBufs& b, const BatchLaunch& L);

@@ -20,20 +20,20 @@ pytestmark = pytest.mark.gpu
 KEYS = ("x", "y", "u", "v", "p", "rho")
 
 
-def _tgv(P, nx, seed, re, prec):
+def _tgv(P, nx, seed, re, prec, skin=0.0):
     s = W.tgv(nx, seed=seed, re=re)
     cfg = P.config_for(s["domain"], s["params"], float(s["h"].min()), float(s["h"].max()),
-                       precision=prec, mass_q=s["mass_q"], list_skin=0.0, lean=1, list_k=64)
+                       precision=prec, mass_q=s["mass_q"], list_skin=skin, lean=1, list_k=64)
     return s, cfg
 
 
-def _varh(P, prec):
+def _varh(P, prec, skin=0.0):
     """An open box with a 1:4 smoothing-length range (several levels)."""
     s = with_fields(W.random_varh(1800, seed=41, h_lo=0.012, ratio=4, periodic=(False, False)),
                     seed=41)
     s["dt"] = 1e-4
     cfg = P.config_for(s["domain"], s["params"], float(s["h"].min()), float(s["h"].max()),
-                       precision=prec, mass_q=s["mass_q"], list_skin=0.0, lean=1, list_k=64)
+                       precision=prec, mass_q=s["mass_q"], list_skin=skin, lean=1, list_k=64)
     return s, cfg
 
 
@@ -50,14 +50,20 @@ def _eager(P, s, cfg, nsteps):
     return E.numpy()
 
 
-def test_alone_vs_mix_vs_eager():
+@pytest.mark.parametrize("skin", [0.0, 0.05])
+def test_alone_vs_mix_vs_eager(skin):
+    """With no list skin every evaluation rebuilds every simulation's list;
+    with a skin each simulation keeps its list until one of its particles
+    moved too far (rebuilds within the first steps here), whatever the other
+    residents do: either way a simulation's state is the same bits alone,
+    in the mix (across a change of the resident set) and in a context."""
     P = lib()
-    s, cfg = _tgv(P, 40, 31, 100.0, P.SPH_FP32)
+    s, cfg = _tgv(P, 40, 31, 100.0, P.SPH_FP32, skin)
     n = s["x"].size
-    v, vcfg = _varh(P, P.SPH_FP64)
-    others = [_tgv(P, nx, sd, re, pr) for nx, sd, re, pr in
+    v, vcfg = _varh(P, P.SPH_FP64, skin)
+    others = [_tgv(P, nx, sd, re, pr, skin) for nx, sd, re, pr in
               ((70, 32, 400.0, P.SPH_FP32), (25, 33, 900.0, P.SPH_FP64), (55, 34, 250.0, P.SPH_FP32))]
-    print(f"[pool] alone vs mix n={n}", flush=True)
+    print(f"[pool] alone vs mix n={n} skin={skin}", flush=True)
     alone = P.Pool(1 << 28, max_sims=8)
     a = alone.admit(cfg, P.Particles.from_arrays(s), dt_of(s))
     mix = P.Pool(1 << 28, max_sims=8)
