@@ -551,16 +551,26 @@ __global__ __launch_bounds__(256) void k_shift_filter(Grid g, int n, const int32
     const double xi = ai.x, yi = ai.y, hi = ai.z;
     const int64_t b0 = rp[i], e = rp[i + 1];
     int cnt = 0;
+    // the next chunk's column entries are read before this chunk's records
+    // are tested, so the two loads of a chunk overlap the previous chunk
+    int jn[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t k = b0 + FG * u + gl;
+        jn[u] = k < e ? col[k] : i;
+    }
     for (int64_t base = b0; base < e; base += 4 * FG) {
         int j[4];
         double4 aj[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int64_t k = base + FG * u + gl;
-            j[u] = k < e ? col[k] : i;
-        }
+        for (int u = 0; u < 4; ++u) j[u] = jn[u];
 #pragma unroll
         for (int u = 0; u < 4; ++u) aj[u] = A[j[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = base + 4 * FG + FG * u + gl;
+            jn[u] = k < e ? col[k] : i;
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double dx = mi_axis(g, 0, xi - aj[u].x);
@@ -812,13 +822,22 @@ __global__ __launch_bounds__(256) void k_hupdate(Grid g, int n, const int64_t* _
     const double xi = ai.x, yi = ai.y, hi = ai.z;
     double sm = 0.0;
     int64_t cnt = 0;
-    const int64_t e = rp[i + 1];
-    for (int64_t base = rp[i]; base < e; base += G * U) {
+    const int64_t b0 = rp[i], e = rp[i + 1];
+    // the next chunk's column entries are read before this chunk's records
+    int jn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = b0 + u * G + gl;
+        jn[u] = k < e ? col[k] : i;
+    }
+    for (int64_t base = b0; base < e; base += G * U) {
         double4 aj[U];
 #pragma unroll
+        for (int u = 0; u < U; ++u) aj[u] = A[jn[u]];
+#pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = base + u * G + gl;
-            aj[u] = A[k < e ? col[k] : i];
+            const int64_t k = base + G * U + u * G + gl;
+            jn[u] = k < e ? col[k] : i;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
