@@ -418,7 +418,7 @@ size_t sph_pool_footprint(const sph_config *cfg, int64_t n);
 /* arena: device memory (256-byte aligned, at least 1 MiB) owned by the
  * caller, outliving the pool; max_sims in [1, 1024] simulations resident at
  * once.  About 1/16 of the arena holds cell tables and the rest particle
- * slots of about 600 bytes each.  Errors: SPH_E_INVAL, SPH_E_NOMEM (arena
+ * slots of about 630 bytes each.  Errors: SPH_E_INVAL, SPH_E_NOMEM (arena
  * too small for max_sims), SPH_E_DEVICE. */
 int sph_pool_create(void *arena, size_t arena_bytes, int32_t max_sims, sph_pool **out);
 void sph_pool_destroy(sph_pool *pool);
@@ -431,7 +431,11 @@ const char *sph_pool_last_error(const sph_pool *pool);
  * the call; init's arrays must stay unchanged until the next sph_pool_step
  * returns.  SPH_E_AGAIN (nothing changed) when no free range holds the
  * particles or the cell tables, or max_sims are resident.  Writes the
- * simulation's id. */
+ * simulation's id.  cfg->list_skin as in a context: 0 builds the
+ * simulation's neighbour list at every evaluation; a skin keeps its sorted
+ * order and list until one of its particles moved by 1.5 skin h (checked on
+ * the device at every evaluation), independently of the other residents,
+ * so its states are the bits a lean context with that configuration gives. */
 int sph_pool_admit(sph_pool *pool, const sph_config *cfg, const sph_particles *init, double dt,
                    void *stream, int32_t *sim_id);
 

@@ -22,7 +22,7 @@
 
 #include "sph_internal.h"
 
-#define POOL_LIST_K 64          // columns of the rate passes' list (rows are exact)
+#define POOL_LIST_K 64          // columns of the rate passes' list (a longer row is walked again)
 #define POOL_MAX_SIMS_CAP 1024  // simulations resident at once, at most
 
 namespace {
