@@ -318,6 +318,7 @@ def serving_bench(SPH, W, args):
     res["arrival_rate_per_s"] = rate
     res["particles_total"] = int(sum(make(r)[1]["x"].size for r in reqs))
     res["saturated"] = sat
+    res["list_skin"] = args.serve_skin
     return res
 
 
