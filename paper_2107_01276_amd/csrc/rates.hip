@@ -14,11 +14,10 @@
 //
 // Pair arithmetic is templated on T (float or double).  Position, velocity
 // and pressure differences are always formed in double and then converted.
-// In float every pair sum is compensated: Kahan for the density and beta
-// sums of pass A (terms of one sign), Neumaier for the average pressure and
-// the shift in pass A and for all four sums of pass B (divergence, EDAC
-// diffusion, pressure gradient, viscous term).  The neighbour predicate is
-// always the double-precision one.
+// In float every pair sum is Kahan-compensated: density, beta, average
+// pressure and shift in pass A; divergence, EDAC diffusion, pressure
+// gradient and viscous term in pass B.  The neighbour predicate is always
+// the double-precision one.
 #include <math.h>
 
 #include "sph_device.h"
@@ -72,9 +71,8 @@
 // (the neighbour predicate, outside it, stays uncontracted).
 #define RATES_FP_CONTRACT _Pragma("clang fp contract(fast)")
 
-// The spline and its derivative for the rate passes.  In double the
-// branch-free form (every bracket clamped at zero) is faster; in float the
-// branches that skip vanished brackets are.
+// The spline and its derivative for the rate passes, in the branch-free
+// form (every bracket clamped at zero).
 template <typename T>
 __device__ __forceinline__ void rate_kern(T q, T& f, T& fp)
 {

@@ -58,30 +58,10 @@ template <typename T> __device__ __forceinline__ T fsqrt(T x);
 template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
 
-// Neumaier-compensated sum (FP32 path); plain sum in double.
-template <typename T>
-struct CSum {
-    T s, c;
-    __device__ __forceinline__ CSum() : s(T(0)), c(T(0)) {}
-    __device__ __forceinline__ void add(T x)
-    {
-        T t = s + x;
-        if (fabs(s) >= fabs(x)) c += (s - t) + x;
-        else c += (x - t) + s;
-        s = t;
-    }
-    __device__ __forceinline__ T get() const { return s + c; }
-    // adds the sum held by lane (this lane ^ o) of the wave
-    __device__ __forceinline__ void merge_xor(int o)
-    {
-        const T so = __shfl_xor(s, o, 64), co = __shfl_xor(c, o, 64);
-        add(so);
-        c += co;
-    }
-};
-// Kahan-compensated sum (FP32 path), for the density sums, whose terms
-// share one sign: the running correction c (the low-order part lost so far,
-// negated) is fed back into the next term; plain sum in double.
+// Kahan-compensated sum (FP32 path): the running correction c (the
+// low-order part lost so far, negated) is fed back into the next term; the
+// error stays within about 2 eps of the sum of the terms' magnitudes.  Plain
+// sum in double.
 template <typename T>
 struct KSum {
     T s, c;
@@ -106,15 +86,6 @@ template <>
 struct KSum<double> {
     double s;
     __device__ __forceinline__ KSum() : s(0.0) {}
-    __device__ __forceinline__ void add(double x) { s += x; }
-    __device__ __forceinline__ double get() const { return s; }
-    __device__ __forceinline__ void merge_xor(int o) { s += __shfl_xor(s, o, 64); }
-};
-
-template <>
-struct CSum<double> {
-    double s;
-    __device__ __forceinline__ CSum() : s(0.0) {}
     __device__ __forceinline__ void add(double x) { s += x; }
     __device__ __forceinline__ double get() const { return s; }
     __device__ __forceinline__ void merge_xor(int o) { s += __shfl_xor(s, o, 64); }
