@@ -67,7 +67,14 @@ __global__ __launch_bounds__(256) void k_flag_rank(int n, const int32_t* __restr
     if (i < n) rank[i] = off + __popcll(b & lt);
 }
 
-static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, int32_t* total)
+// `before_wait` enqueues work that needs the ranks but not the total, so
+// that the device has it queued while the host waits for the total.
+struct NoWork {
+    void operator()() const {}
+};
+template <class F = NoWork>
+static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, int32_t* total,
+                         F&& before_wait = F{})
 {
     Work& w = c->w;
     *total = 0;
@@ -79,6 +86,8 @@ static int compact_ranks(sph_ctx* c, int n, const int32_t* flag, int32_t* rank, 
     if (rc) return rc;
     hipLaunchKernelGGL(k_flag_rank, dim3(nb), dim3(256), 0, c->stream, n, flag, w.idx_b, rank);
     LAUNCHCHK(c, "flag_rank");
+    before_wait();
+    LAUNCHCHK(c, "before_wait");
     const Readback rb{total, w.idx_b + nb, 4};
     return readback(c, &rb, 1);
 }
@@ -1031,12 +1040,13 @@ int adapt_run(sph_ctx* c, sph_particles* ps, const sph_background* bg, sph_adapt
         LAUNCHCHK(c, "merge_closest");
         // number of pairs = number of deleted slots
         int32_t nkeep = 0;
-        rc = compact_ranks(c, n, w.flag, w.idx_a, &nkeep);
+        // the merged state is written while the host waits for the count
+        rc = compact_ranks(c, n, w.flag, w.idx_a, &nkeep, [&] {
+            hipLaunchKernelGGL(k_merge_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, d,
+                               cur, w.flag, w.idx_a, cf.mass_q);
+        });
         if (rc) return rc;
         map->n_merged[it] = n - nkeep;
-        hipLaunchKernelGGL(k_merge_apply, dim3(nb), dim3(256), 0, c->stream, c->grid, n, s, d,
-                           cur, w.flag, w.idx_a, cf.mass_q);
-        LAUNCHCHK(c, "merge_apply");
         rc = copy_state(c, d, s, nkeep);
         if (rc) return rc;
         nprev = n;
