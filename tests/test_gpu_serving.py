@@ -100,18 +100,19 @@ def test_alone_vs_mix_vs_eager(skin):
     mix.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_pool_follows_oracle(prec):
+@pytest.mark.parametrize("prec,skin", [("fp64", 0.0), ("fp32", 0.0), ("fp64", 0.05), ("fp32", 0.05)])
+def test_pool_follows_oracle(prec, skin):
     """Ten pool steps of a periodic Taylor-Green vortex (alone, and beside
     another simulation) against the oracle's trajectory, per particle:
     positions (minimum image) and u, v, p, rho relative to their largest
     magnitude.  FP64 within 1e-12, FP32 within 2e-6 (the FP32 rates are
     within about 1e-6 of the FP64 ones per particle, integrated over ten
-    steps of dt = 4.5e-4)."""
+    steps of dt = 4.5e-4).  With a list skin the simulation keeps its list
+    across steps and rebuilds it when its particles moved too far."""
     P = lib()
     pr = P.SPH_FP64 if prec == "fp64" else P.SPH_FP32
-    s, cfg = _tgv(P, 30, 35, 100.0, pr)
-    o2, c2 = _tgv(P, 45, 36, 600.0, P.SPH_FP32)
+    s, cfg = _tgv(P, 30, 35, 100.0, pr, skin)
+    o2, c2 = _tgv(P, 45, 36, 600.0, P.SPH_FP32, skin)
     pool = P.Pool(1 << 27, max_sims=4)
     other = pool.admit(c2, P.Particles.from_arrays(o2), dt_of(o2))
     sid = pool.admit(cfg, P.Particles.from_arrays(s), dt_of(s))
@@ -127,7 +128,7 @@ def test_pool_follows_oracle(prec):
         errs[k] = float(np.abs(d).max() / np.sqrt(1.0 / s["x"].size))
     for k in ("u", "v", "p", "rho"):
         errs[k] = float(np.abs(g[k] - o[k]).max() / np.abs(o[k]).max())
-    print(f"[pool-oracle] {prec} {errs}", flush=True)
+    print(f"[pool-oracle] {prec} skin={skin} {errs}", flush=True)
     for k, e in errs.items():
         assert e < tol, (k, e)
     pool.close()
