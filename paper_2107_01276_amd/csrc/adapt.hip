@@ -1381,17 +1381,19 @@ struct FSum {
 #define BG_G 4
 
 // Sorted copies for the background sweeps, so that a cell run's records are
-// consecutive: ds_s[sp] = ds[perm[sp]], m_s[sp] = mq[perm[sp]] q.
+// consecutive: ds_s[sp] = ds[perm[sp]], m_s[sp] = (mq[perm[sp]] q) / rho0 (the
+// volume the shifting term takes, divided once per particle: the same
+// correctly rounded quotient as per pair).
 __global__ __launch_bounds__(256) void k_bg_pack(int nb, const int32_t* __restrict__ perm,
                                                  const double* __restrict__ ds,
                                                  const int64_t* __restrict__ mq, double q,
-                                                 double* ds_s, double* m_s)
+                                                 double rho0, double* ds_s, double* m_s)
 {
     const int sp = blockIdx.x * blockDim.x + threadIdx.x;
     if (sp >= nb) return;
     const int b = perm[sp];
     if (ds_s) ds_s[sp] = ds[b];
-    if (m_s) m_s[sp] = (double)mq[b] * q;
+    if (m_s) m_s[sp] = ((double)mq[b] * q) / rho0;
 }
 
 // Size grading of background particle b (sorted position sp, lane gl of its
@@ -1414,10 +1416,9 @@ __device__ __forceinline__ bool bg_grade_row(const Grid& g, const NbrView& nv, i
     double mn = HUGE_VAL, mx = -HUGE_VAL;
     Acc sl;
     int cnt = 0;
-    group_walk<G>(g, nv, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]), gl,
-                  [&](int js, bool pass, double, double, double, double) {
+    group_walk_x<G>(g, nv, ds_s, nv.xs[sp], nv.ys[sp], nv.hs[sp], key_level(g, nv.keys[sp]), gl,
+                    [&](int, bool pass, double, double, double, double, double v) {
                       if (!pass) return;
-                      const double v = ds_s[js];
                       mn = fmin(mn, v);
                       mx = fmax(mx, v);
                       sl.add(log(v));
@@ -1539,8 +1540,9 @@ __device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, 
     const double fxi = kern_f<double>(SPH_XI);
     Acc sh, sx, sy;
     int cnt = 0;
-    group_walk<G>(g, nv, xb, yb, hb, key_level(g, nv.keys[sp]), gl,
-                  [&](int js, bool pass, double dx, double dy, double r2, double hj) {
+    group_walk_x<G>(g, nv, m_s, xb, yb, hb, key_level(g, nv.keys[sp]), gl,
+                    [&](int, bool pass, double dx, double dy, double r2, double hj, double vj) {
+                      // vj = m_j / rho0
                       if (!pass) return;
                       ++cnt;
                       sh.add(hj);
@@ -1548,8 +1550,7 @@ __device__ __forceinline__ bool bg_smooth_row(const Grid& g, const NbrView& nv, 
                       if (r <= 0.0) return;
                       const double hij = 0.5 * (hb + hj);
                       const double wr = kern_f<double>(r / hij) / fxi;
-                      const double mj = m_s[js];
-                      const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+                      const double coef = vj * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
                       const double t = coef * (kern_dw64(r, hij) / r);
                       sx.add(t * dx);
                       sy.add(t * dy);
@@ -1624,8 +1625,8 @@ __global__ __launch_bounds__(256) void k_bg_smooth_exact(Grid g, NbrView nv, int
             if (r <= 0.0) return;
             const double hij = 0.5 * (hb + hj);
             const double wr = kern_f<double>(r / hij) / fxi;
-            const double mj = m_s[js];
-            const double coef = (mj / rho0) * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
+            const double vj = m_s[js];  // m_j / rho0
+            const double coef = vj * (1.0 + 0.24 * ((wr * wr) * (wr * wr)));
             const double t = coef * (kern_dw64(r, hij) / r);
             acc.add(t * (which == 1 ? dx : dy));
         });
@@ -1684,7 +1685,7 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
         if (rc) return rc;
         NbrView nv = nbr_view(c);
         hipLaunchKernelGGL(k_bg_pack, dim3(nbk), dim3(256), 0, c->stream, nb, nv.perm, (const double*)bg->ds,
-                           (const int64_t*)nullptr, 0.0, w.tmp_d[3], (double*)nullptr);
+                           (const int64_t*)nullptr, 0.0, cf.rho0, w.tmp_d[3], (double*)nullptr);
         hipLaunchKernelGGL(k_bg_grade, dim3((unsigned)cdiv((int64_t)nb * BG_G, 256)), dim3(256), 0, c->stream,
                            c->grid, nv, nb, bg->mask, bg->ds, (const double*)w.tmp_d[3], cf.cr, cf.ds_min,
                            cf.ds_max, w.tmp_d[0], w.tmp_i32[0]);
@@ -1718,7 +1719,7 @@ int bg_update_run(sph_ctx* c, sph_background* bg, const sph_particles* solids, c
             unsigned nbk2 = (unsigned)cdiv(nb, 256);
             const NbrView nv2 = nbr_view(c);
             hipLaunchKernelGGL(k_bg_pack, dim3(nbk2), dim3(256), 0, c->stream, nb, nv2.perm,
-                               (const double*)nullptr, (const int64_t*)bg->mq, cf.bg_mass_q,
+                               (const double*)nullptr, (const int64_t*)bg->mq, cf.bg_mass_q, cf.rho0,
                                (double*)nullptr, w.tmp_d[3]);
             hipLaunchKernelGGL(k_bg_smooth_walk, dim3((unsigned)cdiv((int64_t)nb * BG_G, 256)), dim3(256), 0,
                                c->stream, c->grid, nv2, nb, (const double*)w.tmp_d[3], cf.rho0, cf.n_r,
