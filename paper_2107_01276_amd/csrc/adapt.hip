@@ -429,26 +429,58 @@ __global__ __launch_bounds__(256) void k_merge_remap_sorted(Grid g, int nsorted,
                                                             int32_t* mlist, int32_t* mcount)
 {
     const int js = blockIdx.x * blockDim.x + threadIdx.x;
-    if (js >= nsorted) return;
-    const int i = perm[js];
-    if (i < 0) return;
-    if (!keep[i]) {
-        perm[js] = -1;
-        return;
+    bool merged = false;
+    double d = 0.0, h = 0.0;
+    int l = 0;
+    if (js < nsorted) {
+        const int i = perm[js];
+        if (i >= 0 && !keep[i]) {
+            perm[js] = -1;
+        } else if (i >= 0) {
+            const int t = rank[i];
+            perm[js] = t;
+            const int j = closest[i];
+            if (j >= 0 && closest[j] == i) {
+                merged = true;
+                const double x = s.x[t], y = s.y[t];
+                h = s.h[t];
+                xyh[js] = make_double4(x, y, h, 0.0);
+                // distance from the position the particle was filed at (the build's)
+                const double dx = mi_axis(g, 0, x - xs[js]), dy = mi_axis(g, 1, y - ys[js]);
+                d = sqrt(dx * dx + dy * dy);
+                l = key_level(g, keys[js]);
+            }
+        }
     }
-    const int t = rank[i];
-    perm[js] = t;
-    const int j = closest[i];
-    if (!(j >= 0 && closest[j] == i)) return;  // not merged
-    const double x = s.x[t], y = s.y[t], h = s.h[t];
-    xyh[js] = make_double4(x, y, h, 0.0);
-    // distance from the position the particle was filed at (the build's)
-    const double dx = mi_axis(g, 0, x - xs[js]), dy = mi_axis(g, 1, y - ys[js]);
-    const double d = sqrt(dx * dx + dy * dy);
-    const int l = key_level(g, keys[js]);
-    atomicMax(&pad[l], (unsigned long long)__double_as_longlong(d));
-    atomicMax(&hmax[l], (unsigned long long)__double_as_longlong(h));
-    mlist[atomicAdd(mcount, 1)] = js;
+    // the wave's merged particles take one run of the list (one atomic), and
+    // each level present among them one maximum of d and of h (the same
+    // maxima as one atomic per particle, without thousands of atomics on a
+    // few words); every lane of the wave reaches this point
+    const unsigned long long mb = __ballot(merged);
+    if (!mb) return;
+    const int lane = __lane_id();
+    const int lead = __builtin_ctzll(mb);
+    int base = 0;
+    if (lane == lead) base = atomicAdd(mcount, (int)__popcll(mb));
+    base = __shfl(base, lead, 64);
+    if (merged) mlist[base + __popcll(mb & ((1ull << lane) - 1ull))] = js;
+    unsigned long long todo = mb;
+    while (todo) {
+        const int ld = __builtin_ctzll(todo);
+        const int lv = __shfl(l, ld, 64);
+        const bool mine = merged && l == lv;
+        double dm = mine ? d : 0.0, hm = mine ? h : 0.0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            dm = fmax(dm, __shfl_xor(dm, o, 64));
+            hm = fmax(hm, __shfl_xor(hm, o, 64));
+        }
+        if (lane == ld) {
+            atomicMax(&pad[lv], (unsigned long long)__double_as_longlong(dm));
+            atomicMax(&hmax[lv], (unsigned long long)__double_as_longlong(hm));
+        }
+        todo &= ~__ballot(mine);
+    }
 }
 
 // Old slot i (kept): its new slot's last closest partner, renumbered, or the
